@@ -1,0 +1,328 @@
+/*
+ * disc_oracle.c -- FP64 reference for DISC's single-pass, distance-weighted,
+ * mask-aligned feature extraction (arXiv 2603.03935, Sec. III-C; the
+ * "distance-weighted" extraction is named in the abstract and Sec. V).
+ *
+ * TEST INFRASTRUCTURE ONLY (see disc_oracle.h).  Single-threaded, plain C99,
+ * no fast-math.  The readings R-* are listed in the header.
+ */
+#include "disc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Input decoding                                                       */
+/* ------------------------------------------------------------------ */
+
+void disc_oracle_decode_bf16(const uint16_t* in, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t u = ((uint32_t)in[i]) << 16;
+    float f;
+    memcpy(&f, &u, sizeof f);
+    out[i] = (double)f;
+  }
+}
+
+void disc_oracle_decode_f32(const float* in, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = (double)in[i];
+}
+
+/* OCP 8-bit floating point, E4M3 "fn" variant: 1 sign bit, 4 exponent bits
+ * (bias 7), 3 mantissa bits, no infinities, S.1111.111 is NaN. */
+double disc_oracle_e4m3_value(uint8_t code) {
+  int sign = (code >> 7) & 1;
+  int ex = (code >> 3) & 15;
+  int man = code & 7;
+  double v;
+  if (ex == 15 && man == 7) return NAN;
+  if (ex == 0)
+    v = ldexp((double)man, -9); /* subnormal: man/8 * 2^(1-7) */
+  else
+    v = ldexp(1.0 + man / 8.0, ex - 7);
+  return sign ? -v : v;
+}
+
+void disc_oracle_decode_e4m3(const uint8_t* q, const float* scale, int64_t G, int64_t C, double* out) {
+  for (int64_t p = 0; p < G; ++p)
+    for (int64_t c = 0; c < C; ++c)
+      out[p * C + c] = (double)scale[p] * disc_oracle_e4m3_value(q[p * C + c]);
+}
+
+/* ------------------------------------------------------------------ */
+/* R-EDT: exact squared Euclidean distance transform                    */
+/* ------------------------------------------------------------------ */
+
+static int mask_bit(const uint64_t* bits, int32_t wq, int32_t w, int32_t y, int32_t x) {
+  if (x < 0 || x >= w) return 0;
+  return (int)((bits[(int64_t)y * wq + (x >> 6)] >> (x & 63)) & 1u);
+}
+
+/* One-dimensional squared distance transform of a sampled function f over
+ * n samples: out[q] = min_v (q - v)^2 + f[v].  Felzenszwalb & Huttenlocher's
+ * lower envelope of parabolas; the intersection abscissae are rationals with
+ * small denominators, exactly ordered in double precision. */
+static void dt1d(const int64_t* f, int n, int64_t* out, int* v, double* z) {
+  int k = 0;
+  v[0] = 0;
+  z[0] = -HUGE_VAL; /* z[k]: left end of the interval where parabola v[k] is lowest */
+  z[1] = HUGE_VAL;
+  for (int q = 1; q < n; ++q) {
+    double s;
+    for (;;) {
+      const int p = v[k];
+      s = ((double)(f[q] + (int64_t)q * q) - (double)(f[p] + (int64_t)p * p)) / (double)(2 * q - 2 * p);
+      if (s > z[k]) break; /* z[0] = -inf ends the loop at k = 0 */
+      --k;
+    }
+    ++k;
+    v[k] = q;
+    z[k] = s;
+    z[k + 1] = HUGE_VAL;
+  }
+  k = 0;
+  for (int q = 0; q < n; ++q) {
+    while (z[k + 1] < (double)q) ++k;
+    const int64_t d = (int64_t)(q - v[k]);
+    out[q] = d * d + f[v[k]];
+  }
+}
+
+/* R-EDT on the frame padded by a one-pixel background ring, so every mask
+ * pixel has a finite distance.  Row pass (two linear sweeps) then column pass
+ * (lower envelope) -- the standard separable exact EDT, run over the whole
+ * frame for every mask. */
+int disc_oracle_edt_sq(const uint64_t* bits, int32_t h, int32_t w, int32_t* e) {
+  if (!bits || !e || h <= 0 || w <= 0) return -1;
+  const int32_t wq = (w + 63) / 64;
+  const int H = h + 2, W = w + 2;
+  int64_t* g = (int64_t*)malloc(sizeof(int64_t) * (size_t)H * W);
+  int64_t* col = (int64_t*)malloc(sizeof(int64_t) * (size_t)H);
+  int64_t* res = (int64_t*)malloc(sizeof(int64_t) * (size_t)H);
+  int* v = (int*)malloc(sizeof(int) * (size_t)H);
+  double* z = (double*)malloc(sizeof(double) * (size_t)(H + 1));
+  if (!g || !col || !res || !v || !z) {
+    free(g); free(col); free(res); free(v); free(z);
+    return -1;
+  }
+  /* Row pass: horizontal distance to the nearest background pixel. */
+  for (int Y = 0; Y < H; ++Y) {
+    int64_t* row = g + (int64_t)Y * W;
+    for (int X = 0; X < W; ++X) {
+      int inside = (Y >= 1 && Y <= h && X >= 1 && X <= w) ? mask_bit(bits, wq, w, Y - 1, X - 1) : 0;
+      if (!inside)
+        row[X] = 0;
+      else
+        row[X] = row[X - 1] + 1; /* X >= 1 here because X = 0 is padding */
+    }
+    for (int X = W - 2; X >= 0; --X)
+      if (row[X + 1] + 1 < row[X]) row[X] = row[X + 1] + 1;
+  }
+  /* Column pass on squared horizontal distances. */
+  for (int X = 1; X <= w; ++X) {
+    for (int Y = 0; Y < H; ++Y) {
+      int64_t gv = g[(int64_t)Y * W + X];
+      col[Y] = gv * gv;
+    }
+    dt1d(col, H, res, v, z);
+    for (int Y = 1; Y <= h; ++Y) e[(int64_t)(Y - 1) * w + (X - 1)] = (int32_t)res[Y];
+  }
+  free(g); free(col); free(res); free(v); free(z);
+  return 0;
+}
+
+int disc_oracle_edt_sq_batch(const uint64_t* bits, int32_t m, int32_t h, int32_t w, int32_t* e) {
+  if (m < 0 || h <= 0 || w <= 0) return -1;
+  const int64_t wq = (w + 63) / 64;
+  for (int32_t i = 0; i < m; ++i) {
+    int rc = disc_oracle_edt_sq(bits + (int64_t)i * h * wq, h, w, e + (int64_t)i * h * w);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* R-SPAT / R-PATCH: per-patch spatial weights                          */
+/* ------------------------------------------------------------------ */
+
+int disc_oracle_spatial_weights(const uint64_t* bits, int32_t m, int32_t h, int32_t w,
+                                int32_t patch, int32_t gh, int32_t gw, int32_t spatial, double* s) {
+  if (!bits || !s || m < 0 || h <= 0 || w <= 0 || patch <= 0) return -1;
+  if (gh != (h + patch - 1) / patch || gw != (w + patch - 1) / patch) return -1;
+  if (spatial != 0 && spatial != 1) return -1;
+  const int64_t wq = (w + 63) / 64;
+  const int64_t G = (int64_t)gh * gw;
+  int32_t* e = (int32_t*)malloc(sizeof(int32_t) * (size_t)h * w);
+  if (!e) return -1;
+  for (int32_t i = 0; i < m; ++i) {
+    const uint64_t* mb = bits + (int64_t)i * h * wq;
+    double* si = s + (int64_t)i * G;
+    for (int64_t p = 0; p < G; ++p) si[p] = 0.0;
+    if (spatial == 0) disc_oracle_edt_sq(mb, h, w, e);
+    for (int32_t y = 0; y < h; ++y)
+      for (int32_t x = 0; x < w; ++x) {
+        if (!mask_bit(mb, (int32_t)wq, w, y, x)) continue;
+        int64_t p = (int64_t)(y / patch) * gw + (x / patch);
+        si[p] += (spatial == 0) ? sqrt((double)e[(int64_t)y * w + x]) : 1.0;
+      }
+  }
+  free(e);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Eq. (1): distinctiveness map                                         */
+/* ------------------------------------------------------------------ */
+
+int disc_oracle_token_stats(const double* f, int32_t G, int32_t C, double eps,
+                            double* mean, double* r, double* D) {
+  if (!f || G <= 0 || C <= 0) return -1;
+  double* mu = (double*)calloc((size_t)C, sizeof(double));
+  double* rr = (double*)malloc(sizeof(double) * (size_t)G);
+  if (!mu || !rr) {
+    free(mu); free(rr);
+    return -1;
+  }
+  /* spatial mean of all patch features */
+  for (int32_t p = 0; p < G; ++p)
+    for (int32_t c = 0; c < C; ++c) mu[c] += f[(int64_t)p * C + c];
+  for (int32_t c = 0; c < C; ++c) mu[c] /= (double)G;
+  /* residual norms and their mean over the grid */
+  double rbar = 0.0;
+  for (int32_t p = 0; p < G; ++p) {
+    double acc = 0.0;
+    for (int32_t c = 0; c < C; ++c) {
+      double d = f[(int64_t)p * C + c] - mu[c];
+      acc += d * d;
+    }
+    rr[p] = sqrt(acc);
+    rbar += rr[p];
+  }
+  rbar /= (double)G;
+  if (mean)
+    for (int32_t c = 0; c < C; ++c) mean[c] = mu[c];
+  if (r)
+    for (int32_t p = 0; p < G; ++p) r[p] = rr[p];
+  if (D)
+    for (int32_t p = 0; p < G; ++p) D[p] = rr[p] / (rbar + eps);
+  free(mu);
+  free(rr);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* R-POOL / R-PROJ: pooling, projection, normalisation                  */
+/* ------------------------------------------------------------------ */
+
+/* One row: F = (1/Z) sum_p w_p f_p, y = F^T P, out = y/||y||. */
+static int32_t pool_project_row(const double* f, int32_t G, int32_t C, const double* wrow, double Z,
+                                const double* P, int32_t E, double* F, double* y, double* out) {
+  for (int32_t c = 0; c < C; ++c) F[c] = 0.0;
+  for (int32_t p = 0; p < G; ++p) {
+    double wp = wrow[p];
+    if (wp == 0.0) continue;
+    const double* fp = f + (int64_t)p * C;
+    for (int32_t c = 0; c < C; ++c) F[c] += wp * fp[c];
+  }
+  for (int32_t c = 0; c < C; ++c) F[c] /= Z;
+  for (int32_t j = 0; j < E; ++j) y[j] = 0.0;
+  for (int32_t c = 0; c < C; ++c) {
+    const double* Pc = P + (int64_t)c * E;
+    for (int32_t j = 0; j < E; ++j) y[j] += F[c] * Pc[j];
+  }
+  double nn = 0.0;
+  for (int32_t j = 0; j < E; ++j) nn += y[j] * y[j];
+  nn = sqrt(nn);
+  if (nn == 0.0) {
+    for (int32_t j = 0; j < E; ++j) out[j] = 0.0;
+    return 2;
+  }
+  for (int32_t j = 0; j < E; ++j) out[j] = y[j] / nn;
+  return 0;
+}
+
+int disc_oracle_pool_project(const double* f, int32_t G, int32_t C, const double* wts, int32_t m,
+                             const double* P, int32_t E, double* out, int32_t* status, double* pooled) {
+  if (!f || !wts || !P || !out || G <= 0 || C <= 0 || E <= 0 || m < 0) return -1;
+  double* F = (double*)malloc(sizeof(double) * (size_t)C);
+  double* y = (double*)malloc(sizeof(double) * (size_t)E);
+  if (!F || !y) {
+    free(F); free(y);
+    return -1;
+  }
+  for (int32_t i = 0; i < m; ++i) {
+    const double* wr = wts + (int64_t)i * G;
+    double Z = 0.0;
+    for (int32_t p = 0; p < G; ++p) Z += wr[p];
+    int32_t st;
+    if (Z == 0.0) {
+      for (int32_t j = 0; j < E; ++j) out[(int64_t)i * E + j] = 0.0;
+      for (int32_t c = 0; c < C; ++c) F[c] = 0.0;
+      st = 1;
+    } else {
+      st = pool_project_row(f, G, C, wr, Z, P, E, F, y, out + (int64_t)i * E);
+    }
+    if (status) status[i] = st;
+    if (pooled)
+      for (int32_t c = 0; c < C; ++c) pooled[(int64_t)i * C + c] = F[c];
+  }
+  free(F);
+  free(y);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* The whole path for one frame                                         */
+/* ------------------------------------------------------------------ */
+
+int disc_oracle_embed(const double* f, int32_t gh, int32_t gw, int32_t C, int32_t patch,
+                      const uint64_t* bits, int32_t m, int32_t h, int32_t w,
+                      const double* P, int32_t E, int32_t spatial, int32_t distinct, double eps,
+                      double* out, int32_t* status, double* pooled, double* Zout, double* wts) {
+  if (!f || !bits || !P || !out || gh <= 0 || gw <= 0 || C <= 0 || E <= 0 || m < 0) return -1;
+  if (gh != (h + patch - 1) / patch || gw != (w + patch - 1) / patch) return -1;
+  const int32_t G = gh * gw;
+  double* s = (double*)malloc(sizeof(double) * (size_t)m * G + 1);
+  double* D = (double*)malloc(sizeof(double) * (size_t)G);
+  double* wrow = (double*)malloc(sizeof(double) * (size_t)G);
+  double* F = (double*)malloc(sizeof(double) * (size_t)C);
+  double* y = (double*)malloc(sizeof(double) * (size_t)E);
+  int rc = -1;
+  if (!s || !D || !wrow || !F || !y) goto done;
+  if (disc_oracle_spatial_weights(bits, m, h, w, patch, gh, gw, spatial, s)) goto done;
+  if (disc_oracle_token_stats(f, G, C, eps, NULL, NULL, D)) goto done;
+  for (int32_t i = 0; i < m; ++i) {
+    const double* si = s + (int64_t)i * G;
+    double S = 0.0, Z = 0.0;
+    for (int32_t p = 0; p < G; ++p) S += si[p];
+    for (int32_t p = 0; p < G; ++p) {
+      wrow[p] = distinct ? si[p] * D[p] : si[p];
+      Z += wrow[p];
+    }
+    int32_t st;
+    if (S == 0.0) { /* empty mask */
+      for (int32_t p = 0; p < G; ++p) wrow[p] = 0.0;
+      Z = 0.0;
+      for (int32_t j = 0; j < E; ++j) out[(int64_t)i * E + j] = 0.0;
+      for (int32_t c = 0; c < C; ++c) F[c] = 0.0;
+      st = 1;
+    } else {
+      if (Z == 0.0) { /* every touched patch has zero distinctiveness */
+        for (int32_t p = 0; p < G; ++p) wrow[p] = si[p];
+        Z = S;
+      }
+      st = pool_project_row(f, G, C, wrow, Z, P, E, F, y, out + (int64_t)i * E);
+    }
+    if (status) status[i] = st;
+    if (Zout) Zout[i] = Z;
+    if (pooled)
+      for (int32_t c = 0; c < C; ++c) pooled[(int64_t)i * C + c] = F[c];
+    if (wts)
+      for (int32_t p = 0; p < G; ++p) wts[(int64_t)i * G + p] = wrow[p];
+  }
+  rc = 0;
+done:
+  free(s); free(D); free(wrow); free(F); free(y);
+  return rc;
+}

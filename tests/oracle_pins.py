@@ -1,0 +1,402 @@
+"""Pins that fix the oracle to something other than itself.
+
+Every check takes an ``oracle.Oracle`` instance and raises AssertionError when
+the oracle disagrees with what the paper and the mathematics fix: brute force
+on tiny inputs, closed forms, a library routine for a special case, and
+invariants.  ``test_oracle_pins.py`` runs them on the oracle;
+``test_oracle_mutants.py`` runs them on deliberately broken copies of the
+oracle and expects each copy to fail at least one of them.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import disc_inputs as di
+
+# ----------------------------------------------------------------------------
+# helpers (none of them calls the oracle)
+# ----------------------------------------------------------------------------
+
+
+def brute_edt(u8: np.ndarray) -> np.ndarray:
+    """Squared distance from each mask pixel to the nearest non-mask pixel of
+    the integer plane (pixels outside the frame are not in the mask), by
+    enumerating every candidate.  u8: [m][h][w]; returns int64 [m][h][w]."""
+    u8 = np.asarray(u8).astype(bool)
+    m, h, w = u8.shape
+    ys, xs = np.mgrid[0:h, 0:w]
+    py, px = ys.ravel(), xs.ravel()
+    d2 = (py[:, None] - py[None, :]) ** 2 + (px[:, None] - px[None, :]) ** 2
+    # nearest pixel outside the frame: straight up, down, left or right
+    border = np.minimum.reduce([py + 1, h - py, px + 1, w - px]).astype(np.int64) ** 2
+    flat = u8.reshape(m, -1)
+    out = np.empty((m, h * w), dtype=np.int64)
+    n = h * w
+    chunk = max(1, (1 << 22) // (n * n))
+    big = np.iinfo(np.int64).max
+    for i in range(0, m, chunk):
+        M = flat[i:i + chunk]
+        cand = np.where(~M[:, None, :], d2[None], big)
+        best = np.minimum(cand.min(axis=2), border[None])
+        out[i:i + chunk] = np.where(M, best, 0)
+    return out.reshape(m, h, w)
+
+
+def all_masks(h: int, w: int) -> np.ndarray:
+    n = h * w
+    k = np.arange(1 << n, dtype=np.int64)
+    bits = (k[:, None] >> np.arange(n)[None, :]) & 1
+    return bits.reshape(-1, h, w).astype(np.uint8)
+
+
+def rect_mask(h, w, y0, y1, x0, x1):
+    u = np.zeros((h, w), dtype=np.uint8)
+    u[y0:y1 + 1, x0:x1 + 1] = 1
+    return u
+
+
+def rect_edt(h, w, y0, y1, x0, x1):
+    """Closed form for a filled axis-aligned rectangle [y0,y1]x[x0,x1]."""
+    e = np.zeros((h, w), dtype=np.int64)
+    ys, xs = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+    d = np.minimum.reduce([ys - y0 + 1, y1 + 1 - ys, xs - x0 + 1, x1 + 1 - xs])
+    e[y0:y1 + 1, x0:x1 + 1] = d * d
+    return e
+
+
+def block_sum(img: np.ndarray, patch: int) -> np.ndarray:
+    """Sum of a [h][w] image over patch x patch blocks (partial blocks at the
+    bottom/right), flattened patch-row-major."""
+    h, w = img.shape
+    gh, gw = -(-h // patch), -(-w // patch)
+    pad = np.zeros((gh * patch, gw * patch), dtype=np.float64)
+    pad[:h, :w] = img
+    return pad.reshape(gh, patch, gw, patch).sum(axis=(1, 3)).ravel()
+
+
+def random_masks(rng, m, h, w, density):
+    return (rng.random((m, h, w)) < density).astype(np.uint8)
+
+
+# ----------------------------------------------------------------------------
+# P1: the distance transform
+# ----------------------------------------------------------------------------
+
+
+def pin_edt_exhaustive(orc, h, w):
+    u8 = all_masks(h, w)
+    got = orc.edt_sq(di.pack_masks(u8), w)
+    want = brute_edt(u8)
+    bad = np.nonzero((got != want).reshape(len(u8), -1).any(axis=1))[0]
+    assert bad.size == 0, f"EDT differs from brute force on {bad.size} of {len(u8)} {h}x{w} masks (first {bad[:5]})"
+
+
+def pin_edt_random_bruteforce(orc, seed=1, cases=((7, 9), (16, 16), (32, 32), (13, 31), (1, 17), (19, 1))):
+    rng = np.random.default_rng(seed)
+    for (h, w) in cases:
+        for density in (0.05, 0.3, 0.6, 0.85, 0.95):
+            u8 = random_masks(rng, 6, h, w, density)
+            got = orc.edt_sq(di.pack_masks(u8), w)
+            want = brute_edt(u8)
+            assert np.array_equal(got, want), f"EDT differs from brute force ({h}x{w}, density {density})"
+
+
+def pin_edt_scipy(orc, seed=2):
+    from scipy import ndimage
+
+    rng = np.random.default_rng(seed)
+    cases = [random_masks(rng, 3, 64, 96, d) for d in (0.2, 0.7, 0.97)]
+    cases.append(di.unpack_masks(di.masks_ellipses(7, 4, 120, 150, 10, 80), 150))
+    cases.append(di.unpack_masks(di.masks_mixed(8, 4, 96, 200, 1e-2, 0.4), 200))
+    for u8 in cases:
+        m, h, w = u8.shape
+        got = orc.edt_sq(di.pack_masks(u8), w)
+        for i in range(m):
+            padded = np.zeros((h + 2, w + 2), dtype=np.uint8)
+            padded[1:-1, 1:-1] = u8[i]
+            d = ndimage.distance_transform_edt(padded)[1:-1, 1:-1]
+            want = np.rint(d * d).astype(np.int64)
+            assert np.array_equal(got[i], want), "EDT differs from scipy.ndimage.distance_transform_edt"
+
+
+def pin_edt_rectangles(orc):
+    h, w = 23, 70
+    rects = [(0, h - 1, 0, w - 1), (0, 0, 0, 0), (5, 5, 3, 60), (2, 20, 7, 7), (0, 10, 0, 33),
+             (12, h - 1, 40, w - 1), (3, 17, 64, 69), (1, 21, 1, 68), (4, 9, 62, 66)]
+    u8 = np.stack([rect_mask(h, w, *r) for r in rects])
+    got = orc.edt_sq(di.pack_masks(u8), w)
+    for i, r in enumerate(rects):
+        assert np.array_equal(got[i], rect_edt(h, w, *r)), f"EDT of rectangle {r} breaks the closed form"
+
+
+def pin_edt_symmetry(orc, seed=3):
+    rng = np.random.default_rng(seed)
+    u8 = random_masks(rng, 4, 21, 37, 0.75)
+    e = orc.edt_sq(di.pack_masks(u8), 37)
+    eT = orc.edt_sq(di.pack_masks(np.ascontiguousarray(u8.transpose(0, 2, 1))), 21)
+    assert np.array_equal(eT, e.transpose(0, 2, 1)), "EDT is not transpose-equivariant"
+    eF = orc.edt_sq(di.pack_masks(np.ascontiguousarray(u8[:, ::-1, ::-1])), 37)
+    assert np.array_equal(eF, e[:, ::-1, ::-1]), "EDT is not flip-equivariant"
+    single = np.zeros((1, 9, 9), dtype=np.uint8)
+    single[0, 4, 4] = 1
+    es = orc.edt_sq(di.pack_masks(single), 9)
+    assert es[0, 4, 4] == 1 and es.sum() == 1, "single pixel must have squared distance 1"
+    assert ((e >= 1) == (u8 == 1)).all(), "EDT must be >= 1 exactly on the mask"
+
+
+def pin_edt_bbox_locality(orc, seed=4):
+    """A mask away from the frame border has the same EDT in any larger frame."""
+    rng = np.random.default_rng(seed)
+    small = random_masks(rng, 1, 15, 20, 0.8)[0]
+    e_ref = None
+    for (H, W, oy, ox) in ((17, 22, 1, 1), (40, 150, 10, 70), (33, 129, 5, 64)):
+        big = np.zeros((1, H, W), dtype=np.uint8)
+        big[0, oy:oy + 15, ox:ox + 20] = small
+        e = orc.edt_sq(di.pack_masks(big), W)[0]
+        crop = e[oy:oy + 15, ox:ox + 20]
+        assert e.sum() == crop.sum()
+        if e_ref is None:
+            e_ref = crop
+        assert np.array_equal(crop, e_ref), "EDT depends on where the mask sits in the frame"
+
+
+# ----------------------------------------------------------------------------
+# P2: per-patch spatial weights
+# ----------------------------------------------------------------------------
+
+
+def pin_spatial_blocksum(orc, seed=5):
+    rng = np.random.default_rng(seed)
+    for (h, w, patch) in ((30, 33, 7), (16, 16, 4), (27, 40, 14), (9, 70, 5)):
+        u8 = random_masks(rng, 3, h, w, 0.7)
+        bits = di.pack_masks(u8)
+        e = brute_edt(u8)
+        s_edt = orc.spatial_weights(bits, w, patch, 0)
+        s_area = orc.spatial_weights(bits, w, patch, 1)
+        for i in range(3):
+            want = block_sum(np.sqrt(e[i].astype(np.float64)), patch)
+            assert np.allclose(s_edt[i], want, rtol=1e-13, atol=1e-12), "EDT patch weights != block sums of sqrt(EDT)"
+            cnt = block_sum(u8[i].astype(np.float64), patch)
+            assert np.array_equal(s_area[i], cnt), "AREA patch weights != pixel counts per patch"
+            assert s_area[i].sum() == u8[i].sum()
+            assert np.array_equal(s_edt[i] > 0, cnt > 0), "support must be exactly the touched patches"
+
+
+def pin_spatial_rectangle(orc):
+    h, w, patch = 48, 64, 16
+    rects = [(16, 47, 0, 31), (0, 15, 16, 63), (5, 40, 9, 50)]
+    u8 = np.stack([rect_mask(h, w, *r) for r in rects])
+    s = orc.spatial_weights(di.pack_masks(u8), w, patch, 0)
+    for i, r in enumerate(rects):
+        want = block_sum(np.sqrt(rect_edt(h, w, *r).astype(np.float64)), patch)
+        assert np.allclose(s[i], want, rtol=1e-13, atol=1e-12), f"patch weights of rectangle {r} break the closed form"
+
+
+# ----------------------------------------------------------------------------
+# P3: distinctiveness (Eq. 1)
+# ----------------------------------------------------------------------------
+
+
+def pin_token_two_valued(orc, seed=6):
+    rng = np.random.default_rng(seed)
+    G, C, k = 37, 11, 9
+    u, v = rng.normal(size=C), rng.normal(size=C)
+    f = np.tile(v, (G, 1))
+    idx = rng.choice(G, size=k, replace=False)
+    f[idx] = u
+    eps = 1e-6
+    mean, r, D = orc.token_stats(f, eps)
+    duv = np.sqrt(((u - v) ** 2).sum())
+    r_u, r_v = (G - k) / G * duv, k / G * duv
+    want_r = np.full(G, r_v)
+    want_r[idx] = r_u
+    assert np.allclose(mean, (k * u + (G - k) * v) / G, rtol=1e-13, atol=1e-13), "mean of a two-valued map"
+    assert np.allclose(r, want_r, rtol=1e-12), "residual norms of a two-valued map break the closed form"
+    rbar = (k * r_u + (G - k) * r_v) / G
+    assert np.allclose(D, want_r / (rbar + eps), rtol=1e-12), "D of a two-valued map breaks Eq. (1)"
+
+
+def pin_token_invariances(orc, seed=7):
+    rng = np.random.default_rng(seed)
+    G, C = 50, 16
+    f = rng.normal(size=(G, C)) * rng.uniform(0.2, 3, size=(G, 1))
+    _, r, D = orc.token_stats(f, 0.0)
+    _, r2, D2 = orc.token_stats(f + rng.normal(size=C)[None, :], 0.0)
+    assert np.allclose(r2, r, rtol=1e-10) and np.allclose(D2, D, rtol=1e-10), "D must not change under a common shift"
+    _, r3, D3 = orc.token_stats(3.5 * f, 0.0)
+    assert np.allclose(r3, 3.5 * r, rtol=1e-12) and np.allclose(D3, D, rtol=1e-12), "r must scale linearly"
+    eps = 1e-3
+    _, r4, D4 = orc.token_stats(f, eps)
+    rbar = r4.mean()
+    assert np.isclose(D4.sum(), G * rbar / (rbar + eps), rtol=1e-12), "sum of D must equal G rbar/(rbar+eps)"
+
+
+# ----------------------------------------------------------------------------
+# P4 / P5: pooled feature and output
+# ----------------------------------------------------------------------------
+
+
+def pin_pool_constant_on_support(orc, seed=8):
+    """A token map that is constant on a mask's patches pools to that constant,
+    with D on and off, whatever the rest of the map holds."""
+    rng = np.random.default_rng(seed)
+    h, w, patch = 64, 80, 16
+    gh, gw = 4, 5
+    C, E = 12, 9
+    u8 = np.zeros((2, h, w), dtype=np.uint8)
+    u8[0, 20:45, 18:60] = 1
+    u8[1] = di.unpack_masks(di.masks_ellipses(11, 1, h, w, 8, 20), w)[0]
+    bits = di.pack_masks(u8)
+    P = rng.normal(size=(C, E))
+    for i in range(2):
+        f = rng.normal(size=(gh * gw, C))
+        touched = block_sum(u8[i].astype(float), patch) > 0
+        const = rng.normal(size=C)
+        f[touched] = const
+        for distinct in (0, 1):
+            res = orc.embed(f, gh, gw, patch, bits[i:i + 1], w, P, 0, distinct)
+            assert np.allclose(res["pooled"][0], const, rtol=1e-12, atol=1e-12), "constant-on-support map must pool to the constant"
+
+
+def pin_pool_single_patch(orc, seed=9):
+    rng = np.random.default_rng(seed)
+    h, w, patch, C, E = 32, 48, 16, 10, 6
+    u8 = np.zeros((1, h, w), dtype=np.uint8)
+    u8[0, 18:29, 34:46] = 1  # inside patch (1, 2)
+    f = rng.normal(size=(6, C))
+    P = rng.normal(size=(C, E))
+    for distinct in (0, 1):
+        res = orc.embed(f, 2, 3, patch, di.pack_masks(u8), w, P, 0, distinct)
+        assert np.allclose(res["pooled"][0], f[1 * 3 + 2], rtol=1e-13, atol=1e-13), "single-patch mask must give that patch's token"
+
+
+def pin_pool_uniform_mean(orc, seed=10):
+    rng = np.random.default_rng(seed)
+    G, C, E = 20, 7, 5
+    f = rng.normal(size=(G, C))
+    P = rng.normal(size=(C, E))
+    wts = np.zeros((3, G))
+    sel = [np.arange(G), np.array([0, 3, 4, 19]), np.array([7])]
+    for i, s in enumerate(sel):
+        wts[i, s] = 2.5
+    res = orc.pool_project(f, wts, P)
+    for i, s in enumerate(sel):
+        assert np.allclose(res["pooled"][i], f[s].sum(axis=0) / len(s), rtol=1e-13, atol=1e-13), "uniform weights must give the mean"
+
+
+def pin_eps_cancels(orc, seed=11):
+    rng = np.random.default_rng(seed)
+    h, w, patch, C, E = 64, 64, 16, 8, 8
+    bits = di.masks_mixed(12, 5, h, w, 0.01, 0.3)
+    f = rng.normal(size=(16, C))
+    P = rng.normal(size=(C, E))
+    a = orc.embed(f, 4, 4, patch, bits, w, P, 0, 1, 1e-6)
+    b = orc.embed(f, 4, 4, patch, bits, w, P, 0, 1, 0.75)
+    assert np.allclose(a["pooled"], b["pooled"], rtol=1e-12, atol=1e-13), "eps must cancel in the weighted mean"
+    assert np.allclose(a["out"], b["out"], rtol=1e-12, atol=1e-13)
+
+
+def pin_two_valued_rectangle(orc, seed=12):
+    """Two-valued token map + rectangle mask: the whole path in closed form."""
+    rng = np.random.default_rng(seed)
+    h, w, patch = 48, 64, 16
+    gh, gw, C = 3, 4, 6
+    G = gh * gw
+    u, v = rng.normal(size=C), rng.normal(size=C)
+    upatch = np.zeros(G, dtype=bool)
+    upatch[[1, 5, 6, 11]] = True
+    f = np.where(upatch[:, None], u[None, :], v[None, :])
+    rect = (8, 40, 4, 50)
+    u8 = rect_mask(h, w, *rect)[None]
+    perm = np.array([3, 0, 4, 1, 5, 2])  # not an involution, so P != P^T
+    P = np.zeros((C, C))
+    P[np.arange(C), perm] = 1.0  # (F P)[perm[c]] = F[c]
+    eps = 1e-6
+    res = orc.embed(f, gh, gw, patch, di.pack_masks(u8), w, P, 0, 1, eps)
+    s = block_sum(np.sqrt(rect_edt(h, w, *rect).astype(float)), patch)
+    k = upatch.sum()
+    duv = np.sqrt(((u - v) ** 2).sum())
+    r = np.where(upatch, (G - k) / G * duv, k / G * duv)
+    D = r / (r.mean() + eps)
+    wt = s * D
+    F = (wt[:, None] * f).sum(axis=0) / wt.sum()
+    assert np.allclose(res["wts"][0], wt, rtol=1e-12), "weights break the closed form s x D"
+    assert np.allclose(res["Z"][0], wt.sum(), rtol=1e-12)
+    assert np.allclose(res["pooled"][0], F, rtol=1e-12, atol=1e-13), "pooled feature breaks the closed form"
+    y = np.empty(C)
+    y[perm] = F
+    assert np.allclose(res["out"][0], y / np.sqrt((y * y).sum()), rtol=1e-12, atol=1e-13), "projection/normalisation break the closed form"
+
+
+def pin_output_geometry(orc, seed=13):
+    rng = np.random.default_rng(seed)
+    h, w, patch, C = 64, 96, 16, 24
+    bits = di.masks_mixed(14, 6, h, w, 0.01, 0.3)
+    f = rng.normal(size=(4 * 6, C))
+    Q, _ = np.linalg.qr(rng.normal(size=(C, C)))
+    res = orc.embed(f, 4, 6, patch, bits, w, Q, 0, 1)
+    out, F = res["out"], res["pooled"]
+    assert np.allclose(np.linalg.norm(out, axis=1), 1.0, rtol=1e-13), "outputs must be unit vectors"
+    Fn = F / np.linalg.norm(F, axis=1, keepdims=True)
+    assert np.allclose(out @ out.T, Fn @ Fn.T, rtol=1e-11, atol=1e-12), "orthogonal projection must keep cosines"
+
+
+def pin_degenerate(orc, seed=15):
+    rng = np.random.default_rng(seed)
+    h, w, patch, C, E = 32, 32, 16, 5, 4
+    u8 = np.zeros((3, h, w), dtype=np.uint8)
+    u8[1, 3:20, 5:25] = 1
+    u8[2, 0:32, 0:32] = 1
+    bits = di.pack_masks(u8)
+    f = rng.normal(size=(4, C))
+    P = rng.normal(size=(C, E))
+    res = orc.embed(f, 2, 2, patch, bits, w, P)
+    assert res["status"][0] == 1 and not res["out"][0].any(), "empty mask: zero row, status 1"
+    assert (res["status"][1:] == 0).all()
+    # constant token map: D == 0 everywhere -> fall back to spatial weights
+    const = np.tile(rng.normal(size=C), (4, 1))
+    rc = orc.embed(const, 2, 2, patch, bits, w, P)
+    s = orc.spatial_weights(bits, w, patch, 0)
+    assert (rc["status"][1:] == 0).all()
+    assert np.allclose(rc["wts"][1:], s[1:], rtol=0, atol=0), "zero D must fall back to the spatial weights"
+    assert np.allclose(rc["pooled"][1:], const[0], rtol=1e-13), "constant map pools to the constant"
+    rz = orc.embed(f, 2, 2, patch, bits, w, np.zeros((C, E)))
+    assert (rz["status"][1:] == 2).all() and not rz["out"].any(), "zero projection: zero row, status 2"
+
+
+def pin_decoders(orc):
+    known = {0x00: 0.0, 0x01: 2.0 ** -9, 0x07: 7 * 2.0 ** -9, 0x08: 2.0 ** -6, 0x38: 1.0, 0x39: 1.125,
+             0x40: 2.0, 0x7E: 448.0, 0xB8: -1.0, 0xFE: -448.0, 0x80: -0.0}
+    for code, val in known.items():
+        assert orc.e4m3_value(code) == val, f"e4m3 code {code:#x}"
+    assert np.isnan(orc.e4m3_value(0x7F)) and np.isnan(orc.e4m3_value(0xFF))
+    bf = np.array([0x3F80, 0xC000, 0x3E80, 0x0000, 0x7F7F], dtype=np.uint16)
+    got = orc.decode_tokens(bf.reshape(1, 1, -1), "bf16").ravel()
+    assert got[0] == 1.0 and got[1] == -2.0 and got[2] == 0.25 and got[3] == 0.0
+    assert got[4] == float.fromhex("0x1.fep127")
+    q = np.array([[0x38, 0x40], [0xB8, 0x7E]], dtype=np.uint8)
+    sc = np.array([0.5, 3.0], dtype=np.float32)
+    d = orc.decode_tokens(q.reshape(2, 1, 2), "f8", sc)
+    assert np.array_equal(d, np.array([[0.5, 1.0], [-3.0, 1344.0]])), "FP8 tokens decode as scale * value"
+
+
+ALL_PINS = [
+    ("edt_exhaustive_4x4", lambda o: pin_edt_exhaustive(o, 4, 4)),
+    ("edt_random_bruteforce", pin_edt_random_bruteforce),
+    ("edt_scipy", pin_edt_scipy),
+    ("edt_rectangles", pin_edt_rectangles),
+    ("edt_symmetry", pin_edt_symmetry),
+    ("edt_bbox_locality", pin_edt_bbox_locality),
+    ("spatial_blocksum", pin_spatial_blocksum),
+    ("spatial_rectangle", pin_spatial_rectangle),
+    ("token_two_valued", pin_token_two_valued),
+    ("token_invariances", pin_token_invariances),
+    ("pool_constant_on_support", pin_pool_constant_on_support),
+    ("pool_single_patch", pin_pool_single_patch),
+    ("pool_uniform_mean", pin_pool_uniform_mean),
+    ("eps_cancels", pin_eps_cancels),
+    ("two_valued_rectangle", pin_two_valued_rectangle),
+    ("output_geometry", pin_output_geometry),
+    ("degenerate", pin_degenerate),
+    ("decoders", pin_decoders),
+]

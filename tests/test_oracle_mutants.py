@@ -1,0 +1,72 @@
+"""Pin strength: plausible mistakes planted in copies of the oracle (on the CPU)
+must each fail at least one pin.
+
+Each mutant is the oracle source with one textual edit (a dropped term, a
+wrong sign or index, a transposed operand), compiled into a temporary library.
+The committed oracle is never modified.
+"""
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import oracle  # noqa: E402
+import oracle_pins as pins  # noqa: E402
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "disc_oracle.c")
+
+# (id, original text, replacement)
+MUTANTS = [
+    ("row_pass_step", "row[X] = row[X - 1] + 1;", "row[X] = row[X - 1] + 2;"),
+    ("row_pass_no_backward", "if (row[X + 1] + 1 < row[X]) row[X] = row[X + 1] + 1;", "(void)0;"),
+    ("envelope_denominator", "/ (double)(2 * q - 2 * p)", "/ (double)(q - p)"),
+    ("envelope_sign", "(double)(f[q] + (int64_t)q * q) - (double)(f[p] + (int64_t)p * p)",
+     "(double)(f[q] - (int64_t)q * q) - (double)(f[p] - (int64_t)p * p)"),
+    ("envelope_keep_dominated", "if (s > z[k]) break;", "if (s > z[k] || k > 0) break;"),
+    ("envelope_output_offset", "out[q] = d * d + f[v[k]];", "out[q] = d * d + f[q];"),
+    ("column_output_shift", "e[(int64_t)(Y - 1) * w + (X - 1)] = (int32_t)res[Y];",
+     "e[(int64_t)(Y - 1) * w + (X - 1)] = (int32_t)res[Y - 1];"),
+    ("patch_index_transposed", "int64_t p = (int64_t)(y / patch) * gw + (x / patch);",
+     "int64_t p = (int64_t)(x / patch) * gh + (y / patch);"),
+    ("squared_not_euclidean", "si[p] += (spatial == 0) ? sqrt((double)e[(int64_t)y * w + x]) : 1.0;",
+     "si[p] += (spatial == 0) ? (double)e[(int64_t)y * w + x] : 1.0;"),
+    ("mean_not_divided", "for (int32_t c = 0; c < C; ++c) mu[c] /= (double)G;", "(void)0;"),
+    ("residual_squared", "rr[p] = sqrt(acc);", "rr[p] = acc;"),
+    ("D_dropped", "wrow[p] = distinct ? si[p] * D[p] : si[p];", "wrow[p] = si[p];"),
+    ("D_inverted", "wrow[p] = distinct ? si[p] * D[p] : si[p];", "wrow[p] = distinct ? si[p] / D[p] : si[p];"),
+    ("pool_not_normalised", "for (int32_t c = 0; c < C; ++c) F[c] /= Z;", "(void)0;"),
+    ("proj_transposed", "const double* Pc = P + (int64_t)c * E;\n    for (int32_t j = 0; j < E; ++j) y[j] += F[c] * Pc[j];",
+     "for (int32_t j = 0; j < E; ++j) y[j] += F[c] * P[(int64_t)j * C + c];"),
+    ("output_not_normalised", "out[j] = y[j] / nn;", "out[j] = y[j];"),
+    ("no_zero_fallback", "if (Z == 0.0) { /* every touched patch", "if (0) { /* every touched patch"),
+    ("e4m3_bias", "v = ldexp(1.0 + man / 8.0, ex - 7);", "v = ldexp(1.0 + man / 8.0, ex - 8);"),
+    ("e4m3_subnormal", "v = ldexp((double)man, -9);", "v = ldexp((double)man, -10);"),
+]
+
+
+@pytest.fixture(scope="module")
+def source():
+    with open(SRC) as fh:
+        return fh.read()
+
+
+@pytest.mark.parametrize("mid,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, source, mid, old, new):
+    assert source.count(old) == 1, f"mutation site for {mid} not found exactly once"
+    mutated = source.replace(old, new)
+    src = tmp_path / "disc_oracle.c"
+    src.write_text(mutated)
+    lib = oracle.build(force=True, src=str(src), out=str(tmp_path / f"libmut_{mid}.so"))
+    orc = oracle.Oracle(lib)
+    caught = []
+    for name, check in pins.ALL_PINS:
+        try:
+            check(orc)
+        except AssertionError:
+            caught.append(name)
+        except Exception:  # a crash or a rejected argument also exposes the mutant
+            caught.append(name + "(error)")
+        if caught:
+            break
+    assert caught, f"mutant {mid} passes every pin"
