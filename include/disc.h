@@ -1,0 +1,206 @@
+/*
+ * disc.h -- C ABI of libdisc: mask-aligned, distance-weighted feature
+ * extraction from a ViT patch-token map on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is DISC's single-pass instance feature extraction (arXiv
+ * 2603.03935, Sec. III-C): for every 2D instance mask of a frame, aggregate the
+ * patch features that lie inside the mask, weighted by the distinctiveness map
+ * D of Eq. (1), instead of cropping the image and re-running CLIP; the paper
+ * calls the mechanism "distance-weighted" (abstract, Sec. V).  Per mask the
+ * library computes
+ *
+ *   e(x)    exact squared Euclidean distance from mask pixel x to the nearest
+ *           pixel outside the mask (pixels outside the frame count as
+ *           outside), integer-exact;
+ *   s_p     sum over the mask's pixels in patch p of sqrt(e(x))
+ *           (AREA mode: the pixel count), patch p = (floor(y/P), floor(x/P));
+ *   D_p     ||f_p - mean(f)|| / (mean_p ||f_p - mean(f)|| + eps)   (Eq. 1);
+ *   w_p     s_p * D_p (or s_p with distinctiveness off);
+ *   F       sum_p w_p f_p / sum_p w_p    (weighted mean of the tokens);
+ *   out     y / ||y||_2 with y = F^T P  (CLIP embeddings are compared by
+ *           cosine similarity, Sec. III-C and IV-A).
+ *
+ * Degenerate cases: an empty mask gives a zero row (status 1); when every
+ * touched patch has D = 0 the weights fall back to s; a zero projected vector
+ * gives a zero row (status 2).
+ *
+ * Conventions for every entry point:
+ *   - Data pointers are DEVICE pointers (HIP, the current device) unless a
+ *     comment says otherwise.  The caller owns every buffer; the library never
+ *     frees or retains caller memory beyond the call's stream work.
+ *   - Arguments are validated on the host before anything is enqueued.  On a
+ *     validation failure nothing is written to device memory, the call returns
+ *     a non-zero disc_status and disc_last_error() describes the problem.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
+ *     null stream).  A device fault surfaces as DISC_ERR_DEVICE from a later
+ *     call or the caller's own synchronisation.
+ *   - m == 0 masks is a no-op that returns DISC_OK.
+ *   - Calls on different streams may run concurrently; the library keeps one
+ *     workspace per (device, stream) unless the caller passes its own.
+ *
+ * Layouts:
+ *   tokens  [gh][gw][c] row-major, c fastest; gh = ceil(h/patch), gw = ceil(w/patch)
+ *           (the last patch row/column may cover fewer pixels).
+ *   masks   bits[m][h][ceil(w/64)] uint64; bit i of word k of a row is pixel
+ *           column 64k+i; bits at columns >= w are ignored.
+ *   proj    [c][e] row-major.
+ *   out     [m][e] FP32 rows of unit L2 norm (or zero rows, see above).
+ *
+ * Limits of this version: h, w >= 1, every mask's bounding box at most 1118
+ * rows tall (frames up to 1118 rows are always accepted), 8 <= patch <= 64,
+ * c a multiple of 64 up to 2048, e a multiple of 128 up to 1024.
+ */
+#ifndef DISC_H
+#define DISC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DISC_ABI_VERSION 1
+
+typedef enum disc_status {
+  DISC_OK = 0,
+  DISC_ERR_INVALID_ARGUMENT = 1, /* null pointer, negative size, bad enum */
+  DISC_ERR_SHAPE = 2,            /* inconsistent shapes between arguments */
+  DISC_ERR_UNSUPPORTED_DTYPE = 3,
+  DISC_ERR_ALIGNMENT = 4,        /* device pointers must be 16-byte aligned */
+  DISC_ERR_OUT_OF_MEMORY = 5,    /* workspace allocation failed / too small */
+  DISC_ERR_DEVICE = 6,           /* a HIP call failed */
+  DISC_ERR_ADMISSION = 7,        /* serving: request can never be admitted */
+  DISC_ERR_UNIMPLEMENTED = 8,
+  DISC_ERR_LIMIT = 9             /* outside the limits listed above */
+} disc_status;
+
+typedef enum disc_dtype {
+  DISC_F32 = 0,
+  DISC_BF16 = 1,
+  DISC_F8E4M3 = 2 /* OCP e4m3fn; tokens only, with a per-token FP32 scale */
+} disc_dtype;
+
+typedef enum disc_spatial { DISC_SPATIAL_EDT = 0, DISC_SPATIAL_AREA = 1 } disc_spatial;
+
+/* Patch-token map of one frame (the ViT's intermediate-layer patch tokens,
+ * Sec. III-C).  For DISC_F8E4M3 the token value is scale[p] * q. */
+typedef struct disc_tokens {
+  const void* data;    /* [gh][gw][c] */
+  int32_t dtype;       /* disc_dtype */
+  int32_t gh, gw, c;
+  int32_t patch;       /* pixels per patch side */
+  const float* scale;  /* [gh*gw] for DISC_F8E4M3, NULL otherwise */
+} disc_tokens;
+
+/* The frame's binary instance masks (Sec. III-A), bit-packed. */
+typedef struct disc_masks {
+  const uint64_t* bits; /* [m][h][ceil(w/64)] */
+  int32_t m, h, w;
+} disc_masks;
+
+/* Projection into the embedding space, [c][e]; DISC_F32 or DISC_BF16. */
+typedef struct disc_proj {
+  const void* data;
+  int32_t dtype;
+  int32_t c, e;
+} disc_proj;
+
+/* Output of one frame. */
+typedef struct disc_out {
+  float* data;          /* [m][e] FP32 */
+  int32_t m, e;
+  int32_t* mask_status; /* optional [m]: 0 ok, 1 empty mask, 2 zero projection */
+  float* pooled;        /* optional [m][c] FP32 weighted-mean features F */
+} disc_out;
+
+typedef struct disc_options {
+  int32_t spatial;        /* disc_spatial, default DISC_SPATIAL_EDT */
+  int32_t distinct;       /* 1 (default): weights include D of Eq. (1) */
+  float eps;              /* Eq. (1) epsilon, default 1e-6 (cancels in F) */
+  int32_t gemm_dtype;     /* pooling/projection operand type: DISC_F32 or
+                             DISC_BF16; -1 (default) = DISC_F32 for FP32 tokens
+                             and projection, DISC_BF16 otherwise.  FP32
+                             accumulation in every case. */
+  void* workspace;        /* optional caller-owned device workspace */
+  size_t workspace_bytes; /* its size; see disc_workspace_bytes() */
+} disc_options;
+
+/* Fill *o with the defaults listed above. */
+void disc_options_default(disc_options* o);
+
+/* Embed every mask of one frame with default options on the null stream. */
+disc_status disc_embed_masks(const disc_tokens* tokens, const disc_masks* masks, const disc_proj* proj,
+                             disc_out* out);
+
+/* Same with options (NULL = defaults) and a stream. */
+disc_status disc_embed_masks_ex(const disc_tokens* tokens, const disc_masks* masks, const disc_proj* proj,
+                                disc_out* out, const disc_options* opts, void* stream);
+
+/* A ragged batch: frame i has tokens[i], masks[i] and out[i]; frames may
+ * differ in resolution, grid and mask count but share c, the token dtype and
+ * proj.  Each frame keeps its own mean/D (statistics never mix frames). */
+disc_status disc_embed_frames(const disc_tokens* tokens, const disc_masks* masks, int32_t n_frames,
+                              const disc_proj* proj, disc_out* out, const disc_options* opts, void* stream);
+
+/* Device workspace bytes disc_embed_frames needs for these arguments
+ * (0 on invalid arguments). */
+size_t disc_workspace_bytes(const disc_tokens* tokens, const disc_masks* masks, int32_t n_frames,
+                            const disc_proj* proj, const disc_options* opts);
+
+/* Free the library-owned workspaces (synchronises the device first). */
+disc_status disc_release_workspace(void);
+
+/* ---- stage entry points (tests, ablations) ---- */
+
+/* Exact squared EDT of each mask: e[m][h][w] int32 (0 off the mask). */
+disc_status disc_edt_sq(const disc_masks* masks, int32_t* e, void* stream);
+
+/* Per-patch weights w[m][gh*gw] FP32: s_p * D_p (D of Eq. 1 with opts->eps)
+ * or s_p when opts->distinct == 0 (tokens may then be NULL; the grid is taken
+ * from `patch`).  `patch` must equal tokens->patch when tokens is given. */
+disc_status disc_patch_weights(const disc_tokens* tokens, const disc_masks* masks, int32_t patch,
+                               const disc_options* opts, float* w, void* stream);
+
+/* Eq. (1): mean[c], r[gh*gw] = ||f_p - mean||, D[gh*gw] = r/(mean(r)+eps).
+ * Any output pointer may be NULL. */
+disc_status disc_token_stats(const disc_tokens* tokens, float eps, float* mean, float* r, float* D,
+                             void* stream);
+
+/* Pooling + projection + normalisation with caller-given weights
+ * w[m][gh*gw] FP32 (non-negative); rows summing to zero give status 1.
+ * gemm_dtype as in disc_options. */
+disc_status disc_pool_project(const disc_tokens* tokens, const float* w, int32_t m, const disc_proj* proj,
+                              disc_out* out, int32_t gemm_dtype, void* stream);
+
+/* Pack bool/uint8 masks u8[m][h][w] (non-zero = inside) into the bit layout. */
+disc_status disc_pack_masks(const uint8_t* u8, int32_t m, int32_t h, int32_t w, uint64_t* bits, void* stream);
+
+/* ---- profiling ---- */
+
+/* Per-stage device timing with HIP events recorded on the caller's stream
+ * around each stage of disc_embed_frames (and the calls built on it): stages
+ * 0 scan, 1 plan, 2 token_stats, 3 edt, 4 weights, 5 pool, 6 proj.
+ * Off by default; enabling it adds two event records per stage. */
+void disc_trace_enable(int32_t on);
+/* Wait for pending events and zero the accumulated totals. */
+void disc_trace_reset(void);
+/* Total milliseconds and number of timed launches of a stage since the last
+ * reset (waits for pending events); -1 for an unknown stage. */
+int32_t disc_trace_read(int32_t stage, double* total_ms, int64_t* count);
+/* Name of a stage, or NULL. */
+const char* disc_trace_stage_name(int32_t stage);
+
+/* ---- misc ---- */
+
+/* Text of the last error on the calling thread; valid until its next call. */
+const char* disc_last_error(void);
+
+/* DISC_ABI_VERSION of the loaded library. */
+int32_t disc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DISC_H */

@@ -1,0 +1,350 @@
+"""Python binding of libdisc (MI355X / gfx950): DISC's mask-aligned,
+distance-weighted feature extraction (arXiv 2603.03935, Sec. III-C).
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libdisc.so``; PyTorch provides device memory and the current stream.  There
+is no fallback -- importing works without the library, but every call raises
+if ``libdisc.so`` is missing.
+
+Entry points mirror ``include/disc.h``:
+
+* :func:`embed_masks`   one frame -> unit embeddings [m][e] (+ status, pooled)
+* :func:`embed_frames`  a ragged batch of frames in one call
+* :func:`edt_sq`, :func:`patch_weights`, :func:`token_stats`,
+  :func:`pool_project`, :func:`pack_masks`  stage entry points
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdisc.so")
+
+DISC_F32, DISC_BF16, DISC_F8E4M3 = 0, 1, 2
+SPATIAL_EDT, SPATIAL_AREA = 0, 1
+STATUS_NAMES = {
+    0: "DISC_OK", 1: "DISC_ERR_INVALID_ARGUMENT", 2: "DISC_ERR_SHAPE", 3: "DISC_ERR_UNSUPPORTED_DTYPE",
+    4: "DISC_ERR_ALIGNMENT", 5: "DISC_ERR_OUT_OF_MEMORY", 6: "DISC_ERR_DEVICE", 7: "DISC_ERR_ADMISSION",
+    8: "DISC_ERR_UNIMPLEMENTED", 9: "DISC_ERR_LIMIT",
+}
+
+# Every symbol include/disc.h declares (checked by the CPU test suite).
+EXPORTS = [
+    "disc_options_default", "disc_embed_masks", "disc_embed_masks_ex", "disc_embed_frames",
+    "disc_workspace_bytes", "disc_release_workspace", "disc_edt_sq", "disc_patch_weights",
+    "disc_token_stats", "disc_pool_project", "disc_pack_masks", "disc_last_error", "disc_abi_version",
+    "disc_trace_enable", "disc_trace_reset", "disc_trace_read", "disc_trace_stage_name",
+]
+STAGES = ["scan", "plan", "token_stats", "edt", "weights", "pool", "proj"]
+
+
+class DiscError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+# ---------------------------------------------------------------- C structs
+
+class Tokens(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("gh", ctypes.c_int32),
+                ("gw", ctypes.c_int32), ("c", ctypes.c_int32), ("patch", ctypes.c_int32),
+                ("scale", ctypes.c_void_p)]
+
+
+class Masks(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_void_p), ("m", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32)]
+
+
+class Proj(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("c", ctypes.c_int32), ("e", ctypes.c_int32)]
+
+
+class Out(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("m", ctypes.c_int32), ("e", ctypes.c_int32),
+                ("mask_status", ctypes.c_void_p), ("pooled", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("spatial", ctypes.c_int32), ("distinct", ctypes.c_int32), ("eps", ctypes.c_float),
+                ("gemm_dtype", ctypes.c_int32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdisc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libdisc.so not found at {path}; build it with paper_2603_03935_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    lib.disc_options_default.argtypes = [P(Options)]
+    lib.disc_options_default.restype = None
+    lib.disc_embed_masks.argtypes = [P(Tokens), P(Masks), P(Proj), P(Out)]
+    lib.disc_embed_masks_ex.argtypes = [P(Tokens), P(Masks), P(Proj), P(Out), P(Options), vp]
+    lib.disc_embed_frames.argtypes = [P(Tokens), P(Masks), i32, P(Proj), P(Out), P(Options), vp]
+    lib.disc_workspace_bytes.argtypes = [P(Tokens), P(Masks), i32, P(Proj), P(Options)]
+    lib.disc_workspace_bytes.restype = ctypes.c_size_t
+    lib.disc_release_workspace.argtypes = []
+    lib.disc_edt_sq.argtypes = [P(Masks), vp, vp]
+    lib.disc_patch_weights.argtypes = [P(Tokens), P(Masks), i32, P(Options), vp, vp]
+    lib.disc_token_stats.argtypes = [P(Tokens), ctypes.c_float, vp, vp, vp, vp]
+    lib.disc_pool_project.argtypes = [P(Tokens), vp, i32, P(Proj), P(Out), i32, vp]
+    lib.disc_pack_masks.argtypes = [vp, i32, i32, i32, vp, vp]
+    lib.disc_last_error.argtypes = []
+    lib.disc_last_error.restype = ctypes.c_char_p
+    lib.disc_trace_enable.argtypes = [i32]
+    lib.disc_trace_enable.restype = None
+    lib.disc_trace_reset.argtypes = []
+    lib.disc_trace_reset.restype = None
+    lib.disc_trace_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.disc_trace_read.restype = i32
+    lib.disc_trace_stage_name.argtypes = [i32]
+    lib.disc_trace_stage_name.restype = ctypes.c_char_p
+    lib.disc_abi_version.argtypes = []
+    lib.disc_abi_version.restype = i32
+    for name in ("disc_embed_masks", "disc_embed_masks_ex", "disc_embed_frames", "disc_release_workspace",
+                 "disc_edt_sq", "disc_patch_weights", "disc_token_stats", "disc_pool_project", "disc_pack_masks"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise DiscError(status, load().disc_last_error().decode(errors="replace"))
+
+
+def last_error() -> str:
+    return load().disc_last_error().decode(errors="replace")
+
+
+# ---------------------------------------------------------------- marshalling
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream=None) -> Optional[int]:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def token_dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return DISC_F32
+    if t.dtype == torch.bfloat16:
+        return DISC_BF16
+    if t.dtype in (torch.uint8, getattr(torch, "float8_e4m3fn", torch.uint8)):
+        return DISC_F8E4M3
+    raise TypeError(f"unsupported token dtype {t.dtype}")
+
+
+def proj_dtype_code(p) -> int:
+    torch = _torch()
+    if p.dtype == torch.float32:
+        return DISC_F32
+    if p.dtype == torch.bfloat16:
+        return DISC_BF16
+    raise TypeError(f"unsupported projection dtype {p.dtype}")
+
+
+def make_tokens(tokens, patch: int, scale=None) -> Tokens:
+    gh, gw, c = tokens.shape
+    assert tokens.is_contiguous()
+    return Tokens(_ptr(tokens), token_dtype_code(tokens), gh, gw, c, patch, _ptr(scale))
+
+
+def make_masks(bits, h: int, w: int) -> Masks:
+    assert bits.is_contiguous() and bits.element_size() == 8
+    return Masks(_ptr(bits), bits.shape[0], h, w)
+
+
+def make_proj(proj) -> Proj:
+    c, e = proj.shape
+    assert proj.is_contiguous()
+    return Proj(_ptr(proj), proj_dtype_code(proj), c, e)
+
+
+def make_options(spatial: int = SPATIAL_EDT, distinct: int = 1, eps: float = 1e-6, gemm_dtype: int = -1,
+                 workspace=None) -> Options:
+    o = Options()
+    load().disc_options_default(ctypes.byref(o))
+    o.spatial, o.distinct, o.eps, o.gemm_dtype = spatial, distinct, eps, gemm_dtype
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    return o
+
+
+@dataclass
+class FrameInput:
+    tokens: object       # torch tensor [gh][gw][c] (float32 / bfloat16 / uint8 e4m3fn codes), on the GPU
+    bits: object         # torch int64 tensor [m][h][ceil(w/64)], on the GPU
+    h: int
+    w: int
+    patch: int
+    scale: object = None  # float32 [gh*gw] for FP8 tokens
+
+
+@dataclass
+class FrameOutput:
+    out: object          # float32 [m][e]
+    status: object       # int32 [m]
+    pooled: object = None  # float32 [m][c] when requested
+
+
+def alloc_outputs(frames: Sequence[FrameInput], e: int, pooled: bool = False) -> List[FrameOutput]:
+    torch = _torch()
+    res = []
+    for f in frames:
+        m = f.bits.shape[0]
+        dev = f.tokens.device
+        res.append(FrameOutput(torch.empty((m, e), dtype=torch.float32, device=dev),
+                               torch.empty((m,), dtype=torch.int32, device=dev),
+                               torch.empty((m, f.tokens.shape[2]), dtype=torch.float32, device=dev) if pooled else None))
+    return res
+
+
+def embed_frames(frames: Sequence[FrameInput], proj, outputs: Optional[List[FrameOutput]] = None,
+                 pooled: bool = False, options: Optional[Options] = None, stream=None) -> List[FrameOutput]:
+    """disc_embed_frames: one call for a ragged batch of frames."""
+    lib = load()
+    n = len(frames)
+    e = proj.shape[1]
+    if outputs is None:
+        outputs = alloc_outputs(frames, e, pooled)
+    toks = (Tokens * max(n, 1))()
+    msks = (Masks * max(n, 1))()
+    outs = (Out * max(n, 1))()
+    for i, (f, o) in enumerate(zip(frames, outputs)):
+        toks[i] = make_tokens(f.tokens, f.patch, f.scale)
+        msks[i] = make_masks(f.bits, f.h, f.w)
+        outs[i] = Out(_ptr(o.out), o.out.shape[0], o.out.shape[1], _ptr(o.status), _ptr(o.pooled))
+    pj = make_proj(proj)
+    opts = options if options is not None else make_options()
+    _check(lib.disc_embed_frames(toks, msks, n, ctypes.byref(pj), outs, ctypes.byref(opts), _stream_handle(stream)))
+    return outputs
+
+
+def embed_masks(tokens, bits, h: int, w: int, proj, patch: int, scale=None, pooled: bool = False,
+                options: Optional[Options] = None, stream=None) -> FrameOutput:
+    """disc_embed_masks_ex for one frame."""
+    return embed_frames([FrameInput(tokens, bits, h, w, patch, scale)], proj, pooled=pooled, options=options,
+                        stream=stream)[0]
+
+
+def workspace_bytes(frames: Sequence[FrameInput], proj, options: Optional[Options] = None) -> int:
+    lib = load()
+    n = len(frames)
+    toks = (Tokens * max(n, 1))()
+    msks = (Masks * max(n, 1))()
+    for i, f in enumerate(frames):
+        toks[i] = make_tokens(f.tokens, f.patch, f.scale)
+        msks[i] = make_masks(f.bits, f.h, f.w)
+    pj = make_proj(proj)
+    opts = options if options is not None else make_options()
+    return int(lib.disc_workspace_bytes(toks, msks, n, ctypes.byref(pj), ctypes.byref(opts)))
+
+
+def edt_sq(bits, h: int, w: int, stream=None):
+    """disc_edt_sq -> int32 [m][h][w]."""
+    torch = _torch()
+    m = bits.shape[0]
+    e = torch.empty((m, h, w), dtype=torch.int32, device=bits.device)
+    mk = make_masks(bits, h, w)
+    _check(load().disc_edt_sq(ctypes.byref(mk), _ptr(e), _stream_handle(stream)))
+    return e
+
+
+def patch_weights(bits, h: int, w: int, patch: int, tokens=None, scale=None, spatial: int = SPATIAL_EDT,
+                  distinct: int = 1, eps: float = 1e-6, stream=None):
+    """disc_patch_weights -> float32 [m][gh*gw]."""
+    torch = _torch()
+    m = bits.shape[0]
+    gh, gw = -(-h // patch), -(-w // patch)
+    out = torch.empty((m, gh * gw), dtype=torch.float32, device=bits.device)
+    mk = make_masks(bits, h, w)
+    tk = make_tokens(tokens, patch, scale) if tokens is not None else None
+    opts = make_options(spatial, distinct, eps)
+    _check(load().disc_patch_weights(ctypes.byref(tk) if tk is not None else None, ctypes.byref(mk), patch,
+                                     ctypes.byref(opts), _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def token_stats(tokens, patch: int, scale=None, eps: float = 1e-6, stream=None):
+    """disc_token_stats -> (mean [c], r [G], D [G]) float32."""
+    torch = _torch()
+    gh, gw, c = tokens.shape
+    mean = torch.empty((c,), dtype=torch.float32, device=tokens.device)
+    r = torch.empty((gh * gw,), dtype=torch.float32, device=tokens.device)
+    D = torch.empty((gh * gw,), dtype=torch.float32, device=tokens.device)
+    tk = make_tokens(tokens, patch, scale)
+    _check(load().disc_token_stats(ctypes.byref(tk), eps, _ptr(mean), _ptr(r), _ptr(D), _stream_handle(stream)))
+    return mean, r, D
+
+
+def pool_project(tokens, weights, proj, patch: int, scale=None, gemm_dtype: int = -1, pooled: bool = True,
+                 stream=None) -> FrameOutput:
+    """disc_pool_project with caller-given weights [m][gh*gw] (float32)."""
+    torch = _torch()
+    m = weights.shape[0]
+    e = proj.shape[1]
+    res = FrameOutput(torch.empty((m, e), dtype=torch.float32, device=tokens.device),
+                      torch.empty((m,), dtype=torch.int32, device=tokens.device),
+                      torch.empty((m, tokens.shape[2]), dtype=torch.float32, device=tokens.device) if pooled else None)
+    tk = make_tokens(tokens, patch, scale)
+    pj = make_proj(proj)
+    out = Out(_ptr(res.out), m, e, _ptr(res.status), _ptr(res.pooled))
+    _check(load().disc_pool_project(ctypes.byref(tk), _ptr(weights), m, ctypes.byref(pj), ctypes.byref(out),
+                                    gemm_dtype, _stream_handle(stream)))
+    return res
+
+
+def pack_masks(u8, stream=None):
+    """disc_pack_masks: uint8/bool [m][h][w] on the GPU -> int64 bits [m][h][ceil(w/64)]."""
+    torch = _torch()
+    m, h, w = u8.shape
+    bits = torch.empty((m, h, (w + 63) // 64), dtype=torch.int64, device=u8.device)
+    src = u8.to(torch.uint8).contiguous()
+    _check(load().disc_pack_masks(_ptr(src), m, h, w, _ptr(bits), _stream_handle(stream)))
+    return bits
+
+
+def release_workspace():
+    _check(load().disc_release_workspace())
+
+
+def trace_enable(on: bool = True):
+    load().disc_trace_enable(1 if on else 0)
+
+
+def trace_reset():
+    load().disc_trace_reset()
+
+
+def trace_read() -> dict:
+    """{stage: (total_ms, launches)} since the last reset."""
+    lib = load()
+    res = {}
+    for i, name in enumerate(STAGES):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        lib.disc_trace_read(i, ctypes.byref(ms), ctypes.byref(n))
+        res[name] = (ms.value, n.value)
+    return res

@@ -1,0 +1,784 @@
+// C ABI of libdisc: argument validation, workspaces and the kernel sequence
+// of DISC's single-pass feature extraction (arXiv 2603.03935, Sec. III-C).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cstring>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/disc.h"
+#include "disc_device.h"
+
+using namespace disc;
+
+namespace {
+
+thread_local std::string g_err;
+
+disc_status fail(disc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+disc_status ok() {
+  g_err.clear();
+  return DISC_OK;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+constexpr int kMaxWidth = 256 * 56;  // strips per mask fit in 8 bits for every patch size
+
+// --------------------------------------------------------------------------
+// validation
+// --------------------------------------------------------------------------
+disc_status check_tokens(const disc_tokens* t, const char* who) {
+  if (!t) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: tokens is NULL", who);
+  if (!t->data) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: tokens->data is NULL", who);
+  if (t->dtype < DISC_F32 || t->dtype > DISC_F8E4M3)
+    return fail(DISC_ERR_UNSUPPORTED_DTYPE, "%s: unknown token dtype %d", who, t->dtype);
+  if (t->gh <= 0 || t->gw <= 0 || t->c <= 0)
+    return fail(DISC_ERR_INVALID_ARGUMENT, "%s: token grid %dx%dx%d must be positive", who, t->gh, t->gw, t->c);
+  if (t->patch < kMinPatch || t->patch > kMaxPatch)
+    return fail(DISC_ERR_LIMIT, "%s: patch %d outside [%d, %d]", who, t->patch, kMinPatch, kMaxPatch);
+  if (t->c % 64 != 0 || t->c > kMaxC)
+    return fail(DISC_ERR_LIMIT, "%s: channels %d must be a multiple of 64 up to %d", who, t->c, kMaxC);
+  if ((t->dtype == DISC_F8E4M3) != (t->scale != nullptr))
+    return fail(DISC_ERR_INVALID_ARGUMENT, "%s: per-token scales are required for FP8 tokens and only for them", who);
+  if (!aligned16(t->data) || (t->scale && !aligned16(t->scale)))
+    return fail(DISC_ERR_ALIGNMENT, "%s: token pointers must be 16-byte aligned", who);
+  return DISC_OK;
+}
+
+disc_status check_masks(const disc_masks* m, const char* who) {
+  if (!m) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: masks is NULL", who);
+  if (m->m < 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: negative mask count", who);
+  if (m->h <= 0 || m->w <= 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: frame %dx%d must be positive", who, m->h, m->w);
+  if (m->m > 0 && !m->bits) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: masks->bits is NULL", who);
+  if (m->h > kMaxRows - 2) return fail(DISC_ERR_LIMIT, "%s: frame height %d exceeds %d", who, m->h, kMaxRows - 2);
+  if (m->w > kMaxWidth) return fail(DISC_ERR_LIMIT, "%s: frame width %d exceeds %d", who, m->w, kMaxWidth);
+  if (m->bits && !aligned16(m->bits)) return fail(DISC_ERR_ALIGNMENT, "%s: mask bits must be 16-byte aligned", who);
+  if ((int64_t)m->m * m->h * ((m->w + 63) / 64) > (int64_t)1 << 40)
+    return fail(DISC_ERR_LIMIT, "%s: mask batch too large", who);
+  return DISC_OK;
+}
+
+disc_status check_grid(const disc_tokens* t, const disc_masks* m, const char* who) {
+  const int gh = (m->h + t->patch - 1) / t->patch, gw = (m->w + t->patch - 1) / t->patch;
+  if (t->gh != gh || t->gw != gw)
+    return fail(DISC_ERR_SHAPE, "%s: token grid %dx%d does not cover a %dx%d frame with %d-px patches (expected %dx%d)",
+                who, t->gh, t->gw, m->h, m->w, t->patch, gh, gw);
+  return DISC_OK;
+}
+
+disc_status check_proj(const disc_proj* p, int c, const char* who) {
+  if (!p) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: proj is NULL", who);
+  if (!p->data) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: proj->data is NULL", who);
+  if (p->dtype != DISC_F32 && p->dtype != DISC_BF16)
+    return fail(DISC_ERR_UNSUPPORTED_DTYPE, "%s: projection dtype must be F32 or BF16", who);
+  if (p->c != c) return fail(DISC_ERR_SHAPE, "%s: proj has %d input channels, tokens have %d", who, p->c, c);
+  if (p->e <= 0 || p->e % 128 != 0 || p->e > 1024)
+    return fail(DISC_ERR_LIMIT, "%s: embedding width %d must be a multiple of 128 up to 1024", who, p->e);
+  if (!aligned16(p->data)) return fail(DISC_ERR_ALIGNMENT, "%s: proj must be 16-byte aligned", who);
+  return DISC_OK;
+}
+
+disc_status check_out(const disc_out* o, int m, int e, const char* who) {
+  if (!o) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: out is NULL", who);
+  if (m > 0 && !o->data) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: out->data is NULL", who);
+  if (o->m != m) return fail(DISC_ERR_SHAPE, "%s: out has %d rows for %d masks", who, o->m, m);
+  if (o->e != e) return fail(DISC_ERR_SHAPE, "%s: out has width %d, projection %d", who, o->e, e);
+  if ((o->data && !aligned16(o->data)) || (o->pooled && !aligned16(o->pooled)) ||
+      (o->mask_status && (reinterpret_cast<uintptr_t>(o->mask_status) & 3u)))
+    return fail(DISC_ERR_ALIGNMENT, "%s: output pointers must be 16-byte aligned", who);
+  return DISC_OK;
+}
+
+disc_status check_opts(const disc_options* o, const char* who) {
+  if (!o) return DISC_OK;
+  if (o->spatial != DISC_SPATIAL_EDT && o->spatial != DISC_SPATIAL_AREA)
+    return fail(DISC_ERR_INVALID_ARGUMENT, "%s: spatial mode %d", who, o->spatial);
+  if (o->distinct != 0 && o->distinct != 1) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: distinct must be 0 or 1", who);
+  if (!(o->eps >= 0.f)) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: eps must be >= 0", who);
+  if (o->gemm_dtype != -1 && o->gemm_dtype != DISC_F32 && o->gemm_dtype != DISC_BF16)
+    return fail(DISC_ERR_UNSUPPORTED_DTYPE, "%s: gemm dtype must be F32, BF16 or -1", who);
+  if (o->workspace && !aligned16(o->workspace)) return fail(DISC_ERR_ALIGNMENT, "%s: workspace must be 16-byte aligned", who);
+  return DISC_OK;
+}
+
+disc_status hip_fail(hipError_t e, const char* what) {
+  return fail(DISC_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// --------------------------------------------------------------------------
+// workspace layout
+// --------------------------------------------------------------------------
+struct Layout {
+  size_t frames, mask_frame, tiles, frame_ctr, staged_end;  // staged region (uploaded from the host)
+  size_t bbox, area, meta, items, counts, psum, mean, r, s, W, Z, mstat, X, total;
+};
+
+struct Shape {
+  int n_frames = 0;
+  int64_t M = 0, sumG = 0, sumMGs = 0;
+  int C = 0, E = 0, gmax = 0, nchunk = 1, item_cap = 1, n_tiles = 0, gemm_bf16 = 0;
+};
+
+Layout make_layout(const Shape& s) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (size_t)round_up((int64_t)std::max<size_t>(bytes, 1), 256);
+    return at;
+  };
+  L.frames = take(sizeof(FrameDesc) * s.n_frames);
+  L.mask_frame = take(4 * (size_t)s.M);
+  L.tiles = take(16 * (size_t)s.n_tiles);
+  L.frame_ctr = take(4 * (size_t)s.n_frames);
+  L.staged_end = off;
+  L.bbox = take(16 * (size_t)s.M);
+  L.area = take(4 * (size_t)s.M);
+  L.meta = take(4 * (size_t)s.M);
+  L.items = take(4 * (size_t)kClasses * s.item_cap);
+  L.counts = take(4 * 16);
+  L.psum = take(4 * (size_t)s.n_frames * s.nchunk * s.C);
+  L.mean = take(4 * (size_t)s.n_frames * s.C);
+  L.r = take(4 * (size_t)s.sumG);
+  L.s = take(4 * (size_t)s.sumMGs);
+  L.W = take((s.gemm_bf16 ? 2 : 4) * (size_t)s.sumMGs);
+  L.Z = take(4 * (size_t)s.M);
+  L.mstat = take(4 * (size_t)s.M);
+  L.X = take((s.gemm_bf16 ? 2 : 4) * (size_t)s.M * s.C);
+  L.total = off;
+  return L;
+}
+
+// --------------------------------------------------------------------------
+// per (device, stream) workspace cache with a pinned staging buffer
+// --------------------------------------------------------------------------
+struct WsEntry {
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  void* host = nullptr;
+  size_t host_bytes = 0;
+  hipEvent_t ev = nullptr;
+  bool ev_pending = false;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
+std::map<int, int> g_cus;
+
+int num_cus(int dev) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto it = g_cus.find(dev);
+  if (it != g_cus.end()) return it->second;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+  g_cus[dev] = n;
+  return n;
+}
+
+struct Ctx {
+  int dev = 0;
+  hipStream_t st = nullptr;
+  char* dev_ws = nullptr;
+  char* host_stage = nullptr;
+  WsEntry* entry = nullptr;
+};
+
+disc_status acquire(hipStream_t st, const Layout& L, const disc_options* opts, Ctx& cx) {
+  hipError_t e = hipGetDevice(&cx.dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  cx.st = st;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  WsEntry& w = g_ws[{cx.dev, st}];
+  cx.entry = &w;
+  if (!w.ev) {
+    if ((e = hipEventCreateWithFlags(&w.ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  }
+  if (w.ev_pending) {  // the previous call's upload must have consumed the staging buffer
+    if ((e = hipEventSynchronize(w.ev)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    w.ev_pending = false;
+  }
+  if (w.host_bytes < L.staged_end) {
+    if (w.host) (void)hipHostFree(w.host);
+    w.host = nullptr;
+    w.host_bytes = 0;
+    const size_t want = (size_t)round_up((int64_t)(L.staged_end * 5 / 4) + 4096, 4096);
+    if ((e = hipHostMalloc(&w.host, want, hipHostMallocDefault)) != hipSuccess)
+      return fail(DISC_ERR_OUT_OF_MEMORY, "pinned staging of %zu bytes: %s", want, hipGetErrorString(e));
+    w.host_bytes = want;
+  }
+  cx.host_stage = static_cast<char*>(w.host);
+  if (opts && opts->workspace) {
+    if (opts->workspace_bytes < L.total)
+      return fail(DISC_ERR_OUT_OF_MEMORY, "workspace of %zu bytes is smaller than the %zu required", opts->workspace_bytes, L.total);
+    cx.dev_ws = static_cast<char*>(opts->workspace);
+    return DISC_OK;
+  }
+  if (w.dev_bytes < L.total) {
+    if (w.dev) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(w.dev);
+    }
+    w.dev = nullptr;
+    w.dev_bytes = 0;
+    const size_t want = (size_t)round_up((int64_t)(L.total * 5 / 4) + (1 << 20), 1 << 20);
+    if ((e = hipMalloc(&w.dev, want)) != hipSuccess)
+      return fail(DISC_ERR_OUT_OF_MEMORY, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
+    w.dev_bytes = want;
+  }
+  cx.dev_ws = static_cast<char*>(w.dev);
+  return DISC_OK;
+}
+
+disc_status upload(Ctx& cx, const Layout& L) {
+  hipError_t e = hipMemcpyAsync(cx.dev_ws, cx.host_stage, L.staged_end, hipMemcpyHostToDevice, cx.st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if ((e = hipEventRecord(cx.entry->ev, cx.st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  cx.entry->ev_pending = true;
+  return DISC_OK;
+}
+
+Work work_ptrs(char* base, const Layout& L) {
+  Work w;
+  w.bbox = reinterpret_cast<int4*>(base + L.bbox);
+  w.area = reinterpret_cast<int32_t*>(base + L.area);
+  w.meta = reinterpret_cast<int32_t*>(base + L.meta);
+  w.items = reinterpret_cast<int32_t*>(base + L.items);
+  w.counts = reinterpret_cast<int32_t*>(base + L.counts);
+  w.counters = w.counts + 8;
+  w.frame_ctr = reinterpret_cast<uint32_t*>(base + L.frame_ctr);
+  w.psum = reinterpret_cast<float*>(base + L.psum);
+  w.mean = reinterpret_cast<float*>(base + L.mean);
+  w.r = reinterpret_cast<float*>(base + L.r);
+  w.s = reinterpret_cast<float*>(base + L.s);
+  w.W = base + L.W;
+  w.Z = reinterpret_cast<float*>(base + L.Z);
+  w.mstat = reinterpret_cast<int32_t*>(base + L.mstat);
+  w.X = base + L.X;
+  return w;
+}
+
+// --------------------------------------------------------------------------
+// batch description
+// --------------------------------------------------------------------------
+struct FrameIn {
+  const void* tokens = nullptr;
+  const float* scale = nullptr;
+  const uint64_t* bits = nullptr;
+  float* out = nullptr;
+  int32_t* status = nullptr;
+  float* pooled = nullptr;
+  int gh = 0, gw = 0, patch = 16, h = 0, w = 0, m = 0;
+};
+
+struct Plan {
+  Shape shape;
+  Layout L;
+  std::vector<FrameDesc> fds;
+  std::vector<int32_t> mask_frame;
+  std::vector<int4> tiles;
+};
+
+void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p) {
+  Shape& s = p.shape;
+  s.n_frames = (int)fr.size();
+  s.C = C;
+  s.E = E;
+  s.gemm_bf16 = gemm_bf16;
+  int64_t M = 0, sumG = 0, sumMGs = 0;
+  int gmax = 0, nchunk = 1;
+  int64_t item_cap = 1;
+  p.fds.resize(fr.size());
+  for (size_t i = 0; i < fr.size(); ++i) {
+    const FrameIn& f = fr[i];
+    FrameDesc d{};
+    d.tokens = f.tokens;
+    d.scale = f.scale;
+    d.bits = f.bits;
+    d.out = f.out;
+    d.status = f.status;
+    d.pooled = f.pooled;
+    d.gh = f.gh;
+    d.gw = f.gw;
+    d.patch = f.patch;
+    d.G = f.gh * f.gw;
+    d.h = f.h;
+    d.w = f.w;
+    d.wq = (f.w + 63) / 64;
+    d.m = f.m;
+    d.mask_base = (int32_t)M;
+    d.Gs = (int32_t)round_up(d.G, 8);
+    d.w_base = sumMGs;
+    d.r_base = sumG;
+    p.fds[i] = d;
+    for (int j = 0; j < f.m; ++j) p.mask_frame.push_back((int32_t)i);
+    for (int m0 = 0; m0 < f.m; m0 += 64)
+      for (int n0 = 0; n0 < C; n0 += 64) p.tiles.push_back(make_int4((int)i, m0, n0, 0));
+    M += f.m;
+    sumG += d.G;
+    sumMGs += (int64_t)f.m * d.Gs;
+    gmax = std::max(gmax, d.G);
+    nchunk = std::max(nchunk, (d.G + 63) / 64);
+    item_cap += (int64_t)f.m * ((f.w + strip_width(f.patch) - 1) / strip_width(f.patch) + 1);
+  }
+  s.M = M;
+  s.sumG = sumG;
+  s.sumMGs = sumMGs;
+  s.gmax = gmax;
+  s.nchunk = nchunk;
+  s.item_cap = (int)std::min<int64_t>(item_cap, INT32_MAX / 2);
+  s.n_tiles = (int)p.tiles.size();
+  p.L = make_layout(s);
+}
+
+void stage_host(const Plan& p, char* host, char* dev) {
+  std::vector<FrameDesc> fds = p.fds;
+  (void)dev;
+  std::memcpy(host + p.L.frames, fds.data(), sizeof(FrameDesc) * fds.size());
+  if (!p.mask_frame.empty()) std::memcpy(host + p.L.mask_frame, p.mask_frame.data(), 4 * p.mask_frame.size());
+  if (!p.tiles.empty()) std::memcpy(host + p.L.tiles, p.tiles.data(), 16 * p.tiles.size());
+  std::memset(host + p.L.frame_ctr, 0, 4 * (size_t)p.shape.n_frames);
+}
+
+Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int distinct) {
+  Batch b{};
+  b.frames = reinterpret_cast<const FrameDesc*>(dev + p.L.frames);
+  b.mask_frame = reinterpret_cast<const int32_t*>(dev + p.L.mask_frame);
+  b.n_frames = p.shape.n_frames;
+  b.M = (int32_t)p.shape.M;
+  b.C = p.shape.C;
+  b.E = p.shape.E;
+  b.tok_dtype = tok_dtype;
+  b.gemm_bf16 = p.shape.gemm_bf16;
+  b.spatial = spatial;
+  b.distinct = distinct;
+  b.nchunk = p.shape.nchunk;
+  b.item_cap = p.shape.item_cap;
+  return b;
+}
+
+disc_status check_launch(const char* who) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(DISC_ERR_DEVICE, "%s: kernel launch failed: %s", who, hipGetErrorString(e));
+  return DISC_OK;
+}
+
+int resolve_gemm(const disc_options* o, int tok_dtype, int proj_dtype) {
+  const int g = o ? o->gemm_dtype : -1;
+  if (g == DISC_F32) return 0;
+  if (g == DISC_BF16) return 1;
+  return (tok_dtype == DISC_F32 && proj_dtype == DISC_F32) ? 0 : 1;
+}
+
+disc_options defaults() {
+  disc_options o;
+  disc_options_default(&o);
+  return o;
+}
+
+// Validate a ragged batch and describe it.
+disc_status describe(const disc_tokens* tokens, const disc_masks* masks, int32_t n, const disc_proj* proj, disc_out* out,
+                     const disc_options* opts, const char* who, std::vector<FrameIn>& fr) {
+  if (n < 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: negative frame count", who);
+  if (n > 0 && (!tokens || !masks || !out)) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL frame arrays", who);
+  disc_status st;
+  if ((st = check_opts(opts, who))) return st;
+  for (int i = 0; i < n; ++i) {
+    if ((st = check_tokens(&tokens[i], who))) return st;
+    if ((st = check_masks(&masks[i], who))) return st;
+    if ((st = check_grid(&tokens[i], &masks[i], who))) return st;
+    if (tokens[i].c != tokens[0].c) return fail(DISC_ERR_SHAPE, "%s: frames differ in channel count", who);
+    if (tokens[i].dtype != tokens[0].dtype) return fail(DISC_ERR_UNSUPPORTED_DTYPE, "%s: frames differ in token dtype", who);
+  }
+  if (n > 0) {
+    if ((st = check_proj(proj, tokens[0].c, who))) return st;
+    for (int i = 0; i < n; ++i)
+      if ((st = check_out(&out[i], masks[i].m, proj->e, who))) return st;
+  }
+  fr.resize(n);
+  for (int i = 0; i < n; ++i) {
+    FrameIn& f = fr[i];
+    f.tokens = tokens[i].data;
+    f.scale = tokens[i].scale;
+    f.bits = masks[i].bits;
+    f.out = out[i].data;
+    f.status = out[i].mask_status;
+    f.pooled = out[i].pooled;
+    f.gh = tokens[i].gh;
+    f.gw = tokens[i].gw;
+    f.patch = tokens[i].patch;
+    f.h = masks[i].h;
+    f.w = masks[i].w;
+    f.m = masks[i].m;
+  }
+  return DISC_OK;
+}
+
+
+// --------------------------------------------------------------------------
+// per-stage tracing: events around each stage on the caller's stream
+// --------------------------------------------------------------------------
+enum Stage { ST_SCAN = 0, ST_PLAN, ST_STATS, ST_EDT, ST_WEIGHTS, ST_POOL, ST_PROJ, ST_COUNT };
+const char* kStageNames[ST_COUNT] = {"scan", "plan", "token_stats", "edt", "weights", "pool", "proj"};
+
+struct TraceRec {
+  int stage;
+  hipEvent_t a, b;
+};
+std::mutex g_tr_mu;
+bool g_trace_on = false;
+std::vector<TraceRec> g_tr_pending;
+std::vector<hipEvent_t> g_tr_free;
+double g_tr_ms[ST_COUNT] = {};
+int64_t g_tr_n[ST_COUNT] = {};
+
+hipEvent_t tr_event() {
+  if (!g_tr_free.empty()) {
+    hipEvent_t e = g_tr_free.back();
+    g_tr_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+struct StageTimer {
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  StageTimer(int s, hipStream_t stream) : stage(s), st(stream) {
+    std::lock_guard<std::mutex> lk(g_tr_mu);
+    if (!g_trace_on) return;
+    a = tr_event();
+    (void)hipEventRecord(a, st);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_tr_mu);
+    hipEvent_t b = tr_event();
+    (void)hipEventRecord(b, st);
+    g_tr_pending.push_back({stage, a, b});
+  }
+};
+
+void tr_collect() {
+  std::lock_guard<std::mutex> lk(g_tr_mu);
+  for (auto& r : g_tr_pending) {
+    (void)hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      g_tr_ms[r.stage] += ms;
+      g_tr_n[r.stage] += 1;
+    }
+    g_tr_free.push_back(r.a);
+    g_tr_free.push_back(r.b);
+  }
+  g_tr_pending.clear();
+}
+
+}  // namespace
+
+// ==========================================================================
+// exported entry points
+// ==========================================================================
+extern "C" {
+
+void disc_options_default(disc_options* o) {
+  if (!o) return;
+  o->spatial = DISC_SPATIAL_EDT;
+  o->distinct = 1;
+  o->eps = 1e-6f;
+  o->gemm_dtype = -1;
+  o->workspace = nullptr;
+  o->workspace_bytes = 0;
+}
+
+int32_t disc_abi_version(void) { return DISC_ABI_VERSION; }
+
+const char* disc_last_error(void) { return g_err.c_str(); }
+
+size_t disc_workspace_bytes(const disc_tokens* tokens, const disc_masks* masks, int32_t n_frames, const disc_proj* proj,
+                            const disc_options* opts) {
+  std::vector<FrameIn> fr;
+  std::vector<disc_out> outs(std::max(n_frames, 0));
+  for (int i = 0; i < n_frames && masks; ++i) {
+    outs[i].data = reinterpret_cast<float*>(16);
+    outs[i].m = masks[i].m;
+    outs[i].e = proj ? proj->e : 0;
+    outs[i].mask_status = nullptr;
+    outs[i].pooled = nullptr;
+  }
+  if (describe(tokens, masks, n_frames, proj, outs.data(), opts, "disc_workspace_bytes", fr) != DISC_OK) return 0;
+  if (n_frames == 0) return 0;
+  Plan p;
+  build_plan(fr, tokens[0].c, proj->e, resolve_gemm(opts, tokens[0].dtype, proj->dtype), p);
+  return p.L.total;
+}
+
+disc_status disc_embed_frames(const disc_tokens* tokens, const disc_masks* masks, int32_t n_frames, const disc_proj* proj,
+                              disc_out* out, const disc_options* opts, void* stream) {
+  const char* who = "disc_embed_frames";
+  std::vector<FrameIn> fr;
+  disc_status st = describe(tokens, masks, n_frames, proj, out, opts, who, fr);
+  if (st) return st;
+  const disc_options o = opts ? *opts : defaults();
+  int64_t M = 0;
+  for (auto& f : fr) M += f.m;
+  if (n_frames == 0 || M == 0) return ok();
+  Plan p;
+  build_plan(fr, tokens[0].c, proj->e, resolve_gemm(&o, tokens[0].dtype, proj->dtype), p);
+  Ctx cx;
+  if ((st = acquire(static_cast<hipStream_t>(stream), p.L, &o, cx))) return st;
+  stage_host(p, cx.host_stage, cx.dev_ws);
+  if ((st = upload(cx, p.L))) return st;
+  const Batch b = make_batch(p, cx.dev_ws, tokens[0].dtype, o.spatial, o.distinct);
+  const Work w = work_ptrs(cx.dev_ws, p.L);
+  const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
+  { StageTimer t(ST_SCAN, cx.st); launch_scan(b, w, cx.st); }
+  { StageTimer t(ST_PLAN, cx.st); launch_plan(b, w, cx.st); }
+  if (o.distinct) { StageTimer t(ST_STATS, cx.st); launch_token_stats(b, w, p.shape.gmax, cx.st); }
+  { StageTimer t(ST_EDT, cx.st); launch_edt(b, w, nullptr, num_cus(cx.dev), cx.st); }
+  { StageTimer t(ST_WEIGHTS, cx.st); launch_weights(b, w, cx.st); }
+  { StageTimer t(ST_POOL, cx.st); launch_pool(b, w, tiles, p.shape.n_tiles, cx.st); }
+  { StageTimer t(ST_PROJ, cx.st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, cx.st); }
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_embed_masks_ex(const disc_tokens* tokens, const disc_masks* masks, const disc_proj* proj, disc_out* out,
+                                const disc_options* opts, void* stream) {
+  return disc_embed_frames(tokens, masks, 1, proj, out, opts, stream);
+}
+
+disc_status disc_embed_masks(const disc_tokens* tokens, const disc_masks* masks, const disc_proj* proj, disc_out* out) {
+  return disc_embed_frames(tokens, masks, 1, proj, out, nullptr, nullptr);
+}
+
+disc_status disc_release_workspace(void) {
+  (void)hipDeviceSynchronize();
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (auto& kv : g_ws) {
+    if (kv.second.dev) (void)hipFree(kv.second.dev);
+    if (kv.second.host) (void)hipHostFree(kv.second.host);
+    if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
+  }
+  g_ws.clear();
+  return ok();
+}
+
+disc_status disc_edt_sq(const disc_masks* masks, int32_t* e, void* stream) {
+  const char* who = "disc_edt_sq";
+  disc_status st;
+  if ((st = check_masks(masks, who))) return st;
+  if (masks->m == 0) return ok();
+  if (!e) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: e is NULL", who);
+  if (!aligned16(e)) return fail(DISC_ERR_ALIGNMENT, "%s: e must be 16-byte aligned", who);
+  FrameIn f;
+  f.bits = masks->bits;
+  f.patch = 16;
+  f.h = masks->h;
+  f.w = masks->w;
+  f.gh = (f.h + 15) / 16;
+  f.gw = (f.w + 15) / 16;
+  f.m = masks->m;
+  Plan p;
+  build_plan({f}, 64, 128, 0, p);
+  Ctx cx;
+  if ((st = acquire(static_cast<hipStream_t>(stream), p.L, nullptr, cx))) return st;
+  stage_host(p, cx.host_stage, cx.dev_ws);
+  if ((st = upload(cx, p.L))) return st;
+  const Batch b = make_batch(p, cx.dev_ws, DISC_F32, DISC_SPATIAL_EDT, 0);
+  const Work w = work_ptrs(cx.dev_ws, p.L);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(e), 0u, (int64_t)masks->m * masks->h * masks->w, cx.st);
+  launch_scan(b, w, cx.st);
+  launch_plan(b, w, cx.st);
+  launch_edt(b, w, e, num_cus(cx.dev), cx.st);
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_patch_weights(const disc_tokens* tokens, const disc_masks* masks, int32_t patch, const disc_options* opts,
+                               float* wout, void* stream) {
+  const char* who = "disc_patch_weights";
+  disc_status st;
+  if ((st = check_opts(opts, who))) return st;
+  const disc_options o = opts ? *opts : defaults();
+  if ((st = check_masks(masks, who))) return st;
+  if (patch < kMinPatch || patch > kMaxPatch) return fail(DISC_ERR_LIMIT, "%s: patch %d outside [%d, %d]", who, patch, kMinPatch, kMaxPatch);
+  if (o.distinct) {
+    if ((st = check_tokens(tokens, who))) return st;
+    if (tokens->patch != patch) return fail(DISC_ERR_SHAPE, "%s: patch %d differs from tokens->patch %d", who, patch, tokens->patch);
+    if ((st = check_grid(tokens, masks, who))) return st;
+  }
+  if (masks->m == 0) return ok();
+  if (!wout) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: w is NULL", who);
+  if (!aligned16(wout)) return fail(DISC_ERR_ALIGNMENT, "%s: w must be 16-byte aligned", who);
+  FrameIn f;
+  f.bits = masks->bits;
+  f.patch = patch;
+  f.h = masks->h;
+  f.w = masks->w;
+  f.gh = (f.h + patch - 1) / patch;
+  f.gw = (f.w + patch - 1) / patch;
+  f.m = masks->m;
+  if (o.distinct) {
+    f.tokens = tokens->data;
+    f.scale = tokens->scale;
+  }
+  const int C = o.distinct ? tokens->c : 64;
+  Plan p;
+  build_plan({f}, C, 128, 0, p);
+  Ctx cx;
+  if ((st = acquire(static_cast<hipStream_t>(stream), p.L, nullptr, cx))) return st;
+  stage_host(p, cx.host_stage, cx.dev_ws);
+  if ((st = upload(cx, p.L))) return st;
+  const Batch b = make_batch(p, cx.dev_ws, o.distinct ? tokens->dtype : DISC_F32, o.spatial, o.distinct);
+  const Work w = work_ptrs(cx.dev_ws, p.L);
+  launch_scan(b, w, cx.st);
+  launch_plan(b, w, cx.st);
+  if (o.distinct) launch_token_stats(b, w, p.shape.gmax, cx.st);
+  launch_edt(b, w, nullptr, num_cus(cx.dev), cx.st);
+  launch_dense_weights(b, w, wout, o.eps, cx.st);
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_token_stats(const disc_tokens* tokens, float eps, float* mean, float* r, float* D, void* stream) {
+  const char* who = "disc_token_stats";
+  disc_status st;
+  if ((st = check_tokens(tokens, who))) return st;
+  if (!(eps >= 0.f)) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: eps must be >= 0", who);
+  if ((mean && !aligned16(mean)) || (r && !aligned16(r)) || (D && !aligned16(D)))
+    return fail(DISC_ERR_ALIGNMENT, "%s: outputs must be 16-byte aligned", who);
+  FrameIn f;
+  f.tokens = tokens->data;
+  f.scale = tokens->scale;
+  f.gh = tokens->gh;
+  f.gw = tokens->gw;
+  f.patch = tokens->patch;
+  f.h = tokens->gh * tokens->patch;
+  f.w = tokens->gw * tokens->patch;
+  f.m = 0;
+  Plan p;
+  build_plan({f}, tokens->c, 128, 0, p);
+  Ctx cx;
+  if ((st = acquire(static_cast<hipStream_t>(stream), p.L, nullptr, cx))) return st;
+  stage_host(p, cx.host_stage, cx.dev_ws);
+  if ((st = upload(cx, p.L))) return st;
+  const Batch b = make_batch(p, cx.dev_ws, tokens->dtype, 0, 1);
+  const Work w = work_ptrs(cx.dev_ws, p.L);
+  const int G = tokens->gh * tokens->gw;
+  launch_token_stats(b, w, G, cx.st);
+  if (mean) launch_copy_f32(w.mean, mean, tokens->c, cx.st);
+  if (r) launch_copy_f32(w.r, r, G, cx.st);
+  if (D) launch_d_from_r(w.r, G, eps, D, cx.st);
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32_t m, const disc_proj* proj, disc_out* out,
+                              int32_t gemm_dtype, void* stream) {
+  const char* who = "disc_pool_project";
+  disc_status st;
+  if ((st = check_tokens(tokens, who))) return st;
+  if (m < 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: negative mask count", who);
+  if ((st = check_proj(proj, tokens->c, who))) return st;
+  if ((st = check_out(out, m, proj->e, who))) return st;
+  if (gemm_dtype != -1 && gemm_dtype != DISC_F32 && gemm_dtype != DISC_BF16)
+    return fail(DISC_ERR_UNSUPPORTED_DTYPE, "%s: gemm dtype must be F32, BF16 or -1", who);
+  if (m == 0) return ok();
+  if (!wts) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: w is NULL", who);
+  if (!aligned16(wts)) return fail(DISC_ERR_ALIGNMENT, "%s: w must be 16-byte aligned", who);
+  disc_options o = defaults();
+  o.gemm_dtype = gemm_dtype;
+  FrameIn f;
+  f.tokens = tokens->data;
+  f.scale = tokens->scale;
+  f.gh = tokens->gh;
+  f.gw = tokens->gw;
+  f.patch = tokens->patch;
+  f.h = tokens->gh * tokens->patch;
+  f.w = tokens->gw * tokens->patch;
+  f.m = m;
+  f.out = out->data;
+  f.status = out->mask_status;
+  f.pooled = out->pooled;
+  Plan p;
+  build_plan({f}, tokens->c, proj->e, resolve_gemm(&o, tokens->dtype, proj->dtype), p);
+  Ctx cx;
+  if ((st = acquire(static_cast<hipStream_t>(stream), p.L, nullptr, cx))) return st;
+  stage_host(p, cx.host_stage, cx.dev_ws);
+  if ((st = upload(cx, p.L))) return st;
+  const Batch b = make_batch(p, cx.dev_ws, tokens->dtype, 0, 1);
+  const Work w = work_ptrs(cx.dev_ws, p.L);
+  const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
+  launch_user_weights(b, w, wts, cx.st);
+  launch_pool(b, w, tiles, p.shape.n_tiles, cx.st);
+  launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, cx.st);
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_pack_masks(const uint8_t* u8, int32_t m, int32_t h, int32_t w, uint64_t* bits, void* stream) {
+  const char* who = "disc_pack_masks";
+  if (m < 0 || h <= 0 || w <= 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: bad shape %dx%dx%d", who, m, h, w);
+  if (m == 0) return ok();
+  if (!u8 || !bits) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL pointer", who);
+  if (!aligned16(bits)) return fail(DISC_ERR_ALIGNMENT, "%s: bits must be 16-byte aligned", who);
+  launch_pack(u8, m, h, w, bits, static_cast<hipStream_t>(stream));
+  disc_status st;
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+}  // extern "C"
+
+extern "C" {
+
+void disc_trace_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_tr_mu);
+  g_trace_on = on != 0;
+}
+
+void disc_trace_reset(void) {
+  tr_collect();
+  std::lock_guard<std::mutex> lk(g_tr_mu);
+  for (int i = 0; i < ST_COUNT; ++i) {
+    g_tr_ms[i] = 0.0;
+    g_tr_n[i] = 0;
+  }
+}
+
+int32_t disc_trace_read(int32_t stage, double* total_ms, int64_t* count) {
+  if (stage < 0 || stage >= ST_COUNT) return -1;
+  tr_collect();
+  std::lock_guard<std::mutex> lk(g_tr_mu);
+  if (total_ms) *total_ms = g_tr_ms[stage];
+  if (count) *count = g_tr_n[stage];
+  return 0;
+}
+
+const char* disc_trace_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < ST_COUNT) ? kStageNames[stage] : nullptr;
+}
+
+}  // extern "C"

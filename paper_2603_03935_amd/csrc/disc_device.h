@@ -1,0 +1,103 @@
+// Internal declarations shared by the libdisc HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace disc {
+
+// ---------------------------------------------------------------------------
+// Distance-transform work decomposition.
+//
+// A work item is (mask, strip): SW(P) = 64 - 64 % P consecutive pixel columns
+// starting on a patch boundary, processed by one workgroup whose wavefronts
+// each own a band of kBand rows of the mask's bounding box (plus one padding
+// row above and below).  The row count n = bbox height + 2 picks the class,
+// i.e. the workgroup size (K bands) and the LDS footprint.
+// ---------------------------------------------------------------------------
+constexpr int kBand = 96;      // rows per band: 3 x 32-bit stack-bitmap words per lane
+constexpr int kClasses = 5;
+__host__ __device__ constexpr int class_bands(int c) { return c == 0 ? 1 : c == 1 ? 2 : c == 2 ? 4 : c == 3 ? 8 : 12; }
+__host__ __device__ constexpr int class_rows(int c) { return c == 4 ? 1120 : class_bands(c) * kBand; }
+constexpr int kMaxRows = 1120;      // bbox height + 2
+constexpr int kMinPatch = 8;
+constexpr int kMaxPatch = 64;
+constexpr int kItemStripBits = 8;   // item = (mask << 8) | strip
+constexpr int kMaxC = 2048;
+
+__host__ __device__ inline int strip_width(int patch) { return 64 - (64 % patch); }
+
+// LDS layout of one EDT workgroup for a class with `rows` capacity.
+__host__ __device__ inline int edt_g_bytes(int rows) { return rows * 64 * 2; }         // int16 g[rows][64]
+__host__ __device__ inline int edt_bm_words(int rows) { return (rows + 31) / 32; }
+__host__ __device__ inline int edt_bm_bytes(int rows) { return edt_bm_words(rows) * 64 * 4; }  // u32 bm[words][64]
+__host__ __device__ inline int edt_part_rows(int rows) { return rows / kMinPatch + 3; }
+__host__ __device__ inline int edt_part_bytes(int rows) { return edt_part_rows(rows) * 8 * 2 * 4; }  // f32 [pr][8][2]
+__host__ __device__ inline int edt_lds_bytes(int rows) {
+  return edt_g_bytes(rows) + edt_bm_bytes(rows) + edt_part_bytes(rows);
+}
+
+// One frame of a (possibly ragged) batch, in device memory.
+struct FrameDesc {
+  const void* tokens;     // [G][C] in tok_dtype
+  const float* scale;     // [G] for FP8 tokens
+  const uint64_t* bits;   // [m][h][wq]
+  float* out;             // [m][E]
+  int32_t* status;        // [m] or null
+  float* pooled;          // [m][C] or null
+  int32_t gh, gw, patch, G;
+  int32_t h, w, wq, m;
+  int32_t mask_base;      // global index of this frame's first mask
+  int32_t Gs;             // row stride of the per-mask weight rows (G rounded up to 8)
+  int64_t w_base;         // element offset of this frame's [m][Gs] block in s/W
+  int64_t r_base;         // offset of this frame's G entries in r
+};
+
+// Scalar arguments shared by the kernels of one call.
+struct Batch {
+  const FrameDesc* frames;
+  const int32_t* mask_frame;  // [M] frame of each global mask
+  int32_t n_frames, M, C, E;
+  int32_t tok_dtype;          // disc_dtype of the tokens
+  int32_t gemm_bf16;          // 1: BF16 operands, 0: FP32 operands
+  int32_t spatial, distinct;
+  int32_t nchunk;             // token-statistics chunks per frame (capacity)
+  int32_t item_cap;           // capacity of each class's work list
+};
+
+// Workspace pointers (device).
+struct Work {
+  int4* bbox;          // [M] (y0, y1, x0, x1); y0 > y1 for an empty mask
+  int32_t* area;       // [M]
+  int32_t* meta;       // [M] (class << 16) | strips, -1 empty
+  int32_t* items;      // [kClasses][item_cap]
+  int32_t* counts;     // [kClasses] items per class
+  int32_t* counters;   // [kClasses] dynamic work counters
+  uint32_t* frame_ctr; // [F] last-block tickets of the token statistics
+  float* psum;         // [F][nchunk][C]
+  float* mean;         // [F][C]
+  float* r;            // [sum G]
+  float* s;            // [sum m*Gs] spatial weights
+  void* W;             // [sum m*Gs] GEMM-dtype weights
+  float* Z;            // [M] weight sums
+  int32_t* mstat;      // [M] 0 ok, 1 empty
+  void* X;             // [M][C] pooled features in the GEMM dtype
+};
+
+// Host-side launchers (stream = hipStream_t).
+void launch_scan(const Batch& b, const Work& w, hipStream_t st);
+void launch_plan(const Batch& b, const Work& w, hipStream_t st);
+void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st);
+void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st);
+void launch_weights(const Batch& b, const Work& w, hipStream_t st);
+void launch_pool(const Batch& b, const Work& w, const int4* tiles, int n_tiles, hipStream_t st);
+void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st);
+// stage helpers
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+void launch_pack(const uint8_t* u8, int m, int h, int w, uint64_t* bits, hipStream_t st);
+void launch_dense_weights(const Batch& b, const Work& w, float* out, float eps, hipStream_t st);
+void launch_d_from_r(const float* r, int G, float eps, float* D, hipStream_t st);
+void launch_user_weights(const Batch& b, const Work& w, const float* wts, hipStream_t st);
+void launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st);
+
+}  // namespace disc

@@ -1,0 +1,206 @@
+// Mask scan (bounding box + area per mask) and the work planner of the
+// distance transform; also the bit-packing and fill helpers.
+#include "disc_device.h"
+
+namespace disc {
+
+// ---------------------------------------------------------------------------
+// k_scan: one workgroup per mask streams the mask's h*wq words once (the only
+// full read of the mask bits) and reduces min/max row, min/max column and the
+// pixel count.  Columns >= w in the last word of a row are ignored.
+// ---------------------------------------------------------------------------
+__device__ inline int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline int wave_sum(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
+  const int g = blockIdx.x;
+  if (g >= b.M) return;
+  const FrameDesc fd = b.frames[b.mask_frame[g]];
+  const int wq = fd.wq, h = fd.h;
+  const uint64_t* mb = fd.bits + (int64_t)(g - fd.mask_base) * h * wq;
+  const uint64_t last_valid = (fd.w & 63) ? ((1ull << (fd.w & 63)) - 1) : ~0ull;
+  const int64_t nwords = (int64_t)h * wq;
+
+  int ymin = INT32_MAX, ymax = -1, xmin = INT32_MAX, xmax = -1, area = 0;
+  // walk words tid, tid+256, ... keeping (row, word) without a division per word
+  int row = threadIdx.x / wq, k = threadIdx.x % wq;
+  const int drow = 256 / wq, dk = 256 % wq;
+  for (int64_t i = threadIdx.x; i < nwords; i += 256) {
+    uint64_t v = __builtin_nontemporal_load(mb + i);
+    if (k == wq - 1) v &= last_valid;
+    if (v) {
+      ymin = min(ymin, row);
+      ymax = max(ymax, row);
+      xmin = min(xmin, 64 * k + __builtin_ctzll(v));
+      xmax = max(xmax, 64 * k + 63 - __builtin_clzll(v));
+      area += __builtin_popcountll(v);
+    }
+    row += drow;
+    k += dk;
+    if (k >= wq) {
+      k -= wq;
+      row += 1;
+    }
+  }
+  ymin = wave_min(ymin);
+  ymax = wave_max(ymax);
+  xmin = wave_min(xmin);
+  xmax = wave_max(xmax);
+  area = wave_sum(area);
+  __shared__ int red[4][5];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wv][0] = ymin;
+    red[wv][1] = ymax;
+    red[wv][2] = xmin;
+    red[wv][3] = xmax;
+    red[wv][4] = area;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 4; ++i) {
+      ymin = min(ymin, red[i][0]);
+      ymax = max(ymax, red[i][1]);
+      xmin = min(xmin, red[i][2]);
+      xmax = max(xmax, red[i][3]);
+      area += red[i][4];
+    }
+    int meta = -1;
+    if (area > 0) {
+      const int P = fd.patch, SW = strip_width(P);
+      const int xs0 = (xmin / P) * P;
+      const int strips = (xmax + 1 - xs0 + SW - 1) / SW;
+      const int n = ymax - ymin + 3;
+      int cls = kClasses;
+      for (int c = 0; c < kClasses; ++c)
+        if (n <= class_rows(c)) {
+          cls = c;
+          break;
+        }
+      meta = (cls << 16) | strips;  // cls == kClasses would mean "too tall": rejected on the host
+      wk.bbox[g] = make_int4(ymin, ymax, xmin, xmax);
+    } else {
+      wk.bbox[g] = make_int4(1, 0, 1, 0);
+    }
+    wk.area[g] = area;
+    wk.meta[g] = meta;
+  }
+}
+
+void launch_scan(const Batch& b, const Work& w, hipStream_t st) {
+  if (b.M > 0) hipLaunchKernelGGL(k_scan, dim3(b.M), dim3(256), 0, st, b, w);
+}
+
+// ---------------------------------------------------------------------------
+// k_plan: one workgroup turns the per-mask strip counts into one work list per
+// class (mask-major, strip-minor) and resets the dynamic work counters.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_plan(Batch b, Work wk) {
+  __shared__ int wsum[16];
+  __shared__ int base_sh;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int c = 0; c < kClasses; ++c) {
+    if (tid == 0) base_sh = 0;
+    __syncthreads();
+    for (int g0 = 0; g0 < b.M; g0 += 1024) {
+      const int g = g0 + tid;
+      int cnt = 0;
+      if (g < b.M) {
+        const int meta = wk.meta[g];
+        if (meta >= 0 && (meta >> 16) == c) cnt = meta & 0xFFFF;
+      }
+      // inclusive scan within the wave
+      int incl = cnt;
+      for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+      }
+      if (lane == 63) wsum[wv] = incl;
+      __syncthreads();
+      int before = base_sh;
+      for (int i = 0; i < wv; ++i) before += wsum[i];
+      const int off = before + incl - cnt;
+      int32_t* list = wk.items + (int64_t)c * b.item_cap;
+      for (int j = 0; j < cnt; ++j)
+        if (off + j < b.item_cap) list[off + j] = (g << kItemStripBits) | j;
+      __syncthreads();
+      if (tid == 0) {
+        int tot = 0;
+        for (int i = 0; i < 16; ++i) tot += wsum[i];
+        base_sh += tot;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      wk.counts[c] = min(base_sh, b.item_cap);
+      wk.counters[c] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_plan(const Batch& b, const Work& w, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, b, w);
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
+}
+
+__global__ void k_copy_f32(const float* src, float* dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+void launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
+}
+
+// one thread per output word: 64 bytes -> 64 bits
+__global__ void k_pack(const uint8_t* u8, int m, int h, int w, uint64_t* bits) {
+  const int wq = (w + 63) / 64;
+  const int64_t nwords = (int64_t)m * h * wq;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rowi = i / wq;
+    const int k = (int)(i - rowi * wq);
+    const uint8_t* src = u8 + rowi * w + 64 * k;
+    const int nb = min(64, w - 64 * k);
+    uint64_t v = 0;
+    for (int j = 0; j < nb; ++j) v |= (uint64_t)(src[j] != 0) << j;
+    bits[i] = v;
+  }
+}
+
+void launch_pack(const uint8_t* u8, int m, int h, int w, uint64_t* bits, hipStream_t st) {
+  const int64_t nwords = (int64_t)m * h * ((w + 63) / 64);
+  if (nwords <= 0) return;
+  int64_t blocks = (nwords + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, st, u8, m, h, w, bits);
+}
+
+}  // namespace disc

@@ -1,0 +1,339 @@
+// Token statistics of Eq. (1) (arXiv 2603.03935, Sec. III-C) and the per-mask
+// weight finalisation.
+//
+// Eq. (1): D_p = ||f_p - mean|| / (mean_q ||f_q - mean|| + eps).  Inside the
+// weighted mean of the tokens every weight carries the same factor
+// 1/(mean r + eps), which cancels, so the fused path weights with
+// r_p = ||f_p - mean|| directly; D itself is produced only for the stage entry
+// point.  Statistics are per frame (batching never mixes frames).
+#include "disc_device.h"
+
+namespace disc {
+
+constexpr int kChunk = 64;  // tokens per partial-sum chunk
+
+// OCP e4m3fn code -> float (exact)
+__device__ __forceinline__ float e4m3_to_f32(uint32_t code) {
+  const uint32_t sign = (code & 0x80u) << 24;
+  const uint32_t mag = code & 0x7Fu;
+  if (mag == 0x7Fu) return __builtin_nanf("");
+  if (mag >= 8u) return __uint_as_float(sign | ((mag << 20) + (120u << 23)));
+  const float v = (float)mag * 0x1p-9f;
+  return sign ? -v : v;
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+// four consecutive channels of token p as floats (value = scale * code for FP8)
+__device__ __forceinline__ float4 load4(const void* base, int dtype, const float* scale, int64_t p, int C, int c) {
+  const int64_t off = p * C + c;
+  if (dtype == 0) return *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(base) + off);
+  if (dtype == 1) {
+    const uint2 v = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(base) + off);
+    return make_float4(bf16_to_f32(v.x & 0xFFFFu), bf16_to_f32(v.x >> 16), bf16_to_f32(v.y & 0xFFFFu),
+                       bf16_to_f32(v.y >> 16));
+  }
+  const uint32_t v = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(base) + off);
+  const float s = scale[p];
+  return make_float4(s * e4m3_to_f32(v & 0xFFu), s * e4m3_to_f32((v >> 8) & 0xFFu), s * e4m3_to_f32((v >> 16) & 0xFFu),
+                     s * e4m3_to_f32(v >> 24));
+}
+
+// Partial channel sums over chunks of 64 tokens; the last chunk of a frame to
+// finish folds the partials (fixed order) into the frame mean.
+__global__ __launch_bounds__(256) void k_colsum(Batch b, Work wk) {
+  const int f = blockIdx.y, chunk = blockIdx.x;
+  const FrameDesc fd = b.frames[f];
+  const int G = fd.G, C = b.C;
+  const int nch = (G + kChunk - 1) / kChunk;
+  if (chunk >= nch) return;
+  const int p0 = chunk * kChunk, p1 = min(p0 + kChunk, G);
+  float* ps = wk.psum + ((int64_t)f * b.nchunk + chunk) * C;
+  for (int c = threadIdx.x * 4; c < C; c += 1024) {
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int p = p0; p < p1; ++p) {
+      const float4 v = load4(fd.tokens, b.tok_dtype, fd.scale, p, C, c);
+      a.x += v.x;
+      a.y += v.y;
+      a.z += v.z;
+      a.w += v.w;
+    }
+    *reinterpret_cast<float4*>(ps + c) = a;
+  }
+  __threadfence();
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(wk.frame_ctr + f, 1u) == (unsigned)(nch - 1));
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const float inv = 1.0f / (float)G;
+  for (int c = threadIdx.x; c < C; c += 256) {
+    float a = 0.f;
+    for (int j = 0; j < nch; ++j) a += __builtin_nontemporal_load(wk.psum + ((int64_t)f * b.nchunk + j) * C + c);
+    wk.mean[(int64_t)f * C + c] = a * inv;
+  }
+  if (threadIdx.x == 0) wk.frame_ctr[f] = 0u;
+}
+
+// r_p = ||f_p - mean||: one wavefront per token, lanes over channels.
+__global__ __launch_bounds__(256) void k_rnorm(Batch b, Work wk) {
+  const int f = blockIdx.y;
+  const FrameDesc fd = b.frames[f];
+  const int G = fd.G, C = b.C;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const float* mu = wk.mean + (int64_t)f * C;
+  for (int p = blockIdx.x * 16 + wv; p < min(G, (int)(blockIdx.x + 1) * 16); p += 4) {
+    float a = 0.f;
+    for (int c = lane * 4; c < C; c += 256) {
+      const float4 v = load4(fd.tokens, b.tok_dtype, fd.scale, p, C, c);
+      const float4 m = *reinterpret_cast<const float4*>(mu + c);
+      const float dx = v.x - m.x, dy = v.y - m.y, dz = v.z - m.z, dw = v.w - m.w;
+      a += dx * dx + dy * dy + dz * dz + dw * dw;
+    }
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (lane == 0) wk.r[fd.r_base + p] = __builtin_sqrtf(a);
+  }
+}
+
+void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st) {
+  hipLaunchKernelGGL(k_colsum, dim3(b.nchunk, b.n_frames), dim3(256), 0, st, b, w);
+  hipLaunchKernelGGL(k_rnorm, dim3((gmax + 15) / 16, b.n_frames), dim3(256), 0, st, b, w);
+}
+
+// D = r / (mean(r) + eps) for one frame (stage entry point only).
+__global__ __launch_bounds__(1024) void k_d_from_r(const float* r, int G, float eps, float* D) {
+  __shared__ float red[16];
+  float a = 0.f;
+  for (int p = threadIdx.x; p < G; p += 1024) a += r[p];
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  float tot = 0.f;
+  for (int i = 0; i < 16; ++i) tot += red[i];
+  const float denom = tot / (float)G + eps;
+  for (int p = threadIdx.x; p < G; p += 1024) D[p] = r[p] / denom;
+}
+
+void launch_d_from_r(const float* r, int G, float eps, float* D, hipStream_t st) {
+  hipLaunchKernelGGL(k_d_from_r, dim3(1), dim3(1024), 0, st, r, G, eps, D);
+}
+
+// ---------------------------------------------------------------------------
+// Weight finalisation, one workgroup per mask.
+//   w_p = s_p * r_p (distinct) or s_p, times scale_p for FP8 tokens (the GEMM
+//   then multiplies the raw e4m3 codes), rounded to the GEMM operand type and
+//   written as a dense row (zeros outside the mask's patch rectangle).
+//   Z = sum of the rounded weights (per token value: w_p / scale_p for FP8) in
+//   compensated (Neumaier) FP32 summation.  Z == 0 with a non-empty mask and
+//   distinctiveness on (every touched patch equals the frame mean) falls back
+//   to w = s.
+// ---------------------------------------------------------------------------
+struct Neu {
+  float s, c;
+};
+__device__ __forceinline__ void neu_add(Neu& a, float x) {
+  const float t = a.s + x;
+  if (fabsf(a.s) >= fabsf(x))
+    a.c += (a.s - t) + x;
+  else
+    a.c += (x - t) + a.s;
+  a.s = t;
+}
+__device__ __forceinline__ Neu neu_merge(Neu a, Neu b) {
+  neu_add(a, b.s);
+  a.c += b.c;
+  return a;
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  const uint32_t lsb = (u >> 16) & 1u;
+  return (uint16_t)((u + 0x7FFFu + lsb) >> 16);  // finite, non-negative weights only
+}
+
+template <int BF16>
+__device__ float write_row(const Batch& b, const Work& wk, const FrameDesc& fd, int64_t rowoff, int pr0, int pr1,
+                           int pc0, int pc1, bool use_r, Neu& z, float& ssum) {
+  const int G = fd.G, gw = fd.gw;
+  const bool fp8 = b.tok_dtype == 2;
+  const float* r = wk.r + fd.r_base;
+  int pr = threadIdx.x / gw, pc = threadIdx.x % gw;
+  const int dpr = 256 / gw, dpc = 256 % gw;
+  for (int p = threadIdx.x; p < G; p += 256) {
+    float wv = 0.f;
+    if (pr >= pr0 && pr <= pr1 && pc >= pc0 && pc <= pc1) {
+      const float sv = wk.s[rowoff + p];
+      ssum += sv;
+      wv = use_r ? sv * r[p] : sv;
+      if (fp8) wv *= fd.scale[p];
+    }
+    float wr;
+    if (BF16) {
+      const uint16_t hb = f32_to_bf16_rne(wv);
+      reinterpret_cast<uint16_t*>(wk.W)[rowoff + p] = hb;
+      wr = __uint_as_float((uint32_t)hb << 16);
+    } else {
+      reinterpret_cast<float*>(wk.W)[rowoff + p] = wv;
+      wr = wv;
+    }
+    if (wr != 0.f) neu_add(z, fp8 ? wr / fd.scale[p] : wr);
+    pc += dpc;
+    pr += dpr;
+    if (pc >= gw) {
+      pc -= gw;
+      pr += 1;
+    }
+  }
+  return 0.f;
+}
+
+__device__ Neu block_neu(Neu z, float* red) {
+  // wave butterfly, then the four waves in order
+  for (int o = 32; o > 0; o >>= 1) {
+    Neu t;
+    t.s = __shfl_xor(z.s, o);
+    t.c = __shfl_xor(z.c, o);
+    // combine in a lane-independent order so every lane holds the same value
+    const int lane = threadIdx.x & 63;
+    z = (lane & o) ? neu_merge(t, z) : neu_merge(z, t);
+  }
+  const int wv = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[wv * 2] = z.s;
+    red[wv * 2 + 1] = z.c;
+  }
+  __syncthreads();
+  Neu tot{red[0], red[1]};
+  for (int i = 1; i < 4; ++i) tot = neu_merge(tot, Neu{red[2 * i], red[2 * i + 1]});
+  return tot;
+}
+
+template <int BF16>
+__global__ __launch_bounds__(256) void k_weights(Batch b, Work wk) {
+  const int g = blockIdx.x;
+  if (g >= b.M) return;
+  const FrameDesc fd = b.frames[b.mask_frame[g]];
+  const int64_t rowoff = fd.w_base + (int64_t)(g - fd.mask_base) * fd.Gs;
+  const int4 bb = wk.bbox[g];
+  const int P = fd.patch;
+  int pr0 = bb.x / P, pr1 = bb.y / P, pc0 = bb.z / P, pc1 = bb.w / P;
+  const bool empty = bb.x > bb.y;
+  if (empty) pr1 = -1;
+  __shared__ float red[8];
+  __shared__ float ssum_sh[4];
+  Neu z{0.f, 0.f};
+  float ssum = 0.f;
+  write_row<BF16>(b, wk, fd, rowoff, pr0, pr1, pc0, pc1, b.distinct != 0, z, ssum);
+  Neu tot = block_neu(z, red);
+  for (int o = 32; o > 0; o >>= 1) ssum += __shfl_xor(ssum, o);
+  if ((threadIdx.x & 63) == 0) ssum_sh[threadIdx.x >> 6] = ssum;
+  __syncthreads();
+  const float stot = ssum_sh[0] + ssum_sh[1] + ssum_sh[2] + ssum_sh[3];
+  float Z = tot.s + tot.c;
+  if (!empty && stot > 0.f && Z == 0.f && b.distinct) {
+    __syncthreads();
+    Neu z2{0.f, 0.f};
+    float s2 = 0.f;
+    write_row<BF16>(b, wk, fd, rowoff, pr0, pr1, pc0, pc1, false, z2, s2);
+    tot = block_neu(z2, red);
+    Z = tot.s + tot.c;
+  }
+  if (threadIdx.x == 0) {
+    wk.Z[g] = Z;
+    wk.mstat[g] = (empty || !(stot > 0.f)) ? 1 : 0;
+  }
+}
+
+void launch_weights(const Batch& b, const Work& w, hipStream_t st) {
+  if (b.M <= 0) return;
+  if (b.gemm_bf16)
+    hipLaunchKernelGGL(k_weights<1>, dim3(b.M), dim3(256), 0, st, b, w);
+  else
+    hipLaunchKernelGGL(k_weights<0>, dim3(b.M), dim3(256), 0, st, b, w);
+}
+
+// Stage output of disc_patch_weights: dense w[m][G] = s * D (or s), D from
+// Eq. (1) with eps (single frame).
+__global__ __launch_bounds__(256) void k_dense_weights(Batch b, Work wk, float* out, float eps) {
+  const int g = blockIdx.x;
+  if (g >= b.M) return;
+  const FrameDesc fd = b.frames[b.mask_frame[g]];
+  const int G = fd.G, gw = fd.gw, P = fd.patch;
+  const int4 bb = wk.bbox[g];
+  const bool empty = bb.x > bb.y;
+  const int pr0 = bb.x / P, pr1 = bb.y / P, pc0 = bb.z / P, pc1 = bb.w / P;
+  const int64_t rowoff = fd.w_base + (int64_t)(g - fd.mask_base) * fd.Gs;
+  __shared__ float denom_sh;
+  if (b.distinct) {
+    __shared__ float red[4];
+    float a = 0.f;
+    for (int p = threadIdx.x; p < G; p += 256) a += wk.r[fd.r_base + p];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) denom_sh = (red[0] + red[1] + red[2] + red[3]) / (float)G + eps;
+    __syncthreads();
+  }
+  for (int p = threadIdx.x; p < G; p += 256) {
+    const int pr = p / gw, pc = p - pr * gw;
+    float v = 0.f;
+    if (!empty && pr >= pr0 && pr <= pr1 && pc >= pc0 && pc <= pc1) {
+      v = wk.s[rowoff + p];
+      if (b.distinct) v *= wk.r[fd.r_base + p] / denom_sh;
+    }
+    out[(int64_t)(g - fd.mask_base) * G + p] = v;
+  }
+}
+
+void launch_dense_weights(const Batch& b, const Work& w, float* out, float eps, hipStream_t st) {
+  if (b.M > 0) hipLaunchKernelGGL(k_dense_weights, dim3(b.M), dim3(256), 0, st, b, w, out, eps);
+}
+
+// Caller-given weights (disc_pool_project): copy w[m][G] into the GEMM operand
+// (times scale_p for FP8 tokens), Z = compensated sum of the rounded weights,
+// status 1 for an all-zero row.  The mask bounding box is set to the whole
+// frame so the pooling GEMM visits every patch.
+template <int BF16>
+__global__ __launch_bounds__(256) void k_user_weights(Batch b, Work wk, const float* wts) {
+  const int g = blockIdx.x;
+  if (g >= b.M) return;
+  const FrameDesc fd = b.frames[b.mask_frame[g]];
+  const int G = fd.G;
+  const int64_t rowoff = fd.w_base + (int64_t)(g - fd.mask_base) * fd.Gs;
+  const bool fp8 = b.tok_dtype == 2;
+  __shared__ float red[8];
+  Neu z{0.f, 0.f};
+  for (int p = threadIdx.x; p < G; p += 256) {
+    float wv = wts[(int64_t)(g - fd.mask_base) * G + p];
+    if (fp8) wv *= fd.scale[p];
+    float wr;
+    if (BF16) {
+      const uint16_t hb = f32_to_bf16_rne(wv);
+      reinterpret_cast<uint16_t*>(wk.W)[rowoff + p] = hb;
+      wr = __uint_as_float((uint32_t)hb << 16);
+    } else {
+      reinterpret_cast<float*>(wk.W)[rowoff + p] = wv;
+      wr = wv;
+    }
+    if (wr != 0.f) neu_add(z, fp8 ? wr / fd.scale[p] : wr);
+  }
+  const Neu tot = block_neu(z, red);
+  if (threadIdx.x == 0) {
+    const float Z = tot.s + tot.c;
+    wk.Z[g] = Z;
+    wk.mstat[g] = Z > 0.f ? 0 : 1;
+    wk.bbox[g] = make_int4(0, fd.h - 1, 0, fd.w - 1);
+  }
+}
+
+void launch_user_weights(const Batch& b, const Work& w, const float* wts, hipStream_t st) {
+  if (b.M <= 0) return;
+  if (b.gemm_bf16)
+    hipLaunchKernelGGL(k_user_weights<1>, dim3(b.M), dim3(256), 0, st, b, w, wts);
+  else
+    hipLaunchKernelGGL(k_user_weights<0>, dim3(b.M), dim3(256), 0, st, b, w, wts);
+}
+
+}  // namespace disc

@@ -1,0 +1,129 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol include/disc.h declares, and rejects bad arguments before touching the
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2603_03935_amd as disc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "disc.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(disc_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(disc.LIB_PATH):
+        import paper_2603_03935_amd.build as b
+
+        b.build()
+    return disc.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_symbols()
+    assert names, "no declarations parsed"
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, f"libdisc.so lacks {missing}"
+    assert sorted(disc.EXPORTS) == names, "binding's export list differs from the header"
+
+
+def test_abi_version_and_defaults(lib):
+    assert lib.disc_abi_version() == 1
+    o = disc.Options()
+    lib.disc_options_default(ctypes.byref(o))
+    assert (o.spatial, o.distinct, o.gemm_dtype) == (0, 1, -1)
+    assert abs(o.eps - 1e-6) < 1e-12 and o.workspace is None and o.workspace_bytes == 0
+
+
+FAKE = 1 << 20  # aligned, never dereferenced: validation fails before any device work
+
+
+def good():
+    t = disc.Tokens(FAKE, disc.DISC_F32, 30, 40, 1024, 16, None)
+    m = disc.Masks(FAKE, 5, 480, 640)
+    p = disc.Proj(FAKE, disc.DISC_F32, 1024, 768)
+    o = disc.Out(FAKE, 5, 768, None, None)
+    return t, m, p, o
+
+
+def call(lib, t, m, p, o, opts=None):
+    return lib.disc_embed_masks_ex(ctypes.byref(t) if t else None, ctypes.byref(m) if m else None,
+                                   ctypes.byref(p) if p else None, ctypes.byref(o) if o else None,
+                                   ctypes.byref(opts) if opts else None, None)
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda t, m, p, o: setattr(t, "gh", 29), 2),
+    (lambda t, m, p, o: setattr(t, "c", 1000), 9),
+    (lambda t, m, p, o: setattr(t, "dtype", 7), 3),
+    (lambda t, m, p, o: setattr(t, "scale", FAKE), 1),
+    (lambda t, m, p, o: setattr(t, "dtype", disc.DISC_F8E4M3), 1),
+    (lambda t, m, p, o: setattr(t, "data", FAKE + 4), 4),
+    (lambda t, m, p, o: setattr(t, "patch", 4), 9),
+    (lambda t, m, p, o: setattr(m, "m", -1), 1),
+    (lambda t, m, p, o: setattr(m, "bits", None), 1),
+    (lambda t, m, p, o: setattr(m, "h", 2000), 9),
+    (lambda t, m, p, o: setattr(p, "c", 512), 2),
+    (lambda t, m, p, o: setattr(p, "e", 700), 9),
+    (lambda t, m, p, o: setattr(p, "dtype", disc.DISC_F8E4M3), 3),
+    (lambda t, m, p, o: setattr(o, "m", 4), 2),
+    (lambda t, m, p, o: setattr(o, "e", 512), 2),
+    (lambda t, m, p, o: setattr(o, "data", None), 1),
+])
+def test_validation_rejects(lib, mutate, code):
+    t, m, p, o = good()
+    mutate(t, m, p, o)
+    st = call(lib, t, m, p, o)
+    assert st == code, (st, disc.last_error())
+    assert disc.last_error()
+
+
+def test_null_arguments(lib):
+    t, m, p, o = good()
+    assert call(lib, None, m, p, o) == 1
+    assert call(lib, t, None, p, o) == 1
+    assert call(lib, t, m, None, o) == 1
+    assert call(lib, t, m, p, None) == 1
+    opts = disc.Options()
+    lib.disc_options_default(ctypes.byref(opts))
+    opts.spatial = 3
+    assert call(lib, t, m, p, o, opts) == 1
+
+
+def test_workspace_bytes_is_host_only(lib):
+    t, m, p, o = good()
+    n = lib.disc_workspace_bytes(ctypes.byref(t), ctypes.byref(m), 1, ctypes.byref(p), None)
+    # at least the spatial weights, GEMM weights and pooled features of 5 masks
+    assert n >= 5 * 1200 * 4 + 5 * 1200 * 4 + 5 * 1024 * 4
+    t.gh = 1
+    assert lib.disc_workspace_bytes(ctypes.byref(t), ctypes.byref(m), 1, ctypes.byref(p), None) == 0
+
+
+def test_stage_validation(lib):
+    m = disc.Masks(FAKE, 3, 10, 10)
+    assert lib.disc_edt_sq(ctypes.byref(m), None, None) == 1
+    assert lib.disc_edt_sq(ctypes.byref(m), FAKE + 8, None) == 4
+    assert lib.disc_pack_masks(None, 1, 4, 4, FAKE, None) == 1
+    assert lib.disc_pack_masks(FAKE, 1, 0, 4, FAKE, None) == 1
+    t = disc.Tokens(FAKE, disc.DISC_F32, 4, 4, 64, 16, None)
+    opts = disc.Options()
+    lib.disc_options_default(ctypes.byref(opts))
+    mm = disc.Masks(FAKE, 3, 64, 64)
+    assert lib.disc_patch_weights(ctypes.byref(t), ctypes.byref(mm), 8, ctypes.byref(opts), FAKE, None) == 2
+    assert lib.disc_token_stats(ctypes.byref(t), -1.0, None, None, None, None) == 1
+
+
+def test_zero_masks_is_noop(lib):
+    t, m, p, o = good()
+    m.m = 0
+    o.m = 0
+    assert call(lib, t, m, p, o) == 0

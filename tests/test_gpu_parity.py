@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: squared EDT bit-exact; spatial weights and token statistics within a
+relative 1e-5; embeddings per mask cos >= 1 - 1e-6 (FP32 path) and
+cos >= 0.9995 (BF16 / FP8 paths); statuses identical.
+"""
+import numpy as np
+import pytest
+
+import disc_inputs as di
+import oracle
+from gpu_common import (COS_FP32, COS_LOWP, REL_S, check_embeddings, dev_bits, dev_proj, dev_tokens, frame_input,
+                        oracle_frame, torch)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    t = torch()
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_03935_amd as disc
+
+    disc.load()  # fails loudly when the library is missing
+    return disc
+
+
+def _edt_gpu(disc, bits, h, w):
+    e = disc.edt_sq(dev_bits(bits), h, w)
+    torch().cuda.synchronize()
+    return e.cpu().numpy()
+
+
+# ---------------------------------------------------------------- EDT
+
+def test_edt_cfg1_cfg2(gpu):
+    for name in ("cfg1", "cfg2"):
+        fr = di.workload(name).frames[0]
+        got = _edt_gpu(gpu, fr.bits, fr.h, fr.w)
+        want = oracle.edt_sq(fr.bits, fr.w)
+        bad = np.nonzero((got != want).reshape(len(got), -1).any(axis=1))[0]
+        assert bad.size == 0, f"{name}: EDT differs on masks {bad[:10]}"
+
+
+def adversarial_masks(h, w, rng):
+    u = []
+    z = lambda: np.zeros((h, w), dtype=np.uint8)
+    a = z(); a[h // 2, :] = 1; u.append(a)                      # 1-px horizontal line across the frame
+    a = z(); a[:, w // 3] = 1; u.append(a)                      # 1-px vertical line
+    a = z(); idx = np.arange(min(h, w)); a[idx, idx] = 1; u.append(a)  # diagonal
+    a = (np.indices((h, w)).sum(axis=0) % 2).astype(np.uint8); u.append(a)  # checkerboard
+    u.append(np.ones((h, w), dtype=np.uint8))                     # full frame
+    a = np.ones((h, w), dtype=np.uint8); a[rng.integers(0, h, 9), rng.integers(0, w, 9)] = 0; u.append(a)  # holes
+    a = z(); a[0, :] = 1; a[-1, :] = 1; a[:, 0] = 1; a[:, -1] = 1; u.append(a)  # frame border
+    a = z(); a[0, 0] = 1; a[h - 1, w - 1] = 1; a[h // 2, w // 2] = 1; u.append(a)  # single pixels
+    a = z(); a[:, w - 3:] = 1; u.append(a)                      # right edge band
+    u.append((rng.random((h, w)) < 0.97).astype(np.uint8))
+    u.append((rng.random((h, w)) < 0.03).astype(np.uint8))
+    a = z(); yy, xx = np.indices((h, w)); a[((yy - h / 2) ** 2 + (xx - w / 2) ** 2) < (min(h, w) / 2.2) ** 2] = 1; u.append(a)
+    return np.stack(u)
+
+
+@pytest.mark.parametrize("h,w", [(37, 100), (96, 130), (94, 64), (190, 63), (191, 200), (382, 129), (383, 70),
+                                 (766, 65), (767, 90), (1118, 77), (5, 1500)])
+def test_edt_adversarial(gpu, h, w):
+    """Ragged widths, 1-px structures, full frames and every band-count class."""
+    rng = np.random.default_rng(h * 1000 + w)
+    u8 = adversarial_masks(h, w, rng)
+    bits = di.pack_masks(u8)
+    got = _edt_gpu(gpu, bits, h, w)
+    want = oracle.edt_sq(bits, w)
+    for i in range(len(u8)):
+        assert np.array_equal(got[i], want[i]), f"{h}x{w} adversarial mask {i}: {np.argwhere(got[i] != want[i])[:5]}"
+
+
+def test_edt_large_masks_1080p(gpu):
+    bits = di.masks_mixed(77, 24, 1080, 1920, 0.02, 0.35)
+    got = _edt_gpu(gpu, bits, 1080, 1920)
+    want = oracle.edt_sq(bits, 1920)
+    bad = np.nonzero((got != want).reshape(len(got), -1).any(axis=1))[0]
+    assert bad.size == 0, f"1080p EDT differs on masks {bad}"
+
+
+# ---------------------------------------------------------------- weights and statistics
+
+@pytest.mark.parametrize("spatial,distinct", [(0, 1), (0, 0), (1, 1), (1, 0)])
+def test_patch_weights_modes(gpu, spatial, distinct):
+    for name in ("cfg1", "cfg2"):
+        fr = di.workload(name).frames[0]
+        tok = fr.tokens
+        data, scale = dev_tokens(tok)
+        w = gpu.patch_weights(dev_bits(fr.bits), fr.h, fr.w, tok.patch, data, scale, spatial, distinct)
+        got = w.cpu().numpy().astype(np.float64)
+        s = oracle.spatial_weights(fr.bits, fr.w, tok.patch, spatial)
+        if distinct:
+            _, _, D = oracle.token_stats(oracle.decode_tokens(tok.data, tok.dtype, tok.scale), 1e-6)
+            s = s * D[None, :]
+        assert np.array_equal(got > 0, s > 0), f"{name}: weight support differs"
+        err = np.abs(got - s).max() / max(np.abs(s).max(), 1e-30)
+        assert err <= REL_S, f"{name} spatial={spatial} distinct={distinct}: rel err {err:.3e}"
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f8"])
+def test_token_stats(gpu, dtype):
+    for tok in (di.tokens_normal(5, 30, 40, 1024, dtype, 16), di.tokens_structured(6, 45, 80, 1280, dtype, 16)):
+        data, scale = dev_tokens(tok)
+        mean, r, D = gpu.token_stats(data, tok.patch, scale)
+        f64 = oracle.decode_tokens(tok.data, tok.dtype, tok.scale)
+        om, orr, oD = oracle.token_stats(f64, 1e-6)
+        assert np.abs(mean.cpu().numpy() - om).max() <= REL_S * max(np.abs(f64).max(), 1.0)
+        assert np.abs(r.cpu().numpy() - orr).max() <= REL_S * orr.max()
+        assert np.abs(D.cpu().numpy() - oD).max() <= REL_S * oD.max()
+
+
+# ---------------------------------------------------------------- pooling / projection
+
+@pytest.mark.parametrize("gemm", [0, 1])
+def test_pool_project_given_weights(gpu, gemm):
+    """One-hot weights return token rows, uniform weights the mean; vs oracle."""
+    rng = np.random.default_rng(3)
+    gh, gw, C, E, patch = 9, 11, 256, 384, 16
+    G = gh * gw
+    tok = di.tokens_normal(8, gh, gw, C, "f32", patch)
+    P = di.projection(9, C, E, "f32")
+    wts = np.zeros((70, G), dtype=np.float32)
+    for i in range(G // 2):
+        wts[i, 2 * i] = 1.0
+    wts[50:60] = 1.0
+    wts[60:69] = rng.random((9, G)).astype(np.float32) * (rng.random((9, G)) < 0.2)
+    # row 69 stays zero -> status 1
+    data, _ = dev_tokens(tok)
+    res = gpu.pool_project(data, torch().from_numpy(wts).cuda(), dev_proj(P, "f32"), patch, gemm_dtype=gemm)
+    f64 = oracle.decode_tokens(tok.data, "f32")
+    ref = oracle.pool_project(f64, wts.astype(np.float64), P.astype(np.float64))
+    pooled = res.pooled.cpu().numpy()
+    if gemm == 0:
+        assert np.allclose(pooled[:G // 2], f64[::2][:G // 2], rtol=0, atol=0), "one-hot weights must return the token row"
+        assert np.allclose(pooled[:69], ref["pooled"][:69], rtol=1e-5, atol=1e-5)
+    check_embeddings(res.out.cpu().numpy(), res.status.cpu().numpy(), ref, COS_FP32 if gemm == 0 else COS_LOWP, "given weights")
+
+
+# ---------------------------------------------------------------- whole path
+
+def run_frames(disc, frames, P, pdtype, pooled=False, options=None):
+    ins = [frame_input(f) for f in frames]
+    outs = disc.embed_frames(ins, dev_proj(P, pdtype), pooled=pooled, options=options)
+    torch().cuda.synchronize()
+    return outs
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_embed_fp32_configs(gpu, name):
+    wl = di.workload(name)
+    fr = wl.frames[0]
+    out = run_frames(gpu, [fr], wl.proj, wl.proj_dtype, pooled=True)[0]
+    ref = oracle_frame(fr, wl.proj, wl.proj_dtype)
+    c = check_embeddings(out.out.cpu().numpy(), out.status.cpu().numpy(), ref, COS_FP32, name)
+    print(f"{name}: masks {len(c)} min cos {c.min():.10f} median {np.median(c):.10f}")
+    pooled = out.pooled.cpu().numpy()
+    ok = ref["status"] == 0
+    rel = np.abs(pooled[ok] - ref["pooled"][ok]).max() / np.abs(ref["pooled"][ok]).max()
+    assert rel < 1e-4, f"pooled features rel err {rel:.3e}"
+
+
+@pytest.mark.parametrize("tdtype,pdtype", [("bf16", "bf16"), ("f8", "bf16"), ("f32", "bf16")])
+@pytest.mark.parametrize("structured", [False, True])
+def test_embed_lowp(gpu, tdtype, pdtype, structured):
+    h, w, patch, C, E = 480, 640, 16, 1024, 768
+    s = 4242 + structured
+    tok = (di.tokens_structured(s, 30, 40, C, tdtype, patch) if structured else di.tokens_normal(s, 30, 40, C, tdtype, patch))
+    fr = di.Frame(tok, di.masks_mixed(s, 96, h, w, 1e-3, 0.3), h, w)
+    P = di.projection(s + 1, C, E, pdtype)
+    out = run_frames(gpu, [fr], P, pdtype)[0]
+    ref = oracle_frame(fr, P, pdtype)
+    c = check_embeddings(out.out.cpu().numpy(), out.status.cpu().numpy(), ref, COS_LOWP, f"{tdtype}/{pdtype}")
+    print(f"{tdtype} structured={structured}: min cos {c.min():.7f} median {np.median(c):.7f}")
+
+
+def test_embed_modes_fp32(gpu):
+    wl = di.workload("cfg2")
+    fr = wl.frames[0]
+    for spatial in (0, 1):
+        for distinct in (0, 1):
+            opts = gpu.make_options(spatial, distinct)
+            out = run_frames(gpu, [fr], wl.proj, wl.proj_dtype, options=opts)[0]
+            ref = oracle_frame(fr, wl.proj, wl.proj_dtype, spatial, distinct)
+            check_embeddings(out.out.cpu().numpy(), out.status.cpu().numpy(), ref, COS_FP32, f"mode {spatial}/{distinct}")
+
+
+def test_ragged_batch_and_batch_invariance(gpu):
+    """Mixed resolutions in one call; every frame's result equals the frame
+    alone, bit for bit, and the oracle within tolerance."""
+    frames = []
+    for i, (h, w, m) in enumerate([(480, 640, 40), (720, 1280, 65), (480, 640, 1), (720, 1280, 90), (336, 336, 8)]):
+        patch = 14 if h == 336 else 16
+        gh, gw = -(-h // patch), -(-w // patch)
+        frames.append(di.Frame(di.tokens_normal(100 + i, gh, gw, 1024, "bf16", patch),
+                               di.masks_mixed(100 + i, m, h, w, 1e-3, 0.3), h, w))
+    P = di.projection(7, 1024, 768, "bf16")
+    mix = run_frames(gpu, frames, P, "bf16")
+    for i, fr in enumerate(frames):
+        alone = run_frames(gpu, [fr], P, "bf16")[0]
+        a, b = alone.out.cpu().numpy(), mix[i].out.cpu().numpy()
+        assert np.array_equal(a, b), f"frame {i}: result in the batch differs from the frame alone"
+        ref = oracle_frame(fr, P, "bf16")
+        check_embeddings(b, mix[i].status.cpu().numpy(), ref, COS_LOWP, f"ragged frame {i}")
+
+
+def test_degenerate_cases(gpu):
+    h, w, patch, C, E = 64, 96, 16, 128, 128
+    u8 = np.zeros((4, h, w), dtype=np.uint8)
+    u8[1, 10:40, 20:70] = 1
+    u8[2, :, :] = 1
+    u8[3, 5, 5] = 1
+    bits = di.pack_masks(u8)
+    tok = di.tokens_normal(1, 4, 6, C, "f32", patch)
+    P = di.projection(2, C, E, "f32")
+    fr = di.Frame(tok, bits, h, w)
+    out = run_frames(gpu, [fr], P, "f32")[0]
+    check_embeddings(out.out.cpu().numpy(), out.status.cpu().numpy(), oracle_frame(fr, P, "f32"), COS_FP32, "empty mask")
+    # constant token map: D == 0 everywhere -> spatial weights
+    const = di.tokens_from_values(np.tile(np.random.default_rng(0).normal(size=C), (4, 6, 1)), "f32", patch)
+    frc = di.Frame(const, bits, h, w)
+    outc = run_frames(gpu, [frc], P, "f32", pooled=True)[0]
+    refc = oracle_frame(frc, P, "f32")
+    check_embeddings(outc.out.cpu().numpy(), outc.status.cpu().numpy(), refc, COS_FP32, "constant map")
+    # zero projection -> status 2
+    outz = run_frames(gpu, [fr], np.zeros((C, E), dtype=np.float32), "f32")[0]
+    st = outz.status.cpu().numpy()
+    assert list(st) == [1, 2, 2, 2] and not outz.out.cpu().numpy().any()
+    # no masks
+    fr0 = di.Frame(tok, bits[:0], h, w)
+    out0 = run_frames(gpu, [fr0], P, "f32")[0]
+    assert out0.out.shape == (0, E)
+
+
+def test_pack_masks(gpu):
+    rng = np.random.default_rng(11)
+    u8 = (rng.random((5, 37, 130)) < 0.4).astype(np.uint8)
+    bits = gpu.pack_masks(torch().from_numpy(u8).cuda())
+    assert np.array_equal(bits.cpu().numpy().view(np.uint64), di.pack_masks(u8))
+
+
+# ---------------------------------------------------------------- full-size workloads (sampled)
+
+def test_cfg3_full_batch_sampled(gpu):
+    """64-frame BF16 batch in one call, one sampled mask per frame vs oracle."""
+    wl = di.workload("cfg3")
+    outs = run_frames(gpu, wl.frames, wl.proj, "bf16")
+    rng = np.random.default_rng(5)
+    cs = []
+    for i, fr in enumerate(wl.frames):
+        j = int(rng.integers(0, fr.m))
+        ref = oracle_frame(fr, wl.proj, "bf16", idx=[j])
+        got = outs[i].out[j:j + 1].cpu().numpy()
+        cs.append(check_embeddings(got, outs[i].status[j:j + 1].cpu().numpy(), ref, COS_LOWP, f"cfg3 frame {i}"))
+    c = np.concatenate(cs)
+    print(f"cfg3 sampled {len(c)}: min cos {c.min():.7f}")
+
+
+def test_cfg5_full_batch_sampled(gpu):
+    """16 frames 1080x1920, FP8 tokens, 500 masks each: sampled masks vs oracle."""
+    wl = di.workload("cfg5")
+    outs = run_frames(gpu, wl.frames, wl.proj, "bf16")
+    rng = np.random.default_rng(6)
+    cs = []
+    for i, fr in enumerate(wl.frames):
+        idx = sorted(rng.choice(fr.m, size=2, replace=False).tolist())
+        ref = oracle_frame(fr, wl.proj, "bf16", idx=idx)
+        got = outs[i].out[idx].cpu().numpy()
+        cs.append(check_embeddings(got, outs[i].status[idx].cpu().numpy(), ref, COS_LOWP, f"cfg5 frame {i}"))
+    c = np.concatenate(cs)
+    print(f"cfg5 sampled {len(c)}: min cos {c.min():.7f}")
