@@ -128,7 +128,7 @@ disc_status hip_fail(hipError_t e, const char* what) {
 // --------------------------------------------------------------------------
 struct Layout {
   size_t frames, mask_frame, tiles, frame_ctr, staged_end;  // staged region (uploaded from the host)
-  size_t bbox, area, meta, items, counts, psum, mean, r, s, W, Z, mstat, X, total;
+  size_t bbox, area, meta, items, counts, psum, mean, r, s, W, Z, mstat, X, ssq, total;
 };
 
 struct Shape {
@@ -163,6 +163,7 @@ Layout make_layout(const Shape& s) {
   L.Z = take(4 * (size_t)s.M);
   L.mstat = take(4 * (size_t)s.M);
   L.X = take((s.gemm_bf16 ? 2 : 4) * (size_t)s.M * s.C);
+  L.ssq = take(4 * (size_t)s.M * 8);
   L.total = off;
   return L;
 }
@@ -273,6 +274,7 @@ Work work_ptrs(char* base, const Layout& L) {
   w.Z = reinterpret_cast<float*>(base + L.Z);
   w.mstat = reinterpret_cast<int32_t*>(base + L.mstat);
   w.X = base + L.X;
+  w.ssq = reinterpret_cast<float*>(base + L.ssq);
   return w;
 }
 
@@ -559,7 +561,7 @@ disc_status disc_embed_frames(const disc_tokens* tokens, const disc_masks* masks
   { StageTimer t(ST_EDT, cx.st); launch_edt(b, w, nullptr, num_cus(cx.dev), cx.st); }
   { StageTimer t(ST_WEIGHTS, cx.st); launch_weights(b, w, cx.st); }
   { StageTimer t(ST_POOL, cx.st); launch_pool(b, w, tiles, p.shape.n_tiles, cx.st); }
-  { StageTimer t(ST_PROJ, cx.st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, cx.st); }
+  { StageTimer t(ST_PROJ, cx.st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, w.ssq, cx.st); }
   if ((st = check_launch(who))) return st;
   return ok();
 }
@@ -733,7 +735,7 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32
   const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
   launch_user_weights(b, w, wts, cx.st);
   launch_pool(b, w, tiles, p.shape.n_tiles, cx.st);
-  launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, cx.st);
+  launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, w.ssq, cx.st);
   if ((st = check_launch(who))) return st;
   return ok();
 }

@@ -82,6 +82,7 @@ struct Work {
   float* Z;            // [M] weight sums
   int32_t* mstat;      // [M] 0 ok, 1 empty
   void* X;             // [M][C] pooled features in the GEMM dtype
+  float* ssq;          // [M][E/128] partial sums of squares of the projected rows
 };
 
 // Host-side launchers (stream = hipStream_t).
@@ -91,7 +92,7 @@ void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipS
 void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
 void launch_pool(const Batch& b, const Work& w, const int4* tiles, int n_tiles, hipStream_t st);
-void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st);
+void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, float* ssq, hipStream_t st);
 // stage helpers
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 void launch_pack(const uint8_t* u8, int m, int h, int w, uint64_t* bits, hipStream_t st);

@@ -15,9 +15,11 @@
 // from a per-class queue by a persistent grid):
 //   * lanes = 64 consecutive columns, wavefront k = rows [96k, 96k+96) of the
 //     padded box ("band");
-//   * row pass straight from the packed bits: the 64-bit window of the strip
-//     plus the run lengths that continue past its two ends are wave-uniform
-//     (scalar loads), each lane finds its nearest zero bit with clz/ctz;
+//   * row pass straight from the packed bits: each lane fetches, for one row of
+//     its band, the 64-bit window of the strip and the run lengths that
+//     continue past the window's ends (all rows in parallel); the sequential
+//     pass broadcasts each row with readlane and every lane finds its nearest
+//     zero bit with clz/ctz;
 //   * each band builds the lower envelope of its own rows; the envelope is a
 //     stack of row indices kept as a 96-bit bitmap in registers (exact integer
 //     intersection tests, 64-bit cross products);
@@ -231,18 +233,41 @@ __global__ __launch_bounds__(768) void k_edt(Batch b, Work wk, int cls, int rows
 
     const int b0 = kb * kBand, b1 = min(b0 + kBand, n);
 
-    // ---- row pass + this band's lower envelope ----
+    // ---- row pass, part 1: lane l fetches the strip window of rows b0 + l and
+    // b0 + 64 + l, plus the run lengths that continue past the window's ends
+    // (only needed when the edge pixel is inside the mask).  All rows of the
+    // band are fetched in parallel; the sequential part reads them back with
+    // readlane.
+    uint32_t wlo0 = 0, whi0 = 0, wlo1 = 0, whi1 = 0;
+    int L0 = 0, R0 = 0, L1 = 0, R1 = 0;
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      const int u = b0 + lane + 64 * rr;
+      if (u < b1 && u > 0 && u < n - 1) {
+        const uint64_t* row = mb + (int64_t)(y0 - 1 + u) * wq;
+        const uint64_t win = load_window(row, xs, wq, fw);
+        const int L = (win & 1ull) ? run_left(row, xs - 1, wq, fw) : 0;
+        const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw) : 0;
+        if (rr == 0) {
+          wlo0 = (uint32_t)win; whi0 = (uint32_t)(win >> 32); L0 = L; R0 = R;
+        } else {
+          wlo1 = (uint32_t)win; whi1 = (uint32_t)(win >> 32); L1 = L; R1 = R;
+        }
+      }
+    }
+
+    // ---- row pass, part 2 + this band's lower envelope (sequential in u) ----
     uint32_t w0 = 0, w1 = 0, w2 = 0;
     int cnt = 0, s1 = 0, s2 = 0, F1 = 0, F2 = 0;
     for (int u = b0; u < b1; ++u) {
-      int gv = 0;
-      if (u > 0 && u < n - 1) {
-        const uint64_t* row = mb + (int64_t)(y0 - 1 + u) * wq;
-        const uint64_t win = load_window(row, xs, wq, fw);
-        const int L = run_left(row, xs - 1, wq, fw);
-        const int R = run_right(row, xs + 64, wq, fw);
-        gv = lane_ok ? g_from_window(win, lane, L, R) : 0;
-      }
+      const int src = (u - b0) & 63;
+      const bool hi = (u - b0) >= 64;
+      const uint32_t lo32 = __builtin_amdgcn_readlane(hi ? wlo1 : wlo0, src);
+      const uint32_t hi32 = __builtin_amdgcn_readlane(hi ? whi1 : whi0, src);
+      const int L = __builtin_amdgcn_readlane(hi ? L1 : L0, src);
+      const int R = __builtin_amdgcn_readlane(hi ? R1 : R0, src);
+      const uint64_t win = ((uint64_t)hi32 << 32) | lo32;
+      const int gv = lane_ok ? g_from_window(win, lane, L, R) : 0;
       g_lds[u * 64 + lane] = (int16_t)gv;
       if (SPATIAL == 0) {
         const int Fu = gv * gv;

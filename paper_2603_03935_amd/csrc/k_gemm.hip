@@ -2,9 +2,10 @@
 // (arXiv 2603.03935, Sec. III-C), on MFMA with FP32 accumulation:
 //   pooling     X_f = W_f (m_f x G_f) . T_f (G_f x C) / Z, one GEMM per frame
 //               (ragged batch: each frame has its own token map);
-//   projection  Y = X (M x C) . P (C x E) over all masks of the batch, with the
-//               L2 normalisation fused into the epilogue (a workgroup owns
-//               complete output rows).
+//   projection  Y = X (M x C) . P (C x E) over all masks of the batch; the
+//               epilogue also emits each row's partial sum of squares per
+//               128-column tile, and a row pass then applies the L2
+//               normalisation (fixed-order sum of the partials).
 // BF16 operands use v_mfma_f32_32x32x16_bf16, FP32 operands
 // v_mfma_f32_32x32x2f32.  FP8 (e4m3fn) tokens are widened exactly to BF16
 // while staged into LDS; their per-token scales are already in the weights.
@@ -66,9 +67,23 @@ __device__ __forceinline__ void load_tok8(const void* base, int64_t off, bool ok
 }
 
 // ---------------------------------------------------------------------------
-// pooling: tile 64 masks x 64 channels, K = patches in chunks of 32
+// pooling: tile 64 masks x 64 channels, K = patches in chunks of 32.
+// A (weights, k contiguous) is staged row-major; for BF16 operands B (tokens,
+// channel contiguous in memory) is gathered k-packed straight from global
+// memory -- each lane reads 8 consecutive patches of one channel, every load
+// instruction still covering a contiguous run of channels -- so the MFMA
+// operand of a lane is one 16-byte LDS read.  The next K chunk is fetched
+// into registers while the current one is multiplied.
 // ---------------------------------------------------------------------------
 constexpr int PBM = 64, PBN = 64, PBK = 32;
+constexpr int PAS = PBK + 8;  // LDS row stride (elements) of A and k-packed B
+
+template <int TOK>
+__device__ __forceinline__ uint16_t tok_bf16(const void* base, int64_t off) {
+  if (TOK == 0) return f2bf(reinterpret_cast<const float*>(base)[off]);
+  if (TOK == 1) return reinterpret_cast<const uint16_t*>(base)[off];
+  return e4m3_to_bf16(reinterpret_cast<const uint8_t*>(base)[off]);
+}
 
 template <int BF16, int TOK>
 __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tiles) {
@@ -80,8 +95,8 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
 
   __shared__ int kmin_sh, kmax_sh;
-  __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? PBM * (PBK + 8) : 1];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? PBK * PBN : 1];
+  __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? PBM * PAS : 1];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? PBN * PAS : 1];
   __shared__ float As32[BF16 ? 1 : PBM * (PBK + 1)];
   __shared__ __attribute__((aligned(16))) float Bs32[BF16 ? 1 : PBK * PBN];
 
@@ -104,60 +119,67 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
 
   const int64_t wrow0 = fd.w_base + (int64_t)m0 * fd.Gs;
-  // A loader: row tid/4, 8 consecutive k at (tid%4)*8
-  const int ar = tid >> 2, ak = (tid & 3) * 8;
-  // B loader: k row tid/8, 8 consecutive channels at (tid%8)*8
-  const int bk = tid >> 3, bn = (tid & 7) * 8;
+  const int ar = tid >> 2, ak = (tid & 3) * 8;        // A: row, first k of 8
+  const bool arow_ok = ar < mrows;
+  // B (BF16): channel n = tid & 63, patches 8*(tid >> 6) .. +7
+  const int bn16 = tid & 63, bk16 = (tid >> 6) * 8;
+  // B (FP32): patch tid >> 3, channels 8*(tid & 7) .. +7
+  const int bk32 = tid >> 3, bn32 = (tid & 7) * 8;
 
-  for (int k0 = kbeg; k0 < kend; k0 += PBK) {
-    // ---- stage A (weights) ----
-    {
-      const int kk = k0 + ak;
-      const bool rok = ar < mrows;
-      if (BF16) {
-        const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0 + (int64_t)ar * fd.Gs + kk;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (rok && kk + 8 <= G) {
-          v = *reinterpret_cast<const uint4*>(src);
-        } else if (rok) {
-          uint16_t tmp[8];
-          for (int j = 0; j < 8; ++j) tmp[j] = (kk + j < G) ? src[j] : (uint16_t)0;
-          v = make_uint4(tmp[0] | (tmp[1] << 16), tmp[2] | (tmp[3] << 16), tmp[4] | (tmp[5] << 16), tmp[6] | (tmp[7] << 16));
-        }
-        *reinterpret_cast<uint4*>(&As16[ar * (PBK + 8) + ak]) = v;
-      } else {
-        const float* src = reinterpret_cast<const float*>(wk.W) + wrow0 + (int64_t)ar * fd.Gs + kk;
-        for (int j = 0; j < 8; ++j) As32[ar * (PBK + 1) + ak + j] = (rok && kk + j < G) ? src[j] : 0.f;
-      }
-    }
-    // ---- stage B (tokens) ----
-    {
-      const int kr = k0 + bk;
-      const bool ok = kr < G;
-      const int64_t off = (int64_t)kr * C + n0 + bn;
-      if (BF16) {
-        uint16_t ob[8];
-        load_tok8<TOK, 1>(fd.tokens, off, ok, ob, nullptr);
-        uint4 v = make_uint4(ob[0] | (ob[1] << 16), ob[2] | (ob[3] << 16), ob[4] | (ob[5] << 16), ob[6] | (ob[7] << 16));
-        *reinterpret_cast<uint4*>(&Bs16[bk * PBN + bn]) = v;
-      } else {
-        float of[8];
-        load_tok8<TOK, 0>(fd.tokens, off, ok, nullptr, of);
-        *reinterpret_cast<float4*>(&Bs32[bk * PBN + bn]) = make_float4(of[0], of[1], of[2], of[3]);
-        *reinterpret_cast<float4*>(&Bs32[bk * PBN + bn + 4]) = make_float4(of[4], of[5], of[6], of[7]);
-      }
-    }
-    __syncthreads();
-    // ---- MFMA ----
-    const int lr = lane & 31, lk = lane >> 5;
+  uint4 ra16 = make_uint4(0, 0, 0, 0), rb16 = make_uint4(0, 0, 0, 0);
+  float ra32[8], rb32[8];
+
+  auto fetch = [&](int k0) {
+    const int kk = k0 + ak;
     if (BF16) {
+      const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0 + (int64_t)ar * fd.Gs + kk;
+      if (arow_ok && kk + 8 <= G) {
+        ra16 = *reinterpret_cast<const uint4*>(src);
+      } else {
+        uint16_t tmp[8];
+        for (int j = 0; j < 8; ++j) tmp[j] = (arow_ok && kk + j < G) ? src[j] : (uint16_t)0;
+        ra16 = make_uint4(tmp[0] | (tmp[1] << 16), tmp[2] | (tmp[3] << 16), tmp[4] | (tmp[5] << 16), tmp[6] | (tmp[7] << 16));
+      }
+      uint16_t tb[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int kr = k0 + bk16 + j;
+        tb[j] = kr < G ? tok_bf16<TOK>(fd.tokens, (int64_t)kr * C + n0 + bn16) : (uint16_t)0;
+      }
+      rb16 = make_uint4(tb[0] | (tb[1] << 16), tb[2] | (tb[3] << 16), tb[4] | (tb[5] << 16), tb[6] | (tb[7] << 16));
+    } else {
+      const float* src = reinterpret_cast<const float*>(wk.W) + wrow0 + (int64_t)ar * fd.Gs + kk;
+      for (int j = 0; j < 8; ++j) ra32[j] = (arow_ok && kk + j < G) ? src[j] : 0.f;
+      const int kr = k0 + bk32;
+      load_tok8<TOK, 0>(fd.tokens, (int64_t)kr * C + n0 + bn32, kr < G, nullptr, rb32);
+    }
+  };
+  auto stage = [&]() {
+    if (BF16) {
+      *reinterpret_cast<uint4*>(&As16[ar * PAS + ak]) = ra16;
+      *reinterpret_cast<uint4*>(&Bs16[bn16 * PAS + bk16]) = rb16;
+    } else {
+      for (int j = 0; j < 8; ++j) As32[ar * (PBK + 1) + ak + j] = ra32[j];
+      *reinterpret_cast<float4*>(&Bs32[bk32 * PBN + bn32]) = make_float4(rb32[0], rb32[1], rb32[2], rb32[3]);
+      *reinterpret_cast<float4*>(&Bs32[bk32 * PBN + bn32 + 4]) = make_float4(rb32[4], rb32[5], rb32[6], rb32[7]);
+    }
+  };
+
+  const int lr = lane & 31, lk = lane >> 5;
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += PBK) {
+    stage();
+    __syncthreads();
+    if (k0 + PBK < kend) fetch(k0 + PBK);
+    if (BF16) {
+#pragma unroll
       for (int kk = 0; kk < PBK; kk += 16) {
-        const u16x8 av = *reinterpret_cast<const u16x8*>(&As16[(32 * wm + lr) * (PBK + 8) + kk + 8 * lk]);
-        u16x8 bv;
-        for (int j = 0; j < 8; ++j) bv[j] = Bs16[(kk + 8 * lk + j) * PBN + 32 * wn + lr];
+        const u16x8 av = *reinterpret_cast<const u16x8*>(&As16[(32 * wm + lr) * PAS + kk + 8 * lk]);
+        const u16x8 bv = *reinterpret_cast<const u16x8*>(&Bs16[(32 * wn + lr) * PAS + kk + 8 * lk]);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
       }
     } else {
+#pragma unroll
       for (int kk = 0; kk < PBK; kk += 2) {
         const float a = As32[(32 * wm + lr) * (PBK + 1) + kk + lk];
         const float bb = Bs32[(kk + lk) * PBN + 32 * wn + lr];
@@ -199,163 +221,163 @@ void launch_pool(const Batch& b, const Work& w, const int4* tiles, int n_tiles, 
 }
 
 // ---------------------------------------------------------------------------
-// projection + L2 normalisation: 32 rows x all E columns per workgroup; each
-// wavefront covers E/4 columns as NT tiles of 32 x 32.
+// projection: tile 32 rows x 128 columns (4 wavefronts of 32 x 32), K = C.
+// Writes the unnormalised rows and, per (row, 128-column tile), the partial
+// sum of squares; k_norm then normalises each row (fixed-order sum of the
+// partials) and sets the status.
 // ---------------------------------------------------------------------------
-template <int BF16>
-struct ProjCfg {
-  static constexpr int BK = BF16 ? 32 : 16;
-};
-
-template <int BF16, int NT, int PBF16>
-__global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj) {
-  constexpr int BK = ProjCfg<BF16>::BK;
-  constexpr int E = NT * 128;
-  const int C = b.C;
+template <int BF16, int PBF16>
+__global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj, float* ssq) {
+  constexpr int BK = BF16 ? 32 : 16;
+  constexpr int AS = BK + 8;
+  const int C = b.C, E = b.E, nct = E / 128;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int gbase = blockIdx.x * 32;
-  __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? 32 * (BK + 8) : 1];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? BK * E : 1];
+  const int gbase = blockIdx.x * 32, c0 = blockIdx.y * 128;
+  __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? 32 * AS : 1];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? 128 * AS : 1];
   __shared__ float As32[BF16 ? 1 : 32 * (BK + 1)];
-  __shared__ __attribute__((aligned(16))) float Bs32[BF16 ? 1 : BK * E];
+  __shared__ __attribute__((aligned(16))) float Bs32[BF16 ? 1 : BK * 128];
   __shared__ float red[4][32];
-  __shared__ float* orow[32];
-  __shared__ int32_t* srow[32];
-  __shared__ int st_in[32];
 
-  if (tid < 32) {
-    const int g = gbase + tid;
-    if (g < b.M) {
-      const FrameDesc& fd = b.frames[b.mask_frame[g]];
-      orow[tid] = fd.out + (int64_t)(g - fd.mask_base) * b.E;
-      srow[tid] = fd.status ? fd.status + (g - fd.mask_base) : nullptr;
-      st_in[tid] = wk.mstat[g];
+  floatx16 acc;
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+
+  // A loaders: BF16 32 rows x 32 k (4 per thread), FP32 32 rows x 16 k (2 per thread)
+  const int ar = tid >> 3, ak = BF16 ? (tid & 7) * 4 : (tid & 7) * 2;
+  const int ga = gbase + ar;
+  // B loaders: BF16 k-packed (column tid & 127, 16 k at 16 * (tid >> 7)); FP32 [k][col] (k tid >> 4, 8 cols)
+  const int bc = tid & 127, bkk = (tid >> 7) * 16;
+  const int bk32 = tid >> 4, bc32 = (tid & 15) * 8;
+  uint2 ra16 = make_uint2(0, 0);
+  float2 ra32 = make_float2(0.f, 0.f);
+  uint16_t rb16[16];
+  float rb32[8];
+
+  auto fetch = [&](int k0) {
+    if (BF16) {
+      ra16 = ga < b.M ? *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(wk.X) + (int64_t)ga * C + k0 + ak)
+                      : make_uint2(0, 0);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int64_t off = (int64_t)(k0 + bkk + j) * E + c0 + bc;
+        rb16[j] = PBF16 ? reinterpret_cast<const uint16_t*>(proj)[off] : f2bf(reinterpret_cast<const float*>(proj)[off]);
+      }
     } else {
-      orow[tid] = nullptr;
-      srow[tid] = nullptr;
-      st_in[tid] = 1;
+      ra32 = ga < b.M ? *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(wk.X) + (int64_t)ga * C + k0 + ak)
+                      : make_float2(0.f, 0.f);
+      const int64_t off = (int64_t)(k0 + bk32) * E + c0 + bc32;
+      if (PBF16) {
+        const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(proj) + off);
+        const uint32_t v[4] = {a.x, a.y, a.z, a.w};
+        for (int j = 0; j < 4; ++j) {
+          rb32[2 * j] = bf2f((uint16_t)(v[j] & 0xFFFFu));
+          rb32[2 * j + 1] = bf2f((uint16_t)(v[j] >> 16));
+        }
+      } else {
+        const float4* q = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(proj) + off);
+        const float4 a = q[0], c = q[1];
+        rb32[0] = a.x; rb32[1] = a.y; rb32[2] = a.z; rb32[3] = a.w;
+        rb32[4] = c.x; rb32[5] = c.y; rb32[6] = c.z; rb32[7] = c.w;
+      }
     }
-  }
-
-  floatx16 acc[NT];
-  for (int t = 0; t < NT; ++t)
-    for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+  };
+  auto stage = [&]() {
+    if (BF16) {
+      *reinterpret_cast<uint2*>(&As16[ar * AS + ak]) = ra16;
+      uint4 lo = make_uint4(rb16[0] | (rb16[1] << 16), rb16[2] | (rb16[3] << 16), rb16[4] | (rb16[5] << 16), rb16[6] | (rb16[7] << 16));
+      uint4 hi = make_uint4(rb16[8] | (rb16[9] << 16), rb16[10] | (rb16[11] << 16), rb16[12] | (rb16[13] << 16), rb16[14] | (rb16[15] << 16));
+      *reinterpret_cast<uint4*>(&Bs16[bc * AS + bkk]) = lo;
+      *reinterpret_cast<uint4*>(&Bs16[bc * AS + bkk + 8]) = hi;
+    } else {
+      As32[ar * (BK + 1) + ak] = ra32.x;
+      As32[ar * (BK + 1) + ak + 1] = ra32.y;
+      *reinterpret_cast<float4*>(&Bs32[bk32 * 128 + bc32]) = make_float4(rb32[0], rb32[1], rb32[2], rb32[3]);
+      *reinterpret_cast<float4*>(&Bs32[bk32 * 128 + bc32 + 4]) = make_float4(rb32[4], rb32[5], rb32[6], rb32[7]);
+    }
+  };
 
   const int lr = lane & 31, lk = lane >> 5;
+  fetch(0);
   for (int k0 = 0; k0 < C; k0 += BK) {
-    // A: 32 rows x BK of X
-    if (BF16) {
-      const int r = tid >> 3, kk = (tid & 7) * 4;  // 32 x 32, 4 per thread
-      const int g = gbase + r;
-      uint2 v = make_uint2(0, 0);
-      if (g < b.M) v = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(wk.X) + (int64_t)g * C + k0 + kk);
-      *reinterpret_cast<uint2*>(&As16[r * (BK + 8) + kk]) = v;
-    } else {
-      const int r = tid >> 3, kk = (tid & 7) * 2;  // 32 x 16, 2 per thread
-      const int g = gbase + r;
-      float2 v = make_float2(0.f, 0.f);
-      if (g < b.M) v = *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(wk.X) + (int64_t)g * C + k0 + kk);
-      As32[r * (BK + 1) + kk] = v.x;
-      As32[r * (BK + 1) + kk + 1] = v.y;
-    }
-    // B: BK rows x E of P (8 elements per step)
-    for (int idx = tid * 8; idx < BK * E; idx += 256 * 8) {
-      const int kr = idx / E, cc = idx - kr * E;
-      const int64_t off = (int64_t)(k0 + kr) * E + cc;
-      if (BF16) {
-        if (PBF16) {
-          *reinterpret_cast<uint4*>(&Bs16[idx]) = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(proj) + off);
-        } else {
-          const float4* p = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(proj) + off);
-          const float4 a = p[0], c = p[1];
-          *reinterpret_cast<uint4*>(&Bs16[idx]) =
-              make_uint4(f2bf(a.x) | (f2bf(a.y) << 16), f2bf(a.z) | (f2bf(a.w) << 16), f2bf(c.x) | (f2bf(c.y) << 16),
-                         f2bf(c.z) | (f2bf(c.w) << 16));
-        }
-      } else {
-        if (PBF16) {
-          const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(proj) + off);
-          const uint32_t v[4] = {a.x, a.y, a.z, a.w};
-          for (int j = 0; j < 4; ++j) {
-            Bs32[idx + 2 * j] = bf2f((uint16_t)(v[j] & 0xFFFFu));
-            Bs32[idx + 2 * j + 1] = bf2f((uint16_t)(v[j] >> 16));
-          }
-        } else {
-          const float4* p = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(proj) + off);
-          *reinterpret_cast<float4*>(&Bs32[idx]) = p[0];
-          *reinterpret_cast<float4*>(&Bs32[idx + 4]) = p[1];
-        }
-      }
-    }
+    stage();
     __syncthreads();
-    for (int t = 0; t < NT; ++t) {
-      const int cb = wv * (E / 4) + 32 * t;
-      if (BF16) {
-        for (int kk = 0; kk < BK; kk += 16) {
-          const u16x8 av = *reinterpret_cast<const u16x8*>(&As16[lr * (BK + 8) + kk + 8 * lk]);
-          u16x8 bv;
-          for (int j = 0; j < 8; ++j) bv[j] = Bs16[(kk + 8 * lk + j) * E + cb + lr];
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc[t], 0, 0, 0);
-        }
-      } else {
-        for (int kk = 0; kk < BK; kk += 2) {
-          const float a = As32[lr * (BK + 1) + kk + lk];
-          const float bb = Bs32[(kk + lk) * E + cb + lr];
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc[t], 0, 0, 0);
-        }
+    if (k0 + BK < C) fetch(k0 + BK);
+    if (BF16) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 16) {
+        const u16x8 av = *reinterpret_cast<const u16x8*>(&As16[lr * AS + kk + 8 * lk]);
+        const u16x8 bv = *reinterpret_cast<const u16x8*>(&Bs16[(32 * wv + lr) * AS + kk + 8 * lk]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        const float a = As32[lr * (BK + 1) + kk + lk];
+        const float bb = Bs32[(kk + lk) * 128 + 32 * wv + lr];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc, 0, 0, 0);
       }
     }
     __syncthreads();
   }
 
-  // ---- L2 normalisation over each row's E columns ----
+  // ---- store unnormalised rows and per-tile sums of squares ----
   float ss[16];
   for (int v = 0; v < 16; ++v) {
-    float a = 0.f;
-    for (int t = 0; t < NT; ++t) a += acc[t][v] * acc[t][v];
+    float a = acc[v] * acc[v];
     for (int o = 1; o < 32; o <<= 1) a += __shfl_xor(a, o);
     ss[v] = a;
   }
   if (lr == 0)
     for (int v = 0; v < 16; ++v) red[wv][8 * (v >> 2) + 4 * lk + (v & 3)] = ss[v];
-  __syncthreads();
+  const int col = c0 + 32 * wv + lr;
   for (int v = 0; v < 16; ++v) {
     const int r = 8 * (v >> 2) + 4 * lk + (v & 3);
-    float* o = orow[r];
-    if (o == nullptr) continue;
-    const float tot = red[0][r] + red[1][r] + red[2][r] + red[3][r];
-    const bool zero = st_in[r] != 0 || !(tot > 0.f);
-    const float inv = zero ? 0.f : 1.0f / __builtin_sqrtf(tot);
-    for (int t = 0; t < NT; ++t) o[wv * (E / 4) + 32 * t + lr] = acc[t][v] * inv;
+    const int g = gbase + r;
+    if (g >= b.M) continue;
+    const FrameDesc& fd = b.frames[b.mask_frame[g]];
+    fd.out[(int64_t)(g - fd.mask_base) * E + col] = acc[v];
   }
-  if (tid < 32 && orow[tid] != nullptr && srow[tid] != nullptr) {
-    const float tot = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    *srow[tid] = st_in[tid] != 0 ? 1 : (tot > 0.f ? 0 : 2);
-  }
+  __syncthreads();
+  if (tid < 32 && gbase + tid < b.M)
+    ssq[(int64_t)(gbase + tid) * nct + blockIdx.y] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
-template <int BF16, int PBF16>
-static void launch_proj_t(const Batch& b, const Work& w, const void* proj, hipStream_t st) {
-  const dim3 grid((b.M + 31) / 32), block(256);
-  switch (b.E / 128) {
-    case 1: hipLaunchKernelGGL((k_proj<BF16, 1, PBF16>), grid, block, 0, st, b, w, proj); break;
-    case 2: hipLaunchKernelGGL((k_proj<BF16, 2, PBF16>), grid, block, 0, st, b, w, proj); break;
-    case 3: hipLaunchKernelGGL((k_proj<BF16, 3, PBF16>), grid, block, 0, st, b, w, proj); break;
-    case 4: hipLaunchKernelGGL((k_proj<BF16, 4, PBF16>), grid, block, 0, st, b, w, proj); break;
-    case 5: hipLaunchKernelGGL((k_proj<BF16, 5, PBF16>), grid, block, 0, st, b, w, proj); break;
-    case 6: hipLaunchKernelGGL((k_proj<BF16, 6, PBF16>), grid, block, 0, st, b, w, proj); break;
-    case 7: hipLaunchKernelGGL((k_proj<BF16, 7, PBF16>), grid, block, 0, st, b, w, proj); break;
-    default: hipLaunchKernelGGL((k_proj<BF16, 8, PBF16>), grid, block, 0, st, b, w, proj); break;
+// one wavefront per row: fixed-order sum of the partial squares, scale, status
+__global__ __launch_bounds__(256) void k_norm(Batch b, Work wk, const float* ssq) {
+  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= b.M) return;
+  const int E = b.E, nct = E / 128;
+  float tot = 0.f;
+  for (int t = 0; t < nct; ++t) tot += ssq[(int64_t)g * nct + t];
+  const FrameDesc& fd = b.frames[b.mask_frame[g]];
+  const int i = g - fd.mask_base;
+  const int st_in = wk.mstat[g];
+  const bool zero = st_in != 0 || !(tot > 0.f);
+  const float inv = zero ? 0.f : 1.0f / __builtin_sqrtf(tot);
+  float* o = fd.out + (int64_t)i * E;
+  for (int c = lane * 4; c < E; c += 256) {
+    float4 v = *reinterpret_cast<float4*>(o + c);
+    v.x *= inv;
+    v.y *= inv;
+    v.z *= inv;
+    v.w *= inv;
+    *reinterpret_cast<float4*>(o + c) = v;
   }
+  if (lane == 0 && fd.status) fd.status[i] = st_in != 0 ? 1 : (tot > 0.f ? 0 : 2);
 }
 
-void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st) {
+void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, float* ssq, hipStream_t st) {
   if (b.M <= 0) return;
+  const dim3 grid((b.M + 31) / 32, b.E / 128), block(256);
   if (b.gemm_bf16) {
-    if (proj_bf16) launch_proj_t<1, 1>(b, w, proj, st); else launch_proj_t<1, 0>(b, w, proj, st);
+    if (proj_bf16) hipLaunchKernelGGL((k_proj<1, 1>), grid, block, 0, st, b, w, proj, ssq);
+    else hipLaunchKernelGGL((k_proj<1, 0>), grid, block, 0, st, b, w, proj, ssq);
   } else {
-    if (proj_bf16) launch_proj_t<0, 1>(b, w, proj, st); else launch_proj_t<0, 0>(b, w, proj, st);
+    if (proj_bf16) hipLaunchKernelGGL((k_proj<0, 1>), grid, block, 0, st, b, w, proj, ssq);
+    else hipLaunchKernelGGL((k_proj<0, 0>), grid, block, 0, st, b, w, proj, ssq);
   }
+  hipLaunchKernelGGL(k_norm, dim3((b.M + 3) / 4), dim3(256), 0, st, b, w, ssq);
 }
 
 }  // namespace disc

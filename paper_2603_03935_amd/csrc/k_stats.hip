@@ -40,40 +40,82 @@ __device__ __forceinline__ float4 load4(const void* base, int dtype, const float
 }
 
 // Partial channel sums over chunks of 64 tokens; the last chunk of a frame to
-// finish folds the partials (fixed order) into the frame mean.
+// finish folds the partials (fixed order) into the frame mean.  Each thread
+// reads 16-byte vectors (VEC channels) of several token rows.
+template <int TOK>
+__device__ __forceinline__ void load_vec(const void* base, const float* scale, int64_t p, int C, int c, float* v) {
+  const int64_t off = p * C + c;
+  if (TOK == 0) {
+    const float4* q = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(base) + off);
+    const float4 a = q[0], d = q[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = d.x; v[5] = d.y; v[6] = d.z; v[7] = d.w;
+  } else if (TOK == 1) {
+    const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(base) + off);
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+    for (int j = 0; j < 4; ++j) {
+      v[2 * j] = bf16_to_f32(w[j] & 0xFFFFu);
+      v[2 * j + 1] = bf16_to_f32(w[j] >> 16);
+    }
+  } else {
+    const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint8_t*>(base) + off);
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+    const float sc = scale[p];
+    for (int j = 0; j < 16; ++j) v[j] = sc * e4m3_to_f32((w[j >> 2] >> (8 * (j & 3))) & 0xFFu);
+  }
+}
+
+template <int TOK>
 __global__ __launch_bounds__(256) void k_colsum(Batch b, Work wk) {
+  constexpr int VEC = TOK == 2 ? 16 : 8;
   const int f = blockIdx.y, chunk = blockIdx.x;
   const FrameDesc fd = b.frames[f];
   const int G = fd.G, C = b.C;
   const int nch = (G + kChunk - 1) / kChunk;
   if (chunk >= nch) return;
+  const int tpr = C / VEC, rpp = 256 / tpr;
+  const int tid = threadIdx.x, cg = tid % tpr, ro = tid / tpr;
   const int p0 = chunk * kChunk, p1 = min(p0 + kChunk, G);
-  float* ps = wk.psum + ((int64_t)f * b.nchunk + chunk) * C;
-  for (int c = threadIdx.x * 4; c < C; c += 1024) {
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int p = p0; p < p1; ++p) {
-      const float4 v = load4(fd.tokens, b.tok_dtype, fd.scale, p, C, c);
-      a.x += v.x;
-      a.y += v.y;
-      a.z += v.z;
-      a.w += v.w;
+  __shared__ float part[256 * 16];
+  float acc[VEC];
+  for (int j = 0; j < VEC; ++j) acc[j] = 0.f;
+  if (ro < rpp) {
+    int p = p0 + ro;
+    for (; p + 3 * rpp < p1; p += 4 * rpp) {
+      float v0[VEC], v1[VEC], v2[VEC], v3[VEC];
+      load_vec<TOK>(fd.tokens, fd.scale, p, C, cg * VEC, v0);
+      load_vec<TOK>(fd.tokens, fd.scale, p + rpp, C, cg * VEC, v1);
+      load_vec<TOK>(fd.tokens, fd.scale, p + 2 * rpp, C, cg * VEC, v2);
+      load_vec<TOK>(fd.tokens, fd.scale, p + 3 * rpp, C, cg * VEC, v3);
+      for (int j = 0; j < VEC; ++j) acc[j] += ((v0[j] + v1[j]) + v2[j]) + v3[j];
     }
-    *reinterpret_cast<float4*>(ps + c) = a;
+    for (; p < p1; p += rpp) {
+      float v0[VEC];
+      load_vec<TOK>(fd.tokens, fd.scale, p, C, cg * VEC, v0);
+      for (int j = 0; j < VEC; ++j) acc[j] += v0[j];
+    }
+    for (int j = 0; j < VEC; ++j) part[ro * C + cg * VEC + j] = acc[j];
+  }
+  __syncthreads();
+  float* ps = wk.psum + ((int64_t)f * b.nchunk + chunk) * C;
+  for (int c = tid; c < C; c += 256) {
+    float a = 0.f;
+    for (int r = 0; r < rpp; ++r) a += part[r * C + c];
+    ps[c] = a;
   }
   __threadfence();
   __shared__ int last;
   __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(wk.frame_ctr + f, 1u) == (unsigned)(nch - 1));
+  if (tid == 0) last = (atomicAdd(wk.frame_ctr + f, 1u) == (unsigned)(nch - 1));
   __syncthreads();
   if (!last) return;
   __threadfence();
   const float inv = 1.0f / (float)G;
-  for (int c = threadIdx.x; c < C; c += 256) {
+  for (int c = tid; c < C; c += 256) {
     float a = 0.f;
     for (int j = 0; j < nch; ++j) a += __builtin_nontemporal_load(wk.psum + ((int64_t)f * b.nchunk + j) * C + c);
     wk.mean[(int64_t)f * C + c] = a * inv;
   }
-  if (threadIdx.x == 0) wk.frame_ctr[f] = 0u;
+  if (tid == 0) wk.frame_ctr[f] = 0u;
 }
 
 // r_p = ||f_p - mean||: one wavefront per token, lanes over channels.
@@ -97,7 +139,10 @@ __global__ __launch_bounds__(256) void k_rnorm(Batch b, Work wk) {
 }
 
 void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st) {
-  hipLaunchKernelGGL(k_colsum, dim3(b.nchunk, b.n_frames), dim3(256), 0, st, b, w);
+  const dim3 cgrid(b.nchunk, b.n_frames);
+  if (b.tok_dtype == 0) hipLaunchKernelGGL(k_colsum<0>, cgrid, dim3(256), 0, st, b, w);
+  else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_colsum<1>, cgrid, dim3(256), 0, st, b, w);
+  else hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
   hipLaunchKernelGGL(k_rnorm, dim3((gmax + 15) / 16, b.n_frames), dim3(256), 0, st, b, w);
 }
 
