@@ -176,6 +176,79 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* w, int32_t
 /* Pack bool/uint8 masks u8[m][h][w] (non-zero = inside) into the bit layout. */
 disc_status disc_pack_masks(const uint8_t* u8, int32_t m, int32_t h, int32_t w, uint64_t* bits, void* stream);
 
+/* ---- serving ---- */
+
+/* A continuous-batching request loop on one device (the view-quality
+ * pipeline of Sec. III-C embeds every frame's masks as frames arrive).
+ * Requests (one frame each: device-resident tokens and masks, caller-owned
+ * outputs that must stay valid until the ticket completes) enter a FIFO.
+ * `lanes` worker threads each own a stream, a resident workspace sized for the
+ * capacity below and a pinned staging buffer; a free lane packs the waiting
+ * requests (in arrival order, up to max_frames frames / max_masks masks and
+ * while fewer than max_slots requests are in flight) into one batch, runs the
+ * kernel set (replaying a captured hipGraph when use_graph is set), waits for
+ * it and completes the tickets.  Requests arriving while other batches run
+ * are admitted as soon as a lane and slots free up, so batches on different
+ * lanes overlap on the device.  Every result equals the frame processed
+ * alone (the kernels never mix masks or frames).
+ *
+ * Admission: a request that can never fit (more masks than max_masks, a frame
+ * larger than max_h x max_w, a patch smaller than min_patch, other dtype or
+ * channel count) is rejected at submit with DISC_ERR_ADMISSION; one waiting
+ * longer than admission_timeout_ms (0 = no limit) completes with
+ * DISC_ERR_ADMISSION.  Creation fails with DISC_ERR_OUT_OF_MEMORY when
+ * mem_budget cannot hold one lane's workspace; otherwise the number of lanes
+ * is reduced to what the budget holds.
+ * dry_run (host-only testing of the admission logic): no device work at all
+ * and outputs untouched; 1 = batches complete at once, n > 1 = each batch
+ * takes n microseconds.
+ * fault_batch >= 0 makes that batch (0-based, in launch order) complete with
+ * DISC_ERR_DEVICE without running, to test failure handling. */
+typedef struct disc_server disc_server;
+
+typedef struct disc_server_config {
+  disc_proj proj;          /* shared projection (device memory; outlives the server) */
+  int32_t tok_dtype;       /* token dtype of every request */
+  int32_t c;               /* token channels of every request */
+  int32_t max_frames;      /* batch capacity: frames */
+  int32_t max_masks;       /* batch capacity: masks (sum over the batch) */
+  int32_t max_h, max_w;    /* largest frame accepted */
+  int32_t min_patch;       /* smallest patch size accepted */
+  int32_t max_slots;       /* requests in flight (admitted, not completed), at most */
+  int32_t lanes;           /* concurrent batches, 1..8 */
+  size_t mem_budget;       /* device bytes for the lanes' workspaces */
+  int32_t use_graph;       /* 1: capture each lane's kernel set once and replay it */
+  int32_t dry_run;         /* 0 off; 1 host-only; n > 1 host-only, n us per batch */
+  int32_t fault_batch;     /* -1: off; else this batch completes with DISC_ERR_DEVICE */
+  double admission_timeout_ms;
+  disc_options opts;       /* spatial / distinct / eps / gemm_dtype (workspace fields ignored) */
+} disc_server_config;
+
+typedef struct disc_server_stats {
+  uint64_t submitted, completed, failed, rejected, batches;
+  double mean_batch_frames;
+  double p50_ms, p99_ms, max_ms, mean_ms; /* submit -> completion of successful requests */
+  int32_t lanes;                          /* lanes actually running */
+  size_t lane_workspace_bytes;
+} disc_server_stats;
+
+/* Defaults: lanes 2, max_frames 16, max_masks 1024, 720x1280 frames, patch
+ * >= 14, 64 slots, 4 GiB budget, graphs on, no dry run, no fault. */
+void disc_server_config_default(disc_server_config* cfg);
+disc_status disc_server_create(const disc_server_config* cfg, disc_server** out);
+/* Validate and enqueue one frame; *ticket identifies it. */
+disc_status disc_server_submit(disc_server* s, const disc_tokens* tokens, const disc_masks* masks, disc_out* out,
+                               uint64_t* ticket);
+/* *done = 1 once the ticket completed; *result is then its status. */
+disc_status disc_server_poll(disc_server* s, uint64_t ticket, int32_t* done, int32_t* result);
+/* Block until the ticket completed; *result = its status. */
+disc_status disc_server_wait(disc_server* s, uint64_t ticket, int32_t* result);
+/* Block until every submitted request completed. */
+disc_status disc_server_drain(disc_server* s);
+disc_status disc_server_get_stats(disc_server* s, disc_server_stats* st);
+/* Drain, stop the lanes and free the server's memory. */
+void disc_server_destroy(disc_server* s);
+
 /* ---- profiling ---- */
 
 /* Per-stage device timing with HIP events recorded on the caller's stream

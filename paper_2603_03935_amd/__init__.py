@@ -37,6 +37,8 @@ EXPORTS = [
     "disc_workspace_bytes", "disc_release_workspace", "disc_edt_sq", "disc_patch_weights",
     "disc_token_stats", "disc_pool_project", "disc_pack_masks", "disc_last_error", "disc_abi_version",
     "disc_trace_enable", "disc_trace_reset", "disc_trace_read", "disc_trace_stage_name",
+    "disc_server_config_default", "disc_server_create", "disc_server_submit", "disc_server_poll",
+    "disc_server_wait", "disc_server_drain", "disc_server_get_stats", "disc_server_destroy",
 ]
 STAGES = ["scan", "plan", "token_stats", "edt", "weights", "pool", "proj"]
 
@@ -71,6 +73,22 @@ class Out(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("spatial", ctypes.c_int32), ("distinct", ctypes.c_int32), ("eps", ctypes.c_float),
                 ("gemm_dtype", ctypes.c_int32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("proj", Proj), ("tok_dtype", ctypes.c_int32), ("c", ctypes.c_int32),
+                ("max_frames", ctypes.c_int32), ("max_masks", ctypes.c_int32), ("max_h", ctypes.c_int32),
+                ("max_w", ctypes.c_int32), ("min_patch", ctypes.c_int32), ("max_slots", ctypes.c_int32),
+                ("lanes", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("use_graph", ctypes.c_int32),
+                ("dry_run", ctypes.c_int32), ("fault_batch", ctypes.c_int32), ("admission_timeout_ms", ctypes.c_double),
+                ("opts", Options)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("mean_batch_frames", ctypes.c_double),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("lanes", ctypes.c_int32), ("lane_workspace_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -109,6 +127,19 @@ def load(path: str = LIB_PATH):
     lib.disc_trace_read.restype = i32
     lib.disc_trace_stage_name.argtypes = [i32]
     lib.disc_trace_stage_name.restype = ctypes.c_char_p
+    lib.disc_server_config_default.argtypes = [P(ServerConfig)]
+    lib.disc_server_config_default.restype = None
+    lib.disc_server_create.argtypes = [P(ServerConfig), P(vp)]
+    lib.disc_server_submit.argtypes = [vp, P(Tokens), P(Masks), P(Out), P(ctypes.c_uint64)]
+    lib.disc_server_poll.argtypes = [vp, ctypes.c_uint64, P(i32), P(i32)]
+    lib.disc_server_wait.argtypes = [vp, ctypes.c_uint64, P(i32)]
+    lib.disc_server_drain.argtypes = [vp]
+    lib.disc_server_get_stats.argtypes = [vp, P(ServerStats)]
+    lib.disc_server_destroy.argtypes = [vp]
+    lib.disc_server_destroy.restype = None
+    for name in ("disc_server_create", "disc_server_submit", "disc_server_poll", "disc_server_wait",
+                 "disc_server_drain", "disc_server_get_stats"):
+        getattr(lib, name).restype = ctypes.c_int
     lib.disc_abi_version.argtypes = []
     lib.disc_abi_version.restype = i32
     for name in ("disc_embed_masks", "disc_embed_masks_ex", "disc_embed_frames", "disc_release_workspace",
@@ -348,3 +379,93 @@ def trace_read() -> dict:
         lib.disc_trace_read(i, ctypes.byref(ms), ctypes.byref(n))
         res[name] = (ms.value, n.value)
     return res
+
+
+# ---------------------------------------------------------------- serving
+
+class Server:
+    """disc_server_*: a continuous-batching request loop (see include/disc.h).
+
+    Inputs of a submitted request must stay alive (and unchanged) until its
+    ticket completes; this wrapper keeps references to them until then."""
+
+    def __init__(self, proj=None, tok_dtype: int = DISC_BF16, c: int = 1024, e: int = 768, max_frames: int = 16,
+                 max_masks: int = 1024, max_h: int = 720, max_w: int = 1280, min_patch: int = 14,
+                 max_slots: int = 64, lanes: int = 2, mem_budget: int = 4 << 30, use_graph: bool = True,
+                 dry_run: int = 0, fault_batch: int = -1, admission_timeout_ms: float = 0.0,
+                 options: Optional[Options] = None):
+        lib = load()
+        cfg = ServerConfig()
+        lib.disc_server_config_default(ctypes.byref(cfg))
+        if proj is not None:
+            cfg.proj = make_proj(proj)
+        else:
+            cfg.proj = Proj(None, DISC_BF16, c, e)
+        cfg.tok_dtype, cfg.c = tok_dtype, c
+        cfg.max_frames, cfg.max_masks, cfg.max_h, cfg.max_w = max_frames, max_masks, max_h, max_w
+        cfg.min_patch, cfg.max_slots, cfg.lanes, cfg.mem_budget = min_patch, max_slots, lanes, mem_budget
+        cfg.use_graph, cfg.dry_run, cfg.fault_batch = int(use_graph), dry_run, fault_batch
+        cfg.admission_timeout_ms = admission_timeout_ms
+        cfg.opts = options if options is not None else make_options()
+        self._proj = proj
+        self._keep = {}
+        h = ctypes.c_void_p()
+        _check(lib.disc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+        self.e = cfg.proj.e
+
+    def submit(self, tokens_struct: Tokens, masks_struct: Masks, out_struct: Out, keep=None) -> int:
+        t = ctypes.c_uint64()
+        _check(load().disc_server_submit(self.h, ctypes.byref(tokens_struct), ctypes.byref(masks_struct),
+                                         ctypes.byref(out_struct), ctypes.byref(t)))
+        self._keep[t.value] = keep
+        return t.value
+
+    def submit_frame(self, frame: FrameInput, output: Optional[FrameOutput] = None):
+        """Submit one frame; returns (ticket, FrameOutput)."""
+        if output is None:
+            output = alloc_outputs([frame], self.e)[0]
+        tk = make_tokens(frame.tokens, frame.patch, frame.scale)
+        mk = make_masks(frame.bits, frame.h, frame.w)
+        o = Out(_ptr(output.out), output.out.shape[0], output.out.shape[1], _ptr(output.status), _ptr(output.pooled))
+        return self.submit(tk, mk, o, keep=(frame, output)), output
+
+    def poll(self, ticket: int):
+        done, res = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().disc_server_poll(self.h, ticket, ctypes.byref(done), ctypes.byref(res)))
+        if done.value:
+            self._keep.pop(ticket, None)
+        return bool(done.value), res.value
+
+    def wait(self, ticket: int) -> int:
+        res = ctypes.c_int32()
+        _check(load().disc_server_wait(self.h, ticket, ctypes.byref(res)))
+        self._keep.pop(ticket, None)
+        return res.value
+
+    def drain(self):
+        _check(load().disc_server_drain(self.h))
+        self._keep.clear()
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().disc_server_get_stats(self.h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            load().disc_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

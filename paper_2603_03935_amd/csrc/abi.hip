@@ -14,10 +14,12 @@
 
 #include "../../include/disc.h"
 #include "disc_device.h"
+#include "host.h"
 
 using namespace disc;
 
-namespace {
+namespace disc {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -126,16 +128,7 @@ disc_status hip_fail(hipError_t e, const char* what) {
 // --------------------------------------------------------------------------
 // workspace layout
 // --------------------------------------------------------------------------
-struct Layout {
-  size_t frames, mask_frame, tiles, frame_ctr, staged_end;  // staged region (uploaded from the host)
-  size_t bbox, area, meta, items, counts, psum, mean, r, s, W, Z, mstat, X, ssq, total;
-};
 
-struct Shape {
-  int n_frames = 0;
-  int64_t M = 0, sumG = 0, sumMGs = 0;
-  int C = 0, E = 0, gmax = 0, nchunk = 1, item_cap = 1, n_tiles = 0, gemm_bf16 = 0;
-};
 
 Layout make_layout(const Shape& s) {
   Layout L{};
@@ -148,6 +141,7 @@ Layout make_layout(const Shape& s) {
   L.frames = take(sizeof(FrameDesc) * s.n_frames);
   L.mask_frame = take(4 * (size_t)s.M);
   L.tiles = take(16 * (size_t)s.n_tiles);
+  L.dyn = take(16);
   L.frame_ctr = take(4 * (size_t)s.n_frames);
   L.staged_end = off;
   L.bbox = take(16 * (size_t)s.M);
@@ -281,23 +275,7 @@ Work work_ptrs(char* base, const Layout& L) {
 // --------------------------------------------------------------------------
 // batch description
 // --------------------------------------------------------------------------
-struct FrameIn {
-  const void* tokens = nullptr;
-  const float* scale = nullptr;
-  const uint64_t* bits = nullptr;
-  float* out = nullptr;
-  int32_t* status = nullptr;
-  float* pooled = nullptr;
-  int gh = 0, gw = 0, patch = 16, h = 0, w = 0, m = 0;
-};
 
-struct Plan {
-  Shape shape;
-  Layout L;
-  std::vector<FrameDesc> fds;
-  std::vector<int32_t> mask_frame;
-  std::vector<int4> tiles;
-};
 
 void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p) {
   Shape& s = p.shape;
@@ -357,6 +335,8 @@ void stage_host(const Plan& p, char* host, char* dev) {
   std::memcpy(host + p.L.frames, fds.data(), sizeof(FrameDesc) * fds.size());
   if (!p.mask_frame.empty()) std::memcpy(host + p.L.mask_frame, p.mask_frame.data(), 4 * p.mask_frame.size());
   if (!p.tiles.empty()) std::memcpy(host + p.L.tiles, p.tiles.data(), 16 * p.tiles.size());
+  const int32_t dyn[4] = {p.shape.n_frames, (int32_t)p.shape.M, p.shape.n_tiles, 0};
+  std::memcpy(host + p.L.dyn, dyn, sizeof dyn);
   std::memset(host + p.L.frame_ctr, 0, 4 * (size_t)p.shape.n_frames);
 }
 
@@ -364,6 +344,7 @@ Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int disti
   Batch b{};
   b.frames = reinterpret_cast<const FrameDesc*>(dev + p.L.frames);
   b.mask_frame = reinterpret_cast<const int32_t*>(dev + p.L.mask_frame);
+  b.dyn = reinterpret_cast<const int32_t*>(dev + p.L.dyn);
   b.n_frames = p.shape.n_frames;
   b.M = (int32_t)p.shape.M;
   b.C = p.shape.C;
@@ -468,6 +449,7 @@ struct StageTimer {
   hipStream_t st;
   hipEvent_t a = nullptr;
   StageTimer(int s, hipStream_t stream) : stage(s), st(stream) {
+    if (s < 0) return;
     std::lock_guard<std::mutex> lk(g_tr_mu);
     if (!g_trace_on) return;
     a = tr_event();
@@ -497,7 +479,25 @@ void tr_collect() {
   g_tr_pending.clear();
 }
 
-}  // namespace
+void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options& o, const disc_proj* proj, int cus,
+                  hipStream_t st, bool trace) {
+  const int sid = trace ? 0 : -1;
+  const Batch b = make_batch(p, dev_ws, tok_dtype, o.spatial, o.distinct);
+  const Work w = work_ptrs(dev_ws, p.L);
+  const int4* tiles = reinterpret_cast<const int4*>(dev_ws + p.L.tiles);
+  { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_PLAN, st); launch_plan(b, w, st); }
+  if (o.distinct) { StageTimer t(sid < 0 ? -1 : ST_STATS, st); launch_token_stats(b, w, p.shape.gmax, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_POOL, st); launch_pool(b, w, tiles, p.shape.n_tiles, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_PROJ, st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, w.ssq, st); }
+}
+
+}  // namespace host
+}  // namespace disc
+
+using namespace disc::host;
 
 // ==========================================================================
 // exported entry points
@@ -552,16 +552,7 @@ disc_status disc_embed_frames(const disc_tokens* tokens, const disc_masks* masks
   if ((st = acquire(static_cast<hipStream_t>(stream), p.L, &o, cx))) return st;
   stage_host(p, cx.host_stage, cx.dev_ws);
   if ((st = upload(cx, p.L))) return st;
-  const Batch b = make_batch(p, cx.dev_ws, tokens[0].dtype, o.spatial, o.distinct);
-  const Work w = work_ptrs(cx.dev_ws, p.L);
-  const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
-  { StageTimer t(ST_SCAN, cx.st); launch_scan(b, w, cx.st); }
-  { StageTimer t(ST_PLAN, cx.st); launch_plan(b, w, cx.st); }
-  if (o.distinct) { StageTimer t(ST_STATS, cx.st); launch_token_stats(b, w, p.shape.gmax, cx.st); }
-  { StageTimer t(ST_EDT, cx.st); launch_edt(b, w, nullptr, num_cus(cx.dev), cx.st); }
-  { StageTimer t(ST_WEIGHTS, cx.st); launch_weights(b, w, cx.st); }
-  { StageTimer t(ST_POOL, cx.st); launch_pool(b, w, tiles, p.shape.n_tiles, cx.st); }
-  { StageTimer t(ST_PROJ, cx.st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, w.ssq, cx.st); }
+  enqueue_path(p, cx.dev_ws, tokens[0].dtype, o, proj, num_cus(cx.dev), cx.st);
   if ((st = check_launch(who))) return st;
   return ok();
 }

@@ -53,10 +53,14 @@ struct FrameDesc {
   int64_t r_base;         // offset of this frame's G entries in r
 };
 
-// Scalar arguments shared by the kernels of one call.
+// Scalar arguments shared by the kernels of one call.  n_frames and M are
+// capacities (they size the grids); the live counts are read from device
+// memory (dyn), so one captured graph of the kernel set serves every batch
+// that fits the capacities.
 struct Batch {
   const FrameDesc* frames;
   const int32_t* mask_frame;  // [M] frame of each global mask
+  const int32_t* dyn;         // device: [0] frames, [1] masks, [2] pooling tiles
   int32_t n_frames, M, C, E;
   int32_t tok_dtype;          // disc_dtype of the tokens
   int32_t gemm_bf16;          // 1: BF16 operands, 0: FP32 operands
@@ -89,6 +93,7 @@ struct Work {
 void launch_scan(const Batch& b, const Work& w, hipStream_t st);
 void launch_plan(const Batch& b, const Work& w, hipStream_t st);
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st);
+void edt_prepare();
 void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
 void launch_pool(const Batch& b, const Work& w, const int4* tiles, int n_tiles, hipStream_t st);

@@ -1,0 +1,70 @@
+// Host-side planning shared by the one-shot entry points and the serving
+// runtime (internal; not installed).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/disc.h"
+#include "disc_device.h"
+
+namespace disc {
+namespace host {
+
+struct Layout {
+  size_t frames, mask_frame, tiles, dyn, frame_ctr, staged_end;  // staged region (uploaded from the host)
+  size_t bbox, area, meta, items, counts, psum, mean, r, s, W, Z, mstat, X, ssq, total;
+};
+
+struct Shape {
+  int n_frames = 0;
+  int64_t M = 0, sumG = 0, sumMGs = 0;
+  int C = 0, E = 0, gmax = 0, nchunk = 1, item_cap = 1, n_tiles = 0, gemm_bf16 = 0;
+};
+
+struct FrameIn {
+  const void* tokens = nullptr;
+  const float* scale = nullptr;
+  const uint64_t* bits = nullptr;
+  float* out = nullptr;
+  int32_t* status = nullptr;
+  float* pooled = nullptr;
+  int gh = 0, gw = 0, patch = 16, h = 0, w = 0, m = 0;
+};
+
+struct Plan {
+  Shape shape;
+  Layout L;
+  std::vector<FrameDesc> fds;
+  std::vector<int32_t> mask_frame;
+  std::vector<int4> tiles;
+};
+
+extern thread_local std::string g_err;
+bool aligned16(const void* p);
+int64_t round_up(int64_t x, int64_t a);
+disc_status fail(disc_status st, const char* fmt, ...);
+disc_status ok();
+disc_status hip_fail(hipError_t e, const char* what);
+disc_status check_tokens(const disc_tokens* t, const char* who);
+disc_status check_masks(const disc_masks* m, const char* who);
+disc_status check_grid(const disc_tokens* t, const disc_masks* m, const char* who);
+disc_status check_proj(const disc_proj* p, int c, const char* who);
+disc_status check_out(const disc_out* o, int m, int e, const char* who);
+disc_status check_opts(const disc_options* o, const char* who);
+disc_status check_launch(const char* who);
+Layout make_layout(const Shape& s);
+void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p);
+void stage_host(const Plan& p, char* host, char* dev);
+Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int distinct);
+Work work_ptrs(char* base, const Layout& L);
+int resolve_gemm(const disc_options* o, int tok_dtype, int proj_dtype);
+disc_options defaults();
+int num_cus(int dev);
+// Enqueue the whole kernel sequence of a staged plan on a stream.
+// trace = false while capturing a graph.
+void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options& o, const disc_proj* proj, int cus,
+                  hipStream_t st, bool trace = true);
+
+}  // namespace host
+}  // namespace disc

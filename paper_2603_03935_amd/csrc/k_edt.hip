@@ -29,6 +29,8 @@
 //   * each band walks the final envelope over its rows, producing e exactly,
 //     and sums sqrt(e) over each patch (segmented lane reduction per patch
 //     row; a patch row split between two bands is finished in fixed order).
+#include <mutex>
+
 #include "disc_device.h"
 
 namespace disc {
@@ -387,22 +389,35 @@ __global__ __launch_bounds__(768) void k_edt(Batch b, Work wk, int cls, int rows
   }
 }
 
+// Per-class LDS attribute and resident workgroups per CU, computed once
+// (outside any stream capture).
+static std::once_flag g_edt_once;
+static int g_edt_per_cu[2][kClasses];
+
+void edt_prepare() {
+  std::call_once(g_edt_once, [] {
+    for (int sp = 0; sp < 2; ++sp)
+      for (int c = 0; c < kClasses; ++c) {
+        const int threads = 64 * class_bands(c);
+        const size_t lds = (size_t)edt_lds_bytes(class_rows(c));
+        const void* fn = sp == 0 ? reinterpret_cast<const void*>(&k_edt<0>) : reinterpret_cast<const void*>(&k_edt<1>);
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+        g_edt_per_cu[sp][c] = per_cu;
+      }
+  });
+}
+
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st) {
+  edt_prepare();
+  const int sp = b.spatial == 0 ? 0 : 1;
   for (int c = 0; c < kClasses; ++c) {
     const int threads = 64 * class_bands(c);
     const int rows = class_rows(c);
     const size_t lds = (size_t)edt_lds_bytes(rows);
-    const void* fn = b.spatial == 0 ? reinterpret_cast<const void*>(&k_edt<0>) : reinterpret_cast<const void*>(&k_edt<1>);
-    static bool attr_done[2][kClasses] = {};
-    const int sp = b.spatial == 0 ? 0 : 1;
-    if (!attr_done[sp][c]) {
-      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      attr_done[sp][c] = true;
-    }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
-    const int grid = num_cus * per_cu;
-    if (b.spatial == 0)
+    const int grid = num_cus * g_edt_per_cu[sp][c];
+    if (sp == 0)
       hipLaunchKernelGGL(k_edt<0>, dim3(grid), dim3(threads), lds, st, b, w, c, rows, e_out);
     else
       hipLaunchKernelGGL(k_edt<1>, dim3(grid), dim3(threads), lds, st, b, w, c, rows, e_out);

@@ -87,6 +87,7 @@ __device__ __forceinline__ uint16_t tok_bf16(const void* base, int64_t off) {
 
 template <int BF16, int TOK>
 __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tiles) {
+  if ((int)blockIdx.x >= b.dyn[2]) return;
   const int4 t = tiles[blockIdx.x];
   const FrameDesc fd = b.frames[t.x];
   const int m0 = t.y, n0 = t.z, C = b.C;
@@ -233,6 +234,8 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
   const int C = b.C, E = b.E, nct = E / 128;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int gbase = blockIdx.x * 32, c0 = blockIdx.y * 128;
+  const int M = b.dyn[1];
+  if (gbase >= M) return;
   __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? 32 * AS : 1];
   __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? 128 * AS : 1];
   __shared__ float As32[BF16 ? 1 : 32 * (BK + 1)];
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
 
   auto fetch = [&](int k0) {
     if (BF16) {
-      ra16 = ga < b.M ? *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(wk.X) + (int64_t)ga * C + k0 + ak)
+      ra16 = ga < M ? *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(wk.X) + (int64_t)ga * C + k0 + ak)
                       : make_uint2(0, 0);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
         rb16[j] = PBF16 ? reinterpret_cast<const uint16_t*>(proj)[off] : f2bf(reinterpret_cast<const float*>(proj)[off]);
       }
     } else {
-      ra32 = ga < b.M ? *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(wk.X) + (int64_t)ga * C + k0 + ak)
+      ra32 = ga < M ? *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(wk.X) + (int64_t)ga * C + k0 + ak)
                       : make_float2(0.f, 0.f);
       const int64_t off = (int64_t)(k0 + bk32) * E + c0 + bc32;
       if (PBF16) {
@@ -333,12 +336,12 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
   for (int v = 0; v < 16; ++v) {
     const int r = 8 * (v >> 2) + 4 * lk + (v & 3);
     const int g = gbase + r;
-    if (g >= b.M) continue;
+    if (g >= M) continue;
     const FrameDesc& fd = b.frames[b.mask_frame[g]];
     fd.out[(int64_t)(g - fd.mask_base) * E + col] = acc[v];
   }
   __syncthreads();
-  if (tid < 32 && gbase + tid < b.M)
+  if (tid < 32 && gbase + tid < M)
     ssq[(int64_t)(gbase + tid) * nct + blockIdx.y] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
@@ -346,7 +349,7 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
 __global__ __launch_bounds__(256) void k_norm(Batch b, Work wk, const float* ssq) {
   const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (g >= b.M) return;
+  if (g >= b.dyn[1]) return;
   const int E = b.E, nct = E / 128;
   float tot = 0.f;
   for (int t = 0; t < nct; ++t) tot += ssq[(int64_t)g * nct + t];

@@ -24,7 +24,7 @@ __device__ inline int wave_sum(int v) {
 
 __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
   const int g = blockIdx.x;
-  if (g >= b.M) return;
+  if (g >= b.dyn[1]) return;
   const FrameDesc fd = b.frames[b.mask_frame[g]];
   const int wq = fd.wq, h = fd.h;
   const uint64_t* mb = fd.bits + (int64_t)(g - fd.mask_base) * h * wq;
@@ -109,13 +109,14 @@ __global__ __launch_bounds__(1024) void k_plan(Batch b, Work wk) {
   __shared__ int wsum[16];
   __shared__ int base_sh;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int M = b.dyn[1];
   for (int c = 0; c < kClasses; ++c) {
     if (tid == 0) base_sh = 0;
     __syncthreads();
-    for (int g0 = 0; g0 < b.M; g0 += 1024) {
+    for (int g0 = 0; g0 < M; g0 += 1024) {
       const int g = g0 + tid;
       int cnt = 0;
-      if (g < b.M) {
+      if (g < M) {
         const int meta = wk.meta[g];
         if (meta >= 0 && (meta >> 16) == c) cnt = meta & 0xFFFF;
       }

@@ -68,6 +68,7 @@ template <int TOK>
 __global__ __launch_bounds__(256) void k_colsum(Batch b, Work wk) {
   constexpr int VEC = TOK == 2 ? 16 : 8;
   const int f = blockIdx.y, chunk = blockIdx.x;
+  if (f >= b.dyn[0]) return;
   const FrameDesc fd = b.frames[f];
   const int G = fd.G, C = b.C;
   const int nch = (G + kChunk - 1) / kChunk;
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(256) void k_colsum(Batch b, Work wk) {
 // r_p = ||f_p - mean||: one wavefront per token, lanes over channels.
 __global__ __launch_bounds__(256) void k_rnorm(Batch b, Work wk) {
   const int f = blockIdx.y;
+  if (f >= b.dyn[0]) return;
   const FrameDesc fd = b.frames[f];
   const int G = fd.G, C = b.C;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -258,7 +260,7 @@ __device__ Neu block_neu(Neu z, float* red) {
 template <int BF16>
 __global__ __launch_bounds__(256) void k_weights(Batch b, Work wk) {
   const int g = blockIdx.x;
-  if (g >= b.M) return;
+  if (g >= b.dyn[1]) return;
   const FrameDesc fd = b.frames[b.mask_frame[g]];
   const int64_t rowoff = fd.w_base + (int64_t)(g - fd.mask_base) * fd.Gs;
   const int4 bb = wk.bbox[g];
@@ -303,7 +305,7 @@ void launch_weights(const Batch& b, const Work& w, hipStream_t st) {
 // Eq. (1) with eps (single frame).
 __global__ __launch_bounds__(256) void k_dense_weights(Batch b, Work wk, float* out, float eps) {
   const int g = blockIdx.x;
-  if (g >= b.M) return;
+  if (g >= b.dyn[1]) return;
   const FrameDesc fd = b.frames[b.mask_frame[g]];
   const int G = fd.G, gw = fd.gw, P = fd.patch;
   const int4 bb = wk.bbox[g];
@@ -343,7 +345,7 @@ void launch_dense_weights(const Batch& b, const Work& w, float* out, float eps, 
 template <int BF16>
 __global__ __launch_bounds__(256) void k_user_weights(Batch b, Work wk, const float* wts) {
   const int g = blockIdx.x;
-  if (g >= b.M) return;
+  if (g >= b.dyn[1]) return;
   const FrameDesc fd = b.frames[b.mask_frame[g]];
   const int G = fd.G;
   const int64_t rowoff = fd.w_base + (int64_t)(g - fd.mask_base) * fd.Gs;
