@@ -158,6 +158,7 @@ Layout make_layout(const Shape& s) {
   L.mstat = take(4 * (size_t)s.M);
   L.X = take((s.gemm_bf16 ? 2 : 4) * (size_t)s.M * s.C);
   L.ssq = take(4 * (size_t)s.M * 8);
+  L.tkp = take(s.gemm_bf16 ? (size_t)s.tkp_elems * s.tkp_esize : 0);
   L.total = off;
   return L;
 }
@@ -269,6 +270,7 @@ Work work_ptrs(char* base, const Layout& L) {
   w.mstat = reinterpret_cast<int32_t*>(base + L.mstat);
   w.X = base + L.X;
   w.ssq = reinterpret_cast<float*>(base + L.ssq);
+  w.tkp = base + L.tkp;
   return w;
 }
 
@@ -277,13 +279,13 @@ Work work_ptrs(char* base, const Layout& L) {
 // --------------------------------------------------------------------------
 
 
-void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p) {
+void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p, int tok_dtype) {
   Shape& s = p.shape;
   s.n_frames = (int)fr.size();
   s.C = C;
   s.E = E;
   s.gemm_bf16 = gemm_bf16;
-  int64_t M = 0, sumG = 0, sumMGs = 0;
+  int64_t M = 0, sumG = 0, sumMGs = 0, tkp = 0;
   int gmax = 0, nchunk = 1;
   int64_t item_cap = 1;
   p.fds.resize(fr.size());
@@ -308,6 +310,7 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
     d.Gs = (int32_t)round_up(d.G, 8);
     d.w_base = sumMGs;
     d.r_base = sumG;
+    d.t_base = tkp;
     p.fds[i] = d;
     for (int j = 0; j < f.m; ++j) p.mask_frame.push_back((int32_t)i);
     for (int m0 = 0; m0 < f.m; m0 += 64)
@@ -315,6 +318,7 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
     M += f.m;
     sumG += d.G;
     sumMGs += (int64_t)f.m * d.Gs;
+    tkp += (int64_t)round_up(d.G, 8) * C;
     gmax = std::max(gmax, d.G);
     nchunk = std::max(nchunk, (d.G + 63) / 64);
     item_cap += (int64_t)f.m * ((f.w + strip_width(f.patch) - 1) / strip_width(f.patch) + 1);
@@ -322,6 +326,8 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
   s.M = M;
   s.sumG = sumG;
   s.sumMGs = sumMGs;
+  s.tkp_elems = tkp;
+  s.tkp_esize = tok_dtype == DISC_F8E4M3 ? 1 : 2;
   s.gmax = gmax;
   s.nchunk = nchunk;
   s.item_cap = (int)std::min<int64_t>(item_cap, INT32_MAX / 2);
@@ -487,7 +493,10 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   const int4* tiles = reinterpret_cast<const int4*>(dev_ws + p.L.tiles);
   { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st); }
   { StageTimer t(sid < 0 ? -1 : ST_PLAN, st); launch_plan(b, w, st); }
-  if (o.distinct) { StageTimer t(sid < 0 ? -1 : ST_STATS, st); launch_token_stats(b, w, p.shape.gmax, st); }
+  if (o.distinct || p.shape.gemm_bf16) {
+    StageTimer t(sid < 0 ? -1 : ST_STATS, st);
+    launch_token_stats(b, w, p.shape.gmax, o.distinct, p.shape.gemm_bf16, st);
+  }
   { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st); }
   { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); }
   { StageTimer t(sid < 0 ? -1 : ST_POOL, st); launch_pool(b, w, tiles, p.shape.n_tiles, st); }
@@ -532,7 +541,7 @@ size_t disc_workspace_bytes(const disc_tokens* tokens, const disc_masks* masks, 
   if (describe(tokens, masks, n_frames, proj, outs.data(), opts, "disc_workspace_bytes", fr) != DISC_OK) return 0;
   if (n_frames == 0) return 0;
   Plan p;
-  build_plan(fr, tokens[0].c, proj->e, resolve_gemm(opts, tokens[0].dtype, proj->dtype), p);
+  build_plan(fr, tokens[0].c, proj->e, resolve_gemm(opts, tokens[0].dtype, proj->dtype), p, tokens[0].dtype);
   return p.L.total;
 }
 
@@ -547,7 +556,7 @@ disc_status disc_embed_frames(const disc_tokens* tokens, const disc_masks* masks
   for (auto& f : fr) M += f.m;
   if (n_frames == 0 || M == 0) return ok();
   Plan p;
-  build_plan(fr, tokens[0].c, proj->e, resolve_gemm(&o, tokens[0].dtype, proj->dtype), p);
+  build_plan(fr, tokens[0].c, proj->e, resolve_gemm(&o, tokens[0].dtype, proj->dtype), p, tokens[0].dtype);
   Ctx cx;
   if ((st = acquire(static_cast<hipStream_t>(stream), p.L, &o, cx))) return st;
   stage_host(p, cx.host_stage, cx.dev_ws);
@@ -648,7 +657,7 @@ disc_status disc_patch_weights(const disc_tokens* tokens, const disc_masks* mask
   const Work w = work_ptrs(cx.dev_ws, p.L);
   launch_scan(b, w, cx.st);
   launch_plan(b, w, cx.st);
-  if (o.distinct) launch_token_stats(b, w, p.shape.gmax, cx.st);
+  if (o.distinct) launch_token_stats(b, w, p.shape.gmax, 1, 0, cx.st);
   launch_edt(b, w, nullptr, num_cus(cx.dev), cx.st);
   launch_dense_weights(b, w, wout, o.eps, cx.st);
   if ((st = check_launch(who))) return st;
@@ -680,7 +689,7 @@ disc_status disc_token_stats(const disc_tokens* tokens, float eps, float* mean, 
   const Batch b = make_batch(p, cx.dev_ws, tokens->dtype, 0, 1);
   const Work w = work_ptrs(cx.dev_ws, p.L);
   const int G = tokens->gh * tokens->gw;
-  launch_token_stats(b, w, G, cx.st);
+  launch_token_stats(b, w, G, 1, 0, cx.st);
   if (mean) launch_copy_f32(w.mean, mean, tokens->c, cx.st);
   if (r) launch_copy_f32(w.r, r, G, cx.st);
   if (D) launch_d_from_r(w.r, G, eps, D, cx.st);
@@ -716,7 +725,7 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32
   f.status = out->mask_status;
   f.pooled = out->pooled;
   Plan p;
-  build_plan({f}, tokens->c, proj->e, resolve_gemm(&o, tokens->dtype, proj->dtype), p);
+  build_plan({f}, tokens->c, proj->e, resolve_gemm(&o, tokens->dtype, proj->dtype), p, tokens->dtype);
   Ctx cx;
   if ((st = acquire(static_cast<hipStream_t>(stream), p.L, nullptr, cx))) return st;
   stage_host(p, cx.host_stage, cx.dev_ws);
@@ -725,6 +734,7 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32
   const Work w = work_ptrs(cx.dev_ws, p.L);
   const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
   launch_user_weights(b, w, wts, cx.st);
+  if (p.shape.gemm_bf16) launch_token_stats(b, w, p.shape.gmax, 0, 1, cx.st);
   launch_pool(b, w, tiles, p.shape.n_tiles, cx.st);
   launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, w.ssq, cx.st);
   if ((st = check_launch(who))) return st;

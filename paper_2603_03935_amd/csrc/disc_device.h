@@ -51,6 +51,7 @@ struct FrameDesc {
   int32_t Gs;             // row stride of the per-mask weight rows (G rounded up to 8)
   int64_t w_base;         // element offset of this frame's [m][Gs] block in s/W
   int64_t r_base;         // offset of this frame's G entries in r
+  int64_t t_base;         // element offset of this frame's k-packed tokens
 };
 
 // Scalar arguments shared by the kernels of one call.  n_frames and M are
@@ -87,6 +88,7 @@ struct Work {
   int32_t* mstat;      // [M] 0 ok, 1 empty
   void* X;             // [M][C] pooled features in the GEMM dtype
   float* ssq;          // [M][E/128] partial sums of squares of the projected rows
+  void* tkp;           // k-packed tokens [sum ceil(G/8)][C][8] (BF16 bits, or e4m3 codes for FP8 tokens)
 };
 
 // Host-side launchers (stream = hipStream_t).
@@ -94,7 +96,8 @@ void launch_scan(const Batch& b, const Work& w, hipStream_t st);
 void launch_plan(const Batch& b, const Work& w, hipStream_t st);
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st);
 void edt_prepare();
-void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st);
+// want_r: residual norms (needs the mean); pack: k-packed token copy for the BF16 pooling GEMM
+void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
 void launch_pool(const Batch& b, const Work& w, const int4* tiles, int n_tiles, hipStream_t st);
 void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, float* ssq, hipStream_t st);

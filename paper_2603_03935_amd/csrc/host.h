@@ -13,13 +13,15 @@ namespace host {
 
 struct Layout {
   size_t frames, mask_frame, tiles, dyn, frame_ctr, staged_end;  // staged region (uploaded from the host)
-  size_t bbox, area, meta, items, counts, psum, mean, r, s, W, Z, mstat, X, ssq, total;
+  size_t bbox, area, meta, items, counts, psum, mean, r, s, W, Z, mstat, X, ssq, tkp, total;
 };
 
 struct Shape {
   int n_frames = 0;
   int64_t M = 0, sumG = 0, sumMGs = 0;
   int C = 0, E = 0, gmax = 0, nchunk = 1, item_cap = 1, n_tiles = 0, gemm_bf16 = 0;
+  int64_t tkp_elems = 0;  // sum over frames of ceil(G/8)*8*C (k-packed tokens, BF16 GEMM only)
+  int tkp_esize = 2;      // bytes per k-packed element: 1 for FP8 tokens, else 2
 };
 
 struct FrameIn {
@@ -54,7 +56,7 @@ disc_status check_out(const disc_out* o, int m, int e, const char* who);
 disc_status check_opts(const disc_options* o, const char* who);
 disc_status check_launch(const char* who);
 Layout make_layout(const Shape& s);
-void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p);
+void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p, int tok_dtype = DISC_BF16);
 void stage_host(const Plan& p, char* host, char* dev);
 Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int distinct);
 Work work_ptrs(char* base, const Layout& L);

@@ -94,11 +94,14 @@ __device__ __forceinline__ int g_from_window(uint64_t win, int l, int L, int R) 
 }
 
 // Site m (p < m < q, parabola heights F) never lies strictly below both p and
-// q: q overtakes p no later than m does.  Exact in 64-bit integers.
+// q: q overtakes p no later than m does, i.e. Aq/(q-p) <= Am/(m-p) with
+// A = F - Fp + (site^2 - p^2).  |A| < 2^22 and the row distances < 2^11, so
+// both products are below 2^33 and exact in double precision (FP64 FMA runs
+// at the FP32 rate on gfx950, unlike 64-bit integer products).
 __device__ __forceinline__ bool dominated(int p, int Fp, int m, int Fm, int q, int Fq) {
-  const long long Am = (long long)(Fm - Fp) + (long long)((m - p) * (m + p));
-  const long long Aq = (long long)(Fq - Fp) + (long long)((q - p) * (q + p));
-  return Aq * (long long)(m - p) <= Am * (long long)(q - p);
+  const int Am = (Fm - Fp) + (m - p) * (m + p);
+  const int Aq = (Fq - Fp) + (q - p) * (q + p);
+  return (double)Aq * (double)(m - p) <= (double)Am * (double)(q - p);
 }
 
 __device__ __forceinline__ int parab(int site, int F, int y) { return (y - site) * (y - site) + F; }
@@ -204,7 +207,8 @@ __global__ __launch_bounds__(768) void k_edt(Batch b, Work wk, int cls, int rows
   float* part = reinterpret_cast<float*>(smem + edt_g_bytes(rows_cap) + edt_bm_bytes(rows_cap));
   __shared__ int item_sh;
 
-  const int lane = threadIdx.x & 63, kb = threadIdx.x >> 6, K = blockDim.x >> 6;
+  // the band index is wave-uniform; make that visible so row loops run on scalars
+  const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), K = blockDim.x >> 6;
   const int32_t* list = wk.items + (int64_t)cls * b.item_cap;
   const int count = wk.counts[cls];
   const int nbm = edt_bm_words(rows_cap);
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(768) void k_edt(Batch b, Work wk, int cls, int rows
           cur_pr = pr;
           acc = 0.f;
         }
-        acc += SPATIAL == 0 ? __builtin_sqrtf((float)e) : (float)e;
+        acc += SPATIAL == 0 ? __builtin_amdgcn_sqrtf((float)e) : (float)e;  // e >= 0 integer: no denormals
         if (e_out != nullptr && lane_ok && col >= x0 && col <= x1)
           e_out[(int64_t)g * fd.h * fw + (int64_t)Y * fw + col] = e;
       }

@@ -68,12 +68,12 @@ __device__ __forceinline__ void load_tok8(const void* base, int64_t off, bool ok
 
 // ---------------------------------------------------------------------------
 // pooling: tile 64 masks x 64 channels, K = patches in chunks of 32.
-// A (weights, k contiguous) is staged row-major; for BF16 operands B (tokens,
-// channel contiguous in memory) is gathered k-packed straight from global
-// memory -- each lane reads 8 consecutive patches of one channel, every load
-// instruction still covering a contiguous run of channels -- so the MFMA
-// operand of a lane is one 16-byte LDS read.  The next K chunk is fetched
-// into registers while the current one is multiplied.
+// A (weights, k contiguous) is staged row-major; for BF16 operands B is read
+// from the k-packed token copy written by the statistics pass (8 consecutive
+// patches of one channel contiguous), so each B load is one vector and the
+// MFMA operand of a lane is one 16-byte LDS read.  FP8 codes are widened to
+// BF16 here.  The next K chunk is fetched into registers while the current one
+// is multiplied.
 // ---------------------------------------------------------------------------
 constexpr int PBM = 64, PBN = 64, PBK = 32;
 constexpr int PAS = PBK + 8;  // LDS row stride (elements) of A and k-packed B
@@ -141,13 +141,24 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
         for (int j = 0; j < 8; ++j) tmp[j] = (arow_ok && kk + j < G) ? src[j] : (uint16_t)0;
         ra16 = make_uint4(tmp[0] | (tmp[1] << 16), tmp[2] | (tmp[3] << 16), tmp[4] | (tmp[5] << 16), tmp[6] | (tmp[7] << 16));
       }
-      uint16_t tb[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int kr = k0 + bk16 + j;
-        tb[j] = kr < G ? tok_bf16<TOK>(fd.tokens, (int64_t)kr * C + n0 + bn16) : (uint16_t)0;
+      // k-packed tokens: one vector load gives this channel's 8 patches
+      const int grp = (k0 + bk16) >> 3;
+      if (grp * 8 < G) {
+        const int64_t e = fd.t_base + ((int64_t)grp * C + n0 + bn16) * 8;
+        if (TOK == 2) {
+          const uint2 q = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(wk.tkp) + e);
+          uint32_t o[4];
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t w2 = j < 2 ? q.x : q.y;
+            o[j] = e4m3_to_bf16((w2 >> (16 * (j & 1))) & 0xFFu) | ((uint32_t)e4m3_to_bf16((w2 >> (16 * (j & 1) + 8)) & 0xFFu) << 16);
+          }
+          rb16 = make_uint4(o[0], o[1], o[2], o[3]);
+        } else {
+          rb16 = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(wk.tkp) + e);
+        }
+      } else {
+        rb16 = make_uint4(0, 0, 0, 0);
       }
-      rb16 = make_uint4(tb[0] | (tb[1] << 16), tb[2] | (tb[3] << 16), tb[4] | (tb[5] << 16), tb[6] | (tb[7] << 16));
     } else {
       const float* src = reinterpret_cast<const float*>(wk.W) + wrow0 + (int64_t)ar * fd.Gs + kk;
       for (int j = 0; j < 8; ++j) ra32[j] = (arow_ok && kk + j < G) ? src[j] : 0.f;

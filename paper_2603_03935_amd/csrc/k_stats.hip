@@ -119,33 +119,118 @@ __global__ __launch_bounds__(256) void k_colsum(Batch b, Work wk) {
   if (tid == 0) wk.frame_ctr[f] = 0u;
 }
 
-// r_p = ||f_p - mean||: one wavefront per token, lanes over channels.
-__global__ __launch_bounds__(256) void k_rnorm(Batch b, Work wk) {
+// One workgroup per group of 8 consecutive tokens p0..p0+7 of a frame:
+//   * WANT_R: r_p = ||f_p - mean|| for the 8 tokens (block reduction);
+//   * PACK:   the k-packed copy tkp[p0/8][c][0..7] = (f_p0..f_p7)[c] that the
+//             BF16 pooling GEMM reads with one vector load per (8 patches,
+//             channel): BF16 bits (FP32 tokens rounded to nearest even), or
+//             the raw e4m3 codes for FP8 tokens.  Tokens past G pack as 0.
+// Each thread owns CW consecutive channels and loads them for all 8 tokens.
+template <int TOK, int WANT_R, int PACK>
+__global__ __launch_bounds__(256) void k_tokpack(Batch b, Work wk) {
+  constexpr int CW = TOK == 2 ? 8 : 4;
   const int f = blockIdx.y;
   if (f >= b.dyn[0]) return;
   const FrameDesc fd = b.frames[f];
   const int G = fd.G, C = b.C;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int grp = blockIdx.x, p0 = grp * 8;
+  if (p0 >= G) return;
+  const int tid = threadIdx.x;
   const float* mu = wk.mean + (int64_t)f * C;
-  for (int p = blockIdx.x * 16 + wv; p < min(G, (int)(blockIdx.x + 1) * 16); p += 4) {
-    float a = 0.f;
-    for (int c = lane * 4; c < C; c += 256) {
-      const float4 v = load4(fd.tokens, b.tok_dtype, fd.scale, p, C, c);
-      const float4 m = *reinterpret_cast<const float4*>(mu + c);
-      const float dx = v.x - m.x, dy = v.y - m.y, dz = v.z - m.z, dw = v.w - m.w;
-      a += dx * dx + dy * dy + dz * dz + dw * dw;
+  float ss[8];
+  for (int i = 0; i < 8; ++i) ss[i] = 0.f;
+  for (int chunk = tid; chunk < C / CW; chunk += 256) {
+    const int c = chunk * CW;
+    float v[8][CW];
+    uint2 codes[8];  // FP8 only: the 8 raw codes of channels c..c+7
+    for (int i = 0; i < 8; ++i) {
+      const int p = p0 + i;
+      codes[i] = make_uint2(0u, 0u);
+      for (int j = 0; j < CW; ++j) v[i][j] = 0.f;
+      if (p >= G) continue;
+      const int64_t off = (int64_t)p * C + c;
+      if (TOK == 0) {
+        const float4 a = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(fd.tokens) + off);
+        v[i][0] = a.x; v[i][1] = a.y; v[i][2] = a.z; v[i][3] = a.w;
+      } else if (TOK == 1) {
+        const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(fd.tokens) + off);
+        v[i][0] = bf16_to_f32(a.x & 0xFFFFu); v[i][1] = bf16_to_f32(a.x >> 16);
+        v[i][2] = bf16_to_f32(a.y & 0xFFFFu); v[i][3] = bf16_to_f32(a.y >> 16);
+      } else {
+        const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(fd.tokens) + off);
+        codes[i] = a;
+        if (WANT_R) {
+          const float sc = fd.scale[p];
+          for (int j = 0; j < 8; ++j) v[i][j] = sc * e4m3_to_f32(((j < 4 ? a.x : a.y) >> (8 * (j & 3))) & 0xFFu);
+        }
+      }
     }
-    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-    if (lane == 0) wk.r[fd.r_base + p] = __builtin_sqrtf(a);
+    if (WANT_R) {
+      for (int j = 0; j < CW; ++j) {
+        const float m = mu[c + j];
+        for (int i = 0; i < 8; ++i) {
+          const float dd = (p0 + i < G) ? v[i][j] - m : 0.f;
+          ss[i] += dd * dd;
+        }
+      }
+    }
+    if (PACK) {
+      if (TOK == 2) {
+        // channel j: the codes of tokens 0..7 -> 8 bytes
+        uint2* dst = reinterpret_cast<uint2*>(reinterpret_cast<uint8_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
+        for (int j = 0; j < 8; ++j) {
+          uint32_t lo = 0, hi = 0;
+          for (int i = 0; i < 4; ++i) lo |= (((j < 4 ? codes[i].x : codes[i].y) >> (8 * (j & 3))) & 0xFFu) << (8 * i);
+          for (int i = 0; i < 4; ++i) hi |= (((j < 4 ? codes[i + 4].x : codes[i + 4].y) >> (8 * (j & 3))) & 0xFFu) << (8 * i);
+          dst[j] = make_uint2(lo, hi);
+        }
+      } else {
+        // channel j: the BF16 values of tokens 0..7 -> 16 bytes
+        uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
+        for (int j = 0; j < 4; ++j) {
+          uint32_t q[8];
+          for (int i = 0; i < 8; ++i) {
+            const uint32_t u = __float_as_uint(v[i][j]);
+            q[i] = TOK == 1 ? (u >> 16) : ((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+          }
+          dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
+        }
+      }
+    }
+  }
+  if (WANT_R) {
+    __shared__ float red[4][8];
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int i = 0; i < 8; ++i) {
+      float a = ss[i];
+      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+      if (lane == 0) red[wv][i] = a;
+    }
+    __syncthreads();
+    if (tid < 8 && p0 + tid < G)
+      wk.r[fd.r_base + p0 + tid] = __builtin_sqrtf(red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid]);
   }
 }
 
-void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st) {
-  const dim3 cgrid(b.nchunk, b.n_frames);
-  if (b.tok_dtype == 0) hipLaunchKernelGGL(k_colsum<0>, cgrid, dim3(256), 0, st, b, w);
-  else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_colsum<1>, cgrid, dim3(256), 0, st, b, w);
-  else hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
-  hipLaunchKernelGGL(k_rnorm, dim3((gmax + 15) / 16, b.n_frames), dim3(256), 0, st, b, w);
+template <int TOK>
+static void launch_tokpack_t(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st) {
+  const dim3 grid((gmax + 7) / 8, b.n_frames), block(256);
+  if (want_r && pack) hipLaunchKernelGGL((k_tokpack<TOK, 1, 1>), grid, block, 0, st, b, w);
+  else if (want_r) hipLaunchKernelGGL((k_tokpack<TOK, 1, 0>), grid, block, 0, st, b, w);
+  else if (pack) hipLaunchKernelGGL((k_tokpack<TOK, 0, 1>), grid, block, 0, st, b, w);
+}
+
+void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st) {
+  if (want_r) {
+    const dim3 cgrid(b.nchunk, b.n_frames);
+    if (b.tok_dtype == 0) hipLaunchKernelGGL(k_colsum<0>, cgrid, dim3(256), 0, st, b, w);
+    else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_colsum<1>, cgrid, dim3(256), 0, st, b, w);
+    else hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
+  }
+  if (!want_r && !pack) return;
+  if (b.tok_dtype == 0) launch_tokpack_t<0>(b, w, gmax, want_r, pack, st);
+  else if (b.tok_dtype == 1) launch_tokpack_t<1>(b, w, gmax, want_r, pack, st);
+  else launch_tokpack_t<2>(b, w, gmax, want_r, pack, st);
 }
 
 // D = r / (mean(r) + eps) for one frame (stage entry point only).

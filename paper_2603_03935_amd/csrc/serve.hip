@@ -65,6 +65,8 @@ Shape capacity_shape(const disc_server_config& c, int E, int gemm_bf16) {
   s.item_cap = (int)std::min<int64_t>((int64_t)c.max_masks * ((c.max_w + 31) / 32 + 1) + 1, INT32_MAX / 2);
   s.n_tiles = ((c.max_masks + 63) / 64 + c.max_frames) * (c.c / 64);
   s.gemm_bf16 = gemm_bf16;
+  s.tkp_elems = (int64_t)c.max_frames * round_up(G, 8) * c.c;
+  s.tkp_esize = c.tok_dtype == DISC_F8E4M3 ? 1 : 2;
   return s;
 }
 
@@ -124,7 +126,7 @@ int32_t disc_server::run_batch(Lane& ln, const std::vector<Request>& batch) {
   fr.reserve(batch.size());
   for (const Request& r : batch) fr.push_back(r.fin);
   Plan p;
-  build_plan(fr, cfg.c, cfg.proj.e, gemm_bf16, p);
+  build_plan(fr, cfg.c, cfg.proj.e, gemm_bf16, p, cfg.tok_dtype);
   hipError_t e;
   if (cfg.use_graph) {
     if (!ln.graph_ready && capture(ln) != DISC_OK) return DISC_ERR_DEVICE;
