@@ -46,8 +46,9 @@
  *   proj    [c][e] row-major.
  *   out     [m][e] FP32 rows of unit L2 norm (or zero rows, see above).
  *
- * Limits of this version: h, w >= 1, every mask's bounding box at most 1118
- * rows tall (frames up to 1118 rows are always accepted), 8 <= patch <= 64,
+ * Limits of this version: h, w >= 1, w <= 8448, every mask's bounding box at
+ * most 1150 rows tall (frames up to 1150 rows are always accepted),
+ * 8 <= patch <= 64,
  * c a multiple of 64 up to 2048, e a multiple of 128 up to 1024.
  */
 #ifndef DISC_H

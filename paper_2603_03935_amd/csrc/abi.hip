@@ -42,7 +42,10 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-constexpr int kMaxWidth = 256 * 56;  // strips per mask fit in 8 bits for every patch size
+// A strip is at least 33 columns wide for every patch size in [8, 64]
+// (SW = 64 - 64 % P), so 256 strips, the most an item word encodes, cover
+// 256 * 33 columns.
+constexpr int kMaxWidth = 256 * 33;
 
 // --------------------------------------------------------------------------
 // validation
@@ -147,8 +150,9 @@ Layout make_layout(const Shape& s) {
   L.bbox = take(16 * (size_t)s.M);
   L.area = take(4 * (size_t)s.M);
   L.meta = take(4 * (size_t)s.M);
-  L.items = take(4 * (size_t)kClasses * s.item_cap);
-  L.counts = take(4 * 16);
+  L.mrec = take(sizeof(MaskRec) * (size_t)s.M);
+  L.items = take(4 * (size_t)s.item_cap);
+  L.counts = take(4 * 32);
   L.psum = take(4 * (size_t)s.n_frames * s.nchunk * s.C);
   L.mean = take(4 * (size_t)s.n_frames * s.C);
   L.r = take(4 * (size_t)s.sumG);
@@ -257,9 +261,9 @@ Work work_ptrs(char* base, const Layout& L) {
   w.bbox = reinterpret_cast<int4*>(base + L.bbox);
   w.area = reinterpret_cast<int32_t*>(base + L.area);
   w.meta = reinterpret_cast<int32_t*>(base + L.meta);
+  w.mrec = reinterpret_cast<MaskRec*>(base + L.mrec);
   w.items = reinterpret_cast<int32_t*>(base + L.items);
   w.counts = reinterpret_cast<int32_t*>(base + L.counts);
-  w.counters = w.counts + 8;
   w.frame_ctr = reinterpret_cast<uint32_t*>(base + L.frame_ctr);
   w.psum = reinterpret_cast<float*>(base + L.psum);
   w.mean = reinterpret_cast<float*>(base + L.mean);

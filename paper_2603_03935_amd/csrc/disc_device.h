@@ -10,16 +10,19 @@ namespace disc {
 // Distance-transform work decomposition.
 //
 // A work item is (mask, strip): SW(P) = 64 - 64 % P consecutive pixel columns
-// starting on a patch boundary, processed by one workgroup whose wavefronts
-// each own a band of kBand rows of the mask's bounding box (plus one padding
-// row above and below).  The row count n = bbox height + 2 picks the class,
-// i.e. the workgroup size (K bands) and the LDS footprint.
+// starting on a patch boundary.  The item's rows (bounding-box height + one
+// padding row above and below, n rows) are split into bands of B rows, one
+// wavefront per band.  The row count picks the class: B and the band count K.
+// One EDT workgroup has kEdtWaves wavefronts and processes a packet of
+// kEdtWaves / K items of one class side by side.
 // ---------------------------------------------------------------------------
-constexpr int kBand = 96;      // rows per band: 3 x 32-bit stack-bitmap words per lane
-constexpr int kClasses = 5;
-__host__ __device__ constexpr int class_bands(int c) { return c == 0 ? 1 : c == 1 ? 2 : c == 2 ? 4 : c == 3 ? 8 : 12; }
-__host__ __device__ constexpr int class_rows(int c) { return c == 4 ? 1120 : class_bands(c) * kBand; }
-constexpr int kMaxRows = 1120;      // bbox height + 2
+constexpr int kClasses = 6;
+constexpr int kEdtWaves = 16;
+__host__ __device__ constexpr int class_band(int c) { return c == 5 ? 96 : 32; }
+__host__ __device__ constexpr int class_waves(int c) { return c == 5 ? 12 : (1 << c); }
+__host__ __device__ constexpr int class_rows(int c) { return class_band(c) * class_waves(c); }
+__host__ __device__ constexpr int class_items(int c) { return kEdtWaves / class_waves(c); }  // items per packet
+constexpr int kMaxRows = 1152;      // bbox height + 2
 constexpr int kMinPatch = 8;
 constexpr int kMaxPatch = 64;
 constexpr int kItemStripBits = 8;   // item = (mask << 8) | strip
@@ -27,15 +30,20 @@ constexpr int kMaxC = 2048;
 
 __host__ __device__ inline int strip_width(int patch) { return 64 - (64 % patch); }
 
-// LDS layout of one EDT workgroup for a class with `rows` capacity.
-__host__ __device__ inline int edt_g_bytes(int rows) { return rows * 64 * 2; }         // int16 g[rows][64]
-__host__ __device__ inline int edt_bm_words(int rows) { return (rows + 31) / 32; }
-__host__ __device__ inline int edt_bm_bytes(int rows) { return edt_bm_words(rows) * 64 * 4; }  // u32 bm[words][64]
-__host__ __device__ inline int edt_part_rows(int rows) { return rows / kMinPatch + 3; }
-__host__ __device__ inline int edt_part_bytes(int rows) { return edt_part_rows(rows) * 8 * 2 * 4; }  // f32 [pr][8][2]
-__host__ __device__ inline int edt_lds_bytes(int rows) {
-  return edt_g_bytes(rows) + edt_bm_bytes(rows) + edt_part_bytes(rows);
-}
+// LDS of one EDT workgroup (every class fits kMaxRows rows): a 16-byte record
+// per row, the per-column stack bitmaps (one bit per row) and each band's
+// partial patch sums (a band of at most 96 rows meets at most 13 patch rows of
+// at least 8 pixels).
+constexpr int kEdtBmWords = kMaxRows / 32 + 1;
+constexpr int kEdtPartRows = 13;
+// Per-mask record of the distance transform (written by the mask scan).
+struct MaskRec {
+  const uint64_t* bits;    // the mask's first row
+  float* srow;             // the mask's spatial-weight row
+  int32_t y0, y1, x0, x1;  // bounding box
+  int32_t n, patch, gw, wq;
+  int32_t w, h, xs0, g;    // frame width/height, first strip column, global mask index
+};
 
 // One frame of a (possibly ragged) batch, in device memory.
 struct FrameDesc {
@@ -75,9 +83,9 @@ struct Work {
   int4* bbox;          // [M] (y0, y1, x0, x1); y0 > y1 for an empty mask
   int32_t* area;       // [M]
   int32_t* meta;       // [M] (class << 16) | strips, -1 empty
-  int32_t* items;      // [kClasses][item_cap]
-  int32_t* counts;     // [kClasses] items per class
-  int32_t* counters;   // [kClasses] dynamic work counters
+  MaskRec* mrec;       // [M]
+  int32_t* items;      // [item_cap] (mask << 8) | strip, classes back to back
+  int32_t* counts;     // [kClasses] items per class, then [kClasses] class bases in items
   uint32_t* frame_ctr; // [F] last-block tickets of the token statistics
   float* psum;         // [F][nchunk][C]
   float* mean;         // [F][C]

@@ -13,7 +13,7 @@ namespace host {
 
 struct Layout {
   size_t frames, mask_frame, tiles, dyn, frame_ctr, staged_end;  // staged region (uploaded from the host)
-  size_t bbox, area, meta, items, counts, psum, mean, r, s, W, Z, mstat, X, ssq, tkp, total;
+  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, s, W, Z, mstat, X, ssq, tkp, total;
 };
 
 struct Shape {

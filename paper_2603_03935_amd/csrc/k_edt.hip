@@ -11,18 +11,18 @@
 // nearest outside pixel lies in that ring or inside the box, so the result is
 // the full-plane one.
 //
-// GPU decomposition (one workgroup per (mask, column strip) work item, taken
-// from a per-class queue by a persistent grid):
+// GPU decomposition (one workgroup per (mask, column strip) work item; a grid
+// sized to the resident capacity takes the items of a class in a fixed stride):
 //   * lanes = 64 consecutive columns, wavefront k = rows [96k, 96k+96) of the
 //     padded box ("band");
-//   * row pass straight from the packed bits: each lane fetches, for one row of
-//     its band, the 64-bit window of the strip and the run lengths that
-//     continue past the window's ends (all rows in parallel); the sequential
-//     pass broadcasts each row with readlane and every lane finds its nearest
-//     zero bit with clz/ctz;
+//   * row records straight from the packed bits: each lane reads, for one row
+//     of its band, the strip's 64-bit window and the run lengths that continue
+//     past the window's ends, and stores the (at most two) runs crossing the
+//     window as intervals, so that g of any column is two min/max operations
+//     (windows crossed by more runs keep the bits and use clz/ctz);
 //   * each band builds the lower envelope of its own rows; the envelope is a
-//     stack of row indices kept as a 96-bit bitmap in registers (exact integer
-//     intersection tests, 64-bit cross products);
+//     stack of row indices kept as a 96-bit bitmap in registers (exact
+//     intersection tests: cross products below 2^33, exact in FP64);
 //   * band envelopes are merged pairwise in LDS (the merged envelope keeps a
 //     prefix of the upper one and a suffix of the lower one: pop dominated
 //     sites at the junction);
@@ -93,18 +93,55 @@ __device__ __forceinline__ int g_from_window(uint64_t win, int l, int L, int R) 
   return min(dl, dr);
 }
 
+// Row record (16 bytes): the strip window's bits (x, y) and up to two runs of
+// mask pixels crossing the window as open intervals (a, b) in window
+// coordinates, the run lengths past the window's ends folded in, so that
+// g(l) = max(0, min(l - a, b - l)).  z = a1 | b1 << 16, w = a2 | b2 << 16.
+// A window crossed by three or more runs stores b1 = -32768 and w = L | R << 16
+// (run lengths past the two ends) and takes the bit path.
+constexpr int kManyRuns = -32768;
+
+__device__ __forceinline__ uint4 make_rowrec(uint64_t win, int L, int R) {
+  int a[2] = {0, 0}, bnd[2] = {0, 0};
+  int nr = 0;
+  uint64_t t = win;
+  while (t != 0ull && nr < 3) {
+    const int s0 = __builtin_ctzll(t);
+    const uint64_t zeros = ~t & (~0ull << s0);
+    const int e0 = zeros ? __builtin_ctzll(zeros) - 1 : 63;
+    if (nr < 2) {
+      a[nr] = (s0 == 0 ? -L : s0) - 1;
+      bnd[nr] = (e0 == 63 ? 63 + R : e0) + 1;
+    }
+    ++nr;
+    t = e0 == 63 ? 0ull : (t & (~0ull << (e0 + 1)));
+  }
+  const uint32_t lo = (uint32_t)win, hi = (uint32_t)(win >> 32);
+  if (nr >= 3) return make_uint4(lo, hi, (uint32_t)(0xFFFFu | ((uint32_t)(uint16_t)kManyRuns << 16)), (uint32_t)L | ((uint32_t)R << 16));
+  return make_uint4(lo, hi, (uint32_t)(uint16_t)a[0] | ((uint32_t)(uint16_t)bnd[0] << 16),
+                    (uint32_t)(uint16_t)a[1] | ((uint32_t)(uint16_t)bnd[1] << 16));
+}
+
+// horizontal distance g of window column l from a row record
+__device__ __forceinline__ int g_rec(uint4 r, int l) {
+  const int b1 = (int)r.z >> 16;
+  if (b1 == kManyRuns) return g_from_window(((uint64_t)r.y << 32) | r.x, l, (int)(r.w & 0xFFFFu), (int)(r.w >> 16));
+  const int a1 = (int)(int16_t)(r.z & 0xFFFFu), a2 = (int)(int16_t)(r.w & 0xFFFFu), b2 = (int)r.w >> 16;
+  return max(0, max(min(l - a1, b1 - l), min(l - a2, b2 - l)));
+}
+
 // Site m (p < m < q, parabola heights F) never lies strictly below both p and
 // q: q overtakes p no later than m does, i.e. Aq/(q-p) <= Am/(m-p) with
-// A = F - Fp + (site^2 - p^2).  |A| < 2^22 and the row distances < 2^11, so
-// both products are below 2^33 and exact in double precision (FP64 FMA runs
-// at the FP32 rate on gfx950, unlike 64-bit integer products).
+// A = F - Fp + (site^2 - p^2).  |A| < 2^27 (g < 2^14) and the row distances
+// are below 2^11, so both products are below 2^38 and exact in double
+// precision (cheaper on gfx950 than 64-bit integer products).
 __device__ __forceinline__ bool dominated(int p, int Fp, int m, int Fm, int q, int Fq) {
-  const int Am = (Fm - Fp) + (m - p) * (m + p);
-  const int Aq = (Fq - Fp) + (q - p) * (q + p);
+  const int Am = (Fm - Fp) + __mul24(m - p, m + p);
+  const int Aq = (Fq - Fp) + __mul24(q - p, q + p);
   return (double)Aq * (double)(m - p) <= (double)Am * (double)(q - p);
 }
 
-__device__ __forceinline__ int parab(int site, int F, int y) { return (y - site) * (y - site) + F; }
+__device__ __forceinline__ int parab(int site, int F, int y) { return __mul24(y - site, y - site) + F; }
 
 // --- the band's stack bitmap in three registers (rows b0 .. b0+95) ---
 __device__ __forceinline__ void bm_set(uint32_t& w0, uint32_t& w1, uint32_t& w2, int rel) {
@@ -163,28 +200,29 @@ __device__ __forceinline__ int lds_next(const uint32_t* bm, int lane, int pos, i
   }
 }
 
-__device__ __forceinline__ int gsq(const int16_t* g_lds, int row, int lane) {
-  const int v = g_lds[row * 64 + lane];
-  return v * v;
+// g^2 of column `lane` in row `row`, recomputed from the row's record
+__device__ __forceinline__ int gsq(const uint4* rec, int row, int lane, bool lane_ok) {
+  const int g = g_rec(rec[row], lane);
+  return lane_ok ? __mul24(g, g) : 0;
 }
 
 // Merge the envelope of rows [lo, jb) with the envelope of rows [jb, hi).
-__device__ void merge_junction(const int16_t* g_lds, uint32_t* bm, int lane, int lo, int jb, int hi) {
+__device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool lane_ok, int lo, int jb, int hi) {
   int a1 = lds_prev(bm, lane, jb, lo);
   int b1 = lds_next(bm, lane, jb, hi);
   if (a1 < 0 || b1 < 0) return;
   int a2 = lds_prev(bm, lane, a1, lo);
   int b2 = lds_next(bm, lane, b1 + 1, hi);
-  int Fa1 = gsq(g_lds, a1, lane), Fb1 = gsq(g_lds, b1, lane);
-  int Fa2 = a2 >= 0 ? gsq(g_lds, a2, lane) : 0;
-  int Fb2 = b2 >= 0 ? gsq(g_lds, b2, lane) : 0;
+  int Fa1 = gsq(rec, a1, lane, lane_ok), Fb1 = gsq(rec, b1, lane, lane_ok);
+  int Fa2 = a2 >= 0 ? gsq(rec, a2, lane, lane_ok) : 0;
+  int Fb2 = b2 >= 0 ? gsq(rec, b2, lane, lane_ok) : 0;
   for (;;) {
     if (a2 >= 0 && dominated(a2, Fa2, a1, Fa1, b1, Fb1)) {
       bm[(a1 >> 5) * 64 + lane] &= ~(1u << (a1 & 31));
       a1 = a2;
       Fa1 = Fa2;
       a2 = lds_prev(bm, lane, a1, lo);
-      Fa2 = a2 >= 0 ? gsq(g_lds, a2, lane) : 0;
+      Fa2 = a2 >= 0 ? gsq(rec, a2, lane, lane_ok) : 0;
       continue;
     }
     if (b2 >= 0 && dominated(a1, Fa1, b1, Fb1, b2, Fb2)) {
@@ -192,99 +230,119 @@ __device__ void merge_junction(const int16_t* g_lds, uint32_t* bm, int lane, int
       b1 = b2;
       Fb1 = Fb2;
       b2 = lds_next(bm, lane, b1 + 1, hi);
-      Fb2 = b2 >= 0 ? gsq(g_lds, b2, lane) : 0;
+      Fb2 = b2 >= 0 ? gsq(rec, b2, lane, lane_ok) : 0;
       continue;
     }
     break;
   }
 }
 
+// Packets: the items of class c are grouped class_items(c) at a time; the
+// packets of the tallest class come first so that the longest work starts
+// first.  Returns the class of packet p (or -1 past the end) and the item word
+// of wavefront kb's slot in it (or -1 when that slot is empty).
+__device__ __forceinline__ int packet_slot(const int32_t* counts, const int32_t* items, int p, int kb, int& word) {
+  word = -1;
+#pragma unroll
+  for (int c = kClasses - 1; c >= 0; --c) {
+    const int ipp = class_items(c);
+    const int cnt = counts[c];
+    const int np = (cnt + ipp - 1) / ipp;
+    if (p < np) {
+      const int slot = kb / class_waves(c);
+      const int k = p * ipp + slot;
+      if (slot < ipp && k < cnt) word = items[counts[8 + c] + k];
+      return c;
+    }
+    p -= np;
+  }
+  return -1;
+}
+
 template <int SPATIAL>  // 0: EDT, 1: AREA (pixel counts, no transform)
-__global__ __launch_bounds__(768) void k_edt(Batch b, Work wk, int cls, int rows_cap, int32_t* e_out) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  int16_t* g_lds = reinterpret_cast<int16_t*>(smem);
-  uint32_t* bm = reinterpret_cast<uint32_t*>(smem + edt_g_bytes(rows_cap));
-  float* part = reinterpret_cast<float*>(smem + edt_g_bytes(rows_cap) + edt_bm_bytes(rows_cap));
-  __shared__ int item_sh;
+__global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_edt(Batch b, Work wk, int32_t* e_out) {
+  __shared__ uint4 rec_all[kMaxRows];
+  __shared__ uint32_t bm_all[kEdtBmWords * 64];
+  __shared__ float part_all[kEdtWaves * kEdtPartRows * 8];
 
-  // the band index is wave-uniform; make that visible so row loops run on scalars
-  const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), K = blockDim.x >> 6;
-  const int32_t* list = wk.items + (int64_t)cls * b.item_cap;
-  const int count = wk.counts[cls];
-  const int nbm = edt_bm_words(rows_cap);
-  const int npart = edt_part_rows(rows_cap) * 16;
+  // the wavefront index is uniform; make that visible so row loops run on scalars
+  const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int total = 0;
+  for (int c = 0; c < kClasses; ++c) total += (wk.counts[c] + class_items(c) - 1) / class_items(c);
+  float* part = part_all + kb * kEdtPartRows * 8;
 
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) item_sh = atomicAdd(wk.counters + cls, 1);
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(item_sh);
-    if (it >= count) break;
-    const int item = list[it];
-    const int g = item >> kItemStripBits, strip = item & ((1 << kItemStripBits) - 1);
-    const FrameDesc fd = b.frames[b.mask_frame[g]];
-    const int4 bb = wk.bbox[g];
-    const int y0 = bb.x, y1 = bb.y, x0 = bb.z, x1 = bb.w;
-    const int P = fd.patch, SW = strip_width(P);
-    const int xs = (x0 / P) * P + strip * SW;
-    const int n = y1 - y0 + 3;
+  // Packets are taken in a fixed stride (no shared queue).  Each wavefront
+  // prefetches the record of its item in the next packet into one VGPR per
+  // lane (lane j holds dword j) and broadcasts it with readlane.
+  int p = blockIdx.x;
+  if (p >= total) return;
+  int word = -1;
+  int cls = packet_slot(wk.counts, wk.items, p, kb, word);
+  uint32_t pf = 0u;
+  if (word >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(wk.mrec + (word >> kItemStripBits))[lane];
+
+  for (; p < total; p += gridDim.x) {
+    const int K = class_waves(cls), B = class_band(cls), rows_c = class_rows(cls);
+    const int slot = kb / K, j = kb - slot * K;  // item slot in the packet, band in the item
+    const bool has = word >= 0;
+    const int strip = has ? (word & ((1 << kItemStripBits) - 1)) : 0;
+    auto fld = [&](int q) { return (int)__builtin_amdgcn_readlane(pf, q); };
+    const uint64_t* mb = reinterpret_cast<const uint64_t*>(((uint64_t)(uint32_t)fld(1) << 32) | (uint32_t)fld(0));
+    float* srow = reinterpret_cast<float*>(((uint64_t)(uint32_t)fld(3) << 32) | (uint32_t)fld(2));
+    const int y0 = fld(4), y1 = fld(5), x0 = fld(6), x1 = fld(7);
+    const int n = has ? fld(8) : 0;
+    const int P = has ? fld(9) : kMinPatch;
+    const int gw = fld(10), wq = fld(11), fw = fld(12), fh = fld(13), xs0 = fld(14), gidx = fld(15);
+    const int SW = strip_width(P);
+    const int xs = xs0 + strip * SW;
     const bool lane_ok = lane < SW;
     const int col = xs + lane;
-    const int wq = fd.wq, fw = fd.w;
-    const uint64_t* mb = fd.bits + (int64_t)(g - fd.mask_base) * fd.h * wq;
+    // this item's rows and bitmap words in LDS (rows_c is a multiple of 32)
+    uint4* rec = rec_all + slot * rows_c;
+    uint32_t* bm = bm_all + (slot * rows_c / 32) * 64;
 
-    for (int i = threadIdx.x; i < nbm * 64; i += blockDim.x) bm[i] = 0u;
-    for (int i = threadIdx.x; i < npart; i += blockDim.x) part[i] = 0.f;
-    __syncthreads();
+    const int b0 = j * B, b1 = min(b0 + B, n);
 
-    const int b0 = kb * kBand, b1 = min(b0 + kBand, n);
-
-    // ---- row pass, part 1: lane l fetches the strip window of rows b0 + l and
-    // b0 + 64 + l, plus the run lengths that continue past the window's ends
-    // (only needed when the edge pixel is inside the mask).  All rows of the
-    // band are fetched in parallel; the sequential part reads them back with
-    // readlane.
-    uint32_t wlo0 = 0, whi0 = 0, wlo1 = 0, whi1 = 0;
-    int L0 = 0, R0 = 0, L1 = 0, R1 = 0;
+    // ---- row records: lane l reads rows b0 + l (and b0 + 64 + l) of its band:
+    // the strip's 64-bit window and the run lengths past the window's ends
+    // (only read when the edge pixel is inside the mask).
 #pragma unroll
     for (int rr = 0; rr < 2; ++rr) {
       const int u = b0 + lane + 64 * rr;
-      if (u < b1 && u > 0 && u < n - 1) {
-        const uint64_t* row = mb + (int64_t)(y0 - 1 + u) * wq;
-        const uint64_t win = load_window(row, xs, wq, fw);
-        const int L = (win & 1ull) ? run_left(row, xs - 1, wq, fw) : 0;
-        const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw) : 0;
-        if (rr == 0) {
-          wlo0 = (uint32_t)win; whi0 = (uint32_t)(win >> 32); L0 = L; R0 = R;
-        } else {
-          wlo1 = (uint32_t)win; whi1 = (uint32_t)(win >> 32); L1 = L; R1 = R;
+      if (lane + 64 * rr < B && u < b1) {
+        uint4 r = make_uint4(0u, 0u, 0u, 0u);  // padding row: no runs
+        if (u > 0 && u < n - 1) {
+          const uint64_t* row = mb + (int64_t)(y0 - 1 + u) * wq;
+          const uint64_t win = load_window(row, xs, wq, fw);
+          const int L = (win & 1ull) ? run_left(row, xs - 1, wq, fw) : 0;
+          const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw) : 0;
+          r = make_rowrec(win, L, R);
         }
+        rec[u] = r;
       }
     }
+    __syncthreads();
+    // prefetch the record of this wavefront's item in the next packet
+    int ncls = -1, nword = -1;
+    if (p + (int)gridDim.x < total) {
+      ncls = packet_slot(wk.counts, wk.items, p + gridDim.x, kb, nword);
+      if (nword >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(wk.mrec + (nword >> kItemStripBits))[lane];
+    }
 
-    // ---- row pass, part 2 + this band's lower envelope (sequential in u) ----
-    uint32_t w0 = 0, w1 = 0, w2 = 0;
-    int cnt = 0, s1 = 0, s2 = 0, F1 = 0, F2 = 0;
-    for (int u = b0; u < b1; ++u) {
-      const int src = (u - b0) & 63;
-      const bool hi = (u - b0) >= 64;
-      const uint32_t lo32 = __builtin_amdgcn_readlane(hi ? wlo1 : wlo0, src);
-      const uint32_t hi32 = __builtin_amdgcn_readlane(hi ? whi1 : whi0, src);
-      const int L = __builtin_amdgcn_readlane(hi ? L1 : L0, src);
-      const int R = __builtin_amdgcn_readlane(hi ? R1 : R0, src);
-      const uint64_t win = ((uint64_t)hi32 << 32) | lo32;
-      const int gv = lane_ok ? g_from_window(win, lane, L, R) : 0;
-      g_lds[u * 64 + lane] = (int16_t)gv;
-      if (SPATIAL == 0) {
-        const int Fu = gv * gv;
-        while (cnt >= 2 && dominated(s2, F2, s1, F1, u, Fu)) {
+    // ---- this band's lower envelope (sequential in u) ----
+    if (SPATIAL == 0 && b0 < n) {
+      uint32_t w0 = 0, w1 = 0, w2 = 0;
+      int depth = 0, s1 = 0, s2 = 0, F1 = 0, F2 = 0;
+      for (int u = b0; u < b1; ++u) {
+        const int Fu = gsq(rec, u, lane, lane_ok);
+        while (depth >= 2 && dominated(s2, F2, s1, F1, u, Fu)) {
           bm_clear(w0, w1, w2, s1 - b0);
-          --cnt;
+          --depth;
           s1 = s2;
           F1 = F2;
-          if (cnt >= 2) {
+          if (depth >= 2) {
             s2 = b0 + bm_prev(w0, w1, w2, s1 - b0);
-            F2 = gsq(g_lds, s2, lane);
+            F2 = gsq(rec, s2, lane, lane_ok);
           }
         }
         bm_set(w0, w1, w2, u - b0);
@@ -292,49 +350,49 @@ __global__ __launch_bounds__(768) void k_edt(Batch b, Work wk, int cls, int rows
         F2 = F1;
         s1 = u;
         F1 = Fu;
-        ++cnt;
+        ++depth;
       }
-    }
-    if (SPATIAL == 0 && b0 < n) {
       const int wb = b0 >> 5;
       bm[wb * 64 + lane] = w0;
-      if (wb + 1 < nbm) bm[(wb + 1) * 64 + lane] = w1;
-      if (wb + 2 < nbm) bm[(wb + 2) * 64 + lane] = w2;
+      if (B > 32) {
+        bm[(wb + 1) * 64 + lane] = w1;
+        bm[(wb + 2) * 64 + lane] = w2;
+      }
     }
     __syncthreads();
 
     // ---- merge band envelopes pairwise ----
     if (SPATIAL == 0) {
       for (int step = 1; step < K; step <<= 1) {
-        if ((kb % (2 * step)) == 0 && kb + step < K) {
-          const int jb = (kb + step) * kBand;
-          if (jb < n) merge_junction(g_lds, bm, lane, kb * kBand, jb, min((kb + 2 * step) * kBand, n));
+        if ((j % (2 * step)) == 0 && j + step < K) {
+          const int jb = (j + step) * B;
+          if (jb < n) merge_junction(rec, bm, lane, lane_ok, j * B, jb, min((j + 2 * step) * B, n));
         }
         __syncthreads();
       }
     }
 
     // ---- final walk: e over the band's rows, sqrt(e) summed per patch ----
-    const int prbase = y0 / P;
+    const int pfirst = (y0 - 1 + max(b0, 1)) / P;  // first patch row this band meets
     float acc = 0.f;
     int cur_pr = -1;
     int c = 0, Fc = 0, nx = -1, Fn = 0;
     if (SPATIAL == 0 && b0 < n) {
       c = lds_prev(bm, lane, b0 + 1, 0);
-      Fc = gsq(g_lds, c, lane);
+      Fc = gsq(rec, c, lane, lane_ok);
       for (;;) {
-        const int p = lds_prev(bm, lane, c, 0);
-        if (p < 0) break;
-        const int Fp = gsq(g_lds, p, lane);
-        if (parab(p, Fp, b0) <= parab(c, Fc, b0)) {
-          c = p;
-          Fc = Fp;
+        const int q = lds_prev(bm, lane, c, 0);
+        if (q < 0) break;
+        const int Fq = gsq(rec, q, lane, lane_ok);
+        if (parab(q, Fq, b0) <= parab(c, Fc, b0)) {
+          c = q;
+          Fc = Fq;
         } else {
           break;
         }
       }
       nx = lds_next(bm, lane, c + 1, n);
-      Fn = nx >= 0 ? gsq(g_lds, nx, lane) : 0;
+      Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok) : 0;
     }
     auto flush = [&](int pr, float v) {
       v = lane_ok ? v : 0.f;
@@ -343,13 +401,7 @@ __global__ __launch_bounds__(768) void k_edt(Batch b, Work wk, int cls, int rows
         const float t = __shfl_down(v, o);
         if (inseg + o < P && lane + o < 64) v += t;
       }
-      if (inseg == 0 && lane_ok) {
-        const int q = lane / P;
-        const int first_row = max(pr * P, y0);
-        const int band_first = max(y0 - 1 + b0, y0);
-        const int slot = band_first <= first_row ? 0 : 1;
-        part[((pr - prbase) * 8 + q) * 2 + slot] = v;
-      }
+      if (inseg == 0 && lane_ok) part[(pr - pfirst) * 8 + lane / P] = v;
     };
     for (int u = b0; u < b1; ++u) {
       int e;
@@ -358,11 +410,11 @@ __global__ __launch_bounds__(768) void k_edt(Batch b, Work wk, int cls, int rows
           c = nx;
           Fc = Fn;
           nx = lds_next(bm, lane, c + 1, n);
-          Fn = nx >= 0 ? gsq(g_lds, nx, lane) : 0;
+          Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok) : 0;
         }
-        e = (u - c) * (u - c) + Fc;
+        e = __mul24(u - c, u - c) + Fc;
       } else {
-        e = g_lds[u * 64 + lane] > 0 ? 1 : 0;
+        e = gsq(rec, u, lane, lane_ok) > 0 ? 1 : 0;
       }
       if (u >= 1 && u <= n - 2) {
         const int Y = y0 - 1 + u;
@@ -374,58 +426,63 @@ __global__ __launch_bounds__(768) void k_edt(Batch b, Work wk, int cls, int rows
         }
         acc += SPATIAL == 0 ? __builtin_amdgcn_sqrtf((float)e) : (float)e;  // e >= 0 integer: no denormals
         if (e_out != nullptr && lane_ok && col >= x0 && col <= x1)
-          e_out[(int64_t)g * fd.h * fw + (int64_t)Y * fw + col] = e;
+          e_out[(int64_t)gidx * fh * fw + (int64_t)Y * fw + col] = e;
       }
     }
     if (cur_pr >= 0) flush(cur_pr, acc);
     __syncthreads();
 
-    // ---- write the strip's patch sums ----
-    const int npc = SW / P;
-    const int npr = y1 / P - prbase + 1;
-    const int pc0 = xs / P;
-    float* srow = wk.s + fd.w_base + (int64_t)(g - fd.mask_base) * fd.Gs;
-    for (int idx = threadIdx.x; idx < npr * npc; idx += blockDim.x) {
-      const int prl = idx / npc, q = idx - prl * npc;
-      const int pc = pc0 + q;
-      if (pc < fd.gw) srow[(prbase + prl) * fd.gw + pc] = part[(prl * 8 + q) * 2] + part[(prl * 8 + q) * 2 + 1];
+    // ---- the strip's patch sums: each patch row adds the partial sums of the
+    // bands that meet it, in band order ----
+    if (has) {
+      const int npc = SW / P;
+      const int prbase = y0 / P;
+      const int npr = y1 / P - prbase + 1;
+      const int pc0 = xs / P;
+      for (int idx = j * 64 + lane; idx < npr * npc; idx += K * 64) {
+        const int prl = idx / npc, q = idx - prl * npc;
+        const int pc = pc0 + q;
+        const int pr = prbase + prl;
+        const int ua = max(pr * P, y0) - y0 + 1, ub = min(pr * P + P - 1, y1) - y0 + 1;
+        float v = 0.f;
+        for (int jj = ua / B; jj <= ub / B; ++jj) {
+          const int pf_j = (y0 - 1 + max(jj * B, 1)) / P;
+          v += part_all[((slot * K + jj) * kEdtPartRows + (pr - pf_j)) * 8 + q];
+        }
+        if (pc < gw) srow[pr * gw + pc] = v;
+      }
     }
+    __syncthreads();
+    cls = ncls;
+    word = nword;
   }
 }
 
-// Per-class LDS attribute and resident workgroups per CU, computed once
-// (outside any stream capture).
+// Resident workgroups per CU of each variant, computed once (outside any
+// stream capture).
 static std::once_flag g_edt_once;
-static int g_edt_per_cu[2][kClasses];
+static int g_edt_per_cu[2];
 
 void edt_prepare() {
   std::call_once(g_edt_once, [] {
-    for (int sp = 0; sp < 2; ++sp)
-      for (int c = 0; c < kClasses; ++c) {
-        const int threads = 64 * class_bands(c);
-        const size_t lds = (size_t)edt_lds_bytes(class_rows(c));
-        const void* fn = sp == 0 ? reinterpret_cast<const void*>(&k_edt<0>) : reinterpret_cast<const void*>(&k_edt<1>);
-        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
-        g_edt_per_cu[sp][c] = per_cu;
-      }
+    for (int sp = 0; sp < 2; ++sp) {
+      const void* fn = sp == 0 ? reinterpret_cast<const void*>(&k_edt<0>) : reinterpret_cast<const void*>(&k_edt<1>);
+      int per_cu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kEdtWaves * 64, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+      g_edt_per_cu[sp] = per_cu;
+    }
   });
 }
 
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st) {
   edt_prepare();
   const int sp = b.spatial == 0 ? 0 : 1;
-  for (int c = 0; c < kClasses; ++c) {
-    const int threads = 64 * class_bands(c);
-    const int rows = class_rows(c);
-    const size_t lds = (size_t)edt_lds_bytes(rows);
-    const int grid = num_cus * g_edt_per_cu[sp][c];
-    if (sp == 0)
-      hipLaunchKernelGGL(k_edt<0>, dim3(grid), dim3(threads), lds, st, b, w, c, rows, e_out);
-    else
-      hipLaunchKernelGGL(k_edt<1>, dim3(grid), dim3(threads), lds, st, b, w, c, rows, e_out);
-  }
+  const int grid = num_cus * g_edt_per_cu[sp];
+  if (sp == 0)
+    hipLaunchKernelGGL(k_edt<0>, dim3(grid), dim3(kEdtWaves * 64), 0, st, b, w, e_out);
+  else
+    hipLaunchKernelGGL(k_edt<1>, dim3(grid), dim3(kEdtWaves * 64), 0, st, b, w, e_out);
 }
 
 }  // namespace disc

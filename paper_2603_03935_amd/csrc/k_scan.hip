@@ -89,6 +89,22 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
         }
       meta = (cls << 16) | strips;  // cls == kClasses would mean "too tall": rejected on the host
       wk.bbox[g] = make_int4(ymin, ymax, xmin, xmax);
+      MaskRec r;
+      r.bits = mb;
+      r.srow = wk.s + fd.w_base + (int64_t)(g - fd.mask_base) * fd.Gs;
+      r.y0 = ymin;
+      r.y1 = ymax;
+      r.x0 = xmin;
+      r.x1 = xmax;
+      r.n = n;
+      r.patch = P;
+      r.gw = fd.gw;
+      r.wq = wq;
+      r.w = fd.w;
+      r.h = h;
+      r.xs0 = xs0;
+      r.g = g;
+      wk.mrec[g] = r;
     } else {
       wk.bbox[g] = make_int4(1, 0, 1, 0);
     }
@@ -102,16 +118,45 @@ void launch_scan(const Batch& b, const Work& w, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// k_plan: one workgroup turns the per-mask strip counts into one work list per
-// class (mask-major, strip-minor) and resets the dynamic work counters.
+// k_plan: one workgroup turns the per-mask strip counts into the distance-
+// transform work list: one word (mask << 8) | strip per item, classes back to
+// back (mask-major, strip-minor within a class).
+// counts[c] = items of class c, counts[8 + c] = first item of class c.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_plan(Batch b, Work wk) {
   __shared__ int wsum[16];
   __shared__ int base_sh;
+  __shared__ int red[16][kClasses];
+  __shared__ int cls_base[kClasses + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int M = b.dyn[1];
+  // pass 1: items per class
+  int loc[kClasses];
+  for (int c = 0; c < kClasses; ++c) loc[c] = 0;
+  for (int g = tid; g < M; g += 1024) {
+    const int meta = wk.meta[g];
+    if (meta >= 0 && (meta >> 16) < kClasses) loc[meta >> 16] += meta & 0xFFFF;
+  }
   for (int c = 0; c < kClasses; ++c) {
-    if (tid == 0) base_sh = 0;
+    int v = loc[c];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wv][c] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int c = 0; c < kClasses; ++c) {
+      int t = 0;
+      for (int i = 0; i < 16; ++i) t += red[i][c];
+      cls_base[c] = min(acc, b.item_cap);
+      acc += t;
+    }
+    cls_base[kClasses] = min(acc, b.item_cap);
+  }
+  __syncthreads();
+  // pass 2: write the items of each class
+  for (int c = 0; c < kClasses; ++c) {
+    if (tid == 0) base_sh = cls_base[c];
     __syncthreads();
     for (int g0 = 0; g0 < M; g0 += 1024) {
       const int g = g0 + tid;
@@ -120,10 +165,9 @@ __global__ __launch_bounds__(1024) void k_plan(Batch b, Work wk) {
         const int meta = wk.meta[g];
         if (meta >= 0 && (meta >> 16) == c) cnt = meta & 0xFFFF;
       }
-      // inclusive scan within the wave
       int incl = cnt;
       for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(incl, o);
+        const int t = __shfl_up(incl, o);
         if (lane >= o) incl += t;
       }
       if (lane == 63) wsum[wv] = incl;
@@ -131,9 +175,10 @@ __global__ __launch_bounds__(1024) void k_plan(Batch b, Work wk) {
       int before = base_sh;
       for (int i = 0; i < wv; ++i) before += wsum[i];
       const int off = before + incl - cnt;
-      int32_t* list = wk.items + (int64_t)c * b.item_cap;
-      for (int j = 0; j < cnt; ++j)
-        if (off + j < b.item_cap) list[off + j] = (g << kItemStripBits) | j;
+      for (int j = 0; j < cnt; ++j) {
+        if (off + j >= cls_base[c + 1]) break;
+        wk.items[off + j] = (g << kItemStripBits) | j;
+      }
       __syncthreads();
       if (tid == 0) {
         int tot = 0;
@@ -143,8 +188,8 @@ __global__ __launch_bounds__(1024) void k_plan(Batch b, Work wk) {
       __syncthreads();
     }
     if (tid == 0) {
-      wk.counts[c] = min(base_sh, b.item_cap);
-      wk.counters[c] = 0;
+      wk.counts[c] = cls_base[c + 1] - cls_base[c];
+      wk.counts[8 + c] = cls_base[c];
     }
     __syncthreads();
   }

@@ -61,8 +61,8 @@ def adversarial_masks(h, w, rng):
     return np.stack(u)
 
 
-@pytest.mark.parametrize("h,w", [(37, 100), (96, 130), (94, 64), (190, 63), (191, 200), (382, 129), (383, 70),
-                                 (766, 65), (767, 90), (1118, 77), (5, 1500)])
+@pytest.mark.parametrize("h,w", [(30, 100), (31, 130), (62, 64), (63, 63), (126, 200), (127, 129), (254, 70),
+                                 (255, 65), (510, 90), (511, 77), (1150, 77), (5, 1500)])
 def test_edt_adversarial(gpu, h, w):
     """Ragged widths, 1-px structures, full frames and every band-count class."""
     rng = np.random.default_rng(h * 1000 + w)
