@@ -2,25 +2,34 @@
 """Benchmark of DISC's single-pass, distance-weighted mask feature extraction
 (arXiv 2603.03935, Sec. III-C) on one MI355X.
 
-A step is one pass of the whole hot path -- bounding-box scan, exact EDT and
-per-patch weights, token statistics (Eq. 1), weight finalisation, pooling GEMM,
-projection GEMM with L2 normalisation -- over one batch of synthetic input
-already resident in HBM.  The default workload is the plain-FP32 single frame
-(480x640, 30x40x1024 tokens, 128 masks, projection 1024x768): one call of
-disc_embed_masks per step.  ``--config cfg3`` / ``cfg5`` run the batched BF16 /
-FP8 workloads (one disc_embed_frames call per step).
+A step is one pass of the whole hot path -- bounding-box scan, work plan,
+exact EDT fused with the per-patch sqrt(EDT) sums, token statistics (Eq. 1),
+weight finalisation, pooling GEMM, projection GEMM with L2 normalisation --
+over one batch of synthetic input already resident in HBM.
 
-Prints ONE JSON line.  ``value`` is mask embeddings per second; ``roofline``
-reports the dominant stage's achieved algorithmic rate (from HIP events
-recorded around each stage on the launch stream) against the MI355X peak;
-``cpu_baseline`` times the FP64 CPU oracle on a bounded sample.
+Default workload: the plain-FP32 single frame (480x640, 30x40x1024 tokens with
+16-px patches, 128 instance masks, projection 1024x768), one disc_embed_frames
+call per step.  ``--config cfg3`` / ``cfg5`` run the batched BF16 / large FP8
+workloads instead.
+
+Beside the plain path the default run also drives the serving loop with BF16
+operands (16 camera streams, Poisson 30 frames/s each, 480x640 and 720x1280
+frames with Poisson(80) masks; continuous batching with graph replay) and
+reports its latency at that offered load and its saturated throughput.
+
+Prints ONE JSON line.  ``value`` is mask embeddings per second of the plain
+path; ``roofline`` reports the dominant kernel's achieved algorithmic rate
+(stage durations from HIP events recorded on the launch stream) against the
+MI355X peak; ``cpu_baseline`` times the FP64 CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -28,18 +37,30 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# MI355X published peaks (dense).  ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# 32-bit integer VALU operations per second.
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f8": 5000.0}
+PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic integer operations of the exact separable EDT per pixel of the
+# region it must transform (bounding box plus a one-pixel ring): row pass 4
+# (two sweeps, an increment and a select each), g^2 1, lower-envelope
+# construction 6 (each row pushed once and popped at most once, a 3-op
+# intersection test per push and per pop), envelope walk 4 (one comparison of
+# two parabolas per row), e 2, sqrt and patch sum 3.
+EDT_OPS_PER_PIXEL = 20
 CONFIG_DESC = {
     "cfg1": "plain FP32, one 336x336 frame, 8 ellipse masks, tokens 24x24x1024 (14-px patches), proj 1024x768",
     "cfg2": "plain FP32, one 480x640 frame, 128 instance masks, tokens 30x40x1024 (16-px patches), proj 1024x768",
     "cfg3": "batched BF16, 64 frames 480x640, Poisson(60) masks/frame, tokens 30x40x1024, proj 1024x768",
     "cfg5": "large FP8, 16 frames 1080x1920, 500 masks/frame, tokens 68x120x1280 e4m3fn+scale, proj 1280x1024 BF16",
 }
+KERNEL_SOURCES = {"scan": "k_scan.hip", "plan": "k_scan.hip", "edt": "k_edt.hip", "token_stats": "k_stats.hip",
+                  "weights": "k_stats.hip", "pool": "k_gemm.hip", "proj": "k_gemm.hip"}
 
 
 def parse():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
@@ -47,40 +68,212 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-baseline time budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true", help="skip per-stage event timing")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="offered-load duration of the served leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served BF16 leg")
     return ap.parse_args()
 
 
-def workload_stats(wl):
-    """Algorithmic work of one step, per stage."""
+# ---------------------------------------------------------------- algorithmic work
+
+def _bbox(bits: np.ndarray):
+    """Per mask (y0, y1, x0, x1) from packed bits, or None when empty."""
+    rows = bits.any(axis=2)
+    cols = np.bitwise_or.reduce(bits, axis=1)
+    out = []
+    for i in range(bits.shape[0]):
+        ys = np.flatnonzero(rows[i])
+        if ys.size == 0:
+            out.append(None)
+            continue
+        ks = np.flatnonzero(cols[i])
+        lo, hi = int(cols[i][ks[0]]), int(cols[i][ks[-1]])
+        x0 = 64 * int(ks[0]) + ((lo & -lo).bit_length() - 1)
+        x1 = 64 * int(ks[-1]) + hi.bit_length() - 1
+        out.append((int(ys[0]), int(ys[-1]), x0, x1))
+    return out
+
+
+def _touched_patches(bits: np.ndarray, h: int, w: int, P: int) -> int:
+    """Number of (mask, patch) pairs with at least one mask pixel."""
+    m, _, wq = bits.shape
+    gh, gw = -(-h // P), -(-w // P)
+    pad = np.zeros((m, gh * P, wq), dtype=np.uint64)
+    pad[:, :h] = bits
+    rowor = np.bitwise_or.reduce(pad.reshape(m, gh, P, wq), axis=2)
+    u = np.unpackbits(rowor.view(np.uint8), axis=2, bitorder="little")[:, :, :gw * P]
+    return int(u.reshape(m, gh, gw, P).any(axis=3).sum())
+
+
+def workload_units(wl, gemm_bf16: bool):
+    """Algorithmic work of one step per stage: (bound, amount, unit)."""
     M = wl.total_masks
-    bits_bytes = sum(f.bits.nbytes for f in wl.frames)
-    tok_bytes = sum(f.tokens.data.nbytes + (f.tokens.scale.nbytes if f.tokens.scale is not None else 0)
-                    for f in wl.frames)
     C = wl.frames[0].tokens.c
     E = wl.proj.shape[1]
-    return {"M": M, "bits_bytes": bits_bytes, "tok_bytes": tok_bytes, "C": C, "E": E}
+    bits_bytes = sum(f.bits.nbytes for f in wl.frames)
+    tok_bytes = 0
+    r_bytes = 0
+    tkp_bytes = 0
+    w_bytes = 0
+    edt_px = 0
+    nnz = 0
+    for f in wl.frames:
+        t = f.tokens
+        G = t.gh * t.gw
+        tok_bytes += t.data.nbytes + (t.scale.nbytes if t.scale is not None else 0)
+        r_bytes += 4 * G
+        if gemm_bf16:
+            tkp_bytes += G * C * (1 if t.dtype == "f8" else 2)
+        w_bytes += f.m * G * (2 if gemm_bf16 else 4)
+        for bb in _bbox(f.bits):
+            if bb is not None:
+                edt_px += (bb[1] - bb[0] + 3) * (bb[3] - bb[2] + 3)
+        nnz += _touched_patches(f.bits, f.h, f.w, t.patch)
+    gdt = "bf16" if gemm_bf16 else "f32"
+    return {
+        "scan": ("hbm", bits_bytes, "B"),
+        "plan": ("hbm", 4 * M, "B"),
+        "edt": ("alu", EDT_OPS_PER_PIXEL * edt_px, "op"),
+        "token_stats": ("hbm", tok_bytes + r_bytes + tkp_bytes, "B"),
+        "weights": ("hbm", w_bytes, "B"),
+        "pool": ("mfma:" + gdt, 2.0 * nnz * C, "flop"),
+        "proj": ("mfma:" + gdt, 2.0 * M * C * E, "flop"),
+    }, {"masks": M, "edt_pixels": edt_px, "touched_patches": nnz}
 
+
+def _source_sha(stage: str) -> str:
+    p = os.path.join(ROOT, "paper_2603_03935_amd", "csrc", KERNEL_SOURCES[stage])
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(stage: str, workload: str):
+    """HBM bytes per launch from the committed counter runs, if they were taken
+    on the current source of the kernel (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        tab = json.load(f)
+    ent = tab.get(f"{stage}/{workload}")
+    if not ent or ent.get("source_sha") != _source_sha(stage):
+        return None
+    return ent["hbm_bytes_per_launch"]
+
+
+def roofline(stage: str, avg_ms: float, units, workload: str):
+    bound, amount, _ = units[stage]
+    t = avg_ms / 1000.0
+    if bound == "hbm":
+        r = {"bound": "hbm", "achieved": amount / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    elif bound == "alu":
+        r = {"bound": "alu", "achieved": amount / t / 1e12, "peak": PEAK_ALU_TOPS, "unit": "Tops/s"}
+    else:
+        dt = bound.split(":")[1]
+        r = {"bound": "mfma", "achieved": amount / t / 1e12, "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = _traffic(stage, workload)
+    r["kernel"] = stage
+    r["avg_ms"] = avg_ms
+    r["algorithmic_per_launch"] = amount
+    return r
+
+
+# ---------------------------------------------------------------- served leg
+
+def served_leg(disc, di, dev, seconds: float):
+    """Serving loop, BF16 operands: 16 streams at Poisson 30 frames/s each,
+    streams 0-7 480x640 frames, 8-15 720x1280, Poisson(80) masks.  Reports the
+    latency at that offered load (arrival -> completion, measured by the
+    server) and the throughput when the same frames are submitted at once."""
+    import torch
+
+    wl = di.workload("cfg4")
+    proj = dev.dev_proj(wl.proj, "bf16")
+    ins = []
+    for f in wl.frames:
+        data, scale = dev.dev_tokens(f.tokens)
+        ins.append(disc.FrameInput(data, dev.dev_bits(f.bits), f.h, f.w, f.tokens.patch, scale))
+    outs = [disc.alloc_outputs([x], wl.proj.shape[1])[0] for x in ins]
+    torch.cuda.synchronize()
+    cfg = dict(proj=proj, tok_dtype=disc.DISC_BF16, c=1024, e=wl.proj.shape[1], max_frames=8, max_masks=2400,
+               max_h=720, max_w=1280, min_patch=16, lanes=2, use_graph=True, mem_budget=16 << 30)
+    res = {}
+    # offered load: per-stream exponential gaps, merged into one arrival list
+    arrivals = []
+    for s in range(16):
+        gaps = di.exponential_gaps(di.frame_seed(4, 990), s, int(seconds * 30 * 2) + 8, 1.0 / 30.0)
+        t = np.cumsum(gaps)
+        for k, tt in enumerate(t[t < seconds]):
+            # stream s carries the frames of its resolution (s < 8: 480x640)
+            idx = (s % 8) + (8 if s >= 8 else 0) + 16 * (k % 2)
+            arrivals.append((float(tt), idx % len(ins)))
+    arrivals.sort()
+    with disc.Server(**cfg) as srv:
+        for x, o in zip(ins[:4], outs[:4]):  # warm-up: capture graphs, fill caches
+            srv.wait(srv.submit_frame(x, o)[0])
+        srv_stats0 = srv.stats()
+        t0 = time.perf_counter()
+        tickets = []
+        for ta, idx in arrivals:
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            tickets.append(srv.submit_frame(ins[idx], outs[idx])[0])
+        for t in tickets:
+            if srv.wait(t) != 0:
+                raise RuntimeError("served frame failed")
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    masks = sum(ins[i].m for _, i in arrivals)
+    res["offered"] = {"streams": 16, "fps_per_stream": 30, "frames": len(arrivals), "masks": masks,
+                      "seconds": wall, "masks_per_s": masks / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                      "max_ms": st["max_ms"], "batches": st["batches"] - srv_stats0["batches"],
+                      "mean_batch_frames": st["mean_batch_frames"]}
+    # saturated: every frame of the mix submitted back to back, several rounds
+    with disc.Server(**cfg) as srv:
+        for x, o in zip(ins[:4], outs[:4]):
+            srv.wait(srv.submit_frame(x, o)[0])
+        rounds = 8
+        t0 = time.perf_counter()
+        tickets = [srv.submit_frame(ins[i], outs[i])[0] for _ in range(rounds) for i in range(len(ins))]
+        for t in tickets:
+            if srv.wait(t) != 0:
+                raise RuntimeError("served frame failed")
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    masks = rounds * sum(x.m for x in ins)
+    res["saturated"] = {"frames": rounds * len(ins), "masks": masks, "seconds": wall, "masks_per_s": masks / wall,
+                        "frames_per_s": rounds * len(ins) / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                        "mean_batch_frames": st["mean_batch_frames"]}
+    return res
+
+
+# ---------------------------------------------------------------- main
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the path shards by frames with no exchange; see DESIGN.md)"}))
+                                   "(the path shards by frames with no exchange between GPUs)"}))
         sys.exit(2)
     import torch
 
     import disc_inputs as di
+    import disc_inputs.device as dev
     import paper_2603_03935_amd as disc
-    from tests.gpu_common import dev_proj, frame_input
 
     disc.load()
     wl = di.workload(args.config)
-    ins = [frame_input(f) for f in wl.frames]
-    proj = dev_proj(wl.proj, wl.proj_dtype)
+    ins = []
+    for f in wl.frames:
+        data, scale = dev.dev_tokens(f.tokens)
+        ins.append(disc.FrameInput(data, dev.dev_bits(f.bits), f.h, f.w, f.tokens.patch, scale))
+    proj = dev.dev_proj(wl.proj, wl.proj_dtype)
     outs = disc.alloc_outputs(ins, wl.proj.shape[1])
     opts = disc.make_options()
     stream = torch.cuda.current_stream()
-    st = workload_stats(wl)
+    gemm_bf16 = not (wl.proj_dtype == "f32" and wl.frames[0].tokens.dtype == "f32")
+    units, totals = workload_units(wl, gemm_bf16)
 
     def step():
         disc.embed_frames(ins, proj, outputs=outs, options=opts, stream=stream)
@@ -109,52 +302,29 @@ def main():
         stages = disc.trace_read()
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     ms_per_step = wall * 1000.0 / args.steps
-    value = st["M"] / (ms_per_step / 1000.0)
+    value = totals["masks"] / (ms_per_step / 1000.0)
 
-    # roofline of the dominant stage
     avg = {k: (ms / n if n else 0.0) for k, (ms, n) in stages.items()}
     roof = None
     if avg:
         dom = max(avg, key=avg.get)
-        t = avg[dom] / 1000.0
-        gemm_dt = "f32" if wl.proj_dtype == "f32" and wl.frames[0].tokens.dtype == "f32" else "bf16"
-        if dom in ("pool", "proj"):
-            nnz = None
-            flops = 2.0 * st["M"] * st["C"] * st["E"] if dom == "proj" else None
-            if dom == "pool":
-                # algorithmic: every non-zero weight times a token row
-                nnz = 0
-                import oracle  # noqa: F401  (weights support from the masks only)
-                for f in wl.frames:
-                    u = di.unpack_masks(f.bits, f.w)
-                    P = f.tokens.patch
-                    gh, gw = f.tokens.gh, f.tokens.gw
-                    pad = np.zeros((u.shape[0], gh * P, gw * P), dtype=np.uint8)
-                    pad[:, :f.h, :f.w] = u
-                    nnz += int((pad.reshape(u.shape[0], gh, P, gw, P).max(axis=(2, 4)) > 0).sum())
-                flops = 2.0 * nnz * st["C"]
-            roof = {"bound": "mfma", "stage": dom, "achieved": flops / t / 1e12, "peak": PEAK_TFLOPS[gemm_dt],
-                    "unit": "TFLOP/s", "traffic": None}
-        else:
-            nbytes = {"scan": st["bits_bytes"], "token_stats": st["tok_bytes"], "edt": st["bits_bytes"],
-                      "weights": st["M"] * 8, "plan": st["M"] * 4}[dom]
-            roof = {"bound": "hbm", "stage": dom, "achieved": nbytes / t / 1e9, "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "traffic": None}
-        roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["avg_ms"] = avg[dom]
+        roof = roofline(dom, avg[dom], units, args.config)
+
+    served = None
+    if not args.no_serve and args.config == "cfg2":
+        served = served_leg(disc, di, dev, args.serve_seconds)
 
     # CPU baseline: the FP64 oracle as it stands, one core, bounded sample
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
         from tests.gpu_common import oracle_frame
 
         fr = wl.frames[0]
+        n = min(fr.m, 16)
         t0 = time.perf_counter()
         done = 0
         reps = 0
         while True:
-            n = min(fr.m, 16)
             oracle_frame(fr, wl.proj, wl.proj_dtype, idx=list(range(n)))
             done += n
             reps += 1
@@ -162,8 +332,8 @@ def main():
                 break
         el = time.perf_counter() - t0
         cpu = {"value": done / el, "unit": "mask embeddings/s", "cores": 1, "kind": "oracle",
-               "sample": f"{done} masks of {args.config} frame 0 ({reps} runs of the first {min(fr.m, 16)} masks, "
-                         f"full-frame FP64 EDT each), {el:.1f} s, host {os.cpu_count()} cpus visible"}
+               "sample": f"{done} masks of {args.config} frame 0 ({reps} runs over its first {n} masks: token "
+                         f"statistics, full-frame FP64 EDT, pooling, projection), {el:.1f} s on one host thread"}
 
     res = {
         "metric": "mask embeddings/sec and p99 frame latency, BF16 served vs FP32 plain, 1 MI355X",
@@ -176,13 +346,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if wl.proj_dtype == "f32" else ("f8+bf16" if wl.frames[0].tokens.dtype == "f8" else "bf16"),
+        "dtype": "f32" if not gemm_bf16 else ("f8+bf16" if wl.frames[0].tokens.dtype == "f8" else "bf16"),
         "data": "synthetic",
         "config": {"workload": args.config, "desc": CONFIG_DESC[args.config], "frames": len(wl.frames),
-                   "masks_per_step": st["M"], "p50_ms": float(np.percentile(lat, 50)),
-                   "p99_ms": float(np.percentile(lat, 99)), "stage_avg_ms": avg},
+                   "masks_per_step": totals["masks"], "frames_per_s": len(wl.frames) / (ms_per_step / 1000.0),
+                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "stage_avg_ms": avg, "edt_pixels": totals["edt_pixels"],
+                   "touched_patches": totals["touched_patches"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "served_bf16": served,
     }
     print(json.dumps(res))
 

@@ -233,6 +233,10 @@ class FrameInput:
     patch: int
     scale: object = None  # float32 [gh*gw] for FP8 tokens
 
+    @property
+    def m(self) -> int:
+        return int(self.bits.shape[0])
+
 
 @dataclass
 class FrameOutput:

@@ -143,31 +143,44 @@ __device__ __forceinline__ bool dominated(int p, int Fp, int m, int Fm, int q, i
 
 __device__ __forceinline__ int parab(int site, int F, int y) { return __mul24(y - site, y - site) + F; }
 
-// --- the band's stack bitmap in three registers (rows b0 .. b0+95) ---
-__device__ __forceinline__ void bm_set(uint32_t& w0, uint32_t& w1, uint32_t& w2, int rel) {
-  const uint32_t bit = 1u << (rel & 31);
-  const int wi = rel >> 5;
-  if (wi == 0) w0 |= bit;
-  else if (wi == 1) w1 |= bit;
-  else w2 |= bit;
+// --- the band's stack bitmap in NW registers (rows b0 .. b0 + 32 NW - 1) ---
+template <int NW>
+__device__ __forceinline__ void bm_set(uint32_t* w, int rel) {
+  if (NW == 1) {
+    w[0] |= 1u << rel;
+  } else {
+    const uint32_t bit = 1u << (rel & 31);
+    const int wi = rel >> 5;
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+      if (wi == i) w[i] |= bit;
+  }
 }
-__device__ __forceinline__ void bm_clear(uint32_t& w0, uint32_t& w1, uint32_t& w2, int rel) {
-  const uint32_t bit = ~(1u << (rel & 31));
-  const int wi = rel >> 5;
-  if (wi == 0) w0 &= bit;
-  else if (wi == 1) w1 &= bit;
-  else w2 &= bit;
+template <int NW>
+__device__ __forceinline__ void bm_clear(uint32_t* w, int rel) {
+  if (NW == 1) {
+    w[0] &= ~(1u << rel);
+  } else {
+    const uint32_t bit = ~(1u << (rel & 31));
+    const int wi = rel >> 5;
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+      if (wi == i) w[i] &= bit;
+  }
 }
 // highest set bit strictly below rel (one always exists: the band's first row)
-__device__ __forceinline__ int bm_prev(uint32_t w0, uint32_t w1, uint32_t w2, int rel) {
+template <int NW>
+__device__ __forceinline__ int bm_prev(const uint32_t* w, int rel) {
+  if (NW == 1) return 31 - __builtin_clz(w[0] & ((1u << rel) - 1u));
   const int wi = rel >> 5;
   const uint32_t below = (rel & 31) ? ((1u << (rel & 31)) - 1u) : 0u;
-  const uint32_t c2 = wi == 2 ? (w2 & below) : (wi > 2 ? w2 : 0u);
-  const uint32_t c1 = wi == 1 ? (w1 & below) : (wi > 1 ? w1 : 0u);
-  const uint32_t c0 = wi == 0 ? (w0 & below) : w0;
-  if (c2) return 64 + 31 - __builtin_clz(c2);
-  if (c1) return 32 + 31 - __builtin_clz(c1);
-  return 31 - __builtin_clz(c0);
+  int r = -1;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const uint32_t c = wi == i ? (w[i] & below) : (wi > i ? w[i] : 0u);
+    if (c) r = 32 * i + 31 - __builtin_clz(c);
+  }
+  return r;
 }
 
 // --- the column's bitmap in LDS: bm[word][lane] ---
@@ -206,35 +219,71 @@ __device__ __forceinline__ int gsq(const uint4* rec, int row, int lane, bool lan
   return lane_ok ? __mul24(g, g) : 0;
 }
 
-// Merge the envelope of rows [lo, jb) with the envelope of rows [jb, hi).
+// Merge the envelope of rows [lo, jb) with the envelope of rows [jb, hi)
+// (lo and jb multiples of 32): pop dominated sites on either side of the
+// junction.  The bitmap words holding the two innermost sites stay in
+// registers while sites are popped and are written back once at the end.
 __device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool lane_ok, int lo, int jb, int hi) {
   int a1 = lds_prev(bm, lane, jb, lo);
   int b1 = lds_next(bm, lane, jb, hi);
   if (a1 < 0 || b1 < 0) return;
-  int a2 = lds_prev(bm, lane, a1, lo);
-  int b2 = lds_next(bm, lane, b1 + 1, hi);
+  int uwi = a1 >> 5, lwi = b1 >> 5;  // words holding a1 and b1
+  uint32_t uwd = bm[uwi * 64 + lane], lwd = bm[lwi * 64 + lane];
+  bool udirty = false, ldirty = false;
+  // next site below a1 / above b1, from the cached word first
+  auto below = [&](int a) -> int {
+    const uint32_t m = uwd & ((1u << (a & 31)) - 1u);
+    if (m) return (uwi << 5) + 31 - __builtin_clz(m);
+    return lds_prev(bm, lane, uwi << 5, lo);
+  };
+  auto above = [&](int b) -> int {
+    const uint32_t m = (b & 31) == 31 ? 0u : (lwd & (0xFFFFFFFEu << (b & 31)));
+    if (m) {
+      const int r = (lwi << 5) + __builtin_ctz(m);
+      return r < hi ? r : -1;
+    }
+    return lds_next(bm, lane, (lwi + 1) << 5, hi);
+  };
+  int a2 = below(a1);
+  int b2 = above(b1);
   int Fa1 = gsq(rec, a1, lane, lane_ok), Fb1 = gsq(rec, b1, lane, lane_ok);
   int Fa2 = a2 >= 0 ? gsq(rec, a2, lane, lane_ok) : 0;
   int Fb2 = b2 >= 0 ? gsq(rec, b2, lane, lane_ok) : 0;
   for (;;) {
     if (a2 >= 0 && dominated(a2, Fa2, a1, Fa1, b1, Fb1)) {
-      bm[(a1 >> 5) * 64 + lane] &= ~(1u << (a1 & 31));
+      uwd &= ~(1u << (a1 & 31));
+      udirty = true;
       a1 = a2;
       Fa1 = Fa2;
-      a2 = lds_prev(bm, lane, a1, lo);
+      if ((a1 >> 5) != uwi) {
+        bm[uwi * 64 + lane] = uwd;
+        uwi = a1 >> 5;
+        uwd = bm[uwi * 64 + lane];
+        udirty = false;
+      }
+      a2 = below(a1);
       Fa2 = a2 >= 0 ? gsq(rec, a2, lane, lane_ok) : 0;
       continue;
     }
     if (b2 >= 0 && dominated(a1, Fa1, b1, Fb1, b2, Fb2)) {
-      bm[(b1 >> 5) * 64 + lane] &= ~(1u << (b1 & 31));
+      lwd &= ~(1u << (b1 & 31));
+      ldirty = true;
       b1 = b2;
       Fb1 = Fb2;
-      b2 = lds_next(bm, lane, b1 + 1, hi);
+      if ((b1 >> 5) != lwi) {
+        bm[lwi * 64 + lane] = lwd;
+        lwi = b1 >> 5;
+        lwd = bm[lwi * 64 + lane];
+        ldirty = false;
+      }
+      b2 = above(b1);
       Fb2 = b2 >= 0 ? gsq(rec, b2, lane, lane_ok) : 0;
       continue;
     }
     break;
   }
+  if (udirty) bm[uwi * 64 + lane] = uwd;
+  if (ldirty) bm[lwi * 64 + lane] = lwd;
 }
 
 // Packets: the items of class c are grouped class_items(c) at a time; the
@@ -259,8 +308,219 @@ __device__ __forceinline__ int packet_slot(const int32_t* counts, const int32_t*
   return -1;
 }
 
+// One packet: wavefront kb holds band j of the item in slot kb / K (its mask
+// record broadcast from pf; word < 0: no item).  `prefetch` is called once,
+// after the row records are in LDS, to start loading the next packet.
+template <int SPATIAL, int B, typename Prefetch>
+__device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* rec_all, uint32_t* bm_all,
+                                           float* part_all, int lane, int kb, int32_t* e_out, Prefetch prefetch) {
+  constexpr int NW = B / 32;
+  const int rows_c = B * K;
+  const int slot = kb / K, j = kb - slot * K;  // item slot in the packet, band in the item
+  const bool has = word >= 0;
+  const int strip = has ? (word & ((1 << kItemStripBits) - 1)) : 0;
+  auto fld = [&](int q) { return (int)__builtin_amdgcn_readlane(pf, q); };
+  const uint64_t* mb = reinterpret_cast<const uint64_t*>(((uint64_t)(uint32_t)fld(1) << 32) | (uint32_t)fld(0));
+  float* srow = reinterpret_cast<float*>(((uint64_t)(uint32_t)fld(3) << 32) | (uint32_t)fld(2));
+  const int y0 = fld(4), y1 = fld(5), x0 = fld(6), x1 = fld(7);
+  const int n = has ? fld(8) : 0;
+  const int P = has ? fld(9) : kMinPatch;
+  const int gw = fld(10), wq = fld(11), fw = fld(12), fh = fld(13), xs0 = fld(14), gidx = fld(15);
+  const int SW = strip_width(P);
+  const int xs = xs0 + strip * SW;
+  const bool lane_ok = lane < SW;
+  const int col = xs + lane;
+  // this item's rows and bitmap words in LDS (rows_c is a multiple of 32)
+  uint4* rec = rec_all + slot * rows_c;
+  uint32_t* bm = bm_all + (slot * rows_c / 32) * 64;
+  float* part = part_all + kb * kEdtPartRows * 8;
+
+  const int b0 = j * B, b1 = min(b0 + B, n);
+
+  // ---- row records: lane l reads rows b0 + l (and b0 + 64 + l) of its band:
+  // the strip's 64-bit window and the run lengths past the window's ends
+  // (only read when the edge pixel is inside the mask).
+  constexpr int NR = (B + 63) / 64;
+  uint4 rreg[NR];  // this lane's rows' records, kept for the sequential pass
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr) {
+    const int u = b0 + lane + 64 * rr;
+    rreg[rr] = make_uint4(0u, 0u, 0u, 0u);  // padding row: no runs
+    if (lane + 64 * rr < B && u < b1) {
+      if (u > 0 && u < n - 1) {
+        const uint64_t* row = mb + (int64_t)(y0 - 1 + u) * wq;
+        const uint64_t win = load_window(row, xs, wq, fw);
+        const int L = (win & 1ull) ? run_left(row, xs - 1, wq, fw) : 0;
+        const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw) : 0;
+        rreg[rr] = make_rowrec(win, L, R);
+      }
+      rec[u] = rreg[rr];
+    }
+  }
+  __syncthreads();
+  prefetch();
+
+  // ---- this band's lower envelope (sequential in u; row u's record is
+  // broadcast from the lane that read it) ----
+  if (SPATIAL == 0 && b0 < n) {
+    uint32_t w[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = 0u;
+    int depth = 0, s1 = 0, s2 = 0, F1 = 0, F2 = 0;
+    for (int u = b0; u < b1; ++u) {
+      const int k = u - b0;
+      const uint4 src = (NR == 1 || k < 64) ? rreg[0] : rreg[NR - 1];
+      const int kl = k & 63;
+      const uint4 ru = make_uint4(__builtin_amdgcn_readlane(src.x, kl), __builtin_amdgcn_readlane(src.y, kl),
+                                  __builtin_amdgcn_readlane(src.z, kl), __builtin_amdgcn_readlane(src.w, kl));
+      const int gu = g_rec(ru, lane);
+      const int Fu = lane_ok ? __mul24(gu, gu) : 0;
+      while (depth >= 2 && dominated(s2, F2, s1, F1, u, Fu)) {
+        bm_clear<NW>(w, s1 - b0);
+        --depth;
+        s1 = s2;
+        F1 = F2;
+        if (depth >= 2) {
+          s2 = b0 + bm_prev<NW>(w, s1 - b0);
+          F2 = gsq(rec, s2, lane, lane_ok);
+        }
+      }
+      bm_set<NW>(w, u - b0);
+      s2 = s1;
+      F2 = F1;
+      s1 = u;
+      F1 = Fu;
+      ++depth;
+    }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) bm[((b0 >> 5) + i) * 64 + lane] = w[i];
+  }
+  __syncthreads();
+
+  // ---- merge band envelopes pairwise ----
+  if (SPATIAL == 0) {
+    for (int step = 1; step < K; step <<= 1) {
+      if ((j % (2 * step)) == 0 && j + step < K) {
+        const int jb = (j + step) * B;
+        if (jb < n) merge_junction(rec, bm, lane, lane_ok, j * B, jb, min((j + 2 * step) * B, n));
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- final walk: e over the band's rows, sqrt(e) summed per patch ----
+  const int pfirst = (y0 - 1 + max(b0, 1)) / P;  // first patch row this band meets
+  float acc = 0.f;
+  int cur_pr = -1;
+  int c = 0, Fc = 0, nx = -1, Fn = 0;
+  if (SPATIAL == 0 && b0 < n) {
+    c = lds_prev(bm, lane, b0 + 1, 0);
+    Fc = gsq(rec, c, lane, lane_ok);
+    for (;;) {
+      const int q = lds_prev(bm, lane, c, 0);
+      if (q < 0) break;
+      const int Fq = gsq(rec, q, lane, lane_ok);
+      if (parab(q, Fq, b0) <= parab(c, Fc, b0)) {
+        c = q;
+        Fc = Fq;
+      } else {
+        break;
+      }
+    }
+    nx = lds_next(bm, lane, c + 1, n);
+    Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok) : 0;
+  }
+  // the band's own bitmap word(s) stay in registers for the walk
+  const int cw0 = b0 >> 5;
+  uint32_t cw[NW];
+#pragma unroll
+  for (int i = 0; i < NW; ++i) cw[i] = (SPATIAL == 0 && b0 < n) ? bm[(cw0 + i) * 64 + lane] : 0u;
+  auto next_site = [&](int pos) -> int {  // lowest envelope row r with pos <= r < n, or -1
+    if (pos >= n) return -1;
+    const int wi = pos >> 5;
+    if (wi >= cw0 && wi < cw0 + NW) {
+      uint32_t wd = 0u;
+#pragma unroll
+      for (int i = 0; i < NW; ++i)
+        if (wi == cw0 + i) wd = cw[i] & (0xFFFFFFFFu << (pos & 31));
+      if (wd) {
+        const int r = wi * 32 + __builtin_ctz(wd);
+        return r < n ? r : -1;
+      }
+#pragma unroll
+      for (int i = 0; i < NW; ++i)
+        if (wi < cw0 + i && cw[i]) {
+          const int r = (cw0 + i) * 32 + __builtin_ctz(cw[i]);
+          return r < n ? r : -1;
+        }
+      return lds_next(bm, lane, (cw0 + NW) * 32, n);
+    }
+    return lds_next(bm, lane, pos, n);
+  };
+  auto flush = [&](int pr, float v) {
+    v = lane_ok ? v : 0.f;
+    const int inseg = lane % P;
+    for (int o = 1; o < P; o <<= 1) {
+      const float t = __shfl_down(v, o);
+      if (inseg + o < P && lane + o < 64) v += t;
+    }
+    if (inseg == 0 && lane_ok) part[(pr - pfirst) * 8 + lane / P] = v;
+  };
+  for (int u = b0; u < b1; ++u) {
+    int e;
+    if (SPATIAL == 0) {
+      while (nx >= 0 && parab(nx, Fn, u) <= parab(c, Fc, u)) {
+        c = nx;
+        Fc = Fn;
+        nx = next_site(c + 1);
+        Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok) : 0;
+      }
+      e = __mul24(u - c, u - c) + Fc;
+    } else {
+      e = gsq(rec, u, lane, lane_ok) > 0 ? 1 : 0;
+    }
+    if (u >= 1 && u <= n - 2) {
+      const int Y = y0 - 1 + u;
+      const int pr = Y / P;
+      if (pr != cur_pr) {
+        if (cur_pr >= 0) flush(cur_pr, acc);
+        cur_pr = pr;
+        acc = 0.f;
+      }
+      acc += SPATIAL == 0 ? __builtin_amdgcn_sqrtf((float)e) : (float)e;  // e >= 0 integer: no denormals
+      if (e_out != nullptr && lane_ok && col >= x0 && col <= x1)
+        e_out[(int64_t)gidx * fh * fw + (int64_t)Y * fw + col] = e;
+    }
+  }
+  if (cur_pr >= 0) flush(cur_pr, acc);
+  __syncthreads();
+
+  // ---- the strip's patch sums: each patch row adds the partial sums of the
+  // bands that meet it, in band order ----
+  if (has) {
+    const int npc = SW / P;
+    const int prbase = y0 / P;
+    const int npr = y1 / P - prbase + 1;
+    const int pc0 = xs / P;
+    for (int idx = j * 64 + lane; idx < npr * npc; idx += K * 64) {
+      const int prl = idx / npc, q = idx - prl * npc;
+      const int pc = pc0 + q;
+      const int pr = prbase + prl;
+      const int ua = max(pr * P, y0) - y0 + 1, ub = min(pr * P + P - 1, y1) - y0 + 1;
+      float v = 0.f;
+      for (int jj = ua / B; jj <= ub / B; ++jj) {
+        const int pf_j = (y0 - 1 + max(jj * B, 1)) / P;
+        v += part_all[((slot * K + jj) * kEdtPartRows + (pr - pf_j)) * 8 + q];
+      }
+      if (pc < gw) srow[pr * gw + pc] = v;
+    }
+  }
+  __syncthreads();
+}
+
 template <int SPATIAL>  // 0: EDT, 1: AREA (pixel counts, no transform)
-__global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_edt(Batch b, Work wk, int32_t* e_out) {
+__global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_edt(Batch b, Work wk,
+                                                                                                 int32_t* e_out) {
   __shared__ uint4 rec_all[kMaxRows];
   __shared__ uint32_t bm_all[kEdtBmWords * 64];
   __shared__ float part_all[kEdtWaves * kEdtPartRows * 8];
@@ -269,7 +529,6 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
   const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int total = 0;
   for (int c = 0; c < kClasses; ++c) total += (wk.counts[c] + class_items(c) - 1) / class_items(c);
-  float* part = part_all + kb * kEdtPartRows * 8;
 
   // Packets are taken in a fixed stride (no shared queue).  Each wavefront
   // prefetches the record of its item in the next packet into one VGPR per
@@ -282,179 +541,23 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
   if (word >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(wk.mrec + (word >> kItemStripBits))[lane];
 
   for (; p < total; p += gridDim.x) {
-    const int K = class_waves(cls), B = class_band(cls), rows_c = class_rows(cls);
-    const int slot = kb / K, j = kb - slot * K;  // item slot in the packet, band in the item
-    const bool has = word >= 0;
-    const int strip = has ? (word & ((1 << kItemStripBits) - 1)) : 0;
-    auto fld = [&](int q) { return (int)__builtin_amdgcn_readlane(pf, q); };
-    const uint64_t* mb = reinterpret_cast<const uint64_t*>(((uint64_t)(uint32_t)fld(1) << 32) | (uint32_t)fld(0));
-    float* srow = reinterpret_cast<float*>(((uint64_t)(uint32_t)fld(3) << 32) | (uint32_t)fld(2));
-    const int y0 = fld(4), y1 = fld(5), x0 = fld(6), x1 = fld(7);
-    const int n = has ? fld(8) : 0;
-    const int P = has ? fld(9) : kMinPatch;
-    const int gw = fld(10), wq = fld(11), fw = fld(12), fh = fld(13), xs0 = fld(14), gidx = fld(15);
-    const int SW = strip_width(P);
-    const int xs = xs0 + strip * SW;
-    const bool lane_ok = lane < SW;
-    const int col = xs + lane;
-    // this item's rows and bitmap words in LDS (rows_c is a multiple of 32)
-    uint4* rec = rec_all + slot * rows_c;
-    uint32_t* bm = bm_all + (slot * rows_c / 32) * 64;
-
-    const int b0 = j * B, b1 = min(b0 + B, n);
-
-    // ---- row records: lane l reads rows b0 + l (and b0 + 64 + l) of its band:
-    // the strip's 64-bit window and the run lengths past the window's ends
-    // (only read when the edge pixel is inside the mask).
-#pragma unroll
-    for (int rr = 0; rr < 2; ++rr) {
-      const int u = b0 + lane + 64 * rr;
-      if (lane + 64 * rr < B && u < b1) {
-        uint4 r = make_uint4(0u, 0u, 0u, 0u);  // padding row: no runs
-        if (u > 0 && u < n - 1) {
-          const uint64_t* row = mb + (int64_t)(y0 - 1 + u) * wq;
-          const uint64_t win = load_window(row, xs, wq, fw);
-          const int L = (win & 1ull) ? run_left(row, xs - 1, wq, fw) : 0;
-          const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw) : 0;
-          r = make_rowrec(win, L, R);
-        }
-        rec[u] = r;
-      }
-    }
-    __syncthreads();
-    // prefetch the record of this wavefront's item in the next packet
     int ncls = -1, nword = -1;
-    if (p + (int)gridDim.x < total) {
-      ncls = packet_slot(wk.counts, wk.items, p + gridDim.x, kb, nword);
-      if (nword >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(wk.mrec + (nword >> kItemStripBits))[lane];
-    }
-
-    // ---- this band's lower envelope (sequential in u) ----
-    if (SPATIAL == 0 && b0 < n) {
-      uint32_t w0 = 0, w1 = 0, w2 = 0;
-      int depth = 0, s1 = 0, s2 = 0, F1 = 0, F2 = 0;
-      for (int u = b0; u < b1; ++u) {
-        const int Fu = gsq(rec, u, lane, lane_ok);
-        while (depth >= 2 && dominated(s2, F2, s1, F1, u, Fu)) {
-          bm_clear(w0, w1, w2, s1 - b0);
-          --depth;
-          s1 = s2;
-          F1 = F2;
-          if (depth >= 2) {
-            s2 = b0 + bm_prev(w0, w1, w2, s1 - b0);
-            F2 = gsq(rec, s2, lane, lane_ok);
-          }
-        }
-        bm_set(w0, w1, w2, u - b0);
-        s2 = s1;
-        F2 = F1;
-        s1 = u;
-        F1 = Fu;
-        ++depth;
+    uint32_t npf = pf;
+    auto prefetch = [&]() {
+      if (p + (int)gridDim.x < total) {
+        ncls = packet_slot(wk.counts, wk.items, p + gridDim.x, kb, nword);
+        if (nword >= 0 && lane < 16) npf = reinterpret_cast<const uint32_t*>(wk.mrec + (nword >> kItemStripBits))[lane];
       }
-      const int wb = b0 >> 5;
-      bm[wb * 64 + lane] = w0;
-      if (B > 32) {
-        bm[(wb + 1) * 64 + lane] = w1;
-        bm[(wb + 2) * 64 + lane] = w2;
-      }
-    }
-    __syncthreads();
-
-    // ---- merge band envelopes pairwise ----
-    if (SPATIAL == 0) {
-      for (int step = 1; step < K; step <<= 1) {
-        if ((j % (2 * step)) == 0 && j + step < K) {
-          const int jb = (j + step) * B;
-          if (jb < n) merge_junction(rec, bm, lane, lane_ok, j * B, jb, min((j + 2 * step) * B, n));
-        }
-        __syncthreads();
-      }
-    }
-
-    // ---- final walk: e over the band's rows, sqrt(e) summed per patch ----
-    const int pfirst = (y0 - 1 + max(b0, 1)) / P;  // first patch row this band meets
-    float acc = 0.f;
-    int cur_pr = -1;
-    int c = 0, Fc = 0, nx = -1, Fn = 0;
-    if (SPATIAL == 0 && b0 < n) {
-      c = lds_prev(bm, lane, b0 + 1, 0);
-      Fc = gsq(rec, c, lane, lane_ok);
-      for (;;) {
-        const int q = lds_prev(bm, lane, c, 0);
-        if (q < 0) break;
-        const int Fq = gsq(rec, q, lane, lane_ok);
-        if (parab(q, Fq, b0) <= parab(c, Fc, b0)) {
-          c = q;
-          Fc = Fq;
-        } else {
-          break;
-        }
-      }
-      nx = lds_next(bm, lane, c + 1, n);
-      Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok) : 0;
-    }
-    auto flush = [&](int pr, float v) {
-      v = lane_ok ? v : 0.f;
-      const int inseg = lane % P;
-      for (int o = 1; o < P; o <<= 1) {
-        const float t = __shfl_down(v, o);
-        if (inseg + o < P && lane + o < 64) v += t;
-      }
-      if (inseg == 0 && lane_ok) part[(pr - pfirst) * 8 + lane / P] = v;
     };
-    for (int u = b0; u < b1; ++u) {
-      int e;
-      if (SPATIAL == 0) {
-        while (nx >= 0 && parab(nx, Fn, u) <= parab(c, Fc, u)) {
-          c = nx;
-          Fc = Fn;
-          nx = lds_next(bm, lane, c + 1, n);
-          Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok) : 0;
-        }
-        e = __mul24(u - c, u - c) + Fc;
-      } else {
-        e = gsq(rec, u, lane, lane_ok) > 0 ? 1 : 0;
-      }
-      if (u >= 1 && u <= n - 2) {
-        const int Y = y0 - 1 + u;
-        const int pr = Y / P;
-        if (pr != cur_pr) {
-          if (cur_pr >= 0) flush(cur_pr, acc);
-          cur_pr = pr;
-          acc = 0.f;
-        }
-        acc += SPATIAL == 0 ? __builtin_amdgcn_sqrtf((float)e) : (float)e;  // e >= 0 integer: no denormals
-        if (e_out != nullptr && lane_ok && col >= x0 && col <= x1)
-          e_out[(int64_t)gidx * fh * fw + (int64_t)Y * fw + col] = e;
-      }
-    }
-    if (cur_pr >= 0) flush(cur_pr, acc);
-    __syncthreads();
-
-    // ---- the strip's patch sums: each patch row adds the partial sums of the
-    // bands that meet it, in band order ----
-    if (has) {
-      const int npc = SW / P;
-      const int prbase = y0 / P;
-      const int npr = y1 / P - prbase + 1;
-      const int pc0 = xs / P;
-      for (int idx = j * 64 + lane; idx < npr * npc; idx += K * 64) {
-        const int prl = idx / npc, q = idx - prl * npc;
-        const int pc = pc0 + q;
-        const int pr = prbase + prl;
-        const int ua = max(pr * P, y0) - y0 + 1, ub = min(pr * P + P - 1, y1) - y0 + 1;
-        float v = 0.f;
-        for (int jj = ua / B; jj <= ub / B; ++jj) {
-          const int pf_j = (y0 - 1 + max(jj * B, 1)) / P;
-          v += part_all[((slot * K + jj) * kEdtPartRows + (pr - pf_j)) * 8 + q];
-        }
-        if (pc < gw) srow[pr * gw + pc] = v;
-      }
-    }
-    __syncthreads();
+    if (cls == kClasses - 1)
+      edt_packet<SPATIAL, class_band(kClasses - 1)>(class_waves(cls), pf, word, rec_all, bm_all, part_all, lane, kb,
+                                                    e_out, prefetch);
+    else
+      edt_packet<SPATIAL, class_band(0)>(class_waves(cls), pf, word, rec_all, bm_all, part_all, lane, kb, e_out,
+                                         prefetch);
     cls = ncls;
     word = nword;
+    pf = npf;
   }
 }
 

@@ -6,6 +6,7 @@ import numpy as np
 
 import disc_inputs as di
 import oracle
+from disc_inputs.device import dev_bits, dev_proj, dev_tokens  # noqa: F401
 
 # Tolerances of the path against the FP64 oracle (per mask, cosine similarity).
 COS_FP32 = 1.0 - 1e-6
@@ -17,30 +18,6 @@ def torch():
     import torch as t
 
     return t
-
-
-def dev_bits(bits: np.ndarray):
-    t = torch()
-    return t.from_numpy(np.ascontiguousarray(bits).view(np.int64)).cuda()
-
-
-def dev_tokens(tok: di.Tokens):
-    t = torch()
-    if tok.dtype == "f32":
-        data = t.from_numpy(np.ascontiguousarray(tok.data)).cuda()
-    elif tok.dtype == "bf16":
-        data = t.from_numpy(np.ascontiguousarray(tok.data).view(np.int16)).cuda().view(t.bfloat16)
-    else:
-        data = t.from_numpy(np.ascontiguousarray(tok.data)).cuda()
-    scale = t.from_numpy(tok.scale).cuda() if tok.scale is not None else None
-    return data, scale
-
-
-def dev_proj(P: np.ndarray, dtype: str):
-    t = torch()
-    if dtype == "f32":
-        return t.from_numpy(np.ascontiguousarray(P)).cuda()
-    return t.from_numpy(np.ascontiguousarray(P).view(np.int16)).cuda().view(t.bfloat16)
 
 
 def frame_input(fr: di.Frame):

@@ -1,0 +1,38 @@
+"""Host logic of the benchmark: the algorithmic work counts its roofline uses
+(bounding boxes from packed bits, touched patches), checked against the
+unpacked masks."""
+import numpy as np
+
+import bench
+import disc_inputs as di
+
+
+def test_bbox_and_touched_patches_match_unpacked_masks():
+    for seed, (h, w, P) in enumerate([(70, 130, 16), (33, 65, 14), (64, 64, 8)]):
+        bits = di.masks_mixed(100 + seed, 12, h, w, 0.002, 0.4)
+        u = di.unpack_masks(bits, w).copy()
+        u[0] = 0  # an empty mask
+        bits = di.pack_masks(u)
+        bb = bench._bbox(bits)
+        assert bb[0] is None
+        for i in range(1, len(u)):
+            ys, xs = np.nonzero(u[i])
+            assert bb[i] == (ys.min(), ys.max(), xs.min(), xs.max())
+        gh, gw = -(-h // P), -(-w // P)
+        pad = np.zeros((len(u), gh * P, gw * P), dtype=np.uint8)
+        pad[:, :h, :w] = u
+        want = int((pad.reshape(len(u), gh, P, gw, P).max(axis=(2, 4)) > 0).sum())
+        assert bench._touched_patches(bits, h, w, P) == want
+
+
+def test_workload_units_counts():
+    wl = di.workload("cfg1")
+    units, tot = bench.workload_units(wl, gemm_bf16=False)
+    f = wl.frames[0]
+    assert tot["masks"] == f.m
+    assert units["proj"][1] == 2.0 * f.m * 1024 * 768
+    assert units["pool"][1] == 2.0 * tot["touched_patches"] * 1024
+    assert units["edt"][1] == bench.EDT_OPS_PER_PIXEL * tot["edt_pixels"]
+    assert units["scan"][1] == f.bits.nbytes
+    r = bench.roofline("edt", 1.0, units, "cfg1")
+    assert r["bound"] == "alu" and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-15
