@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--no-trace", action="store_true", help="skip per-stage event timing")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="offered-load duration of the served leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served BF16 leg")
+    ap.add_argument("--edt-layout", type=int, default=-1, choices=[-1, 0, 1],
+                    help="distance-transform band layout (-1: chosen per call)")
     return ap.parse_args()
 
 
@@ -270,7 +272,7 @@ def main():
         ins.append(disc.FrameInput(data, dev.dev_bits(f.bits), f.h, f.w, f.tokens.patch, scale))
     proj = dev.dev_proj(wl.proj, wl.proj_dtype)
     outs = disc.alloc_outputs(ins, wl.proj.shape[1])
-    opts = disc.make_options()
+    opts = disc.make_options(edt_layout=args.edt_layout)
     stream = torch.cuda.current_stream()
     gemm_bf16 = not (wl.proj_dtype == "f32" and wl.frames[0].tokens.dtype == "f32")
     units, totals = workload_units(wl, gemm_bf16)

@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define DISC_ABI_VERSION 1
+#define DISC_ABI_VERSION 2
 
 typedef enum disc_status {
   DISC_OK = 0,
@@ -125,6 +125,11 @@ typedef struct disc_options {
                              accumulation in every case. */
   void* workspace;        /* optional caller-owned device workspace */
   size_t workspace_bytes; /* its size; see disc_workspace_bytes() */
+  int32_t edt_layout;     /* distance-transform band layout: -1 (default)
+                             chosen per call from the amount of work, 0 short
+                             bands (lowest latency for few masks), 1 longer
+                             bands (throughput for large batches).  Results
+                             are identical bit for bit in every layout. */
 } disc_options;
 
 /* Fill *o with the defaults listed above. */

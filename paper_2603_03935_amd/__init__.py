@@ -72,7 +72,8 @@ class Out(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("spatial", ctypes.c_int32), ("distinct", ctypes.c_int32), ("eps", ctypes.c_float),
-                ("gemm_dtype", ctypes.c_int32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("gemm_dtype", ctypes.c_int32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("edt_layout", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -214,10 +215,11 @@ def make_proj(proj) -> Proj:
 
 
 def make_options(spatial: int = SPATIAL_EDT, distinct: int = 1, eps: float = 1e-6, gemm_dtype: int = -1,
-                 workspace=None) -> Options:
+                 workspace=None, edt_layout: int = -1) -> Options:
     o = Options()
     load().disc_options_default(ctypes.byref(o))
     o.spatial, o.distinct, o.eps, o.gemm_dtype = spatial, distinct, eps, gemm_dtype
+    o.edt_layout = edt_layout
     if workspace is not None:
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -309,7 +311,7 @@ def edt_sq(bits, h: int, w: int, stream=None):
 
 
 def patch_weights(bits, h: int, w: int, patch: int, tokens=None, scale=None, spatial: int = SPATIAL_EDT,
-                  distinct: int = 1, eps: float = 1e-6, stream=None):
+                  distinct: int = 1, eps: float = 1e-6, stream=None, edt_layout: int = -1):
     """disc_patch_weights -> float32 [m][gh*gw]."""
     torch = _torch()
     m = bits.shape[0]
@@ -317,7 +319,7 @@ def patch_weights(bits, h: int, w: int, patch: int, tokens=None, scale=None, spa
     out = torch.empty((m, gh * gw), dtype=torch.float32, device=bits.device)
     mk = make_masks(bits, h, w)
     tk = make_tokens(tokens, patch, scale) if tokens is not None else None
-    opts = make_options(spatial, distinct, eps)
+    opts = make_options(spatial, distinct, eps, edt_layout=edt_layout)
     _check(load().disc_patch_weights(ctypes.byref(tk) if tk is not None else None, ctypes.byref(mk), patch,
                                      ctypes.byref(opts), _ptr(out), _stream_handle(stream)))
     return out

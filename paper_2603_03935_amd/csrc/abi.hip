@@ -121,6 +121,8 @@ disc_status check_opts(const disc_options* o, const char* who) {
   if (o->gemm_dtype != -1 && o->gemm_dtype != DISC_F32 && o->gemm_dtype != DISC_BF16)
     return fail(DISC_ERR_UNSUPPORTED_DTYPE, "%s: gemm dtype must be F32, BF16 or -1", who);
   if (o->workspace && !aligned16(o->workspace)) return fail(DISC_ERR_ALIGNMENT, "%s: workspace must be 16-byte aligned", who);
+  if (o->edt_layout < -1 || o->edt_layout > 1)
+    return fail(DISC_ERR_INVALID_ARGUMENT, "%s: edt_layout must be -1, 0 or 1", who);
   return DISC_OK;
 }
 
@@ -501,7 +503,7 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
     StageTimer t(sid < 0 ? -1 : ST_STATS, st);
     launch_token_stats(b, w, p.shape.gmax, o.distinct, p.shape.gemm_bf16, st);
   }
-  { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st, o.edt_layout); }
   { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); }
   { StageTimer t(sid < 0 ? -1 : ST_POOL, st); launch_pool(b, w, tiles, p.shape.n_tiles, st); }
   { StageTimer t(sid < 0 ? -1 : ST_PROJ, st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, w.ssq, st); }
@@ -525,6 +527,7 @@ void disc_options_default(disc_options* o) {
   o->gemm_dtype = -1;
   o->workspace = nullptr;
   o->workspace_bytes = 0;
+  o->edt_layout = -1;
 }
 
 int32_t disc_abi_version(void) { return DISC_ABI_VERSION; }
@@ -662,7 +665,7 @@ disc_status disc_patch_weights(const disc_tokens* tokens, const disc_masks* mask
   launch_scan(b, w, cx.st);
   launch_plan(b, w, cx.st);
   if (o.distinct) launch_token_stats(b, w, p.shape.gmax, 1, 0, cx.st);
-  launch_edt(b, w, nullptr, num_cus(cx.dev), cx.st);
+  launch_edt(b, w, nullptr, num_cus(cx.dev), cx.st, o.edt_layout);
   launch_dense_weights(b, w, wout, o.eps, cx.st);
   if ((st = check_launch(who))) return st;
   return ok();

@@ -12,16 +12,23 @@ namespace disc {
 // A work item is (mask, strip): SW(P) = 64 - 64 % P consecutive pixel columns
 // starting on a patch boundary.  The item's rows (bounding-box height + one
 // padding row above and below, n rows) are split into bands of B rows, one
-// wavefront per band.  The row count picks the class: B and the band count K.
+// wavefront per band.  The row count picks the class c (n <= class_rows(c)).
 // One EDT workgroup has kEdtWaves wavefronts and processes a packet of
-// kEdtWaves / K items of one class side by side.
+// kEdtWaves / K items of one class side by side.  Two band layouts share the
+// classes: mode 0 (short bands, for small batches where the longest item sets
+// the time) and mode 1 (longer bands and fewer merge steps, for batches that
+// fill the GPU many times over):
+//   class        0    1    2    3    4     5
+//   rows        32   64  128  256  512  1152
+//   mode 0 B,K  32,1 32,2 32,4 32,8 32,16 96,12
+//   mode 1 B,K  32,1 64,1 64,2 64,4 64,8  96,12
 // ---------------------------------------------------------------------------
 constexpr int kClasses = 6;
 constexpr int kEdtWaves = 16;
-__host__ __device__ constexpr int class_band(int c) { return c == 5 ? 96 : 32; }
-__host__ __device__ constexpr int class_waves(int c) { return c == 5 ? 12 : (1 << c); }
-__host__ __device__ constexpr int class_rows(int c) { return class_band(c) * class_waves(c); }
-__host__ __device__ constexpr int class_items(int c) { return kEdtWaves / class_waves(c); }  // items per packet
+__host__ __device__ constexpr int class_rows(int c) { return c == 5 ? 1152 : (32 << c); }
+__host__ __device__ constexpr int class_band(int mode, int c) { return c == 5 ? 96 : (mode == 0 || c == 0) ? 32 : 64; }
+__host__ __device__ constexpr int class_waves(int mode, int c) { return class_rows(c) / class_band(mode, c); }
+__host__ __device__ constexpr int class_items(int mode, int c) { return kEdtWaves / class_waves(mode, c); }
 constexpr int kMaxRows = 1152;      // bbox height + 2
 constexpr int kMinPatch = 8;
 constexpr int kMaxPatch = 64;
@@ -31,11 +38,15 @@ constexpr int kMaxC = 2048;
 __host__ __device__ inline int strip_width(int patch) { return 64 - (64 % patch); }
 
 // LDS of one EDT workgroup (every class fits kMaxRows rows): a 16-byte record
-// per row, the per-column stack bitmaps (one bit per row) and each band's
-// partial patch sums (a band of at most 96 rows meets at most 13 patch rows of
-// at least 8 pixels).
+// per row, the per-column stack bitmaps (one bit per row) and the partial
+// patch sums of every 32-row block of the items' rows (a block meets at most
+// 6 patch rows of at least 8 pixels).  Patch sums are always formed per
+// 32-row block, whatever the band height, so the order of the additions (and
+// the result) depends only on the mask.
 constexpr int kEdtBmWords = kMaxRows / 32 + 1;
-constexpr int kEdtPartRows = 13;
+constexpr int kEdtBlocks = kMaxRows / 32;
+constexpr int kEdtPartRows = 6;
+
 // Per-mask record of the distance transform (written by the mask scan).
 struct MaskRec {
   const uint64_t* bits;    // the mask's first row
@@ -102,7 +113,7 @@ struct Work {
 // Host-side launchers (stream = hipStream_t).
 void launch_scan(const Batch& b, const Work& w, hipStream_t st);
 void launch_plan(const Batch& b, const Work& w, hipStream_t st);
-void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st);
+void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode = -1);
 void edt_prepare();
 // want_r: residual norms (needs the mean); pack: k-packed token copy for the BF16 pooling GEMM
 void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st);

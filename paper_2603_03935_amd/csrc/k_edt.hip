@@ -143,45 +143,62 @@ __device__ __forceinline__ bool dominated(int p, int Fp, int m, int Fm, int q, i
 
 __device__ __forceinline__ int parab(int site, int F, int y) { return __mul24(y - site, y - site) + F; }
 
-// --- the band's stack bitmap in NW registers (rows b0 .. b0 + 32 NW - 1) ---
+// --- the band's stack bitmap in NW (1..3) registers, rows b0 .. b0 + 32 NW - 1 ---
 template <int NW>
-__device__ __forceinline__ void bm_set(uint32_t* w, int rel) {
-  if (NW == 1) {
-    w[0] |= 1u << rel;
-  } else {
-    const uint32_t bit = 1u << (rel & 31);
+struct BandBits {
+  uint32_t w0 = 0u, w1 = 0u, w2 = 0u;
+  __device__ __forceinline__ void set(int rel) {
+    if (NW == 1) {
+      w0 |= 1u << rel;
+    } else {
+      const uint32_t bit = 1u << (rel & 31);
+      const int wi = rel >> 5;
+      w0 = wi == 0 ? (w0 | bit) : w0;
+      w1 = wi == 1 ? (w1 | bit) : w1;
+      if (NW > 2) w2 = wi == 2 ? (w2 | bit) : w2;
+    }
+  }
+  __device__ __forceinline__ void clear(int rel) {
+    if (NW == 1) {
+      w0 &= ~(1u << rel);
+    } else {
+      const uint32_t bit = ~(1u << (rel & 31));
+      const int wi = rel >> 5;
+      w0 = wi == 0 ? (w0 & bit) : w0;
+      w1 = wi == 1 ? (w1 & bit) : w1;
+      if (NW > 2) w2 = wi == 2 ? (w2 & bit) : w2;
+    }
+  }
+  // highest set bit strictly below rel (one always exists: the band's first row)
+  __device__ __forceinline__ int prev(int rel) const {
+    if (NW == 1) return 31 - __builtin_clz(w0 & ((1u << rel) - 1u));
     const int wi = rel >> 5;
-#pragma unroll
-    for (int i = 0; i < NW; ++i)
-      if (wi == i) w[i] |= bit;
+    const uint32_t below = (rel & 31) ? ((1u << (rel & 31)) - 1u) : 0u;
+    const uint32_t c0 = wi == 0 ? (w0 & below) : w0;
+    const uint32_t c1 = wi == 1 ? (w1 & below) : (wi > 1 ? w1 : 0u);
+    const uint32_t c2 = NW > 2 ? (wi == 2 ? (w2 & below) : 0u) : 0u;
+    if (c2) return 64 + 31 - __builtin_clz(c2);
+    if (c1) return 32 + 31 - __builtin_clz(c1);
+    return 31 - __builtin_clz(c0);
   }
-}
-template <int NW>
-__device__ __forceinline__ void bm_clear(uint32_t* w, int rel) {
-  if (NW == 1) {
-    w[0] &= ~(1u << rel);
-  } else {
-    const uint32_t bit = ~(1u << (rel & 31));
+  // lowest set bit at or above rel (0 <= rel < 32 NW), or -1
+  __device__ __forceinline__ int next(int rel) const {
+    if (NW == 1) {
+      const uint32_t m = w0 & (0xFFFFFFFFu << rel);
+      return m ? __builtin_ctz(m) : -1;
+    }
     const int wi = rel >> 5;
-#pragma unroll
-    for (int i = 0; i < NW; ++i)
-      if (wi == i) w[i] &= bit;
+    const uint32_t above = 0xFFFFFFFFu << (rel & 31);
+    const uint32_t c0 = wi == 0 ? (w0 & above) : 0u;
+    const uint32_t c1 = wi == 1 ? (w1 & above) : (wi < 1 ? w1 : 0u);
+    const uint32_t c2 = NW > 2 ? (wi == 2 ? (w2 & above) : (wi < 2 ? w2 : 0u)) : 0u;
+    if (c0) return __builtin_ctz(c0);
+    if (c1) return 32 + __builtin_ctz(c1);
+    if (c2) return 64 + __builtin_ctz(c2);
+    return -1;
   }
-}
-// highest set bit strictly below rel (one always exists: the band's first row)
-template <int NW>
-__device__ __forceinline__ int bm_prev(const uint32_t* w, int rel) {
-  if (NW == 1) return 31 - __builtin_clz(w[0] & ((1u << rel) - 1u));
-  const int wi = rel >> 5;
-  const uint32_t below = (rel & 31) ? ((1u << (rel & 31)) - 1u) : 0u;
-  int r = -1;
-#pragma unroll
-  for (int i = 0; i < NW; ++i) {
-    const uint32_t c = wi == i ? (w[i] & below) : (wi > i ? w[i] : 0u);
-    if (c) r = 32 * i + 31 - __builtin_clz(c);
-  }
-  return r;
-}
+  __device__ __forceinline__ uint32_t word(int i) const { return i == 0 ? w0 : i == 1 ? w1 : w2; }
+};
 
 // --- the column's bitmap in LDS: bm[word][lane] ---
 // highest set row r with lo <= r < pos (lo a multiple of 32), or -1
@@ -214,9 +231,13 @@ __device__ __forceinline__ int lds_next(const uint32_t* bm, int lane, int pos, i
 }
 
 // g^2 of column `lane` in row `row`, recomputed from the row's record
+// (g < 2^16, so the square is one 24-bit multiply)
+__device__ __forceinline__ int sq16(int g) {
+  const uint32_t v = (uint32_t)g & 0xFFFFu;
+  return (int)(v * v);
+}
 __device__ __forceinline__ int gsq(const uint4* rec, int row, int lane, bool lane_ok) {
-  const int g = g_rec(rec[row], lane);
-  return lane_ok ? __mul24(g, g) : 0;
+  return lane_ok ? sq16(g_rec(rec[row], lane)) : 0;
 }
 
 // Merge the envelope of rows [lo, jb) with the envelope of rows [jb, hi)
@@ -290,15 +311,16 @@ __device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool la
 // packets of the tallest class come first so that the longest work starts
 // first.  Returns the class of packet p (or -1 past the end) and the item word
 // of wavefront kb's slot in it (or -1 when that slot is empty).
-__device__ __forceinline__ int packet_slot(const int32_t* counts, const int32_t* items, int p, int kb, int& word) {
+__device__ __forceinline__ int packet_slot(int mode, const int32_t* counts, const int32_t* items, int p, int kb,
+                                           int& word) {
   word = -1;
 #pragma unroll
   for (int c = kClasses - 1; c >= 0; --c) {
-    const int ipp = class_items(c);
+    const int ipp = class_items(mode, c);
     const int cnt = counts[c];
     const int np = (cnt + ipp - 1) / ipp;
     if (p < np) {
-      const int slot = kb / class_waves(c);
+      const int slot = kb / class_waves(mode, c);
       const int k = p * ipp + slot;
       if (slot < ipp && k < cnt) word = items[counts[8 + c] + k];
       return c;
@@ -333,7 +355,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   // this item's rows and bitmap words in LDS (rows_c is a multiple of 32)
   uint4* rec = rec_all + slot * rows_c;
   uint32_t* bm = bm_all + (slot * rows_c / 32) * 64;
-  float* part = part_all + kb * kEdtPartRows * 8;
+  float* part = part_all + (slot * rows_c / 32) * kEdtPartRows * 8;  // this item's blocks
 
   const int b0 = j * B, b1 = min(b0 + B, n);
 
@@ -363,37 +385,50 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   // ---- this band's lower envelope (sequential in u; row u's record is
   // broadcast from the lane that read it) ----
   if (SPATIAL == 0 && b0 < n) {
-    uint32_t w[NW];
-#pragma unroll
-    for (int i = 0; i < NW; ++i) w[i] = 0u;
-    int depth = 0, s1 = 0, s2 = 0, F1 = 0, F2 = 0;
+    BandBits<NW> w;
+    // Stack top s1 and the site below it, s2, with K = F + site^2.  The top
+    // is dominated by a new site u iff (Ku - K2)(s1 - s2) <= (K1 - K2)(u - s2)
+    // (the three-site test above in this form); the products are below 2^39
+    // and exact in FP64.  d12 = s1 - s2 and dK = K1 - K2 are kept in FP64
+    // while the stack is unchanged.
+    int depth = 0, s1 = 0, s2 = 0, K1 = 0, K2 = 0;
+    double d12 = 0.0, dK = 0.0;
     for (int u = b0; u < b1; ++u) {
-      const int k = u - b0;
-      const uint4 src = (NR == 1 || k < 64) ? rreg[0] : rreg[NR - 1];
-      const int kl = k & 63;
-      const uint4 ru = make_uint4(__builtin_amdgcn_readlane(src.x, kl), __builtin_amdgcn_readlane(src.y, kl),
-                                  __builtin_amdgcn_readlane(src.z, kl), __builtin_amdgcn_readlane(src.w, kl));
-      const int gu = g_rec(ru, lane);
-      const int Fu = lane_ok ? __mul24(gu, gu) : 0;
-      while (depth >= 2 && dominated(s2, F2, s1, F1, u, Fu)) {
-        bm_clear<NW>(w, s1 - b0);
+      uint4 ru;
+      if (NR == 1) {
+        const int k = u - b0;
+        ru = make_uint4(__builtin_amdgcn_readlane(rreg[0].x, k), __builtin_amdgcn_readlane(rreg[0].y, k),
+                        __builtin_amdgcn_readlane(rreg[0].z, k), __builtin_amdgcn_readlane(rreg[0].w, k));
+      } else {
+        ru = rec[u];  // one broadcast LDS read
+      }
+      const int Ku = (lane_ok ? sq16(g_rec(ru, lane)) : 0) + u * u;
+      bool pop = depth >= 2 && (double)(Ku - K2) * d12 <= dK * (double)(u - s2);
+      while (pop) {
+        w.clear(s1 - b0);
         --depth;
         s1 = s2;
-        F1 = F2;
+        K1 = K2;
+        pop = false;
         if (depth >= 2) {
-          s2 = b0 + bm_prev<NW>(w, s1 - b0);
-          F2 = gsq(rec, s2, lane, lane_ok);
+          s2 = b0 + w.prev(s1 - b0);
+          K2 = gsq(rec, s2, lane, lane_ok) + __mul24(s2, s2);
+          d12 = (double)(s1 - s2);
+          dK = (double)(K1 - K2);
+          pop = (double)(Ku - K2) * d12 <= dK * (double)(u - s2);
         }
       }
-      bm_set<NW>(w, u - b0);
+      w.set(u - b0);
       s2 = s1;
-      F2 = F1;
+      K2 = K1;
       s1 = u;
-      F1 = Fu;
+      K1 = Ku;
       ++depth;
+      d12 = (double)(s1 - s2);
+      dK = (double)(K1 - K2);
     }
 #pragma unroll
-    for (int i = 0; i < NW; ++i) bm[((b0 >> 5) + i) * 64 + lane] = w[i];
+    for (int i = 0; i < NW; ++i) bm[((b0 >> 5) + i) * 64 + lane] = w.word(i);
   }
   __syncthreads();
 
@@ -411,7 +446,6 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   // ---- final walk: e over the band's rows, sqrt(e) summed per patch ----
   const int pfirst = (y0 - 1 + max(b0, 1)) / P;  // first patch row this band meets
   float acc = 0.f;
-  int cur_pr = -1;
   int c = 0, Fc = 0, nx = -1, Fn = 0;
   if (SPATIAL == 0 && b0 < n) {
     c = lds_prev(bm, lane, b0 + 1, 0);
@@ -432,71 +466,76 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   }
   // the band's own bitmap word(s) stay in registers for the walk
   const int cw0 = b0 >> 5;
-  uint32_t cw[NW];
-#pragma unroll
-  for (int i = 0; i < NW; ++i) cw[i] = (SPATIAL == 0 && b0 < n) ? bm[(cw0 + i) * 64 + lane] : 0u;
+  BandBits<NW> cw;
+  if (SPATIAL == 0 && b0 < n) {
+    cw.w0 = bm[cw0 * 64 + lane];
+    if (NW > 1) cw.w1 = bm[(cw0 + 1) * 64 + lane];
+    if (NW > 2) cw.w2 = bm[(cw0 + 2) * 64 + lane];
+  }
   auto next_site = [&](int pos) -> int {  // lowest envelope row r with pos <= r < n, or -1
     if (pos >= n) return -1;
-    const int wi = pos >> 5;
-    if (wi >= cw0 && wi < cw0 + NW) {
-      uint32_t wd = 0u;
-#pragma unroll
-      for (int i = 0; i < NW; ++i)
-        if (wi == cw0 + i) wd = cw[i] & (0xFFFFFFFFu << (pos & 31));
-      if (wd) {
-        const int r = wi * 32 + __builtin_ctz(wd);
-        return r < n ? r : -1;
-      }
-#pragma unroll
-      for (int i = 0; i < NW; ++i)
-        if (wi < cw0 + i && cw[i]) {
-          const int r = (cw0 + i) * 32 + __builtin_ctz(cw[i]);
-          return r < n ? r : -1;
-        }
-      return lds_next(bm, lane, (cw0 + NW) * 32, n);
+    const int rel = pos - (cw0 << 5);
+    if (rel >= 0 && rel < 32 * NW) {
+      const int r = cw.next(rel);
+      if (r >= 0) return (cw0 << 5) + r < n ? (cw0 << 5) + r : -1;
+      return lds_next(bm, lane, (cw0 + NW) << 5, n);
     }
     return lds_next(bm, lane, pos, n);
   };
-  auto flush = [&](int pr, float v) {
+  auto flush = [&](int blk, int pr, float v) {
     v = lane_ok ? v : 0.f;
     const int inseg = lane % P;
     for (int o = 1; o < P; o <<= 1) {
       const float t = __shfl_down(v, o);
       if (inseg + o < P && lane + o < 64) v += t;
     }
-    if (inseg == 0 && lane_ok) part[(pr - pfirst) * 8 + lane / P] = v;
+    const int pf_blk = (y0 - 1 + max(blk * 32, 1)) / P;  // first patch row the block meets
+    if (inseg == 0 && lane_ok) part[(blk * kEdtPartRows + (pr - pf_blk)) * 8 + lane / P] = v;
   };
-  for (int u = b0; u < b1; ++u) {
+  // rows 0 and n-1 are padding and produce nothing: walk rows [ua, ub)
+  const int ua = max(b0, 1), ub = min(b1, n - 1);
+  int pr = (y0 - 1 + ua) / P;               // patch row of row u
+  int pr_next = (pr + 1) * P - (y0 - 1);    // first row of the next patch row
+  int blk = ua >> 5, blk_next = (blk + 1) * 32;
+  // site nx takes over from c at row u iff Fn - Fc <= (nx - c)(2u - c - nx)
+  int dF = Fn - Fc, dc = nx - c, sc = nx + c;
+  for (int u = ua; u < ub; ++u) {
+    if (u == pr_next || u == blk_next) {
+      flush(blk, pr, acc);
+      acc = 0.f;
+      if (u == pr_next) {
+        ++pr;
+        pr_next += P;
+      }
+      if (u == blk_next) {
+        ++blk;
+        blk_next += 32;
+      }
+    }
     int e;
     if (SPATIAL == 0) {
-      while (nx >= 0 && parab(nx, Fn, u) <= parab(c, Fc, u)) {
+      while (nx >= 0 && dF <= __mul24(dc, 2 * u - sc)) {
         c = nx;
         Fc = Fn;
         nx = next_site(c + 1);
         Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok) : 0;
+        dF = Fn - Fc;
+        dc = nx - c;
+        sc = nx + c;
       }
       e = __mul24(u - c, u - c) + Fc;
     } else {
       e = gsq(rec, u, lane, lane_ok) > 0 ? 1 : 0;
     }
-    if (u >= 1 && u <= n - 2) {
-      const int Y = y0 - 1 + u;
-      const int pr = Y / P;
-      if (pr != cur_pr) {
-        if (cur_pr >= 0) flush(cur_pr, acc);
-        cur_pr = pr;
-        acc = 0.f;
-      }
-      acc += SPATIAL == 0 ? __builtin_amdgcn_sqrtf((float)e) : (float)e;  // e >= 0 integer: no denormals
-      if (e_out != nullptr && lane_ok && col >= x0 && col <= x1)
-        e_out[(int64_t)gidx * fh * fw + (int64_t)Y * fw + col] = e;
-    }
+    acc += SPATIAL == 0 ? __builtin_amdgcn_sqrtf((float)e) : (float)e;  // e >= 0 integer: no denormals
+    if (e_out != nullptr && lane_ok && col >= x0 && col <= x1)
+      e_out[(int64_t)gidx * fh * fw + (int64_t)(y0 - 1 + u) * fw + col] = e;
   }
-  if (cur_pr >= 0) flush(cur_pr, acc);
+  if (ua < ub) flush(blk, pr, acc);
   __syncthreads();
 
   // ---- the strip's patch sums: each patch row adds the partial sums of the
-  // bands that meet it, in band order ----
+  // 32-row blocks that meet it, in block order ----
   if (has) {
     const int npc = SW / P;
     const int prbase = y0 / P;
@@ -508,9 +547,9 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
       const int pr = prbase + prl;
       const int ua = max(pr * P, y0) - y0 + 1, ub = min(pr * P + P - 1, y1) - y0 + 1;
       float v = 0.f;
-      for (int jj = ua / B; jj <= ub / B; ++jj) {
-        const int pf_j = (y0 - 1 + max(jj * B, 1)) / P;
-        v += part_all[((slot * K + jj) * kEdtPartRows + (pr - pf_j)) * 8 + q];
+      for (int kk = ua >> 5; kk <= ub >> 5; ++kk) {
+        const int pf_blk = (y0 - 1 + max(kk * 32, 1)) / P;
+        v += part[(kk * kEdtPartRows + (pr - pf_blk)) * 8 + q];
       }
       if (pc < gw) srow[pr * gw + pc] = v;
     }
@@ -518,17 +557,28 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   __syncthreads();
 }
 
+// Band layout for this launch (uniform over the grid): mode 1 when the work
+// in mode-0 wavefronts exceeds four times what the grid holds at once.
+__device__ __forceinline__ int pick_mode(const int32_t* counts, int mode_arg) {
+  if (mode_arg >= 0) return mode_arg;
+  int64_t waves0 = 0;
+  for (int c = 0; c < kClasses; ++c) waves0 += (int64_t)counts[c] * class_waves(0, c);
+  return waves0 > 4ll * gridDim.x * kEdtWaves ? 1 : 0;
+}
+
 template <int SPATIAL>  // 0: EDT, 1: AREA (pixel counts, no transform)
-__global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_edt(Batch b, Work wk,
-                                                                                                 int32_t* e_out) {
+__global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_edt(
+    const int32_t* __restrict__ counts, const int32_t* __restrict__ items, const MaskRec* __restrict__ mrec,
+    int32_t* e_out, int mode_arg) {
   __shared__ uint4 rec_all[kMaxRows];
   __shared__ uint32_t bm_all[kEdtBmWords * 64];
-  __shared__ float part_all[kEdtWaves * kEdtPartRows * 8];
+  __shared__ float part_all[kEdtBlocks * kEdtPartRows * 8];
 
   // the wavefront index is uniform; make that visible so row loops run on scalars
   const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int mode = pick_mode(counts, mode_arg);
   int total = 0;
-  for (int c = 0; c < kClasses; ++c) total += (wk.counts[c] + class_items(c) - 1) / class_items(c);
+  for (int c = 0; c < kClasses; ++c) total += (counts[c] + class_items(mode, c) - 1) / class_items(mode, c);
 
   // Packets are taken in a fixed stride (no shared queue).  Each wavefront
   // prefetches the record of its item in the next packet into one VGPR per
@@ -536,25 +586,26 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
   int p = blockIdx.x;
   if (p >= total) return;
   int word = -1;
-  int cls = packet_slot(wk.counts, wk.items, p, kb, word);
+  int cls = packet_slot(mode, counts, items, p, kb, word);
   uint32_t pf = 0u;
-  if (word >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(wk.mrec + (word >> kItemStripBits))[lane];
+  if (word >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(mrec + (word >> kItemStripBits))[lane];
 
   for (; p < total; p += gridDim.x) {
     int ncls = -1, nword = -1;
     uint32_t npf = pf;
     auto prefetch = [&]() {
       if (p + (int)gridDim.x < total) {
-        ncls = packet_slot(wk.counts, wk.items, p + gridDim.x, kb, nword);
-        if (nword >= 0 && lane < 16) npf = reinterpret_cast<const uint32_t*>(wk.mrec + (nword >> kItemStripBits))[lane];
+        ncls = packet_slot(mode, counts, items, p + gridDim.x, kb, nword);
+        if (nword >= 0 && lane < 16) npf = reinterpret_cast<const uint32_t*>(mrec + (nword >> kItemStripBits))[lane];
       }
     };
-    if (cls == kClasses - 1)
-      edt_packet<SPATIAL, class_band(kClasses - 1)>(class_waves(cls), pf, word, rec_all, bm_all, part_all, lane, kb,
-                                                    e_out, prefetch);
+    const int B = class_band(mode, cls), K = class_waves(mode, cls);
+    if (B == 96)
+      edt_packet<SPATIAL, 96>(K, pf, word, rec_all, bm_all, part_all, lane, kb, e_out, prefetch);
+    else if (B == 64)
+      edt_packet<SPATIAL, 64>(K, pf, word, rec_all, bm_all, part_all, lane, kb, e_out, prefetch);
     else
-      edt_packet<SPATIAL, class_band(0)>(class_waves(cls), pf, word, rec_all, bm_all, part_all, lane, kb, e_out,
-                                         prefetch);
+      edt_packet<SPATIAL, 32>(K, pf, word, rec_all, bm_all, part_all, lane, kb, e_out, prefetch);
     cls = ncls;
     word = nword;
     pf = npf;
@@ -578,14 +629,14 @@ void edt_prepare() {
   });
 }
 
-void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st) {
+void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode) {
   edt_prepare();
   const int sp = b.spatial == 0 ? 0 : 1;
   const int grid = num_cus * g_edt_per_cu[sp];
   if (sp == 0)
-    hipLaunchKernelGGL(k_edt<0>, dim3(grid), dim3(kEdtWaves * 64), 0, st, b, w, e_out);
+    hipLaunchKernelGGL(k_edt<0>, dim3(grid), dim3(kEdtWaves * 64), 0, st, w.counts, w.items, w.mrec, e_out, mode);
   else
-    hipLaunchKernelGGL(k_edt<1>, dim3(grid), dim3(kEdtWaves * 64), 0, st, b, w, e_out);
+    hipLaunchKernelGGL(k_edt<1>, dim3(grid), dim3(kEdtWaves * 64), 0, st, w.counts, w.items, w.mrec, e_out, mode);
 }
 
 }  // namespace disc
