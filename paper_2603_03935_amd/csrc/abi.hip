@@ -147,7 +147,6 @@ Layout make_layout(const Shape& s) {
   L.mask_frame = take(4 * (size_t)s.M);
   L.tiles = take(16 * (size_t)s.n_tiles);
   L.dyn = take(16);
-  L.frame_ctr = take(4 * (size_t)s.n_frames);
   L.staged_end = off;
   L.bbox = take(16 * (size_t)s.M);
   L.area = take(4 * (size_t)s.M);
@@ -163,7 +162,8 @@ Layout make_layout(const Shape& s) {
   L.Z = take(4 * (size_t)s.M);
   L.mstat = take(4 * (size_t)s.M);
   L.X = take((s.gemm_bf16 ? 2 : 4) * (size_t)s.M * s.C);
-  L.ssq = take(4 * (size_t)s.M * 8);
+  L.ppart = take(s.pool_split > 1 ? 4 * (size_t)s.n_tiles * s.kgroups * 64 * 64 : 0);
+  L.qpart = take(s.proj_split > 1 ? 4 * (size_t)((s.C + kProjKG - 1) / kProjKG) * s.M * s.E : 0);
   L.tkp = take(s.gemm_bf16 ? (size_t)s.tkp_elems * s.tkp_esize : 0);
   L.total = off;
   return L;
@@ -266,7 +266,6 @@ Work work_ptrs(char* base, const Layout& L) {
   w.mrec = reinterpret_cast<MaskRec*>(base + L.mrec);
   w.items = reinterpret_cast<int32_t*>(base + L.items);
   w.counts = reinterpret_cast<int32_t*>(base + L.counts);
-  w.frame_ctr = reinterpret_cast<uint32_t*>(base + L.frame_ctr);
   w.psum = reinterpret_cast<float*>(base + L.psum);
   w.mean = reinterpret_cast<float*>(base + L.mean);
   w.r = reinterpret_cast<float*>(base + L.r);
@@ -275,7 +274,8 @@ Work work_ptrs(char* base, const Layout& L) {
   w.Z = reinterpret_cast<float*>(base + L.Z);
   w.mstat = reinterpret_cast<int32_t*>(base + L.mstat);
   w.X = base + L.X;
-  w.ssq = reinterpret_cast<float*>(base + L.ssq);
+  w.ppart = reinterpret_cast<float*>(base + L.ppart);
+  w.qpart = reinterpret_cast<float*>(base + L.qpart);
   w.tkp = base + L.tkp;
   return w;
 }
@@ -326,7 +326,7 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
     sumMGs += (int64_t)f.m * d.Gs;
     tkp += (int64_t)round_up(d.G, 8) * C;
     gmax = std::max(gmax, d.G);
-    nchunk = std::max(nchunk, (d.G + 63) / 64);
+    nchunk = std::max(nchunk, stat_nchunk(d.G));
     item_cap += (int64_t)f.m * ((f.w + strip_width(f.patch) - 1) / strip_width(f.patch) + 1);
   }
   s.M = M;
@@ -338,7 +338,17 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
   s.nchunk = nchunk;
   s.item_cap = (int)std::min<int64_t>(item_cap, INT32_MAX / 2);
   s.n_tiles = (int)p.tiles.size();
+  choose_splits(s);
   p.L = make_layout(s);
+}
+
+void choose_splits(Shape& s) {
+  s.kgroups = std::max(1, (s.gmax + kPoolKG - 1) / kPoolKG);
+  const int pool_tiles = std::max(1, s.n_tiles);
+  s.pool_split = pool_tiles >= kTargetWGs ? 1 : std::min(s.kgroups, (kTargetWGs + pool_tiles - 1) / pool_tiles);
+  const int qgroups = std::max(1, (s.C + kProjKG - 1) / kProjKG);
+  const int64_t proj_tiles = std::max<int64_t>(1, (s.M + 31) / 32 * (s.E / 128));
+  s.proj_split = proj_tiles >= kTargetWGs ? 1 : (int)std::min<int64_t>(qgroups, (kTargetWGs + proj_tiles - 1) / proj_tiles);
 }
 
 void stage_host(const Plan& p, char* host, char* dev) {
@@ -349,7 +359,6 @@ void stage_host(const Plan& p, char* host, char* dev) {
   if (!p.tiles.empty()) std::memcpy(host + p.L.tiles, p.tiles.data(), 16 * p.tiles.size());
   const int32_t dyn[4] = {p.shape.n_frames, (int32_t)p.shape.M, p.shape.n_tiles, 0};
   std::memcpy(host + p.L.dyn, dyn, sizeof dyn);
-  std::memset(host + p.L.frame_ctr, 0, 4 * (size_t)p.shape.n_frames);
 }
 
 Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int distinct) {
@@ -367,6 +376,10 @@ Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int disti
   b.distinct = distinct;
   b.nchunk = p.shape.nchunk;
   b.item_cap = p.shape.item_cap;
+  b.n_tiles = p.shape.n_tiles;
+  b.kgroups = p.shape.kgroups;
+  b.pool_split = p.shape.pool_split;
+  b.proj_split = p.shape.proj_split;
   return b;
 }
 
@@ -505,8 +518,8 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   }
   { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st, o.edt_layout); }
   { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); }
-  { StageTimer t(sid < 0 ? -1 : ST_POOL, st); launch_pool(b, w, tiles, p.shape.n_tiles, st); }
-  { StageTimer t(sid < 0 ? -1 : ST_PROJ, st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, w.ssq, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_POOL, st); launch_pool(b, w, tiles, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_PROJ, st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, st); }
 }
 
 }  // namespace host
@@ -742,8 +755,8 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32
   const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
   launch_user_weights(b, w, wts, cx.st);
   if (p.shape.gemm_bf16) launch_token_stats(b, w, p.shape.gmax, 0, 1, cx.st);
-  launch_pool(b, w, tiles, p.shape.n_tiles, cx.st);
-  launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, w.ssq, cx.st);
+  launch_pool(b, w, tiles, cx.st);
+  launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, cx.st);
   if ((st = check_launch(who))) return st;
   return ok();
 }

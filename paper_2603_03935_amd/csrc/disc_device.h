@@ -34,6 +34,17 @@ constexpr int kMinPatch = 8;
 constexpr int kMaxPatch = 64;
 constexpr int kItemStripBits = 8;   // item = (mask << 8) | strip
 constexpr int kMaxC = 2048;
+// Frame mean: partial channel sums over chunks of stat_chunk(G) tokens (a
+// multiple of 32 chosen from G alone, so at most 64 chunks per frame), added
+// in chunk order.
+__host__ __device__ inline int stat_chunk(int G) { return 32 * ((G + 32 * 64 - 1) / (32 * 64)); }
+__host__ __device__ inline int stat_nchunk(int G) { return (G + stat_chunk(G) - 1) / stat_chunk(G); }
+// The GEMMs accumulate K in fixed groups (pooling: 256 patches, projection:
+// 256 channels) and add the group sums in order, so splitting K over several
+// workgroups (for small batches) gives the same bits as one pass.
+constexpr int kPoolKG = 256;
+constexpr int kProjKG = 256;
+constexpr int kTargetWGs = 512;  // workgroups that fill the 256 CUs twice
 
 __host__ __device__ inline int strip_width(int patch) { return 64 - (64 % patch); }
 
@@ -87,6 +98,9 @@ struct Batch {
   int32_t spatial, distinct;
   int32_t nchunk;             // token-statistics chunks per frame (capacity)
   int32_t item_cap;           // capacity of each class's work list
+  int32_t n_tiles;            // pooling tiles (capacity)
+  int32_t kgroups;            // pooling K groups of the largest frame
+  int32_t pool_split, proj_split;  // workgroups sharing one GEMM tile's K range
 };
 
 // Workspace pointers (device).
@@ -97,7 +111,6 @@ struct Work {
   MaskRec* mrec;       // [M]
   int32_t* items;      // [item_cap] (mask << 8) | strip, classes back to back
   int32_t* counts;     // [kClasses] items per class, then [kClasses] class bases in items
-  uint32_t* frame_ctr; // [F] last-block tickets of the token statistics
   float* psum;         // [F][nchunk][C]
   float* mean;         // [F][C]
   float* r;            // [sum G]
@@ -106,7 +119,8 @@ struct Work {
   float* Z;            // [M] weight sums
   int32_t* mstat;      // [M] 0 ok, 1 empty
   void* X;             // [M][C] pooled features in the GEMM dtype
-  float* ssq;          // [M][E/128] partial sums of squares of the projected rows
+  float* ppart;        // pooling group sums [tile][kgroups][64*64] (split K only)
+  float* qpart;        // projection group sums [C/256][M][E] (split K only)
   void* tkp;           // k-packed tokens [sum ceil(G/8)][C][8] (BF16 bits, or e4m3 codes for FP8 tokens)
 };
 
@@ -118,8 +132,8 @@ void edt_prepare();
 // want_r: residual norms (needs the mean); pack: k-packed token copy for the BF16 pooling GEMM
 void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
-void launch_pool(const Batch& b, const Work& w, const int4* tiles, int n_tiles, hipStream_t st);
-void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, float* ssq, hipStream_t st);
+void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st);
+void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st);
 // stage helpers
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 void launch_pack(const uint8_t* u8, int m, int h, int w, uint64_t* bits, hipStream_t st);

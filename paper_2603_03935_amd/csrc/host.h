@@ -12,8 +12,8 @@ namespace disc {
 namespace host {
 
 struct Layout {
-  size_t frames, mask_frame, tiles, dyn, frame_ctr, staged_end;  // staged region (uploaded from the host)
-  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, s, W, Z, mstat, X, ssq, tkp, total;
+  size_t frames, mask_frame, tiles, dyn, staged_end;  // staged region (uploaded from the host)
+  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, s, W, Z, mstat, X, ppart, qpart, tkp, total;
 };
 
 struct Shape {
@@ -22,7 +22,13 @@ struct Shape {
   int C = 0, E = 0, gmax = 0, nchunk = 1, item_cap = 1, n_tiles = 0, gemm_bf16 = 0;
   int64_t tkp_elems = 0;  // sum over frames of ceil(G/8)*8*C (k-packed tokens, BF16 GEMM only)
   int tkp_esize = 2;      // bytes per k-packed element: 1 for FP8 tokens, else 2
+  int kgroups = 1;        // pooling K groups of the largest frame
+  int pool_split = 1, proj_split = 1;
 };
+
+// Split K of the pooling / projection GEMMs when their tiles alone would not
+// fill the GPU (depends only on the capacity shape).
+void choose_splits(Shape& s);
 
 struct FrameIn {
   const void* tokens = nullptr;

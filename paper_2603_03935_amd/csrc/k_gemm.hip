@@ -2,10 +2,13 @@
 // (arXiv 2603.03935, Sec. III-C), on MFMA with FP32 accumulation:
 //   pooling     X_f = W_f (m_f x G_f) . T_f (G_f x C) / Z, one GEMM per frame
 //               (ragged batch: each frame has its own token map);
-//   projection  Y = X (M x C) . P (C x E) over all masks of the batch; the
-//               epilogue also emits each row's partial sum of squares per
-//               128-column tile, and a row pass then applies the L2
-//               normalisation (fixed-order sum of the partials).
+//   projection  Y = X (M x C) . P (C x E) over all masks of the batch, then
+//               a row pass applies the L2 normalisation.
+// K is accumulated in fixed groups (kPoolKG patches, kProjKG channels) whose
+// sums are added in group order.  When a batch has too few tiles to fill the
+// GPU, a tile's K groups are spread over several workgroups that store their
+// group sums, and a second pass adds them in the same order: the result is the
+// same bits either way, so a mask's embedding does not depend on its batch.
 // BF16 operands use v_mfma_f32_32x32x16_bf16, FP32 operands
 // v_mfma_f32_32x32x2f32.  FP8 (e4m3fn) tokens are widened exactly to BF16
 // while staged into LDS; their per-token scales are already in the weights.
@@ -85,10 +88,55 @@ __device__ __forceinline__ uint16_t tok_bf16(const void* base, int64_t off) {
   return e4m3_to_bf16(reinterpret_cast<const uint8_t*>(base)[off]);
 }
 
+// K range [kbeg, kend) of a tile: the union of its masks' patch-row ranges
+// (rows of patches outside every mask's box hold zero weights for all of them).
+__device__ __forceinline__ void tile_krange(const Work& wk, const FrameDesc& fd, int m0, int mrows, int tid,
+                                            int* kmin_sh, int* kmax_sh, int& kbeg, int& kend) {
+  if (tid == 0) {
+    *kmin_sh = INT32_MAX;
+    *kmax_sh = 0;
+  }
+  __syncthreads();
+  if (tid < mrows) {
+    const int4 bb = wk.bbox[fd.mask_base + m0 + tid];
+    if (bb.x <= bb.y) {
+      atomicMin(kmin_sh, (bb.x / fd.patch) * fd.gw);
+      atomicMax(kmax_sh, (bb.y / fd.patch + 1) * fd.gw);
+    }
+  }
+  __syncthreads();
+  kbeg = (*kmin_sh / PBK) * PBK;
+  kend = min(*kmax_sh, fd.G);
+}
+
+// divide by Z, store X (GEMM dtype) and the optional FP32 pooled output
+template <int BF16>
+__device__ __forceinline__ void pool_store(const Work& wk, const FrameDesc& fd, int m0, int n0, int C, int lane, int wm,
+                                           int wn, const floatx16& acc) {
+  const int col = n0 + 32 * wn + (lane & 31);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int r = 32 * wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int mi = m0 + r;
+    if (mi >= fd.m) continue;
+    const int g = fd.mask_base + mi;
+    const float Z = wk.Z[g];
+    const float val = (wk.mstat[g] == 0 && Z > 0.f) ? acc[v] / Z : 0.f;
+    if (BF16)
+      reinterpret_cast<uint16_t*>(wk.X)[(int64_t)g * C + col] = f2bf(val);
+    else
+      reinterpret_cast<float*>(wk.X)[(int64_t)g * C + col] = val;
+    if (fd.pooled) fd.pooled[(int64_t)mi * C + col] = val;
+  }
+}
+
+// grid: tiles x S; workgroup (tile, s) takes the s-th share of the tile's K groups
 template <int BF16, int TOK>
 __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tiles) {
-  if ((int)blockIdx.x >= b.dyn[2]) return;
-  const int4 t = tiles[blockIdx.x];
+  const int S = b.pool_split;
+  const int tix = blockIdx.x / S, sidx = blockIdx.x - tix * S;
+  if (tix >= b.dyn[2]) return;
+  const int4 t = tiles[tix];
   const FrameDesc fd = b.frames[t.x];
   const int m0 = t.y, n0 = t.z, C = b.C;
   const int mrows = min(PBM, fd.m - m0);
@@ -101,23 +149,15 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   __shared__ float As32[BF16 ? 1 : PBM * (PBK + 1)];
   __shared__ __attribute__((aligned(16))) float Bs32[BF16 ? 1 : PBK * PBN];
 
-  if (tid == 0) {
-    kmin_sh = INT32_MAX;
-    kmax_sh = 0;
-  }
-  __syncthreads();
-  if (tid < mrows) {
-    const int4 bb = wk.bbox[fd.mask_base + m0 + tid];
-    if (bb.x <= bb.y) {
-      atomicMin(&kmin_sh, (bb.x / fd.patch) * fd.gw);
-      atomicMax(&kmax_sh, (bb.y / fd.patch + 1) * fd.gw);
-    }
-  }
-  __syncthreads();
-  const int kbeg = (kmin_sh / PBK) * PBK, kend = min(kmax_sh, G);
+  int kbeg, kend;
+  tile_krange(wk, fd, m0, mrows, tid, &kmin_sh, &kmax_sh, kbeg, kend);
+  const int gbeg = kbeg / kPoolKG, gend = kbeg < kend ? (kend + kPoolKG - 1) / kPoolKG : gbeg;
+  const int per = (gend - gbeg + S - 1) / S;
+  const int ga = gbeg + sidx * per, gb = min(gend, ga + per);
+  const int kstart = max(kbeg, ga * kPoolKG), kstop = min(kend, gb * kPoolKG);
 
-  floatx16 acc;
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  const floatx16 zero16 = {};
+  floatx16 total = zero16, acc = zero16;
 
   const int64_t wrow0 = fd.w_base + (int64_t)m0 * fd.Gs;
   const int ar = tid >> 2, ak = (tid & 3) * 8;        // A: row, first k of 8
@@ -176,13 +216,30 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
       *reinterpret_cast<float4*>(&Bs32[bk32 * PBN + bn32 + 4]) = make_float4(rb32[4], rb32[5], rb32[6], rb32[7]);
     }
   };
+  // a finished K group: add it to the running total, or store it for the reduce pass
+  float* gpart = wk.ppart + ((int64_t)tix * b.kgroups) * (PBM * PBN) + tid * 16;
+  auto fold = [&](int grp) {
+    if (S == 1) {
+      total += acc;
+    } else {
+      float4* dst = reinterpret_cast<float4*>(gpart + (int64_t)grp * (PBM * PBN));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dst[i] = make_float4(acc[4 * i], acc[4 * i + 1], acc[4 * i + 2], acc[4 * i + 3]);
+    }
+    acc = zero16;
+  };
 
   const int lr = lane & 31, lk = lane >> 5;
-  if (kbeg < kend) fetch(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += PBK) {
+  int cur = kstart / kPoolKG;
+  if (kstart < kstop) fetch(kstart);
+  for (int k0 = kstart; k0 < kstop; k0 += PBK) {
+    if (k0 / kPoolKG != cur) {
+      fold(cur);
+      cur = k0 / kPoolKG;
+    }
     stage();
     __syncthreads();
-    if (k0 + PBK < kend) fetch(k0 + PBK);
+    if (k0 + PBK < kstop) fetch(k0 + PBK);
     if (BF16) {
 #pragma unroll
       for (int kk = 0; kk < PBK; kk += 16) {
@@ -200,65 +257,86 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
     }
     __syncthreads();
   }
-
-  // ---- epilogue: divide by Z, store X (GEMM dtype) and the optional FP32 pooled output ----
-  const int col = n0 + 32 * wn + (lane & 31);
-  for (int v = 0; v < 16; ++v) {
-    const int r = 32 * wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-    const int mi = m0 + r;
-    if (mi >= fd.m) continue;
-    const int g = fd.mask_base + mi;
-    const float Z = wk.Z[g];
-    const float val = (wk.mstat[g] == 0 && Z > 0.f) ? acc[v] / Z : 0.f;
-    if (BF16)
-      reinterpret_cast<uint16_t*>(wk.X)[(int64_t)g * C + col] = f2bf(val);
-    else
-      reinterpret_cast<float*>(wk.X)[(int64_t)g * C + col] = val;
-    if (fd.pooled) fd.pooled[(int64_t)mi * C + col] = val;
-  }
+  if (kstart < kstop) fold(cur);
+  if (S == 1) pool_store<BF16>(wk, fd, m0, n0, C, lane, wm, wn, total);
 }
 
-void launch_pool(const Batch& b, const Work& w, const int4* tiles, int n_tiles, hipStream_t st) {
-  if (n_tiles <= 0) return;
-  const dim3 grid(n_tiles), block(256);
+// split K: add each tile's stored group sums in group order, then store
+template <int BF16>
+__global__ __launch_bounds__(256) void k_pool_reduce(Batch b, Work wk, const int4* tiles) {
+  const int tix = blockIdx.x;
+  if (tix >= b.dyn[2]) return;
+  const int4 t = tiles[tix];
+  const FrameDesc fd = b.frames[t.x];
+  const int m0 = t.y, n0 = t.z;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
+  __shared__ int kmin_sh, kmax_sh;
+  int kbeg, kend;
+  tile_krange(wk, fd, m0, min(PBM, fd.m - m0), tid, &kmin_sh, &kmax_sh, kbeg, kend);
+  const int gbeg = kbeg / kPoolKG, gend = kbeg < kend ? (kend + kPoolKG - 1) / kPoolKG : gbeg;
+  floatx16 total = {};
+  const float* gpart = wk.ppart + ((int64_t)tix * b.kgroups) * (PBM * PBN) + tid * 16;
+  for (int grp = gbeg; grp < gend; ++grp) {
+    const float4* src = reinterpret_cast<const float4*>(gpart + (int64_t)grp * (PBM * PBN));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float4 v = src[i];
+      total[4 * i] += v.x;
+      total[4 * i + 1] += v.y;
+      total[4 * i + 2] += v.z;
+      total[4 * i + 3] += v.w;
+    }
+  }
+  pool_store<BF16>(wk, fd, m0, n0, b.C, lane, wm, wn, total);
+}
+
+void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st) {
+  if (b.n_tiles <= 0) return;
+  const dim3 grid(b.n_tiles * b.pool_split), block(256);
   if (b.gemm_bf16) {
     if (b.tok_dtype == 0) hipLaunchKernelGGL((k_pool<1, 0>), grid, block, 0, st, b, w, tiles);
     else if (b.tok_dtype == 1) hipLaunchKernelGGL((k_pool<1, 1>), grid, block, 0, st, b, w, tiles);
     else hipLaunchKernelGGL((k_pool<1, 2>), grid, block, 0, st, b, w, tiles);
+    if (b.pool_split > 1) hipLaunchKernelGGL((k_pool_reduce<1>), dim3(b.n_tiles), block, 0, st, b, w, tiles);
   } else {
     if (b.tok_dtype == 0) hipLaunchKernelGGL((k_pool<0, 0>), grid, block, 0, st, b, w, tiles);
     else if (b.tok_dtype == 1) hipLaunchKernelGGL((k_pool<0, 1>), grid, block, 0, st, b, w, tiles);
     else hipLaunchKernelGGL((k_pool<0, 2>), grid, block, 0, st, b, w, tiles);
+    if (b.pool_split > 1) hipLaunchKernelGGL((k_pool_reduce<0>), dim3(b.n_tiles), block, 0, st, b, w, tiles);
   }
 }
 
 // ---------------------------------------------------------------------------
-// projection: tile 32 rows x 128 columns (4 wavefronts of 32 x 32), K = C.
-// Writes the unnormalised rows and, per (row, 128-column tile), the partial
-// sum of squares; k_norm then normalises each row (fixed-order sum of the
-// partials) and sets the status.
+// projection: tile 32 rows x 128 columns (4 wavefronts of 32 x 32), K = C in
+// groups of kProjKG channels.  grid: (row tiles x S, E / 128).  With S = 1 the
+// workgroup writes the unnormalised rows; otherwise each writes its groups'
+// sums to qpart and k_norm adds them in group order.
 // ---------------------------------------------------------------------------
 template <int BF16, int PBF16>
-__global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj, float* ssq) {
+__global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj) {
   constexpr int BK = BF16 ? 32 : 16;
   constexpr int AS = BK + 8;
-  const int C = b.C, E = b.E, nct = E / 128;
+  const int C = b.C, E = b.E, S = b.proj_split;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int gbase = blockIdx.x * 32, c0 = blockIdx.y * 128;
+  const int rt = blockIdx.x / S, sidx = blockIdx.x - rt * S;
+  const int gbase = rt * 32, c0 = blockIdx.y * 128;
   const int M = b.dyn[1];
   if (gbase >= M) return;
+  const int ngr = (C + kProjKG - 1) / kProjKG;
+  const int per = (ngr + S - 1) / S;
+  const int ga = sidx * per, gb = min(ngr, ga + per);
+  const int kstart = ga * kProjKG, kstop = min(C, gb * kProjKG);
   __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? 32 * AS : 1];
   __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? 128 * AS : 1];
   __shared__ float As32[BF16 ? 1 : 32 * (BK + 1)];
   __shared__ __attribute__((aligned(16))) float Bs32[BF16 ? 1 : BK * 128];
-  __shared__ float red[4][32];
 
-  floatx16 acc;
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  const floatx16 zero16 = {};
+  floatx16 total = zero16, acc = zero16;
 
   // A loaders: BF16 32 rows x 32 k (4 per thread), FP32 32 rows x 16 k (2 per thread)
   const int ar = tid >> 3, ak = BF16 ? (tid & 7) * 4 : (tid & 7) * 2;
-  const int ga = gbase + ar;
+  const int ga_row = gbase + ar;
   // B loaders: BF16 k-packed (column tid & 127, 16 k at 16 * (tid >> 7)); FP32 [k][col] (k tid >> 4, 8 cols)
   const int bc = tid & 127, bkk = (tid >> 7) * 16;
   const int bk32 = tid >> 4, bc32 = (tid & 15) * 8;
@@ -269,16 +347,16 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
 
   auto fetch = [&](int k0) {
     if (BF16) {
-      ra16 = ga < M ? *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(wk.X) + (int64_t)ga * C + k0 + ak)
-                      : make_uint2(0, 0);
+      ra16 = ga_row < M ? *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(wk.X) + (int64_t)ga_row * C + k0 + ak)
+                        : make_uint2(0, 0);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int64_t off = (int64_t)(k0 + bkk + j) * E + c0 + bc;
         rb16[j] = PBF16 ? reinterpret_cast<const uint16_t*>(proj)[off] : f2bf(reinterpret_cast<const float*>(proj)[off]);
       }
     } else {
-      ra32 = ga < M ? *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(wk.X) + (int64_t)ga * C + k0 + ak)
-                      : make_float2(0.f, 0.f);
+      ra32 = ga_row < M ? *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(wk.X) + (int64_t)ga_row * C + k0 + ak)
+                        : make_float2(0.f, 0.f);
       const int64_t off = (int64_t)(k0 + bk32) * E + c0 + bc32;
       if (PBF16) {
         const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(proj) + off);
@@ -309,13 +387,31 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
       *reinterpret_cast<float4*>(&Bs32[bk32 * 128 + bc32 + 4]) = make_float4(rb32[4], rb32[5], rb32[6], rb32[7]);
     }
   };
-
   const int lr = lane & 31, lk = lane >> 5;
-  fetch(0);
-  for (int k0 = 0; k0 < C; k0 += BK) {
+  const int col = c0 + 32 * wv + lr;
+  auto fold = [&](int grp) {
+    if (S == 1) {
+      total += acc;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int g = gbase + 8 * (v >> 2) + 4 * lk + (v & 3);
+        if (g < M) wk.qpart[((int64_t)grp * b.M + g) * E + col] = acc[v];
+      }
+    }
+    acc = zero16;
+  };
+
+  int cur = kstart / kProjKG;
+  if (kstart < kstop) fetch(kstart);
+  for (int k0 = kstart; k0 < kstop; k0 += BK) {
+    if (k0 / kProjKG != cur) {
+      fold(cur);
+      cur = k0 / kProjKG;
+    }
     stage();
     __syncthreads();
-    if (k0 + BK < C) fetch(k0 + BK);
+    if (k0 + BK < kstop) fetch(k0 + BK);
     if (BF16) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 16) {
@@ -333,65 +429,76 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
     }
     __syncthreads();
   }
-
-  // ---- store unnormalised rows and per-tile sums of squares ----
-  float ss[16];
+  if (kstart < kstop) fold(cur);
+  if (S > 1) return;
+  // ---- store the unnormalised rows ----
+#pragma unroll
   for (int v = 0; v < 16; ++v) {
-    float a = acc[v] * acc[v];
-    for (int o = 1; o < 32; o <<= 1) a += __shfl_xor(a, o);
-    ss[v] = a;
-  }
-  if (lr == 0)
-    for (int v = 0; v < 16; ++v) red[wv][8 * (v >> 2) + 4 * lk + (v & 3)] = ss[v];
-  const int col = c0 + 32 * wv + lr;
-  for (int v = 0; v < 16; ++v) {
-    const int r = 8 * (v >> 2) + 4 * lk + (v & 3);
-    const int g = gbase + r;
+    const int g = gbase + 8 * (v >> 2) + 4 * lk + (v & 3);
     if (g >= M) continue;
     const FrameDesc& fd = b.frames[b.mask_frame[g]];
-    fd.out[(int64_t)(g - fd.mask_base) * E + col] = acc[v];
+    fd.out[(int64_t)(g - fd.mask_base) * E + col] = total[v];
   }
-  __syncthreads();
-  if (tid < 32 && gbase + tid < M)
-    ssq[(int64_t)(gbase + tid) * nct + blockIdx.y] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
-// one wavefront per row: fixed-order sum of the partial squares, scale, status
-__global__ __launch_bounds__(256) void k_norm(Batch b, Work wk, const float* ssq) {
+// One wavefront per row: (split K: add the group sums in group order and)
+// normalise.  The sum of squares has a fixed order: each lane sums its columns
+// lane*4 + 256 i in order, then a fixed butterfly over the lanes.
+__global__ __launch_bounds__(256) void k_norm(Batch b, Work wk) {
   const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (g >= b.dyn[1]) return;
-  const int E = b.E, nct = E / 128;
-  float tot = 0.f;
-  for (int t = 0; t < nct; ++t) tot += ssq[(int64_t)g * nct + t];
+  const int E = b.E, S = b.proj_split;
+  const int ngr = (b.C + kProjKG - 1) / kProjKG;
   const FrameDesc& fd = b.frames[b.mask_frame[g]];
   const int i = g - fd.mask_base;
-  const int st_in = wk.mstat[g];
-  const bool zero = st_in != 0 || !(tot > 0.f);
-  const float inv = zero ? 0.f : 1.0f / __builtin_sqrtf(tot);
   float* o = fd.out + (int64_t)i * E;
-  for (int c = lane * 4; c < E; c += 256) {
-    float4 v = *reinterpret_cast<float4*>(o + c);
-    v.x *= inv;
-    v.y *= inv;
-    v.z *= inv;
-    v.w *= inv;
-    *reinterpret_cast<float4*>(o + c) = v;
+  float4 v[4];  // E <= 1024: at most 4 chunks of 4 columns per lane
+  float ss = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = lane * 4 + 256 * k;
+    v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c >= E) continue;
+    if (S == 1) {
+      v[k] = *reinterpret_cast<const float4*>(o + c);
+    } else {
+      for (int grp = 0; grp < ngr; ++grp) {
+        const float4 q = *reinterpret_cast<const float4*>(wk.qpart + ((int64_t)grp * b.M + g) * E + c);
+        v[k].x += q.x;
+        v[k].y += q.y;
+        v[k].z += q.z;
+        v[k].w += q.w;
+      }
+    }
+    ss += v[k].x * v[k].x;
+    ss += v[k].y * v[k].y;
+    ss += v[k].z * v[k].z;
+    ss += v[k].w * v[k].w;
   }
-  if (lane == 0 && fd.status) fd.status[i] = st_in != 0 ? 1 : (tot > 0.f ? 0 : 2);
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+  const int st_in = wk.mstat[g];
+  const bool zero = st_in != 0 || !(ss > 0.f);
+  const float inv = zero ? 0.f : 1.0f / __builtin_sqrtf(ss);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = lane * 4 + 256 * k;
+    if (c < E) *reinterpret_cast<float4*>(o + c) = make_float4(v[k].x * inv, v[k].y * inv, v[k].z * inv, v[k].w * inv);
+  }
+  if (lane == 0 && fd.status) fd.status[i] = st_in != 0 ? 1 : (ss > 0.f ? 0 : 2);
 }
 
-void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, float* ssq, hipStream_t st) {
+void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st) {
   if (b.M <= 0) return;
-  const dim3 grid((b.M + 31) / 32, b.E / 128), block(256);
+  const dim3 grid((b.M + 31) / 32 * b.proj_split, b.E / 128), block(256);
   if (b.gemm_bf16) {
-    if (proj_bf16) hipLaunchKernelGGL((k_proj<1, 1>), grid, block, 0, st, b, w, proj, ssq);
-    else hipLaunchKernelGGL((k_proj<1, 0>), grid, block, 0, st, b, w, proj, ssq);
+    if (proj_bf16) hipLaunchKernelGGL((k_proj<1, 1>), grid, block, 0, st, b, w, proj);
+    else hipLaunchKernelGGL((k_proj<1, 0>), grid, block, 0, st, b, w, proj);
   } else {
-    if (proj_bf16) hipLaunchKernelGGL((k_proj<0, 1>), grid, block, 0, st, b, w, proj, ssq);
-    else hipLaunchKernelGGL((k_proj<0, 0>), grid, block, 0, st, b, w, proj, ssq);
+    if (proj_bf16) hipLaunchKernelGGL((k_proj<0, 1>), grid, block, 0, st, b, w, proj);
+    else hipLaunchKernelGGL((k_proj<0, 0>), grid, block, 0, st, b, w, proj);
   }
-  hipLaunchKernelGGL(k_norm, dim3((b.M + 3) / 4), dim3(256), 0, st, b, w, ssq);
+  hipLaunchKernelGGL(k_norm, dim3((b.M + 3) / 4), dim3(256), 0, st, b, w);
 }
 
 }  // namespace disc

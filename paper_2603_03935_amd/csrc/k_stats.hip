@@ -10,7 +10,6 @@
 
 namespace disc {
 
-constexpr int kChunk = 64;  // tokens per partial-sum chunk
 
 // OCP e4m3fn code -> float (exact)
 __device__ __forceinline__ float e4m3_to_f32(uint32_t code) {
@@ -39,9 +38,9 @@ __device__ __forceinline__ float4 load4(const void* base, int dtype, const float
                      s * e4m3_to_f32(v >> 24));
 }
 
-// Partial channel sums over chunks of 64 tokens; the last chunk of a frame to
-// finish folds the partials (fixed order) into the frame mean.  Each thread
-// reads 16-byte vectors (VEC channels) of several token rows.
+// Partial channel sums over chunks of stat_chunk(G) tokens (k_colsum), folded
+// in a fixed order into the frame mean by k_mean.  Each thread reads 16-byte
+// vectors (VEC channels) of several token rows.
 template <int TOK>
 __device__ __forceinline__ void load_vec(const void* base, const float* scale, int64_t p, int C, int c, float* v) {
   const int64_t off = p * C + c;
@@ -71,11 +70,11 @@ __global__ __launch_bounds__(256) void k_colsum(Batch b, Work wk) {
   if (f >= b.dyn[0]) return;
   const FrameDesc fd = b.frames[f];
   const int G = fd.G, C = b.C;
-  const int nch = (G + kChunk - 1) / kChunk;
+  const int nch = stat_nchunk(G);
   if (chunk >= nch) return;
   const int tpr = C / VEC, rpp = 256 / tpr;
   const int tid = threadIdx.x, cg = tid % tpr, ro = tid / tpr;
-  const int p0 = chunk * kChunk, p1 = min(p0 + kChunk, G);
+  const int p0 = chunk * stat_chunk(G), p1 = min(p0 + stat_chunk(G), G);
   __shared__ float part[256 * 16];
   float acc[VEC];
   for (int j = 0; j < VEC; ++j) acc[j] = 0.f;
@@ -103,20 +102,19 @@ __global__ __launch_bounds__(256) void k_colsum(Batch b, Work wk) {
     for (int r = 0; r < rpp; ++r) a += part[r * C + c];
     ps[c] = a;
   }
-  __threadfence();
-  __shared__ int last;
-  __syncthreads();
-  if (tid == 0) last = (atomicAdd(wk.frame_ctr + f, 1u) == (unsigned)(nch - 1));
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const float inv = 1.0f / (float)G;
-  for (int c = tid; c < C; c += 256) {
-    float a = 0.f;
-    for (int j = 0; j < nch; ++j) a += __builtin_nontemporal_load(wk.psum + ((int64_t)f * b.nchunk + j) * C + c);
-    wk.mean[(int64_t)f * C + c] = a * inv;
-  }
-  if (tid == 0) wk.frame_ctr[f] = 0u;
+}
+
+// mean[f][c] = (sum of the chunk partials in chunk order) / G
+__global__ __launch_bounds__(256) void k_mean(Batch b, Work wk) {
+  const int f = blockIdx.y, c = blockIdx.x * 256 + threadIdx.x;
+  if (f >= b.dyn[0] || c >= b.C) return;
+  const int G = b.frames[f].G;
+  const int nch = stat_nchunk(G);
+  const float* ps = wk.psum + (int64_t)f * b.nchunk * b.C + c;
+  float a = 0.f;
+#pragma unroll 8
+  for (int j = 0; j < nch; ++j) a += ps[(int64_t)j * b.C];
+  wk.mean[(int64_t)f * b.C + c] = a * (1.0f / (float)G);
 }
 
 // One workgroup per group of 8 consecutive tokens p0..p0+7 of a frame:
@@ -226,6 +224,7 @@ void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int
     if (b.tok_dtype == 0) hipLaunchKernelGGL(k_colsum<0>, cgrid, dim3(256), 0, st, b, w);
     else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_colsum<1>, cgrid, dim3(256), 0, st, b, w);
     else hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
+    hipLaunchKernelGGL(k_mean, dim3((b.C + 255) / 256, b.n_frames), dim3(256), 0, st, b, w);
   }
   if (!want_r && !pack) return;
   if (b.tok_dtype == 0) launch_tokpack_t<0>(b, w, gmax, want_r, pack, st);
