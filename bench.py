@@ -2,8 +2,8 @@
 """Benchmark of DISC's single-pass, distance-weighted mask feature extraction
 (arXiv 2603.03935, Sec. III-C) on one MI355X.
 
-A step is one pass of the whole hot path -- bounding-box scan, work plan,
-exact EDT fused with the per-patch sqrt(EDT) sums, token statistics (Eq. 1),
+A step is one pass of the whole hot path -- bounding-box scan (which also
+lists the distance-transform work), exact EDT fused with the per-patch sqrt(EDT) sums, token statistics (Eq. 1),
 weight finalisation, pooling GEMM, projection GEMM with L2 normalisation --
 over one batch of synthetic input already resident in HBM.
 
@@ -55,7 +55,7 @@ CONFIG_DESC = {
     "cfg3": "batched BF16, 64 frames 480x640, Poisson(60) masks/frame, tokens 30x40x1024, proj 1024x768",
     "cfg5": "large FP8, 16 frames 1080x1920, 500 masks/frame, tokens 68x120x1280 e4m3fn+scale, proj 1280x1024 BF16",
 }
-KERNEL_SOURCES = {"scan": "k_scan.hip", "plan": "k_scan.hip", "edt": "k_edt.hip", "token_stats": "k_stats.hip",
+KERNEL_SOURCES = {"scan": "k_scan.hip", "edt": "k_edt.hip", "token_stats": "k_stats.hip",
                   "weights": "k_stats.hip", "pool": "k_gemm.hip", "proj": "k_gemm.hip"}
 
 
@@ -133,7 +133,6 @@ def workload_units(wl, gemm_bf16: bool):
     gdt = "bf16" if gemm_bf16 else "f32"
     return {
         "scan": ("hbm", bits_bytes, "B"),
-        "plan": ("hbm", 4 * M, "B"),
         "edt": ("alu", EDT_OPS_PER_PIXEL * edt_px, "op"),
         "token_stats": ("hbm", tok_bytes + r_bytes + tkp_bytes, "B"),
         "weights": ("hbm", w_bytes, "B"),

@@ -40,7 +40,7 @@ EXPORTS = [
     "disc_server_config_default", "disc_server_create", "disc_server_submit", "disc_server_poll",
     "disc_server_wait", "disc_server_drain", "disc_server_get_stats", "disc_server_destroy",
 ]
-STAGES = ["scan", "plan", "token_stats", "edt", "weights", "pool", "proj"]
+STAGES = ["scan", "token_stats", "edt", "weights", "pool", "proj"]
 
 
 class DiscError(RuntimeError):

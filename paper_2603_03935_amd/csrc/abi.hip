@@ -147,13 +147,13 @@ Layout make_layout(const Shape& s) {
   L.mask_frame = take(4 * (size_t)s.M);
   L.tiles = take(16 * (size_t)s.n_tiles);
   L.dyn = take(16);
+  L.counts = take(4 * 32);
   L.staged_end = off;
   L.bbox = take(16 * (size_t)s.M);
   L.area = take(4 * (size_t)s.M);
   L.meta = take(4 * (size_t)s.M);
   L.mrec = take(sizeof(MaskRec) * (size_t)s.M);
-  L.items = take(4 * (size_t)s.item_cap);
-  L.counts = take(4 * 32);
+  L.items = take(4 * (size_t)kClasses * s.item_cap);
   L.psum = take(4 * (size_t)s.n_frames * s.nchunk * s.C);
   L.mean = take(4 * (size_t)s.n_frames * s.C);
   L.r = take(4 * (size_t)s.sumG);
@@ -359,6 +359,7 @@ void stage_host(const Plan& p, char* host, char* dev) {
   if (!p.tiles.empty()) std::memcpy(host + p.L.tiles, p.tiles.data(), 16 * p.tiles.size());
   const int32_t dyn[4] = {p.shape.n_frames, (int32_t)p.shape.M, p.shape.n_tiles, 0};
   std::memcpy(host + p.L.dyn, dyn, sizeof dyn);
+  std::memset(host + p.L.counts, 0, 4 * 32);
 }
 
 Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int distinct) {
@@ -444,8 +445,8 @@ disc_status describe(const disc_tokens* tokens, const disc_masks* masks, int32_t
 // --------------------------------------------------------------------------
 // per-stage tracing: events around each stage on the caller's stream
 // --------------------------------------------------------------------------
-enum Stage { ST_SCAN = 0, ST_PLAN, ST_STATS, ST_EDT, ST_WEIGHTS, ST_POOL, ST_PROJ, ST_COUNT };
-const char* kStageNames[ST_COUNT] = {"scan", "plan", "token_stats", "edt", "weights", "pool", "proj"};
+enum Stage { ST_SCAN = 0, ST_STATS, ST_EDT, ST_WEIGHTS, ST_POOL, ST_PROJ, ST_COUNT };
+const char* kStageNames[ST_COUNT] = {"scan", "token_stats", "edt", "weights", "pool", "proj"};
 
 struct TraceRec {
   int stage;
@@ -511,7 +512,6 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   const Work w = work_ptrs(dev_ws, p.L);
   const int4* tiles = reinterpret_cast<const int4*>(dev_ws + p.L.tiles);
   { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st); }
-  { StageTimer t(sid < 0 ? -1 : ST_PLAN, st); launch_plan(b, w, st); }
   if (o.distinct || p.shape.gemm_bf16) {
     StageTimer t(sid < 0 ? -1 : ST_STATS, st);
     launch_token_stats(b, w, p.shape.gmax, o.distinct, p.shape.gemm_bf16, st);
@@ -632,7 +632,6 @@ disc_status disc_edt_sq(const disc_masks* masks, int32_t* e, void* stream) {
   const Work w = work_ptrs(cx.dev_ws, p.L);
   launch_fill_u32(reinterpret_cast<uint32_t*>(e), 0u, (int64_t)masks->m * masks->h * masks->w, cx.st);
   launch_scan(b, w, cx.st);
-  launch_plan(b, w, cx.st);
   launch_edt(b, w, e, num_cus(cx.dev), cx.st);
   if ((st = check_launch(who))) return st;
   return ok();
@@ -676,7 +675,6 @@ disc_status disc_patch_weights(const disc_tokens* tokens, const disc_masks* mask
   const Batch b = make_batch(p, cx.dev_ws, o.distinct ? tokens->dtype : DISC_F32, o.spatial, o.distinct);
   const Work w = work_ptrs(cx.dev_ws, p.L);
   launch_scan(b, w, cx.st);
-  launch_plan(b, w, cx.st);
   if (o.distinct) launch_token_stats(b, w, p.shape.gmax, 1, 0, cx.st);
   launch_edt(b, w, nullptr, num_cus(cx.dev), cx.st, o.edt_layout);
   launch_dense_weights(b, w, wout, o.eps, cx.st);

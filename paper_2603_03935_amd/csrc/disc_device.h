@@ -97,7 +97,7 @@ struct Batch {
   int32_t gemm_bf16;          // 1: BF16 operands, 0: FP32 operands
   int32_t spatial, distinct;
   int32_t nchunk;             // token-statistics chunks per frame (capacity)
-  int32_t item_cap;           // capacity of each class's work list
+  int32_t item_cap;           // capacity of each class's work list (and the list stride)
   int32_t n_tiles;            // pooling tiles (capacity)
   int32_t kgroups;            // pooling K groups of the largest frame
   int32_t pool_split, proj_split;  // workgroups sharing one GEMM tile's K range
@@ -109,8 +109,8 @@ struct Work {
   int32_t* area;       // [M]
   int32_t* meta;       // [M] (class << 16) | strips, -1 empty
   MaskRec* mrec;       // [M]
-  int32_t* items;      // [item_cap] (mask << 8) | strip, classes back to back
-  int32_t* counts;     // [kClasses] items per class, then [kClasses] class bases in items
+  int32_t* items;      // [kClasses][item_cap] (mask << 8) | strip, one list per class
+  int32_t* counts;     // [kClasses] items per class (zeroed when a batch is staged)
   float* psum;         // [F][nchunk][C]
   float* mean;         // [F][C]
   float* r;            // [sum G]
@@ -126,7 +126,6 @@ struct Work {
 
 // Host-side launchers (stream = hipStream_t).
 void launch_scan(const Batch& b, const Work& w, hipStream_t st);
-void launch_plan(const Batch& b, const Work& w, hipStream_t st);
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode = -1);
 void edt_prepare();
 // want_r: residual norms (needs the mean); pack: k-packed token copy for the BF16 pooling GEMM

@@ -311,8 +311,8 @@ __device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool la
 // packets of the tallest class come first so that the longest work starts
 // first.  Returns the class of packet p (or -1 past the end) and the item word
 // of wavefront kb's slot in it (or -1 when that slot is empty).
-__device__ __forceinline__ int packet_slot(int mode, const int32_t* counts, const int32_t* items, int p, int kb,
-                                           int& word) {
+__device__ __forceinline__ int packet_slot(int mode, const int32_t* counts, const int32_t* items, int item_cap, int p,
+                                           int kb, int& word) {
   word = -1;
 #pragma unroll
   for (int c = kClasses - 1; c >= 0; --c) {
@@ -322,7 +322,7 @@ __device__ __forceinline__ int packet_slot(int mode, const int32_t* counts, cons
     if (p < np) {
       const int slot = kb / class_waves(mode, c);
       const int k = p * ipp + slot;
-      if (slot < ipp && k < cnt) word = items[counts[8 + c] + k];
+      if (slot < ipp && k < cnt) word = items[(int64_t)c * item_cap + k];
       return c;
     }
     p -= np;
@@ -559,26 +559,28 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
 
 // Band layout for this launch (uniform over the grid): mode 1 when the work
 // in mode-0 wavefronts exceeds four times what the grid holds at once.
-__device__ __forceinline__ int pick_mode(const int32_t* counts, int mode_arg) {
+__device__ __forceinline__ int pick_mode(const int32_t* counts, int item_cap, int mode_arg) {
   if (mode_arg >= 0) return mode_arg;
   int64_t waves0 = 0;
-  for (int c = 0; c < kClasses; ++c) waves0 += (int64_t)counts[c] * class_waves(0, c);
+  for (int c = 0; c < kClasses; ++c) waves0 += (int64_t)min(counts[c], item_cap) * class_waves(0, c);
   return waves0 > 4ll * gridDim.x * kEdtWaves ? 1 : 0;
 }
 
 template <int SPATIAL>  // 0: EDT, 1: AREA (pixel counts, no transform)
 __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_edt(
-    const int32_t* __restrict__ counts, const int32_t* __restrict__ items, const MaskRec* __restrict__ mrec,
-    int32_t* e_out, int mode_arg) {
+    const int32_t* __restrict__ counts, const int32_t* __restrict__ items, int item_cap,
+    const MaskRec* __restrict__ mrec, int32_t* e_out, int mode_arg) {
   __shared__ uint4 rec_all[kMaxRows];
   __shared__ uint32_t bm_all[kEdtBmWords * 64];
   __shared__ float part_all[kEdtBlocks * kEdtPartRows * 8];
 
   // the wavefront index is uniform; make that visible so row loops run on scalars
   const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int mode = pick_mode(counts, mode_arg);
+  const int mode = pick_mode(counts, item_cap, mode_arg);
   int total = 0;
-  for (int c = 0; c < kClasses; ++c) total += (counts[c] + class_items(mode, c) - 1) / class_items(mode, c);
+  int cnt[kClasses];
+  for (int c = 0; c < kClasses; ++c) cnt[c] = min(counts[c], item_cap);
+  for (int c = 0; c < kClasses; ++c) total += (cnt[c] + class_items(mode, c) - 1) / class_items(mode, c);
 
   // Packets are taken in a fixed stride (no shared queue).  Each wavefront
   // prefetches the record of its item in the next packet into one VGPR per
@@ -586,7 +588,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
   int p = blockIdx.x;
   if (p >= total) return;
   int word = -1;
-  int cls = packet_slot(mode, counts, items, p, kb, word);
+  int cls = packet_slot(mode, cnt, items, item_cap, p, kb, word);
   uint32_t pf = 0u;
   if (word >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(mrec + (word >> kItemStripBits))[lane];
 
@@ -595,7 +597,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
     uint32_t npf = pf;
     auto prefetch = [&]() {
       if (p + (int)gridDim.x < total) {
-        ncls = packet_slot(mode, counts, items, p + gridDim.x, kb, nword);
+        ncls = packet_slot(mode, cnt, items, item_cap, p + gridDim.x, kb, nword);
         if (nword >= 0 && lane < 16) npf = reinterpret_cast<const uint32_t*>(mrec + (nword >> kItemStripBits))[lane];
       }
     };
@@ -634,9 +636,9 @@ void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipS
   const int sp = b.spatial == 0 ? 0 : 1;
   const int grid = num_cus * g_edt_per_cu[sp];
   if (sp == 0)
-    hipLaunchKernelGGL(k_edt<0>, dim3(grid), dim3(kEdtWaves * 64), 0, st, w.counts, w.items, w.mrec, e_out, mode);
+    hipLaunchKernelGGL(k_edt<0>, dim3(grid), dim3(kEdtWaves * 64), 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, mode);
   else
-    hipLaunchKernelGGL(k_edt<1>, dim3(grid), dim3(kEdtWaves * 64), 0, st, w.counts, w.items, w.mrec, e_out, mode);
+    hipLaunchKernelGGL(k_edt<1>, dim3(grid), dim3(kEdtWaves * 64), 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, mode);
 }
 
 }  // namespace disc

@@ -1,5 +1,6 @@
-// Mask scan (bounding box + area per mask) and the work planner of the
-// distance transform; also the bit-packing and fill helpers.
+// Mask scan (bounding box + area per mask), which also appends each mask's
+// distance-transform work items to its class's list; the bit-packing and fill
+// helpers.
 #include "disc_device.h"
 
 namespace disc {
@@ -58,6 +59,7 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
   xmax = wave_max(xmax);
   area = wave_sum(area);
   __shared__ int red[4][5];
+  __shared__ int app[3];  // class, strips, first slot in the class list
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) {
     red[wv][0] = ymin;
@@ -76,6 +78,7 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
       area += red[i][4];
     }
     int meta = -1;
+    app[1] = 0;
     if (area > 0) {
       const int P = fd.patch, SW = strip_width(P);
       const int xs0 = (xmin / P) * P;
@@ -105,98 +108,29 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
       r.xs0 = xs0;
       r.g = g;
       wk.mrec[g] = r;
+      if (cls < kClasses) {
+        // the order of items inside a class list does not affect any result
+        app[0] = cls;
+        app[1] = strips;
+        app[2] = atomicAdd(wk.counts + cls, strips);
+      }
     } else {
       wk.bbox[g] = make_int4(1, 0, 1, 0);
     }
     wk.area[g] = area;
     wk.meta[g] = meta;
   }
+  __syncthreads();
+  const int strips = app[1];
+  if (strips > 0) {
+    int32_t* list = wk.items + (int64_t)app[0] * b.item_cap + app[2];
+    for (int j = threadIdx.x; j < strips; j += 256)
+      if (app[2] + j < b.item_cap) list[j] = (g << kItemStripBits) | j;
+  }
 }
 
 void launch_scan(const Batch& b, const Work& w, hipStream_t st) {
   if (b.M > 0) hipLaunchKernelGGL(k_scan, dim3(b.M), dim3(256), 0, st, b, w);
-}
-
-// ---------------------------------------------------------------------------
-// k_plan: one workgroup turns the per-mask strip counts into the distance-
-// transform work list: one word (mask << 8) | strip per item, classes back to
-// back (mask-major, strip-minor within a class).
-// counts[c] = items of class c, counts[8 + c] = first item of class c.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_plan(Batch b, Work wk) {
-  __shared__ int wsum[16];
-  __shared__ int base_sh;
-  __shared__ int red[16][kClasses];
-  __shared__ int cls_base[kClasses + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int M = b.dyn[1];
-  // pass 1: items per class
-  int loc[kClasses];
-  for (int c = 0; c < kClasses; ++c) loc[c] = 0;
-  for (int g = tid; g < M; g += 1024) {
-    const int meta = wk.meta[g];
-    if (meta >= 0 && (meta >> 16) < kClasses) loc[meta >> 16] += meta & 0xFFFF;
-  }
-  for (int c = 0; c < kClasses; ++c) {
-    int v = loc[c];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0) red[wv][c] = v;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int c = 0; c < kClasses; ++c) {
-      int t = 0;
-      for (int i = 0; i < 16; ++i) t += red[i][c];
-      cls_base[c] = min(acc, b.item_cap);
-      acc += t;
-    }
-    cls_base[kClasses] = min(acc, b.item_cap);
-  }
-  __syncthreads();
-  // pass 2: write the items of each class
-  for (int c = 0; c < kClasses; ++c) {
-    if (tid == 0) base_sh = cls_base[c];
-    __syncthreads();
-    for (int g0 = 0; g0 < M; g0 += 1024) {
-      const int g = g0 + tid;
-      int cnt = 0;
-      if (g < M) {
-        const int meta = wk.meta[g];
-        if (meta >= 0 && (meta >> 16) == c) cnt = meta & 0xFFFF;
-      }
-      int incl = cnt;
-      for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(incl, o);
-        if (lane >= o) incl += t;
-      }
-      if (lane == 63) wsum[wv] = incl;
-      __syncthreads();
-      int before = base_sh;
-      for (int i = 0; i < wv; ++i) before += wsum[i];
-      const int off = before + incl - cnt;
-      for (int j = 0; j < cnt; ++j) {
-        if (off + j >= cls_base[c + 1]) break;
-        wk.items[off + j] = (g << kItemStripBits) | j;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        int tot = 0;
-        for (int i = 0; i < 16; ++i) tot += wsum[i];
-        base_sh += tot;
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      wk.counts[c] = cls_base[c + 1] - cls_base[c];
-      wk.counts[8 + c] = cls_base[c];
-    }
-    __syncthreads();
-  }
-}
-
-void launch_plan(const Batch& b, const Work& w, hipStream_t st) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, b, w);
 }
 
 // ---------------------------------------------------------------------------
