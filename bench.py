@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the served BF16 leg")
     ap.add_argument("--edt-layout", type=int, default=-1, choices=[-1, 0, 1],
                     help="distance-transform band layout (-1: chosen per call)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times) and exit: the reference that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
     return ap.parse_args()
 
 
@@ -258,6 +261,16 @@ def main():
                                    "(the path shards by frames with no exchange between GPUs)"}))
         sys.exit(2)
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 3}))
+        return
 
     import disc_inputs as di
     import disc_inputs.device as dev
