@@ -127,7 +127,7 @@ def workload_units(wl, gemm_bf16: bool):
         tok_bytes += t.data.nbytes + (t.scale.nbytes if t.scale is not None else 0)
         r_bytes += 4 * G
         if gemm_bf16:
-            tkp_bytes += G * C * (1 if t.dtype == "f8" else 2)
+            tkp_bytes += G * C * 2
         w_bytes += f.m * G * (2 if gemm_bf16 else 4)
         for bb in _bbox(f.bits):
             if bb is not None:

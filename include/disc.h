@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define DISC_ABI_VERSION 2
+#define DISC_ABI_VERSION 3
 
 typedef enum disc_status {
   DISC_OK = 0,
@@ -130,6 +130,12 @@ typedef struct disc_options {
                              bands (lowest latency for few masks), 1 longer
                              bands (throughput for large batches).  Results
                              are identical bit for bit in every layout. */
+  int32_t pool_tile;      /* channels per pooling workgroup in units of 64:
+                             -1 (default) autotuned (the first call with a
+                             new problem shape times every width and keeps
+                             the fastest), or 1, 2 or 4 (4 and 2 only when
+                             they divide c / 64).  Results are identical bit
+                             for bit for every width. */
 } disc_options;
 
 /* Fill *o with the defaults listed above. */

@@ -123,6 +123,8 @@ disc_status check_opts(const disc_options* o, const char* who) {
   if (o->workspace && !aligned16(o->workspace)) return fail(DISC_ERR_ALIGNMENT, "%s: workspace must be 16-byte aligned", who);
   if (o->edt_layout < -1 || o->edt_layout > 1)
     return fail(DISC_ERR_INVALID_ARGUMENT, "%s: edt_layout must be -1, 0 or 1", who);
+  if (o->pool_tile != -1 && o->pool_tile != 1 && o->pool_tile != 2 && o->pool_tile != 4)
+    return fail(DISC_ERR_INVALID_ARGUMENT, "%s: pool_tile must be -1, 1, 2 or 4", who);
   return DISC_OK;
 }
 
@@ -333,7 +335,7 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
   s.sumG = sumG;
   s.sumMGs = sumMGs;
   s.tkp_elems = tkp;
-  s.tkp_esize = tok_dtype == DISC_F8E4M3 ? 1 : 2;
+  s.tkp_esize = 2;
   s.gmax = gmax;
   s.nchunk = nchunk;
   s.item_cap = (int)std::min<int64_t>(item_cap, INT32_MAX / 2);
@@ -505,8 +507,77 @@ void tr_collect() {
   g_tr_pending.clear();
 }
 
+// --------------------------------------------------------------------------
+// Pooling autotuner.  The pooling GEMM can give each workgroup 1, 2 or 4
+// adjacent 64-channel tiles (wider tiles fetch each weight row once for more
+// channels but hold more accumulators, so fewer workgroups fit per CU).  The
+// first call with a new problem signature, outside graph capture, runs every
+// valid width on its own data (each run writes the same bits), times the
+// second of two runs of each with HIP events, and keeps the fastest; later
+// calls (and captured graphs) use the stored choice, or a size rule before
+// one exists.
+// --------------------------------------------------------------------------
+namespace {
+struct PoolKey {
+  int C, bf16, tok, n_tiles, split, kgroups;
+  bool operator<(const PoolKey& o) const {
+    return std::tie(C, bf16, tok, n_tiles, split, kgroups) < std::tie(o.C, o.bf16, o.tok, o.n_tiles, o.split, o.kgroups);
+  }
+};
+std::mutex g_tune_mu;
+std::map<PoolKey, int> g_tune;
+
+int pool_nt_rule(const Shape& s) {
+  for (int nt : {4, 2})
+    if (pool_nt_valid(s.C, nt) && s.n_tiles / nt * s.pool_split >= 4 * kTargetWGs) return nt;
+  return 1;
+}
+}  // namespace
+
+int pool_tile_choice(const Plan& p, int tok_dtype, const disc_options& o, bool tune, const Batch& b, const Work& w,
+                     const int4* tiles, hipStream_t st, bool* ran) {
+  *ran = false;
+  if (o.pool_tile > 0) return pool_nt_valid(p.shape.C, o.pool_tile) ? o.pool_tile : 1;
+  const Shape& s = p.shape;
+  const PoolKey key{s.C, s.gemm_bf16, tok_dtype, s.n_tiles, s.pool_split, s.kgroups};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  if (!tune) return pool_nt_rule(s);
+  std::vector<int> cand;
+  for (int nt : {1, 2, 4})
+    if (pool_nt_valid(s.C, nt)) cand.push_back(nt);
+  std::vector<hipEvent_t> ev(4 * cand.size());
+  for (auto& e : ev) (void)hipEventCreate(&e);
+  for (size_t i = 0; i < cand.size(); ++i)
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipEventRecord(ev[4 * i + 2 * rep], st);
+      launch_pool(b, w, tiles, st, cand[i]);
+      (void)hipEventRecord(ev[4 * i + 2 * rep + 1], st);
+    }
+  (void)hipEventSynchronize(ev.back());
+  int best = cand[0];
+  float best_ms = 1e30f;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[4 * i + 2], ev[4 * i + 3]) == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = cand[i];
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+  }
+  *ran = true;  // X already holds the pooled result (every run writes the same bits)
+  return best;
+}
+
 void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options& o, const disc_proj* proj, int cus,
-                  hipStream_t st, bool trace) {
+                  hipStream_t st, bool trace, bool tune) {
   const int sid = trace ? 0 : -1;
   const Batch b = make_batch(p, dev_ws, tok_dtype, o.spatial, o.distinct);
   const Work w = work_ptrs(dev_ws, p.L);
@@ -518,7 +589,12 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   }
   { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st, o.edt_layout); }
   { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); }
-  { StageTimer t(sid < 0 ? -1 : ST_POOL, st); launch_pool(b, w, tiles, st); }
+  {
+    StageTimer t(sid < 0 ? -1 : ST_POOL, st);
+    bool ran = false;
+    const int nt = pool_tile_choice(p, tok_dtype, o, tune, b, w, tiles, st, &ran);
+    if (!ran) launch_pool(b, w, tiles, st, nt);
+  }
   { StageTimer t(sid < 0 ? -1 : ST_PROJ, st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, st); }
 }
 
@@ -541,6 +617,7 @@ void disc_options_default(disc_options* o) {
   o->workspace = nullptr;
   o->workspace_bytes = 0;
   o->edt_layout = -1;
+  o->pool_tile = -1;
 }
 
 int32_t disc_abi_version(void) { return DISC_ABI_VERSION; }
@@ -581,7 +658,7 @@ disc_status disc_embed_frames(const disc_tokens* tokens, const disc_masks* masks
   if ((st = acquire(static_cast<hipStream_t>(stream), p.L, &o, cx))) return st;
   stage_host(p, cx.host_stage, cx.dev_ws);
   if ((st = upload(cx, p.L))) return st;
-  enqueue_path(p, cx.dev_ws, tokens[0].dtype, o, proj, num_cus(cx.dev), cx.st);
+  enqueue_path(p, cx.dev_ws, tokens[0].dtype, o, proj, num_cus(cx.dev), cx.st, true, true);
   if ((st = check_launch(who))) return st;
   return ok();
 }
@@ -753,7 +830,7 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32
   const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
   launch_user_weights(b, w, wts, cx.st);
   if (p.shape.gemm_bf16) launch_token_stats(b, w, p.shape.gmax, 0, 1, cx.st);
-  launch_pool(b, w, tiles, cx.st);
+  launch_pool(b, w, tiles, cx.st, o.pool_tile > 0 ? o.pool_tile : 1);
   launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, cx.st);
   if ((st = check_launch(who))) return st;
   return ok();

@@ -121,7 +121,7 @@ struct Work {
   void* X;             // [M][C] pooled features in the GEMM dtype
   float* ppart;        // pooling group sums [tile][kgroups][64*64] (split K only)
   float* qpart;        // projection group sums [C/256][M][E] (split K only)
-  void* tkp;           // k-packed tokens [sum ceil(G/8)][C][8] (BF16 bits, or e4m3 codes for FP8 tokens)
+  void* tkp;           // k-packed tokens [sum ceil(G/8)][C][8], BF16 bits (FP8 tokens: their code values)
 };
 
 // Host-side launchers (stream = hipStream_t).
@@ -131,7 +131,9 @@ void edt_prepare();
 // want_r: residual norms (needs the mean); pack: k-packed token copy for the BF16 pooling GEMM
 void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
-void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st);
+// nt: 64-channel tiles per workgroup (1, 2 or 4; any value gives the same result)
+void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st, int nt = 1);
+bool pool_nt_valid(int C, int nt);
 void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st);
 // stage helpers
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);

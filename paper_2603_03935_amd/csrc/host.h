@@ -21,7 +21,7 @@ struct Shape {
   int64_t M = 0, sumG = 0, sumMGs = 0;
   int C = 0, E = 0, gmax = 0, nchunk = 1, item_cap = 1, n_tiles = 0, gemm_bf16 = 0;
   int64_t tkp_elems = 0;  // sum over frames of ceil(G/8)*8*C (k-packed tokens, BF16 GEMM only)
-  int tkp_esize = 2;      // bytes per k-packed element: 1 for FP8 tokens, else 2
+  int tkp_esize = 2;      // bytes per k-packed element (BF16)
   int kgroups = 1;        // pooling K groups of the largest frame
   int pool_split = 1, proj_split = 1;
 };
@@ -71,8 +71,10 @@ disc_options defaults();
 int num_cus(int dev);
 // Enqueue the whole kernel sequence of a staged plan on a stream.
 // trace = false while capturing a graph.
+// tune = true lets the pooling autotuner time its candidates on this call
+// (never while capturing a graph).
 void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options& o, const disc_proj* proj, int cus,
-                  hipStream_t st, bool trace = true);
+                  hipStream_t st, bool trace = true, bool tune = false);
 
 }  // namespace host
 }  // namespace disc

@@ -73,10 +73,13 @@ __device__ __forceinline__ void load_tok8(const void* base, int64_t off, bool ok
 // pooling: tile 64 masks x 64 channels, K = patches in chunks of 32.
 // A (weights, k contiguous) is staged row-major; for BF16 operands B is read
 // from the k-packed token copy written by the statistics pass (8 consecutive
-// patches of one channel contiguous), so each B load is one vector and the
-// MFMA operand of a lane is one 16-byte LDS read.  FP8 codes are widened to
-// BF16 here.  The next K chunk is fetched into registers while the current one
-// is multiplied.
+// patches of one channel contiguous, BF16; FP8 code values were widened there,
+// once per token), so each B load is one vector and the MFMA operand of a lane
+// is one 16-byte LDS read.  The next K chunk is fetched into registers while the current one
+// is multiplied.  A workgroup may take NT = 1, 2 or 4 adjacent 64-channel
+// tiles of the same masks (one A fetch for NT x 64 channels); the tile list,
+// the K order and therefore the result do not depend on NT, which the pooling
+// autotuner picks per problem shape.
 // ---------------------------------------------------------------------------
 constexpr int PBM = 64, PBN = 64, PBK = 32;
 constexpr int PAS = PBK + 8;  // LDS row stride (elements) of A and k-packed B
@@ -130,11 +133,14 @@ __device__ __forceinline__ void pool_store(const Work& wk, const FrameDesc& fd, 
   }
 }
 
-// grid: tiles x S; workgroup (tile, s) takes the s-th share of the tile's K groups
-template <int BF16, int TOK>
+// grid: (tiles / NT) x S; workgroup (super-tile, s) takes the s-th share of the
+// K groups of NT adjacent tiles
+template <int BF16, int TOK, int NT>
 __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tiles) {
+  constexpr int BN = PBN * NT;  // channels per workgroup
   const int S = b.pool_split;
-  const int tix = blockIdx.x / S, sidx = blockIdx.x - tix * S;
+  const int stix = blockIdx.x / S, sidx = blockIdx.x - stix * S;
+  const int tix = stix * NT;  // first 64-channel tile
   if (tix >= b.dyn[2]) return;
   const int4 t = tiles[tix];
   const FrameDesc fd = b.frames[t.x];
@@ -145,9 +151,9 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
 
   __shared__ int kmin_sh, kmax_sh;
   __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? PBM * PAS : 1];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? PBN * PAS : 1];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? BN * PAS : 1];
   __shared__ float As32[BF16 ? 1 : PBM * (PBK + 1)];
-  __shared__ __attribute__((aligned(16))) float Bs32[BF16 ? 1 : PBK * PBN];
+  __shared__ __attribute__((aligned(16))) float Bs32[BF16 ? 1 : PBK * BN];
 
   int kbeg, kend;
   tile_krange(wk, fd, m0, mrows, tid, &kmin_sh, &kmax_sh, kbeg, kend);
@@ -157,18 +163,20 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   const int kstart = max(kbeg, ga * kPoolKG), kstop = min(kend, gb * kPoolKG);
 
   const floatx16 zero16 = {};
-  floatx16 total = zero16, acc = zero16;
+  floatx16 total[NT], acc[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) total[j] = acc[j] = zero16;
 
   const int64_t wrow0 = fd.w_base + (int64_t)m0 * fd.Gs;
   const int ar = tid >> 2, ak = (tid & 3) * 8;        // A: row, first k of 8
   const bool arow_ok = ar < mrows;
-  // B (BF16): channel n = tid & 63, patches 8*(tid >> 6) .. +7
+  // B (BF16): channels (tid & 63) + 64 j, patches 8*(tid >> 6) .. +7
   const int bn16 = tid & 63, bk16 = (tid >> 6) * 8;
-  // B (FP32): patch tid >> 3, channels 8*(tid & 7) .. +7
+  // B (FP32): patch tid >> 3, channels 8*(tid & 7) + 64 j .. +7
   const int bk32 = tid >> 3, bn32 = (tid & 7) * 8;
 
-  uint4 ra16 = make_uint4(0, 0, 0, 0), rb16 = make_uint4(0, 0, 0, 0);
-  float ra32[8], rb32[8];
+  uint4 ra16 = make_uint4(0, 0, 0, 0), rb16[NT];
+  float ra32[8], rb32[NT][8];
 
   auto fetch = [&](int k0) {
     const int kk = k0 + ak;
@@ -181,52 +189,53 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
         for (int j = 0; j < 8; ++j) tmp[j] = (arow_ok && kk + j < G) ? src[j] : (uint16_t)0;
         ra16 = make_uint4(tmp[0] | (tmp[1] << 16), tmp[2] | (tmp[3] << 16), tmp[4] | (tmp[5] << 16), tmp[6] | (tmp[7] << 16));
       }
-      // k-packed tokens: one vector load gives this channel's 8 patches
+      // k-packed tokens: one vector load gives one channel's 8 patches
       const int grp = (k0 + bk16) >> 3;
-      if (grp * 8 < G) {
-        const int64_t e = fd.t_base + ((int64_t)grp * C + n0 + bn16) * 8;
-        if (TOK == 2) {
-          const uint2 q = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(wk.tkp) + e);
-          uint32_t o[4];
-          for (int j = 0; j < 4; ++j) {
-            const uint32_t w2 = j < 2 ? q.x : q.y;
-            o[j] = e4m3_to_bf16((w2 >> (16 * (j & 1))) & 0xFFu) | ((uint32_t)e4m3_to_bf16((w2 >> (16 * (j & 1) + 8)) & 0xFFu) << 16);
-          }
-          rb16 = make_uint4(o[0], o[1], o[2], o[3]);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        if (grp * 8 < G) {
+          const int64_t e = fd.t_base + ((int64_t)grp * C + n0 + bn16 + 64 * j) * 8;
+          rb16[j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(wk.tkp) + e);
         } else {
-          rb16 = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(wk.tkp) + e);
+          rb16[j] = make_uint4(0, 0, 0, 0);
         }
-      } else {
-        rb16 = make_uint4(0, 0, 0, 0);
       }
     } else {
       const float* src = reinterpret_cast<const float*>(wk.W) + wrow0 + (int64_t)ar * fd.Gs + kk;
       for (int j = 0; j < 8; ++j) ra32[j] = (arow_ok && kk + j < G) ? src[j] : 0.f;
       const int kr = k0 + bk32;
-      load_tok8<TOK, 0>(fd.tokens, (int64_t)kr * C + n0 + bn32, kr < G, nullptr, rb32);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) load_tok8<TOK, 0>(fd.tokens, (int64_t)kr * C + n0 + bn32 + 64 * j, kr < G, nullptr, rb32[j]);
     }
   };
   auto stage = [&]() {
     if (BF16) {
       *reinterpret_cast<uint4*>(&As16[ar * PAS + ak]) = ra16;
-      *reinterpret_cast<uint4*>(&Bs16[bn16 * PAS + bk16]) = rb16;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) *reinterpret_cast<uint4*>(&Bs16[(bn16 + 64 * j) * PAS + bk16]) = rb16[j];
     } else {
       for (int j = 0; j < 8; ++j) As32[ar * (PBK + 1) + ak + j] = ra32[j];
-      *reinterpret_cast<float4*>(&Bs32[bk32 * PBN + bn32]) = make_float4(rb32[0], rb32[1], rb32[2], rb32[3]);
-      *reinterpret_cast<float4*>(&Bs32[bk32 * PBN + bn32 + 4]) = make_float4(rb32[4], rb32[5], rb32[6], rb32[7]);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        *reinterpret_cast<float4*>(&Bs32[bk32 * BN + bn32 + 64 * j]) = make_float4(rb32[j][0], rb32[j][1], rb32[j][2], rb32[j][3]);
+        *reinterpret_cast<float4*>(&Bs32[bk32 * BN + bn32 + 64 * j + 4]) = make_float4(rb32[j][4], rb32[j][5], rb32[j][6], rb32[j][7]);
+      }
     }
   };
   // a finished K group: add it to the running total, or store it for the reduce pass
-  float* gpart = wk.ppart + ((int64_t)tix * b.kgroups) * (PBM * PBN) + tid * 16;
   auto fold = [&](int grp) {
-    if (S == 1) {
-      total += acc;
-    } else {
-      float4* dst = reinterpret_cast<float4*>(gpart + (int64_t)grp * (PBM * PBN));
 #pragma unroll
-      for (int i = 0; i < 4; ++i) dst[i] = make_float4(acc[4 * i], acc[4 * i + 1], acc[4 * i + 2], acc[4 * i + 3]);
+    for (int j = 0; j < NT; ++j) {
+      if (S == 1) {
+        total[j] += acc[j];
+      } else {
+        // sub-tile j of this wavefront lies in 64-channel tile tix + j
+        float4* dst = reinterpret_cast<float4*>(wk.ppart + (((int64_t)(tix + j) * b.kgroups + grp) * (PBM * PBN)) + tid * 16);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dst[i] = make_float4(acc[j][4 * i], acc[j][4 * i + 1], acc[j][4 * i + 2], acc[j][4 * i + 3]);
+      }
+      acc[j] = zero16;
     }
-    acc = zero16;
   };
 
   const int lr = lane & 31, lk = lane >> 5;
@@ -244,21 +253,30 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
 #pragma unroll
       for (int kk = 0; kk < PBK; kk += 16) {
         const u16x8 av = *reinterpret_cast<const u16x8*>(&As16[(32 * wm + lr) * PAS + kk + 8 * lk]);
-        const u16x8 bv = *reinterpret_cast<const u16x8*>(&Bs16[(32 * wn + lr) * PAS + kk + 8 * lk]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const u16x8 bv = *reinterpret_cast<const u16x8*>(&Bs16[(64 * j + 32 * wn + lr) * PAS + kk + 8 * lk]);
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc[j], 0, 0, 0);
+        }
       }
     } else {
 #pragma unroll
       for (int kk = 0; kk < PBK; kk += 2) {
         const float a = As32[(32 * wm + lr) * (PBK + 1) + kk + lk];
-        const float bb = Bs32[(kk + lk) * PBN + 32 * wn + lr];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const float bb = Bs32[(kk + lk) * BN + 64 * j + 32 * wn + lr];
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc[j], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
   }
   if (kstart < kstop) fold(cur);
-  if (S == 1) pool_store<BF16>(wk, fd, m0, n0, C, lane, wm, wn, total);
+  if (S == 1) {
+#pragma unroll
+    for (int j = 0; j < NT; ++j) pool_store<BF16>(wk, fd, m0, n0 + 64 * j, C, lane, wm, wn, total[j]);
+  }
 }
 
 // split K: add each tile's stored group sums in group order, then store
@@ -290,19 +308,33 @@ __global__ __launch_bounds__(256) void k_pool_reduce(Batch b, Work wk, const int
   pool_store<BF16>(wk, fd, m0, n0, b.C, lane, wm, wn, total);
 }
 
-void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st) {
+template <int BF16, int TOK>
+static void launch_pool_t(const Batch& b, const Work& w, const int4* tiles, int nt, hipStream_t st) {
+  const dim3 block(256);
+  const int S = b.pool_split;
+  if (nt == 4)
+    hipLaunchKernelGGL((k_pool<BF16, TOK, 4>), dim3(b.n_tiles / 4 * S), block, 0, st, b, w, tiles);
+  else if (nt == 2)
+    hipLaunchKernelGGL((k_pool<BF16, TOK, 2>), dim3(b.n_tiles / 2 * S), block, 0, st, b, w, tiles);
+  else
+    hipLaunchKernelGGL((k_pool<BF16, TOK, 1>), dim3(b.n_tiles * S), block, 0, st, b, w, tiles);
+  if (S > 1) hipLaunchKernelGGL((k_pool_reduce<BF16>), dim3(b.n_tiles), block, 0, st, b, w, tiles);
+}
+
+// NT must divide C / 64 (the tiles of one mask tile are consecutive in the list)
+bool pool_nt_valid(int C, int nt) { return nt == 1 || ((C / 64) % nt == 0); }
+
+void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st, int nt) {
   if (b.n_tiles <= 0) return;
-  const dim3 grid(b.n_tiles * b.pool_split), block(256);
+  if (!pool_nt_valid(b.C, nt)) nt = 1;
   if (b.gemm_bf16) {
-    if (b.tok_dtype == 0) hipLaunchKernelGGL((k_pool<1, 0>), grid, block, 0, st, b, w, tiles);
-    else if (b.tok_dtype == 1) hipLaunchKernelGGL((k_pool<1, 1>), grid, block, 0, st, b, w, tiles);
-    else hipLaunchKernelGGL((k_pool<1, 2>), grid, block, 0, st, b, w, tiles);
-    if (b.pool_split > 1) hipLaunchKernelGGL((k_pool_reduce<1>), dim3(b.n_tiles), block, 0, st, b, w, tiles);
+    if (b.tok_dtype == 0) launch_pool_t<1, 0>(b, w, tiles, nt, st);
+    else if (b.tok_dtype == 1) launch_pool_t<1, 1>(b, w, tiles, nt, st);
+    else launch_pool_t<1, 2>(b, w, tiles, nt, st);
   } else {
-    if (b.tok_dtype == 0) hipLaunchKernelGGL((k_pool<0, 0>), grid, block, 0, st, b, w, tiles);
-    else if (b.tok_dtype == 1) hipLaunchKernelGGL((k_pool<0, 1>), grid, block, 0, st, b, w, tiles);
-    else hipLaunchKernelGGL((k_pool<0, 2>), grid, block, 0, st, b, w, tiles);
-    if (b.pool_split > 1) hipLaunchKernelGGL((k_pool_reduce<0>), dim3(b.n_tiles), block, 0, st, b, w, tiles);
+    if (b.tok_dtype == 0) launch_pool_t<0, 0>(b, w, tiles, nt, st);
+    else if (b.tok_dtype == 1) launch_pool_t<0, 1>(b, w, tiles, nt, st);
+    else launch_pool_t<0, 2>(b, w, tiles, nt, st);
   }
 }
 

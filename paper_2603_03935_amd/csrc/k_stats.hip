@@ -23,6 +23,15 @@ __device__ __forceinline__ float e4m3_to_f32(uint32_t code) {
 
 __device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
 
+// e4m3fn code -> BF16 bits of the same value (exact: e4m3 values are BF16 values)
+__device__ __forceinline__ uint32_t e4m3_to_bf16_bits(uint32_t code) {
+  const uint32_t sign = (code & 0x80u) << 8;
+  const uint32_t mag = code & 0x7Fu;
+  if (mag == 0x7Fu) return sign | 0x7FC0u;
+  if (mag >= 8u) return sign | ((mag << 4) + (120u << 7));
+  return sign | (__float_as_uint((float)mag * 0x1p-9f) >> 16);  // subnormal e4m3 -> normal bf16
+}
+
 // four consecutive channels of token p as floats (value = scale * code for FP8)
 __device__ __forceinline__ float4 load4(const void* base, int dtype, const float* scale, int64_t p, int C, int c) {
   const int64_t off = p * C + c;
@@ -121,8 +130,9 @@ __global__ __launch_bounds__(256) void k_mean(Batch b, Work wk) {
 //   * WANT_R: r_p = ||f_p - mean|| for the 8 tokens (block reduction);
 //   * PACK:   the k-packed copy tkp[p0/8][c][0..7] = (f_p0..f_p7)[c] that the
 //             BF16 pooling GEMM reads with one vector load per (8 patches,
-//             channel): BF16 bits (FP32 tokens rounded to nearest even), or
-//             the raw e4m3 codes for FP8 tokens.  Tokens past G pack as 0.
+//             channel): BF16 bits (FP32 tokens rounded to nearest even; the
+//             unscaled e4m3 code values for FP8 tokens, exact).  Tokens past
+//             G pack as 0.
 // Each thread owns CW consecutive channels and loads them for all 8 tokens.
 template <int TOK, int WANT_R, int PACK>
 __global__ __launch_bounds__(256) void k_tokpack(Batch b, Work wk) {
@@ -174,13 +184,13 @@ __global__ __launch_bounds__(256) void k_tokpack(Batch b, Work wk) {
     }
     if (PACK) {
       if (TOK == 2) {
-        // channel j: the codes of tokens 0..7 -> 8 bytes
-        uint2* dst = reinterpret_cast<uint2*>(reinterpret_cast<uint8_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
+        // channel j: the code values of tokens 0..7 widened (exactly) to BF16
+        // -> 16 bytes; the per-token scales live in the weights
+        uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
         for (int j = 0; j < 8; ++j) {
-          uint32_t lo = 0, hi = 0;
-          for (int i = 0; i < 4; ++i) lo |= (((j < 4 ? codes[i].x : codes[i].y) >> (8 * (j & 3))) & 0xFFu) << (8 * i);
-          for (int i = 0; i < 4; ++i) hi |= (((j < 4 ? codes[i + 4].x : codes[i + 4].y) >> (8 * (j & 3))) & 0xFFu) << (8 * i);
-          dst[j] = make_uint2(lo, hi);
+          uint32_t q[8];
+          for (int i = 0; i < 8; ++i) q[i] = e4m3_to_bf16_bits(((j < 4 ? codes[i].x : codes[i].y) >> (8 * (j & 3))) & 0xFFu);
+          dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
         }
       } else {
         // channel j: the BF16 values of tokens 0..7 -> 16 bytes

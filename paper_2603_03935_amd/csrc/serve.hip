@@ -66,7 +66,7 @@ Shape capacity_shape(const disc_server_config& c, int E, int gemm_bf16) {
   s.n_tiles = ((c.max_masks + 63) / 64 + c.max_frames) * (c.c / 64);
   s.gemm_bf16 = gemm_bf16;
   s.tkp_elems = (int64_t)c.max_frames * round_up(G, 8) * c.c;
-  s.tkp_esize = c.tok_dtype == DISC_F8E4M3 ? 1 : 2;
+  s.tkp_esize = 2;
   choose_splits(s);
   return s;
 }

@@ -37,10 +37,10 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.disc_abi_version() == 2
+    assert lib.disc_abi_version() == 3
     o = disc.Options()
     lib.disc_options_default(ctypes.byref(o))
-    assert (o.spatial, o.distinct, o.gemm_dtype, o.edt_layout) == (0, 1, -1, -1)
+    assert (o.spatial, o.distinct, o.gemm_dtype, o.edt_layout, o.pool_tile) == (0, 1, -1, -1, -1)
     assert abs(o.eps - 1e-6) < 1e-12 and o.workspace is None and o.workspace_bytes == 0
 
 
@@ -99,6 +99,9 @@ def test_null_arguments(lib):
     assert call(lib, t, m, p, o, opts) == 1
     lib.disc_options_default(ctypes.byref(opts))
     opts.edt_layout = 2
+    assert call(lib, t, m, p, o, opts) == 1
+    lib.disc_options_default(ctypes.byref(opts))
+    opts.pool_tile = 3
     assert call(lib, t, m, p, o, opts) == 1
 
 

@@ -290,3 +290,19 @@ def test_cfg5_full_batch_sampled(gpu):
         cs.append(check_embeddings(got, outs[i].status[idx].cpu().numpy(), ref, COS_LOWP, f"cfg5 frame {i}"))
     c = np.concatenate(cs)
     print(f"cfg5 sampled {len(c)}: min cos {c.min():.7f}")
+
+
+@pytest.mark.parametrize("name,frames", [("cfg2", None), ("cfg3", 6), ("cfg5", 2)])
+def test_pool_tile_widths_agree_bitwise(gpu, name, frames):
+    """The pooling GEMM's tile widths (1, 2, 4 x 64 channels per workgroup) and
+    the autotuned choice give the same bits."""
+    wl = di.workload(name, frames=frames)
+    ins = [frame_input(f) for f in wl.frames]
+    proj = dev_proj(wl.proj, wl.proj_dtype)
+    res = {}
+    for nt in (-1, 1, 2, 4):
+        outs = gpu.embed_frames(ins, proj, options=gpu.make_options(pool_tile=nt))
+        res[nt] = [o.out.cpu().numpy() for o in outs]
+    for nt in (1, 2, 4):
+        for i, (a, b) in enumerate(zip(res[-1], res[nt])):
+            assert np.array_equal(a, b), f"{name}: pool_tile {nt} differs from the tuned width on frame {i}"
