@@ -48,8 +48,10 @@ def _declare(lib):
     lib.disc_oracle_embed.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, i32, vp, i32, i32, i32, dbl,
                                       vp, vp, vp, vp, vp]
     lib.disc_oracle_pool_project.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp]
+    lib.disc_oracle_query_topk.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp, vp]
     for f in (lib.disc_oracle_edt_sq, lib.disc_oracle_edt_sq_batch, lib.disc_oracle_spatial_weights,
-              lib.disc_oracle_token_stats, lib.disc_oracle_embed, lib.disc_oracle_pool_project):
+              lib.disc_oracle_token_stats, lib.disc_oracle_embed, lib.disc_oracle_pool_project,
+              lib.disc_oracle_query_topk):
         f.restype = ctypes.c_int
     return lib
 
@@ -144,6 +146,18 @@ class Oracle:
                                                  _p(pooled)))
         return {"out": out, "status": status, "pooled": pooled}
 
+    def query_topk(self, emb: np.ndarray, text: np.ndarray, k: int) -> dict:
+        """R-QUERY: sim [q][m], top-k scores / indices [q][k] per query."""
+        emb = np.ascontiguousarray(emb, dtype=np.float64)
+        text = np.ascontiguousarray(text, dtype=np.float64)
+        m, e = emb.shape
+        q = text.shape[0]
+        sim = np.zeros((q, m))
+        scores = np.zeros((q, k))
+        idx = np.zeros((q, k), dtype=np.int32)
+        _check(self.lib.disc_oracle_query_topk(_p(emb), m, _p(text), q, e, k, _p(sim), _p(scores), _p(idx)))
+        return {"sim": sim, "scores": scores, "idx": idx}
+
     def proj_to_f64(self, P: np.ndarray, dtype: str) -> np.ndarray:
         """Caller-format projection [C][E] -> float64."""
         C, E = P.shape
@@ -189,6 +203,10 @@ def embed(*args, **kw):
 
 def pool_project(f, wts, P):
     return get().pool_project(f, wts, P)
+
+
+def query_topk(emb, text, k):
+    return get().query_topk(emb, text, k)
 
 
 def proj_to_f64(P, dtype):

@@ -326,3 +326,49 @@ done:
   free(s); free(D); free(wrow); free(F); free(y);
   return rc;
 }
+
+/* ------------------------------------------------------------------ */
+/* Open-vocabulary query (R-QUERY)                                      */
+/* ------------------------------------------------------------------ */
+
+static double norm2(const double* v, int32_t n) {
+  double a = 0.0;
+  for (int32_t i = 0; i < n; ++i) a += v[i] * v[i];
+  return sqrt(a);
+}
+
+int disc_oracle_query_topk(const double* emb, int32_t m, const double* text, int32_t q, int32_t e, int32_t k,
+                           double* sim, double* scores, int32_t* idx) {
+  if (!emb || !text || !scores || !idx || m < 0 || q < 0 || e <= 0 || k <= 0) return -1;
+  double* row = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+  char* used = (char*)malloc((size_t)(m > 0 ? m : 1));
+  if (!row || !used) {
+    free(row); free(used);
+    return -1;
+  }
+  for (int32_t j = 0; j < q; ++j) {
+    const double* t = text + (int64_t)j * e;
+    const double nt = norm2(t, e);
+    for (int32_t i = 0; i < m; ++i) {
+      const double* y = emb + (int64_t)i * e;
+      const double ny = norm2(y, e);
+      double d = 0.0;
+      for (int32_t c = 0; c < e; ++c) d += t[c] * y[c];
+      row[i] = (nt > 0.0 && ny > 0.0) ? d / (nt * ny) : 0.0;
+      used[i] = 0;
+      if (sim) sim[(int64_t)j * m + i] = row[i];
+    }
+    /* k passes of "best remaining": higher score first, then lower index */
+    for (int32_t r = 0; r < k; ++r) {
+      int32_t best = -1;
+      for (int32_t i = 0; i < m; ++i)
+        if (!used[i] && (best < 0 || row[i] > row[best])) best = i;
+      idx[(int64_t)j * k + r] = best;
+      scores[(int64_t)j * k + r] = best >= 0 ? row[best] : -INFINITY;
+      if (best >= 0) used[best] = 1;
+    }
+  }
+  free(row);
+  free(used);
+  return 0;
+}

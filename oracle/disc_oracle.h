@@ -27,6 +27,11 @@
  *           fall back to the spatial weights; zero projected vector -> zero
  *           row, status 2.
  *   R-PROJ  y = F^T P with no bias, then y / ||y||_2.
+ *   R-QUERY open-vocabulary query (Sec. III-C, the figure of the weighted
+ *           similarity heat-map; Sec. IV): the similarity of a text
+ *           embedding t and an instance embedding y is cos(t, y) (0 when
+ *           either is the zero vector); a query returns the k instances of
+ *           highest similarity, higher first, ties to the lower index.
  *
  * Parity status: every function below is pinned by tests that do not use the
  * oracle itself (brute force, closed forms, a library routine, invariants).
@@ -83,6 +88,12 @@ int disc_oracle_embed(const double* f, int32_t gh, int32_t gw, int32_t C, int32_
  * A row whose weights sum to zero gives a zero row and status 1. */
 int disc_oracle_pool_project(const double* f, int32_t G, int32_t C, const double* wts, int32_t m,
                              const double* P, int32_t E, double* out, int32_t* status, double* pooled);
+
+/* R-QUERY: sim[q][m] (may be NULL) = cos(text_j, emb_i); for each query j the
+ * k best instances: idx[j][r], scores[j][r], r = 0..k-1 (idx -1 and score
+ * -inf past m).  emb[m][e], text[q][e]. */
+int disc_oracle_query_topk(const double* emb, int32_t m, const double* text, int32_t q, int32_t e, int32_t k,
+                           double* sim, double* scores, int32_t* idx);
 
 #ifdef __cplusplus
 }

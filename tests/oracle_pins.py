@@ -380,6 +380,53 @@ def pin_decoders(orc):
     assert np.array_equal(d, np.array([[0.5, 1.0], [-3.0, 1344.0]])), "FP8 tokens decode as scale * value"
 
 
+# ---------------------------------------------------------------- open-vocabulary query (R-QUERY)
+
+def _rank(sim_row: np.ndarray, k: int):
+    """Top-k by an explicit sort key (score descending, index ascending)."""
+    order = sorted(range(len(sim_row)), key=lambda i: (-sim_row[i], i))[:k]
+    return order
+
+
+def pin_query_orthonormal(orc):
+    """Orthonormal instance embeddings: a query equal to instance i (up to a
+    positive scale) finds i with similarity 1 and every other instance at 0,
+    the zeros ranked by index; a zero query scores 0 everywhere."""
+    e = np.eye(6)
+    text = np.stack([3.0 * e[4], e[1], np.zeros(6)])
+    r = orc.query_topk(e, text, 4)
+    assert r["idx"][0].tolist() == [4, 0, 1, 2] and r["idx"][1].tolist() == [1, 0, 2, 3]
+    assert np.array_equal(r["scores"][0], [1.0, 0.0, 0.0, 0.0])
+    assert np.array_equal(r["sim"][2], np.zeros(6)) and r["idx"][2].tolist() == [0, 1, 2, 3]
+    r = orc.query_topk(e[:2], text[:1], 4)
+    assert r["idx"][0].tolist() == [0, 1, -1, -1] and np.isinf(r["scores"][0, 2]) and r["scores"][0, 2] < 0
+
+
+def pin_query_bruteforce(orc, seed=31):
+    """Similarities against numpy (normalise, then matrix product) and the
+    ranking against an explicit sort; scaling an instance by a positive
+    factor changes nothing."""
+    rng = np.random.default_rng(seed)
+    emb = rng.standard_normal((57, 19))
+    text = rng.standard_normal((7, 19))
+    emb[5] = 0.0
+    r = orc.query_topk(emb, text, 9)
+    en = np.linalg.norm(emb, axis=1)
+    tn = np.linalg.norm(text, axis=1)
+    want = (text / tn[:, None]) @ np.where(en[:, None] > 0, emb / np.where(en > 0, en, 1)[:, None], 0).T
+    assert np.allclose(r["sim"], want, rtol=0, atol=1e-13), "cosine similarities"
+    for j in range(7):
+        assert r["idx"][j].tolist() == _rank(r["sim"][j], 9), f"ranking of query {j}"
+        assert np.array_equal(r["scores"][j], r["sim"][j][r["idx"][j]])
+    emb2 = emb.copy()
+    emb2[11] *= 7.5
+    r2 = orc.query_topk(emb2, text, 9)
+    assert np.allclose(r2["sim"], r["sim"], atol=1e-14) and np.array_equal(r2["idx"], r["idx"])
+    # ties go to the lower index
+    r3 = orc.query_topk(np.stack([emb[3], emb[3], emb[3]]), text[:1], 3)
+    assert r3["idx"][0].tolist() == [0, 1, 2]
+
+
 ALL_PINS = [
     ("edt_exhaustive_4x4", lambda o: pin_edt_exhaustive(o, 4, 4)),
     ("edt_random_bruteforce", pin_edt_random_bruteforce),
@@ -399,4 +446,6 @@ ALL_PINS = [
     ("output_geometry", pin_output_geometry),
     ("degenerate", pin_degenerate),
     ("decoders", pin_decoders),
+    ("query_orthonormal", pin_query_orthonormal),
+    ("query_bruteforce", pin_query_bruteforce),
 ]

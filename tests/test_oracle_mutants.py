@@ -42,6 +42,10 @@ MUTANTS = [
     ("no_zero_fallback", "if (Z == 0.0) { /* every touched patch", "if (0) { /* every touched patch"),
     ("e4m3_bias", "v = ldexp(1.0 + man / 8.0, ex - 7);", "v = ldexp(1.0 + man / 8.0, ex - 8);"),
     ("e4m3_subnormal", "v = ldexp((double)man, -9);", "v = ldexp((double)man, -10);"),
+    ("query_text_not_normalised", "row[i] = (nt > 0.0 && ny > 0.0) ? d / (nt * ny) : 0.0;",
+     "row[i] = (nt > 0.0 && ny > 0.0) ? d / ny : 0.0;"),
+    ("query_ties_to_higher_index", "if (!used[i] && (best < 0 || row[i] > row[best])) best = i;",
+     "if (!used[i] && (best < 0 || row[i] >= row[best])) best = i;"),
 ]
 
 
