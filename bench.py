@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--no-trace", action="store_true", help="skip per-stage event timing")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="offered-load duration of the served leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served BF16 leg")
+    ap.add_argument("--no-query", action="store_true", help="skip the open-vocabulary query leg")
     ap.add_argument("--edt-layout", type=int, default=-1, choices=[-1, 0, 1],
                     help="distance-transform band layout (-1: chosen per call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -252,6 +253,34 @@ def served_leg(disc, di, dev, seconds: float):
     return res
 
 
+# ---------------------------------------------------------------- query leg
+
+def query_leg(disc, di, reps: int = 20):
+    """Open-vocabulary query: 1024 text embeddings against 8000 instance
+    embeddings (the mask count of the large FP8 workload) of width 1024,
+    top-10 per query.  The similarity GEMM is timed against the FP32 MFMA
+    peak (2 q m e flops)."""
+    import torch
+
+    m, e, q, k = 8000, 1024, 1024, 10
+    emb = torch.from_numpy(di.normal_rows(di.frame_seed(6, 0), m, e, "f32")[0]).cuda()
+    text = torch.from_numpy(di.normal_rows(di.frame_seed(6, 1), q, e, "f32")[0]).cuda()
+    for _ in range(3):
+        disc.query_topk(emb, text, k)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        disc.query_topk(emb, text, k)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    flops = 2.0 * q * m * e
+    return {"queries": q, "instances": m, "width": e, "k": k, "ms_per_call": ms,
+            "queries_per_s": q / (ms / 1000.0), "sim_tflops": flops / (ms / 1000.0) / 1e12,
+            "sim_frac_of_fp32_mfma_peak": flops / (ms / 1000.0) / 1e12 / PEAK_TFLOPS["f32"]}
+
+
 # ---------------------------------------------------------------- main
 
 def main():
@@ -327,6 +356,7 @@ def main():
     served = None
     if not args.no_serve and args.config == "cfg2":
         served = served_leg(disc, di, dev, args.serve_seconds)
+    query = None if args.no_query else query_leg(disc, di)
 
     # CPU baseline: the FP64 oracle as it stands, one core, bounded sample
     cpu = None
@@ -370,6 +400,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "served_bf16": served,
+        "query_topk": query,
     }
     print(json.dumps(res))
 

@@ -188,6 +188,25 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* w, int32_t
 /* Pack bool/uint8 masks u8[m][h][w] (non-zero = inside) into the bit layout. */
 disc_status disc_pack_masks(const uint8_t* u8, int32_t m, int32_t h, int32_t w, uint64_t* bits, void* stream);
 
+/* ---- open-vocabulary query (consumer of the embeddings) ---- */
+
+/* For each of q text embeddings, the k instances whose embeddings are most
+ * similar (arXiv 2603.03935, Sec. III-C: instances are retrieved by the cosine
+ * similarity of their CLIP-space embedding with a text embedding).
+ *   emb    [m][e] FP32 instance embeddings (e.g. the rows disc_embed_* wrote;
+ *          they need not be normalised).
+ *   text   [q][e] text embeddings, text_dtype DISC_F32 or DISC_BF16.
+ *   sim    [q][m] FP32, written: sim[j][i] = cos(text_j, emb_i), 0 when either
+ *          vector is zero (caller-owned; also the scratch of the ranking).
+ *   scores [q][k] FP32 and idx [q][k] int32, written: per query the k best
+ *          instances, higher similarity first, ties to the lower index;
+ *          idx -1 and score -inf past m.
+ * All pointers are device pointers, 16-byte aligned; e a multiple of 16 up
+ * to 4096, 1 <= k <= 256, m <= 2^24.  Invalid arguments: nothing is
+ * enqueued, DISC_ERR_* is returned.  Asynchronous on `stream`. */
+disc_status disc_query_topk(const float* emb, int32_t m, const void* text, int32_t text_dtype, int32_t q, int32_t e,
+                            int32_t k, float* sim, float* scores, int32_t* idx, void* stream);
+
 /* ---- serving ---- */
 
 /* A continuous-batching request loop on one device (the view-quality

@@ -39,6 +39,7 @@ EXPORTS = [
     "disc_trace_enable", "disc_trace_reset", "disc_trace_read", "disc_trace_stage_name",
     "disc_server_config_default", "disc_server_create", "disc_server_submit", "disc_server_poll",
     "disc_server_wait", "disc_server_drain", "disc_server_get_stats", "disc_server_destroy",
+    "disc_query_topk",
 ]
 STAGES = ["scan", "token_stats", "edt", "weights", "pool", "proj"]
 
@@ -118,6 +119,7 @@ def load(path: str = LIB_PATH):
     lib.disc_token_stats.argtypes = [P(Tokens), ctypes.c_float, vp, vp, vp, vp]
     lib.disc_pool_project.argtypes = [P(Tokens), vp, i32, P(Proj), P(Out), i32, vp]
     lib.disc_pack_masks.argtypes = [vp, i32, i32, i32, vp, vp]
+    lib.disc_query_topk.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp, vp, vp, vp]
     lib.disc_last_error.argtypes = []
     lib.disc_last_error.restype = ctypes.c_char_p
     lib.disc_trace_enable.argtypes = [i32]
@@ -144,7 +146,8 @@ def load(path: str = LIB_PATH):
     lib.disc_abi_version.argtypes = []
     lib.disc_abi_version.restype = i32
     for name in ("disc_embed_masks", "disc_embed_masks_ex", "disc_embed_frames", "disc_release_workspace",
-                 "disc_edt_sq", "disc_patch_weights", "disc_token_stats", "disc_pool_project", "disc_pack_masks"):
+                 "disc_edt_sq", "disc_patch_weights", "disc_token_stats", "disc_pool_project", "disc_pack_masks",
+                 "disc_query_topk"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -363,6 +366,20 @@ def pack_masks(u8, stream=None):
     src = u8.to(torch.uint8).contiguous()
     _check(load().disc_pack_masks(_ptr(src), m, h, w, _ptr(bits), _stream_handle(stream)))
     return bits
+
+
+def query_topk(emb, text, k: int, stream=None):
+    """disc_query_topk -> (scores [q][k] float32, idx [q][k] int32, sim [q][m] float32)."""
+    torch = _torch()
+    m, e = emb.shape
+    q = text.shape[0]
+    sim = torch.empty((q, max(m, 1)), dtype=torch.float32, device=text.device)
+    scores = torch.empty((q, k), dtype=torch.float32, device=text.device)
+    idx = torch.empty((q, k), dtype=torch.int32, device=text.device)
+    tdt = DISC_BF16 if text.dtype == torch.bfloat16 else DISC_F32
+    _check(load().disc_query_topk(_ptr(emb), m, _ptr(text), tdt, q, e, k, _ptr(sim), _ptr(scores), _ptr(idx),
+                                  _stream_handle(stream)))
+    return scores, idx, sim[:, :m]
 
 
 def release_workspace():

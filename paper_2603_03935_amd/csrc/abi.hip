@@ -848,6 +848,32 @@ disc_status disc_pack_masks(const uint8_t* u8, int32_t m, int32_t h, int32_t w, 
   return ok();
 }
 
+disc_status disc_query_topk(const float* emb, int32_t m, const void* text, int32_t text_dtype, int32_t q, int32_t e,
+                            int32_t k, float* sim, float* scores, int32_t* idx, void* stream) {
+  const char* who = "disc_query_topk";
+  if (m < 0 || q < 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: negative count (m %d, q %d)", who, m, q);
+  if (e <= 0 || e % 16 != 0 || e > 4096)
+    return fail(DISC_ERR_LIMIT, "%s: embedding width %d must be a multiple of 16 up to 4096", who, e);
+  if (k < 1 || k > 256) return fail(DISC_ERR_LIMIT, "%s: k = %d outside [1, 256]", who, k);
+  if (m > (1 << 24)) return fail(DISC_ERR_LIMIT, "%s: m = %d exceeds 2^24", who, m);
+  if (text_dtype != DISC_F32 && text_dtype != DISC_BF16)
+    return fail(DISC_ERR_UNSUPPORTED_DTYPE, "%s: text dtype must be F32 or BF16", who);
+  if (q == 0) return ok();
+  if (!text || !sim || !scores || !idx || (m > 0 && !emb)) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL pointer", who);
+  if ((m > 0 && !aligned16(emb)) || !aligned16(text) || !aligned16(sim) || !aligned16(scores) || !aligned16(idx))
+    return fail(DISC_ERR_ALIGNMENT, "%s: pointers must be 16-byte aligned", who);
+  Layout L{};
+  L.staged_end = 0;
+  L.total = (size_t)round_up(4 * ((int64_t)m + q), 256);
+  Ctx cx;
+  disc_status st;
+  if ((st = acquire(static_cast<hipStream_t>(stream), L, nullptr, cx))) return st;
+  launch_query(emb, m, text, text_dtype == DISC_BF16, q, e, k, reinterpret_cast<float*>(cx.dev_ws), sim, scores, idx,
+               cx.st);
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
 }  // extern "C"
 
 extern "C" {

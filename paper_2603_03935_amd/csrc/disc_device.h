@@ -137,6 +137,9 @@ bool pool_nt_valid(int C, int nt);
 void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st);
 // stage helpers
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+// open-vocabulary query: inv holds m + q floats of scratch
+void launch_query(const float* emb, int m, const void* text, int text_bf16, int q, int e, int k, float* inv,
+                  float* sim, float* scores, int32_t* idx, hipStream_t st);
 void launch_pack(const uint8_t* u8, int m, int h, int w, uint64_t* bits, hipStream_t st);
 void launch_dense_weights(const Batch& b, const Work& w, float* out, float eps, hipStream_t st);
 void launch_d_from_r(const float* r, int G, float eps, float* D, hipStream_t st);

@@ -133,3 +133,15 @@ def test_zero_masks_is_noop(lib):
     m.m = 0
     o.m = 0
     assert call(lib, t, m, p, o) == 0
+
+
+def test_query_validation(lib):
+    """disc_query_topk rejects bad arguments on the host (nothing is launched)."""
+    def q(m=10, e=64, k=4, dt=disc.DISC_F32, qn=3, text=FAKE, sim=FAKE):
+        return lib.disc_query_topk(FAKE, m, text, dt, qn, e, k, sim, FAKE, FAKE, None)
+    assert q(e=60) == 9 and q(e=0) == 9 and q(e=8192) == 9
+    assert q(k=0) == 9 and q(k=257) == 9
+    assert q(dt=disc.DISC_F8E4M3) == 3
+    assert q(m=-1) == 1 and q(text=None) == 1 and q(sim=None) == 1
+    assert q(text=FAKE + 8) == 4
+    assert q(qn=0) == 0  # no queries: nothing to do

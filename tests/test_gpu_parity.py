@@ -306,3 +306,65 @@ def test_pool_tile_widths_agree_bitwise(gpu, name, frames):
     for nt in (1, 2, 4):
         for i, (a, b) in enumerate(zip(res[-1], res[nt])):
             assert np.array_equal(a, b), f"{name}: pool_tile {nt} differs from the tuned width on frame {i}"
+
+
+# ---------------------------------------------------------------- open-vocabulary query
+
+def _check_topk(scores, idx, ref, tol, what):
+    """Scores within tol of the oracle's; indices identical where the oracle's
+    consecutive scores are separated by more than 2 tol, otherwise any index
+    whose oracle similarity is within tol of the oracle's score at that rank."""
+    q, k = ref["idx"].shape
+    for j in range(q):
+        assert np.allclose(scores[j], ref["scores"][j], rtol=0, atol=tol), f"{what}: scores of query {j}"
+        for r in range(k):
+            want = ref["idx"][j, r]
+            if want < 0:
+                assert idx[j, r] == -1
+                continue
+            s = ref["scores"][j]
+            gap_ok = (r == 0 or s[r - 1] - s[r] > 2 * tol) and (r == k - 1 or s[r] - s[r + 1] > 2 * tol)
+            if gap_ok:
+                assert idx[j, r] == want, f"{what}: query {j} rank {r}: {idx[j, r]} vs {want}"
+            else:
+                assert abs(ref["sim"][j, idx[j, r]] - s[r]) <= tol, f"{what}: query {j} rank {r} near-tie invalid"
+        assert len(set(idx[j][idx[j] >= 0].tolist())) == int((idx[j] >= 0).sum()), "an instance listed twice"
+
+
+@pytest.mark.parametrize("tdt", ["f32", "bf16"])
+def test_query_topk_vs_oracle(gpu, tdt):
+    t = torch()
+    rng = np.random.default_rng(41)
+    m, e, q, k = 3001, 768, 37, 10
+    emb = rng.standard_normal((m, e)).astype(np.float32)
+    emb[7] = 0.0
+    emb[100:110] = emb[99]  # exact ties: lower index first
+    text = rng.standard_normal((q, e)).astype(np.float32)
+    text[3] = emb[100] * 2.0  # best match: the tied group, in index order
+    if tdt == "bf16":
+        tq, _ = di.quantize(text.astype(np.float64), "bf16")
+        text_dev = t.from_numpy(tq.view(np.int16)).cuda().view(t.bfloat16)
+        text_ref = oracle.decode_tokens(tq.reshape(1, q, e), "bf16").reshape(q, e)
+    else:
+        text_dev = t.from_numpy(text).cuda()
+        text_ref = text.astype(np.float64)
+    scores, idx, sim = gpu.query_topk(t.from_numpy(emb).cuda(), text_dev, k)
+    ref = oracle.query_topk(emb.astype(np.float64), text_ref, k)
+    tol = 2e-6
+    assert np.abs(sim.cpu().numpy() - ref["sim"]).max() <= tol
+    _check_topk(scores.cpu().numpy(), idx.cpu().numpy(), ref, tol, tdt)
+    assert idx.cpu().numpy()[3].tolist() == list(range(99, 109)), "identical instances rank by index"
+
+
+def test_query_topk_on_embeddings(gpu):
+    """The query over the embeddings of a frame, k larger than m (padding)."""
+    t = torch()
+    fr = di.workload("cfg1").frames[0]
+    P = di.workload("cfg1").proj
+    out = gpu.embed_frames([frame_input(fr)], dev_proj(P, "f32"))[0].out
+    rng = np.random.default_rng(43)
+    text = rng.standard_normal((5, 768)).astype(np.float32)
+    scores, idx, sim = gpu.query_topk(out, t.from_numpy(text).cuda(), 12)
+    ref = oracle.query_topk(out.cpu().numpy().astype(np.float64), text.astype(np.float64), 12)
+    _check_topk(scores.cpu().numpy(), idx.cpu().numpy(), ref, 2e-6, "cfg1 embeddings")
+    assert (idx.cpu().numpy()[:, 8:] == -1).all() and np.isinf(scores.cpu().numpy()[:, 8:]).all()
