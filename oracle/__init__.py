@@ -49,9 +49,14 @@ def _declare(lib):
                                       vp, vp, vp, vp, vp]
     lib.disc_oracle_pool_project.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp]
     lib.disc_oracle_query_topk.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp, vp]
+    lib.disc_oracle_mask_dbar.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, vp]
+    lib.disc_oracle_angle_score.argtypes = [vp, vp, vp, i32, vp]
+    lib.disc_oracle_view_quality.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, dbl, vp, vp]
+    lib.disc_oracle_fuse.argtypes = [vp, vp, vp, i32, i32, vp, vp, i32, vp]
     for f in (lib.disc_oracle_edt_sq, lib.disc_oracle_edt_sq_batch, lib.disc_oracle_spatial_weights,
               lib.disc_oracle_token_stats, lib.disc_oracle_embed, lib.disc_oracle_pool_project,
-              lib.disc_oracle_query_topk):
+              lib.disc_oracle_query_topk, lib.disc_oracle_mask_dbar, lib.disc_oracle_angle_score,
+              lib.disc_oracle_view_quality, lib.disc_oracle_fuse):
         f.restype = ctypes.c_int
     return lib
 
@@ -158,6 +163,51 @@ class Oracle:
         _check(self.lib.disc_oracle_query_topk(_p(emb), m, _p(text), q, e, k, _p(sim), _p(scores), _p(idx)))
         return {"sim": sim, "scores": scores, "idx": idx}
 
+    def mask_dbar(self, bits: np.ndarray, w: int, patch: int, D: np.ndarray):
+        """R-Q: (Dbar [m], area [m]) of each mask given the frame's D [G]."""
+        bits = np.ascontiguousarray(bits)
+        m, h, _ = bits.shape
+        gh, gw = -(-h // patch), -(-w // patch)
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        dbar = np.zeros(m)
+        area = np.zeros(m, dtype=np.int32)
+        _check(self.lib.disc_oracle_mask_dbar(_p(bits), m, h, w, patch, gh, gw, _p(D), _p(dbar), _p(area)))
+        return dbar, area
+
+    def angle_score(self, rays: np.ndarray, normals: np.ndarray, off: np.ndarray) -> np.ndarray:
+        rays = np.ascontiguousarray(rays, dtype=np.float64)
+        normals = np.ascontiguousarray(normals, dtype=np.float64)
+        off = np.ascontiguousarray(off, dtype=np.int32)
+        m = len(off) - 1
+        out = np.zeros(m)
+        _check(self.lib.disc_oracle_angle_score(_p(rays), _p(normals), _p(off), m, _p(out)))
+        return out
+
+    def view_quality(self, area, dbar, emb, g, angle, H: int, W: int, lam: float = 3.3):
+        area = np.ascontiguousarray(area, dtype=np.int32)
+        dbar = np.ascontiguousarray(dbar, dtype=np.float64)
+        emb = np.ascontiguousarray(emb, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        ang = None if angle is None else np.ascontiguousarray(angle, dtype=np.float64)
+        m, e = emb.shape
+        Q = np.zeros(m)
+        comp = np.zeros((m, 4))
+        _check(self.lib.disc_oracle_view_quality(_p(area), _p(dbar), _p(emb), _p(g), _p(ang), m, e, H, W, lam,
+                                                 _p(Q), _p(comp)))
+        return Q, comp
+
+    def fuse(self, ids, q, emb, map_q, map_emb):
+        """R-FUSE on copies of the map; returns (map_q, map_emb, won)."""
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        emb = np.ascontiguousarray(emb, dtype=np.float64)
+        mq = np.array(map_q, dtype=np.float64)
+        me = np.array(map_emb, dtype=np.float64)
+        m, e = emb.shape
+        won = np.zeros(m, dtype=np.int32)
+        _check(self.lib.disc_oracle_fuse(_p(ids), _p(q), _p(emb), m, e, _p(mq), _p(me), len(mq), _p(won)))
+        return mq, me, won
+
     def proj_to_f64(self, P: np.ndarray, dtype: str) -> np.ndarray:
         """Caller-format projection [C][E] -> float64."""
         C, E = P.shape
@@ -207,6 +257,22 @@ def pool_project(f, wts, P):
 
 def query_topk(emb, text, k):
     return get().query_topk(emb, text, k)
+
+
+def mask_dbar(bits, w, patch, D):
+    return get().mask_dbar(bits, w, patch, D)
+
+
+def angle_score(rays, normals, off):
+    return get().angle_score(rays, normals, off)
+
+
+def view_quality(*args, **kw):
+    return get().view_quality(*args, **kw)
+
+
+def fuse(ids, q, emb, map_q, map_emb):
+    return get().fuse(ids, q, emb, map_q, map_emb)
 
 
 def proj_to_f64(P, dtype):

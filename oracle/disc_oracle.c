@@ -372,3 +372,98 @@ int disc_oracle_query_topk(const double* emb, int32_t m, const double* text, int
   free(used);
   return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* View quality and fusion (R-Q, R-FUSE)                                */
+/* ------------------------------------------------------------------ */
+
+int disc_oracle_mask_dbar(const uint64_t* bits, int32_t m, int32_t h, int32_t w, int32_t patch, int32_t gh,
+                          int32_t gw, const double* D, double* dbar, int32_t* area) {
+  if (!bits || !D || !dbar || !area || m < 0 || h <= 0 || w <= 0 || patch <= 0) return -1;
+  if (gh != (h + patch - 1) / patch || gw != (w + patch - 1) / patch) return -1;
+  const int32_t wq = (w + 63) / 64;
+  for (int32_t i = 0; i < m; ++i) {
+    const uint64_t* mb = bits + (int64_t)i * h * wq;
+    double acc = 0.0;
+    int32_t cnt = 0;
+    for (int32_t y = 0; y < h; ++y)
+      for (int32_t x = 0; x < w; ++x)
+        if ((mb[(int64_t)y * wq + x / 64] >> (x % 64)) & 1u) {
+          acc += D[(int64_t)(y / patch) * gw + (x / patch)];
+          ++cnt;
+        }
+    area[i] = cnt;
+    dbar[i] = cnt > 0 ? acc / (double)cnt : 0.0;
+  }
+  return 0;
+}
+
+int disc_oracle_angle_score(const double* rays, const double* normals, const int32_t* off, int32_t m,
+                            double* angle) {
+  if (!off || !angle || m < 0) return -1;
+  for (int32_t i = 0; i < m; ++i) {
+    const int32_t a = off[i], b = off[i + 1];
+    if (b < a) return -1;
+    double s = 0.0;
+    for (int32_t v = a; v < b; ++v) {
+      const double* r = rays + (int64_t)3 * v;
+      const double* n = normals + (int64_t)3 * v;
+      const double c = -(r[0] * n[0] + r[1] * n[1] + r[2] * n[2]);
+      s += c > 0.0 ? c : 0.0;
+    }
+    angle[i] = b > a ? s / (double)(b - a) : 0.0;
+  }
+  return 0;
+}
+
+int disc_oracle_view_quality(const int32_t* area, const double* dbar, const double* emb, const double* g,
+                             const double* angle, int32_t m, int32_t e, int32_t H, int32_t W, double lambda,
+                             double* Q, double* comp) {
+  if (!area || !dbar || !emb || !g || !Q || m < 0 || e <= 0 || H <= 0 || W <= 0) return -1;
+  const double ng = norm2(g, e);
+  for (int32_t i = 0; i < m; ++i) {
+    const double* y = emb + (int64_t)i * e;
+    double size = lambda * (double)area[i] / ((double)H * (double)W);
+    if (size > 1.0) size = 1.0;
+    const double ny = norm2(y, e);
+    double d = 0.0;
+    for (int32_t c = 0; c < e; ++c) d += y[c] * g[c];
+    double sem = (ny > 0.0 && ng > 0.0) ? d / (ny * ng) : 0.0;
+    if (sem < 0.0) sem = 0.0;
+    if (sem > 1.0) sem = 1.0;
+    const double dist = 0.5 + 0.5 * dbar[i];
+    const double ang = angle ? angle[i] : 1.0;
+    Q[i] = size * ang * sem * dist;
+    if (comp) {
+      comp[4 * (int64_t)i] = size;
+      comp[4 * (int64_t)i + 1] = ang;
+      comp[4 * (int64_t)i + 2] = sem;
+      comp[4 * (int64_t)i + 3] = dist;
+    }
+  }
+  return 0;
+}
+
+int disc_oracle_fuse(const int32_t* ids, const double* q, const double* emb, int32_t m, int32_t e,
+                     double* map_q, double* map_emb, int32_t n_map, int32_t* won) {
+  if (!ids || !q || !emb || !map_q || !map_emb || m < 0 || e <= 0 || n_map < 0) return -1;
+  int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_map > 0 ? n_map : 1));
+  if (!owner) return -1;
+  for (int32_t t = 0; t < n_map; ++t) owner[t] = -1;
+  for (int32_t i = 0; i < m; ++i) {
+    const int32_t t = ids[i];
+    if (t < 0 || t >= n_map) continue;
+    if (q[i] > map_q[t]) {
+      map_q[t] = q[i];
+      for (int32_t c = 0; c < e; ++c) map_emb[(int64_t)t * e + c] = emb[(int64_t)i * e + c];
+      owner[t] = i;
+    }
+  }
+  if (won) {
+    for (int32_t i = 0; i < m; ++i) won[i] = 0;
+    for (int32_t t = 0; t < n_map; ++t)
+      if (owner[t] >= 0) won[owner[t]] = 1;
+  }
+  free(owner);
+  return 0;
+}

@@ -32,6 +32,17 @@
  *           embedding t and an instance embedding y is cos(t, y) (0 when
  *           either is the zero vector); a query returns the k instances of
  *           highest similarity, higher first, ties to the lower index.
+ *   R-Q     view quality (Sec. III-C, Eqs. 2-3): Q = S_size S_angle S_sem
+ *           S_dist with S_size = min(lambda |M| / (H W), 1), lambda = 3.3;
+ *           S_dist = 0.5 + 0.5 Dbar, Dbar = D of Eq. (1) averaged over the
+ *           mask's pixels (each pixel takes its patch's D; 0 for an empty
+ *           mask); S_sem = min(max(cos(y, g), 0), 1) with y the mask's
+ *           embedding and g the frame's global image embedding; S_angle =
+ *           mean over the detection's voxels of max(0, -r.n) (0 without
+ *           voxels), or a caller-given value.
+ *   R-FUSE  an observation replaces its instance's feature when its Q is
+ *           strictly higher than the instance's; observations are taken in
+ *           index order (so among equal Q the first wins).
  *
  * Parity status: every function below is pinned by tests that do not use the
  * oracle itself (brute force, closed forms, a library routine, invariants).
@@ -94,6 +105,24 @@ int disc_oracle_pool_project(const double* f, int32_t G, int32_t C, const double
  * -inf past m).  emb[m][e], text[q][e]. */
 int disc_oracle_query_topk(const double* emb, int32_t m, const double* text, int32_t q, int32_t e, int32_t k,
                            double* sim, double* scores, int32_t* idx);
+
+/* R-Q: Dbar[m] and area |M| [m] of each mask, given D[G] of the frame. */
+int disc_oracle_mask_dbar(const uint64_t* bits, int32_t m, int32_t h, int32_t w, int32_t patch, int32_t gh,
+                          int32_t gw, const double* D, double* dbar, int32_t* area);
+/* R-Q: S_angle[m] from voxel view rays and normals r[nv][3], n[nv][3], the
+ * voxels of mask i being [off[i], off[i+1]). */
+int disc_oracle_angle_score(const double* rays, const double* normals, const int32_t* off, int32_t m,
+                            double* angle);
+/* R-Q: Q[m] and the factors comp[m][4] = (S_size, S_angle, S_sem, S_dist)
+ * (comp may be NULL).  angle may be NULL (S_angle = 1). emb[m][e], g[e]. */
+int disc_oracle_view_quality(const int32_t* area, const double* dbar, const double* emb, const double* g,
+                             const double* angle, int32_t m, int32_t e, int32_t H, int32_t W, double lambda,
+                             double* Q, double* comp);
+/* R-FUSE: update map_q[n_map], map_emb[n_map][e] in place from observations
+ * (ids[m] in [0, n_map), or < 0 to skip; q[m]; emb[m][e]); won[m] (may be
+ * NULL) = 1 where the observation ends up in the map. */
+int disc_oracle_fuse(const int32_t* ids, const double* q, const double* emb, int32_t m, int32_t e,
+                     double* map_q, double* map_emb, int32_t n_map, int32_t* won);
 
 #ifdef __cplusplus
 }

@@ -427,6 +427,128 @@ def pin_query_bruteforce(orc, seed=31):
     assert r3["idx"][0].tolist() == [0, 1, 2]
 
 
+# ---------------------------------------------------------------- view quality and fusion (R-Q, R-FUSE)
+
+def pin_dbar_patch_counts(orc, seed=41):
+    """Dbar by patch pixel counts: sum_p count_p D_p / sum_p count_p, where
+    count_p (the mask's pixels in patch p) comes from a block sum of the u8
+    mask; a mask inside one patch takes that patch's D exactly."""
+    rng = np.random.default_rng(seed)
+    h, w, P = 23, 37, 5
+    gh, gw = -(-h // P), -(-w // P)
+    D = rng.uniform(0.1, 3.0, gh * gw)
+    u8 = random_masks(rng, 4, h, w, 0.35)
+    u8[3] = 0
+    u8[3, 11:14, 21:24] = 1  # inside patch (2, 4)
+    bits = di.pack_masks(u8)
+    dbar, area = orc.mask_dbar(bits, w, P, D)
+    for i in range(3):
+        cnt = block_sum(u8[i].astype(np.float64), P).reshape(-1)
+        assert area[i] == u8[i].sum()
+        assert abs(dbar[i] - (cnt * D).sum() / cnt.sum()) < 1e-12, f"Dbar of mask {i}"
+    assert area[3] == 9 and dbar[3] == D[2 * gw + 4]
+    empty = di.pack_masks(np.zeros((1, h, w), np.uint8))
+    d0, a0 = orc.mask_dbar(empty, w, P, D)
+    assert d0[0] == 0.0 and a0[0] == 0
+
+
+def pin_angle_closed_forms(orc):
+    """Head-on views score 1, grazing and back-facing views 0, a view at 60
+    degrees 1/2; the score is the per-voxel mean; no voxels gives 0."""
+    n = np.array([[0.0, 0.0, 1.0]] * 6)
+    c60 = np.cos(np.pi / 3)
+    rays = np.array([[0, 0, -1.0], [1.0, 0, 0], [0, 0, 1.0], [np.sin(np.pi / 3), 0, -c60], [0, -1.0, 0], [0, 0, -1.0]])
+    off = np.array([0, 1, 2, 3, 4, 6, 6], dtype=np.int32)
+    a = orc.angle_score(rays, n, off)
+    assert np.allclose(a, [1.0, 0.0, 0.0, 0.5, 0.5, 0.0], atol=1e-15), a
+    # rotation invariance: rotate rays and normals together
+    rng = np.random.default_rng(42)
+    R, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    rays2 = rng.standard_normal((40, 3))
+    rays2 /= np.linalg.norm(rays2, axis=1)[:, None]
+    n2 = rng.standard_normal((40, 3))
+    n2 /= np.linalg.norm(n2, axis=1)[:, None]
+    off2 = np.array([0, 7, 7, 25, 40], dtype=np.int32)
+    a2 = orc.angle_score(rays2, n2, off2)
+    a3 = orc.angle_score(rays2 @ R.T, n2 @ R.T, off2)
+    assert np.allclose(a2, a3, atol=1e-14)
+    want = [np.mean(np.maximum(0, -np.einsum("ij,ij->i", rays2[s:t], n2[s:t]))) if t > s else 0.0
+            for s, t in zip(off2[:-1], off2[1:])]
+    assert np.allclose(a2, want, atol=1e-14)
+
+
+def pin_quality_factors(orc):
+    """Each factor from its closed form: S_size grows linearly with the area
+    up to the plateau at H W / lambda; S_sem is the cosine clipped to [0, 1]
+    (1 along g, 1/sqrt(2) at 45 degrees, 0 orthogonal or opposite); S_dist
+    maps Dbar in [0, 1] onto [1/2, 1]; Q is the product."""
+    H, W = 30, 40
+    g = np.array([0.0, 2.0, 0.0])
+    emb = np.array([[0, 5.0, 0], [1.0, 1.0, 0], [1.0, 0, 0], [0, -1.0, 0], [0, 3.0, 0]])
+    area = np.array([100, 0, 1200, 363, 364], dtype=np.int32)
+    dbar = np.array([0.0, 1.0, 0.4, 2.0, 1.0])
+    ang = np.array([1.0, 0.25, 1.0, 1.0, 0.5])
+    Q, comp = orc.view_quality(area, dbar, emb, g, ang, H, W)
+    size = np.array([3.3 * 100 / 1200, 0.0, 1.0, 3.3 * 363 / 1200, 1.0])
+    assert np.allclose(comp[:, 0], size, atol=1e-15)
+    assert np.allclose(comp[:, 2], [1.0, 1 / np.sqrt(2), 0.0, 0.0, 1.0], atol=1e-15)
+    assert np.allclose(comp[:, 3], [0.5, 1.0, 0.7, 1.5, 1.0], atol=1e-15)
+    assert np.array_equal(comp[:, 1], ang)
+    assert np.allclose(Q, comp.prod(axis=1), atol=1e-15)
+    assert Q[4] == 0.5 and Q[1] == 0.0
+    Q2, _ = orc.view_quality(area, dbar, 7.0 * emb, 0.1 * g, ang, H, W)
+    assert np.allclose(Q2, Q, atol=1e-15), "Q does not depend on the embeddings' scale"
+    Qn, compn = orc.view_quality(area, dbar, emb, g, None, H, W)
+    assert np.array_equal(compn[:, 1], np.ones(5)), "no angle input: S_angle = 1"
+    Qz, _ = orc.view_quality(area, dbar, np.zeros_like(emb), g, ang, H, W)
+    assert np.array_equal(Qz, np.zeros(5)), "a zero embedding has S_sem = 0"
+
+
+def _fuse_argmax(ids, q, map_q, n_map):
+    """Winner per instance: the first observation of the largest Q above the
+    instance's current Q."""
+    win = {}
+    for t in range(n_map):
+        cand = [i for i in range(len(ids)) if ids[i] == t and q[i] > map_q[t]]
+        if cand:
+            best = max(q[i] for i in cand)
+            win[t] = min(i for i in cand if q[i] == best)
+    return win
+
+
+def pin_fuse_argmax(orc, seed=43):
+    """Fusion equals a per-instance argmax over the observations (ties to the
+    first) gated by the stored Q; untouched instances keep their feature."""
+    rng = np.random.default_rng(seed)
+    n_map, m, e = 9, 40, 5
+    map_q = rng.uniform(0.2, 0.6, n_map)
+    map_q[2] = 2.0  # never beaten
+    map_emb = rng.standard_normal((n_map, e))
+    ids = rng.integers(-1, n_map, m).astype(np.int32)
+    ids[ids == 7] = 6  # instance 7 is never observed
+    q = np.round(rng.uniform(0.0, 1.0, m), 1)  # many exact ties
+    emb = rng.standard_normal((m, e))
+    mq, me, won = orc.fuse(ids, q, emb, map_q, map_emb)
+    win = _fuse_argmax(ids, q, map_q, n_map)
+    for t in range(n_map):
+        if t in win:
+            assert mq[t] == q[win[t]] and np.array_equal(me[t], emb[win[t]]), f"instance {t}"
+        else:
+            assert mq[t] == map_q[t] and np.array_equal(me[t], map_emb[t]), f"instance {t} untouched"
+    assert sorted(np.nonzero(won)[0].tolist()) == sorted(win.values())
+    assert 7 not in win and 2 not in win
+    # feeding the observations one at a time gives the same map
+    mq1, me1 = map_q.copy(), map_emb.copy()
+    for i in range(m):
+        mq1, me1, _ = orc.fuse(ids[i:i + 1], q[i:i + 1], emb[i:i + 1], mq1, me1)
+    assert np.array_equal(mq1, mq) and np.array_equal(me1, me)
+    # explicit ties: the first of two equal observations wins; an observation
+    # equal to the stored Q does not replace it
+    mq2, me2, won2 = orc.fuse(np.array([0, 0, 1], np.int32), np.array([0.9, 0.9, 0.5]), emb[:3],
+                              np.array([0.1, 0.5]), map_emb[:2])
+    assert won2.tolist() == [1, 0, 0] and np.array_equal(me2[0], emb[0]) and np.array_equal(me2[1], map_emb[1])
+
+
 ALL_PINS = [
     ("edt_exhaustive_4x4", lambda o: pin_edt_exhaustive(o, 4, 4)),
     ("edt_random_bruteforce", pin_edt_random_bruteforce),
@@ -448,4 +570,8 @@ ALL_PINS = [
     ("decoders", pin_decoders),
     ("query_orthonormal", pin_query_orthonormal),
     ("query_bruteforce", pin_query_bruteforce),
+    ("dbar_patch_counts", pin_dbar_patch_counts),
+    ("angle_closed_forms", pin_angle_closed_forms),
+    ("quality_factors", pin_quality_factors),
+    ("fuse_argmax", pin_fuse_argmax),
 ]

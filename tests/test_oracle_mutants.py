@@ -46,6 +46,17 @@ MUTANTS = [
      "row[i] = (nt > 0.0 && ny > 0.0) ? d / ny : 0.0;"),
     ("query_ties_to_higher_index", "if (!used[i] && (best < 0 || row[i] > row[best])) best = i;",
      "if (!used[i] && (best < 0 || row[i] >= row[best])) best = i;"),
+    ("dbar_patch_transposed", "acc += D[(int64_t)(y / patch) * gw + (x / patch)];",
+     "acc += D[(int64_t)(x / patch) * gh + (y / patch)];"),
+    ("angle_sign", "const double c = -(r[0] * n[0] + r[1] * n[1] + r[2] * n[2]);",
+     "const double c = (r[0] * n[0] + r[1] * n[1] + r[2] * n[2]);"),
+    ("angle_not_averaged", "angle[i] = b > a ? s / (double)(b - a) : 0.0;", "angle[i] = s;"),
+    ("size_no_lambda", "double size = lambda * (double)area[i] / ((double)H * (double)W);",
+     "double size = (double)area[i] / ((double)H * (double)W);"),
+    ("size_no_plateau", "if (size > 1.0) size = 1.0;", "(void)0;"),
+    ("sem_not_rectified", "if (sem < 0.0) sem = 0.0;", "(void)0;"),
+    ("dist_not_affine", "const double dist = 0.5 + 0.5 * dbar[i];", "const double dist = dbar[i];"),
+    ("fuse_ties_to_last", "if (q[i] > map_q[t]) {", "if (q[i] >= map_q[t]) {"),
 ]
 
 
