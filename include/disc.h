@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define DISC_ABI_VERSION 3
+#define DISC_ABI_VERSION 4
 
 typedef enum disc_status {
   DISC_OK = 0,
@@ -113,6 +113,11 @@ typedef struct disc_out {
   int32_t m, e;
   int32_t* mask_status; /* optional [m]: 0 ok, 1 empty mask, 2 zero projection */
   float* pooled;        /* optional [m][c] FP32 weighted-mean features F */
+  float* dbar;          /* optional [m]: the mask's mean distinctiveness, D of
+                           Eq. (1) (with eps) averaged over the mask's pixels,
+                           each pixel taking its patch's D; 0 for an empty mask
+                           (the S_dist input of the view quality, Sec. III-C) */
+  int32_t* area;        /* optional [m]: the mask's pixel count |M| */
 } disc_out;
 
 typedef struct disc_options {
@@ -206,6 +211,52 @@ disc_status disc_pack_masks(const uint8_t* u8, int32_t m, int32_t h, int32_t w, 
  * enqueued, DISC_ERR_* is returned.  Asynchronous on `stream`. */
 disc_status disc_query_topk(const float* emb, int32_t m, const void* text, int32_t text_dtype, int32_t q, int32_t e,
                             int32_t k, float* sim, float* scores, int32_t* idx, void* stream);
+
+/* ---- view quality and fusion (consumers of the embeddings) ---- */
+
+/* View quality of each observation (arXiv 2603.03935, Sec. III-C, Eqs. 2-3):
+ *   Q = S_size * S_angle * S_sem * S_dist
+ *   S_size  = min(lambda * area / (img_h * img_w), 1)   (the paper: lambda = 3.3)
+ *   S_angle = angle[i], or 1 when angle is NULL (see disc_angle_score)
+ *   S_sem   = min(max(cos(emb_i, g), 0), 1), 0 when either vector is zero
+ *   S_dist  = 0.5 + 0.5 * dbar[i]
+ *   area [m] int32 and dbar [m] FP32 (e.g. what disc_embed_* wrote to
+ *   disc_out.area / .dbar), emb [m][e] FP32 (the mask's embedding), g [e]
+ *   FP32 (the frame's global image embedding), angle [m] FP32 or NULL.
+ *   q [m] FP32, written; comp [m][4] FP32 or NULL, written with
+ *   (S_size, S_angle, S_sem, S_dist).
+ * Device pointers; emb and g 16-byte aligned; e a multiple of 4 up to 4096;
+ * img_h, img_w >= 1; lambda > 0.  Invalid arguments: nothing is enqueued,
+ * DISC_ERR_* is returned.  Asynchronous on `stream`. */
+disc_status disc_view_quality(const int32_t* area, const float* dbar, const float* emb, const float* g,
+                              const float* angle, int32_t m, int32_t e, int32_t img_h, int32_t img_w, float lambda,
+                              float* q, float* comp, void* stream);
+
+/* S_angle of Eq. (3): for detection i, the mean over its voxels v of
+ * max(0, -r_v . n_v), r_v the unit viewing ray and n_v the unit surface
+ * normal; 0 for a detection without voxels.
+ *   rays, normals [nv][3] FP32; off [m + 1] int32 (device): the voxels of
+ *   detection i are [off[i], off[i+1]) (indices clamped to [0, nv], an
+ *   inverted range counts as empty).  angle [m] FP32, written.
+ * Device pointers.  Asynchronous on `stream`. */
+disc_status disc_angle_score(const float* rays, const float* normals, int32_t nv, const int32_t* off, int32_t m,
+                             float* angle, void* stream);
+
+/* Feature fusion (Sec. III-C): an instance's feature is replaced by an
+ * observed feature of higher view quality.  Observations i < m target
+ * instance ids[i] (skipped unless 0 <= ids[i] < n_map) with quality q[i] and
+ * feature emb[i][e]; per instance the observation of the largest q above
+ * map_q[t] replaces map_q[t] and map_emb[t] (the first such observation
+ * among equal q), which is what taking the observations one by one in index
+ * order gives.  Instances that no observation beats keep their row.
+ *   ids [m] int32, q [m] FP32, emb [m][e] FP32, map_q [n_map] FP32 and
+ *   map_emb [n_map][e] FP32 (updated in place), won [m] int32 or NULL
+ *   (written: 1 where the observation entered the map).
+ * Device pointers, emb/map_emb 16-byte aligned, e a multiple of 4 up to 4096,
+ * n_map <= 2^28.  Asynchronous on `stream`; calls that update one map must
+ * be ordered (one stream). */
+disc_status disc_fuse(const int32_t* ids, const float* q, const float* emb, int32_t m, int32_t e, float* map_q,
+                      float* map_emb, int32_t n_map, int32_t* won, void* stream);
 
 /* ---- serving ---- */
 

@@ -12,6 +12,9 @@ Entry points mirror ``include/disc.h``:
 * :func:`embed_frames`  a ragged batch of frames in one call
 * :func:`edt_sq`, :func:`patch_weights`, :func:`token_stats`,
   :func:`pool_project`, :func:`pack_masks`  stage entry points
+* :func:`query_topk`    open-vocabulary retrieval over the embeddings
+* :func:`view_quality`, :func:`angle_score`, :func:`fuse`  view quality Q
+  and replace-if-higher feature fusion
 """
 from __future__ import annotations
 
@@ -39,7 +42,7 @@ EXPORTS = [
     "disc_trace_enable", "disc_trace_reset", "disc_trace_read", "disc_trace_stage_name",
     "disc_server_config_default", "disc_server_create", "disc_server_submit", "disc_server_poll",
     "disc_server_wait", "disc_server_drain", "disc_server_get_stats", "disc_server_destroy",
-    "disc_query_topk",
+    "disc_query_topk", "disc_view_quality", "disc_angle_score", "disc_fuse",
 ]
 STAGES = ["scan", "token_stats", "edt", "weights", "pool", "proj"]
 
@@ -68,7 +71,8 @@ class Proj(ctypes.Structure):
 
 class Out(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("m", ctypes.c_int32), ("e", ctypes.c_int32),
-                ("mask_status", ctypes.c_void_p), ("pooled", ctypes.c_void_p)]
+                ("mask_status", ctypes.c_void_p), ("pooled", ctypes.c_void_p),
+                ("dbar", ctypes.c_void_p), ("area", ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -120,6 +124,9 @@ def load(path: str = LIB_PATH):
     lib.disc_pool_project.argtypes = [P(Tokens), vp, i32, P(Proj), P(Out), i32, vp]
     lib.disc_pack_masks.argtypes = [vp, i32, i32, i32, vp, vp]
     lib.disc_query_topk.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp, vp, vp, vp]
+    lib.disc_view_quality.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, ctypes.c_float, vp, vp, vp]
+    lib.disc_angle_score.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+    lib.disc_fuse.argtypes = [vp, vp, vp, i32, i32, vp, vp, i32, vp, vp]
     lib.disc_last_error.argtypes = []
     lib.disc_last_error.restype = ctypes.c_char_p
     lib.disc_trace_enable.argtypes = [i32]
@@ -147,7 +154,7 @@ def load(path: str = LIB_PATH):
     lib.disc_abi_version.restype = i32
     for name in ("disc_embed_masks", "disc_embed_masks_ex", "disc_embed_frames", "disc_release_workspace",
                  "disc_edt_sq", "disc_patch_weights", "disc_token_stats", "disc_pool_project", "disc_pack_masks",
-                 "disc_query_topk"):
+                 "disc_query_topk", "disc_view_quality", "disc_angle_score", "disc_fuse"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -249,9 +256,13 @@ class FrameOutput:
     out: object          # float32 [m][e]
     status: object       # int32 [m]
     pooled: object = None  # float32 [m][c] when requested
+    dbar: object = None    # float32 [m] mean distinctiveness, when requested
+    area: object = None    # int32 [m] pixel counts, when requested
 
 
-def alloc_outputs(frames: Sequence[FrameInput], e: int, pooled: bool = False) -> List[FrameOutput]:
+def alloc_outputs(frames: Sequence[FrameInput], e: int, pooled: bool = False,
+                  quality: bool = False) -> List[FrameOutput]:
+    """Output buffers; quality=True adds dbar and area (the inputs of view_quality)."""
     torch = _torch()
     res = []
     for f in frames:
@@ -259,25 +270,33 @@ def alloc_outputs(frames: Sequence[FrameInput], e: int, pooled: bool = False) ->
         dev = f.tokens.device
         res.append(FrameOutput(torch.empty((m, e), dtype=torch.float32, device=dev),
                                torch.empty((m,), dtype=torch.int32, device=dev),
-                               torch.empty((m, f.tokens.shape[2]), dtype=torch.float32, device=dev) if pooled else None))
+                               torch.empty((m, f.tokens.shape[2]), dtype=torch.float32, device=dev) if pooled else None,
+                               torch.empty((m,), dtype=torch.float32, device=dev) if quality else None,
+                               torch.empty((m,), dtype=torch.int32, device=dev) if quality else None))
     return res
 
 
+def _out(o: "FrameOutput") -> "Out":
+    return Out(_ptr(o.out), o.out.shape[0], o.out.shape[1], _ptr(o.status), _ptr(o.pooled), _ptr(o.dbar),
+               _ptr(o.area))
+
+
 def embed_frames(frames: Sequence[FrameInput], proj, outputs: Optional[List[FrameOutput]] = None,
-                 pooled: bool = False, options: Optional[Options] = None, stream=None) -> List[FrameOutput]:
+                 pooled: bool = False, options: Optional[Options] = None, stream=None,
+                 quality: bool = False) -> List[FrameOutput]:
     """disc_embed_frames: one call for a ragged batch of frames."""
     lib = load()
     n = len(frames)
     e = proj.shape[1]
     if outputs is None:
-        outputs = alloc_outputs(frames, e, pooled)
+        outputs = alloc_outputs(frames, e, pooled, quality)
     toks = (Tokens * max(n, 1))()
     msks = (Masks * max(n, 1))()
     outs = (Out * max(n, 1))()
     for i, (f, o) in enumerate(zip(frames, outputs)):
         toks[i] = make_tokens(f.tokens, f.patch, f.scale)
         msks[i] = make_masks(f.bits, f.h, f.w)
-        outs[i] = Out(_ptr(o.out), o.out.shape[0], o.out.shape[1], _ptr(o.status), _ptr(o.pooled))
+        outs[i] = _out(o)
     pj = make_proj(proj)
     opts = options if options is not None else make_options()
     _check(lib.disc_embed_frames(toks, msks, n, ctypes.byref(pj), outs, ctypes.byref(opts), _stream_handle(stream)))
@@ -285,10 +304,10 @@ def embed_frames(frames: Sequence[FrameInput], proj, outputs: Optional[List[Fram
 
 
 def embed_masks(tokens, bits, h: int, w: int, proj, patch: int, scale=None, pooled: bool = False,
-                options: Optional[Options] = None, stream=None) -> FrameOutput:
+                options: Optional[Options] = None, stream=None, quality: bool = False) -> FrameOutput:
     """disc_embed_masks_ex for one frame."""
     return embed_frames([FrameInput(tokens, bits, h, w, patch, scale)], proj, pooled=pooled, options=options,
-                        stream=stream)[0]
+                        stream=stream, quality=quality)[0]
 
 
 def workspace_bytes(frames: Sequence[FrameInput], proj, options: Optional[Options] = None) -> int:
@@ -382,6 +401,38 @@ def query_topk(emb, text, k: int, stream=None):
     return scores, idx, sim[:, :m]
 
 
+def view_quality(area, dbar, emb, g, img_h: int, img_w: int, angle=None, lam: float = 3.3, stream=None):
+    """disc_view_quality -> (q [m] float32, comp [m][4] float32: S_size, S_angle, S_sem, S_dist)."""
+    torch = _torch()
+    m, e = emb.shape
+    q = torch.empty((m,), dtype=torch.float32, device=emb.device)
+    comp = torch.empty((m, 4), dtype=torch.float32, device=emb.device)
+    _check(load().disc_view_quality(_ptr(area), _ptr(dbar), _ptr(emb), _ptr(g), _ptr(angle), m, e, img_h, img_w,
+                                    lam, _ptr(q), _ptr(comp), _stream_handle(stream)))
+    return q, comp
+
+
+def angle_score(rays, normals, off, stream=None):
+    """disc_angle_score -> angle [m] float32 (rays, normals [nv][3]; off [m+1] int32)."""
+    torch = _torch()
+    m = off.shape[0] - 1
+    angle = torch.empty((max(m, 0),), dtype=torch.float32, device=off.device)
+    _check(load().disc_angle_score(_ptr(rays), _ptr(normals), rays.shape[0], _ptr(off), m, _ptr(angle),
+                                   _stream_handle(stream)))
+    return angle
+
+
+def fuse(ids, q, emb, map_q, map_emb, won=None, stream=None):
+    """disc_fuse: updates map_q / map_emb in place; returns won [m] int32."""
+    torch = _torch()
+    m, e = emb.shape
+    if won is None:
+        won = torch.empty((m,), dtype=torch.int32, device=emb.device)
+    _check(load().disc_fuse(_ptr(ids), _ptr(q), _ptr(emb), m, e, _ptr(map_q), _ptr(map_emb), map_q.shape[0],
+                            _ptr(won), _stream_handle(stream)))
+    return won
+
+
 def release_workspace():
     _check(load().disc_release_workspace())
 
@@ -445,13 +496,13 @@ class Server:
         self._keep[t.value] = keep
         return t.value
 
-    def submit_frame(self, frame: FrameInput, output: Optional[FrameOutput] = None):
+    def submit_frame(self, frame: FrameInput, output: Optional[FrameOutput] = None, quality: bool = False):
         """Submit one frame; returns (ticket, FrameOutput)."""
         if output is None:
-            output = alloc_outputs([frame], self.e)[0]
+            output = alloc_outputs([frame], self.e, quality=quality)[0]
         tk = make_tokens(frame.tokens, frame.patch, frame.scale)
         mk = make_masks(frame.bits, frame.h, frame.w)
-        o = Out(_ptr(output.out), output.out.shape[0], output.out.shape[1], _ptr(output.status), _ptr(output.pooled))
+        o = _out(output)
         return self.submit(tk, mk, o, keep=(frame, output)), output
 
     def poll(self, ticket: int):

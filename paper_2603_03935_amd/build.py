@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdisc.so")
-SOURCES = ["abi.hip", "serve.hip", "k_scan.hip", "k_edt.hip", "k_stats.hip", "k_gemm.hip", "k_query.hip"]
+SOURCES = ["abi.hip", "serve.hip", "k_scan.hip", "k_edt.hip", "k_stats.hip", "k_gemm.hip", "k_query.hip",
+           "k_quality.hip"]
 ARCH = os.environ.get("DISC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -107,8 +107,9 @@ disc_status check_out(const disc_out* o, int m, int e, const char* who) {
   if (o->m != m) return fail(DISC_ERR_SHAPE, "%s: out has %d rows for %d masks", who, o->m, m);
   if (o->e != e) return fail(DISC_ERR_SHAPE, "%s: out has width %d, projection %d", who, o->e, e);
   if ((o->data && !aligned16(o->data)) || (o->pooled && !aligned16(o->pooled)) ||
-      (o->mask_status && (reinterpret_cast<uintptr_t>(o->mask_status) & 3u)))
-    return fail(DISC_ERR_ALIGNMENT, "%s: output pointers must be 16-byte aligned", who);
+      (o->mask_status && (reinterpret_cast<uintptr_t>(o->mask_status) & 3u)) ||
+      (o->dbar && (reinterpret_cast<uintptr_t>(o->dbar) & 3u)) || (o->area && (reinterpret_cast<uintptr_t>(o->area) & 3u)))
+    return fail(DISC_ERR_ALIGNMENT, "%s: output pointers must be 16-byte aligned (status, dbar, area: 4)", who);
   return DISC_OK;
 }
 
@@ -159,6 +160,7 @@ Layout make_layout(const Shape& s) {
   L.psum = take(4 * (size_t)s.n_frames * s.nchunk * s.C);
   L.mean = take(4 * (size_t)s.n_frames * s.C);
   L.r = take(4 * (size_t)s.sumG);
+  L.rbar = take(4 * (size_t)s.n_frames);
   L.s = take(4 * (size_t)s.sumMGs);
   L.W = take((s.gemm_bf16 ? 2 : 4) * (size_t)s.sumMGs);
   L.Z = take(4 * (size_t)s.M);
@@ -271,6 +273,7 @@ Work work_ptrs(char* base, const Layout& L) {
   w.psum = reinterpret_cast<float*>(base + L.psum);
   w.mean = reinterpret_cast<float*>(base + L.mean);
   w.r = reinterpret_cast<float*>(base + L.r);
+  w.rbar = reinterpret_cast<float*>(base + L.rbar);
   w.s = reinterpret_cast<float*>(base + L.s);
   w.W = base + L.W;
   w.Z = reinterpret_cast<float*>(base + L.Z);
@@ -290,6 +293,7 @@ Work work_ptrs(char* base, const Layout& L) {
 void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p, int tok_dtype) {
   Shape& s = p.shape;
   s.n_frames = (int)fr.size();
+  s.want_dbar = false;
   s.C = C;
   s.E = E;
   s.gemm_bf16 = gemm_bf16;
@@ -306,6 +310,9 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
     d.out = f.out;
     d.status = f.status;
     d.pooled = f.pooled;
+    d.dbar = f.dbar;
+    d.area_out = f.area;
+    if (f.dbar) s.want_dbar = true;
     d.gh = f.gh;
     d.gw = f.gw;
     d.patch = f.patch;
@@ -433,6 +440,8 @@ disc_status describe(const disc_tokens* tokens, const disc_masks* masks, int32_t
     f.out = out[i].data;
     f.status = out[i].mask_status;
     f.pooled = out[i].pooled;
+    f.dbar = out[i].dbar;
+    f.area = out[i].area;
     f.gh = tokens[i].gh;
     f.gw = tokens[i].gw;
     f.patch = tokens[i].patch;
@@ -579,14 +588,18 @@ int pool_tile_choice(const Plan& p, int tok_dtype, const disc_options& o, bool t
 void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options& o, const disc_proj* proj, int cus,
                   hipStream_t st, bool trace, bool tune) {
   const int sid = trace ? 0 : -1;
-  const Batch b = make_batch(p, dev_ws, tok_dtype, o.spatial, o.distinct);
+  Batch b = make_batch(p, dev_ws, tok_dtype, o.spatial, o.distinct);
+  b.eps = o.eps;
   const Work w = work_ptrs(dev_ws, p.L);
   const int4* tiles = reinterpret_cast<const int4*>(dev_ws + p.L.tiles);
-  { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st); }
-  if (o.distinct || p.shape.gemm_bf16) {
+  // token statistics first: the mask scan folds r into the mean distinctiveness
+  const bool want_r = o.distinct || p.shape.want_dbar;
+  if (want_r || p.shape.gemm_bf16) {
     StageTimer t(sid < 0 ? -1 : ST_STATS, st);
-    launch_token_stats(b, w, p.shape.gmax, o.distinct, p.shape.gemm_bf16, st);
+    launch_token_stats(b, w, p.shape.gmax, want_r, p.shape.gemm_bf16, st);
+    if (p.shape.want_dbar) launch_rbar(b, w, st);
   }
+  { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st); }
   { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st, o.edt_layout); }
   { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); }
   {
@@ -870,6 +883,62 @@ disc_status disc_query_topk(const float* emb, int32_t m, const void* text, int32
   if ((st = acquire(static_cast<hipStream_t>(stream), L, nullptr, cx))) return st;
   launch_query(emb, m, text, text_dtype == DISC_BF16, q, e, k, reinterpret_cast<float*>(cx.dev_ws), sim, scores, idx,
                cx.st);
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_view_quality(const int32_t* area, const float* dbar, const float* emb, const float* g,
+                              const float* angle, int32_t m, int32_t e, int32_t img_h, int32_t img_w, float lambda,
+                              float* q, float* comp, void* stream) {
+  const char* who = "disc_view_quality";
+  if (m < 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: negative count %d", who, m);
+  if (e <= 0 || e % 4 != 0 || e > 4096)
+    return fail(DISC_ERR_LIMIT, "%s: embedding width %d must be a multiple of 4 up to 4096", who, e);
+  if (img_h < 1 || img_w < 1) return fail(DISC_ERR_SHAPE, "%s: image size %d x %d", who, img_h, img_w);
+  if (!(lambda > 0.f) || lambda > 1e30f) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: lambda must be positive", who);
+  if (m == 0) return ok();
+  if (!area || !dbar || !emb || !g || !q) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL pointer", who);
+  if (!aligned16(emb) || !aligned16(g) || (comp && !aligned16(comp)))
+    return fail(DISC_ERR_ALIGNMENT, "%s: emb, g and comp must be 16-byte aligned", who);
+  launch_quality(area, dbar, emb, g, angle, m, e, img_h, img_w, lambda, q, comp, static_cast<hipStream_t>(stream));
+  disc_status st;
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_angle_score(const float* rays, const float* normals, int32_t nv, const int32_t* off, int32_t m,
+                             float* angle, void* stream) {
+  const char* who = "disc_angle_score";
+  if (m < 0 || nv < 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: negative count (m %d, nv %d)", who, m, nv);
+  if (nv > (1 << 29)) return fail(DISC_ERR_LIMIT, "%s: nv = %d exceeds 2^29", who, nv);
+  if (m == 0) return ok();
+  if (!off || !angle || (nv > 0 && (!rays || !normals)))
+    return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL pointer", who);
+  launch_angle(rays, normals, nv, off, m, angle, static_cast<hipStream_t>(stream));
+  disc_status st;
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_fuse(const int32_t* ids, const float* q, const float* emb, int32_t m, int32_t e, float* map_q,
+                      float* map_emb, int32_t n_map, int32_t* won, void* stream) {
+  const char* who = "disc_fuse";
+  if (m < 0 || n_map < 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: negative count (m %d, n_map %d)", who, m, n_map);
+  if (e <= 0 || e % 4 != 0 || e > 4096)
+    return fail(DISC_ERR_LIMIT, "%s: embedding width %d must be a multiple of 4 up to 4096", who, e);
+  if (n_map > (1 << 28)) return fail(DISC_ERR_LIMIT, "%s: n_map = %d exceeds 2^28", who, n_map);
+  if (m == 0) return ok();
+  if (!ids || !q || !emb || (n_map > 0 && (!map_q || !map_emb)))
+    return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL pointer", who);
+  if (!aligned16(emb) || (n_map > 0 && !aligned16(map_emb)))
+    return fail(DISC_ERR_ALIGNMENT, "%s: emb and map_emb must be 16-byte aligned", who);
+  Layout L{};
+  L.staged_end = 0;
+  L.total = (size_t)round_up(8 * (int64_t)std::max(n_map, 1), 256);
+  Ctx cx;
+  disc_status st;
+  if ((st = acquire(static_cast<hipStream_t>(stream), L, nullptr, cx))) return st;
+  launch_fuse(ids, q, emb, m, e, map_q, map_emb, n_map, won, reinterpret_cast<uint64_t*>(cx.dev_ws), cx.st);
   if ((st = check_launch(who))) return st;
   return ok();
 }

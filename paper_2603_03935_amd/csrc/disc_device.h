@@ -75,6 +75,8 @@ struct FrameDesc {
   float* out;             // [m][E]
   int32_t* status;        // [m] or null
   float* pooled;          // [m][C] or null
+  float* dbar;            // [m] or null: mean D over the mask's pixels
+  int32_t* area_out;      // [m] or null: pixel counts
   int32_t gh, gw, patch, G;
   int32_t h, w, wq, m;
   int32_t mask_base;      // global index of this frame's first mask
@@ -101,6 +103,7 @@ struct Batch {
   int32_t n_tiles;            // pooling tiles (capacity)
   int32_t kgroups;            // pooling K groups of the largest frame
   int32_t pool_split, proj_split;  // workgroups sharing one GEMM tile's K range
+  float eps;                  // Eq. (1) epsilon (only the mean distinctiveness uses it)
 };
 
 // Workspace pointers (device).
@@ -114,6 +117,7 @@ struct Work {
   float* psum;         // [F][nchunk][C]
   float* mean;         // [F][C]
   float* r;            // [sum G]
+  float* rbar;         // [F] mean of r per frame (frames that ask for dbar)
   float* s;            // [sum m*Gs] spatial weights
   void* W;             // [sum m*Gs] GEMM-dtype weights
   float* Z;            // [M] weight sums
@@ -131,6 +135,13 @@ void edt_prepare();
 // want_r: residual norms (needs the mean); pack: k-packed token copy for the BF16 pooling GEMM
 void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
+void launch_rbar(const Batch& b, const Work& w, hipStream_t st);
+void launch_quality(const int32_t* area, const float* dbar, const float* emb, const float* g, const float* angle, int m,
+                    int e, int img_h, int img_w, float lambda, float* q, float* comp, hipStream_t st);
+void launch_angle(const float* rays, const float* normals, int nv, const int32_t* off, int m, float* angle,
+                  hipStream_t st);
+void launch_fuse(const int32_t* ids, const float* q, const float* emb, int m, int e, float* map_q, float* map_emb,
+                 int n_map, int32_t* won, uint64_t* best, hipStream_t st);
 // nt: 64-channel tiles per workgroup (1, 2 or 4; any value gives the same result)
 void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st, int nt = 1);
 bool pool_nt_valid(int C, int nt);

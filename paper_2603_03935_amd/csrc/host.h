@@ -13,7 +13,7 @@ namespace host {
 
 struct Layout {
   size_t frames, mask_frame, tiles, dyn, staged_end;  // staged region (uploaded from the host)
-  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, s, W, Z, mstat, X, ppart, qpart, tkp, total;
+  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, rbar, s, W, Z, mstat, X, ppart, qpart, tkp, total;
 };
 
 struct Shape {
@@ -24,6 +24,7 @@ struct Shape {
   int tkp_esize = 2;      // bytes per k-packed element (BF16)
   int kgroups = 1;        // pooling K groups of the largest frame
   int pool_split = 1, proj_split = 1;
+  bool want_dbar = false;  // some frame asks for the mean distinctiveness (needs r and its mean)
 };
 
 // Split K of the pooling / projection GEMMs when their tiles alone would not
@@ -37,6 +38,8 @@ struct FrameIn {
   float* out = nullptr;
   int32_t* status = nullptr;
   float* pooled = nullptr;
+  float* dbar = nullptr;
+  int32_t* area = nullptr;
   int gh = 0, gw = 0, patch = 16, h = 0, w = 0, m = 0;
 };
 

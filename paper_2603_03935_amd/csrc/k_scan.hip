@@ -9,6 +9,11 @@ namespace disc {
 // k_scan: one workgroup per mask streams the mask's h*wq words once (the only
 // full read of the mask bits) and reduces min/max row, min/max column and the
 // pixel count.  Columns >= w in the last word of a row are ignored.
+// For frames that ask for it, the same pass sums r_p over the mask's pixels
+// (each pixel takes its patch's r) and writes the mean distinctiveness
+//   dbar = sum_x r_p(x) / (|M| (mean(r) + eps))
+// i.e. D of Eq. (1) averaged over the mask's pixels; the token statistics
+// (r and its mean) run before the scan.
 // ---------------------------------------------------------------------------
 __device__ inline int wave_min(int v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
@@ -33,6 +38,9 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
   const int64_t nwords = (int64_t)h * wq;
 
   int ymin = INT32_MAX, ymax = -1, xmin = INT32_MAX, xmax = -1, area = 0;
+  const float* rf = fd.dbar ? wk.r + fd.r_base : nullptr;
+  const int P = fd.patch;
+  float rsum = 0.f;
   // walk words tid, tid+256, ... keeping (row, word) without a division per word
   int row = threadIdx.x / wq, k = threadIdx.x % wq;
   const int drow = 256 / wq, dk = 256 % wq;
@@ -45,6 +53,19 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
       xmin = min(xmin, 64 * k + __builtin_ctzll(v));
       xmax = max(xmax, 64 * k + 63 - __builtin_clzll(v));
       area += __builtin_popcountll(v);
+      if (rf) {
+        // split the word at patch-column boundaries; set bits lie at columns < w,
+        // so every patch read is inside the frame's gh x gw grid
+        const float* rrow = rf + (int64_t)(row / P) * fd.gw;
+        int pc = (64 * k) / P, lo = 0;
+        while (lo < 64) {
+          const int hi = min((pc + 1) * P - 64 * k, 64);
+          const uint64_t seg = v & (hi == 64 ? ~0ull : ((1ull << hi) - 1)) & ~((1ull << lo) - 1);
+          if (seg) rsum += (float)__builtin_popcountll(seg) * rrow[pc];
+          lo = hi;
+          ++pc;
+        }
+      }
     }
     row += drow;
     k += dk;
@@ -58,6 +79,8 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
   xmin = wave_min(xmin);
   xmax = wave_max(xmax);
   area = wave_sum(area);
+  for (int o = 32; o > 0; o >>= 1) rsum += __shfl_xor(rsum, o);
+  __shared__ float rred[4];
   __shared__ int red[4][5];
   __shared__ int app[3];  // class, strips, first slot in the class list
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -67,6 +90,7 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
     red[wv][2] = xmin;
     red[wv][3] = xmax;
     red[wv][4] = area;
+    rred[wv] = rsum;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -80,7 +104,7 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
     int meta = -1;
     app[1] = 0;
     if (area > 0) {
-      const int P = fd.patch, SW = strip_width(P);
+      const int SW = strip_width(P);
       const int xs0 = (xmin / P) * P;
       const int strips = (xmax + 1 - xs0 + SW - 1) / SW;
       const int n = ymax - ymin + 3;
@@ -119,6 +143,13 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
     }
     wk.area[g] = area;
     wk.meta[g] = meta;
+    const int64_t li = g - fd.mask_base;
+    if (fd.area_out) fd.area_out[li] = area;
+    if (fd.dbar) {
+      const float tot = ((rred[0] + rred[1]) + rred[2]) + rred[3];
+      const int f = b.mask_frame[g];
+      fd.dbar[li] = area > 0 ? (tot / (float)area) / (wk.rbar[f] + b.eps) : 0.f;
+    }
   }
   __syncthreads();
   const int strips = app[1];

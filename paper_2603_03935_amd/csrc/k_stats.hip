@@ -260,6 +260,27 @@ void launch_d_from_r(const float* r, int G, float eps, float* D, hipStream_t st)
   hipLaunchKernelGGL(k_d_from_r, dim3(1), dim3(1024), 0, st, r, G, eps, D);
 }
 
+// Mean of r per frame, for the frames that ask for the mean distinctiveness
+// of their masks (one workgroup per frame, fixed summation order).
+__global__ __launch_bounds__(256) void k_rbar(Batch b, Work wk) {
+  const int f = blockIdx.x;
+  if (f >= b.dyn[0]) return;
+  const FrameDesc fd = b.frames[f];
+  if (!fd.dbar) return;
+  const float* r = wk.r + fd.r_base;
+  float a = 0.f;
+  for (int p = threadIdx.x; p < fd.G; p += 256) a += r[p];
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  __shared__ float red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) wk.rbar[f] = (((red[0] + red[1]) + red[2]) + red[3]) / (float)fd.G;
+}
+
+void launch_rbar(const Batch& b, const Work& w, hipStream_t st) {
+  if (b.n_frames > 0) hipLaunchKernelGGL(k_rbar, dim3(b.n_frames), dim3(256), 0, st, b, w);
+}
+
 // ---------------------------------------------------------------------------
 // Weight finalisation, one workgroup per mask.
 //   w_p = s_p * r_p (distinct) or s_p, times scale_p for FP8 tokens (the GEMM

@@ -67,6 +67,7 @@ Shape capacity_shape(const disc_server_config& c, int E, int gemm_bf16) {
   s.gemm_bf16 = gemm_bf16;
   s.tkp_elems = (int64_t)c.max_frames * round_up(G, 8) * c.c;
   s.tkp_esize = 2;
+  s.want_dbar = true;  // any request may ask for the mean distinctiveness
   choose_splits(s);
   return s;
 }
@@ -313,6 +314,8 @@ disc_status disc_server_submit(disc_server* s, const disc_tokens* t, const disc_
   r.fin.out = o->data;
   r.fin.status = o->mask_status;
   r.fin.pooled = o->pooled;
+  r.fin.dbar = o->dbar;
+  r.fin.area = o->area;
   r.fin.gh = t->gh;
   r.fin.gw = t->gw;
   r.fin.patch = t->patch;

@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.disc_abi_version() == 3
+    assert lib.disc_abi_version() == 4
     o = disc.Options()
     lib.disc_options_default(ctypes.byref(o))
     assert (o.spatial, o.distinct, o.gemm_dtype, o.edt_layout, o.pool_tile) == (0, 1, -1, -1, -1)
@@ -145,3 +145,37 @@ def test_query_validation(lib):
     assert q(m=-1) == 1 and q(text=None) == 1 and q(sim=None) == 1
     assert q(text=FAKE + 8) == 4
     assert q(qn=0) == 0  # no queries: nothing to do
+
+
+def test_quality_and_fusion_validation(lib):
+    """disc_view_quality / disc_angle_score / disc_fuse reject bad arguments on
+    the host (nothing is launched); zero observations are a no-op."""
+    def vq(m=10, e=64, h=480, w=640, lam=3.3, emb=FAKE, area=FAKE, comp=None):
+        return lib.disc_view_quality(area, FAKE, emb, FAKE, None, m, e, h, w, lam, FAKE, comp, None)
+    assert vq(e=62) == 9 and vq(e=0) == 9 and vq(e=8192) == 9
+    assert vq(h=0) == 2 and vq(w=-1) == 2
+    assert vq(lam=0.0) == 1 and vq(lam=-1.0) == 1 and vq(lam=float("nan")) == 1
+    assert vq(m=-1) == 1 and vq(area=None) == 1 and vq(emb=FAKE + 4) == 4 and vq(comp=FAKE + 8) == 4
+    assert vq(m=0) == 0
+
+    def ang(m=10, nv=100, rays=FAKE, off=FAKE):
+        return lib.disc_angle_score(rays, FAKE, nv, off, m, FAKE, None)
+    assert ang(m=-1) == 1 and ang(nv=-1) == 1 and ang(nv=1 << 30) == 9
+    assert ang(off=None) == 1 and ang(rays=None) == 1
+    assert ang(m=0) == 0
+
+    def fu(m=10, e=64, n_map=5, ids=FAKE, emb=FAKE, map_emb=FAKE):
+        return lib.disc_fuse(ids, FAKE, emb, m, e, FAKE, map_emb, n_map, None, None)
+    assert fu(e=6) == 9 and fu(n_map=(1 << 28) + 1) == 9
+    assert fu(m=-1) == 1 and fu(n_map=-1) == 1 and fu(ids=None) == 1 and fu(map_emb=None) == 1
+    assert fu(emb=FAKE + 4) == 4 and fu(map_emb=FAKE + 8) == 4
+    assert fu(m=0) == 0
+
+
+def test_out_quality_pointer_alignment(lib):
+    """dbar and area outputs must be 4-byte aligned."""
+    t, mk, pj, _ = good()
+    o = disc.Out(FAKE, 5, 768, None, None, FAKE + 2, None)
+    assert lib.disc_embed_masks(ctypes.byref(t), ctypes.byref(mk), ctypes.byref(pj), ctypes.byref(o)) == 4
+    o = disc.Out(FAKE, 5, 768, None, None, None, FAKE + 1)
+    assert lib.disc_embed_masks(ctypes.byref(t), ctypes.byref(mk), ctypes.byref(pj), ctypes.byref(o)) == 4

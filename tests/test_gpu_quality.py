@@ -1,0 +1,193 @@
+"""View quality Q (Sec. III-C, Eqs. 2-3) and replace-if-higher fusion on the
+GPU, through the C ABI, against the FP64 oracle.
+
+Bars: mask areas and fusion results (winners, copied rows, stored Q) exact;
+the mean distinctiveness within a relative 1e-5 (FP32 residual norms and
+sums), the Q factors and S_angle within 1e-5 relative / 1e-6 absolute (FP32
+dot products of unit-scale vectors).
+"""
+import numpy as np
+import pytest
+
+import disc_inputs as di
+import oracle
+from gpu_common import dev_proj, frame_input, torch
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+ABS = 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    t = torch()
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_03935_amd as disc
+
+    disc.load()
+    return disc
+
+
+def _dbar_ref(fr, eps=1e-6):
+    tok = fr.tokens
+    f64 = oracle.decode_tokens(tok.data, tok.dtype, tok.scale).reshape(-1, tok.data.shape[-1])
+    _, _, D = oracle.token_stats(f64, eps)
+    return oracle.mask_dbar(fr.bits, fr.w, tok.patch, D)
+
+
+def _frames_mixed():
+    frames = []
+    for i, (h, w, m, patch, dt) in enumerate([(480, 640, 60, 16, "bf16"), (337, 501, 25, 14, "f8"),
+                                             (130, 70, 9, 16, "f32"), (720, 1280, 40, 16, "bf16")]):
+        gh, gw = -(-h // patch), -(-w // patch)
+        bits = di.masks_mixed(300 + i, m, h, w, 1e-3, 0.3)
+        bits[3] = 0  # an empty mask
+        frames.append(di.Frame(di.tokens_normal(300 + i, gh, gw, 256, dt, patch), bits, h, w))
+    return frames
+
+
+@pytest.mark.parametrize("distinct", [1, 0])
+def test_dbar_area_vs_oracle(gpu, distinct):
+    """dbar and area from the embedding call (a ragged batch of frames with
+    different patch sizes, widths that are not multiples of 64, every token
+    dtype and an empty mask); asking for them leaves the embeddings unchanged."""
+    frames = _frames_mixed()
+    P = di.projection(5, 256, 128, "f32")
+    proj = dev_proj(P, "f32")
+    opts = gpu.make_options(0, distinct)
+    ins = [frame_input(f) for f in frames]
+    # one batch call per token dtype (frames of one call share the dtype)
+    with_q, plain = [None] * len(frames), [None] * len(frames)
+    for dt in sorted({f.tokens.dtype for f in frames}):
+        sel = [i for i, f in enumerate(frames) if f.tokens.dtype == dt]
+        a = gpu.embed_frames([ins[i] for i in sel], proj, options=opts, quality=True)
+        b = gpu.embed_frames([ins[i] for i in sel], proj, options=opts)
+        for j, i in enumerate(sel):
+            with_q[i], plain[i] = a[j], b[j]
+    torch().cuda.synchronize()
+    for i, fr in enumerate(frames):
+        dbar_ref, area_ref = _dbar_ref(fr)
+        area = with_q[i].area.cpu().numpy()
+        dbar = with_q[i].dbar.cpu().numpy().astype(np.float64)
+        assert np.array_equal(area, area_ref), f"frame {i}: areas"
+        assert dbar[3] == 0.0 and area[3] == 0
+        err = np.abs(dbar - dbar_ref) / np.maximum(np.abs(dbar_ref), 1e-30)
+        err[area_ref == 0] = 0
+        assert err.max() <= REL, f"frame {i}: dbar rel err {err.max():.3e} at mask {err.argmax()}"
+        assert np.array_equal(with_q[i].out.cpu().numpy(), plain[i].out.cpu().numpy()), f"frame {i}: embeddings"
+
+
+def test_dbar_full_frame_and_single_patch(gpu):
+    """A mask covering the frame has dbar = mean(D) = mean(r) / (mean(r) + eps);
+    a mask inside one patch takes that patch's D."""
+    h, w, patch, C = 96, 160, 16, 128
+    u8 = np.zeros((2, h, w), np.uint8)
+    u8[0] = 1
+    u8[1, 35:41, 70:75] = 1  # patch (2, 4)
+    fr = di.Frame(di.tokens_normal(9, 6, 10, C, "f32", patch), di.pack_masks(u8), h, w)
+    P = di.projection(9, C, 128, "f32")
+    out = gpu.embed_frames([frame_input(fr)], dev_proj(P, "f32"), quality=True)[0]
+    dbar = out.dbar.cpu().numpy().astype(np.float64)
+    f64 = oracle.decode_tokens(fr.tokens.data, "f32").reshape(-1, C)
+    _, r, D = oracle.token_stats(f64)
+    assert abs(dbar[0] - r.mean() / (r.mean() + 1e-6)) <= REL
+    assert abs(dbar[1] - D[2 * 10 + 4]) <= REL * D[2 * 10 + 4]
+    assert out.area.cpu().numpy().tolist() == [h * w, 30]
+
+
+def test_view_quality_vs_oracle(gpu):
+    t = torch()
+    rng = np.random.default_rng(51)
+    m, e, H, W = 2051, 768, 480, 640
+    g = rng.standard_normal(e).astype(np.float32)
+    emb = rng.standard_normal((m, e)).astype(np.float32) * 0.05 + 0.02 * g  # mostly positive cosines
+    emb[0] = 0.0
+    emb[1] = g
+    emb[2] = -g
+    emb[3] = 3.0 * g
+    area = rng.integers(0, H * W // 2, m).astype(np.int32)
+    area[4] = 0
+    area[5] = H * W
+    dbar = rng.uniform(0.0, 2.0, m).astype(np.float32)
+    angle = rng.uniform(0.0, 1.0, m).astype(np.float32)
+    dv = lambda a: t.from_numpy(a).cuda()  # noqa: E731
+    for ang in (angle, None):
+        q, comp = gpu.view_quality(dv(area), dv(dbar), dv(emb), dv(g), H, W, None if ang is None else dv(ang))
+        Qr, compr = oracle.view_quality(area, dbar.astype(np.float64), emb.astype(np.float64), g.astype(np.float64),
+                                        None if ang is None else ang.astype(np.float64), H, W)
+        q, comp = q.cpu().numpy(), comp.cpu().numpy()
+        assert np.allclose(comp, compr, rtol=REL, atol=ABS), np.abs(comp - compr).max(axis=0)
+        assert np.allclose(q, Qr, rtol=REL, atol=ABS), np.abs(q - Qr).max()
+        assert comp[0, 2] == 0.0 and comp[2, 2] == 0.0 and abs(comp[1, 2] - 1.0) <= 1e-6 and comp[5, 0] == 1.0
+
+
+def test_angle_score_vs_oracle(gpu):
+    t = torch()
+    rng = np.random.default_rng(52)
+    lens = rng.integers(0, 200, 1500)
+    lens[:3] = [0, 1, 64]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    nv = int(off[-1])
+    rays = rng.standard_normal((nv, 3))
+    rays /= np.linalg.norm(rays, axis=1)[:, None]
+    nrm = rng.standard_normal((nv, 3))
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    rays, nrm = rays.astype(np.float32), nrm.astype(np.float32)
+    got = gpu.angle_score(t.from_numpy(rays).cuda(), t.from_numpy(nrm).cuda(), t.from_numpy(off).cuda())
+    ref = oracle.angle_score(rays.astype(np.float64), nrm.astype(np.float64), off)
+    got = got.cpu().numpy()
+    assert got[0] == 0.0
+    assert np.allclose(got, ref, rtol=REL, atol=ABS), np.abs(got - ref).max()
+
+
+def _fuse_case(rng, m, n_map, e):
+    ids = rng.integers(-3, n_map + 3, m).astype(np.int32)  # some outside [0, n_map)
+    q = np.round(rng.uniform(0.0, 1.0, m), 2).astype(np.float32)  # many ties
+    emb = rng.standard_normal((m, e)).astype(np.float32)
+    return ids, q, emb
+
+
+def test_fuse_vs_oracle(gpu):
+    """Two calls in a row on one map (the second smaller), the map, the
+    stored Q and the winners exact."""
+    t = torch()
+    rng = np.random.default_rng(53)
+    n_map, e = 700, 768
+    map_q = rng.uniform(0.0, 0.8, n_map).astype(np.float32)
+    map_emb = rng.standard_normal((n_map, e)).astype(np.float32)
+    dq, demb = t.from_numpy(map_q.copy()).cuda(), t.from_numpy(map_emb.copy()).cuda()
+    rq, remb = map_q.astype(np.float64), map_emb.astype(np.float64)
+    for m in (5000, 333):
+        ids, q, emb = _fuse_case(rng, m, n_map, e)
+        won = gpu.fuse(t.from_numpy(ids).cuda(), t.from_numpy(q).cuda(), t.from_numpy(emb).cuda(), dq, demb)
+        rq, remb, rwon = oracle.fuse(ids, q.astype(np.float64), emb.astype(np.float64), rq, remb)
+        assert np.array_equal(won.cpu().numpy(), rwon), f"m={m}: winners"
+        assert np.array_equal(dq.cpu().numpy().astype(np.float64), rq), f"m={m}: stored Q"
+        assert np.array_equal(demb.cpu().numpy().astype(np.float64), remb), f"m={m}: map rows"
+
+
+def test_quality_chain_on_embeddings(gpu):
+    """embed (with dbar, area) -> view quality -> fusion into a map, each step
+    against the oracle on the previous step's GPU output."""
+    t = torch()
+    fr = di.workload("cfg2").frames[0]
+    wl = di.workload("cfg2")
+    out = gpu.embed_frames([frame_input(fr)], dev_proj(wl.proj, wl.proj_dtype), quality=True)[0]
+    m, e = out.out.shape
+    rng = np.random.default_rng(54)
+    g = rng.standard_normal(e).astype(np.float32)
+    q, comp = gpu.view_quality(out.area, out.dbar, out.out, t.from_numpy(g).cuda(), fr.h, fr.w)
+    emb = out.out.cpu().numpy().astype(np.float64)
+    dbar_ref, area_ref = _dbar_ref(fr)
+    Qr, _ = oracle.view_quality(area_ref, dbar_ref, emb, g.astype(np.float64), None, fr.h, fr.w)
+    assert np.allclose(q.cpu().numpy(), Qr, rtol=1e-4, atol=ABS)
+    ids = t.from_numpy(rng.integers(0, 16, m).astype(np.int32)).cuda()
+    map_q = t.zeros(16, dtype=t.float32, device="cuda")
+    map_emb = t.zeros((16, e), dtype=t.float32, device="cuda")
+    won = gpu.fuse(ids, q, out.out, map_q, map_emb)
+    rq, remb, rwon = oracle.fuse(ids.cpu().numpy(), q.cpu().numpy().astype(np.float64), emb, np.zeros(16),
+                                 np.zeros((16, e)))
+    assert np.array_equal(won.cpu().numpy(), rwon) and np.array_equal(map_q.cpu().numpy().astype(np.float64), rq)
+    assert np.array_equal(map_emb.cpu().numpy().astype(np.float64), remb)

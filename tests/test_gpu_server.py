@@ -40,7 +40,7 @@ def test_server_matches_frames_alone(disc, stream_frames, use_graph):
     frames, P = stream_frames
     proj = dev_proj(P, "bf16")
     ins = [frame_input(f) for f in frames]
-    alone = [disc.embed_frames([x], proj)[0] for x in ins]
+    alone = [disc.embed_frames([x], proj, quality=True)[0] for x in ins]
     torch().cuda.synchronize()
     with disc.Server(proj, tok_dtype=disc.DISC_BF16, c=1024, max_frames=4, max_masks=600, lanes=2,
                      use_graph=use_graph, mem_budget=8 << 30) as srv:
@@ -49,7 +49,7 @@ def test_server_matches_frames_alone(disc, stream_frames, use_graph):
 
         def producer(k):
             for i in range(k, len(ins), 3):
-                t, out = srv.submit_frame(ins[i])
+                t, out = srv.submit_frame(ins[i], quality=i % 2 == 0)  # half ask for dbar / area
                 with lock:
                     results[i] = (t, out)
 
@@ -66,6 +66,9 @@ def test_server_matches_frames_alone(disc, stream_frames, use_graph):
             a, b = alone[i].out.cpu().numpy(), out.out.cpu().numpy()
             assert np.array_equal(a, b), f"frame {i}: served result differs from the frame alone"
             assert np.array_equal(alone[i].status.cpu().numpy(), out.status.cpu().numpy())
+            if i % 2 == 0:
+                assert np.array_equal(alone[i].dbar.cpu().numpy(), out.dbar.cpu().numpy()), f"frame {i}: dbar"
+                assert np.array_equal(alone[i].area.cpu().numpy(), out.area.cpu().numpy()), f"frame {i}: area"
         for i in (0, 2):
             ref = oracle_frame(frames[i], P, "bf16")
             check_embeddings(results[i][1].out.cpu().numpy(), results[i][1].status.cpu().numpy(), ref, COS_LOWP,
