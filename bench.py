@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="offered-load duration of the served leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served BF16 leg")
     ap.add_argument("--no-query", action="store_true", help="skip the open-vocabulary query leg")
+    ap.add_argument("--no-quality", action="store_true", help="skip the view-quality / fusion leg")
     ap.add_argument("--edt-layout", type=int, default=-1, choices=[-1, 0, 1],
                     help="distance-transform band layout (-1: chosen per call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -281,6 +282,78 @@ def query_leg(disc, di, reps: int = 20):
             "sim_frac_of_fp32_mfma_peak": flops / (ms / 1000.0) / 1e12 / PEAK_TFLOPS["f32"]}
 
 
+def _time_ms(fn, reps: int) -> float:
+    import torch
+
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def quality_leg(disc, di, dev, ins, proj, outs, opts, reps: int = 50):
+    """View quality and fusion (Sec. III-C, Eqs. 2-3): the extra cost of the
+    mean distinctiveness and area outputs in the embedding call of the bench
+    workload, and the three streaming kernels at mapping scale -- Q for 100k
+    observations of width 768, S_angle over 4M voxels in 20k detections, and
+    fusion of 100k observations into a 20k-instance map.  Bandwidth figures
+    count the algorithmic bytes (every input element read once, every output
+    written once) against the HBM peak."""
+    import torch
+
+    q_outs = disc.alloc_outputs(ins, outs[0].out.shape[1], quality=True)
+    plain_ms = _time_ms(lambda: disc.embed_frames(ins, proj, outputs=outs, options=opts), reps)
+    q_ms = _time_ms(lambda: disc.embed_frames(ins, proj, outputs=q_outs, options=opts), reps)
+
+    rng = np.random.default_rng(di.frame_seed(7, 0))
+    m, e = 100_000, 768
+    emb = torch.from_numpy(di.normal_rows(di.frame_seed(7, 1), m, e, "f32")[0]).cuda()
+    g = torch.from_numpy(di.normal_rows(di.frame_seed(7, 2), 1, e, "f32")[0][0]).cuda()
+    area = torch.from_numpy(rng.integers(1, 480 * 640 // 4, m).astype(np.int32)).cuda()
+    dbar = torch.from_numpy(rng.uniform(0.2, 2.0, m).astype(np.float32)).cuda()
+    ang = torch.from_numpy(rng.uniform(0.0, 1.0, m).astype(np.float32)).cuda()
+    vq_ms = _time_ms(lambda: disc.view_quality(area, dbar, emb, g, 480, 640, ang), reps)
+    vq_bytes = m * e * 4 + m * (4 + 4 + 4) + m * 4 + m * 16
+
+    nd, nv = 20_000, 4_000_000
+    lens = rng.multinomial(nv - nd * 50, np.full(nd, 1.0 / nd)) + 50
+    off = torch.from_numpy(np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)).cuda()
+    rays = torch.nn.functional.normalize(torch.from_numpy(rng.standard_normal((nv, 3), dtype=np.float32)).cuda(), dim=1)
+    nrm = torch.nn.functional.normalize(torch.from_numpy(rng.standard_normal((nv, 3), dtype=np.float32)).cuda(), dim=1)
+    an_ms = _time_ms(lambda: disc.angle_score(rays, nrm, off), reps)
+    an_bytes = nv * 24 + (nd + 1) * 4 + nd * 4
+
+    n_map = 20_000
+    ids = torch.from_numpy(rng.integers(0, n_map, m).astype(np.int32)).cuda()
+    q = torch.from_numpy(rng.uniform(0.0, 1.0, m).astype(np.float32)).cuda()
+    map_q0 = torch.from_numpy(rng.uniform(0.0, 0.9, n_map).astype(np.float32)).cuda()
+    map_emb = torch.zeros((n_map, e), dtype=torch.float32, device="cuda")
+    map_q = map_q0.clone()
+    won = torch.empty((m,), dtype=torch.int32, device="cuda")
+
+    def fuse_once():
+        map_q.copy_(map_q0)  # same decisions every repetition
+        disc.fuse(ids, q, emb, map_q, map_emb, won=won)
+
+    fu_ms = _time_ms(fuse_once, reps)  # includes the 80 KB reset copy of map_q
+    winners = int(won.sum().item())
+    fu_bytes = m * (4 + 4 + 4) + winners * e * 8 + n_map * 4
+    gbs = lambda b, ms: b / (ms / 1000.0) / 1e9  # noqa: E731
+    return {"embed_ms": plain_ms, "embed_with_dbar_area_ms": q_ms, "dbar_area_overhead": q_ms / plain_ms - 1.0,
+            "view_quality": {"observations": m, "width": e, "ms": vq_ms, "gbs": gbs(vq_bytes, vq_ms),
+                             "frac_of_hbm_peak": gbs(vq_bytes, vq_ms) / PEAK_HBM_GBS},
+            "angle_score": {"detections": nd, "voxels": nv, "ms": an_ms, "gbs": gbs(an_bytes, an_ms),
+                            "frac_of_hbm_peak": gbs(an_bytes, an_ms) / PEAK_HBM_GBS},
+            "fuse": {"observations": m, "instances": n_map, "winners": winners, "ms": fu_ms,
+                     "gbs": gbs(fu_bytes, fu_ms), "frac_of_hbm_peak": gbs(fu_bytes, fu_ms) / PEAK_HBM_GBS}}
+
+
 # ---------------------------------------------------------------- main
 
 def main():
@@ -357,6 +430,7 @@ def main():
     if not args.no_serve and args.config == "cfg2":
         served = served_leg(disc, di, dev, args.serve_seconds)
     query = None if args.no_query else query_leg(disc, di)
+    quality = None if args.no_quality else quality_leg(disc, di, dev, ins, proj, outs, opts)
 
     # CPU baseline: the FP64 oracle as it stands, one core, bounded sample
     cpu = None
@@ -401,6 +475,7 @@ def main():
         "cpu_baseline": cpu,
         "served_bf16": served,
         "query_topk": query,
+        "view_quality_fusion": quality,
     }
     print(json.dumps(res))
 
