@@ -18,9 +18,13 @@ frames with Poisson(80) masks; continuous batching with graph replay) and
 reports its latency at that offered load and its saturated throughput.
 
 Prints ONE JSON line.  ``value`` is mask embeddings per second of the plain
-path; ``roofline`` reports the dominant kernel's achieved algorithmic rate
-(stage durations from HIP events recorded on the launch stream) against the
-MI355X peak; ``cpu_baseline`` times the FP64 CPU oracle on a bounded sample.
+path over exactly K timed steps; ``roofline`` reports the dominant kernel's
+achieved algorithmic rate against the MI355X peak, its duration taken from
+HIP events recorded on the launch stream around that stage in every timed
+step (only that stage: each event record costs a few microseconds);
+``config.stage_avg_ms`` comes from an untimed pass with every stage between
+events and ``p50_ms``/``p99_ms`` from an untimed pass with per-step events;
+``cpu_baseline`` times the FP64 CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -72,6 +76,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the served BF16 leg")
     ap.add_argument("--no-query", action="store_true", help="skip the open-vocabulary query leg")
     ap.add_argument("--no-quality", action="store_true", help="skip the view-quality / fusion leg")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the weighting-mode ablation leg")
     ap.add_argument("--edt-layout", type=int, default=-1, choices=[-1, 0, 1],
                     help="distance-transform band layout (-1: chosen per call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -354,6 +359,40 @@ def quality_leg(disc, di, dev, ins, proj, outs, opts, reps: int = 50):
                      "gbs": gbs(fu_bytes, fu_ms), "frac_of_hbm_peak": gbs(fu_bytes, fu_ms) / PEAK_HBM_GBS}}
 
 
+ABLATION_MODES = {"edt_x_D": (0, 1), "edt_only": (0, 0), "area_x_D": (1, 1), "area_naive_average": (1, 0)}
+
+
+def ablation_leg(disc, di, dev, ins, proj, outs, masks: int, reps: int = 50):
+    """The weighting modes at the bench workload (EDT x D as built, EDT
+    alone, the pixel-count (AREA) weighting with and without D, and the naive
+    average over the mask), and how close each mode's embedding comes to the
+    known object features of a synthetic object scene (40 overlapping
+    ellipses on a background, 480x640, patch tokens mixing the features of
+    the pixels they cover, noise and 12 high-norm outlier tokens): cosine of
+    each mask's embedding with its object's projected feature."""
+    import torch
+    from disc_inputs.scene import object_scene
+
+    res = {}
+    scene = object_scene(di.frame_seed(8, 0))
+    fr = scene.frame
+    data, scale = dev.dev_tokens(fr.tokens)
+    sin = disc.FrameInput(data, dev.dev_bits(fr.bits), fr.h, fr.w, fr.tokens.patch, scale)
+    P = di.projection(di.frame_seed(8, 1), fr.tokens.data.shape[-1], 768, "f32")
+    sproj = torch.from_numpy(P).cuda()
+    ref = scene.truth @ P.astype(np.float64)
+    ref /= np.linalg.norm(ref, axis=1)[:, None]
+    for name, (sp, dd) in ABLATION_MODES.items():
+        o = disc.make_options(sp, dd)
+        ms = _time_ms(lambda: disc.embed_frames(ins, proj, outputs=outs, options=o), reps)
+        got = disc.embed_frames([sin], sproj, options=o)[0].out.cpu().numpy().astype(np.float64)
+        cos = (got * ref).sum(axis=1)
+        res[name] = {"spatial": "edt" if sp == 0 else "area", "distinct": bool(dd), "ms_per_step": ms,
+                     "masks_per_s": masks / (ms / 1000.0), "scene_masks": int(len(cos)),
+                     "scene_cos_mean": float(cos.mean()), "scene_cos_p10": float(np.percentile(cos, 10))}
+    return res
+
+
 # ---------------------------------------------------------------- main
 
 def main():
@@ -398,39 +437,59 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # timed region: per-step events for latency, per-stage events for the roofline
+    # untimed breakdown pass: every stage between HIP events (each event record
+    # costs a few microseconds, so the timed region below carries only the
+    # dominant stage's events)
+    stages = {}
     if not args.no_trace:
+        disc.trace_select(None)
         disc.trace_reset()
         disc.trace_enable(True)
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        for _ in range(min(args.steps, 50)):
+            step()
+        torch.cuda.synchronize()
+        disc.trace_enable(False)
+        stages = disc.trace_read()
+    avg = {k: (ms / n if n else 0.0) for k, (ms, n) in stages.items()}
+    dom = max(avg, key=avg.get) if avg else None
+
+    # timed region: exactly K steps; the dominant stage is timed live with
+    # events on its launch stream
+    if dom:
+        disc.trace_select([dom])
+        disc.trace_reset()
+        disc.trace_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    roof = None
+    if dom:
+        disc.trace_enable(False)
+        live_ms, live_n = disc.trace_read()[dom]
+        disc.trace_select(None)
+        roof = roofline(dom, live_ms / max(live_n, 1), units, args.config)
+    ms_per_step = wall * 1000.0 / args.steps
+    value = totals["masks"] / (ms_per_step / 1000.0)
+
+    # latency pass: per-step events (untimed)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     for i in range(args.steps):
         starts[i].record(stream)
         step()
         ends[i].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    stages = {}
-    if not args.no_trace:
-        disc.trace_enable(False)
-        stages = disc.trace_read()
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
-    ms_per_step = wall * 1000.0 / args.steps
-    value = totals["masks"] / (ms_per_step / 1000.0)
-
-    avg = {k: (ms / n if n else 0.0) for k, (ms, n) in stages.items()}
-    roof = None
-    if avg:
-        dom = max(avg, key=avg.get)
-        roof = roofline(dom, avg[dom], units, args.config)
 
     served = None
     if not args.no_serve and args.config == "cfg2":
         served = served_leg(disc, di, dev, args.serve_seconds)
     query = None if args.no_query else query_leg(disc, di)
     quality = None if args.no_quality else quality_leg(disc, di, dev, ins, proj, outs, opts)
+    ablation = None if args.no_ablation else ablation_leg(disc, di, dev, ins, proj, outs, totals["masks"])
 
     # CPU baseline: the FP64 oracle as it stands, one core, bounded sample
     cpu = None
@@ -476,6 +535,7 @@ def main():
         "served_bf16": served,
         "query_topk": query,
         "view_quality_fusion": quality,
+        "ablation": ablation,
     }
     print(json.dumps(res))
 

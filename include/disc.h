@@ -335,9 +335,12 @@ void disc_server_destroy(disc_server* s);
 
 /* Per-stage device timing with HIP events recorded on the caller's stream
  * around each stage of disc_embed_frames (and the calls built on it): stages
- * 0 scan, 1 plan, 2 token_stats, 3 edt, 4 weights, 5 pool, 6 proj.
- * Off by default; enabling it adds two event records per stage. */
+ * 0 scan, 1 token_stats, 2 edt, 3 weights, 4 pool, 5 proj.
+ * Off by default; enabling it adds two event records per timed stage. */
 void disc_trace_enable(int32_t on);
+/* Which stages are timed while tracing is on: bit s for stage s (default:
+ * all).  Timing one stage keeps the other stages free of event records. */
+void disc_trace_select(uint32_t stage_mask);
 /* Wait for pending events and zero the accumulated totals. */
 void disc_trace_reset(void);
 /* Total milliseconds and number of timed launches of a stage since the last

@@ -39,7 +39,7 @@ EXPORTS = [
     "disc_options_default", "disc_embed_masks", "disc_embed_masks_ex", "disc_embed_frames",
     "disc_workspace_bytes", "disc_release_workspace", "disc_edt_sq", "disc_patch_weights",
     "disc_token_stats", "disc_pool_project", "disc_pack_masks", "disc_last_error", "disc_abi_version",
-    "disc_trace_enable", "disc_trace_reset", "disc_trace_read", "disc_trace_stage_name",
+    "disc_trace_enable", "disc_trace_select", "disc_trace_reset", "disc_trace_read", "disc_trace_stage_name",
     "disc_server_config_default", "disc_server_create", "disc_server_submit", "disc_server_poll",
     "disc_server_wait", "disc_server_drain", "disc_server_get_stats", "disc_server_destroy",
     "disc_query_topk", "disc_view_quality", "disc_angle_score", "disc_fuse",
@@ -131,6 +131,8 @@ def load(path: str = LIB_PATH):
     lib.disc_last_error.restype = ctypes.c_char_p
     lib.disc_trace_enable.argtypes = [i32]
     lib.disc_trace_enable.restype = None
+    lib.disc_trace_select.argtypes = [ctypes.c_uint32]
+    lib.disc_trace_select.restype = None
     lib.disc_trace_reset.argtypes = []
     lib.disc_trace_reset.restype = None
     lib.disc_trace_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -439,6 +441,12 @@ def release_workspace():
 
 def trace_enable(on: bool = True):
     load().disc_trace_enable(1 if on else 0)
+
+
+def trace_select(stages=None):
+    """Time only the named stages while tracing is on (None: all)."""
+    mask = 0xFFFFFFFF if stages is None else sum(1 << STAGES.index(s) for s in stages)
+    load().disc_trace_select(mask)
 
 
 def trace_reset():

@@ -465,6 +465,7 @@ struct TraceRec {
 };
 std::mutex g_tr_mu;
 bool g_trace_on = false;
+uint32_t g_trace_mask = 0xFFFFFFFFu;
 std::vector<TraceRec> g_tr_pending;
 std::vector<hipEvent_t> g_tr_free;
 double g_tr_ms[ST_COUNT] = {};
@@ -488,7 +489,7 @@ struct StageTimer {
   StageTimer(int s, hipStream_t stream) : stage(s), st(stream) {
     if (s < 0) return;
     std::lock_guard<std::mutex> lk(g_tr_mu);
-    if (!g_trace_on) return;
+    if (!g_trace_on || !((g_trace_mask >> s) & 1u)) return;
     a = tr_event();
     (void)hipEventRecord(a, st);
   }
@@ -950,6 +951,11 @@ extern "C" {
 void disc_trace_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_tr_mu);
   g_trace_on = on != 0;
+}
+
+void disc_trace_select(uint32_t stage_mask) {
+  std::lock_guard<std::mutex> lk(g_tr_mu);
+  g_trace_mask = stage_mask;
 }
 
 void disc_trace_reset(void) {

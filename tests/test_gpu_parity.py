@@ -368,3 +368,16 @@ def test_query_topk_on_embeddings(gpu):
     ref = oracle.query_topk(out.cpu().numpy().astype(np.float64), text.astype(np.float64), 12)
     _check_topk(scores.cpu().numpy(), idx.cpu().numpy(), ref, 2e-6, "cfg1 embeddings")
     assert (idx.cpu().numpy()[:, 8:] == -1).all() and np.isinf(scores.cpu().numpy()[:, 8:]).all()
+
+
+def test_object_scene_modes_vs_oracle(gpu):
+    """The synthetic object scene (overlapping objects, outline patches that
+    mix features, outlier tokens) through every weighting mode."""
+    from disc_inputs.scene import object_scene
+
+    sc = object_scene(di.frame_seed(8, 0))
+    P = di.projection(di.frame_seed(8, 1), 1024, 768, "f32")
+    for spatial, distinct in [(0, 1), (0, 0), (1, 1), (1, 0)]:
+        out = run_frames(gpu, [sc.frame], P, "f32", options=gpu.make_options(spatial, distinct))[0]
+        ref = oracle_frame(sc.frame, P, "f32", spatial, distinct)
+        check_embeddings(out.out.cpu().numpy(), out.status.cpu().numpy(), ref, COS_FP32, f"scene {spatial}/{distinct}")
