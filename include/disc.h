@@ -258,6 +258,70 @@ disc_status disc_angle_score(const float* rays, const float* normals, int32_t nv
 disc_status disc_fuse(const int32_t* ids, const float* q, const float* emb, int32_t m, int32_t e, float* map_q,
                       float* map_emb, int32_t n_map, int32_t* won, void* stream);
 
+/* ---- geometry (the mapping side of each segment, Sec. III-B) ---- */
+
+/* Pinhole camera of a depth frame.  Pixel (x, y) (integer column and row)
+ * with depth z maps to the camera point ((x - cx) z / fx, (y - cy) z / fy, z)
+ * and the world point R p + t (R row-major camera-to-world rotation).
+ * Depths that are not finite or lie outside [depth_min, depth_max] are
+ * missing readings.  All arithmetic is single precision, each operation
+ * rounded on its own in the order written (no fused multiply-add). */
+typedef struct disc_camera {
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float depth_min, depth_max;
+} disc_camera;
+
+/* Back-projection, pass 1: offsets [m + 1] (device int32) written with the
+ * exclusive prefix sum of each mask's point count (pixels of the mask with a
+ * valid depth and x, y multiples of stride); offsets[m] is the total.
+ *   depth [h][w] FP32 metres (device), masks as for disc_embed_* (h, w the
+ *   depth frame's), cam a host struct, 1 <= stride <= 64.
+ * Asynchronous on `stream`. */
+disc_status disc_backproject_count(const float* depth, const disc_masks* masks, const disc_camera* cam,
+                                   int32_t stride, int32_t* offsets, void* stream);
+/* Back-projection, pass 2: the world points of each mask, in row-major pixel
+ * order, written to points [offsets[i] ...][3] FP32 (the caller reads
+ * offsets[m] after pass 1 to size points).  Same arguments as pass 1. */
+disc_status disc_backproject(const float* depth, const disc_masks* masks, const disc_camera* cam, int32_t stride,
+                             const int32_t* offsets, float* points, void* stream);
+
+/* DBSCAN noise removal (Sec. III-B: segment point clouds are filtered with
+ * DBSCAN): within each segment, a point is a core point when at least
+ * min_pts points (itself included) lie within distance eps (squared distance
+ * <= eps^2 in single precision); keep[i] = 1 for core points and for points
+ * within eps of a core point, 0 for the noise.
+ *   points [n][3] FP32, offsets [m + 1] int32 (segment i = points
+ *   [offsets[i], offsets[i+1]), offsets[m] = n), keep [n] int32 written.
+ * n <= 2^23, m <= 65535, eps > 0, min_pts >= 1.  Asynchronous on `stream`. */
+disc_status disc_dbscan_denoise(const float* points, const int32_t* offsets, int32_t m, int32_t n, float eps,
+                                int32_t min_pts, int32_t* keep, void* stream);
+
+/* Voxel sets (Sec. III-B: the filtered points are voxelised): voxel of a
+ * point floor(p / voxel) per axis; per segment the distinct voxels of its
+ * points with keep[i] != 0 (keep may be NULL: all points), listed in
+ * lexicographic (x, y, z) order.
+ *   voffsets [m + 1] int32 written (prefix sums of the voxel counts),
+ *   voxels [n][3] int32 (capacity n rows; rows [voffsets[i], voffsets[i+1])
+ *   written), status [m] int32 or NULL: 0 ok, 1 some point's voxel lies
+ *   beyond +-32767 per axis (the point is left out), 2 more than 8192
+ *   distinct voxels (the segment's rows are left unwritten).
+ * n <= 2^23, m <= 65535, voxel > 0.  Asynchronous on `stream`. */
+disc_status disc_voxelize(const float* points, const int32_t* offsets, const int32_t* keep, int32_t m, int32_t n,
+                          float voxel, int32_t* voffsets, int32_t* voxels, int32_t* status, void* stream);
+
+/* Exact voxel overlap (Sec. III-B: association by voxel intersection): for
+ * each pair k, counts[k] = number of voxels shared by set pairs[k][0] of A
+ * and set pairs[k][1] of B (0 for an index out of range).
+ *   va [.][3] int32 with offsets oa [na + 1], vb / ob likewise, each set
+ *   sorted lexicographically without repeats (as disc_voxelize writes them),
+ *   coordinates within +-2^20; pairs [np][2] int32; counts [np] int32.
+ * Asynchronous on `stream`. */
+disc_status disc_voxel_overlap(const int32_t* va, const int32_t* oa, int32_t na, const int32_t* vb,
+                               const int32_t* ob, int32_t nb, const int32_t* pairs, int32_t np, int32_t* counts,
+                               void* stream);
+
 /* ---- serving ---- */
 
 /* A continuous-batching request loop on one device (the view-quality

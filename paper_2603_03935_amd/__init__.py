@@ -43,6 +43,7 @@ EXPORTS = [
     "disc_server_config_default", "disc_server_create", "disc_server_submit", "disc_server_poll",
     "disc_server_wait", "disc_server_drain", "disc_server_get_stats", "disc_server_destroy",
     "disc_query_topk", "disc_view_quality", "disc_angle_score", "disc_fuse",
+    "disc_backproject_count", "disc_backproject", "disc_dbscan_denoise", "disc_voxelize", "disc_voxel_overlap",
 ]
 STAGES = ["scan", "token_stats", "edt", "weights", "pool", "proj"]
 
@@ -67,6 +68,25 @@ class Masks(ctypes.Structure):
 
 class Proj(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("c", ctypes.c_int32), ("e", ctypes.c_int32)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("depth_min", ctypes.c_float),
+                ("depth_max", ctypes.c_float)]
+
+
+def make_camera(cam: dict) -> Camera:
+    """dict with fx, fy, cx, cy, R (3x3 camera-to-world), t (3), depth_min, depth_max."""
+    c = Camera()
+    c.fx, c.fy, c.cx, c.cy = cam["fx"], cam["fy"], cam["cx"], cam["cy"]
+    R = [float(v) for row in cam["R"] for v in row]
+    for k in range(9):
+        c.R[k] = R[k]
+    for k in range(3):
+        c.t[k] = float(cam["t"][k])
+    c.depth_min, c.depth_max = cam["depth_min"], cam["depth_max"]
+    return c
 
 
 class Out(ctypes.Structure):
@@ -127,6 +147,11 @@ def load(path: str = LIB_PATH):
     lib.disc_view_quality.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, ctypes.c_float, vp, vp, vp]
     lib.disc_angle_score.argtypes = [vp, vp, i32, vp, i32, vp, vp]
     lib.disc_fuse.argtypes = [vp, vp, vp, i32, i32, vp, vp, i32, vp, vp]
+    lib.disc_backproject_count.argtypes = [vp, P(Masks), P(Camera), i32, vp, vp]
+    lib.disc_backproject.argtypes = [vp, P(Masks), P(Camera), i32, vp, vp, vp]
+    lib.disc_dbscan_denoise.argtypes = [vp, vp, i32, i32, ctypes.c_float, i32, vp, vp]
+    lib.disc_voxelize.argtypes = [vp, vp, vp, i32, i32, ctypes.c_float, vp, vp, vp, vp]
+    lib.disc_voxel_overlap.argtypes = [vp, vp, i32, vp, vp, i32, vp, i32, vp, vp]
     lib.disc_last_error.argtypes = []
     lib.disc_last_error.restype = ctypes.c_char_p
     lib.disc_trace_enable.argtypes = [i32]
@@ -156,7 +181,9 @@ def load(path: str = LIB_PATH):
     lib.disc_abi_version.restype = i32
     for name in ("disc_embed_masks", "disc_embed_masks_ex", "disc_embed_frames", "disc_release_workspace",
                  "disc_edt_sq", "disc_patch_weights", "disc_token_stats", "disc_pool_project", "disc_pack_masks",
-                 "disc_query_topk", "disc_view_quality", "disc_angle_score", "disc_fuse"):
+                 "disc_query_topk", "disc_view_quality", "disc_angle_score", "disc_fuse",
+                 "disc_backproject_count", "disc_backproject", "disc_dbscan_denoise", "disc_voxelize",
+                 "disc_voxel_overlap"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -433,6 +460,58 @@ def fuse(ids, q, emb, map_q, map_emb, won=None, stream=None):
     _check(load().disc_fuse(_ptr(ids), _ptr(q), _ptr(emb), m, e, _ptr(map_q), _ptr(map_emb), map_q.shape[0],
                             _ptr(won), _stream_handle(stream)))
     return won
+
+
+def backproject(depth, bits, h: int, w: int, cam: dict, stride: int = 1, stream=None):
+    """disc_backproject_count + disc_backproject -> (points [n][3] float32, offsets [m+1] int32).
+    Synchronises once to size the point buffer."""
+    torch = _torch()
+    lib = load()
+    m = bits.shape[0]
+    mk = make_masks(bits, h, w)
+    c = make_camera(cam)
+    off = torch.empty((m + 1,), dtype=torch.int32, device=depth.device)
+    sh = _stream_handle(stream)
+    _check(lib.disc_backproject_count(_ptr(depth), ctypes.byref(mk), ctypes.byref(c), stride, _ptr(off), sh))
+    n = int(off[m].item())
+    pts = torch.empty((max(n, 1), 3), dtype=torch.float32, device=depth.device)
+    _check(lib.disc_backproject(_ptr(depth), ctypes.byref(mk), ctypes.byref(c), stride, _ptr(off), _ptr(pts), sh))
+    return pts[:n], off
+
+
+def dbscan_denoise(points, offsets, eps: float, min_pts: int, stream=None):
+    """disc_dbscan_denoise -> keep [n] int32."""
+    torch = _torch()
+    n, m = points.shape[0], offsets.shape[0] - 1
+    keep = torch.empty((max(n, 1),), dtype=torch.int32, device=offsets.device)
+    _check(load().disc_dbscan_denoise(_ptr(points), _ptr(offsets), m, n, eps, min_pts, _ptr(keep),
+                                      _stream_handle(stream)))
+    return keep[:n]
+
+
+def voxelize(points, offsets, voxel: float, keep=None, stream=None):
+    """disc_voxelize -> (voxels [nv][3] int32, voffsets [m+1] int32, status [m] int32).
+    Synchronises once to trim the voxel buffer."""
+    torch = _torch()
+    n, m = points.shape[0], offsets.shape[0] - 1
+    dev = offsets.device
+    voff = torch.empty((m + 1,), dtype=torch.int32, device=dev)
+    vox = torch.empty((max(n, 1), 3), dtype=torch.int32, device=dev)
+    status = torch.empty((max(m, 1),), dtype=torch.int32, device=dev)
+    _check(load().disc_voxelize(_ptr(points), _ptr(offsets), _ptr(keep), m, n, voxel, _ptr(voff), _ptr(vox),
+                                _ptr(status), _stream_handle(stream)))
+    nv = int(voff[m].item())
+    return vox[:nv], voff, status[:m]
+
+
+def voxel_overlap(va, oa, vb, ob, pairs, stream=None):
+    """disc_voxel_overlap -> counts [np] int32."""
+    torch = _torch()
+    np_ = pairs.shape[0]
+    out = torch.empty((max(np_, 1),), dtype=torch.int32, device=pairs.device)
+    _check(load().disc_voxel_overlap(_ptr(va), _ptr(oa), oa.shape[0] - 1, _ptr(vb), _ptr(ob), ob.shape[0] - 1,
+                                     _ptr(pairs), np_, _ptr(out), _stream_handle(stream)))
+    return out[:np_]
 
 
 def release_workspace():

@@ -944,6 +944,120 @@ disc_status disc_fuse(const int32_t* ids, const float* q, const float* emb, int3
   return ok();
 }
 
+static disc_status geom_masks(const float* depth, const disc_masks* masks, const disc_camera* cam, int32_t stride,
+                              const char* who) {
+  disc_status st;
+  if ((st = check_masks(masks, who))) return st;
+  if (!cam) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: cam is NULL", who);
+  if (stride < 1 || stride > 64) return fail(DISC_ERR_LIMIT, "%s: stride %d outside [1, 64]", who, stride);
+  if (masks->m > 0 && !depth) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: depth is NULL", who);
+  if (!(cam->fx != 0.f) || !(cam->fy != 0.f)) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: zero focal length", who);
+  return DISC_OK;
+}
+
+static void cam_floats(const disc_camera* c, float* f) {
+  f[0] = c->fx;
+  f[1] = c->fy;
+  f[2] = c->cx;
+  f[3] = c->cy;
+  for (int k = 0; k < 9; ++k) f[4 + k] = c->R[k];
+  for (int k = 0; k < 3; ++k) f[13 + k] = c->t[k];
+  f[16] = c->depth_min;
+  f[17] = c->depth_max;
+}
+
+disc_status disc_backproject_count(const float* depth, const disc_masks* masks, const disc_camera* cam,
+                                   int32_t stride, int32_t* offsets, void* stream) {
+  const char* who = "disc_backproject_count";
+  disc_status st;
+  if ((st = geom_masks(depth, masks, cam, stride, who))) return st;
+  if (!offsets) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: offsets is NULL", who);
+  const int m = masks->m;
+  Layout L{};
+  L.staged_end = 0;
+  L.total = (size_t)round_up(4 * ((int64_t)m + 1 + (int64_t)scan_scratch_ints(m)), 256);
+  Ctx cx;
+  if ((st = acquire(static_cast<hipStream_t>(stream), L, nullptr, cx))) return st;
+  float cf[18];
+  cam_floats(cam, cf);
+  int32_t* counts = reinterpret_cast<int32_t*>(cx.dev_ws);
+  launch_bp_count(depth, masks->bits, m, masks->h, masks->w, stride, cf, counts, offsets, counts + m + 1, cx.st);
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_backproject(const float* depth, const disc_masks* masks, const disc_camera* cam, int32_t stride,
+                             const int32_t* offsets, float* points, void* stream) {
+  const char* who = "disc_backproject";
+  disc_status st;
+  if ((st = geom_masks(depth, masks, cam, stride, who))) return st;
+  if (masks->m == 0) return ok();
+  if (!offsets || !points) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL pointer", who);
+  float cf[18];
+  cam_floats(cam, cf);
+  launch_bp_write(depth, masks->bits, masks->m, masks->h, masks->w, stride, cf, offsets, points,
+                  static_cast<hipStream_t>(stream));
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+static disc_status check_cloud(const float* points, const int32_t* offsets, int32_t m, int32_t n, const char* who) {
+  if (m < 0 || n < 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: negative count (m %d, n %d)", who, m, n);
+  if (m > 65535) return fail(DISC_ERR_LIMIT, "%s: m = %d exceeds 65535 segments", who, m);
+  if (n > (1 << 23)) return fail(DISC_ERR_LIMIT, "%s: n = %d exceeds 2^23 points", who, n);
+  if (!offsets || (n > 0 && !points)) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL pointer", who);
+  return DISC_OK;
+}
+
+disc_status disc_dbscan_denoise(const float* points, const int32_t* offsets, int32_t m, int32_t n, float eps,
+                                int32_t min_pts, int32_t* keep, void* stream) {
+  const char* who = "disc_dbscan_denoise";
+  disc_status st;
+  if ((st = check_cloud(points, offsets, m, n, who))) return st;
+  if (!(eps > 0.f) || eps > 1e30f) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: eps must be positive", who);
+  if (min_pts < 1) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: min_pts must be >= 1", who);
+  if (n == 0) return ok();
+  if (!keep) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: keep is NULL", who);
+  Layout L{};
+  L.staged_end = 0;
+  L.total = (size_t)round_up((int64_t)dbscan_ws_bytes(n), 256);
+  Ctx cx;
+  if ((st = acquire(static_cast<hipStream_t>(stream), L, nullptr, cx))) return st;
+  launch_dbscan(points, offsets, m, n, eps, min_pts, keep, cx.dev_ws, cx.st);
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_voxelize(const float* points, const int32_t* offsets, const int32_t* keep, int32_t m, int32_t n,
+                          float voxel, int32_t* voffsets, int32_t* voxels, int32_t* status, void* stream) {
+  const char* who = "disc_voxelize";
+  disc_status st;
+  if ((st = check_cloud(points, offsets, m, n, who))) return st;
+  if (!(voxel > 0.f) || voxel > 1e30f) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: voxel must be positive", who);
+  if (!voffsets || (n > 0 && !voxels)) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL pointer", who);
+  Layout L{};
+  L.staged_end = 0;
+  L.total = (size_t)round_up((int64_t)voxel_ws_bytes(n, m), 256);
+  Ctx cx;
+  if ((st = acquire(static_cast<hipStream_t>(stream), L, nullptr, cx))) return st;
+  launch_voxelize(points, offsets, keep, m, n, voxel, voffsets, voxels, status, cx.dev_ws, cx.st);
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_voxel_overlap(const int32_t* va, const int32_t* oa, int32_t na, const int32_t* vb,
+                               const int32_t* ob, int32_t nb, const int32_t* pairs, int32_t np, int32_t* counts,
+                               void* stream) {
+  const char* who = "disc_voxel_overlap";
+  if (na < 0 || nb < 0 || np < 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: negative count", who);
+  if (np == 0) return ok();
+  if (!oa || !ob || !pairs || !counts) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL pointer", who);
+  launch_overlap(va, oa, na, vb, ob, nb, pairs, np, counts, static_cast<hipStream_t>(stream));
+  disc_status st;
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
 }  // extern "C"
 
 extern "C" {

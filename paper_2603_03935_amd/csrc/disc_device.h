@@ -140,6 +140,20 @@ void launch_quality(const int32_t* area, const float* dbar, const float* emb, co
                     int e, int img_h, int img_w, float lambda, float* q, float* comp, hipStream_t st);
 void launch_angle(const float* rays, const float* normals, int nv, const int32_t* off, int m, float* angle,
                   hipStream_t st);
+// geometry (k_geom.hip); cam = 18 floats (fx, fy, cx, cy, R[9], t[3], dmin, dmax)
+size_t scan_scratch_ints(int n);
+void launch_bp_count(const float* depth, const uint64_t* bits, int m, int h, int w, int s, const float* cam,
+                     int32_t* counts, int32_t* offsets, int32_t* scratch, hipStream_t st);
+void launch_bp_write(const float* depth, const uint64_t* bits, int m, int h, int w, int s, const float* cam,
+                     const int32_t* offsets, float* points, hipStream_t st);
+size_t dbscan_ws_bytes(int n);
+void launch_dbscan(const float* pts, const int32_t* off, int m, int n, float eps, int min_pts, int32_t* keep,
+                   char* ws, hipStream_t st);
+size_t voxel_ws_bytes(int n, int m);
+void launch_voxelize(const float* pts, const int32_t* off, const int32_t* keep, int m, int n, float v, int32_t* voff,
+                     int32_t* vox, int32_t* status, char* ws, hipStream_t st);
+void launch_overlap(const int32_t* va, const int32_t* oa, int na, const int32_t* vb, const int32_t* ob, int nb,
+                    const int32_t* pairs, int np, int32_t* out, hipStream_t st);
 void launch_fuse(const int32_t* ids, const float* q, const float* emb, int m, int e, float* map_q, float* map_emb,
                  int n_map, int32_t* won, uint64_t* best, hipStream_t st);
 // nt: 64-channel tiles per workgroup (1, 2 or 4; any value gives the same result)

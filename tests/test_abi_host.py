@@ -179,3 +179,28 @@ def test_out_quality_pointer_alignment(lib):
     assert lib.disc_embed_masks(ctypes.byref(t), ctypes.byref(mk), ctypes.byref(pj), ctypes.byref(o)) == 4
     o = disc.Out(FAKE, 5, 768, None, None, None, FAKE + 1)
     assert lib.disc_embed_masks(ctypes.byref(t), ctypes.byref(mk), ctypes.byref(pj), ctypes.byref(o)) == 4
+
+
+def test_geometry_validation(lib):
+    """The geometry entry points reject bad arguments on the host."""
+    cam = disc.make_camera({"fx": 500.0, "fy": 500.0, "cx": 1.0, "cy": 1.0, "R": [[1, 0, 0], [0, 1, 0], [0, 0, 1]],
+                            "t": [0, 0, 0], "depth_min": 0.1, "depth_max": 9.0})
+    mk = disc.Masks(FAKE, 3, 48, 64)
+    bc = lambda stride=1, c=cam, depth=FAKE, off=FAKE: lib.disc_backproject_count(  # noqa: E731
+        depth, ctypes.byref(mk), ctypes.byref(c) if c is not None else None, stride, off, None)
+    assert bc(stride=0) == 9 and bc(stride=65) == 9
+    assert bc(c=None) == 1 and bc(depth=None) == 1 and bc(off=None) == 1
+    zero = disc.make_camera({"fx": 0.0, "fy": 500.0, "cx": 1.0, "cy": 1.0, "R": [[1, 0, 0], [0, 1, 0], [0, 0, 1]],
+                             "t": [0, 0, 0], "depth_min": 0.1, "depth_max": 9.0})
+    assert bc(c=zero) == 1
+    db = lambda m=2, n=100, eps=0.05, mp=5, keep=FAKE: lib.disc_dbscan_denoise(  # noqa: E731
+        FAKE, FAKE, m, n, eps, mp, keep, None)
+    assert db(m=70000) == 9 and db(n=(1 << 23) + 1) == 9 and db(m=-1) == 1
+    assert db(eps=0.0) == 1 and db(eps=float("nan")) == 1 and db(mp=0) == 1 and db(keep=None) == 1
+    assert db(n=0) == 0
+    vx = lambda m=2, n=100, v=0.05, voff=FAKE: lib.disc_voxelize(  # noqa: E731
+        FAKE, FAKE, None, m, n, v, voff, FAKE, None, None)
+    assert vx(v=0.0) == 1 and vx(v=-1.0) == 1 and vx(voff=None) == 1 and vx(m=70000) == 9
+    assert lib.disc_voxel_overlap(FAKE, FAKE, 1, FAKE, FAKE, 1, FAKE, -1, FAKE, None) == 1
+    assert lib.disc_voxel_overlap(FAKE, FAKE, 1, FAKE, FAKE, 1, None, 3, FAKE, None) == 1
+    assert lib.disc_voxel_overlap(FAKE, FAKE, 1, FAKE, FAKE, 1, FAKE, 0, FAKE, None) == 0

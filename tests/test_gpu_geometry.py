@@ -1,0 +1,113 @@
+"""The geometry workload on the GPU (back-projection, DBSCAN noise removal,
+voxel sets, voxel overlap), through the C ABI, against the oracle.
+
+Bars: every output is compared exactly -- the points bit for bit (both sides
+compute them in single precision, each operation rounded in the same order),
+the keep flags, voxel lists, offsets and overlap counts element by element.
+"""
+import numpy as np
+import pytest
+
+import disc_inputs as di
+from disc_inputs.scene import depth_scene
+from gpu_common import dev_bits, torch
+from oracle import geometry as og
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    t = torch()
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_03935_amd as disc
+
+    disc.load()
+    return disc
+
+
+def _run_bp(gpu, sc, stride):
+    t = torch()
+    pts, off = gpu.backproject(t.from_numpy(sc.depth).cuda(), dev_bits(sc.bits), sc.h, sc.w, sc.camera, stride)
+    t.cuda.synchronize()
+    return pts.cpu().numpy(), off.cpu().numpy().astype(np.int64)
+
+
+@pytest.mark.parametrize("h,w,stride", [(120, 160, 1), (97, 130, 3), (480, 640, 2)])
+def test_backproject_vs_oracle(gpu, h, w, stride):
+    sc = depth_scene(di.frame_seed(9, h), h, w, n_obj=14 if h < 480 else 40)
+    pts, off = _run_bp(gpu, sc, stride)
+    rp, roff = og.backproject(sc.depth, sc.bits, sc.w, sc.camera, stride)
+    assert np.array_equal(off, roff), "offsets"
+    assert np.array_equal(pts.view(np.uint32), rp.view(np.uint32)), "points (bit for bit)"
+
+
+def test_backproject_edge_cases(gpu):
+    t = torch()
+    h, w = 33, 70
+    sc = depth_scene(di.frame_seed(9, 1), h, w, n_obj=5, min_area=1)
+    bits = np.concatenate([sc.bits, np.zeros((1,) + sc.bits.shape[1:], np.uint64)])  # an empty mask last
+    sc2 = type(sc)(sc.depth, bits, h, w, sc.camera)
+    pts, off = _run_bp(gpu, sc2, 1)
+    rp, roff = og.backproject(sc.depth, bits, w, sc.camera, 1)
+    assert np.array_equal(off, roff) and off[-1] == off[-2]
+    assert np.array_equal(pts.view(np.uint32), rp.view(np.uint32))
+    # no masks
+    pts0, off0 = gpu.backproject(t.from_numpy(sc.depth).cuda(), dev_bits(bits[:0]), h, w, sc.camera, 1)
+    assert off0.cpu().tolist() == [0] and pts0.shape[0] == 0
+
+
+@pytest.mark.parametrize("eps,min_pts", [(0.03, 8), (0.05, 20), (0.02, 1)])
+def test_dbscan_vs_oracle(gpu, eps, min_pts):
+    t = torch()
+    sc = depth_scene(di.frame_seed(9, 2), 130, 180, n_obj=14)
+    pts, off = _run_bp(gpu, sc, 1)
+    keep = gpu.dbscan_denoise(t.from_numpy(pts).cuda(), t.from_numpy(off.astype(np.int32)).cuda(), eps, min_pts)
+    want = og.dbscan_keep(pts, off, eps, min_pts)
+    got = keep.cpu().numpy()
+    assert np.array_equal(got, want), f"{(got != want).sum()} of {len(want)} flags differ"
+    if min_pts > 1:
+        assert 0 < (1 - want).sum() < len(want), "the scene has both noise and kept points"
+
+
+@pytest.mark.parametrize("voxel", [0.02, 0.05])
+def test_voxelize_vs_oracle(gpu, voxel):
+    t = torch()
+    sc = depth_scene(di.frame_seed(9, 3), 240, 320, n_obj=24)
+    pts, off = _run_bp(gpu, sc, 2)
+    dp, doff = t.from_numpy(pts).cuda(), t.from_numpy(off.astype(np.int32)).cuda()
+    keep = gpu.dbscan_denoise(dp, doff, 0.04, 6)
+    for k in (keep, None):
+        vox, voff, status = gpu.voxelize(dp, doff, voxel, keep=k)
+        rv, roff = og.voxelize(pts, off, None if k is None else keep.cpu().numpy(), voxel)
+        assert not status.cpu().numpy().any()
+        assert np.array_equal(voff.cpu().numpy(), roff), "voxel offsets"
+        assert np.array_equal(vox.cpu().numpy(), rv), "voxel lists"
+
+
+def test_voxel_overlap_vs_oracle(gpu):
+    """Segments of one frame against the voxel sets of a second view of the
+    same scene (shifted camera) and against themselves."""
+    t = torch()
+    sc = depth_scene(di.frame_seed(9, 4), 200, 260, n_obj=18)
+    sc2 = depth_scene(di.frame_seed(9, 4), 200, 260, n_obj=18)
+    sc2.camera["t"] = sc2.camera["t"] + np.array([0.03, 0.0, -0.02])
+    sets = []
+    for s in (sc, sc2):
+        pts, off = _run_bp(gpu, s, 1)
+        vox, voff, _ = gpu.voxelize(t.from_numpy(pts).cuda(), t.from_numpy(off.astype(np.int32)).cuda(), 0.05)
+        sets.append((vox, voff))
+    (va, oa), (vb, ob) = sets
+    na, nb = oa.shape[0] - 1, ob.shape[0] - 1
+    pairs = np.array([(i, j) for i in range(na) for j in range(nb)] + [(i, i) for i in range(na)] + [(-1, 0), (0, nb)],
+                     np.int32)
+    cnt = gpu.voxel_overlap(va, oa, vb, ob, t.from_numpy(pairs).cuda())
+    want = og.voxel_overlap(va.cpu().numpy(), oa.cpu().numpy().astype(np.int64), vb.cpu().numpy(),
+                            ob.cpu().numpy().astype(np.int64), [tuple(p) for p in pairs[:-2]])
+    got = cnt.cpu().numpy()
+    assert np.array_equal(got[:-2], want)
+    assert got[-2] == 0 and got[-1] == 0, "pairs out of range count 0"
+    assert got[:-2].max() > 0
+    same = gpu.voxel_overlap(va, oa, va, oa, t.from_numpy(np.array([(i, i) for i in range(na)], np.int32)).cuda())
+    assert np.array_equal(same.cpu().numpy(), np.diff(oa.cpu().numpy())), "a set overlaps itself completely"
