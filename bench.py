@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-query", action="store_true", help="skip the open-vocabulary query leg")
     ap.add_argument("--no-quality", action="store_true", help="skip the view-quality / fusion leg")
     ap.add_argument("--no-ablation", action="store_true", help="skip the weighting-mode ablation leg")
+    ap.add_argument("--no-geometry", action="store_true", help="skip the geometry (back-projection .. overlap) leg")
     ap.add_argument("--edt-layout", type=int, default=-1, choices=[-1, 0, 1],
                     help="distance-transform band layout (-1: chosen per call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -359,6 +360,43 @@ def quality_leg(disc, di, dev, ins, proj, outs, opts, reps: int = 50):
                      "gbs": gbs(fu_bytes, fu_ms), "frac_of_hbm_peak": gbs(fu_bytes, fu_ms) / PEAK_HBM_GBS}}
 
 
+def geometry_leg(disc, di, dev, reps: int = 20):
+    """The mapping side of each segment (Sec. III-B) on one synthetic RGB-D
+    frame (480x640, 40 overlapping dome-shaped objects in front of a plane,
+    range-scaled depth noise, 0.3 % outlier and 1 % missing readings):
+    back-projection of every mask pixel (stride 1), DBSCAN noise removal
+    (eps 3 cm, 8 points), voxel sets (2 cm) and the exact overlap of every
+    segment with every segment of a second view of the scene (camera moved
+    3 cm)."""
+    import torch
+    from disc_inputs.scene import depth_scene
+
+    sc = depth_scene(di.frame_seed(9, 0), 480, 640, n_obj=40)
+    depth = torch.from_numpy(sc.depth).cuda()
+    bits = dev.dev_bits(sc.bits)
+    m = sc.bits.shape[0]
+    bp_ms = _time_ms(lambda: disc.backproject(depth, bits, sc.h, sc.w, sc.camera, 1), reps)
+    pts, off = disc.backproject(depth, bits, sc.h, sc.w, sc.camera, 1)
+    n = pts.shape[0]
+    db_ms = _time_ms(lambda: disc.dbscan_denoise(pts, off, 0.03, 8), reps)
+    keep = disc.dbscan_denoise(pts, off, 0.03, 8)
+    vx_ms = _time_ms(lambda: disc.voxelize(pts, off, 0.02, keep=keep), reps)
+    va, oa, _ = disc.voxelize(pts, off, 0.02, keep=keep)
+    cam2 = dict(sc.camera)
+    cam2["t"] = cam2["t"] + np.array([0.03, 0.0, -0.02])
+    p2, o2 = disc.backproject(depth, bits, sc.h, sc.w, cam2, 1)
+    vb, ob, _ = disc.voxelize(p2, o2, 0.02)
+    pairs = torch.from_numpy(np.array([(i, j) for i in range(m) for j in range(m)], np.int32)).cuda()
+    ov_ms = _time_ms(lambda: disc.voxel_overlap(va, oa, vb, ob, pairs), reps)
+    return {"frame": "480x640 RGB-D, %d segments" % m, "points": int(n), "kept": int(keep.sum().item()),
+            "voxels": int(va.shape[0]), "pairs": int(pairs.shape[0]),
+            "backproject_ms": bp_ms, "backproject_mpts_per_s": n / (bp_ms / 1000.0) / 1e6,
+            "dbscan_ms": db_ms, "dbscan_mpts_per_s": n / (db_ms / 1000.0) / 1e6,
+            "voxelize_ms": vx_ms, "voxelize_mpts_per_s": n / (vx_ms / 1000.0) / 1e6,
+            "overlap_ms": ov_ms, "overlap_pairs_per_s": pairs.shape[0] / (ov_ms / 1000.0),
+            "note": "backproject and voxelize include one host synchronisation each (sizing their outputs)"}
+
+
 ABLATION_MODES = {"edt_x_D": (0, 1), "edt_only": (0, 0), "area_x_D": (1, 1), "area_naive_average": (1, 0)}
 
 
@@ -490,6 +528,7 @@ def main():
     query = None if args.no_query else query_leg(disc, di)
     quality = None if args.no_quality else quality_leg(disc, di, dev, ins, proj, outs, opts)
     ablation = None if args.no_ablation else ablation_leg(disc, di, dev, ins, proj, outs, totals["masks"])
+    geometry = None if args.no_geometry else geometry_leg(disc, di, dev)
 
     # CPU baseline: the FP64 oracle as it stands, one core, bounded sample
     cpu = None
@@ -536,6 +575,7 @@ def main():
         "query_topk": query,
         "view_quality_fusion": quality,
         "ablation": ablation,
+        "geometry": geometry,
     }
     print(json.dumps(res))
 
