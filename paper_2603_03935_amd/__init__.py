@@ -127,6 +127,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libdisc.so not found at {path}; build it with paper_2603_03935_amd/build.py")
+    # PyTorch ships its own HIP runtime: load it first so that the library
+    # binds to the same runtime instance as the tensors it is handed
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     vp, i32 = ctypes.c_void_p, ctypes.c_int32

@@ -21,8 +21,9 @@
 //   voxels           a global hash set of (segment, voxel) keys gives the
 //                    distinct voxels and their count per segment; each
 //                    segment's keys are gathered and sorted in LDS (bitonic);
-//   overlap          one wavefront per (segment, instance) pair: each lane
-//                    binary-searches keys of the shorter list in the longer.
+//   overlap          one workgroup per (segment, instance) pair: the longer
+//                    list is staged in LDS chunk by chunk and the keys of the
+//                    shorter list are binary-searched there.
 #include "disc_device.h"
 
 namespace disc {
@@ -269,6 +270,28 @@ __device__ __forceinline__ int seg_of(const int32_t* off, int m, int i) {
   return lo;
 }
 
+// counter[key] += (number of active lanes with that key), one atomic per
+// distinct key in the wavefront; returns the old value plus this lane's rank
+// among the lanes with its key (lanes whose key repeats are usually
+// neighbours: points are grouped by segment and cell)
+__device__ __forceinline__ int agg_atomic_add(int32_t* counter, int key, bool active) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint64_t pending = __ballot(active);
+  int result = 0;
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const int k = __shfl(key, leader);
+    const uint64_t same = __ballot(active && key == k) & pending;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter + k, __builtin_popcountll(same));
+    base = __shfl(base, leader);
+    if ((same >> lane) & 1ull) result = base + __builtin_popcountll(same & below);
+    pending &= ~same;
+  }
+  return result;
+}
+
 __global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = v;
@@ -284,28 +307,38 @@ struct DbWork {
   int32_t* cur;    // [T]
   int32_t* slot;   // [n]
   int32_t* idx;    // [n] point indices grouped by slot
-  int32_t* core;   // [n]
+  int32_t* core;   // [n] core flag of each sorted position
+  float4* spts;    // [n] the points in slot order
   uint32_t mask;   // T - 1
 };
 
 __global__ __launch_bounds__(256) void k_db_insert(const float* pts, const int32_t* off, int m, int n, float eps,
                                                    DbWork d) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int seg = seg_of(off, m, i);
-  const float* p = pts + 3 * (int64_t)i;
-  bool fresh;
-  const uint32_t h =
-      hash_insert(d.keys, d.mask, cell_key(seg, cell_of(p[0], eps), cell_of(p[1], eps), cell_of(p[2], eps)), fresh);
-  d.slot[i] = (int32_t)h;
-  atomicAdd(d.cnt + h, 1);
+  const bool act = i < n;
+  int h = 0;
+  if (act) {
+    const int seg = seg_of(off, m, i);
+    const float* p = pts + 3 * (int64_t)i;
+    bool fresh;
+    h = (int)hash_insert(d.keys, d.mask, cell_key(seg, cell_of(p[0], eps), cell_of(p[1], eps), cell_of(p[2], eps)),
+                         fresh);
+    d.slot[i] = h;
+  }
+  agg_atomic_add(d.cnt, h, act);
 }
 
-__global__ __launch_bounds__(256) void k_db_fill(int n, DbWork d) {
+// counting sort by slot: idx[pos] = point, spts[pos] = its coordinates
+__global__ __launch_bounds__(256) void k_db_fill(const float* pts, int n, DbWork d) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int h = d.slot[i];
-  d.idx[d.start[h] + atomicAdd(d.cur + h, 1)] = i;
+  const bool act = i < n;
+  const int h = act ? d.slot[i] : 0;
+  const int r = agg_atomic_add(d.cur, h, act);
+  if (!act) return;
+  const int pos = d.start[h] + r;
+  d.idx[pos] = i;
+  const float* p = pts + 3 * (int64_t)i;
+  d.spts[pos] = make_float4(p[0], p[1], p[2], __int_as_float(h));
 }
 
 __device__ __forceinline__ float sqdist(const float* p, const float* q) {
@@ -314,50 +347,52 @@ __device__ __forceinline__ float sqdist(const float* p, const float* q) {
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// PASS 0: core test (stop at min_pts neighbours); PASS 1: border test (stop at
-// the first core neighbour)
+// Over sorted positions t (points of one cell are adjacent, so a wavefront
+// mostly scans the same neighbour lists).  PASS 0: core test (stop at
+// min_pts neighbours); PASS 1: border test (stop at the first core
+// neighbour), keep written at the point's original index.  The point's own
+// cell is visited first.
 template <int PASS>
-__global__ __launch_bounds__(256) void k_db_scan(const float* pts, const int32_t* off, int m, int n, float eps,
-                                                 int min_pts, DbWork d, int32_t* keep) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  if (PASS == 1 && d.core[i]) {
-    keep[i] = 1;
+__global__ __launch_bounds__(256) void k_db_scan(const int32_t* off, int m, int n, float eps, int min_pts, DbWork d,
+                                                 int32_t* keep) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  if (PASS == 1 && d.core[t]) {
+    keep[d.idx[t]] = 1;
     return;
   }
-  const int seg = seg_of(off, m, i);
-  const float* p = pts + 3 * (int64_t)i;
+  const float4 pt = d.spts[t];
+  const float p[3] = {pt.x, pt.y, pt.z};
+  const int seg = (int)(d.keys[__float_as_int(pt.w)] >> 48);
   const float e2 = eps * eps;
   const int cx = cell_of(p[0], eps), cy = cell_of(p[1], eps), cz = cell_of(p[2], eps);
   // clamped cell coordinates can repeat at the edge of the key range: visit
   // each distinct neighbouring cell once (clamping is monotonic, so repeats
   // are adjacent)
-  auto rep = [](int c, int d) { return d > -1 && cell16(c + d) == cell16(c + d - 1); };
+  auto rep = [](int c, int dd) { return dd > -1 && cell16(c + dd) == cell16(c + dd - 1); };
   int found = 0;
   bool done = false;
-  for (int dz = -1; dz <= 1 && !done; ++dz) {
-    if (rep(cz, dz)) continue;
-    for (int dy = -1; dy <= 1 && !done; ++dy) {
-      if (rep(cy, dy)) continue;
-      for (int dx = -1; dx <= 1 && !done; ++dx) {
-        if (rep(cx, dx)) continue;
-        const int h = hash_find(d.keys, d.mask, cell_key(seg, cx + dx, cy + dy, cz + dz));
-        if (h < 0) continue;
-        const int b = d.start[h], e = b + d.cnt[h];
-        for (int k = b; k < e; ++k) {
-          const int q = d.idx[k];
-          if (sqdist(p, pts + 3 * (int64_t)q) <= e2 && (PASS == 0 || d.core[q])) {
-            if (++found >= (PASS == 0 ? min_pts : 1)) {
-              done = true;
-              break;
-            }
-          }
+  for (int k27 = 0; k27 < 27 && !done; ++k27) {
+    // offsets in the order (0,0,0), then the other 26
+    const int c = k27 == 0 ? 13 : (k27 <= 13 ? k27 - 1 : k27);
+    const int dz = c / 9 - 1, dy = (c / 3) % 3 - 1, dx = c % 3 - 1;
+    if (rep(cz, dz) || rep(cy, dy) || rep(cx, dx)) continue;
+    const int h = hash_find(d.keys, d.mask, cell_key(seg, cx + dx, cy + dy, cz + dz));
+    if (h < 0) continue;
+    const int b = d.start[h], e = b + d.cnt[h];
+    for (int k = b; k < e; ++k) {
+      const float4 q = d.spts[k];
+      const float qq[3] = {q.x, q.y, q.z};
+      if (sqdist(p, qq) <= e2 && (PASS == 0 || d.core[k])) {
+        if (++found >= (PASS == 0 ? min_pts : 1)) {
+          done = true;
+          break;
         }
       }
     }
   }
-  if (PASS == 0) d.core[i] = done ? 1 : 0;
-  else keep[i] = done ? 1 : 0;
+  if (PASS == 0) d.core[t] = done ? 1 : 0;
+  else keep[d.idx[t]] = done ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -376,26 +411,28 @@ struct VoxWork {
 __global__ __launch_bounds__(256) void k_vox_insert(const float* pts, const int32_t* off, const int32_t* keep, int m,
                                                     int n, float v, VoxWork d, int32_t* status) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n || (keep && !keep[i])) return;
-  const int seg = seg_of(off, m, i);
-  const float* p = pts + 3 * (int64_t)i;
-  const int vx = cell_of(p[0], v), vy = cell_of(p[1], v), vz = cell_of(p[2], v);
-  if (vx < -32767 || vx > 32767 || vy < -32767 || vy > 32767 || vz < -32767 || vz > 32767) {
-    if (status) status[seg] = 1;
-    return;
+  bool fresh = false;
+  int seg = 0;
+  if (i < n && (!keep || keep[i])) {
+    seg = seg_of(off, m, i);
+    const float* p = pts + 3 * (int64_t)i;
+    const int vx = cell_of(p[0], v), vy = cell_of(p[1], v), vz = cell_of(p[2], v);
+    if (vx < -32767 || vx > 32767 || vy < -32767 || vy > 32767 || vz < -32767 || vz > 32767) {
+      if (status) status[seg] = 1;
+    } else {
+      hash_insert(d.keys, d.mask, cell_key(seg, vx, vy, vz), fresh);
+    }
   }
-  bool fresh;
-  hash_insert(d.keys, d.mask, cell_key(seg, vx, vy, vz), fresh);
-  if (fresh) atomicAdd(d.vcnt + seg, 1);
+  agg_atomic_add(d.vcnt, seg, fresh);
 }
 
 __global__ __launch_bounds__(256) void k_vox_gather(VoxWork d, int64_t T, const int32_t* voff) {
   const int64_t h = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (h >= T) return;
-  const uint64_t k = d.keys[h];
-  if (k == kEmpty) return;
-  const int seg = (int)(k >> 48);
-  d.tmp[voff[seg] + atomicAdd(d.vcur + seg, 1)] = k;
+  const uint64_t k = h < T ? d.keys[h] : kEmpty;
+  const bool act = k != kEmpty;
+  const int seg = act ? (int)(k >> 48) : 0;
+  const int r = agg_atomic_add(d.vcur, seg, act);
+  if (act) d.tmp[voff[seg] + r] = k;
 }
 
 // one workgroup per segment: bitonic sort of its keys in LDS (at most
@@ -447,40 +484,58 @@ __device__ __forceinline__ uint64_t vox_code(const int32_t* v) {
          (uint64_t)(uint32_t)(v[2] + (1 << 20));
 }
 
-// voxel coordinates within +-2^20 (the voxel sets above are within +-32767)
+// One workgroup per (segment, instance) pair: the longer list is staged in
+// LDS in chunks of kOvChunk codes and every key of the shorter list that
+// falls inside a chunk's range is binary-searched there.  Voxel coordinates
+// within +-2^20 (the voxel sets above are within +-32767).
+constexpr int kOvChunk = 4096;
+
 __global__ __launch_bounds__(256) void k_overlap(const int32_t* va, const int32_t* oa, const int32_t* vb,
                                                  const int32_t* ob, const int32_t* pairs, int np, int na, int nb,
                                                  int32_t* out) {
-  const int pr = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (pr >= np) return;
+  __shared__ uint64_t sb[kOvChunk];
+  __shared__ int red[4];
+  const int pr = blockIdx.x;
   const int i = pairs[2 * pr], j = pairs[2 * pr + 1];
   int cnt = 0;
-  if (i >= 0 && i < na && j >= 0 && j < nb) {
+  if (i >= 0 && i < na && j >= 0 && j < nb) {  // uniform over the workgroup
     int a0 = oa[i], a1 = oa[i + 1], b0 = ob[j], b1 = ob[j + 1];
-    const int32_t* s = va;  // the shorter list is searched in the longer
+    const int32_t* s = va;  // keys of the shorter list are searched in the longer
     const int32_t* l = vb;
     if (a1 - a0 > b1 - b0) {
       s = vb;
       l = va;
-      int t0 = a0, t1 = a1;
+      const int t0 = a0, t1 = a1;
       a0 = b0;
       a1 = b1;
       b0 = t0;
       b1 = t1;
     }
-    for (int k = a0 + lane; k < a1; k += 64) {
-      const uint64_t key = vox_code(s + 3 * (int64_t)k);
-      int lo = b0, hi = b1;  // first element >= key
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (vox_code(l + 3 * (int64_t)mid) < key) lo = mid + 1;
-        else hi = mid;
+    if (a1 > a0) {
+      for (int c0 = b0; c0 < b1; c0 += kOvChunk) {
+        const int len = min(kOvChunk, b1 - c0);
+        __syncthreads();
+        for (int k = threadIdx.x; k < len; k += 256) sb[k] = vox_code(l + 3 * (int64_t)(c0 + k));
+        __syncthreads();
+        const uint64_t first = sb[0], last = sb[len - 1];
+        for (int k = a0 + threadIdx.x; k < a1; k += 256) {
+          const uint64_t key = vox_code(s + 3 * (int64_t)k);
+          if (key < first || key > last) continue;
+          int lo = 0, hi = len;  // first element >= key
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sb[mid] < key) lo = mid + 1;
+            else hi = mid;
+          }
+          cnt += (lo < len && sb[lo] == key) ? 1 : 0;
+        }
       }
-      cnt += (lo < b1 && vox_code(l + 3 * (int64_t)lo) == key) ? 1 : 0;
     }
   }
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-  if (lane == 0) out[pr] = cnt;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) out[pr] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -522,7 +577,7 @@ static uint32_t table_size(int n) {
 
 size_t dbscan_ws_bytes(int n) {
   const size_t T = table_size(n);
-  return T * 8 + 3 * T * 4 + 3 * (size_t)n * 4 + scan_scratch_ints((int)T) * 4 + 4096;
+  return T * 8 + 3 * T * 4 + 3 * (size_t)n * 4 + (size_t)n * 16 + scan_scratch_ints((int)T) * 4 + 4096;
 }
 
 void launch_dbscan(const float* pts, const int32_t* off, int m, int n, float eps, int min_pts, int32_t* keep,
@@ -543,6 +598,7 @@ void launch_dbscan(const float* pts, const int32_t* off, int m, int n, float eps
   d.slot = reinterpret_cast<int32_t*>(take((size_t)n * 4));
   d.idx = reinterpret_cast<int32_t*>(take((size_t)n * 4));
   d.core = reinterpret_cast<int32_t*>(take((size_t)n * 4));
+  d.spts = reinterpret_cast<float4*>(take((size_t)n * 16));
   int32_t* scratch = reinterpret_cast<int32_t*>(take(scan_scratch_ints((int)T) * 4));
   d.mask = T - 1;
   hipLaunchKernelGGL(k_fill_u64, dim3((T + 255) / 256), dim3(256), 0, st, d.keys, kEmpty, (int64_t)T);
@@ -551,9 +607,9 @@ void launch_dbscan(const float* pts, const int32_t* off, int m, int n, float eps
   const int nb = (n + 255) / 256;
   hipLaunchKernelGGL(k_db_insert, dim3(nb), dim3(256), 0, st, pts, off, m, n, eps, d);
   exclusive_scan(d.cnt, (int)T, d.start, false, scratch, st);
-  hipLaunchKernelGGL(k_db_fill, dim3(nb), dim3(256), 0, st, n, d);
-  hipLaunchKernelGGL(k_db_scan<0>, dim3(nb), dim3(256), 0, st, pts, off, m, n, eps, min_pts, d, keep);
-  hipLaunchKernelGGL(k_db_scan<1>, dim3(nb), dim3(256), 0, st, pts, off, m, n, eps, min_pts, d, keep);
+  hipLaunchKernelGGL(k_db_fill, dim3(nb), dim3(256), 0, st, pts, n, d);
+  hipLaunchKernelGGL(k_db_scan<0>, dim3(nb), dim3(256), 0, st, off, m, n, eps, min_pts, d, keep);
+  hipLaunchKernelGGL(k_db_scan<1>, dim3(nb), dim3(256), 0, st, off, m, n, eps, min_pts, d, keep);
 }
 
 size_t voxel_ws_bytes(int n, int m) {
@@ -592,7 +648,7 @@ void launch_voxelize(const float* pts, const int32_t* off, const int32_t* keep, 
 
 void launch_overlap(const int32_t* va, const int32_t* oa, int na, const int32_t* vb, const int32_t* ob, int nb,
                     const int32_t* pairs, int np, int32_t* out, hipStream_t st) {
-  if (np > 0) hipLaunchKernelGGL(k_overlap, dim3((np + 3) / 4), dim3(256), 0, st, va, oa, vb, ob, pairs, np, na, nb, out);
+  if (np > 0) hipLaunchKernelGGL(k_overlap, dim3(np), dim3(256), 0, st, va, oa, vb, ob, pairs, np, na, nb, out);
 }
 
 }  // namespace disc
