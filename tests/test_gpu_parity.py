@@ -381,3 +381,36 @@ def test_object_scene_modes_vs_oracle(gpu):
         out = run_frames(gpu, [sc.frame], P, "f32", options=gpu.make_options(spatial, distinct))[0]
         ref = oracle_frame(sc.frame, P, "f32", spatial, distinct)
         check_embeddings(out.out.cpu().numpy(), out.status.cpu().numpy(), ref, COS_FP32, f"scene {spatial}/{distinct}")
+
+
+def test_edt_max_width(gpu):
+    """The widest frame accepted (8448 columns = 256 strips): masks spanning
+    many strips, a full-width band and blobs cut by strip edges."""
+    h, w = 40, 8448
+    rng = np.random.default_rng(8448)
+    u8 = np.zeros((4, h, w), np.uint8)
+    u8[0, 5:30, :] = 1
+    u8[1, :, 100:8400] = 1
+    u8[1, 20, 4000:4100] = 0
+    u8[2] = rng.random((h, w)) < 0.6
+    yy, xx = np.indices((h, w))
+    u8[3] = ((yy - 20) / 18.0) ** 2 + ((xx - 6000) / 2400.0) ** 2 <= 1.0
+    bits = di.pack_masks(u8)
+    got = _edt_gpu(gpu, bits, h, w)
+    want = oracle.edt_sq(bits, w)
+    for i in range(4):
+        assert np.array_equal(got[i], want[i]), f"max-width mask {i}"
+
+
+@pytest.mark.parametrize("patch,C,E", [(8, 128, 128), (64, 256, 256), (16, 2048, 1024)])
+def test_embed_extreme_shapes(gpu, patch, C, E):
+    """Smallest and largest patch sizes, and the largest channel count and
+    embedding width, FP32 path."""
+    h, w = 200, 264
+    gh, gw = -(-h // patch), -(-w // patch)
+    fr = di.Frame(di.tokens_normal(patch + C, gh, gw, C, "f32", patch),
+                  di.masks_mixed(patch + E, 24, h, w, 1e-3, 0.4), h, w)
+    P = di.projection(patch, C, E, "f32")
+    out = run_frames(gpu, [fr], P, "f32")[0]
+    check_embeddings(out.out.cpu().numpy(), out.status.cpu().numpy(), oracle_frame(fr, P, "f32"), COS_FP32,
+                     f"patch {patch} C {C} E {E}")
