@@ -122,12 +122,18 @@ __device__ __forceinline__ uint4 make_rowrec(uint64_t win, int L, int R) {
                     (uint32_t)(uint16_t)a[1] | ((uint32_t)(uint16_t)bnd[1] << 16));
 }
 
+// g of window column l from a record with at most two runs
+__device__ __forceinline__ int g_runs(uint4 r, int l) {
+  const int a1 = (int)(int16_t)(r.z & 0xFFFFu), b1 = (int)r.z >> 16;
+  const int a2 = (int)(int16_t)(r.w & 0xFFFFu), b2 = (int)r.w >> 16;
+  return max(0, max(min(l - a1, b1 - l), min(l - a2, b2 - l)));
+}
+
 // horizontal distance g of window column l from a row record
 __device__ __forceinline__ int g_rec(uint4 r, int l) {
   const int b1 = (int)r.z >> 16;
   if (b1 == kManyRuns) return g_from_window(((uint64_t)r.y << 32) | r.x, l, (int)(r.w & 0xFFFFu), (int)(r.w >> 16));
-  const int a1 = (int)(int16_t)(r.z & 0xFFFFu), a2 = (int)(int16_t)(r.w & 0xFFFFu), b2 = (int)r.w >> 16;
-  return max(0, max(min(l - a1, b1 - l), min(l - a2, b2 - l)));
+  return g_runs(r, l);
 }
 
 // Site m (p < m < q, parabola heights F) never lies strictly below both p and
@@ -236,15 +242,20 @@ __device__ __forceinline__ int sq16(int g) {
   const uint32_t v = (uint32_t)g & 0xFFFFu;
   return (int)(v * v);
 }
-__device__ __forceinline__ int gsq(const uint4* rec, int row, int lane, bool lane_ok) {
-  return lane_ok ? sq16(g_rec(rec[row], lane)) : 0;
+// many = some row of the packet crosses three or more runs (uniform): else
+// the records decode without the bit path and without a branch
+__device__ __forceinline__ int gsq(const uint4* rec, int row, int lane, bool lane_ok, bool many) {
+  const uint4 r = rec[row];
+  const int g = many ? g_rec(r, lane) : g_runs(r, lane);
+  return lane_ok ? sq16(g) : 0;
 }
 
 // Merge the envelope of rows [lo, jb) with the envelope of rows [jb, hi)
 // (lo and jb multiples of 32): pop dominated sites on either side of the
 // junction.  The bitmap words holding the two innermost sites stay in
 // registers while sites are popped and are written back once at the end.
-__device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool lane_ok, int lo, int jb, int hi) {
+__device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool lane_ok, bool many, int lo, int jb,
+                               int hi) {
   int a1 = lds_prev(bm, lane, jb, lo);
   int b1 = lds_next(bm, lane, jb, hi);
   if (a1 < 0 || b1 < 0) return;
@@ -267,9 +278,9 @@ __device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool la
   };
   int a2 = below(a1);
   int b2 = above(b1);
-  int Fa1 = gsq(rec, a1, lane, lane_ok), Fb1 = gsq(rec, b1, lane, lane_ok);
-  int Fa2 = a2 >= 0 ? gsq(rec, a2, lane, lane_ok) : 0;
-  int Fb2 = b2 >= 0 ? gsq(rec, b2, lane, lane_ok) : 0;
+  int Fa1 = gsq(rec, a1, lane, lane_ok, many), Fb1 = gsq(rec, b1, lane, lane_ok, many);
+  int Fa2 = a2 >= 0 ? gsq(rec, a2, lane, lane_ok, many) : 0;
+  int Fb2 = b2 >= 0 ? gsq(rec, b2, lane, lane_ok, many) : 0;
   for (;;) {
     if (a2 >= 0 && dominated(a2, Fa2, a1, Fa1, b1, Fb1)) {
       uwd &= ~(1u << (a1 & 31));
@@ -283,7 +294,7 @@ __device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool la
         udirty = false;
       }
       a2 = below(a1);
-      Fa2 = a2 >= 0 ? gsq(rec, a2, lane, lane_ok) : 0;
+      Fa2 = a2 >= 0 ? gsq(rec, a2, lane, lane_ok, many) : 0;
       continue;
     }
     if (b2 >= 0 && dominated(a1, Fa1, b1, Fb1, b2, Fb2)) {
@@ -298,7 +309,7 @@ __device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool la
         ldirty = false;
       }
       b2 = above(b1);
-      Fb2 = b2 >= 0 ? gsq(rec, b2, lane, lane_ok) : 0;
+      Fb2 = b2 >= 0 ? gsq(rec, b2, lane, lane_ok, many) : 0;
       continue;
     }
     break;
@@ -333,7 +344,7 @@ __device__ __forceinline__ int packet_slot(int mode, const int32_t* counts, cons
 // One packet: wavefront kb holds band j of the item in slot kb / K (its mask
 // record broadcast from pf; word < 0: no item).  `prefetch` is called once,
 // after the row records are in LDS, to start loading the next packet.
-template <int SPATIAL, int B, typename Prefetch>
+template <int SPATIAL, int B, bool WE, typename Prefetch>
 __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* rec_all, uint32_t* bm_all,
                                            float* part_all, int lane, int kb, int32_t* e_out, Prefetch prefetch) {
   constexpr int NW = B / 32;
@@ -364,6 +375,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   // (only read when the edge pixel is inside the mask).
   constexpr int NR = (B + 63) / 64;
   uint4 rreg[NR];  // this lane's rows' records, kept for the sequential pass
+  bool my_many = false;
 #pragma unroll
   for (int rr = 0; rr < NR; ++rr) {
     const int u = b0 + lane + 64 * rr;
@@ -377,9 +389,10 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
         rreg[rr] = make_rowrec(win, L, R);
       }
       rec[u] = rreg[rr];
+      my_many |= ((int)rreg[rr].z >> 16) == kManyRuns;
     }
   }
-  __syncthreads();
+  const bool many = __builtin_amdgcn_readfirstlane(__syncthreads_or(my_many ? 1 : 0)) != 0;
   prefetch();
 
   // ---- this band's lower envelope (sequential in u; row u's record is
@@ -412,7 +425,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
         pop = false;
         if (depth >= 2) {
           s2 = b0 + w.prev(s1 - b0);
-          K2 = gsq(rec, s2, lane, lane_ok) + __mul24(s2, s2);
+          K2 = gsq(rec, s2, lane, lane_ok, many) + __mul24(s2, s2);
           d12 = (double)(s1 - s2);
           dK = (double)(K1 - K2);
           pop = (double)(Ku - K2) * d12 <= dK * (double)(u - s2);
@@ -437,7 +450,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
     for (int step = 1; step < K; step <<= 1) {
       if ((j % (2 * step)) == 0 && j + step < K) {
         const int jb = (j + step) * B;
-        if (jb < n) merge_junction(rec, bm, lane, lane_ok, j * B, jb, min((j + 2 * step) * B, n));
+        if (jb < n) merge_junction(rec, bm, lane, lane_ok, many, j * B, jb, min((j + 2 * step) * B, n));
       }
       __syncthreads();
     }
@@ -449,11 +462,11 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   int c = 0, Fc = 0, nx = -1, Fn = 0;
   if (SPATIAL == 0 && b0 < n) {
     c = lds_prev(bm, lane, b0 + 1, 0);
-    Fc = gsq(rec, c, lane, lane_ok);
+    Fc = gsq(rec, c, lane, lane_ok, many);
     for (;;) {
       const int q = lds_prev(bm, lane, c, 0);
       if (q < 0) break;
-      const int Fq = gsq(rec, q, lane, lane_ok);
+      const int Fq = gsq(rec, q, lane, lane_ok, many);
       if (parab(q, Fq, b0) <= parab(c, Fc, b0)) {
         c = q;
         Fc = Fq;
@@ -462,7 +475,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
       }
     }
     nx = lds_next(bm, lane, c + 1, n);
-    Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok) : 0;
+    Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok, many) : 0;
   }
   // the band's own bitmap word(s) stay in registers for the walk
   const int cw0 = b0 >> 5;
@@ -492,15 +505,38 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
     const int pf_blk = (y0 - 1 + max(blk * 32, 1)) / P;  // first patch row the block meets
     if (inseg == 0 && lane_ok) part[(blk * kEdtPartRows + (pr - pf_blk)) * 8 + lane / P] = v;
   };
-  // rows 0 and n-1 are padding and produce nothing: walk rows [ua, ub)
+  // rows 0 and n-1 are padding and produce nothing: walk rows [ua, ub) in
+  // segments that end where a patch row or a 32-row block ends (flush points)
   const int ua = max(b0, 1), ub = min(b1, n - 1);
   int pr = (y0 - 1 + ua) / P;               // patch row of row u
   int pr_next = (pr + 1) * P - (y0 - 1);    // first row of the next patch row
   int blk = ua >> 5, blk_next = (blk + 1) * 32;
   // site nx takes over from c at row u iff Fn - Fc <= (nx - c)(2u - c - nx)
   int dF = Fn - Fc, dc = nx - c, sc = nx + c;
-  for (int u = ua; u < ub; ++u) {
-    if (u == pr_next || u == blk_next) {
+  int u = ua;
+  while (u < ub) {
+    const int seg_end = min(ub, min(pr_next, blk_next));
+    for (; u < seg_end; ++u) {
+      int e;
+      if (SPATIAL == 0) {
+        while (nx >= 0 && dF <= __mul24(dc, 2 * u - sc)) {
+          c = nx;
+          Fc = Fn;
+          nx = next_site(c + 1);
+          Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok, many) : 0;
+          dF = Fn - Fc;
+          dc = nx - c;
+          sc = nx + c;
+        }
+        e = __mul24(u - c, u - c) + Fc;
+      } else {
+        e = gsq(rec, u, lane, lane_ok, many) > 0 ? 1 : 0;
+      }
+      acc += SPATIAL == 0 ? __builtin_amdgcn_sqrtf((float)e) : (float)e;  // e >= 0 integer: no denormals
+      if (WE && lane_ok && col >= x0 && col <= x1)
+        e_out[(int64_t)gidx * fh * fw + (int64_t)(y0 - 1 + u) * fw + col] = e;
+    }
+    if (u < ub) {  // u is a flush point
       flush(blk, pr, acc);
       acc = 0.f;
       if (u == pr_next) {
@@ -512,24 +548,6 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
         blk_next += 32;
       }
     }
-    int e;
-    if (SPATIAL == 0) {
-      while (nx >= 0 && dF <= __mul24(dc, 2 * u - sc)) {
-        c = nx;
-        Fc = Fn;
-        nx = next_site(c + 1);
-        Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok) : 0;
-        dF = Fn - Fc;
-        dc = nx - c;
-        sc = nx + c;
-      }
-      e = __mul24(u - c, u - c) + Fc;
-    } else {
-      e = gsq(rec, u, lane, lane_ok) > 0 ? 1 : 0;
-    }
-    acc += SPATIAL == 0 ? __builtin_amdgcn_sqrtf((float)e) : (float)e;  // e >= 0 integer: no denormals
-    if (e_out != nullptr && lane_ok && col >= x0 && col <= x1)
-      e_out[(int64_t)gidx * fh * fw + (int64_t)(y0 - 1 + u) * fw + col] = e;
   }
   if (ua < ub) flush(blk, pr, acc);
   __syncthreads();
@@ -566,7 +584,8 @@ __device__ __forceinline__ int pick_mode(const int32_t* counts, int item_cap, in
   return waves0 > 4ll * gridDim.x * kEdtWaves ? 1 : 0;
 }
 
-template <int SPATIAL>  // 0: EDT, 1: AREA (pixel counts, no transform)
+// SPATIAL 0: EDT, 1: AREA (pixel counts, no transform); WE: also write e
+template <int SPATIAL, bool WE>
 __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_edt(
     const int32_t* __restrict__ counts, const int32_t* __restrict__ items, int item_cap,
     const MaskRec* __restrict__ mrec, int32_t* e_out, int mode_arg) {
@@ -603,11 +622,11 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
     };
     const int B = class_band(mode, cls), K = class_waves(mode, cls);
     if (B == 96)
-      edt_packet<SPATIAL, 96>(K, pf, word, rec_all, bm_all, part_all, lane, kb, e_out, prefetch);
+      edt_packet<SPATIAL, 96, WE>(K, pf, word, rec_all, bm_all, part_all, lane, kb, e_out, prefetch);
     else if (B == 64)
-      edt_packet<SPATIAL, 64>(K, pf, word, rec_all, bm_all, part_all, lane, kb, e_out, prefetch);
+      edt_packet<SPATIAL, 64, WE>(K, pf, word, rec_all, bm_all, part_all, lane, kb, e_out, prefetch);
     else
-      edt_packet<SPATIAL, 32>(K, pf, word, rec_all, bm_all, part_all, lane, kb, e_out, prefetch);
+      edt_packet<SPATIAL, 32, WE>(K, pf, word, rec_all, bm_all, part_all, lane, kb, e_out, prefetch);
     cls = ncls;
     word = nword;
     pf = npf;
@@ -616,29 +635,42 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
 
 // Resident workgroups per CU of each variant, computed once (outside any
 // stream capture).
+// Resident workgroups per CU of each variant (EDT, EDT writing e, AREA),
+// computed once (outside any stream capture).
 static std::once_flag g_edt_once;
-static int g_edt_per_cu[2];
+static int g_edt_per_cu[3];
+
+static const void* edt_variant(int v) {
+  return v == 0 ? reinterpret_cast<const void*>(&k_edt<0, false>)
+                : v == 1 ? reinterpret_cast<const void*>(&k_edt<0, true>)
+                         : reinterpret_cast<const void*>(&k_edt<1, false>);
+}
 
 void edt_prepare() {
   std::call_once(g_edt_once, [] {
-    for (int sp = 0; sp < 2; ++sp) {
-      const void* fn = sp == 0 ? reinterpret_cast<const void*>(&k_edt<0>) : reinterpret_cast<const void*>(&k_edt<1>);
+    for (int v = 0; v < 3; ++v) {
       int per_cu = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kEdtWaves * 64, 0) != hipSuccess || per_cu < 1)
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, edt_variant(v), kEdtWaves * 64, 0) != hipSuccess ||
+          per_cu < 1)
         per_cu = 1;
-      g_edt_per_cu[sp] = per_cu;
+      g_edt_per_cu[v] = per_cu;
     }
   });
 }
 
+// e_out (squared distances of the bounding boxes) is written by the EDT
+// variant only; the AREA variant never produces distances.
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode) {
   edt_prepare();
-  const int sp = b.spatial == 0 ? 0 : 1;
-  const int grid = num_cus * g_edt_per_cu[sp];
-  if (sp == 0)
-    hipLaunchKernelGGL(k_edt<0>, dim3(grid), dim3(kEdtWaves * 64), 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, mode);
+  const int v = b.spatial != 0 ? 2 : (e_out ? 1 : 0);
+  const int grid = num_cus * g_edt_per_cu[v];
+  const dim3 blk(kEdtWaves * 64);
+  if (v == 0)
+    hipLaunchKernelGGL((k_edt<0, false>), dim3(grid), blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, mode);
+  else if (v == 1)
+    hipLaunchKernelGGL((k_edt<0, true>), dim3(grid), blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, mode);
   else
-    hipLaunchKernelGGL(k_edt<1>, dim3(grid), dim3(kEdtWaves * 64), 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, mode);
+    hipLaunchKernelGGL((k_edt<1, false>), dim3(grid), blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, nullptr, mode);
 }
 
 }  // namespace disc
