@@ -415,7 +415,8 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
       } else {
         ru = rec[u];  // one broadcast LDS read
       }
-      const int Ku = (lane_ok ? sq16(g_rec(ru, lane)) : 0) + u * u;
+      const int gu = many ? g_rec(ru, lane) : g_runs(ru, lane);
+      const int Ku = (lane_ok ? sq16(gu) : 0) + u * u;
       bool pop = depth >= 2 && (double)(Ku - K2) * d12 <= dK * (double)(u - s2);
       while (pop) {
         w.clear(s1 - b0);
@@ -511,21 +512,22 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   int pr = (y0 - 1 + ua) / P;               // patch row of row u
   int pr_next = (pr + 1) * P - (y0 - 1);    // first row of the next patch row
   int blk = ua >> 5, blk_next = (blk + 1) * 32;
-  // site nx takes over from c at row u iff Fn - Fc <= (nx - c)(2u - c - nx)
-  int dF = Fn - Fc, dc = nx - c, sc = nx + c;
+  // site nx takes over from c at row u iff Fn - Fc <= (nx - c)(2u - c - nx);
+  // without a next site the test is made false (dF = 2^30, dc = 0)
+  int dF = nx >= 0 ? Fn - Fc : (1 << 30), dc = nx >= 0 ? nx - c : 0, sc = nx + c;
   int u = ua;
   while (u < ub) {
     const int seg_end = min(ub, min(pr_next, blk_next));
     for (; u < seg_end; ++u) {
       int e;
       if (SPATIAL == 0) {
-        while (nx >= 0 && dF <= __mul24(dc, 2 * u - sc)) {
+        while (dF <= __mul24(dc, 2 * u - sc)) {
           c = nx;
           Fc = Fn;
           nx = next_site(c + 1);
           Fn = nx >= 0 ? gsq(rec, nx, lane, lane_ok, many) : 0;
-          dF = Fn - Fc;
-          dc = nx - c;
+          dF = nx >= 0 ? Fn - Fc : (1 << 30);
+          dc = nx >= 0 ? nx - c : 0;
           sc = nx + c;
         }
         e = __mul24(u - c, u - c) + Fc;
