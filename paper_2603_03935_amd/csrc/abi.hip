@@ -537,6 +537,17 @@ struct PoolKey {
 std::mutex g_tune_mu;
 std::map<PoolKey, int> g_tune;
 
+// launch the pooling GEMM for a choice nt | (unsplit << 4)
+void launch_pool_choice(const Batch& b, const Work& w, const int4* tiles, hipStream_t st, int choice) {
+  if (choice >> 4) {
+    Batch b1 = b;
+    b1.pool_split = 1;
+    launch_pool(b1, w, tiles, st, choice & 15);
+  } else {
+    launch_pool(b, w, tiles, st, choice & 15);
+  }
+}
+
 int pool_nt_rule(const Shape& s) {
   for (int nt : {4, 2})
     if (pool_nt_valid(s.C, nt) && s.n_tiles / nt * s.pool_split >= 4 * kTargetWGs) return nt;
@@ -544,6 +555,11 @@ int pool_nt_rule(const Shape& s) {
 }
 }  // namespace
 
+// The pooling launch of a problem shape: channels per workgroup (NT x 64) and
+// whether K is split over several workgroups.  Every choice gives the same
+// bits (fixed K groups added in group order), so the first call of a shape
+// times each candidate twice and keeps the fastest; captured graphs and
+// untuned calls use a rule.  Returned as nt | (unsplit << 4).
 int pool_tile_choice(const Plan& p, int tok_dtype, const disc_options& o, bool tune, const Batch& b, const Work& w,
                      const int4* tiles, hipStream_t st, bool* ran) {
   *ran = false;
@@ -557,14 +573,15 @@ int pool_tile_choice(const Plan& p, int tok_dtype, const disc_options& o, bool t
   }
   if (!tune) return pool_nt_rule(s);
   std::vector<int> cand;
-  for (int nt : {1, 2, 4})
-    if (pool_nt_valid(s.C, nt)) cand.push_back(nt);
+  for (int uns = 0; uns < (s.pool_split > 1 ? 2 : 1); ++uns)
+    for (int nt : {1, 2, 4})
+      if (pool_nt_valid(s.C, nt)) cand.push_back(nt | (uns << 4));
   std::vector<hipEvent_t> ev(4 * cand.size());
   for (auto& e : ev) (void)hipEventCreate(&e);
   for (size_t i = 0; i < cand.size(); ++i)
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(ev[4 * i + 2 * rep], st);
-      launch_pool(b, w, tiles, st, cand[i]);
+      launch_pool_choice(b, w, tiles, st, cand[i]);
       (void)hipEventRecord(ev[4 * i + 2 * rep + 1], st);
     }
   (void)hipEventSynchronize(ev.back());
@@ -607,7 +624,7 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
     StageTimer t(sid < 0 ? -1 : ST_POOL, st);
     bool ran = false;
     const int nt = pool_tile_choice(p, tok_dtype, o, tune, b, w, tiles, st, &ran);
-    if (!ran) launch_pool(b, w, tiles, st, nt);
+    if (!ran) launch_pool_choice(b, w, tiles, st, nt);
   }
   { StageTimer t(sid < 0 ? -1 : ST_PROJ, st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, st); }
 }
