@@ -41,11 +41,9 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
   const float* rf = fd.dbar ? wk.r + fd.r_base : nullptr;
   const int P = fd.patch;
   float rsum = 0.f;
-  // walk words tid, tid+256, ... keeping (row, word) without a division per word
-  int row = threadIdx.x / wq, k = threadIdx.x % wq;
-  const int drow = 256 / wq, dk = 256 % wq;
-  for (int64_t i = threadIdx.x; i < nwords; i += 256) {
-    uint64_t v = __builtin_nontemporal_load(mb + i);
+  // words tid, tid+256, ... in groups of four independent loads in flight;
+  // (row, word) of each load without a division per word
+  auto visit = [&](uint64_t v, int row, int k) {
     if (k == wq - 1) v &= last_valid;
     if (v) {
       ymin = min(ymin, row);
@@ -67,12 +65,31 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
         }
       }
     }
-    row += drow;
-    k += dk;
-    if (k >= wq) {
-      k -= wq;
-      row += 1;
+  };
+  int row = threadIdx.x / wq, k = threadIdx.x % wq;
+  const int drow = 256 / wq, dk = 256 % wq;
+  auto step = [&](int& r, int& kk) {
+    r += drow;
+    kk += dk;
+    if (kk >= wq) {
+      kk -= wq;
+      r += 1;
     }
+  };
+  int64_t i = threadIdx.x;
+  for (; i + 3 * 256 < nwords; i += 4 * 256) {
+    uint64_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load(mb + i + q * 256);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      visit(v[q], row, k);
+      step(row, k);
+    }
+  }
+  for (; i < nwords; i += 256) {
+    visit(__builtin_nontemporal_load(mb + i), row, k);
+    step(row, k);
   }
   ymin = wave_min(ymin);
   ymax = wave_max(ymax);
