@@ -165,6 +165,7 @@ Layout make_layout(const Shape& s) {
   L.W = take((s.gemm_bf16 ? 2 : 4) * (size_t)s.sumMGs);
   L.Z = take(4 * (size_t)s.M);
   L.mstat = take(4 * (size_t)s.M);
+  L.perm = take(4 * (size_t)s.M);
   L.X = take((s.gemm_bf16 ? 2 : 4) * (size_t)s.M * s.C);
   L.ppart = take(s.pool_split > 1 ? 4 * (size_t)s.n_tiles * s.kgroups * 64 * 64 : 0);
   L.qpart = take(s.proj_split > 1 ? 4 * (size_t)((s.C + kProjKG - 1) / kProjKG) * s.M * s.E : 0);
@@ -278,6 +279,7 @@ Work work_ptrs(char* base, const Layout& L) {
   w.W = base + L.W;
   w.Z = reinterpret_cast<float*>(base + L.Z);
   w.mstat = reinterpret_cast<int32_t*>(base + L.mstat);
+  w.perm = reinterpret_cast<int32_t*>(base + L.perm);
   w.X = base + L.X;
   w.ppart = reinterpret_cast<float*>(base + L.ppart);
   w.qpart = reinterpret_cast<float*>(base + L.qpart);
@@ -619,7 +621,7 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   }
   { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st); }
   { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st, o.edt_layout); }
-  { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); launch_pool_order(b, w, st); }
   {
     StageTimer t(sid < 0 ? -1 : ST_POOL, st);
     bool ran = false;
@@ -860,6 +862,7 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32
   const Work w = work_ptrs(cx.dev_ws, p.L);
   const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
   launch_user_weights(b, w, wts, cx.st);
+  launch_pool_order(b, w, cx.st);
   if (p.shape.gemm_bf16) launch_token_stats(b, w, p.shape.gmax, 0, 1, cx.st);
   launch_pool(b, w, tiles, cx.st, o.pool_tile > 0 ? o.pool_tile : 1);
   launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, cx.st);

@@ -122,6 +122,7 @@ struct Work {
   void* W;             // [sum m*Gs] GEMM-dtype weights
   float* Z;            // [M] weight sums
   int32_t* mstat;      // [M] 0 ok, 1 empty
+  int32_t* perm;       // [M] pooling order: perm[mask_base + i] = frame-local mask of tile row i
   void* X;             // [M][C] pooled features in the GEMM dtype
   float* ppart;        // pooling group sums [tile][kgroups][64*64] (split K only)
   float* qpart;        // projection group sums [C/256][M][E] (split K only)
@@ -130,6 +131,7 @@ struct Work {
 
 // Host-side launchers (stream = hipStream_t).
 void launch_scan(const Batch& b, const Work& w, hipStream_t st);
+void launch_pool_order(const Batch& b, const Work& w, hipStream_t st);
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode = -1);
 void edt_prepare();
 // want_r: residual norms (needs the mean); pack: k-packed token copy for the BF16 pooling GEMM

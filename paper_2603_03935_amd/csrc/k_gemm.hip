@@ -93,6 +93,9 @@ __device__ __forceinline__ uint16_t tok_bf16(const void* base, int64_t off) {
 
 // K range [kbeg, kend) of a tile: the union of its masks' patch-row ranges
 // (rows of patches outside every mask's box hold zero weights for all of them).
+// Tile row i of a frame holds mask perm[mask_base + i] (masks ordered by the
+// first patch row of their box, so that a tile's range is narrow); which masks
+// share a tile never changes a mask's result.
 __device__ __forceinline__ void tile_krange(const Work& wk, const FrameDesc& fd, int m0, int mrows, int tid,
                                             int* kmin_sh, int* kmax_sh, int& kbeg, int& kend) {
   if (tid == 0) {
@@ -101,7 +104,7 @@ __device__ __forceinline__ void tile_krange(const Work& wk, const FrameDesc& fd,
   }
   __syncthreads();
   if (tid < mrows) {
-    const int4 bb = wk.bbox[fd.mask_base + m0 + tid];
+    const int4 bb = wk.bbox[fd.mask_base + wk.perm[fd.mask_base + m0 + tid]];
     if (bb.x <= bb.y) {
       atomicMin(kmin_sh, (bb.x / fd.patch) * fd.gw);
       atomicMax(kmax_sh, (bb.y / fd.patch + 1) * fd.gw);
@@ -120,8 +123,8 @@ __device__ __forceinline__ void pool_store(const Work& wk, const FrameDesc& fd, 
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int r = 32 * wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-    const int mi = m0 + r;
-    if (mi >= fd.m) continue;
+    if (m0 + r >= fd.m) continue;
+    const int mi = wk.perm[fd.mask_base + m0 + r];
     const int g = fd.mask_base + mi;
     const float Z = wk.Z[g];
     const float val = (wk.mstat[g] == 0 && Z > 0.f) ? acc[v] / Z : 0.f;
@@ -167,9 +170,9 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
 #pragma unroll
   for (int j = 0; j < NT; ++j) total[j] = acc[j] = zero16;
 
-  const int64_t wrow0 = fd.w_base + (int64_t)m0 * fd.Gs;
   const int ar = tid >> 2, ak = (tid & 3) * 8;        // A: row, first k of 8
   const bool arow_ok = ar < mrows;
+  const int64_t wrow0 = fd.w_base + (int64_t)(arow_ok ? wk.perm[fd.mask_base + m0 + ar] : 0) * fd.Gs;
   // B (BF16): channels (tid & 63) + 64 j, patches 8*(tid >> 6) .. +7
   const int bn16 = tid & 63, bk16 = (tid >> 6) * 8;
   // B (FP32): patch tid >> 3, channels 8*(tid & 7) + 64 j .. +7
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   auto fetch = [&](int k0) {
     const int kk = k0 + ak;
     if (BF16) {
-      const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0 + (int64_t)ar * fd.Gs + kk;
+      const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0 + kk;
       if (arow_ok && kk + 8 <= G) {
         ra16 = *reinterpret_cast<const uint4*>(src);
       } else {
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
         }
       }
     } else {
-      const float* src = reinterpret_cast<const float*>(wk.W) + wrow0 + (int64_t)ar * fd.Gs + kk;
+      const float* src = reinterpret_cast<const float*>(wk.W) + wrow0 + kk;
       for (int j = 0; j < 8; ++j) ra32[j] = (arow_ok && kk + j < G) ? src[j] : 0.f;
       const int kr = k0 + bk32;
 #pragma unroll

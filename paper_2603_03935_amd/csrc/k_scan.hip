@@ -182,6 +182,48 @@ void launch_scan(const Batch& b, const Work& w, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// k_pool_order: one workgroup per frame orders its masks for the pooling
+// tiles by the first patch row of their box (counting sort over 256 buckets,
+// empty masks last), so that each 64-mask tile reads a narrow band of token
+// rows.  The order within a bucket follows the atomics and may differ from
+// run to run: which masks share a tile never changes a mask's result.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pool_order(Batch b, Work wk) {
+  const int f = blockIdx.x;
+  if (f >= b.dyn[0]) return;
+  const FrameDesc fd = b.frames[f];
+  __shared__ int cnt[256];
+  __shared__ int wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  cnt[tid] = 0;
+  __syncthreads();
+  auto key = [&](int i) {
+    const int4 bb = wk.bbox[fd.mask_base + i];
+    return bb.x > bb.y ? 255 : min(bb.x / fd.patch, 254);
+  };
+  for (int i = tid; i < fd.m; i += 256) atomicAdd(&cnt[key(i)], 1);
+  __syncthreads();
+  // exclusive prefix of the 256 bucket counts
+  const int v = cnt[tid];
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(x, o);
+    if (lane >= o) x += t;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  int before = 0;
+  for (int k = 0; k < wv; ++k) before += wsum[k];
+  cnt[tid] = before + x - v;
+  __syncthreads();
+  for (int i = tid; i < fd.m; i += 256) wk.perm[fd.mask_base + atomicAdd(&cnt[key(i)], 1)] = i;
+}
+
+void launch_pool_order(const Batch& b, const Work& w, hipStream_t st) {
+  if (b.n_frames > 0 && b.M > 0) hipLaunchKernelGGL(k_pool_order, dim3(b.n_frames), dim3(256), 0, st, b, w);
+}
+
+// ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
