@@ -486,15 +486,17 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
     if (NW > 1) cw.w1 = bm[(cw0 + 1) * 64 + lane];
     if (NW > 2) cw.w2 = bm[(cw0 + 2) * 64 + lane];
   }
-  auto next_site = [&](int pos) -> int {  // lowest envelope row r with pos <= r < n, or -1
-    if (pos >= n) return -1;
-    const int rel = pos - (cw0 << 5);
-    if (rel >= 0 && rel < 32 * NW) {
-      const int r = cw.next(rel);
-      if (r >= 0) return (cw0 << 5) + r < n ? (cw0 << 5) + r : -1;
-      return lds_next(bm, lane, (cw0 + NW) << 5, n);
-    }
-    return lds_next(bm, lane, pos, n);
+  // lowest envelope row r with pos <= r < n, or -1: from the band's own
+  // bitmap words in registers when pos lies in them (no branch), else (rare)
+  // from LDS
+  auto next_site = [&](int pos) -> int {
+    const int base = cw0 << 5;
+    const int rel = pos - base;
+    const bool in = (unsigned)rel < 32u * NW;
+    const int r0 = cw.next(in ? rel : 0);
+    int r = (in && r0 >= 0) ? base + r0 : -1;
+    if (r < 0) r = lds_next(bm, lane, in ? base + 32 * NW : pos, n);
+    return r < n ? r : -1;
   };
   auto flush = [&](int blk, int pr, float v) {
     v = lane_ok ? v : 0.f;
