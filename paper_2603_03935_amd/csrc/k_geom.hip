@@ -399,10 +399,11 @@ __global__ __launch_bounds__(256) void k_db_scan(const int32_t* off, int m, int 
 // voxel sets
 // ---------------------------------------------------------------------------
 struct VoxWork {
-  uint64_t* keys;  // [T] hash set of (segment, voxel)
-  int32_t* vcnt;   // [m]
-  int32_t* vcur;   // [m]
-  uint64_t* tmp;   // [T] gathered keys, grouped by segment
+  uint64_t* keys;   // [T] hash set of (segment, voxel)
+  int32_t* vcnt;    // [m]
+  int32_t* vcur;    // [m]
+  uint64_t* tmp;    // [T] gathered keys, grouped by segment
+  int32_t* fresh;   // [n] slot of the key this point inserted first, or -1
   uint32_t mask;
 };
 
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(256) void k_vox_insert(const float* pts, const int3
                                                     int n, float v, VoxWork d, int32_t* status) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   bool fresh = false;
-  int seg = 0;
+  int seg = 0, h = -1;
   if (i < n && (!keep || keep[i])) {
     seg = seg_of(off, m, i);
     const float* p = pts + 3 * (int64_t)i;
@@ -420,16 +421,20 @@ __global__ __launch_bounds__(256) void k_vox_insert(const float* pts, const int3
     if (vx < -32767 || vx > 32767 || vy < -32767 || vy > 32767 || vz < -32767 || vz > 32767) {
       if (status) status[seg] = 1;
     } else {
-      hash_insert(d.keys, d.mask, cell_key(seg, vx, vy, vz), fresh);
+      h = (int)hash_insert(d.keys, d.mask, cell_key(seg, vx, vy, vz), fresh);
     }
   }
+  if (i < n) d.fresh[i] = fresh ? h : -1;
   agg_atomic_add(d.vcnt, seg, fresh);
 }
 
-__global__ __launch_bounds__(256) void k_vox_gather(VoxWork d, int64_t T, const int32_t* voff) {
-  const int64_t h = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const uint64_t k = h < T ? d.keys[h] : kEmpty;
-  const bool act = k != kEmpty;
+// over the points (grouped by segment, so a wavefront's appends share one
+// counter): the point that inserted a key appends it to its segment's range
+__global__ __launch_bounds__(256) void k_vox_gather(VoxWork d, int n, const int32_t* voff) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int h = i < n ? d.fresh[i] : -1;
+  const bool act = h >= 0;
+  const uint64_t k = act ? d.keys[h] : 0ull;
   const int seg = act ? (int)(k >> 48) : 0;
   const int r = agg_atomic_add(d.vcur, seg, act);
   if (act) d.tmp[voff[seg] + r] = k;
@@ -614,7 +619,7 @@ void launch_dbscan(const float* pts, const int32_t* off, int m, int n, float eps
 
 size_t voxel_ws_bytes(int n, int m) {
   const size_t T = table_size(n);
-  return 2 * T * 8 + 2 * (size_t)(m + 1) * 4 + scan_scratch_ints(m) * 4 + 4096;
+  return 2 * T * 8 + 2 * (size_t)(m + 1) * 4 + (size_t)n * 4 + 4 + scan_scratch_ints(m) * 4 + 4096;
 }
 
 // distinct voxels per segment -> voff [m + 1]; their keys gathered by
@@ -633,6 +638,7 @@ void launch_voxelize(const float* pts, const int32_t* off, const int32_t* keep, 
   d.tmp = reinterpret_cast<uint64_t*>(take((size_t)T * 8));
   d.vcnt = reinterpret_cast<int32_t*>(take((size_t)(m + 1) * 4));
   d.vcur = reinterpret_cast<int32_t*>(take((size_t)(m + 1) * 4));
+  d.fresh = reinterpret_cast<int32_t*>(take((size_t)n * 4 + 4));
   int32_t* scratch = reinterpret_cast<int32_t*>(take(scan_scratch_ints(m) * 4));
   d.mask = T - 1;
   hipLaunchKernelGGL(k_fill_u64, dim3((T + 255) / 256), dim3(256), 0, st, d.keys, kEmpty, (int64_t)T);
@@ -642,7 +648,7 @@ void launch_voxelize(const float* pts, const int32_t* off, const int32_t* keep, 
   if (n > 0)
     hipLaunchKernelGGL(k_vox_insert, dim3((n + 255) / 256), dim3(256), 0, st, pts, off, keep, m, n, v, d, status);
   exclusive_scan(d.vcnt, m, voff, true, scratch, st);
-  hipLaunchKernelGGL(k_vox_gather, dim3((T + 255) / 256), dim3(256), 0, st, d, (int64_t)T, voff);
+  if (n > 0) hipLaunchKernelGGL(k_vox_gather, dim3((n + 255) / 256), dim3(256), 0, st, d, n, voff);
   if (m > 0) hipLaunchKernelGGL(k_vox_sort, dim3(m), dim3(1024), 0, st, d.tmp, voff, vox, status);
 }
 
