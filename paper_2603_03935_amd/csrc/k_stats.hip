@@ -147,61 +147,91 @@ __global__ __launch_bounds__(256) void k_tokpack(Batch b, Work wk) {
   const float* mu = wk.mean + (int64_t)f * C;
   float ss[8];
   for (int i = 0; i < 8; ++i) ss[i] = 0.f;
-  for (int chunk = tid; chunk < C / CW; chunk += 256) {
-    const int c = chunk * CW;
-    float v[8][CW];
-    uint2 codes[8];  // FP8 only: the 8 raw codes of channels c..c+7
-    for (int i = 0; i < 8; ++i) {
-      const int p = p0 + i;
-      codes[i] = make_uint2(0u, 0u);
-      for (int j = 0; j < CW; ++j) v[i][j] = 0.f;
-      if (p >= G) continue;
-      const int64_t off = (int64_t)p * C + c;
-      if (TOK == 0) {
-        const float4 a = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(fd.tokens) + off);
-        v[i][0] = a.x; v[i][1] = a.y; v[i][2] = a.z; v[i][3] = a.w;
-      } else if (TOK == 1) {
-        const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(fd.tokens) + off);
-        v[i][0] = bf16_to_f32(a.x & 0xFFFFu); v[i][1] = bf16_to_f32(a.x >> 16);
-        v[i][2] = bf16_to_f32(a.y & 0xFFFFu); v[i][3] = bf16_to_f32(a.y >> 16);
-      } else {
-        const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(fd.tokens) + off);
-        codes[i] = a;
+  if (TOK == 2) {
+    // FP8: each code is widened once to BF16 bits (exact), which serve both
+    // the k-packed copy and (times the token's scale) the residual norms;
+    // channel by channel, so nothing is held per (token, channel)
+    float sc[8];
+    for (int i = 0; i < 8; ++i) sc[i] = (WANT_R && p0 + i < G) ? fd.scale[p0 + i] : 0.f;
+    for (int chunk = tid; chunk < C / CW; chunk += 256) {
+      const int c = chunk * CW;
+      uint2 codes[8];
+      for (int i = 0; i < 8; ++i) {
+        const int p = p0 + i;
+        codes[i] = p < G ? *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(fd.tokens) + (int64_t)p * C + c)
+                         : make_uint2(0u, 0u);
+      }
+      uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
+      for (int j = 0; j < 8; ++j) {
+        uint32_t q[8];
+        for (int i = 0; i < 8; ++i) q[i] = e4m3_to_bf16_bits(((j < 4 ? codes[i].x : codes[i].y) >> (8 * (j & 3))) & 0xFFu);
+        if (PACK) dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
         if (WANT_R) {
-          const float sc = fd.scale[p];
-          for (int j = 0; j < 8; ++j) v[i][j] = sc * e4m3_to_f32(((j < 4 ? a.x : a.y) >> (8 * (j & 3))) & 0xFFu);
-        }
-      }
-    }
-    if (WANT_R) {
-      for (int j = 0; j < CW; ++j) {
-        const float m = mu[c + j];
-        for (int i = 0; i < 8; ++i) {
-          const float dd = (p0 + i < G) ? v[i][j] - m : 0.f;
-          ss[i] += dd * dd;
-        }
-      }
-    }
-    if (PACK) {
-      if (TOK == 2) {
-        // channel j: the code values of tokens 0..7 widened (exactly) to BF16
-        // -> 16 bytes; the per-token scales live in the weights
-        uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
-        for (int j = 0; j < 8; ++j) {
-          uint32_t q[8];
-          for (int i = 0; i < 8; ++i) q[i] = e4m3_to_bf16_bits(((j < 4 ? codes[i].x : codes[i].y) >> (8 * (j & 3))) & 0xFFu);
-          dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
-        }
-      } else {
-        // channel j: the BF16 values of tokens 0..7 -> 16 bytes
-        uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
-        for (int j = 0; j < 4; ++j) {
-          uint32_t q[8];
+          const float m = mu[c + j];
           for (int i = 0; i < 8; ++i) {
-            const uint32_t u = __float_as_uint(v[i][j]);
-            q[i] = TOK == 1 ? (u >> 16) : ((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+            const float dd = (p0 + i < G) ? sc[i] * bf16_to_f32(q[i]) - m : 0.f;
+            ss[i] += dd * dd;
           }
-          dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
+        }
+      }
+    }
+  } else {
+  for (int chunk = tid; chunk < C / CW; chunk += 256) {
+      const int c = chunk * CW;
+      float v[8][CW];
+      uint2 codes[8];  // FP8 only: the 8 raw codes of channels c..c+7
+      for (int i = 0; i < 8; ++i) {
+        const int p = p0 + i;
+        codes[i] = make_uint2(0u, 0u);
+        for (int j = 0; j < CW; ++j) v[i][j] = 0.f;
+        if (p >= G) continue;
+        const int64_t off = (int64_t)p * C + c;
+        if (TOK == 0) {
+          const float4 a = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(fd.tokens) + off);
+          v[i][0] = a.x; v[i][1] = a.y; v[i][2] = a.z; v[i][3] = a.w;
+        } else if (TOK == 1) {
+          const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(fd.tokens) + off);
+          v[i][0] = bf16_to_f32(a.x & 0xFFFFu); v[i][1] = bf16_to_f32(a.x >> 16);
+          v[i][2] = bf16_to_f32(a.y & 0xFFFFu); v[i][3] = bf16_to_f32(a.y >> 16);
+        } else {
+          const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(fd.tokens) + off);
+          codes[i] = a;
+          if (WANT_R) {
+            const float sc = fd.scale[p];
+            for (int j = 0; j < 8; ++j) v[i][j] = sc * e4m3_to_f32(((j < 4 ? a.x : a.y) >> (8 * (j & 3))) & 0xFFu);
+          }
+        }
+      }
+      if (WANT_R) {
+        for (int j = 0; j < CW; ++j) {
+          const float m = mu[c + j];
+          for (int i = 0; i < 8; ++i) {
+            const float dd = (p0 + i < G) ? v[i][j] - m : 0.f;
+            ss[i] += dd * dd;
+          }
+        }
+      }
+      if (PACK) {
+        if (TOK == 2) {
+          // channel j: the code values of tokens 0..7 widened (exactly) to BF16
+          // -> 16 bytes; the per-token scales live in the weights
+          uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
+          for (int j = 0; j < 8; ++j) {
+            uint32_t q[8];
+            for (int i = 0; i < 8; ++i) q[i] = e4m3_to_bf16_bits(((j < 4 ? codes[i].x : codes[i].y) >> (8 * (j & 3))) & 0xFFu);
+            dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
+          }
+        } else {
+          // channel j: the BF16 values of tokens 0..7 -> 16 bytes
+          uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
+          for (int j = 0; j < 4; ++j) {
+            uint32_t q[8];
+            for (int i = 0; i < 8; ++i) {
+              const uint32_t u = __float_as_uint(v[i][j]);
+              q[i] = TOK == 1 ? (u >> 16) : ((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+            }
+            dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
+          }
         }
       }
     }
