@@ -111,3 +111,29 @@ def test_voxel_overlap_vs_oracle(gpu):
     assert got[:-2].max() > 0
     same = gpu.voxel_overlap(va, oa, va, oa, t.from_numpy(np.array([(i, i) for i in range(na)], np.int32)).cuda())
     assert np.array_equal(same.cpu().numpy(), np.diff(oa.cpu().numpy())), "a set overlaps itself completely"
+
+
+def test_cloud_edge_cases(gpu):
+    """Empty segments, a one-point segment, a segment with more distinct voxels
+    than one workgroup sorts (status 2, its count still exact) and a point
+    whose voxel lies beyond the key range (status 1, the point left out)."""
+    t = torch()
+    rng = np.random.default_rng(71)
+    v = 0.05
+    grid = np.stack(np.meshgrid(np.arange(100), np.arange(100), [0], indexing="ij"), -1).reshape(-1, 3)
+    segs = [np.zeros((0, 3)), np.array([[0.3, 0.2, 1.0]]), 0.3 + 0.01 * rng.standard_normal((5, 3)), np.zeros((0, 3)),
+            (grid + 0.5) * v,                                            # 10000 distinct voxels
+            np.concatenate([rng.uniform(-1, 1, (40, 3)), [[1e6, 0.0, 0.0]]])]  # one point far out
+    pts = np.concatenate(segs).astype(np.float32)
+    off = np.cumsum([0] + [len(x) for x in segs]).astype(np.int64)
+    dp, doff = t.from_numpy(pts).cuda(), t.from_numpy(off.astype(np.int32)).cuda()
+    keep = gpu.dbscan_denoise(dp, doff, 0.05, 3).cpu().numpy()
+    assert np.array_equal(keep, og.dbscan_keep(pts, off, 0.05, 3))
+    vox, voff, status = gpu.voxelize(dp, doff, v)
+    voff, status, vox = voff.cpu().numpy(), status.cpu().numpy(), vox.cpu().numpy()
+    assert status.tolist() == [0, 0, 0, 0, 2, 1]
+    far = np.arange(len(pts)) != len(pts) - 1  # the oracle without the out-of-range point
+    rv, roff = og.voxelize(pts, off, far.astype(np.uint8), v)
+    assert np.array_equal(voff, roff), "voxel counts (exact also for the oversized segment)"
+    for s in (0, 1, 2, 3, 5):
+        assert np.array_equal(vox[voff[s]:voff[s + 1]], rv[roff[s]:roff[s + 1]]), f"segment {s}"
