@@ -191,3 +191,24 @@ def test_quality_chain_on_embeddings(gpu):
                                  np.zeros((16, e)))
     assert np.array_equal(won.cpu().numpy(), rwon) and np.array_equal(map_q.cpu().numpy().astype(np.float64), rq)
     assert np.array_equal(map_emb.cpu().numpy().astype(np.float64), remb)
+
+
+def test_consumers_degenerate_inputs(gpu):
+    """No instances, no voxels, no valid ids: every consumer returns the
+    documented padding and leaves the map untouched."""
+    t = torch()
+    e = 64
+    text = t.ones((3, e), dtype=t.float32, device="cuda")
+    scores, idx, _ = gpu.query_topk(t.zeros((0, e), dtype=t.float32, device="cuda"), text, 4)
+    assert (idx.cpu().numpy() == -1).all() and np.isinf(scores.cpu().numpy()).all()
+    off = t.zeros((5,), dtype=t.int32, device="cuda")  # four detections without voxels
+    ang = gpu.angle_score(t.zeros((0, 3), dtype=t.float32, device="cuda"), t.zeros((0, 3), dtype=t.float32,
+                                                                                   device="cuda"), off)
+    assert ang.cpu().tolist() == [0.0] * 4
+    map_q = t.full((3,), 0.5, dtype=t.float32, device="cuda")
+    map_emb = t.ones((3, e), dtype=t.float32, device="cuda")
+    ids = t.tensor([-1, 3, 7], dtype=t.int32, device="cuda")
+    won = gpu.fuse(ids, t.ones((3,), dtype=t.float32, device="cuda"), t.zeros((3, e), dtype=t.float32, device="cuda"),
+                   map_q, map_emb)
+    assert won.cpu().tolist() == [0, 0, 0]
+    assert map_q.cpu().tolist() == [0.5] * 3 and bool((map_emb == 1).all())
