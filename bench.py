@@ -142,6 +142,13 @@ def workload_units(wl, gemm_bf16: bool):
                 edt_px += (bb[1] - bb[0] + 3) * (bb[3] - bb[2] + 3)
         nnz += _touched_patches(f.bits, f.h, f.w, t.patch)
     gdt = "bf16" if gemm_bf16 else "f32"
+    gb = 2 if gemm_bf16 else 4
+    # bytes a GEMM must move at least: pooling reads each frame's tokens (as
+    # the GEMM operand) and the weights once and writes X; projection reads X
+    # and P once and writes the FP32 rows
+    pool_bytes = (tkp_bytes if gemm_bf16 else tok_bytes) + w_bytes + M * C * gb
+    proj_bytes = M * C * gb + C * E * gb + M * E * 4
+    hbm_views = {"pool": pool_bytes, "proj": proj_bytes}
     return {
         "scan": ("hbm", bits_bytes, "B"),
         "edt": ("alu", EDT_OPS_PER_PIXEL * edt_px, "op"),
@@ -149,7 +156,7 @@ def workload_units(wl, gemm_bf16: bool):
         "weights": ("hbm", w_bytes, "B"),
         "pool": ("mfma:" + gdt, 2.0 * nnz * C, "flop"),
         "proj": ("mfma:" + gdt, 2.0 * M * C * E, "flop"),
-    }, {"masks": M, "edt_pixels": edt_px, "touched_patches": nnz}
+    }, {"masks": M, "edt_pixels": edt_px, "touched_patches": nnz, "hbm_views": hbm_views}
 
 
 def _source_sha(stage: str) -> str:
@@ -170,6 +177,32 @@ def _traffic(stage: str, workload: str):
     if not ent or ent.get("source_sha") != _source_sha(stage):
         return None
     return ent["hbm_bytes_per_launch"]
+
+
+def stage_rooflines(avg: dict, units, totals) -> dict:
+    """Every stage against its own bound (from the untimed breakdown pass);
+    the GEMM stages also against HBM with the bytes they must move."""
+    out = {}
+    for st, ms in avg.items():
+        if st not in units or ms <= 0:
+            continue
+        bound, amount, _ = units[st]
+        t = ms / 1000.0
+        if bound == "hbm":
+            r = {"bound": "hbm", "achieved": amount / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+        elif bound == "alu":
+            r = {"bound": "alu", "achieved": amount / t / 1e12, "peak": PEAK_ALU_TOPS, "unit": "Tops/s"}
+        else:
+            r = {"bound": "mfma", "achieved": amount / t / 1e12, "peak": PEAK_TFLOPS[bound.split(":")[1]],
+                 "unit": "TFLOP/s"}
+        r["frac"] = r["achieved"] / r["peak"]
+        hb = totals.get("hbm_views", {}).get(st)
+        if hb:
+            r["hbm_gbs"] = hb / t / 1e9
+            r["hbm_frac"] = r["hbm_gbs"] / PEAK_HBM_GBS
+        r["avg_ms"] = ms
+        out[st] = r
+    return out
 
 
 def roofline(stage: str, avg_ms: float, units, workload: str):
@@ -567,7 +600,8 @@ def main():
         "config": {"workload": args.config, "desc": CONFIG_DESC[args.config], "frames": len(wl.frames),
                    "masks_per_step": totals["masks"], "frames_per_s": len(wl.frames) / (ms_per_step / 1000.0),
                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                   "stage_avg_ms": avg, "edt_pixels": totals["edt_pixels"],
+                   "stage_avg_ms": avg, "stage_roofline": stage_rooflines(avg, units, totals),
+                   "edt_pixels": totals["edt_pixels"],
                    "touched_patches": totals["touched_patches"]},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -36,3 +36,18 @@ def test_workload_units_counts():
     assert units["scan"][1] == f.bits.nbytes
     r = bench.roofline("edt", 1.0, units, "cfg1")
     assert r["bound"] == "alu" and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-15
+
+
+def test_stage_rooflines():
+    wl = di.workload("cfg1")
+    units, tot = bench.workload_units(wl, gemm_bf16=False)
+    avg = {"scan": 0.01, "edt": 0.1, "token_stats": 0.02, "weights": 0.005, "pool": 0.03, "proj": 0.02}
+    r = bench.stage_rooflines(avg, units, tot)
+    assert set(r) == set(avg)
+    assert r["scan"]["bound"] == "hbm" and abs(r["scan"]["achieved"] - units["scan"][1] / 1e-5 / 1e9) < 1e-6
+    assert r["proj"]["bound"] == "mfma" and r["proj"]["peak"] == bench.PEAK_TFLOPS["f32"]
+    f = wl.frames[0]
+    C, E = 1024, 768
+    assert abs(r["proj"]["hbm_gbs"] * 2e-5 * 1e9 - (f.m * C * 4 + C * E * 4 + f.m * E * 4)) < 1e-3
+    for v in r.values():
+        assert abs(v["frac"] - v["achieved"] / v["peak"]) < 1e-15
