@@ -169,6 +169,7 @@ Layout make_layout(const Shape& s) {
   L.X = take((s.gemm_bf16 ? 2 : 4) * (size_t)s.M * s.C);
   L.ppart = take(s.pool_split > 1 ? 4 * (size_t)s.n_tiles * s.kgroups * 64 * 64 : 0);
   L.qpart = take(s.proj_split > 1 ? 4 * (size_t)((s.C + kProjKG - 1) / kProjKG) * s.M * s.E : 0);
+  L.ppack = take(s.gemm_bf16 ? 2 * (size_t)s.C * s.E : 0);
   L.tkp = take(s.gemm_bf16 ? (size_t)s.tkp_elems * s.tkp_esize : 0);
   L.total = off;
   return L;
@@ -283,6 +284,7 @@ Work work_ptrs(char* base, const Layout& L) {
   w.X = base + L.X;
   w.ppart = reinterpret_cast<float*>(base + L.ppart);
   w.qpart = reinterpret_cast<float*>(base + L.qpart);
+  w.ppack = base + L.ppack;
   w.tkp = base + L.tkp;
   return w;
 }
@@ -358,8 +360,13 @@ void choose_splits(Shape& s) {
   const int pool_tiles = std::max(1, s.n_tiles);
   s.pool_split = pool_tiles >= kTargetWGs ? 1 : std::min(s.kgroups, (kTargetWGs + pool_tiles - 1) / pool_tiles);
   const int qgroups = std::max(1, (s.C + kProjKG - 1) / kProjKG);
-  const int64_t proj_tiles = std::max<int64_t>(1, (s.M + 31) / 32 * (s.E / 128));
-  s.proj_split = proj_tiles >= kTargetWGs ? 1 : (int)std::min<int64_t>(qgroups, (kTargetWGs + proj_tiles - 1) / proj_tiles);
+  // BF16 tiles are 128 rows and run a whole K in a few microseconds, so they
+  // split K only when too few to spread over the chip: the group sums cost
+  // 8 bytes per group, row and column of extra traffic.
+  const int rows = s.gemm_bf16 ? 128 : 32;
+  const int64_t proj_tiles = std::max<int64_t>(1, (s.M + rows - 1) / rows * (s.E / 128));
+  const int64_t enough = s.gemm_bf16 ? kTargetWGs / 8 : kTargetWGs;
+  s.proj_split = proj_tiles >= enough ? 1 : (int)std::min<int64_t>(qgroups, (kTargetWGs + proj_tiles - 1) / proj_tiles);
 }
 
 void stage_host(const Plan& p, char* host, char* dev) {

@@ -126,6 +126,7 @@ struct Work {
   void* X;             // [M][C] pooled features in the GEMM dtype
   float* ppart;        // pooling group sums [tile][kgroups][64*64] (split K only)
   float* qpart;        // projection group sums [C/256][M][E] (split K only)
+  void* ppack;         // k-packed BF16 copy of P [C/8][E][8] (BF16 GEMMs)
   void* tkp;           // k-packed tokens [sum ceil(G/8)][C][8], BF16 bits (FP8 tokens: their code values)
 };
 

@@ -466,14 +466,186 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
   }
   if (kstart < kstop) fold(cur);
   if (S > 1) return;
-  // ---- store the unnormalised rows ----
+  // ---- store the unnormalised rows (row pointers resolved once per tile) ----
+  __shared__ float* rowp[32];
+  if (tid < 32) {
+    const int g = gbase + tid;
+    float* p = nullptr;
+    if (g < M) {
+      const FrameDesc& fd = b.frames[b.mask_frame[g]];
+      p = fd.out + (int64_t)(g - fd.mask_base) * E;
+    }
+    rowp[tid] = p;
+  }
+  __syncthreads();
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    const int g = gbase + 8 * (v >> 2) + 4 * lk + (v & 3);
-    if (g >= M) continue;
-    const FrameDesc& fd = b.frames[b.mask_frame[g]];
-    fd.out[(int64_t)(g - fd.mask_base) * E + col] = total[v];
+    const int r = 8 * (v >> 2) + 4 * lk + (v & 3);
+    if (gbase + r < M) rowp[r][col] = total[v];
   }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 projection, large tiles: 128 rows x 128 columns per workgroup, 4
+// wavefronts of 64 x 64 (2 x 2 MFMA 32x32x16 tiles each).  A = X rows (k
+// contiguous), B = a k-packed copy of P ([C/8][E][8], written by
+// k_pack_proj: 8 consecutive k of one column in 16 bytes), both staged in LDS
+// as [row][k] / [column][k] so every load is 16 bytes.  The MFMA, its k
+// order within a group and the K groups are those of k_proj, so the result is
+// the same bits.
+// ---------------------------------------------------------------------------
+template <int PBF16>
+__global__ __launch_bounds__(256) void k_pack_proj(const void* proj, int C, int E, uint4* ppack) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)(C / 8) * E) return;
+  const int kg = (int)(t / E), n = (int)(t - (int64_t)kg * E);
+  uint32_t q[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t off = (int64_t)(kg * 8 + j) * E + n;
+    q[j] = PBF16 ? reinterpret_cast<const uint16_t*>(proj)[off] : f2bf(reinterpret_cast<const float*>(proj)[off]);
+  }
+  ppack[t] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
+}
+
+__global__ __launch_bounds__(256) void k_proj_bf16(Batch b, Work wk) {
+  constexpr int BK = 128, AS = BK + 8;
+  const int C = b.C, E = b.E, S = b.proj_split;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
+  const int rt = blockIdx.x / S, sidx = blockIdx.x - rt * S;
+  const int gbase = rt * 128, c0 = blockIdx.y * 128;
+  const int M = b.dyn[1];
+  if (gbase >= M) return;
+  const int ngr = (C + kProjKG - 1) / kProjKG;
+  const int per = (ngr + S - 1) / S;
+  const int ga = sidx * per, gb = min(ngr, ga + per);
+  const int kstart = ga * kProjKG, kstop = min(C, gb * kProjKG);
+  __shared__ __attribute__((aligned(16))) uint16_t As[128 * AS];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[128 * AS];
+  // running sum of the K groups (unsplit K), one float4 slot set per thread:
+  // slot (4 (2 i + j) + v / 4) of thread t at [slot][t]
+  __shared__ float4 Ts[16 * 256];
+
+  const floatx16 zero16 = {};
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = zero16;
+  if (S == 1)
+    for (int t = 0; t < 16; ++t) Ts[t * 256 + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  // loaders, 8 chunks of 8 k (16 bytes) per thread and operand: A chunk
+  // q = tid + 256 i is row q >> 4, k 8 (q & 15); B chunk q is k group q >> 7
+  // of column q & 127.  Chunks past the K range (C a multiple of 64 only)
+  // load zeros and their MFMAs are skipped.
+  const uint16_t* X = reinterpret_cast<const uint16_t*>(wk.X);
+  const uint4* pp = reinterpret_cast<const uint4*>(wk.ppack);
+  uint4 ra[8], rb[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int q = tid + 256 * i, r = q >> 4, ka = k0 + 8 * (q & 15);
+      ra[i] = gbase + r < M && ka < kstop ? *reinterpret_cast<const uint4*>(X + (int64_t)(gbase + r) * C + ka)
+                                          : make_uint4(0, 0, 0, 0);
+      const int kb = k0 + 8 * (q >> 7);
+      rb[i] = kb < kstop ? pp[(int64_t)(kb >> 3) * E + c0 + (q & 127)] : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int q = tid + 256 * i;
+      *reinterpret_cast<uint4*>(&As[(q >> 4) * AS + 8 * (q & 15)]) = ra[i];
+      *reinterpret_cast<uint4*>(&Bs[(q & 127) * AS + 8 * (q >> 7)]) = rb[i];
+    }
+  };
+  const int lr = lane & 31, lk = lane >> 5;
+  auto fold = [&](int grp) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (S == 1) {
+#pragma unroll
+          for (int v4 = 0; v4 < 4; ++v4) {
+            float4& t = Ts[(4 * (2 * i + j) + v4) * 256 + tid];
+            float4 u = t;
+            u.x += acc[i][j][4 * v4];
+            u.y += acc[i][j][4 * v4 + 1];
+            u.z += acc[i][j][4 * v4 + 2];
+            u.w += acc[i][j][4 * v4 + 3];
+            t = u;
+          }
+        } else {
+          const int col = c0 + 64 * wn + 32 * j + lr;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int g = gbase + 64 * wm + 32 * i + 8 * (v >> 2) + 4 * lk + (v & 3);
+            if (g < M) wk.qpart[((int64_t)grp * b.M + g) * E + col] = acc[i][j][v];
+          }
+        }
+        acc[i][j] = zero16;
+      }
+  };
+
+  int cur = kstart / kProjKG;
+  if (kstart < kstop) fetch(kstart);
+  for (int k0 = kstart; k0 < kstop; k0 += BK) {
+    if (k0 / kProjKG != cur) {
+      fold(cur);
+      cur = k0 / kProjKG;
+    }
+    stage();
+    __syncthreads();
+    if (k0 + BK < kstop) fetch(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      if (k0 + kk >= kstop) break;
+      u16x8 av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = *reinterpret_cast<const u16x8*>(&As[(64 * wm + 32 * i + lr) * AS + kk + 8 * lk]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const u16x8*>(&Bs[(64 * wn + 32 * j + lr) * AS + kk + 8 * lk]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[i]),
+                                                              __builtin_bit_cast(bf16x8, bv[j]), acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  if (kstart < kstop) fold(cur);
+  if (S > 1) return;
+  // output row pointers of the tile, resolved once
+  __shared__ float* rowp[128];
+  if (tid < 128) {
+    const int g = gbase + tid;
+    float* p = nullptr;
+    if (g < M) {
+      const FrameDesc& fd = b.frames[b.mask_frame[g]];
+      p = fd.out + (int64_t)(g - fd.mask_base) * E;
+    }
+    rowp[tid] = p;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = c0 + 64 * wn + 32 * j + lr;
+#pragma unroll
+      for (int v4 = 0; v4 < 4; ++v4) {
+        const float4 t = Ts[(4 * (2 * i + j) + v4) * 256 + tid];
+        const float tv[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = 64 * wm + 32 * i + 8 * v4 + 4 * lk + u;
+          if (gbase + r < M) rowp[r][col] = tv[u];
+        }
+      }
+    }
 }
 
 // One wavefront per row: (split K: add the group sums in group order and)
@@ -525,11 +697,15 @@ __global__ __launch_bounds__(256) void k_norm(Batch b, Work wk) {
 
 void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st) {
   if (b.M <= 0) return;
-  const dim3 grid((b.M + 31) / 32 * b.proj_split, b.E / 128), block(256);
+  const dim3 block(256);
   if (b.gemm_bf16) {
-    if (proj_bf16) hipLaunchKernelGGL((k_proj<1, 1>), grid, block, 0, st, b, w, proj);
-    else hipLaunchKernelGGL((k_proj<1, 0>), grid, block, 0, st, b, w, proj);
+    const int64_t np = (int64_t)(b.C / 8) * b.E;
+    const dim3 pg((unsigned)((np + 255) / 256));
+    if (proj_bf16) hipLaunchKernelGGL((k_pack_proj<1>), pg, block, 0, st, proj, b.C, b.E, reinterpret_cast<uint4*>(w.ppack));
+    else hipLaunchKernelGGL((k_pack_proj<0>), pg, block, 0, st, proj, b.C, b.E, reinterpret_cast<uint4*>(w.ppack));
+    hipLaunchKernelGGL(k_proj_bf16, dim3((b.M + 127) / 128 * b.proj_split, b.E / 128), block, 0, st, b, w);
   } else {
+    const dim3 grid((b.M + 31) / 32 * b.proj_split, b.E / 128);
     if (proj_bf16) hipLaunchKernelGGL((k_proj<0, 1>), grid, block, 0, st, b, w, proj);
     else hipLaunchKernelGGL((k_proj<0, 0>), grid, block, 0, st, b, w, proj);
   }

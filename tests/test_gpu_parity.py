@@ -308,6 +308,20 @@ def test_pool_tile_widths_agree_bitwise(gpu, name, frames):
             assert np.array_equal(a, b), f"{name}: pool_tile {nt} differs from the tuned width on frame {i}"
 
 
+def test_projection_split_invariance(gpu):
+    """The BF16 projection runs whole-K tiles on a full cfg3 batch and split-K
+    tiles (group sums added in group order) on a few of its frames: the same
+    frames get the same bits either way."""
+    wl = di.workload("cfg3")
+    ins = [frame_input(f) for f in wl.frames]
+    proj = dev_proj(wl.proj, wl.proj_dtype)
+    full = gpu.embed_frames(ins, proj)
+    few = gpu.embed_frames(ins[:3], proj)
+    assert sum(o.out.shape[0] for o in full) > 128 * 64 // 6, "the full batch must take the whole-K path"
+    for i in range(3):
+        assert np.array_equal(full[i].out.cpu().numpy(), few[i].out.cpu().numpy()), f"frame {i}: split-K result differs"
+
+
 # ---------------------------------------------------------------- open-vocabulary query
 
 def _check_topk(scores, idx, ref, tol, what):
