@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--no-quality", action="store_true", help="skip the view-quality / fusion leg")
     ap.add_argument("--no-ablation", action="store_true", help="skip the weighting-mode ablation leg")
     ap.add_argument("--no-geometry", action="store_true", help="skip the geometry (back-projection .. overlap) leg")
-    ap.add_argument("--edt-layout", type=int, default=-1, choices=[-1, 0, 1],
+    ap.add_argument("--edt-layout", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="distance-transform band layout (-1: chosen per call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference that "

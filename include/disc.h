@@ -130,11 +130,11 @@ typedef struct disc_options {
                              accumulation in every case. */
   void* workspace;        /* optional caller-owned device workspace */
   size_t workspace_bytes; /* its size; see disc_workspace_bytes() */
-  int32_t edt_layout;     /* distance-transform band layout: -1 (default)
-                             chosen per call from the amount of work, 0 short
-                             bands (lowest latency for few masks), 1 longer
-                             bands (throughput for large batches).  Results
-                             are identical bit for bit in every layout. */
+  int32_t edt_layout;     /* distance-transform layout: -1 (default) and 2
+                             the direct column search; 0 and 1 the lower-
+                             envelope kernel with short (0) or longer (1)
+                             bands.  Results are identical bit for bit in
+                             every layout. */
   int32_t pool_tile;      /* channels per pooling workgroup in units of 64:
                              -1 (default) autotuned (the first call with a
                              new problem shape times every width and keeps

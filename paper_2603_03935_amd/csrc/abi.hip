@@ -122,8 +122,8 @@ disc_status check_opts(const disc_options* o, const char* who) {
   if (o->gemm_dtype != -1 && o->gemm_dtype != DISC_F32 && o->gemm_dtype != DISC_BF16)
     return fail(DISC_ERR_UNSUPPORTED_DTYPE, "%s: gemm dtype must be F32, BF16 or -1", who);
   if (o->workspace && !aligned16(o->workspace)) return fail(DISC_ERR_ALIGNMENT, "%s: workspace must be 16-byte aligned", who);
-  if (o->edt_layout < -1 || o->edt_layout > 1)
-    return fail(DISC_ERR_INVALID_ARGUMENT, "%s: edt_layout must be -1, 0 or 1", who);
+  if (o->edt_layout < -1 || o->edt_layout > 2)
+    return fail(DISC_ERR_INVALID_ARGUMENT, "%s: edt_layout must be -1, 0, 1 or 2", who);
   if (o->pool_tile != -1 && o->pool_tile != 1 && o->pool_tile != 2 && o->pool_tile != 4)
     return fail(DISC_ERR_INVALID_ARGUMENT, "%s: pool_tile must be -1, 1, 2 or 4", who);
   return DISC_OK;
@@ -298,6 +298,7 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
   Shape& s = p.shape;
   s.n_frames = (int)fr.size();
   s.want_dbar = false;
+  s.max_rows = 0;
   s.C = C;
   s.E = E;
   s.gemm_bf16 = gemm_bf16;
@@ -317,6 +318,7 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
     d.dbar = f.dbar;
     d.area_out = f.area;
     if (f.dbar) s.want_dbar = true;
+    s.max_rows = std::max(s.max_rows, std::min(f.h + 2, kMaxRows));
     d.gh = f.gh;
     d.gw = f.gw;
     d.patch = f.patch;
@@ -399,6 +401,7 @@ Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int disti
   b.kgroups = p.shape.kgroups;
   b.pool_split = p.shape.pool_split;
   b.proj_split = p.shape.proj_split;
+  b.max_rows = p.shape.max_rows > 0 ? p.shape.max_rows : kMaxRows;
   return b;
 }
 

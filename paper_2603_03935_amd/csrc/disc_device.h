@@ -104,6 +104,7 @@ struct Batch {
   int32_t kgroups;            // pooling K groups of the largest frame
   int32_t pool_split, proj_split;  // workgroups sharing one GEMM tile's K range
   float eps;                  // Eq. (1) epsilon (only the mean distinctiveness uses it)
+  int32_t max_rows;           // tallest frame + 2 (the tallest distance-transform item)
 };
 
 // Workspace pointers (device).

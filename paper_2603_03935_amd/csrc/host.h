@@ -25,6 +25,7 @@ struct Shape {
   int kgroups = 1;        // pooling K groups of the largest frame
   int pool_split = 1, proj_split = 1;
   bool want_dbar = false;  // some frame asks for the mean distinctiveness (needs r and its mean)
+  int max_rows = kMaxRows;  // tallest frame + 2 (distance-transform rows of the tallest item)
 };
 
 // Split K of the pooling / projection GEMMs when their tiles alone would not

@@ -11,7 +11,12 @@
 // nearest outside pixel lies in that ring or inside the box, so the result is
 // the full-plane one.
 //
-// GPU decomposition (one workgroup per (mask, column strip) work item; a grid
+// Two kernels compute it.  The default, k_edt_direct, tabulates g per (row,
+// column) in LDS and searches each pixel's column outward (see there).  The
+// lower-envelope kernel k_edt (layouts 0 and 1) is kept as a second,
+// independent computation of the same bits.
+//
+// Envelope decomposition (one workgroup per (mask, column strip) work item; a grid
 // sized to the resident capacity takes the items of a class in a fixed stride):
 //   * lanes = 64 consecutive columns, wavefront k = rows [96k, 96k+96) of the
 //     padded box ("band");
@@ -318,6 +323,44 @@ __device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool la
   if (ldirty) bm[lwi * 64 + lane] = lwd;
 }
 
+// Partial patch sums of one 32-row block: the per-lane sums v of the block's
+// rows in patch row pr are added across the P lanes of each patch (a fixed
+// tree) and stored at (block, patch row within the block, patch column).
+__device__ __forceinline__ void flush_patch_part(float* part, int lane, bool lane_ok, int P, int y0, int blk, int pr,
+                                                 float v) {
+  v = lane_ok ? v : 0.f;
+  const int inseg = lane % P;
+  for (int o = 1; o < P; o <<= 1) {
+    const float t = __shfl_down(v, o);
+    if (inseg + o < P && lane + o < 64) v += t;
+  }
+  const int pf_blk = (y0 - 1 + max(blk * 32, 1)) / P;  // first patch row the block meets
+  if (inseg == 0 && lane_ok) part[(blk * kEdtPartRows + (pr - pf_blk)) * 8 + lane / P] = v;
+}
+
+// The strip's patch sums: each patch row adds the partial sums of the 32-row
+// blocks that meet it, in block order.  Wavefront j of the K that share the
+// item takes every K-th patch.
+__device__ __forceinline__ void strip_patch_sums(const float* part, float* srow, int lane, int j, int K, int P, int SW,
+                                                 int xs, int y0, int y1, int gw) {
+  const int npc = SW / P;
+  const int prbase = y0 / P;
+  const int npr = y1 / P - prbase + 1;
+  const int pc0 = xs / P;
+  for (int idx = j * 64 + lane; idx < npr * npc; idx += K * 64) {
+    const int prl = idx / npc, q = idx - prl * npc;
+    const int pc = pc0 + q;
+    const int pr = prbase + prl;
+    const int ua = max(pr * P, y0) - y0 + 1, ub = min(pr * P + P - 1, y1) - y0 + 1;
+    float v = 0.f;
+    for (int kk = ua >> 5; kk <= ub >> 5; ++kk) {
+      const int pf_blk = (y0 - 1 + max(kk * 32, 1)) / P;
+      v += part[(kk * kEdtPartRows + (pr - pf_blk)) * 8 + q];
+    }
+    if (pc < gw) srow[pr * gw + pc] = v;
+  }
+}
+
 // Packets: the items of class c are grouped class_items(c) at a time; the
 // packets of the tallest class come first so that the longest work starts
 // first.  Returns the class of packet p (or -1 past the end) and the item word
@@ -498,16 +541,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
     if (r < 0) r = lds_next(bm, lane, in ? base + 32 * NW : pos, n);
     return r < n ? r : -1;
   };
-  auto flush = [&](int blk, int pr, float v) {
-    v = lane_ok ? v : 0.f;
-    const int inseg = lane % P;
-    for (int o = 1; o < P; o <<= 1) {
-      const float t = __shfl_down(v, o);
-      if (inseg + o < P && lane + o < 64) v += t;
-    }
-    const int pf_blk = (y0 - 1 + max(blk * 32, 1)) / P;  // first patch row the block meets
-    if (inseg == 0 && lane_ok) part[(blk * kEdtPartRows + (pr - pf_blk)) * 8 + lane / P] = v;
-  };
+  auto flush = [&](int blk, int pr, float v) { flush_patch_part(part, lane, lane_ok, P, y0, blk, pr, v); };
   // rows 0 and n-1 are padding and produce nothing: walk rows [ua, ub) in
   // segments that end where a patch row or a 32-row block ends (flush points)
   const int ua = max(b0, 1), ub = min(b1, n - 1);
@@ -556,26 +590,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   if (ua < ub) flush(blk, pr, acc);
   __syncthreads();
 
-  // ---- the strip's patch sums: each patch row adds the partial sums of the
-  // 32-row blocks that meet it, in block order ----
-  if (has) {
-    const int npc = SW / P;
-    const int prbase = y0 / P;
-    const int npr = y1 / P - prbase + 1;
-    const int pc0 = xs / P;
-    for (int idx = j * 64 + lane; idx < npr * npc; idx += K * 64) {
-      const int prl = idx / npc, q = idx - prl * npc;
-      const int pc = pc0 + q;
-      const int pr = prbase + prl;
-      const int ua = max(pr * P, y0) - y0 + 1, ub = min(pr * P + P - 1, y1) - y0 + 1;
-      float v = 0.f;
-      for (int kk = ua >> 5; kk <= ub >> 5; ++kk) {
-        const int pf_blk = (y0 - 1 + max(kk * 32, 1)) / P;
-        v += part[(kk * kEdtPartRows + (pr - pf_blk)) * 8 + q];
-      }
-      if (pc < gw) srow[pr * gw + pc] = v;
-    }
-  }
+  if (has) strip_patch_sums(part, srow, lane, j, K, P, SW, xs, y0, y1, gw);
   __syncthreads();
 }
 
@@ -637,22 +652,215 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
-// Resident workgroups per CU of each variant, computed once (outside any
-// stream capture).
-// Resident workgroups per CU of each variant (EDT, EDT writing e, AREA),
-// computed once (outside any stream capture).
+// ---------------------------------------------------------------------------
+// Direct column search (layout 2).  With g tabulated per (row, column) in LDS,
+// the column pass e(u) = min_v (u - v)^2 + g(v)^2 is searched outward from u:
+// distance d is visited while d^2 is below the best value so far, so a pixel
+// costs about its own distance in steps, and no row or column waits on
+// another (no envelope, no band merges).  Rows 0 and n-1 of an item are
+// padding (g = 0): a search that reaches one of them ends there, so an active
+// search never leaves the item; visiting two distances per step reads at
+// most one row past it (a guard row or a neighbouring slot's row), whose
+// value can no longer win.  The sums of sqrt(e) are formed as by the
+// envelope walk (per 32-row block and patch row, rows in order, the same lane
+// tree), so both layouts give the same bits.
+//
+// Packets: an item of class c <= 4 has 2^c blocks of 32 rows and 16 >> c
+// items share a 16-wavefront workgroup, one wavefront per block.  A class-5
+// item (up to 1152 rows) takes a workgroup alone; wavefront j does blocks
+// j, j + 16, j + 32.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int direct_items(int c) { return c == 5 ? 1 : (kEdtWaves >> c); }
+constexpr int kDirRows = 8;   // rows searched together
+constexpr int kDirSteps = 2;  // distances per search step
+// A group's search reads at most kDirRows + kDirSteps - 2 rows past its item
+// on either side (a row that is done keeps being updated while another row of
+// its group searches; the step visits kDirSteps distances): guard rows.
+constexpr int kDirGuard = 12;
+static_assert(kDirGuard >= kDirRows + kDirSteps - 2, "guard rows");
+
+// class of packet p over the classes with a nonzero count (tallest first) and
+// the item word of wavefront kb's slot in it (-1: none)
+__device__ __forceinline__ int direct_slot(const int* cnt, const int32_t* items, int item_cap, int p, int kb, int& word) {
+  word = -1;
+#pragma unroll
+  for (int c = kClasses - 1; c >= 0; --c) {
+    const int ipp = direct_items(c);
+    const int np = (cnt[c] + ipp - 1) / ipp;
+    if (p < np) {
+      const int k = p * ipp + (c == 5 ? 0 : (kb >> c));
+      if (k < cnt[c]) word = items[(int64_t)c * item_cap + k];
+      return c;
+    }
+    p -= np;
+  }
+  return -1;
+}
+
+template <int SPATIAL, bool WE>
+__device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, uint16_t* gt_all, float* part_all, int lane,
+                                              int kb, int32_t* e_out) {
+  const int rows_c = class_rows(cls);
+  const int K = cls == 5 ? kEdtWaves : rows_c / 32;  // wavefronts per item
+  const int slot = kb / K, j = kb - slot * K;
+  const bool has = word >= 0;
+  const int strip = has ? (word & ((1 << kItemStripBits) - 1)) : 0;
+  auto fld = [&](int q) { return (int)__builtin_amdgcn_readlane(pf, q); };
+  const uint64_t* mb = reinterpret_cast<const uint64_t*>(((uint64_t)(uint32_t)fld(1) << 32) | (uint32_t)fld(0));
+  float* srow = reinterpret_cast<float*>(((uint64_t)(uint32_t)fld(3) << 32) | (uint32_t)fld(2));
+  const int y0 = fld(4), y1 = fld(5), x0 = fld(6), x1 = fld(7);
+  const int n = has ? fld(8) : 0;
+  const int P = has ? fld(9) : kMinPatch;
+  const int gw = fld(10), wq = fld(11), fw = fld(12), fh = fld(13), xs0 = fld(14), gidx = fld(15);
+  const int SW = strip_width(P);
+  const int xs = xs0 + strip * SW;
+  const bool lane_ok = lane < SW;
+  const int col = xs + lane;
+  uint16_t* gt = gt_all + slot * rows_c * 64;  // row u, column lane at gt[u * 64 + lane]
+  float* part = part_all + (slot * rows_c / 32) * kEdtPartRows * 8;
+
+  // ---- g table: per block, lane l < 32 builds row b0 + l's record; every
+  // row's record is then broadcast and decoded by all lanes.  Every row of
+  // the slot is written (0 past the item), so the one row a search may read
+  // past its item holds a real g (<= 8448), never a stale value. ----
+  for (int b0 = j * 32; b0 < rows_c; b0 += K * 32) {
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);  // padding row: no runs
+    const int u = b0 + lane;
+    if (lane < 32 && u > 0 && u < n - 1) {
+      const uint64_t* row = mb + (int64_t)(y0 - 1 + u) * wq;
+      const uint64_t win = load_window(row, xs, wq, fw);
+      const int L = (win & 1ull) ? run_left(row, xs - 1, wq, fw) : 0;
+      const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw) : 0;
+      r = make_rowrec(win, L, R);
+    }
+    for (int k = 0; k < 32; ++k) {
+      const uint4 ru = make_uint4(__builtin_amdgcn_readlane(r.x, k), __builtin_amdgcn_readlane(r.y, k),
+                                  __builtin_amdgcn_readlane(r.z, k), __builtin_amdgcn_readlane(r.w, k));
+      gt[(b0 + k) * 64 + lane] = (uint16_t)(lane_ok ? g_rec(ru, lane) : 0);
+    }
+  }
+  __syncthreads();
+
+  // ---- e of each row of the wavefront's blocks, sqrt(e) summed per patch.
+  // Rows are searched kDirRows at a time, kDirSteps distances per step: the
+  // group's candidates at distances d .. d + kDirSteps - 1 come from
+  // kDirRows + kDirSteps - 1 consecutive table rows on each side, and a step
+  // runs while any row of the group can still improve (rows that are done
+  // are updated with candidates that cannot win).  Each group's rows are then
+  // added in row order. ----
+  for (int b0 = j * 32; b0 < n; b0 += K * 32) {
+    const int blk = b0 >> 5;
+    const int ua = max(b0, 1), ub = min(b0 + 32, n - 1);
+    if (ua >= ub) continue;
+    int pr = (y0 - 1 + ua) / P;             // patch row of row u
+    int pr_next = (pr + 1) * P - (y0 - 1);  // first row of the next patch row
+    float acc = 0.f;
+#pragma unroll
+    for (int gi = 0; gi < 32; gi += kDirRows) {
+      if (b0 + gi >= ub) break;
+      const uint16_t* base = gt + (b0 + gi) * 64 + lane;  // row u0 = b0 + gi
+      int best[kDirRows];
+      int bmax = 0;
+#pragma unroll
+      for (int k = 0; k < kDirRows; ++k) {
+        const int g = base[k * 64];
+        best[k] = SPATIAL == 0 ? g * g : (g > 0 ? 1 : 0);
+        bmax = max(bmax, best[k]);
+      }
+      if (SPATIAL == 0) {
+        for (int d = 1; d * d < bmax; d += kDirSteps) {
+          // window rows: up u0 - d - (kDirSteps - 1) + t, down u0 + d + t
+          constexpr int NWIN = kDirRows + kDirSteps - 1;
+          const uint16_t* pu = base - (d + kDirSteps - 1) * 64;
+          const uint16_t* pd = base + d * 64;
+          int su[NWIN], sd[NWIN];
+#pragma unroll
+          for (int t = 0; t < NWIN; ++t) {
+            const int x = pu[t * 64], y = pd[t * 64];
+            su[t] = x * x;
+            sd[t] = y * y;
+          }
+          bmax = 0;
+#pragma unroll
+          for (int k = 0; k < kDirRows; ++k) {
+#pragma unroll
+            for (int i = 0; i < kDirSteps; ++i)  // row u0 + k at distance d + i
+              best[k] = min(best[k], (d + i) * (d + i) + min(su[k - i + kDirSteps - 1], sd[k + i]));
+            bmax = max(bmax, best[k]);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kDirRows; ++k) {
+        const int u = b0 + gi + k;
+        if (u < ua || u >= ub) continue;
+        if (u == pr_next) {
+          flush_patch_part(part, lane, lane_ok, P, y0, blk, pr, acc);
+          acc = 0.f;
+          ++pr;
+          pr_next += P;
+        }
+        const int e = best[k];
+        acc += SPATIAL == 0 ? __builtin_amdgcn_sqrtf((float)e) : (float)e;  // e >= 0 integer: no denormals
+        if (WE && lane_ok && col >= x0 && col <= x1)
+          e_out[(int64_t)gidx * fh * fw + (int64_t)(y0 - 1 + u) * fw + col] = e;
+      }
+    }
+    flush_patch_part(part, lane, lane_ok, P, y0, blk, pr, acc);
+  }
+  __syncthreads();
+  if (has) strip_patch_sums(part, srow, lane, j, K, P, SW, xs, y0, y1, gw);
+  __syncthreads();
+}
+
+// ROWS: table rows of one workgroup (512: classes 0-4, 1152: class 5)
+template <int SPATIAL, bool WE, int ROWS>
+__global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(ROWS > 512 ? 4 : 8))) void k_edt_direct(const int32_t* __restrict__ counts,
+                                                               const int32_t* __restrict__ items, int item_cap,
+                                                               const MaskRec* __restrict__ mrec, int32_t* e_out) {
+  __shared__ __attribute__((aligned(16))) uint16_t gt_all[(ROWS + 2 * kDirGuard) * 64];  // zero guard rows at each end
+  __shared__ float part_all[kEdtBlocks * kEdtPartRows * 8];
+  const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int i = threadIdx.x; i < (ROWS + 2 * kDirGuard) * 64 / 2; i += kEdtWaves * 64) reinterpret_cast<uint32_t*>(gt_all)[i] = 0u;
+  __syncthreads();
+  int cnt[kClasses];
+  int total = 0;
+#pragma unroll
+  for (int c = 0; c < kClasses; ++c) {
+    cnt[c] = (ROWS > 512) == (c == 5) ? min(counts[c], item_cap) : 0;
+    total += (cnt[c] + direct_items(c) - 1) / direct_items(c);
+  }
+  for (int p = blockIdx.x; p < total; p += gridDim.x) {
+    int word;
+    const int cls = direct_slot(cnt, items, item_cap, p, kb, word);
+    uint32_t pf = 0u;  // the item's record: lane q < 16 holds dword q
+    if (word >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(mrec + (word >> kItemStripBits))[lane];
+    direct_packet<SPATIAL, WE>(cls, pf, word, gt_all + kDirGuard * 64, part_all, lane, kb, e_out);
+  }
+}
+
+// Resident workgroups per CU of each kernel variant, computed once (outside
+// any stream capture): envelope EDT and AREA (layouts 0 and 1), then the
+// direct search for (EDT, EDT writing e, AREA) x (classes 0-4, class 5).
 static std::once_flag g_edt_once;
-static int g_edt_per_cu[3];
+static int g_edt_per_cu[8];
 
 static const void* edt_variant(int v) {
-  return v == 0 ? reinterpret_cast<const void*>(&k_edt<0, false>)
-                : v == 1 ? reinterpret_cast<const void*>(&k_edt<0, true>)
-                         : reinterpret_cast<const void*>(&k_edt<1, false>);
+  switch (v) {
+    case 0: return reinterpret_cast<const void*>(&k_edt<0, false>);
+    case 1: return reinterpret_cast<const void*>(&k_edt<1, false>);
+    case 2: return reinterpret_cast<const void*>(&k_edt_direct<0, false, 512>);
+    case 3: return reinterpret_cast<const void*>(&k_edt_direct<0, true, 512>);
+    case 4: return reinterpret_cast<const void*>(&k_edt_direct<1, false, 512>);
+    case 5: return reinterpret_cast<const void*>(&k_edt_direct<0, false, kMaxRows>);
+    case 6: return reinterpret_cast<const void*>(&k_edt_direct<0, true, kMaxRows>);
+    default: return reinterpret_cast<const void*>(&k_edt_direct<1, false, kMaxRows>);
+  }
 }
 
 void edt_prepare() {
   std::call_once(g_edt_once, [] {
-    for (int v = 0; v < 3; ++v) {
+    for (int v = 0; v < 8; ++v) {
       int per_cu = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, edt_variant(v), kEdtWaves * 64, 0) != hipSuccess ||
           per_cu < 1)
@@ -662,19 +870,37 @@ void edt_prepare() {
   });
 }
 
-// e_out (squared distances of the bounding boxes) is written by the EDT
-// variant only; the AREA variant never produces distances.
+// Layout -1 (default) and 2 run the direct search; 0 and 1 the envelope
+// kernel in that band layout.  e_out (squared distances of the bounding
+// boxes) is written by the direct search only (callers that pass it use the
+// default layout); the AREA variants never produce distances.
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode) {
   edt_prepare();
-  const int v = b.spatial != 0 ? 2 : (e_out ? 1 : 0);
-  const int grid = num_cus * g_edt_per_cu[v];
   const dim3 blk(kEdtWaves * 64);
-  if (v == 0)
-    hipLaunchKernelGGL((k_edt<0, false>), dim3(grid), blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, mode);
-  else if (v == 1)
-    hipLaunchKernelGGL((k_edt<0, true>), dim3(grid), blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, mode);
-  else
-    hipLaunchKernelGGL((k_edt<1, false>), dim3(grid), blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, nullptr, mode);
+  if (mode == 0 || mode == 1) {
+    const int v = b.spatial != 0 ? 1 : 0;
+    const dim3 grid(num_cus * g_edt_per_cu[v]);
+    if (v == 0)
+      hipLaunchKernelGGL((k_edt<0, false>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, nullptr, mode);
+    else
+      hipLaunchKernelGGL((k_edt<1, false>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, nullptr, mode);
+    return;
+  }
+  const int kind = b.spatial != 0 ? 2 : (e_out ? 1 : 0);
+  auto go = [&](int dv) {
+    const dim3 grid(num_cus * g_edt_per_cu[dv]);
+    switch (dv) {
+      case 2: hipLaunchKernelGGL((k_edt_direct<0, false, 512>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
+      case 3: hipLaunchKernelGGL((k_edt_direct<0, true, 512>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
+      case 4: hipLaunchKernelGGL((k_edt_direct<1, false, 512>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
+      case 5: hipLaunchKernelGGL((k_edt_direct<0, false, kMaxRows>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
+      case 6: hipLaunchKernelGGL((k_edt_direct<0, true, kMaxRows>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
+      default: hipLaunchKernelGGL((k_edt_direct<1, false, kMaxRows>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
+    }
+  };
+  // items taller than 512 rows (class 5) first, when the batch can have any
+  if (b.max_rows > 512) go(5 + kind);
+  go(2 + kind);
 }
 
 }  // namespace disc

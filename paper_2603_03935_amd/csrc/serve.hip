@@ -68,6 +68,7 @@ Shape capacity_shape(const disc_server_config& c, int E, int gemm_bf16) {
   s.tkp_elems = (int64_t)c.max_frames * round_up(G, 8) * c.c;
   s.tkp_esize = 2;
   s.want_dbar = true;  // any request may ask for the mean distinctiveness
+  s.max_rows = c.max_h + 2;
   choose_splits(s);
   return s;
 }

@@ -98,7 +98,7 @@ def test_null_arguments(lib):
     opts.spatial = 3
     assert call(lib, t, m, p, o, opts) == 1
     lib.disc_options_default(ctypes.byref(opts))
-    opts.edt_layout = 2
+    opts.edt_layout = 3
     assert call(lib, t, m, p, o, opts) == 1
     lib.disc_options_default(ctypes.byref(opts))
     opts.pool_tile = 3

@@ -85,8 +85,9 @@ def test_edt_large_masks_1080p(gpu):
 @pytest.mark.parametrize("name,h,w,P", [("cfg2", 480, 640, 16), ("adv", 511, 200, 14), ("adv", 300, 130, 16),
                                         ("adv", 100, 90, 8), ("adv", 40, 333, 64)])
 def test_edt_layouts_agree_bitwise(gpu, name, h, w, P):
-    """Short-band and long-band layouts of the distance transform give the same
-    patch weights bit for bit (and match the oracle), across every class."""
+    """Short-band, long-band and direct-search layouts of the distance
+    transform give the same patch weights bit for bit (and match the oracle),
+    across every class."""
     if name == "cfg2":
         bits = di.workload("cfg2").frames[0].bits
     else:
@@ -94,7 +95,9 @@ def test_edt_layouts_agree_bitwise(gpu, name, h, w, P):
     b = dev_bits(bits)
     w0 = gpu.patch_weights(b, h, w, P, distinct=0, edt_layout=0).cpu().numpy()
     w1 = gpu.patch_weights(b, h, w, P, distinct=0, edt_layout=1).cpu().numpy()
+    w2 = gpu.patch_weights(b, h, w, P, distinct=0, edt_layout=2).cpu().numpy()
     assert np.array_equal(w0, w1), "band layouts disagree"
+    assert np.array_equal(w0, w2), "direct search disagrees with the band layouts"
     s = oracle.spatial_weights(bits, w, P, 0)
     err = np.abs(w1.astype(np.float64) - s).max() / max(np.abs(s).max(), 1e-30)
     assert err < REL_S, err
