@@ -671,13 +671,14 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
 // j, j + 16, j + 32.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int direct_items(int c) { return c == 5 ? 1 : (kEdtWaves >> c); }
-constexpr int kDirRows = 8;   // rows searched together
-constexpr int kDirSteps = 2;  // distances per search step
+constexpr int kDirRows = 4;   // rows searched together
+constexpr int kDirSteps = 4;  // distances per search step (windows start on 4-row words)
 // A group's search reads at most kDirRows + kDirSteps - 2 rows past its item
 // on either side (a row that is done keeps being updated while another row of
 // its group searches; the step visits kDirSteps distances): guard rows.
 constexpr int kDirGuard = 12;
-static_assert(kDirGuard >= kDirRows + kDirSteps - 2, "guard rows");
+static_assert(kDirGuard >= kDirRows + kDirSteps - 2 && kDirGuard % 4 == 0, "guard rows");
+static_assert(kDirRows % 4 == 0 && kDirSteps == 4, "the search windows are read as whole 4-row words");
 
 // class of packet p over the classes with a nonzero count (tallest first) and
 // the item word of wavefront kb's slot in it (-1: none)
@@ -698,7 +699,7 @@ __device__ __forceinline__ int direct_slot(const int* cnt, const int32_t* items,
 }
 
 template <int SPATIAL, bool WE>
-__device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, uint16_t* gt_all, float* part_all, int lane,
+__device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, uint2* gt_all, float* part_all, int lane,
                                               int kb, int32_t* e_out) {
   const int rows_c = class_rows(cls);
   const int K = cls == 5 ? kEdtWaves : rows_c / 32;  // wavefronts per item
@@ -716,7 +717,7 @@ __device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, ui
   const int xs = xs0 + strip * SW;
   const bool lane_ok = lane < SW;
   const int col = xs + lane;
-  uint16_t* gt = gt_all + slot * rows_c * 64;  // row u, column lane at gt[u * 64 + lane]
+  uint2* gt = gt_all + (slot * rows_c / 4) * 64;  // rows 4q .. 4q + 3 of column lane: 16 bits each in gt[q * 64 + lane]
   float* part = part_all + (slot * rows_c / 32) * kEdtPartRows * 8;
 
   // ---- g table: per block, lane l < 32 builds row b0 + l's record; every
@@ -733,10 +734,16 @@ __device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, ui
       const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw) : 0;
       r = make_rowrec(win, L, R);
     }
-    for (int k = 0; k < 32; ++k) {
-      const uint4 ru = make_uint4(__builtin_amdgcn_readlane(r.x, k), __builtin_amdgcn_readlane(r.y, k),
-                                  __builtin_amdgcn_readlane(r.z, k), __builtin_amdgcn_readlane(r.w, k));
-      gt[(b0 + k) * 64 + lane] = (uint16_t)(lane_ok ? g_rec(ru, lane) : 0);
+    for (int k4 = 0; k4 < 32; k4 += 4) {
+      uint32_t h[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint4 ru =
+            make_uint4(__builtin_amdgcn_readlane(r.x, k4 + k), __builtin_amdgcn_readlane(r.y, k4 + k),
+                       __builtin_amdgcn_readlane(r.z, k4 + k), __builtin_amdgcn_readlane(r.w, k4 + k));
+        h[k] = lane_ok ? (uint32_t)g_rec(ru, lane) : 0u;
+      }
+      gt[((b0 + k4) >> 2) * 64 + lane] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
     }
   }
   __syncthreads();
@@ -758,34 +765,47 @@ __device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, ui
 #pragma unroll
     for (int gi = 0; gi < 32; gi += kDirRows) {
       if (b0 + gi >= ub) break;
-      const uint16_t* base = gt + (b0 + gi) * 64 + lane;  // row u0 = b0 + gi
+      const uint2* base = gt + ((b0 + gi) >> 2) * 64 + lane;  // quad of row u0 = b0 + gi
       int best[kDirRows];
       int bmax = 0;
 #pragma unroll
-      for (int k = 0; k < kDirRows; ++k) {
-        const int g = base[k * 64];
-        best[k] = SPATIAL == 0 ? g * g : (g > 0 ? 1 : 0);
-        bmax = max(bmax, best[k]);
+      for (int q = 0; q < kDirRows / 4; ++q) {
+        const uint2 w = base[q * 64];
+        const int g4[4] = {(int)(w.x & 0xFFFFu), (int)(w.x >> 16), (int)(w.y & 0xFFFFu), (int)(w.y >> 16)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          best[4 * q + k] = SPATIAL == 0 ? g4[k] * g4[k] : (g4[k] > 0 ? 1 : 0);
+          bmax = max(bmax, best[4 * q + k]);
+        }
       }
       if (SPATIAL == 0) {
+        // d = 1 (mod 4): the windows start on quads, up at u0 - d - 3, down
+        // at u0 + d - 1 (one row early)
         for (int d = 1; d * d < bmax; d += kDirSteps) {
-          // window rows: up u0 - d - (kDirSteps - 1) + t, down u0 + d + t
-          constexpr int NWIN = kDirRows + kDirSteps - 1;
-          const uint16_t* pu = base - (d + kDirSteps - 1) * 64;
-          const uint16_t* pd = base + d * 64;
-          int su[NWIN], sd[NWIN];
+          constexpr int NQ = (kDirRows + kDirSteps) / 4;  // quads per window
+          const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * 64;
+          const uint2* pd = base + ((d - 1) >> 2) * 64;
+          int su[4 * NQ], sd[4 * NQ];
 #pragma unroll
-          for (int t = 0; t < NWIN; ++t) {
-            const int x = pu[t * 64], y = pd[t * 64];
-            su[t] = x * x;
-            sd[t] = y * y;
+          for (int q = 0; q < NQ; ++q) {
+            const uint2 x = pu[q * 64], y = pd[q * 64];
+            const int xa = (int)(x.x & 0xFFFFu), xb = (int)(x.x >> 16), xc = (int)(x.y & 0xFFFFu), xd = (int)(x.y >> 16);
+            const int ya = (int)(y.x & 0xFFFFu), yb = (int)(y.x >> 16), yc = (int)(y.y & 0xFFFFu), yd = (int)(y.y >> 16);
+            su[4 * q] = xa * xa;
+            su[4 * q + 1] = xb * xb;
+            su[4 * q + 2] = xc * xc;
+            su[4 * q + 3] = xd * xd;
+            sd[4 * q] = ya * ya;
+            sd[4 * q + 1] = yb * yb;
+            sd[4 * q + 2] = yc * yc;
+            sd[4 * q + 3] = yd * yd;
           }
           bmax = 0;
 #pragma unroll
           for (int k = 0; k < kDirRows; ++k) {
 #pragma unroll
-            for (int i = 0; i < kDirSteps; ++i)  // row u0 + k at distance d + i
-              best[k] = min(best[k], (d + i) * (d + i) + min(su[k - i + kDirSteps - 1], sd[k + i]));
+            for (int i = 0; i < kDirSteps; ++i)  // row u0 + k at distance d + i: up row index k - i + 3, down k + i + 1
+              best[k] = min(best[k], (d + i) * (d + i) + min(su[k - i + kDirSteps - 1], sd[k + i + 1]));
             bmax = max(bmax, best[k]);
           }
         }
@@ -818,10 +838,10 @@ template <int SPATIAL, bool WE, int ROWS>
 __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(ROWS > 512 ? 4 : 8))) void k_edt_direct(const int32_t* __restrict__ counts,
                                                                const int32_t* __restrict__ items, int item_cap,
                                                                const MaskRec* __restrict__ mrec, int32_t* e_out) {
-  __shared__ __attribute__((aligned(16))) uint16_t gt_all[(ROWS + 2 * kDirGuard) * 64];  // zero guard rows at each end
+  __shared__ uint2 gt_all[(ROWS + 2 * kDirGuard) / 4 * 64];  // g table, 4 rows per word; zero guard rows at each end
   __shared__ float part_all[kEdtBlocks * kEdtPartRows * 8];
   const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int i = threadIdx.x; i < (ROWS + 2 * kDirGuard) * 64 / 2; i += kEdtWaves * 64) reinterpret_cast<uint32_t*>(gt_all)[i] = 0u;
+  for (int i = threadIdx.x; i < (ROWS + 2 * kDirGuard) / 4 * 64; i += kEdtWaves * 64) gt_all[i] = make_uint2(0u, 0u);
   __syncthreads();
   int cnt[kClasses];
   int total = 0;
@@ -835,7 +855,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const int cls = direct_slot(cnt, items, item_cap, p, kb, word);
     uint32_t pf = 0u;  // the item's record: lane q < 16 holds dword q
     if (word >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(mrec + (word >> kItemStripBits))[lane];
-    direct_packet<SPATIAL, WE>(cls, pf, word, gt_all + kDirGuard * 64, part_all, lane, kb, e_out);
+    direct_packet<SPATIAL, WE>(cls, pf, word, gt_all + kDirGuard / 4 * 64, part_all, lane, kb, e_out);
   }
 }
 
