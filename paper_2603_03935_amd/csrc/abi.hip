@@ -170,6 +170,7 @@ Layout make_layout(const Shape& s) {
   L.ppart = take(s.pool_split > 1 ? 4 * (size_t)s.n_tiles * s.kgroups * 64 * 64 : 0);
   L.qpart = take(s.proj_split > 1 ? 4 * (size_t)((s.C + kProjKG - 1) / kProjKG) * s.M * s.E : 0);
   L.ppack = take(s.gemm_bf16 ? 2 * (size_t)s.C * s.E : 0);
+  L.edt_part = take(4 * (size_t)kDirSplitPackets * kDirPartFloats);
   L.tkp = take(s.gemm_bf16 ? (size_t)s.tkp_elems * s.tkp_esize : 0);
   L.total = off;
   return L;
@@ -285,6 +286,7 @@ Work work_ptrs(char* base, const Layout& L) {
   w.ppart = reinterpret_cast<float*>(base + L.ppart);
   w.qpart = reinterpret_cast<float*>(base + L.qpart);
   w.ppack = base + L.ppack;
+  w.edt_part = reinterpret_cast<float*>(base + L.edt_part);
   w.tkp = base + L.tkp;
   return w;
 }

@@ -50,13 +50,20 @@ __host__ __device__ inline int strip_width(int patch) { return 64 - (64 % patch)
 
 // LDS of one EDT workgroup (every class fits kMaxRows rows): a 16-byte record
 // per row, the per-column stack bitmaps (one bit per row) and the partial
-// patch sums of every 32-row block of the items' rows (a block meets at most
-// 6 patch rows of at least 8 pixels).  Patch sums are always formed per
-// 32-row block, whatever the band height, so the order of the additions (and
-// the result) depends only on the mask.
+// patch sums of every 16-row block of the items' rows (a block meets at most
+// 3 patch rows of at least 8 pixels).  Patch sums are always formed per
+// 16-row block, whatever the layout or band height, so the order of the
+// additions (and the result) depends only on the mask.
+constexpr int kBlkRows = 16;
 constexpr int kEdtBmWords = kMaxRows / 32 + 1;
-constexpr int kEdtBlocks = kMaxRows / 32;
-constexpr int kEdtPartRows = 6;
+constexpr int kEdtBlocks = kMaxRows / kBlkRows;
+constexpr int kEdtPartRows = 3;
+// Direct search: a packet of at most 512 rows may be shared by up to
+// kDirSplitMax workgroups when the batch has few packets; their block partial
+// sums go to a global buffer of kDirSplitPackets packets.
+constexpr int kDirSplitMax = 4;
+constexpr int kDirSplitPackets = 512;
+constexpr int kDirPartFloats = 512 / kBlkRows * kEdtPartRows * 8;  // per packet
 
 // Per-mask record of the distance transform (written by the mask scan).
 struct MaskRec {
@@ -127,6 +134,7 @@ struct Work {
   void* X;             // [M][C] pooled features in the GEMM dtype
   float* ppart;        // pooling group sums [tile][kgroups][64*64] (split K only)
   float* qpart;        // projection group sums [C/256][M][E] (split K only)
+  float* edt_part;     // direct EDT block partial sums of shared packets [kDirSplitPackets][kDirPartFloats]
   void* ppack;         // k-packed BF16 copy of P [C/8][E][8] (BF16 GEMMs)
   void* tkp;           // k-packed tokens [sum ceil(G/8)][C][8], BF16 bits (FP8 tokens: their code values)
 };

@@ -323,7 +323,7 @@ __device__ void merge_junction(const uint4* rec, uint32_t* bm, int lane, bool la
   if (ldirty) bm[lwi * 64 + lane] = lwd;
 }
 
-// Partial patch sums of one 32-row block: the per-lane sums v of the block's
+// Partial patch sums of one 16-row block: the per-lane sums v of the block's
 // rows in patch row pr are added across the P lanes of each patch (a fixed
 // tree) and stored at (block, patch row within the block, patch column).
 __device__ __forceinline__ void flush_patch_part(float* part, int lane, bool lane_ok, int P, int y0, int blk, int pr,
@@ -334,11 +334,11 @@ __device__ __forceinline__ void flush_patch_part(float* part, int lane, bool lan
     const float t = __shfl_down(v, o);
     if (inseg + o < P && lane + o < 64) v += t;
   }
-  const int pf_blk = (y0 - 1 + max(blk * 32, 1)) / P;  // first patch row the block meets
+  const int pf_blk = (y0 - 1 + max(blk * kBlkRows, 1)) / P;  // first patch row the block meets
   if (inseg == 0 && lane_ok) part[(blk * kEdtPartRows + (pr - pf_blk)) * 8 + lane / P] = v;
 }
 
-// The strip's patch sums: each patch row adds the partial sums of the 32-row
+// The strip's patch sums: each patch row adds the partial sums of the 16-row
 // blocks that meet it, in block order.  Wavefront j of the K that share the
 // item takes every K-th patch.
 __device__ __forceinline__ void strip_patch_sums(const float* part, float* srow, int lane, int j, int K, int P, int SW,
@@ -353,8 +353,8 @@ __device__ __forceinline__ void strip_patch_sums(const float* part, float* srow,
     const int pr = prbase + prl;
     const int ua = max(pr * P, y0) - y0 + 1, ub = min(pr * P + P - 1, y1) - y0 + 1;
     float v = 0.f;
-    for (int kk = ua >> 5; kk <= ub >> 5; ++kk) {
-      const int pf_blk = (y0 - 1 + max(kk * 32, 1)) / P;
+    for (int kk = ua / kBlkRows; kk <= ub / kBlkRows; ++kk) {
+      const int pf_blk = (y0 - 1 + max(kk * kBlkRows, 1)) / P;
       v += part[(kk * kEdtPartRows + (pr - pf_blk)) * 8 + q];
     }
     if (pc < gw) srow[pr * gw + pc] = v;
@@ -409,7 +409,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   // this item's rows and bitmap words in LDS (rows_c is a multiple of 32)
   uint4* rec = rec_all + slot * rows_c;
   uint32_t* bm = bm_all + (slot * rows_c / 32) * 64;
-  float* part = part_all + (slot * rows_c / 32) * kEdtPartRows * 8;  // this item's blocks
+  float* part = part_all + (slot * rows_c / kBlkRows) * kEdtPartRows * 8;  // this item's blocks
 
   const int b0 = j * B, b1 = min(b0 + B, n);
 
@@ -543,11 +543,11 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
   };
   auto flush = [&](int blk, int pr, float v) { flush_patch_part(part, lane, lane_ok, P, y0, blk, pr, v); };
   // rows 0 and n-1 are padding and produce nothing: walk rows [ua, ub) in
-  // segments that end where a patch row or a 32-row block ends (flush points)
+  // segments that end where a patch row or a 16-row block ends (flush points)
   const int ua = max(b0, 1), ub = min(b1, n - 1);
   int pr = (y0 - 1 + ua) / P;               // patch row of row u
   int pr_next = (pr + 1) * P - (y0 - 1);    // first row of the next patch row
-  int blk = ua >> 5, blk_next = (blk + 1) * 32;
+  int blk = ua / kBlkRows, blk_next = (blk + 1) * kBlkRows;
   // site nx takes over from c at row u iff Fn - Fc <= (nx - c)(2u - c - nx);
   // without a next site the test is made false (dF = 2^30, dc = 0)
   int dF = nx >= 0 ? Fn - Fc : (1 << 30), dc = nx >= 0 ? nx - c : 0, sc = nx + c;
@@ -583,7 +583,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
       }
       if (u == blk_next) {
         ++blk;
-        blk_next += 32;
+        blk_next += kBlkRows;
       }
     }
   }
@@ -653,88 +653,152 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
 }
 
 // ---------------------------------------------------------------------------
-// Direct column search (layout 2).  With g tabulated per (row, column) in LDS,
-// the column pass e(u) = min_v (u - v)^2 + g(v)^2 is searched outward from u:
-// distance d is visited while d^2 is below the best value so far, so a pixel
-// costs about its own distance in steps, and no row or column waits on
-// another (no envelope, no band merges).  Rows 0 and n-1 of an item are
-// padding (g = 0): a search that reaches one of them ends there, so an active
-// search never leaves the item; visiting two distances per step reads at
-// most one row past it (a guard row or a neighbouring slot's row), whose
-// value can no longer win.  The sums of sqrt(e) are formed as by the
-// envelope walk (per 32-row block and patch row, rows in order, the same lane
-// tree), so both layouts give the same bits.
+// Direct column search (layouts -1 and 2).  With g tabulated per (row,
+// column) in LDS, the column pass e(u) = min_v (u - v)^2 + g(v)^2 is searched
+// outward from u: distance d is visited while d^2 is below the best value so
+// far, so a pixel costs about its own distance in steps, and no row or column
+// waits on another (no envelope, no band merges).  Rows 0 and n-1 of an item
+// are padding (g = 0): a search that reaches one of them ends there.  The
+// sums of sqrt(e) are formed as by the envelope walk (per 16-row block and
+// patch row, rows in order, the same lane tree), so all layouts give the same
+// bits.
 //
-// Packets: an item of class c <= 4 has 2^c blocks of 32 rows and 16 >> c
-// items share a 16-wavefront workgroup, one wavefront per block.  A class-5
-// item (up to 1152 rows) takes a workgroup alone; wavefront j does blocks
-// j, j + 16, j + 32.
+// Packets: class c <= 4 items (2^c x 32 rows) are packed 16 >> c to a packet
+// of 512 rows, a class-5 item (up to 1152 rows) is a packet alone.  A
+// workgroup tabulates g for the whole packet, then its 16 wavefronts take the
+// packet's 16-row blocks in a stride.  When the batch has few packets (at
+// most half the resident workgroups), up to kDirSplitMax workgroups share a
+// packet: each tabulates it and searches every S-th block, the block partial
+// sums go to global memory and k_edt_dsums adds them.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int direct_items(int c) { return c == 5 ? 1 : (kEdtWaves >> c); }
 constexpr int kDirRows = 4;   // rows searched together
 constexpr int kDirSteps = 4;  // distances per search step (windows start on 4-row words)
 // A group's search reads at most kDirRows + kDirSteps - 2 rows past its item
 // on either side (a row that is done keeps being updated while another row of
-// its group searches; the step visits kDirSteps distances): guard rows.
+// its group searches; a step visits kDirSteps distances): zeroed guard rows
+// at the ends of the table, real rows of the neighbouring slot elsewhere
+// (every slot row is written, 0 past its item, so every value read is a
+// g <= 8448 and the arithmetic cannot overflow; a candidate read past the
+// item can no longer win).
 constexpr int kDirGuard = 12;
 static_assert(kDirGuard >= kDirRows + kDirSteps - 2 && kDirGuard % 4 == 0, "guard rows");
-static_assert(kDirRows % 4 == 0 && kDirSteps == 4, "the search windows are read as whole 4-row words");
+static_assert(kDirRows % 4 == 0 && kDirSteps == 4 && kBlkRows % kDirRows == 0, "search windows are whole 4-row words");
 
-// class of packet p over the classes with a nonzero count (tallest first) and
-// the item word of wavefront kb's slot in it (-1: none)
-__device__ __forceinline__ int direct_slot(const int* cnt, const int32_t* items, int item_cap, int p, int kb, int& word) {
-  word = -1;
+// the packets of the classes in the kernel's range (tallest first)
+__device__ __forceinline__ int direct_count(const int32_t* counts, int item_cap, bool tall, int* cnt) {
+  int total = 0;
+#pragma unroll
+  for (int c = 0; c < kClasses; ++c) {
+    cnt[c] = tall == (c == 5) ? min(counts[c], item_cap) : 0;
+    total += (cnt[c] + direct_items(c) - 1) / direct_items(c);
+  }
+  return total;
+}
+// workgroups per packet (uniform over the launch)
+__device__ __forceinline__ int direct_split(bool tall, int total, int grid) {
+  return (!tall && total > 0 && 2 * total <= grid && total <= kDirSplitPackets) ? min(kDirSplitMax, grid / total) : 1;
+}
+// class of packet p, its first item index and the class's item count
+__device__ __forceinline__ int direct_packet_class(const int* cnt, int p, int& first, int& ccount) {
 #pragma unroll
   for (int c = kClasses - 1; c >= 0; --c) {
     const int ipp = direct_items(c);
     const int np = (cnt[c] + ipp - 1) / ipp;
     if (p < np) {
-      const int k = p * ipp + (c == 5 ? 0 : (kb >> c));
-      if (k < cnt[c]) word = items[(int64_t)c * item_cap + k];
+      first = p * ipp;
+      ccount = cnt[c];
       return c;
     }
     p -= np;
   }
   return -1;
 }
+// item words and mask records of packet p's slots into LDS (recs: 16 dwords per slot)
+__device__ __forceinline__ int direct_load_packet(const int* cnt, const int32_t* items, int item_cap,
+                                                  const MaskRec* mrec, int p, uint32_t* recs, int* words) {
+  int first = 0, ccount = 0;
+  const int cls = direct_packet_class(cnt, p, first, ccount);
+  const int ipp = direct_items(cls);
+  if ((int)threadIdx.x < ipp * 16) {
+    const int sl = threadIdx.x >> 4, q = threadIdx.x & 15;
+    const int k = first + sl;
+    const int word = k < ccount ? items[(int64_t)cls * item_cap + k] : -1;
+    if (q == 0) words[sl] = word;
+    recs[sl * 16 + q] = word >= 0 ? reinterpret_cast<const uint32_t*>(mrec + (word >> kItemStripBits))[q] : 0u;
+  }
+  __syncthreads();
+  return cls;
+}
+
+struct DirItem {
+  const uint64_t* mb;
+  float* srow;
+  int y0, y1, x0, x1, n, P, gw, wq, fw, fh, gidx, SW, xs;
+  bool has;
+};
+__device__ __forceinline__ DirItem direct_item(const uint32_t* recs, const int* words, int slot) {
+  auto fld = [&](int q) { return (int)__builtin_amdgcn_readfirstlane(recs[slot * 16 + q]); };
+  DirItem it;
+  const int word = __builtin_amdgcn_readfirstlane(words[slot]);
+  it.has = word >= 0;
+  it.mb = reinterpret_cast<const uint64_t*>(((uint64_t)(uint32_t)fld(1) << 32) | (uint32_t)fld(0));
+  it.srow = reinterpret_cast<float*>(((uint64_t)(uint32_t)fld(3) << 32) | (uint32_t)fld(2));
+  it.y0 = fld(4);
+  it.y1 = fld(5);
+  it.x0 = fld(6);
+  it.x1 = fld(7);
+  it.n = it.has ? fld(8) : 0;
+  it.P = it.has ? fld(9) : kMinPatch;
+  it.gw = fld(10);
+  it.wq = fld(11);
+  it.fw = fld(12);
+  it.fh = fld(13);
+  it.gidx = fld(15);
+  it.SW = strip_width(it.P);
+  it.xs = fld(14) + (it.has ? (word & ((1 << kItemStripBits) - 1)) : 0) * it.SW;
+  return it;
+}
+
+// The patch sums of packet slots from their block partial sums (part: the
+// packet's blocks, kEdtPartRows x 8 floats each): wavefront kb of the
+// 16 / ipp that share a slot.
+__device__ __forceinline__ void direct_strip_sums(int cls, const uint32_t* recs, const int* words, const float* part,
+                                                  int lane, int kb) {
+  const int ipp = direct_items(cls), rows_c = class_rows(cls);
+  const int K = kEdtWaves / ipp, slot = kb / K, j = kb - slot * K;
+  const DirItem it = direct_item(recs, words, slot);
+  if (it.has)
+    strip_patch_sums(part + (slot * rows_c / kBlkRows) * kEdtPartRows * 8, it.srow, lane, j, K, it.P, it.SW, it.xs,
+                     it.y0, it.y1, it.gw);
+}
 
 template <int SPATIAL, bool WE>
-__device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, uint2* gt_all, float* part_all, int lane,
-                                              int kb, int32_t* e_out) {
-  const int rows_c = class_rows(cls);
-  const int K = cls == 5 ? kEdtWaves : rows_c / 32;  // wavefronts per item
-  const int slot = kb / K, j = kb - slot * K;
-  const bool has = word >= 0;
-  const int strip = has ? (word & ((1 << kItemStripBits) - 1)) : 0;
-  auto fld = [&](int q) { return (int)__builtin_amdgcn_readlane(pf, q); };
-  const uint64_t* mb = reinterpret_cast<const uint64_t*>(((uint64_t)(uint32_t)fld(1) << 32) | (uint32_t)fld(0));
-  float* srow = reinterpret_cast<float*>(((uint64_t)(uint32_t)fld(3) << 32) | (uint32_t)fld(2));
-  const int y0 = fld(4), y1 = fld(5), x0 = fld(6), x1 = fld(7);
-  const int n = has ? fld(8) : 0;
-  const int P = has ? fld(9) : kMinPatch;
-  const int gw = fld(10), wq = fld(11), fw = fld(12), fh = fld(13), xs0 = fld(14), gidx = fld(15);
-  const int SW = strip_width(P);
-  const int xs = xs0 + strip * SW;
-  const bool lane_ok = lane < SW;
-  const int col = xs + lane;
-  uint2* gt = gt_all + (slot * rows_c / 4) * 64;  // rows 4q .. 4q + 3 of column lane: 16 bits each in gt[q * 64 + lane]
-  float* part = part_all + (slot * rows_c / 32) * kEdtPartRows * 8;
+__device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint32_t* recs, const int* words,
+                                              uint2* gt_all, float* part, int lane, int kb, int32_t* e_out) {
+  const int rows_c = class_rows(cls), ipp = direct_items(cls);
+  const int nbs = rows_c / kBlkRows;  // blocks per slot
+  const int nblk = ipp * nbs;         // blocks of the packet
 
-  // ---- g table: per block, lane l < 32 builds row b0 + l's record; every
-  // row's record is then broadcast and decoded by all lanes.  Every row of
-  // the slot is written (0 past the item), so the one row a search may read
-  // past its item holds a real g (<= 8448), never a stale value. ----
-  for (int b0 = j * 32; b0 < rows_c; b0 += K * 32) {
+  // ---- g table: every block of every slot (0 past the slot's item); lane l
+  // < 16 builds row l's record, then each row's record is broadcast and
+  // decoded by all lanes, four rows per 64-bit word ----
+  for (int b = kb; b < nblk; b += kEdtWaves) {
+    const int slot = b / nbs, r0 = (b - slot * nbs) * kBlkRows;
+    const DirItem it = direct_item(recs, words, slot);
+    const bool lane_ok = lane < it.SW;
     uint4 r = make_uint4(0u, 0u, 0u, 0u);  // padding row: no runs
-    const int u = b0 + lane;
-    if (lane < 32 && u > 0 && u < n - 1) {
-      const uint64_t* row = mb + (int64_t)(y0 - 1 + u) * wq;
-      const uint64_t win = load_window(row, xs, wq, fw);
-      const int L = (win & 1ull) ? run_left(row, xs - 1, wq, fw) : 0;
-      const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw) : 0;
+    const int u = r0 + lane;
+    if (lane < kBlkRows && u > 0 && u < it.n - 1) {
+      const uint64_t* row = it.mb + (int64_t)(it.y0 - 1 + u) * it.wq;
+      const uint64_t win = load_window(row, it.xs, it.wq, it.fw);
+      const int L = (win & 1ull) ? run_left(row, it.xs - 1, it.wq, it.fw) : 0;
+      const int R = (win >> 63) ? run_right(row, it.xs + 64, it.wq, it.fw) : 0;
       r = make_rowrec(win, L, R);
     }
-    for (int k4 = 0; k4 < 32; k4 += 4) {
+    uint2* gt = gt_all + ((slot * rows_c + r0) >> 2) * 64 + lane;
+#pragma unroll
+    for (int k4 = 0; k4 < kBlkRows; k4 += 4) {
       uint32_t h[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -743,29 +807,35 @@ __device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, ui
                        __builtin_amdgcn_readlane(r.z, k4 + k), __builtin_amdgcn_readlane(r.w, k4 + k));
         h[k] = lane_ok ? (uint32_t)g_rec(ru, lane) : 0u;
       }
-      gt[((b0 + k4) >> 2) * 64 + lane] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+      gt[(k4 >> 2) * 64] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
     }
   }
   __syncthreads();
 
-  // ---- e of each row of the wavefront's blocks, sqrt(e) summed per patch.
-  // Rows are searched kDirRows at a time, kDirSteps distances per step: the
-  // group's candidates at distances d .. d + kDirSteps - 1 come from
-  // kDirRows + kDirSteps - 1 consecutive table rows on each side, and a step
+  // ---- search: this workgroup's blocks (every S-th from s), one wavefront
+  // per block in a stride.  Rows are searched kDirRows at a time, kDirSteps
+  // distances per step: the group's candidates at distances d .. d +
+  // kDirSteps - 1 come from consecutive table rows on each side, and a step
   // runs while any row of the group can still improve (rows that are done
   // are updated with candidates that cannot win).  Each group's rows are then
   // added in row order. ----
-  for (int b0 = j * 32; b0 < n; b0 += K * 32) {
-    const int blk = b0 >> 5;
-    const int ua = max(b0, 1), ub = min(b0 + 32, n - 1);
+  for (int b = s + S * kb; b < nblk; b += S * kEdtWaves) {
+    const int slot = b / nbs, lb = b - slot * nbs, b0 = lb * kBlkRows;
+    const DirItem it = direct_item(recs, words, slot);
+    const int n = it.n, P = it.P, y0 = it.y0;
+    const int ua = max(b0, 1), ub = min(b0 + kBlkRows, n - 1);
     if (ua >= ub) continue;
+    const bool lane_ok = lane < it.SW;
+    const int col = it.xs + lane;
+    float* bpart = part + (slot * nbs) * kEdtPartRows * 8;  // the slot's blocks
     int pr = (y0 - 1 + ua) / P;             // patch row of row u
     int pr_next = (pr + 1) * P - (y0 - 1);  // first row of the next patch row
     float acc = 0.f;
+    const uint2* tb = gt_all + ((slot * rows_c + b0) >> 2) * 64 + lane;  // the block's first word
 #pragma unroll
-    for (int gi = 0; gi < 32; gi += kDirRows) {
+    for (int gi = 0; gi < kBlkRows; gi += kDirRows) {
       if (b0 + gi >= ub) break;
-      const uint2* base = gt + ((b0 + gi) >> 2) * 64 + lane;  // quad of row u0 = b0 + gi
+      const uint2* base = tb + (gi >> 2) * 64;  // row u0 = b0 + gi
       int best[kDirRows];
       int bmax = 0;
 #pragma unroll
@@ -779,10 +849,10 @@ __device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, ui
         }
       }
       if (SPATIAL == 0) {
-        // d = 1 (mod 4): the windows start on quads, up at u0 - d - 3, down
+        // d = 1 (mod 4): the windows start on words, up at u0 - d - 3, down
         // at u0 + d - 1 (one row early)
         for (int d = 1; d * d < bmax; d += kDirSteps) {
-          constexpr int NQ = (kDirRows + kDirSteps) / 4;  // quads per window
+          constexpr int NQ = (kDirRows + kDirSteps) / 4;  // words per window
           const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * 64;
           const uint2* pd = base + ((d - 1) >> 2) * 64;
           int su[4 * NQ], sd[4 * NQ];
@@ -804,7 +874,7 @@ __device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, ui
 #pragma unroll
           for (int k = 0; k < kDirRows; ++k) {
 #pragma unroll
-            for (int i = 0; i < kDirSteps; ++i)  // row u0 + k at distance d + i: up row index k - i + 3, down k + i + 1
+            for (int i = 0; i < kDirSteps; ++i)  // row u0 + k at distance d + i: up index k - i + 3, down k + i + 1
               best[k] = min(best[k], (d + i) * (d + i) + min(su[k - i + kDirSteps - 1], sd[k + i + 1]));
             bmax = max(bmax, best[k]);
           }
@@ -815,47 +885,64 @@ __device__ __forceinline__ void direct_packet(int cls, uint32_t pf, int word, ui
         const int u = b0 + gi + k;
         if (u < ua || u >= ub) continue;
         if (u == pr_next) {
-          flush_patch_part(part, lane, lane_ok, P, y0, blk, pr, acc);
+          flush_patch_part(bpart, lane, lane_ok, P, y0, lb, pr, acc);
           acc = 0.f;
           ++pr;
           pr_next += P;
         }
         const int e = best[k];
         acc += SPATIAL == 0 ? __builtin_amdgcn_sqrtf((float)e) : (float)e;  // e >= 0 integer: no denormals
-        if (WE && lane_ok && col >= x0 && col <= x1)
-          e_out[(int64_t)gidx * fh * fw + (int64_t)(y0 - 1 + u) * fw + col] = e;
+        if (WE && lane_ok && col >= it.x0 && col <= it.x1)
+          e_out[(int64_t)it.gidx * it.fh * it.fw + (int64_t)(y0 - 1 + u) * it.fw + col] = e;
       }
     }
-    flush_patch_part(part, lane, lane_ok, P, y0, blk, pr, acc);
+    flush_patch_part(bpart, lane, lane_ok, P, y0, lb, pr, acc);
   }
-  __syncthreads();
-  if (has) strip_patch_sums(part, srow, lane, j, K, P, SW, xs, y0, y1, gw);
   __syncthreads();
 }
 
 // ROWS: table rows of one workgroup (512: classes 0-4, 1152: class 5)
 template <int SPATIAL, bool WE, int ROWS>
-__global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(ROWS > 512 ? 4 : 8))) void k_edt_direct(const int32_t* __restrict__ counts,
-                                                               const int32_t* __restrict__ items, int item_cap,
-                                                               const MaskRec* __restrict__ mrec, int32_t* e_out) {
+__global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(ROWS > 512 ? 4 : 8))) void k_edt_direct(
+    const int32_t* __restrict__ counts, const int32_t* __restrict__ items, int item_cap,
+    const MaskRec* __restrict__ mrec, int32_t* e_out, float* gpart) {
   __shared__ uint2 gt_all[(ROWS + 2 * kDirGuard) / 4 * 64];  // g table, 4 rows per word; zero guard rows at each end
   __shared__ float part_all[kEdtBlocks * kEdtPartRows * 8];
+  __shared__ uint32_t recs[kEdtWaves * 16];
+  __shared__ int words[kEdtWaves];
   const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int i = threadIdx.x; i < (ROWS + 2 * kDirGuard) / 4 * 64; i += kEdtWaves * 64) gt_all[i] = make_uint2(0u, 0u);
-  __syncthreads();
   int cnt[kClasses];
-  int total = 0;
-#pragma unroll
-  for (int c = 0; c < kClasses; ++c) {
-    cnt[c] = (ROWS > 512) == (c == 5) ? min(counts[c], item_cap) : 0;
-    total += (cnt[c] + direct_items(c) - 1) / direct_items(c);
+  const int total = direct_count(counts, item_cap, ROWS > 512, cnt);
+  const int S = direct_split(ROWS > 512, total, gridDim.x);
+  for (int vp = blockIdx.x; vp < total * S; vp += gridDim.x) {
+    const int p = vp / S, s = vp - p * S;
+    const int cls = direct_load_packet(cnt, items, item_cap, mrec, p, recs, words);
+    float* part = S == 1 ? part_all : gpart + (int64_t)p * kDirPartFloats;
+    direct_packet<SPATIAL, WE>(cls, s, S, recs, words, gt_all + kDirGuard / 4 * 64, part, lane, kb, e_out);
+    if (S == 1) {
+      direct_strip_sums(cls, recs, words, part_all, lane, kb);
+      __syncthreads();
+    }
   }
+}
+
+// Patch sums of the packets that k_edt_direct shared between workgroups
+// (nothing to do when it shared none); grid: the direct kernel's grid.
+__global__ __launch_bounds__(kEdtWaves * 64) void k_edt_dsums(const int32_t* __restrict__ counts,
+                                                              const int32_t* __restrict__ items, int item_cap,
+                                                              const MaskRec* __restrict__ mrec, const float* gpart,
+                                                              int direct_grid) {
+  __shared__ uint32_t recs[kEdtWaves * 16];
+  __shared__ int words[kEdtWaves];
+  const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int cnt[kClasses];
+  const int total = direct_count(counts, item_cap, false, cnt);
+  if (direct_split(false, total, direct_grid) == 1) return;
   for (int p = blockIdx.x; p < total; p += gridDim.x) {
-    int word;
-    const int cls = direct_slot(cnt, items, item_cap, p, kb, word);
-    uint32_t pf = 0u;  // the item's record: lane q < 16 holds dword q
-    if (word >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(mrec + (word >> kItemStripBits))[lane];
-    direct_packet<SPATIAL, WE>(cls, pf, word, gt_all + kDirGuard / 4 * 64, part_all, lane, kb, e_out);
+    const int cls = direct_load_packet(cnt, items, item_cap, mrec, p, recs, words);
+    direct_strip_sums(cls, recs, words, gpart + (int64_t)p * kDirPartFloats, lane, kb);
+    __syncthreads();
   }
 }
 
@@ -909,18 +996,22 @@ void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipS
   const int kind = b.spatial != 0 ? 2 : (e_out ? 1 : 0);
   auto go = [&](int dv) {
     const dim3 grid(num_cus * g_edt_per_cu[dv]);
+    float* gp = w.edt_part;
     switch (dv) {
-      case 2: hipLaunchKernelGGL((k_edt_direct<0, false, 512>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
-      case 3: hipLaunchKernelGGL((k_edt_direct<0, true, 512>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
-      case 4: hipLaunchKernelGGL((k_edt_direct<1, false, 512>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
-      case 5: hipLaunchKernelGGL((k_edt_direct<0, false, kMaxRows>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
-      case 6: hipLaunchKernelGGL((k_edt_direct<0, true, kMaxRows>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
-      default: hipLaunchKernelGGL((k_edt_direct<1, false, kMaxRows>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out); break;
+      case 2: hipLaunchKernelGGL((k_edt_direct<0, false, 512>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, gp); break;
+      case 3: hipLaunchKernelGGL((k_edt_direct<0, true, 512>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, gp); break;
+      case 4: hipLaunchKernelGGL((k_edt_direct<1, false, 512>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, gp); break;
+      case 5: hipLaunchKernelGGL((k_edt_direct<0, false, kMaxRows>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, gp); break;
+      case 6: hipLaunchKernelGGL((k_edt_direct<0, true, kMaxRows>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, gp); break;
+      default: hipLaunchKernelGGL((k_edt_direct<1, false, kMaxRows>), grid, blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, e_out, gp); break;
     }
+    return (int)grid.x;
   };
-  // items taller than 512 rows (class 5) first, when the batch can have any
+  // items taller than 512 rows (class 5) first, when the batch can have any;
+  // then the rest, whose packets may be shared (their patch sums follow)
   if (b.max_rows > 512) go(5 + kind);
-  go(2 + kind);
+  const int g = go(2 + kind);
+  hipLaunchKernelGGL(k_edt_dsums, dim3(num_cus), blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, w.edt_part, g);
 }
 
 }  // namespace disc
