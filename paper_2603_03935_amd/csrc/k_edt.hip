@@ -780,34 +780,57 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
   const int nbs = rows_c / kBlkRows;  // blocks per slot
   const int nblk = ipp * nbs;         // blocks of the packet
 
-  // ---- g table: every block of every slot (0 past the slot's item); lane l
-  // < 16 builds row l's record, then each row's record is broadcast and
-  // decoded by all lanes, four rows per 64-bit word ----
-  for (int b = kb; b < nblk; b += kEdtWaves) {
-    const int slot = b / nbs, r0 = (b - slot * nbs) * kBlkRows;
-    const DirItem it = direct_item(recs, words, slot);
-    const bool lane_ok = lane < it.SW;
+  // ---- g table: every block of every slot (0 past the slot's item).  A
+  // wavefront takes up to four blocks per round: lane l reads row l & 15 of
+  // the (l >> 4)-th block (its window and the run lengths past the window's
+  // ends), so the global reads of the round overlap; then each block's rows
+  // are broadcast and decoded by all lanes, four rows per 64-bit word. ----
+  for (int b1 = kb; b1 < nblk; b1 += 4 * kEdtWaves) {
     uint4 r = make_uint4(0u, 0u, 0u, 0u);  // padding row: no runs
-    const int u = r0 + lane;
-    if (lane < kBlkRows && u > 0 && u < it.n - 1) {
-      const uint64_t* row = it.mb + (int64_t)(it.y0 - 1 + u) * it.wq;
-      const uint64_t win = load_window(row, it.xs, it.wq, it.fw);
-      const int L = (win & 1ull) ? run_left(row, it.xs - 1, it.wq, it.fw) : 0;
-      const int R = (win >> 63) ? run_right(row, it.xs + 64, it.wq, it.fw) : 0;
-      r = make_rowrec(win, L, R);
-    }
-    uint2* gt = gt_all + ((slot * rows_c + r0) >> 2) * 64 + lane;
-#pragma unroll
-    for (int k4 = 0; k4 < kBlkRows; k4 += 4) {
-      uint32_t h[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint4 ru =
-            make_uint4(__builtin_amdgcn_readlane(r.x, k4 + k), __builtin_amdgcn_readlane(r.y, k4 + k),
-                       __builtin_amdgcn_readlane(r.z, k4 + k), __builtin_amdgcn_readlane(r.w, k4 + k));
-        h[k] = lane_ok ? (uint32_t)g_rec(ru, lane) : 0u;
+    {
+      const int bl = b1 + kEdtWaves * (lane >> 4);
+      if (bl < nblk) {
+        const int slot = bl / nbs;
+        const int word = words[slot];
+        const uint32_t* rc = recs + slot * 16;
+        const int n = word >= 0 ? (int)rc[8] : 0;
+        const int u = (bl - slot * nbs) * kBlkRows + (lane & 15);
+        if (u > 0 && u < n - 1) {
+          const uint64_t* mb = reinterpret_cast<const uint64_t*>(((uint64_t)rc[1] << 32) | rc[0]);
+          const int y0 = (int)rc[4], wq = (int)rc[11], fw = (int)rc[12];
+          const int xs = (int)rc[14] + (word & ((1 << kItemStripBits) - 1)) * strip_width((int)rc[9]);
+          const uint64_t* row = mb + (int64_t)(y0 - 1 + u) * wq;
+          const uint64_t win = load_window(row, xs, wq, fw);
+          const int L = (win & 1ull) ? run_left(row, xs - 1, wq, fw) : 0;
+          const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw) : 0;
+          r = make_rowrec(win, L, R);
+        }
       }
-      gt[(k4 >> 2) * 64] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int b = b1 + kEdtWaves * t;
+      if (b >= nblk) break;
+      const int slot = b / nbs, r0 = (b - slot * nbs) * kBlkRows;
+      const DirItem it = direct_item(recs, words, slot);
+      const bool lane_ok = lane < it.SW;
+      uint2* gt = gt_all + ((slot * rows_c + r0) >> 2) * 64 + lane;
+#pragma unroll
+      for (int k4 = 0; k4 < kBlkRows; k4 += 4) {
+        if (r0 + k4 >= it.n - 1) {  // padding rows only
+          gt[(k4 >> 2) * 64] = make_uint2(0u, 0u);
+          continue;
+        }
+        uint32_t h[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int src = 16 * t + k4 + k;
+          const uint4 ru = make_uint4(__builtin_amdgcn_readlane(r.x, src), __builtin_amdgcn_readlane(r.y, src),
+                                      __builtin_amdgcn_readlane(r.z, src), __builtin_amdgcn_readlane(r.w, src));
+          h[k] = lane_ok ? (uint32_t)g_rec(ru, lane) : 0u;
+        }
+        gt[(k4 >> 2) * 64] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+      }
     }
   }
   __syncthreads();
