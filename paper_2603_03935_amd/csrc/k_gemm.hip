@@ -115,24 +115,39 @@ __device__ __forceinline__ void tile_krange(const Work& wk, const FrameDesc& fd,
   kend = min(*kmax_sh, fd.G);
 }
 
+// The tile's rows resolved once (all threads call it; it synchronises):
+// (global mask index, index in the frame, Z bits, 1 if the row is stored
+// divided by Z else 0), or g = -1 past the frame's masks.
+__device__ __forceinline__ void pool_rows(const Work& wk, const FrameDesc& fd, int m0, int tid, int4* rows) {
+  if (tid < PBM) {
+    int4 v = make_int4(-1, 0, 0, 0);
+    if (m0 + tid < fd.m) {
+      const int mi = wk.perm[fd.mask_base + m0 + tid];
+      const int g = fd.mask_base + mi;
+      const float Z = wk.Z[g];
+      v = make_int4(g, mi, __float_as_int(Z), (wk.mstat[g] == 0 && Z > 0.f) ? 1 : 0);
+    }
+    rows[tid] = v;
+  }
+  __syncthreads();
+}
+
 // divide by Z, store X (GEMM dtype) and the optional FP32 pooled output
 template <int BF16>
-__device__ __forceinline__ void pool_store(const Work& wk, const FrameDesc& fd, int m0, int n0, int C, int lane, int wm,
-                                           int wn, const floatx16& acc) {
+__device__ __forceinline__ void pool_store(const Work& wk, const FrameDesc& fd, const int4* rows, int n0, int C,
+                                           int lane, int wm, int wn, const floatx16& acc) {
   const int col = n0 + 32 * wn + (lane & 31);
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int r = 32 * wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-    if (m0 + r >= fd.m) continue;
-    const int mi = wk.perm[fd.mask_base + m0 + r];
-    const int g = fd.mask_base + mi;
-    const float Z = wk.Z[g];
-    const float val = (wk.mstat[g] == 0 && Z > 0.f) ? acc[v] / Z : 0.f;
+    const int4 rw = rows[r];
+    if (rw.x < 0) continue;
+    const float val = rw.w ? acc[v] / __int_as_float(rw.z) : 0.f;
     if (BF16)
-      reinterpret_cast<uint16_t*>(wk.X)[(int64_t)g * C + col] = f2bf(val);
+      reinterpret_cast<uint16_t*>(wk.X)[(int64_t)rw.x * C + col] = f2bf(val);
     else
-      reinterpret_cast<float*>(wk.X)[(int64_t)g * C + col] = val;
-    if (fd.pooled) fd.pooled[(int64_t)mi * C + col] = val;
+      reinterpret_cast<float*>(wk.X)[(int64_t)rw.x * C + col] = val;
+    if (fd.pooled) fd.pooled[(int64_t)rw.y * C + col] = val;
   }
 }
 
@@ -277,8 +292,10 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   }
   if (kstart < kstop) fold(cur);
   if (S == 1) {
+    __shared__ int4 rows[PBM];
+    pool_rows(wk, fd, m0, tid, rows);
 #pragma unroll
-    for (int j = 0; j < NT; ++j) pool_store<BF16>(wk, fd, m0, n0 + 64 * j, C, lane, wm, wn, total[j]);
+    for (int j = 0; j < NT; ++j) pool_store<BF16>(wk, fd, rows, n0 + 64 * j, C, lane, wm, wn, total[j]);
   }
 }
 
@@ -308,7 +325,9 @@ __global__ __launch_bounds__(256) void k_pool_reduce(Batch b, Work wk, const int
       total[4 * i + 3] += v.w;
     }
   }
-  pool_store<BF16>(wk, fd, m0, n0, b.C, lane, wm, wn, total);
+  __shared__ int4 rows[PBM];
+  pool_rows(wk, fd, m0, tid, rows);
+  pool_store<BF16>(wk, fd, rows, n0, b.C, lane, wm, wn, total);
 }
 
 template <int BF16, int TOK>
