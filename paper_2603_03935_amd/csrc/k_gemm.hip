@@ -193,19 +193,23 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   // B (FP32): patch tid >> 3, channels 8*(tid & 7) + 64 j .. +7
   const int bk32 = tid >> 3, bn32 = (tid & 7) * 8;
 
-  uint4 ra16 = make_uint4(0, 0, 0, 0), rb16[NT];
-  float ra32[8], rb32[NT][8];
+  // FP32 operands: two register sets, the loads of step k + 2 PBK are in
+  // flight while step k computes (small batches are latency-bound).  BF16:
+  // one set, one step ahead (more resident workgroups hide the latency).
+  constexpr int DIST = BF16 ? 1 : 2;
+  uint4 ra16[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)}, rb16[2][NT];
+  float ra32[2][8], rb32[2][NT][8];
 
-  auto fetch = [&](int k0) {
+  auto fetch = [&](int k0, int q) {
     const int kk = k0 + ak;
     if (BF16) {
       const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0 + kk;
       if (arow_ok && kk + 8 <= G) {
-        ra16 = *reinterpret_cast<const uint4*>(src);
+        ra16[q] = *reinterpret_cast<const uint4*>(src);
       } else {
         uint16_t tmp[8];
         for (int j = 0; j < 8; ++j) tmp[j] = (arow_ok && kk + j < G) ? src[j] : (uint16_t)0;
-        ra16 = make_uint4(tmp[0] | (tmp[1] << 16), tmp[2] | (tmp[3] << 16), tmp[4] | (tmp[5] << 16), tmp[6] | (tmp[7] << 16));
+        ra16[q] = make_uint4(tmp[0] | (tmp[1] << 16), tmp[2] | (tmp[3] << 16), tmp[4] | (tmp[5] << 16), tmp[6] | (tmp[7] << 16));
       }
       // k-packed tokens: one vector load gives one channel's 8 patches
       const int grp = (k0 + bk16) >> 3;
@@ -213,30 +217,37 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
       for (int j = 0; j < NT; ++j) {
         if (grp * 8 < G) {
           const int64_t e = fd.t_base + ((int64_t)grp * C + n0 + bn16 + 64 * j) * 8;
-          rb16[j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(wk.tkp) + e);
+          rb16[q][j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(wk.tkp) + e);
         } else {
-          rb16[j] = make_uint4(0, 0, 0, 0);
+          rb16[q][j] = make_uint4(0, 0, 0, 0);
         }
       }
     } else {
+      // weight rows start on 8 elements (Gs and the frame bases are multiples of 8)
       const float* src = reinterpret_cast<const float*>(wk.W) + wrow0 + kk;
-      for (int j = 0; j < 8; ++j) ra32[j] = (arow_ok && kk + j < G) ? src[j] : 0.f;
+      if (arow_ok && kk + 8 <= G) {
+        const float4 x = reinterpret_cast<const float4*>(src)[0], y = reinterpret_cast<const float4*>(src)[1];
+        ra32[q][0] = x.x; ra32[q][1] = x.y; ra32[q][2] = x.z; ra32[q][3] = x.w;
+        ra32[q][4] = y.x; ra32[q][5] = y.y; ra32[q][6] = y.z; ra32[q][7] = y.w;
+      } else {
+        for (int j = 0; j < 8; ++j) ra32[q][j] = (arow_ok && kk + j < G) ? src[j] : 0.f;
+      }
       const int kr = k0 + bk32;
 #pragma unroll
-      for (int j = 0; j < NT; ++j) load_tok8<TOK, 0>(fd.tokens, (int64_t)kr * C + n0 + bn32 + 64 * j, kr < G, nullptr, rb32[j]);
+      for (int j = 0; j < NT; ++j) load_tok8<TOK, 0>(fd.tokens, (int64_t)kr * C + n0 + bn32 + 64 * j, kr < G, nullptr, rb32[q][j]);
     }
   };
-  auto stage = [&]() {
+  auto stage = [&](int q) {
     if (BF16) {
-      *reinterpret_cast<uint4*>(&As16[ar * PAS + ak]) = ra16;
+      *reinterpret_cast<uint4*>(&As16[ar * PAS + ak]) = ra16[q];
 #pragma unroll
-      for (int j = 0; j < NT; ++j) *reinterpret_cast<uint4*>(&Bs16[(bn16 + 64 * j) * PAS + bk16]) = rb16[j];
+      for (int j = 0; j < NT; ++j) *reinterpret_cast<uint4*>(&Bs16[(bn16 + 64 * j) * PAS + bk16]) = rb16[q][j];
     } else {
-      for (int j = 0; j < 8; ++j) As32[ar * (PBK + 1) + ak + j] = ra32[j];
+      for (int j = 0; j < 8; ++j) As32[ar * (PBK + 1) + ak + j] = ra32[q][j];
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
-        *reinterpret_cast<float4*>(&Bs32[bk32 * BN + bn32 + 64 * j]) = make_float4(rb32[j][0], rb32[j][1], rb32[j][2], rb32[j][3]);
-        *reinterpret_cast<float4*>(&Bs32[bk32 * BN + bn32 + 64 * j + 4]) = make_float4(rb32[j][4], rb32[j][5], rb32[j][6], rb32[j][7]);
+        *reinterpret_cast<float4*>(&Bs32[bk32 * BN + bn32 + 64 * j]) = make_float4(rb32[q][j][0], rb32[q][j][1], rb32[q][j][2], rb32[q][j][3]);
+        *reinterpret_cast<float4*>(&Bs32[bk32 * BN + bn32 + 64 * j + 4]) = make_float4(rb32[q][j][4], rb32[q][j][5], rb32[q][j][6], rb32[q][j][7]);
       }
     }
   };
@@ -258,15 +269,14 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
 
   const int lr = lane & 31, lk = lane >> 5;
   int cur = kstart / kPoolKG;
-  if (kstart < kstop) fetch(kstart);
-  for (int k0 = kstart; k0 < kstop; k0 += PBK) {
+  auto step = [&](int k0, int q) {
     if (k0 / kPoolKG != cur) {
       fold(cur);
       cur = k0 / kPoolKG;
     }
-    stage();
+    stage(q);
     __syncthreads();
-    if (k0 + PBK < kstop) fetch(k0 + PBK);
+    if (k0 + DIST * PBK < kstop) fetch(k0 + DIST * PBK, q);
     if (BF16) {
 #pragma unroll
       for (int kk = 0; kk < PBK; kk += 16) {
@@ -289,6 +299,17 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
       }
     }
     __syncthreads();
+  };
+  if (kstart < kstop) fetch(kstart, 0);
+  if (DIST == 2) {
+    if (kstart + PBK < kstop) fetch(kstart + PBK, 1);
+    for (int k0 = kstart; k0 < kstop; k0 += 2 * PBK) {
+      step(k0, 0);
+      if (k0 + PBK >= kstop) break;
+      step(k0 + PBK, 1);
+    }
+  } else {
+    for (int k0 = kstart; k0 < kstop; k0 += PBK) step(k0, 0);
   }
   if (kstart < kstop) fold(cur);
   if (S == 1) {
