@@ -683,7 +683,7 @@ constexpr int kDirSteps = 4;  // distances per search step (windows start on 4-r
 // item can no longer win).
 constexpr int kDirGuard = 12;
 static_assert(kDirGuard >= kDirRows + kDirSteps - 2 && kDirGuard % 4 == 0, "guard rows");
-static_assert(kDirRows % 4 == 0 && kDirSteps == 4 && kBlkRows % kDirRows == 0, "search windows are whole 4-row words");
+static_assert(kDirRows == 4 && kDirSteps == 4 && kBlkRows % kDirRows == 0, "search windows are whole 4-row words");
 
 // the packets of the classes in the kernel's range (tallest first)
 __device__ __forceinline__ int direct_count(const int32_t* counts, int item_cap, bool tall, int* cnt) {
@@ -773,7 +773,21 @@ __device__ __forceinline__ void direct_strip_sums(int cls, const uint32_t* recs,
                      it.y0, it.y1, it.gw);
 }
 
-template <int SPATIAL, bool WE>
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ us2 as_us2(uint32_t x) { return __builtin_bit_cast(us2, x); }
+__device__ __forceinline__ us2 sq2(uint32_t x) { const us2 v = as_us2(x); return v * v; }
+__device__ __forceinline__ int max4(us2 a, us2 b) {
+  const us2 m = __builtin_elementwise_max(a, b);
+  return max((int)m.x, (int)m.y);
+}
+
+// PK: items of at most 512 rows.  Every e is then at most 255^2 (rows 0 and
+// n - 1 are padding with g = 0, and min(u, n - 1 - u) <= 255), so g is
+// clamped to 255 in the table (a candidate with g >= 255 is >= 255^2 >= e
+// either way: no e changes) and the search runs in packed 16-bit arithmetic,
+// two rows per instruction: squares < 2^16, sums saturate at 65535, which
+// is never below the best value (<= 65025).
+template <int SPATIAL, bool WE, bool PK>
 __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint32_t* recs, const int* words,
                                               uint2* gt_all, float* part, int lane, int kb, int32_t* e_out) {
   const int rows_c = class_rows(cls), ipp = direct_items(cls);
@@ -828,6 +842,7 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
           const uint4 ru = make_uint4(__builtin_amdgcn_readlane(r.x, src), __builtin_amdgcn_readlane(r.y, src),
                                       __builtin_amdgcn_readlane(r.z, src), __builtin_amdgcn_readlane(r.w, src));
           h[k] = lane_ok ? (uint32_t)g_rec(ru, lane) : 0u;
+          if (PK) h[k] = min(h[k], 255u);
         }
         gt[(k4 >> 2) * 64] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
       }
@@ -871,7 +886,44 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
           bmax = max(bmax, best[4 * q + k]);
         }
       }
-      if (SPATIAL == 0) {
+      if (SPATIAL == 0 && PK) {
+        // packed: rows (0,1) and (2,3) of the group in one register each;
+        // the window rows as aligned pairs (2j, 2j+1) and odd pairs
+        // (2j+1, 2j+2)
+        us2 B[2] = {as_us2((uint32_t)best[0] | ((uint32_t)best[1] << 16)), as_us2((uint32_t)best[2] | ((uint32_t)best[3] << 16))};
+        for (int d = 1; d * d < bmax; d += kDirSteps) {
+          const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * 64;
+          const uint2* pd = base + ((d - 1) >> 2) * 64;
+          const uint2 u0w = pu[0], u1w = pu[64], d0w = pd[0], d1w = pd[64];
+          const uint32_t U[4] = {__builtin_bit_cast(uint32_t, sq2(u0w.x)), __builtin_bit_cast(uint32_t, sq2(u0w.y)),
+                                 __builtin_bit_cast(uint32_t, sq2(u1w.x)), __builtin_bit_cast(uint32_t, sq2(u1w.y))};
+          const uint32_t Dn[4] = {__builtin_bit_cast(uint32_t, sq2(d0w.x)), __builtin_bit_cast(uint32_t, sq2(d0w.y)),
+                                  __builtin_bit_cast(uint32_t, sq2(d1w.x)), __builtin_bit_cast(uint32_t, sq2(d1w.y))};
+          uint32_t Uo[3], Do[3];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            Uo[j] = __builtin_amdgcn_alignbyte(U[j + 1], U[j], 2);
+            Do[j] = __builtin_amdgcn_alignbyte(Dn[j + 1], Dn[j], 2);
+          }
+#pragma unroll
+          for (int i = 0; i < kDirSteps; ++i) {
+            const uint32_t dd = (uint32_t)min((d + i) * (d + i), 65535);
+            const us2 D = as_us2(dd | (dd << 16));
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {  // rows 2q, 2q + 1 at distance d + i
+              const uint32_t up = (i & 1) ? U[(3 + 2 * q - i) >> 1] : Uo[(2 + 2 * q - i) >> 1];
+              const uint32_t dn = (i & 1) ? Dn[(1 + 2 * q + i) >> 1] : Do[(2 * q + i) >> 1];
+              B[q] = __builtin_elementwise_min(
+                  B[q], __builtin_elementwise_add_sat(__builtin_elementwise_min(as_us2(up), as_us2(dn)), D));
+            }
+          }
+          bmax = max4(B[0], B[1]);
+        }
+        best[0] = B[0].x;
+        best[1] = B[0].y;
+        best[2] = B[1].x;
+        best[3] = B[1].y;
+      } else if (SPATIAL == 0) {
         // d = 1 (mod 4): the windows start on words, up at u0 - d - 3, down
         // at u0 + d - 1 (one row early)
         for (int d = 1; d * d < bmax; d += kDirSteps) {
@@ -942,7 +994,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const int p = vp / S, s = vp - p * S;
     const int cls = direct_load_packet(cnt, items, item_cap, mrec, p, recs, words);
     float* part = S == 1 ? part_all : gpart + (int64_t)p * kDirPartFloats;
-    direct_packet<SPATIAL, WE>(cls, s, S, recs, words, gt_all + kDirGuard / 4 * 64, part, lane, kb, e_out);
+    direct_packet<SPATIAL, WE, (ROWS <= 512)>(cls, s, S, recs, words, gt_all + kDirGuard / 4 * 64, part, lane, kb, e_out);
     if (S == 1) {
       direct_strip_sums(cls, recs, words, part_all, lane, kb);
       __syncthreads();
