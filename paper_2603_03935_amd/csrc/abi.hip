@@ -168,6 +168,7 @@ Layout make_layout(const Shape& s) {
   L.perm = take(4 * (size_t)s.M);
   L.X = take((s.gemm_bf16 ? 2 : 4) * (size_t)s.M * s.C);
   L.ppart = take(s.pool_split > 1 ? 4 * (size_t)s.n_tiles * s.kgroups * 64 * 64 : 0);
+  L.ptile = take(s.pool_split > 1 ? 16 * (size_t)s.n_tiles * 65 : 0);
   L.qpart = take(s.proj_split > 1 ? 4 * (size_t)((s.C + kProjKG - 1) / kProjKG) * s.M * s.E : 0);
   L.ppack = take(s.gemm_bf16 ? 2 * (size_t)s.C * s.E : 0);
   L.edt_part = take(4 * (size_t)kDirSplitPackets * kDirPartFloats);
@@ -284,6 +285,7 @@ Work work_ptrs(char* base, const Layout& L) {
   w.perm = reinterpret_cast<int32_t*>(base + L.perm);
   w.X = base + L.X;
   w.ppart = reinterpret_cast<float*>(base + L.ppart);
+  w.ptile = reinterpret_cast<int4*>(base + L.ptile);
   w.qpart = reinterpret_cast<float*>(base + L.qpart);
   w.ppack = base + L.ppack;
   w.edt_part = reinterpret_cast<float*>(base + L.edt_part);

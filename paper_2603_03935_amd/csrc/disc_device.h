@@ -133,6 +133,7 @@ struct Work {
   int32_t* perm;       // [M] pooling order: perm[mask_base + i] = frame-local mask of tile row i
   void* X;             // [M][C] pooled features in the GEMM dtype
   float* ppart;        // pooling group sums [tile][kgroups][64*64] (split K only)
+  int4* ptile;         // per pooling tile: (first, end K group), then its 64 rows as pool_rows gives them (split K only)
   float* qpart;        // projection group sums [C/256][M][E] (split K only)
   float* edt_part;     // direct EDT block partial sums of shared packets [kDirSplitPackets][kDirPartFloats]
   void* ppack;         // k-packed BF16 copy of P [C/8][E][8] (BF16 GEMMs)

@@ -13,7 +13,7 @@ namespace host {
 
 struct Layout {
   size_t frames, mask_frame, tiles, dyn, staged_end;  // staged region (uploaded from the host)
-  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, rbar, s, W, Z, mstat, perm, X, ppart, qpart, ppack, edt_part, tkp, total;
+  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, rbar, s, W, Z, mstat, perm, X, ppart, ptile, qpart, ppack, edt_part, tkp, total;
 };
 
 struct Shape {

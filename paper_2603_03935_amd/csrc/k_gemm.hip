@@ -179,6 +179,21 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   const int per = (gend - gbeg + S - 1) / S;
   const int ga = gbeg + sidx * per, gb = min(gend, ga + per);
   const int kstart = max(kbeg, ga * kPoolKG), kstop = min(kend, gb * kPoolKG);
+  if (S > 1 && sidx == 0 && tid <= PBM) {
+    // for the reduce pass: the tiles' K groups and rows (no wait here)
+    int4 v = make_int4(gbeg, gend, 0, 0);
+    if (tid < PBM) {
+      v = make_int4(-1, 0, 0, 0);
+      if (m0 + tid < fd.m) {
+        const int mi = wk.perm[fd.mask_base + m0 + tid];
+        const int g = fd.mask_base + mi;
+        const float Z = wk.Z[g];
+        v = make_int4(g, mi, __float_as_int(Z), (wk.mstat[g] == 0 && Z > 0.f) ? 1 : 0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) wk.ptile[(int64_t)(tix + j) * (PBM + 1) + (tid < PBM ? 1 + tid : 0)] = v;
+  }
 
   const floatx16 zero16 = {};
   floatx16 total[NT], acc[NT];
@@ -325,17 +340,16 @@ template <int BF16>
 __global__ __launch_bounds__(256) void k_pool_reduce(Batch b, Work wk, const int4* tiles) {
   const int tix = blockIdx.x;
   if (tix >= b.dyn[2]) return;
-  const int4 t = tiles[tix];
-  const FrameDesc fd = b.frames[t.x];
-  const int m0 = t.y, n0 = t.z;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
-  __shared__ int kmin_sh, kmax_sh;
-  int kbeg, kend;
-  tile_krange(wk, fd, m0, min(PBM, fd.m - m0), tid, &kmin_sh, &kmax_sh, kbeg, kend);
-  const int gbeg = kbeg / kPoolKG, gend = kbeg < kend ? (kend + kPoolKG - 1) / kPoolKG : gbeg;
+  // the tile's K groups and rows, as the first share of the split pass wrote them
+  const int4* info = wk.ptile + (int64_t)tix * (PBM + 1);
+  __shared__ int4 rows[PBM];
+  if (tid < PBM) rows[tid] = info[1 + tid];
+  const int4 kr = info[0];
+  const int4 t = tiles[tix];
   floatx16 total = {};
   const float* gpart = wk.ppart + ((int64_t)tix * b.kgroups) * (PBM * PBN) + tid * 16;
-  for (int grp = gbeg; grp < gend; ++grp) {
+  for (int grp = kr.x; grp < kr.y; ++grp) {
     const float4* src = reinterpret_cast<const float4*>(gpart + (int64_t)grp * (PBM * PBN));
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -346,9 +360,8 @@ __global__ __launch_bounds__(256) void k_pool_reduce(Batch b, Work wk, const int
       total[4 * i + 3] += v.w;
     }
   }
-  __shared__ int4 rows[PBM];
-  pool_rows(wk, fd, m0, tid, rows);
-  pool_store<BF16>(wk, fd, rows, n0, b.C, lane, wm, wn, total);
+  __syncthreads();
+  pool_store<BF16>(wk, b.frames[t.x], rows, t.z, b.C, lane, wm, wn, total);
 }
 
 template <int BF16, int TOK>
