@@ -633,7 +633,7 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
     launch_token_stats(b, w, p.shape.gmax, want_r, p.shape.gemm_bf16, st);
     if (p.shape.want_dbar) launch_rbar(b, w, st);
   }
-  { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st, p.shape.want_dbar); }
   { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st, o.edt_layout); }
   { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); launch_pool_order(b, w, st); }
   {

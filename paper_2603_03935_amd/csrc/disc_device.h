@@ -141,7 +141,9 @@ struct Work {
 };
 
 // Host-side launchers (stream = hipStream_t).
-void launch_scan(const Batch& b, const Work& w, hipStream_t st);
+// any_dbar: some frame of the batch asks for the mean distinctiveness (its
+// float sum is formed per scan thread, so such batches always use one width)
+void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar = true);
 void launch_pool_order(const Batch& b, const Work& w, hipStream_t st);
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode = -1);
 void edt_prepare();

@@ -774,6 +774,7 @@ __device__ __forceinline__ void direct_strip_sums(int cls, const uint32_t* recs,
 }
 
 typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ us2 as_us2(uint32_t x) { return __builtin_bit_cast(us2, x); }
 __device__ __forceinline__ us2 sq2(uint32_t x) { const us2 v = as_us2(x); return v * v; }
 __device__ __forceinline__ int max4(us2 a, us2 b) {
@@ -829,22 +830,50 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
       const DirItem it = direct_item(recs, words, slot);
       const bool lane_ok = lane < it.SW;
       uint2* gt = gt_all + ((slot * rows_c + r0) >> 2) * 64 + lane;
+      const s16x2 l2 = {(short)lane, (short)lane};
 #pragma unroll
       for (int k4 = 0; k4 < kBlkRows; k4 += 4) {
         if (r0 + k4 >= it.n - 1) {  // padding rows only
           gt[(k4 >> 2) * 64] = make_uint2(0u, 0u);
           continue;
         }
-        uint32_t h[4];
+        uint32_t wd[2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int src = 16 * t + k4 + k;
-          const uint4 ru = make_uint4(__builtin_amdgcn_readlane(r.x, src), __builtin_amdgcn_readlane(r.y, src),
-                                      __builtin_amdgcn_readlane(r.z, src), __builtin_amdgcn_readlane(r.w, src));
-          h[k] = lane_ok ? (uint32_t)g_rec(ru, lane) : 0u;
-          if (PK) h[k] = min(h[k], 255u);
+        for (int q = 0; q < 2; ++q) {  // rows k4 + 2q and k4 + 2q + 1
+          const int src = 16 * t + k4 + 2 * q;
+          const uint32_t z0 = __builtin_amdgcn_readlane(r.z, src), w0 = __builtin_amdgcn_readlane(r.w, src);
+          const uint32_t z1 = __builtin_amdgcn_readlane(r.z, src + 1), w1 = __builtin_amdgcn_readlane(r.w, src + 1);
+          if (((int)z0 >> 16) != kManyRuns && ((int)z1 >> 16) != kManyRuns) {
+            // both rows have at most two runs: g of the two rows at once in
+            // packed 16-bit arithmetic (every endpoint and difference is
+            // below 2^15 in magnitude), as g_runs computes it
+            const s16x2 a1 = __builtin_bit_cast(s16x2, (z0 & 0xFFFFu) | (z1 << 16));
+            const s16x2 b1 = __builtin_bit_cast(s16x2, (z0 >> 16) | (z1 & 0xFFFF0000u));
+            const s16x2 a2 = __builtin_bit_cast(s16x2, (w0 & 0xFFFFu) | (w1 << 16));
+            const s16x2 b2 = __builtin_bit_cast(s16x2, (w0 >> 16) | (w1 & 0xFFFF0000u));
+            const s16x2 zero = {0, 0};
+            s16x2 g = __builtin_elementwise_max(
+                __builtin_elementwise_max(__builtin_elementwise_min(l2 - a1, b1 - l2), __builtin_elementwise_min(l2 - a2, b2 - l2)),
+                zero);
+            if (PK) {
+              const s16x2 cap = {255, 255};
+              g = __builtin_elementwise_min(g, cap);
+            }
+            wd[q] = lane_ok ? __builtin_bit_cast(uint32_t, g) : 0u;
+          } else {
+            uint32_t h[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+              const uint4 ru =
+                  make_uint4(__builtin_amdgcn_readlane(r.x, src + e), __builtin_amdgcn_readlane(r.y, src + e),
+                             __builtin_amdgcn_readlane(r.z, src + e), __builtin_amdgcn_readlane(r.w, src + e));
+              h[e] = lane_ok ? (uint32_t)g_rec(ru, lane) : 0u;
+              if (PK) h[e] = min(h[e], 255u);
+            }
+            wd[q] = h[0] | (h[1] << 16);
+          }
         }
-        gt[(k4 >> 2) * 64] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        gt[(k4 >> 2) * 64] = make_uint2(wd[0], wd[1]);
       }
     }
   }

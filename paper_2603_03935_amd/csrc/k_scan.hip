@@ -6,7 +6,10 @@
 namespace disc {
 
 // ---------------------------------------------------------------------------
-// k_scan: one workgroup per mask streams the mask's h*wq words once (the only
+// k_scan: one workgroup per mask (1024 threads for small batches without
+// D-bar, so that a mask is read in a couple of rounds of loads, else 256:
+// D-bar's float sum depends on the width, and must not depend on the batch)
+// streams the mask's h*wq words once (the only
 // full read of the mask bits) and reduces min/max row, min/max column and the
 // pixel count.  Columns >= w in the last word of a row are ignored.
 // For frames that ask for it, the same pass sums r_p over the mask's pixels
@@ -28,7 +31,9 @@ __device__ inline int wave_sum(int v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
+template <int kScanThreads>
+__global__ __launch_bounds__(kScanThreads) void k_scan(Batch b, Work wk) {
+  constexpr int kScanWaves = kScanThreads / 64;
   const int g = blockIdx.x;
   if (g >= b.dyn[1]) return;
   const FrameDesc fd = b.frames[b.mask_frame[g]];
@@ -41,7 +46,7 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
   const float* rf = fd.dbar ? wk.r + fd.r_base : nullptr;
   const int P = fd.patch;
   float rsum = 0.f;
-  // words tid, tid+256, ... in groups of four independent loads in flight;
+  // words tid, tid + kScanThreads, ... in groups of four independent loads in flight;
   // (row, word) of each load without a division per word
   auto visit = [&](uint64_t v, int row, int k) {
     if (k == wq - 1) v &= last_valid;
@@ -67,7 +72,7 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
     }
   };
   int row = threadIdx.x / wq, k = threadIdx.x % wq;
-  const int drow = 256 / wq, dk = 256 % wq;
+  const int drow = kScanThreads / wq, dk = kScanThreads % wq;
   auto step = [&](int& r, int& kk) {
     r += drow;
     kk += dk;
@@ -77,17 +82,17 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
     }
   };
   int64_t i = threadIdx.x;
-  for (; i + 3 * 256 < nwords; i += 4 * 256) {
+  for (; i + 3 * kScanThreads < nwords; i += 4 * kScanThreads) {
     uint64_t v[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load(mb + i + q * 256);
+    for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load(mb + i + q * kScanThreads);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       visit(v[q], row, k);
       step(row, k);
     }
   }
-  for (; i < nwords; i += 256) {
+  for (; i < nwords; i += kScanThreads) {
     visit(__builtin_nontemporal_load(mb + i), row, k);
     step(row, k);
   }
@@ -97,8 +102,8 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
   xmax = wave_max(xmax);
   area = wave_sum(area);
   for (int o = 32; o > 0; o >>= 1) rsum += __shfl_xor(rsum, o);
-  __shared__ float rred[4];
-  __shared__ int red[4][5];
+  __shared__ float rred[kScanWaves];
+  __shared__ int red[kScanWaves][5];
   __shared__ int app[3];  // class, strips, first slot in the class list
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) {
@@ -111,7 +116,7 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 1; i < 4; ++i) {
+    for (int i = 1; i < kScanWaves; ++i) {
       ymin = min(ymin, red[i][0]);
       ymax = max(ymax, red[i][1]);
       xmin = min(xmin, red[i][2]);
@@ -163,7 +168,8 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
     const int64_t li = g - fd.mask_base;
     if (fd.area_out) fd.area_out[li] = area;
     if (fd.dbar) {
-      const float tot = ((rred[0] + rred[1]) + rred[2]) + rred[3];
+      float tot = rred[0];
+      for (int i = 1; i < kScanWaves; ++i) tot += rred[i];
       const int f = b.mask_frame[g];
       fd.dbar[li] = area > 0 ? (tot / (float)area) / (wk.rbar[f] + b.eps) : 0.f;
     }
@@ -172,13 +178,17 @@ __global__ __launch_bounds__(256) void k_scan(Batch b, Work wk) {
   const int strips = app[1];
   if (strips > 0) {
     int32_t* list = wk.items + (int64_t)app[0] * b.item_cap + app[2];
-    for (int j = threadIdx.x; j < strips; j += 256)
+    for (int j = threadIdx.x; j < strips; j += kScanThreads)
       if (app[2] + j < b.item_cap) list[j] = (g << kItemStripBits) | j;
   }
 }
 
-void launch_scan(const Batch& b, const Work& w, hipStream_t st) {
-  if (b.M > 0) hipLaunchKernelGGL(k_scan, dim3(b.M), dim3(256), 0, st, b, w);
+void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar) {
+  if (b.M <= 0) return;
+  if (b.M <= 512 && !any_dbar)
+    hipLaunchKernelGGL(k_scan<1024>, dim3(b.M), dim3(1024), 0, st, b, w);
+  else
+    hipLaunchKernelGGL(k_scan<256>, dim3(b.M), dim3(256), 0, st, b, w);
 }
 
 // ---------------------------------------------------------------------------
