@@ -634,8 +634,9 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
     if (p.shape.want_dbar) launch_rbar(b, w, st);
   }
   { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st, p.shape.want_dbar); }
-  { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st, o.edt_layout); }
-  { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); launch_pool_order(b, w, st); }
+  // the pooling order rides on the launch after the distance transform
+  { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st, o.edt_layout, true); }
+  { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); }
   {
     StageTimer t(sid < 0 ? -1 : ST_POOL, st);
     bool ran = false;

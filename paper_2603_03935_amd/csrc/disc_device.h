@@ -144,8 +144,51 @@ struct Work {
 // any_dbar: some frame of the batch asks for the mean distinctiveness (its
 // float sum is formed per scan thread, so such batches always use one width)
 void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar = true);
+// Pooling order of frame f's masks: a counting sort over 256 buckets by the
+// first patch row of the box (empty masks last), so that each 64-mask pooling
+// tile reads a narrow band of token rows.  The order within a bucket follows
+// the atomics and may differ from run to run: which masks share a tile never
+// changes a mask's result.  Any block size >= 256 (the first 256 threads own
+// the buckets); all threads of the block call it.
+__device__ inline void pool_order_frame(const Batch& b, const Work& wk, int f, int* cnt, int* wsum) {
+  const FrameDesc& fd = b.frames[f];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nt = blockDim.x;
+  const int m = fd.m, base = fd.mask_base, P = fd.patch;
+  auto key = [&](int i) {
+    const int4 bb = wk.bbox[base + i];
+    return bb.x > bb.y ? 255 : min(bb.x / P, 254);
+  };
+  if (tid < 256) cnt[tid] = 0;
+  __syncthreads();
+  for (int i = tid; i < m; i += nt) atomicAdd(&cnt[key(i)], 1);
+  __syncthreads();
+  // exclusive prefix of the 256 bucket counts (the first four wavefronts)
+  int v = 0, x = 0;
+  if (tid < 256) {
+    v = cnt[tid];
+    x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(x, o);
+      if (lane >= o) x += t;
+    }
+    if (lane == 63) wsum[wv] = x;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    int before = 0;
+    for (int k = 0; k < wv; ++k) before += wsum[k];
+    cnt[tid] = before + x - v;
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += nt) wk.perm[base + atomicAdd(&cnt[key(i)], 1)] = i;
+  __syncthreads();
+}
+
 void launch_pool_order(const Batch& b, const Work& w, hipStream_t st);
-void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode = -1);
+// order_pool: also order every frame's masks for the pooling (as
+// launch_pool_order), inside the launch that follows the distance transform
+void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode = -1,
+                bool order_pool = false);
 void edt_prepare();
 // want_r: residual norms (needs the mean); pack: k-packed token copy for the BF16 pooling GEMM
 void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st);

@@ -1032,13 +1032,20 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
 }
 
 // Patch sums of the packets that k_edt_direct shared between workgroups
-// (nothing to do when it shared none); grid: the direct kernel's grid.
-__global__ __launch_bounds__(kEdtWaves * 64) void k_edt_dsums(const int32_t* __restrict__ counts,
+// (nothing to do when it shared none); grid: the direct kernel's grid.  With
+// order_pool it first orders every frame's masks for the pooling (one
+// workgroup per frame, in a stride).
+__global__ __launch_bounds__(kEdtWaves * 64) void k_edt_dsums(Batch b, const int32_t* __restrict__ counts,
                                                               const int32_t* __restrict__ items, int item_cap,
                                                               const MaskRec* __restrict__ mrec, const float* gpart,
-                                                              int direct_grid) {
+                                                              int direct_grid, Work wk, int order_pool) {
   __shared__ uint32_t recs[kEdtWaves * 16];
   __shared__ int words[kEdtWaves];
+  if (order_pool) {
+    __shared__ int ocnt[256];
+    __shared__ int owsum[4];
+    for (int f = blockIdx.x; f < b.dyn[0]; f += gridDim.x) pool_order_frame(b, wk, f, ocnt, owsum);
+  }
   const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int cnt[kClasses];
   const int total = direct_count(counts, item_cap, false, cnt);
@@ -1085,10 +1092,12 @@ void edt_prepare() {
 // kernel in that band layout.  e_out (squared distances of the bounding
 // boxes) is written by the direct search only (callers that pass it use the
 // default layout); the AREA variants never produce distances.
-void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode) {
+void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode,
+                bool order_pool) {
   edt_prepare();
   const dim3 blk(kEdtWaves * 64);
   if (mode == 0 || mode == 1) {
+    if (order_pool) launch_pool_order(b, w, st);
     const int v = b.spatial != 0 ? 1 : 0;
     const dim3 grid(num_cus * g_edt_per_cu[v]);
     if (v == 0)
@@ -1115,7 +1124,9 @@ void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipS
   // then the rest, whose packets may be shared (their patch sums follow)
   if (b.max_rows > 512) go(5 + kind);
   const int g = go(2 + kind);
-  hipLaunchKernelGGL(k_edt_dsums, dim3(num_cus), blk, 0, st, w.counts, w.items, b.item_cap, w.mrec, w.edt_part, g);
+  const int op = order_pool && b.n_frames > 0 && b.M > 0 ? 1 : 0;
+  hipLaunchKernelGGL(k_edt_dsums, dim3(num_cus), blk, 0, st, b, w.counts, w.items, b.item_cap, w.mrec, w.edt_part, g, w,
+                     op);
 }
 
 }  // namespace disc

@@ -199,34 +199,9 @@ void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar) {
 // run to run: which masks share a tile never changes a mask's result.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_pool_order(Batch b, Work wk) {
-  const int f = blockIdx.x;
-  if (f >= b.dyn[0]) return;
-  const FrameDesc fd = b.frames[f];
   __shared__ int cnt[256];
   __shared__ int wsum[4];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  cnt[tid] = 0;
-  __syncthreads();
-  auto key = [&](int i) {
-    const int4 bb = wk.bbox[fd.mask_base + i];
-    return bb.x > bb.y ? 255 : min(bb.x / fd.patch, 254);
-  };
-  for (int i = tid; i < fd.m; i += 256) atomicAdd(&cnt[key(i)], 1);
-  __syncthreads();
-  // exclusive prefix of the 256 bucket counts
-  const int v = cnt[tid];
-  int x = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(x, o);
-    if (lane >= o) x += t;
-  }
-  if (lane == 63) wsum[wv] = x;
-  __syncthreads();
-  int before = 0;
-  for (int k = 0; k < wv; ++k) before += wsum[k];
-  cnt[tid] = before + x - v;
-  __syncthreads();
-  for (int i = tid; i < fd.m; i += 256) wk.perm[fd.mask_base + atomicAdd(&cnt[key(i)], 1)] = i;
+  for (int f = blockIdx.x; f < b.dyn[0]; f += gridDim.x) pool_order_frame(b, wk, f, cnt, wsum);
 }
 
 void launch_pool_order(const Batch& b, const Work& w, hipStream_t st) {
