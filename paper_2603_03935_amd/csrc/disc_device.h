@@ -61,7 +61,7 @@ constexpr int kEdtPartRows = 3;
 // Direct search: a packet of at most 512 rows may be shared by up to
 // kDirSplitMax workgroups when the batch has few packets; their block partial
 // sums go to a global buffer of kDirSplitPackets packets.
-constexpr int kDirSplitMax = 4;
+constexpr int kDirSplitMax = 2;
 constexpr int kDirSplitPackets = 512;
 constexpr int kDirPartFloats = 512 / kBlkRows * kEdtPartRows * 8;  // per packet
 
