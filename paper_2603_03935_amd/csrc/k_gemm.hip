@@ -716,21 +716,33 @@ __global__ __launch_bounds__(256) void k_norm(Batch b, Work wk) {
   float4 v[4];  // E <= 1024: at most 4 chunks of 4 columns per lane
   float ss = 0.f;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int c = lane * 4 + 256 * k;
-    v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (c >= E) continue;
-    if (S == 1) {
-      v[k] = *reinterpret_cast<const float4*>(o + c);
-    } else {
-      for (int grp = 0; grp < ngr; ++grp) {
-        const float4 q = *reinterpret_cast<const float4*>(wk.qpart + ((int64_t)grp * b.M + g) * E + c);
-        v[k].x += q.x;
-        v[k].y += q.y;
-        v[k].z += q.z;
-        v[k].w += q.w;
+  for (int k = 0; k < 4; ++k) v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (S == 1) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (lane * 4 + 256 * k < E) v[k] = *reinterpret_cast<const float4*>(o + lane * 4 + 256 * k);
+  } else {
+    // group sums added in group order; the four chunks of a group load together
+    for (int grp = 0; grp < ngr; ++grp) {
+      const float* qp = wk.qpart + ((int64_t)grp * b.M + g) * E;
+      float4 q[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        q[k] = lane * 4 + 256 * k < E ? *reinterpret_cast<const float4*>(qp + lane * 4 + 256 * k)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        v[k].x += q[k].x;
+        v[k].y += q[k].y;
+        v[k].z += q[k].z;
+        v[k].w += q[k].w;
       }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = lane * 4 + 256 * k;
+    if (c >= E) continue;
     ss += v[k].x * v[k].x;
     ss += v[k].y * v[k].y;
     ss += v[k].z * v[k].z;
