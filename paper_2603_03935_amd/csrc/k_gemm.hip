@@ -395,15 +395,16 @@ void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t s
 }
 
 // ---------------------------------------------------------------------------
-// projection: tile 32 rows x 128 columns (4 wavefronts of 32 x 32), K = C in
-// groups of kProjKG channels.  grid: (row tiles x S, E / 128).  With S = 1 the
-// workgroup writes the unnormalised rows; otherwise each writes its groups'
-// sums to qpart and k_norm adds them in group order.
+// projection with FP32 operands: tile 32 rows x 128 columns (4 wavefronts of
+// 32 x 32, v_mfma_f32_32x32x2f32), K = C in groups of kProjKG channels.  grid:
+// (row tiles x S, E / 128).  With S = 1 the workgroup writes the
+// unnormalised rows; otherwise each writes its groups' sums to qpart and
+// k_norm adds them in group order.  (BF16 operands: k_proj_bf16.)  PBF16: P
+// is stored as BF16 (widened exactly).
 // ---------------------------------------------------------------------------
-template <int BF16, int PBF16>
+template <int PBF16>
 __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj) {
-  constexpr int BK = BF16 ? 32 : 16;
-  constexpr int AS = BK + 8;
+  constexpr int BK = 16;
   const int C = b.C, E = b.E, S = b.proj_split;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int rt = blockIdx.x / S, sidx = blockIdx.x - rt * S;
@@ -414,66 +415,42 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
   const int per = (ngr + S - 1) / S;
   const int ga = sidx * per, gb = min(ngr, ga + per);
   const int kstart = ga * kProjKG, kstop = min(C, gb * kProjKG);
-  __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? 32 * AS : 1];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? 128 * AS : 1];
-  __shared__ float As32[BF16 ? 1 : 32 * (BK + 1)];
-  __shared__ __attribute__((aligned(16))) float Bs32[BF16 ? 1 : BK * 128];
+  __shared__ float As32[32 * (BK + 1)];
+  __shared__ __attribute__((aligned(16))) float Bs32[BK * 128];
 
   const floatx16 zero16 = {};
   floatx16 total = zero16, acc = zero16;
 
-  // A loaders: BF16 32 rows x 32 k (4 per thread), FP32 32 rows x 16 k (2 per thread)
-  const int ar = tid >> 3, ak = BF16 ? (tid & 7) * 4 : (tid & 7) * 2;
+  // A loaders: 32 rows x 16 k (2 per thread); B loaders: [k][col] (k tid >> 4, 8 columns)
+  const int ar = tid >> 3, ak = (tid & 7) * 2;
   const int ga_row = gbase + ar;
-  // B loaders: BF16 k-packed (column tid & 127, 16 k at 16 * (tid >> 7)); FP32 [k][col] (k tid >> 4, 8 cols)
-  const int bc = tid & 127, bkk = (tid >> 7) * 16;
   const int bk32 = tid >> 4, bc32 = (tid & 15) * 8;
-  uint2 ra16 = make_uint2(0, 0);
   float2 ra32 = make_float2(0.f, 0.f);
-  uint16_t rb16[16];
   float rb32[8];
 
   auto fetch = [&](int k0) {
-    if (BF16) {
-      ra16 = ga_row < M ? *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(wk.X) + (int64_t)ga_row * C + k0 + ak)
-                        : make_uint2(0, 0);
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int64_t off = (int64_t)(k0 + bkk + j) * E + c0 + bc;
-        rb16[j] = PBF16 ? reinterpret_cast<const uint16_t*>(proj)[off] : f2bf(reinterpret_cast<const float*>(proj)[off]);
+    ra32 = ga_row < M ? *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(wk.X) + (int64_t)ga_row * C + k0 + ak)
+                      : make_float2(0.f, 0.f);
+    const int64_t off = (int64_t)(k0 + bk32) * E + c0 + bc32;
+    if (PBF16) {
+      const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(proj) + off);
+      const uint32_t v[4] = {a.x, a.y, a.z, a.w};
+      for (int j = 0; j < 4; ++j) {
+        rb32[2 * j] = bf2f((uint16_t)(v[j] & 0xFFFFu));
+        rb32[2 * j + 1] = bf2f((uint16_t)(v[j] >> 16));
       }
     } else {
-      ra32 = ga_row < M ? *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(wk.X) + (int64_t)ga_row * C + k0 + ak)
-                        : make_float2(0.f, 0.f);
-      const int64_t off = (int64_t)(k0 + bk32) * E + c0 + bc32;
-      if (PBF16) {
-        const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(proj) + off);
-        const uint32_t v[4] = {a.x, a.y, a.z, a.w};
-        for (int j = 0; j < 4; ++j) {
-          rb32[2 * j] = bf2f((uint16_t)(v[j] & 0xFFFFu));
-          rb32[2 * j + 1] = bf2f((uint16_t)(v[j] >> 16));
-        }
-      } else {
-        const float4* q = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(proj) + off);
-        const float4 a = q[0], c = q[1];
-        rb32[0] = a.x; rb32[1] = a.y; rb32[2] = a.z; rb32[3] = a.w;
-        rb32[4] = c.x; rb32[5] = c.y; rb32[6] = c.z; rb32[7] = c.w;
-      }
+      const float4* q = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(proj) + off);
+      const float4 a = q[0], c = q[1];
+      rb32[0] = a.x; rb32[1] = a.y; rb32[2] = a.z; rb32[3] = a.w;
+      rb32[4] = c.x; rb32[5] = c.y; rb32[6] = c.z; rb32[7] = c.w;
     }
   };
   auto stage = [&]() {
-    if (BF16) {
-      *reinterpret_cast<uint2*>(&As16[ar * AS + ak]) = ra16;
-      uint4 lo = make_uint4(rb16[0] | (rb16[1] << 16), rb16[2] | (rb16[3] << 16), rb16[4] | (rb16[5] << 16), rb16[6] | (rb16[7] << 16));
-      uint4 hi = make_uint4(rb16[8] | (rb16[9] << 16), rb16[10] | (rb16[11] << 16), rb16[12] | (rb16[13] << 16), rb16[14] | (rb16[15] << 16));
-      *reinterpret_cast<uint4*>(&Bs16[bc * AS + bkk]) = lo;
-      *reinterpret_cast<uint4*>(&Bs16[bc * AS + bkk + 8]) = hi;
-    } else {
-      As32[ar * (BK + 1) + ak] = ra32.x;
-      As32[ar * (BK + 1) + ak + 1] = ra32.y;
-      *reinterpret_cast<float4*>(&Bs32[bk32 * 128 + bc32]) = make_float4(rb32[0], rb32[1], rb32[2], rb32[3]);
-      *reinterpret_cast<float4*>(&Bs32[bk32 * 128 + bc32 + 4]) = make_float4(rb32[4], rb32[5], rb32[6], rb32[7]);
-    }
+    As32[ar * (BK + 1) + ak] = ra32.x;
+    As32[ar * (BK + 1) + ak + 1] = ra32.y;
+    *reinterpret_cast<float4*>(&Bs32[bk32 * 128 + bc32]) = make_float4(rb32[0], rb32[1], rb32[2], rb32[3]);
+    *reinterpret_cast<float4*>(&Bs32[bk32 * 128 + bc32 + 4]) = make_float4(rb32[4], rb32[5], rb32[6], rb32[7]);
   };
   const int lr = lane & 31, lk = lane >> 5;
   const int col = c0 + 32 * wv + lr;
@@ -500,20 +477,11 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
     stage();
     __syncthreads();
     if (k0 + BK < kstop) fetch(k0 + BK);
-    if (BF16) {
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 16) {
-        const u16x8 av = *reinterpret_cast<const u16x8*>(&As16[lr * AS + kk + 8 * lk]);
-        const u16x8 bv = *reinterpret_cast<const u16x8*>(&Bs16[(32 * wv + lr) * AS + kk + 8 * lk]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
-      }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 2) {
-        const float a = As32[lr * (BK + 1) + kk + lk];
-        const float bb = Bs32[(kk + lk) * 128 + 32 * wv + lr];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc, 0, 0, 0);
-      }
+    for (int kk = 0; kk < BK; kk += 2) {
+      const float a = As32[lr * (BK + 1) + kk + lk];
+      const float bb = Bs32[(kk + lk) * 128 + 32 * wv + lr];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc, 0, 0, 0);
     }
     __syncthreads();
   }
@@ -543,9 +511,10 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
 // wavefronts of 64 x 64 (2 x 2 MFMA 32x32x16 tiles each).  A = X rows (k
 // contiguous), B = a k-packed copy of P ([C/8][E][8], written by
 // k_pack_proj: 8 consecutive k of one column in 16 bytes), both staged in LDS
-// as [row][k] / [column][k] so every load is 16 bytes.  The MFMA, its k
-// order within a group and the K groups are those of k_proj, so the result is
-// the same bits.
+// as [row][k] / [column][k] so every load is 16 bytes.  Each element adds
+// its k in fixed order within fixed K groups (kProjKG channels) and the group
+// sums in group order, whether one workgroup runs the whole K or the groups
+// are split over several (then k_norm adds them): the same bits either way.
 // ---------------------------------------------------------------------------
 template <int PBF16>
 __global__ __launch_bounds__(256) void k_pack_proj(const void* proj, int C, int E, uint4* ppack) {
@@ -771,8 +740,8 @@ void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16,
     hipLaunchKernelGGL(k_proj_bf16, dim3((b.M + 127) / 128 * b.proj_split, b.E / 128), block, 0, st, b, w);
   } else {
     const dim3 grid((b.M + 31) / 32 * b.proj_split, b.E / 128);
-    if (proj_bf16) hipLaunchKernelGGL((k_proj<0, 1>), grid, block, 0, st, b, w, proj);
-    else hipLaunchKernelGGL((k_proj<0, 0>), grid, block, 0, st, b, w, proj);
+    if (proj_bf16) hipLaunchKernelGGL((k_proj<1>), grid, block, 0, st, b, w, proj);
+    else hipLaunchKernelGGL((k_proj<0>), grid, block, 0, st, b, w, proj);
   }
   hipLaunchKernelGGL(k_norm, dim3((b.M + 3) / 4), dim3(256), 0, st, b, w);
 }
