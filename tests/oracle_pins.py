@@ -284,6 +284,27 @@ def pin_pool_uniform_mean(orc, seed=10):
         assert np.allclose(res["pooled"][i], f[s].sum(axis=0) / len(s), rtol=1e-13, atol=1e-13), "uniform weights must give the mean"
 
 
+def pin_pool_zero_weight_row(orc, seed=14):
+    """Given weights (the stage entry point): an all-zero weight row has no
+    weighted mean (Sec. III-C divides by the weight sum), so it gives a zero
+    output row, status 1 (empty) and a zero pooled row; the rows around it keep
+    their own weighted means, normalised projections and status 0."""
+    rng = np.random.default_rng(seed)
+    G, C, E = 12, 5, 4
+    f = rng.normal(size=(G, C))
+    P = rng.normal(size=(C, E))
+    wts = rng.uniform(0.5, 2.0, size=(3, G))
+    wts[1] = 0.0
+    res = orc.pool_project(f, wts, P)
+    assert res["status"].tolist() == [0, 1, 0], "a zero weight row is status 1, the others 0"
+    assert not res["out"][1].any() and not res["pooled"][1].any(), "a zero weight row gives zero rows"
+    for i in (0, 2):
+        F = (wts[i][:, None] * f).sum(axis=0) / wts[i].sum()
+        assert np.allclose(res["pooled"][i], F, rtol=1e-13, atol=1e-13), "neighbouring rows keep their weighted mean"
+        y = F @ P
+        assert np.allclose(res["out"][i], y / np.sqrt((y * y).sum()), rtol=1e-12, atol=1e-13)
+
+
 def pin_eps_cancels(orc, seed=11):
     rng = np.random.default_rng(seed)
     h, w, patch, C, E = 64, 64, 16, 8, 8
@@ -563,6 +584,7 @@ ALL_PINS = [
     ("pool_constant_on_support", pin_pool_constant_on_support),
     ("pool_single_patch", pin_pool_single_patch),
     ("pool_uniform_mean", pin_pool_uniform_mean),
+    ("pool_zero_weight_row", pin_pool_zero_weight_row),
     ("eps_cancels", pin_eps_cancels),
     ("two_valued_rectangle", pin_two_valued_rectangle),
     ("output_geometry", pin_output_geometry),

@@ -57,6 +57,11 @@ MUTANTS = [
     ("sem_not_rectified", "if (sem < 0.0) sem = 0.0;", "(void)0;"),
     ("dist_not_affine", "const double dist = 0.5 + 0.5 * dbar[i];", "const double dist = dbar[i];"),
     ("fuse_ties_to_last", "if (q[i] > map_q[t]) {", "if (q[i] >= map_q[t]) {"),
+    ("zero_weight_row_status", "      st = 1;\n    } else {\n      st = pool_project_row(f, G, C, wr, Z",
+     "      st = 2;\n    } else {\n      st = pool_project_row(f, G, C, wr, Z"),
+    ("zero_weight_row_stale_pooled",
+     "    if (Z == 0.0) {\n      for (int32_t j = 0; j < E; ++j) out[(int64_t)i * E + j] = 0.0;\n      for (int32_t c = 0; c < C; ++c) F[c] = 0.0;",
+     "    if (Z == 0.0) {\n      for (int32_t j = 0; j < E; ++j) out[(int64_t)i * E + j] = 0.0;"),
 ]
 
 
