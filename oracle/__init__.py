@@ -49,13 +49,14 @@ def _declare(lib):
                                       vp, vp, vp, vp, vp]
     lib.disc_oracle_pool_project.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp]
     lib.disc_oracle_query_topk.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp, vp]
+    lib.disc_oracle_query_heatmap.argtypes = [vp, i32, i32, vp, i32, vp, i32, dbl, vp]
     lib.disc_oracle_mask_dbar.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, vp]
     lib.disc_oracle_angle_score.argtypes = [vp, vp, vp, i32, vp]
     lib.disc_oracle_view_quality.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, dbl, vp, vp]
     lib.disc_oracle_fuse.argtypes = [vp, vp, vp, i32, i32, vp, vp, i32, vp]
     for f in (lib.disc_oracle_edt_sq, lib.disc_oracle_edt_sq_batch, lib.disc_oracle_spatial_weights,
               lib.disc_oracle_token_stats, lib.disc_oracle_embed, lib.disc_oracle_pool_project,
-              lib.disc_oracle_query_topk, lib.disc_oracle_mask_dbar, lib.disc_oracle_angle_score,
+              lib.disc_oracle_query_topk, lib.disc_oracle_query_heatmap, lib.disc_oracle_mask_dbar, lib.disc_oracle_angle_score,
               lib.disc_oracle_view_quality, lib.disc_oracle_fuse):
         f.restype = ctypes.c_int
     return lib
@@ -163,6 +164,18 @@ class Oracle:
         _check(self.lib.disc_oracle_query_topk(_p(emb), m, _p(text), q, e, k, _p(sim), _p(scores), _p(idx)))
         return {"sim": sim, "scores": scores, "idx": idx}
 
+    def query_heatmap(self, f: np.ndarray, P: np.ndarray, text: np.ndarray, eps: float = 1e-6) -> np.ndarray:
+        """R-HEAT: heat [q][G] = D_p cos(text_j, f_p^T P) for tokens f [G][C] (doubles)."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        text = np.ascontiguousarray(text, dtype=np.float64)
+        G, C = f.shape
+        E = P.shape[1]
+        q = text.shape[0]
+        heat = np.zeros((q, G))
+        _check(self.lib.disc_oracle_query_heatmap(_p(f), G, C, _p(P), E, _p(text), q, eps, _p(heat)))
+        return heat
+
     def mask_dbar(self, bits: np.ndarray, w: int, patch: int, D: np.ndarray):
         """R-Q: (Dbar [m], area [m]) of each mask given the frame's D [G]."""
         bits = np.ascontiguousarray(bits)
@@ -257,6 +270,10 @@ def pool_project(f, wts, P):
 
 def query_topk(emb, text, k):
     return get().query_topk(emb, text, k)
+
+
+def query_heatmap(f, P, text, eps=1e-6):
+    return get().query_heatmap(f, P, text, eps)
 
 
 def mask_dbar(bits, w, patch, D):

@@ -373,6 +373,45 @@ int disc_oracle_query_topk(const double* emb, int32_t m, const double* text, int
   return 0;
 }
 
+/* R-HEAT: weighted dense similarity of one text query with every patch
+ * (Sec. III-C, the feature-similarity figure): the patch token projected into
+ * the embedding space, y_p = f_p^T P, compared with t_j by cosine similarity
+ * and weighted by the patch's distinctiveness D_p of Eq. (1). */
+int disc_oracle_query_heatmap(const double* f, int32_t G, int32_t C, const double* P, int32_t E,
+                              const double* text, int32_t q, double eps, double* heat) {
+  if (!f || !P || !text || !heat || G <= 0 || C <= 0 || E <= 0 || q < 0) return -1;
+  double* D = (double*)malloc(sizeof(double) * (size_t)G);
+  double* y = (double*)malloc(sizeof(double) * (size_t)E);
+  if (!D || !y) {
+    free(D); free(y);
+    return -1;
+  }
+  if (disc_oracle_token_stats(f, G, C, eps, NULL, NULL, D)) {
+    free(D); free(y);
+    return -1;
+  }
+  for (int32_t p = 0; p < G; ++p) {
+    /* y_p = f_p^T P */
+    for (int32_t k = 0; k < E; ++k) y[k] = 0.0;
+    for (int32_t c = 0; c < C; ++c) {
+      const double fc = f[(int64_t)p * C + c];
+      const double* Pc = P + (int64_t)c * E;
+      for (int32_t k = 0; k < E; ++k) y[k] += fc * Pc[k];
+    }
+    const double ny = norm2(y, E);
+    for (int32_t j = 0; j < q; ++j) {
+      const double* t = text + (int64_t)j * E;
+      const double nt = norm2(t, E);
+      double d = 0.0;
+      for (int32_t k = 0; k < E; ++k) d += t[k] * y[k];
+      heat[(int64_t)j * G + p] = (nt > 0.0 && ny > 0.0) ? D[p] * (d / (nt * ny)) : 0.0;
+    }
+  }
+  free(D);
+  free(y);
+  return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* View quality and fusion (R-Q, R-FUSE)                                */
 /* ------------------------------------------------------------------ */

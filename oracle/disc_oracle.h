@@ -32,6 +32,10 @@
  *           embedding t and an instance embedding y is cos(t, y) (0 when
  *           either is the zero vector); a query returns the k instances of
  *           highest similarity, higher first, ties to the lower index.
+ *   R-HEAT  weighted similarity heat-map of a text query (Sec. III-C, the
+ *           feature-similarity figure): per patch p, D_p of Eq. (1) times
+ *           cos(t, y_p) with y_p = f_p^T P the patch token projected into the
+ *           embedding space (0 when either vector is zero).
  *   R-Q     view quality (Sec. III-C, Eqs. 2-3): Q = S_size S_angle S_sem
  *           S_dist with S_size = min(lambda |M| / (H W), 1), lambda = 3.3;
  *           S_dist = 0.5 + 0.5 Dbar, Dbar = D of Eq. (1) averaged over the
@@ -105,6 +109,11 @@ int disc_oracle_pool_project(const double* f, int32_t G, int32_t C, const double
  * -inf past m).  emb[m][e], text[q][e]. */
 int disc_oracle_query_topk(const double* emb, int32_t m, const double* text, int32_t q, int32_t e, int32_t k,
                            double* sim, double* scores, int32_t* idx);
+
+/* R-HEAT: heat[q][G] = D_p cos(text_j, f_p^T P) for tokens f[G][C],
+ * projection P[C][E], text[q][E]; D with epsilon eps (Eq. 1). */
+int disc_oracle_query_heatmap(const double* f, int32_t G, int32_t C, const double* P, int32_t E,
+                              const double* text, int32_t q, double eps, double* heat);
 
 /* R-Q: Dbar[m] and area |M| [m] of each mask, given D[G] of the frame. */
 int disc_oracle_mask_dbar(const uint64_t* bits, int32_t m, int32_t h, int32_t w, int32_t patch, int32_t gh,

@@ -448,6 +448,58 @@ def pin_query_bruteforce(orc, seed=31):
     assert r3["idx"][0].tolist() == [0, 1, 2]
 
 
+def pin_heatmap_two_valued(orc, seed=33):
+    """R-HEAT on a two-valued map (k patches u, the rest v, u and v
+    orthogonal) with a permutation projection: a text along the projected u
+    scores D_u (Eq. 1 closed form) on the u patches and 0 on the v patches, a
+    text along minus the projected v scores -D_v there and 0 on u, a zero
+    text scores 0.  A transposed projection, a dropped or inverted D, or a
+    missing norm all break it."""
+    rng = np.random.default_rng(seed)
+    G, C, k = 23, 7, 5
+    u = np.zeros(C); u[1] = 2.0; u[4] = -1.0
+    v = np.zeros(C); v[0] = 3.0; v[2] = 0.5; v[6] = 1.5
+    f = np.tile(v, (G, 1))
+    idx = rng.choice(G, size=k, replace=False)
+    f[idx] = u
+    perm = np.array([3, 6, 0, 5, 1, 2, 4])  # not an involution: P and P^T differ
+    P = np.zeros((C, C))
+    P[np.arange(C), perm] = 1.0
+    yu, yv = u @ P, v @ P
+    eps = 1e-6
+    duv = np.sqrt(((u - v) ** 2).sum())
+    r_u, r_v = (G - k) / G * duv, k / G * duv
+    rbar = (k * r_u + (G - k) * r_v) / G
+    D_u, D_v = r_u / (rbar + eps), r_v / (rbar + eps)
+    text = np.stack([5.0 * yu, -0.25 * yv, np.zeros(C)])
+    h = orc.query_heatmap(f, P, text, eps)
+    isu = np.zeros(G, bool)
+    isu[idx] = True
+    want = np.zeros((3, G))
+    want[0, isu] = D_u
+    want[1, ~isu] = -D_v
+    assert np.allclose(h, want, rtol=1e-12, atol=1e-14), "two-valued heat-map breaks its closed form"
+
+
+def pin_heatmap_invariances(orc, seed=34):
+    """A constant token map has D = 0 everywhere, so its heat-map is 0; the
+    heat-map does not change when a text or the token map is scaled by a
+    positive factor; and with an orthogonal projection Q, (tokens, Q, t)
+    gives the heat-map of (tokens, identity, t Q^T) (cosines are preserved)."""
+    rng = np.random.default_rng(seed)
+    G, C, q = 31, 12, 4
+    f = rng.normal(size=(G, C)) * rng.uniform(0.3, 2.0, size=(G, 1))
+    t = rng.normal(size=(q, C))
+    Q, _ = np.linalg.qr(rng.normal(size=(C, C)))
+    h = orc.query_heatmap(f, Q, t)
+    # the mean of equal values is exact up to rounding, so D is at most ~1e-16 / eps
+    assert np.allclose(orc.query_heatmap(np.tile(f[3], (G, 1)), Q, t), 0.0, atol=1e-8), "constant map must give 0"
+    assert np.allclose(orc.query_heatmap(2.5 * f, Q, 0.3 * t, 1e-6 * 2.5), h, rtol=1e-11, atol=1e-13), "scale"
+    h_id = orc.query_heatmap(f, np.eye(C), t @ Q.T)
+    assert np.allclose(h, h_id, rtol=1e-10, atol=1e-12), "orthogonal projection must preserve the cosines"
+    assert np.all(np.abs(h) <= orc.token_stats(f, 1e-6)[2][None, :] * (1 + 1e-12)), "|heat| <= D"
+
+
 # ---------------------------------------------------------------- view quality and fusion (R-Q, R-FUSE)
 
 def pin_dbar_patch_counts(orc, seed=41):
@@ -591,6 +643,8 @@ ALL_PINS = [
     ("degenerate", pin_degenerate),
     ("decoders", pin_decoders),
     ("query_orthonormal", pin_query_orthonormal),
+    ("heatmap_two_valued", pin_heatmap_two_valued),
+    ("heatmap_invariances", pin_heatmap_invariances),
     ("query_bruteforce", pin_query_bruteforce),
     ("dbar_patch_counts", pin_dbar_patch_counts),
     ("angle_closed_forms", pin_angle_closed_forms),

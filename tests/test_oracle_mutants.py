@@ -46,6 +46,12 @@ MUTANTS = [
      "row[i] = (nt > 0.0 && ny > 0.0) ? d / ny : 0.0;"),
     ("query_ties_to_higher_index", "if (!used[i] && (best < 0 || row[i] > row[best])) best = i;",
      "if (!used[i] && (best < 0 || row[i] >= row[best])) best = i;"),
+    ("heatmap_D_dropped", "heat[(int64_t)j * G + p] = (nt > 0.0 && ny > 0.0) ? D[p] * (d / (nt * ny)) : 0.0;",
+     "heat[(int64_t)j * G + p] = (nt > 0.0 && ny > 0.0) ? (d / (nt * ny)) : 0.0;"),
+    ("heatmap_token_norm_dropped", "heat[(int64_t)j * G + p] = (nt > 0.0 && ny > 0.0) ? D[p] * (d / (nt * ny)) : 0.0;",
+     "heat[(int64_t)j * G + p] = (nt > 0.0 && ny > 0.0) ? D[p] * (d / nt) : 0.0;"),
+    ("heatmap_proj_transposed", "      for (int32_t k = 0; k < E; ++k) y[k] += fc * Pc[k];",
+     "      for (int32_t k = 0; k < E; ++k) y[k] += fc * P[(int64_t)k * C + c];"),
     ("dbar_patch_transposed", "acc += D[(int64_t)(y / patch) * gw + (x / patch)];",
      "acc += D[(int64_t)(x / patch) * gh + (y / patch)];"),
     ("angle_sign", "const double c = -(r[0] * n[0] + r[1] * n[1] + r[2] * n[2]);",
