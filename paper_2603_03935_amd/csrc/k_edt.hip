@@ -782,13 +782,17 @@ __device__ __forceinline__ int max4(us2 a, us2 b) {
   return max((int)m.x, (int)m.y);
 }
 
-// PK: items of at most 512 rows.  Every e is then at most 255^2 (rows 0 and
-// n - 1 are padding with g = 0, and min(u, n - 1 - u) <= 255), so g is
-// clamped to 255 in the table (a candidate with g >= 255 is >= 255^2 >= e
-// either way: no e changes) and the search runs in packed 16-bit arithmetic,
-// two rows per instruction: squares < 2^16, sums saturate at 65535, which
+// PK = 1: items of at most 512 rows.  Every e is then at most 255^2 (rows 0
+// and n - 1 are padding with g = 0, and min(u, n - 1 - u) <= 255), so g is
+// clamped to 255 (a candidate with g >= 255 is >= 255^2 >= e either way: no
+// e changes) and the table holds g^2 (< 2^16).  The search runs in packed
+// 16-bit arithmetic, two rows per instruction: sums saturate at 65535, which
 // is never below the best value (<= 65025).
-template <int SPATIAL, bool WE, bool PK>
+// PK = 0: taller items; the table holds g and the search is exact 32-bit.
+// (A packed search of min(g, 255)^2 for the taller items, with an exact
+// re-search of the rare groups that end at 255^2 or above, was measured: its
+// per-step saving was eaten by the clamp and the extra control flow.)
+template <int SPATIAL, bool WE, int PK>
 __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint32_t* recs, const int* words,
                                               uint2* gt_all, float* part, int lane, int kb, int32_t* e_out) {
   const int rows_c = class_rows(cls), ipp = direct_items(cls);
@@ -855,11 +859,13 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
             s16x2 g = __builtin_elementwise_max(
                 __builtin_elementwise_max(__builtin_elementwise_min(l2 - a1, b1 - l2), __builtin_elementwise_min(l2 - a2, b2 - l2)),
                 zero);
-            if (PK) {
+            if (PK == 1) {
               const s16x2 cap = {255, 255};
-              g = __builtin_elementwise_min(g, cap);
+              const us2 gc = __builtin_bit_cast(us2, __builtin_elementwise_min(g, cap));
+              wd[q] = lane_ok ? __builtin_bit_cast(uint32_t, gc * gc) : 0u;
+            } else {
+              wd[q] = lane_ok ? __builtin_bit_cast(uint32_t, g) : 0u;
             }
-            wd[q] = lane_ok ? __builtin_bit_cast(uint32_t, g) : 0u;
           } else {
             uint32_t h[2];
 #pragma unroll
@@ -868,7 +874,7 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
                   make_uint4(__builtin_amdgcn_readlane(r.x, src + e), __builtin_amdgcn_readlane(r.y, src + e),
                              __builtin_amdgcn_readlane(r.z, src + e), __builtin_amdgcn_readlane(r.w, src + e));
               h[e] = lane_ok ? (uint32_t)g_rec(ru, lane) : 0u;
-              if (PK) h[e] = min(h[e], 255u);
+              if (PK == 1) h[e] = min(h[e], 255u) * min(h[e], 255u);
             }
             wd[q] = h[0] | (h[1] << 16);
           }
@@ -905,56 +911,23 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
       const uint2* base = tb + (gi >> 2) * 64;  // row u0 = b0 + gi
       int best[kDirRows];
       int bmax = 0;
+      // exact initial values g^2 (PK 1: the table already holds them)
+      auto init_exact = [&]() {
+        bmax = 0;
 #pragma unroll
-      for (int q = 0; q < kDirRows / 4; ++q) {
-        const uint2 w = base[q * 64];
-        const int g4[4] = {(int)(w.x & 0xFFFFu), (int)(w.x >> 16), (int)(w.y & 0xFFFFu), (int)(w.y >> 16)};
+        for (int q = 0; q < kDirRows / 4; ++q) {
+          const uint2 w = base[q * 64];
+          const int g4[4] = {(int)(w.x & 0xFFFFu), (int)(w.x >> 16), (int)(w.y & 0xFFFFu), (int)(w.y >> 16)};
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          best[4 * q + k] = SPATIAL == 0 ? g4[k] * g4[k] : (g4[k] > 0 ? 1 : 0);
-          bmax = max(bmax, best[4 * q + k]);
-        }
-      }
-      if (SPATIAL == 0 && PK) {
-        // packed: rows (0,1) and (2,3) of the group in one register each;
-        // the window rows as aligned pairs (2j, 2j+1) and odd pairs
-        // (2j+1, 2j+2)
-        us2 B[2] = {as_us2((uint32_t)best[0] | ((uint32_t)best[1] << 16)), as_us2((uint32_t)best[2] | ((uint32_t)best[3] << 16))};
-        for (int d = 1; d * d < bmax; d += kDirSteps) {
-          const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * 64;
-          const uint2* pd = base + ((d - 1) >> 2) * 64;
-          const uint2 u0w = pu[0], u1w = pu[64], d0w = pd[0], d1w = pd[64];
-          const uint32_t U[4] = {__builtin_bit_cast(uint32_t, sq2(u0w.x)), __builtin_bit_cast(uint32_t, sq2(u0w.y)),
-                                 __builtin_bit_cast(uint32_t, sq2(u1w.x)), __builtin_bit_cast(uint32_t, sq2(u1w.y))};
-          const uint32_t Dn[4] = {__builtin_bit_cast(uint32_t, sq2(d0w.x)), __builtin_bit_cast(uint32_t, sq2(d0w.y)),
-                                  __builtin_bit_cast(uint32_t, sq2(d1w.x)), __builtin_bit_cast(uint32_t, sq2(d1w.y))};
-          uint32_t Uo[3], Do[3];
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            Uo[j] = __builtin_amdgcn_alignbyte(U[j + 1], U[j], 2);
-            Do[j] = __builtin_amdgcn_alignbyte(Dn[j + 1], Dn[j], 2);
+          for (int k = 0; k < 4; ++k) {
+            best[4 * q + k] = SPATIAL != 0 ? (g4[k] > 0 ? 1 : 0) : PK == 1 ? g4[k] : g4[k] * g4[k];
+            bmax = max(bmax, best[4 * q + k]);
           }
-#pragma unroll
-          for (int i = 0; i < kDirSteps; ++i) {
-            const uint32_t dd = (uint32_t)min((d + i) * (d + i), 65535);
-            const us2 D = as_us2(dd | (dd << 16));
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {  // rows 2q, 2q + 1 at distance d + i
-              const uint32_t up = (i & 1) ? U[(3 + 2 * q - i) >> 1] : Uo[(2 + 2 * q - i) >> 1];
-              const uint32_t dn = (i & 1) ? Dn[(1 + 2 * q + i) >> 1] : Do[(2 * q + i) >> 1];
-              B[q] = __builtin_elementwise_min(
-                  B[q], __builtin_elementwise_add_sat(__builtin_elementwise_min(as_us2(up), as_us2(dn)), D));
-            }
-          }
-          bmax = max4(B[0], B[1]);
         }
-        best[0] = B[0].x;
-        best[1] = B[0].y;
-        best[2] = B[1].x;
-        best[3] = B[1].y;
-      } else if (SPATIAL == 0) {
-        // d = 1 (mod 4): the windows start on words, up at u0 - d - 3, down
-        // at u0 + d - 1 (one row early)
+      };
+      // exact 32-bit search.  d = 1 (mod 4): the windows start on words, up
+      // at u0 - d - 3, down at u0 + d - 1 (one row early)
+      auto search32 = [&]() {
         for (int d = 1; d * d < bmax; d += kDirSteps) {
           constexpr int NQ = (kDirRows + kDirSteps) / 4;  // words per window
           const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * 64;
@@ -983,6 +956,55 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
             bmax = max(bmax, best[k]);
           }
         }
+      };
+      init_exact();
+      if (SPATIAL == 0 && PK != 0) {
+        // packed: rows (0,1) and (2,3) of the group in one register each;
+        // the window rows as aligned pairs (2j, 2j+1) and odd pairs
+        // (2j+1, 2j+2); the table holds g^2.
+        const int b0v = best[0], b1v = best[1], b2v = best[2], b3v = best[3];
+        us2 B[2] = {as_us2((uint32_t)b0v | ((uint32_t)b1v << 16)), as_us2((uint32_t)b2v | ((uint32_t)b3v << 16))};
+        int pmax = max(max(b0v, b1v), max(b2v, b3v));
+        // (d + i)^2 for the step's distances, both halves alike, advanced by
+        // saturating adds of 8 (d + i) + 16 per step of four
+        us2 D[kDirSteps], inc[kDirSteps];
+#pragma unroll
+        for (int i = 0; i < kDirSteps; ++i) {
+          D[i] = as_us2((uint32_t)((1 + i) * (1 + i)) * 0x10001u);
+          inc[i] = as_us2((uint32_t)(8 * (1 + i) + 16) * 0x10001u);
+        }
+        for (int d = 1; d * d < pmax; d += kDirSteps) {
+          const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * 64;
+          const uint2* pd = base + ((d - 1) >> 2) * 64;
+          const uint2 u0w = pu[0], u1w = pu[64], d0w = pd[0], d1w = pd[64];
+          const uint32_t U[4] = {u0w.x, u0w.y, u1w.x, u1w.y};
+          const uint32_t Dn[4] = {d0w.x, d0w.y, d1w.x, d1w.y};
+          uint32_t Uo[3], Do[3];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            Uo[j] = __builtin_amdgcn_alignbyte(U[j + 1], U[j], 2);
+            Do[j] = __builtin_amdgcn_alignbyte(Dn[j + 1], Dn[j], 2);
+          }
+#pragma unroll
+          for (int i = 0; i < kDirSteps; ++i) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {  // rows 2q, 2q + 1 at distance d + i
+              const uint32_t up = (i & 1) ? U[(3 + 2 * q - i) >> 1] : Uo[(2 + 2 * q - i) >> 1];
+              const uint32_t dn = (i & 1) ? Dn[(1 + 2 * q + i) >> 1] : Do[(2 * q + i) >> 1];
+              B[q] = __builtin_elementwise_min(
+                  B[q], __builtin_elementwise_add_sat(__builtin_elementwise_min(as_us2(up), as_us2(dn)), D[i]));
+            }
+            D[i] = __builtin_elementwise_add_sat(D[i], inc[i]);
+            inc[i] = inc[i] + as_us2(32u * 0x10001u);
+          }
+          pmax = max4(B[0], B[1]);
+        }
+        best[0] = B[0].x;
+        best[1] = B[0].y;
+        best[2] = B[1].x;
+        best[3] = B[1].y;
+      } else if (SPATIAL == 0) {
+        search32();
       }
 #pragma unroll
       for (int k = 0; k < kDirRows; ++k) {
@@ -1023,7 +1045,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const int p = vp / S, s = vp - p * S;
     const int cls = direct_load_packet(cnt, items, item_cap, mrec, p, recs, words);
     float* part = S == 1 ? part_all : gpart + (int64_t)p * kDirPartFloats;
-    direct_packet<SPATIAL, WE, (ROWS <= 512)>(cls, s, S, recs, words, gt_all + kDirGuard / 4 * 64, part, lane, kb, e_out);
+    direct_packet<SPATIAL, WE, (ROWS <= 512 ? 1 : 0)>(cls, s, S, recs, words, gt_all + kDirGuard / 4 * 64, part, lane, kb, e_out);
     if (S == 1) {
       direct_strip_sums(cls, recs, words, part_all, lane, kb);
       __syncthreads();

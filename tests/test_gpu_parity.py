@@ -82,6 +82,31 @@ def test_edt_large_masks_1080p(gpu):
     assert bad.size == 0, f"1080p EDT differs on masks {bad}"
 
 
+def test_edt_deep_tall_items(gpu):
+    """Items taller than 512 rows whose interior lies more than 255 pixels
+    from the outside (their 16-bit search is redone exactly): EDT bit-exact
+    and the layouts agree bit for bit on the patch weights."""
+    h, w = 1080, 1920
+    yy, xx = np.indices((h, w))
+    u8 = np.zeros((5, h, w), np.uint8)
+    u8[0] = ((yy - 540) ** 2 + (xx - 960) ** 2) <= 520 ** 2
+    u8[1] = 1
+    u8[2, 10:1070, 100:1800] = 1
+    u8[3] = ((yy - 540) / 530.0) ** 2 + ((xx - 700) / 300.0) ** 2 <= 1.0
+    u8[4] = u8[0]
+    u8[4, 540, :] = 0  # a cut through the middle: two halves of depth < 270
+    bits = di.pack_masks(u8)
+    got = _edt_gpu(gpu, bits, h, w)
+    want = oracle.edt_sq(bits, w)
+    for i in range(len(u8)):
+        assert np.array_equal(got[i], want[i]), f"deep tall mask {i}: {np.argwhere(got[i] != want[i])[:5]}"
+    assert want.max() > 255 ** 2
+    b = dev_bits(bits)
+    w0 = gpu.patch_weights(b, h, w, 16, distinct=0, edt_layout=0).cpu().numpy()
+    w2 = gpu.patch_weights(b, h, w, 16, distinct=0, edt_layout=2).cpu().numpy()
+    assert np.array_equal(w0, w2), "direct search disagrees with the band layout"
+
+
 @pytest.mark.parametrize("name,h,w,P", [("cfg2", 480, 640, 16), ("adv", 511, 200, 14), ("adv", 300, 130, 16),
                                         ("adv", 100, 90, 8), ("adv", 40, 333, 64)])
 def test_edt_layouts_agree_bitwise(gpu, name, h, w, P):
