@@ -75,6 +75,18 @@ struct MaskRec {
 };
 
 // One frame of a (possibly ragged) batch, in device memory.
+// OCP e4m3fn code -> float (exact)
+__device__ __forceinline__ float e4m3_to_f32(uint32_t code) {
+  const uint32_t sign = (code & 0x80u) << 24;
+  const uint32_t mag = code & 0x7Fu;
+  if (mag == 0x7Fu) return __builtin_nanf("");
+  if (mag >= 8u) return __uint_as_float(sign | ((mag << 20) + (120u << 23)));
+  const float v = (float)mag * 0x1p-9f;
+  return sign ? -v : v;
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
 struct FrameDesc {
   const void* tokens;     // [G][C] in tok_dtype
   const float* scale;     // [G] for FP8 tokens

@@ -11,17 +11,6 @@
 namespace disc {
 
 
-// OCP e4m3fn code -> float (exact)
-__device__ __forceinline__ float e4m3_to_f32(uint32_t code) {
-  const uint32_t sign = (code & 0x80u) << 24;
-  const uint32_t mag = code & 0x7Fu;
-  if (mag == 0x7Fu) return __builtin_nanf("");
-  if (mag >= 8u) return __uint_as_float(sign | ((mag << 20) + (120u << 23)));
-  const float v = (float)mag * 0x1p-9f;
-  return sign ? -v : v;
-}
-
-__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
 
 // e4m3fn code -> BF16 bits of the same value (exact: e4m3 values are BF16 values)
 __device__ __forceinline__ uint32_t e4m3_to_bf16_bits(uint32_t code) {
@@ -344,6 +333,18 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
   return (uint16_t)((u + 0x7FFFu + lsb) >> 16);  // finite, non-negative weights only
 }
 
+// The term a weight adds to Z, in token-value units: the rounded GEMM operand,
+// divided by the token's scale for FP8 tokens.  A token whose scale is 0 (an
+// all-zero token) adds nothing to the pooled sum, but its weight still counts
+// in Z, as in the FP64 definition: the unscaled weight, rounded like an
+// operand.
+template <int BF16>
+__device__ __forceinline__ float z_term(float wr, float wu, bool fp8, float sc) {
+  if (!fp8) return wr;
+  if (sc != 0.f) return wr / sc;
+  return BF16 ? __uint_as_float((uint32_t)f32_to_bf16_rne(wu) << 16) : wu;
+}
+
 template <int BF16>
 __device__ float write_row(const Batch& b, const Work& wk, const FrameDesc& fd, int64_t rowoff, int pr0, int pr1,
                            int pc0, int pc1, bool use_r, Neu& z, float& ssum) {
@@ -353,12 +354,16 @@ __device__ float write_row(const Batch& b, const Work& wk, const FrameDesc& fd, 
   int pr = threadIdx.x / gw, pc = threadIdx.x % gw;
   const int dpr = 256 / gw, dpc = 256 % gw;
   for (int p = threadIdx.x; p < G; p += 256) {
-    float wv = 0.f;
+    float wv = 0.f, wu = 0.f, sc = 1.f;
     if (pr >= pr0 && pr <= pr1 && pc >= pc0 && pc <= pc1) {
       const float sv = wk.s[rowoff + p];
       ssum += sv;
-      wv = use_r ? sv * r[p] : sv;
-      if (fp8) wv *= fd.scale[p];
+      wu = use_r ? sv * r[p] : sv;
+      wv = wu;
+      if (fp8) {
+        sc = fd.scale[p];
+        wv *= sc;
+      }
     }
     float wr;
     if (BF16) {
@@ -369,7 +374,8 @@ __device__ float write_row(const Batch& b, const Work& wk, const FrameDesc& fd, 
       reinterpret_cast<float*>(wk.W)[rowoff + p] = wv;
       wr = wv;
     }
-    if (wr != 0.f) neu_add(z, fp8 ? wr / fd.scale[p] : wr);
+    const float zt = z_term<BF16>(wr, wu, fp8, sc);
+    if (zt != 0.f) neu_add(z, zt);
     pc += dpc;
     pr += dpr;
     if (pc >= gw) {
@@ -498,8 +504,9 @@ __global__ __launch_bounds__(256) void k_user_weights(Batch b, Work wk, const fl
   __shared__ float red[8];
   Neu z{0.f, 0.f};
   for (int p = threadIdx.x; p < G; p += 256) {
-    float wv = wts[(int64_t)(g - fd.mask_base) * G + p];
-    if (fp8) wv *= fd.scale[p];
+    const float wu = wts[(int64_t)(g - fd.mask_base) * G + p];
+    const float sc = fp8 ? fd.scale[p] : 1.f;
+    const float wv = fp8 ? wu * sc : wu;
     float wr;
     if (BF16) {
       const uint16_t hb = f32_to_bf16_rne(wv);
@@ -509,7 +516,8 @@ __global__ __launch_bounds__(256) void k_user_weights(Batch b, Work wk, const fl
       reinterpret_cast<float*>(wk.W)[rowoff + p] = wv;
       wr = wv;
     }
-    if (wr != 0.f) neu_add(z, fp8 ? wr / fd.scale[p] : wr);
+    const float zt = z_term<BF16>(wr, wu, fp8, sc);
+    if (zt != 0.f) neu_add(z, zt);
   }
   const Neu tot = block_neu(z, red);
   if (threadIdx.x == 0) {

@@ -223,6 +223,37 @@ def test_embed_lowp(gpu, tdtype, pdtype, structured):
     print(f"{tdtype} structured={structured}: min cos {c.min():.7f} median {np.median(c):.7f}")
 
 
+def test_fp8_zero_tokens_pooled(gpu):
+    """All-zero tokens (FP8 scale 0) inside masks: their weight still counts
+    in Z, as in the FP64 definition, so the pooled features (not only the
+    unit embeddings) match the oracle."""
+    h, w, patch, C, E = 200, 264, 16, 256, 256
+    gh, gw = -(-h // patch), -(-w // patch)
+    vals = di.tokens_structured(77, gh, gw, C, "f64", patch).data.reshape(gh * gw, C).copy()
+    zero = [r * gw + c for r in range(3, 8) for c in range(4, 10)]
+    vals[zero] = 0.0
+    tok = di.tokens_from_values(vals.reshape(gh, gw, C), "f8", patch)
+    # a zero scale makes the token exactly zero whatever its codes
+    tok.scale[zero] = 0.0
+    tok.data.reshape(gh * gw, C)[zero] = np.random.default_rng(5).integers(0, 126, (len(zero), C), dtype=np.uint8)
+    u8 = np.zeros((4, h, w), np.uint8)
+    u8[0, 40:130, 50:170] = 1                      # covers the zero block and more
+    u8[1, 48:128, 64:160] = 1                      # inside the zero block
+    u8[2, 20:190, 20:250] = 1                      # a large box around it
+    u8[3] = di.unpack_masks(di.masks_mixed(78, 1, h, w, 0.05, 0.2), w)[0]
+    fr = di.Frame(tok, di.pack_masks(u8), h, w)
+    P = di.projection(79, C, E, "bf16")
+    out = run_frames(gpu, [fr], P, "bf16", pooled=True)[0]
+    ref = oracle_frame(fr, P, "bf16")
+    st = out.status.cpu().numpy()
+    assert np.array_equal(st, ref["status"])
+    ok = ref["status"] == 0
+    pooled = out.pooled.cpu().numpy().astype(np.float64)
+    rel = np.abs(pooled[ok] - ref["pooled"][ok]).max() / np.abs(ref["pooled"][ok]).max()
+    assert rel < 5e-3, f"pooled features with zero tokens: rel err {rel:.3e}"
+    check_embeddings(out.out.cpu().numpy(), st, ref, COS_LOWP, "fp8 zero tokens")
+
+
 def test_embed_modes_fp32(gpu):
     wl = di.workload("cfg2")
     fr = wl.frames[0]
