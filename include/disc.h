@@ -212,6 +212,23 @@ disc_status disc_pack_masks(const uint8_t* u8, int32_t m, int32_t h, int32_t w, 
 disc_status disc_query_topk(const float* emb, int32_t m, const void* text, int32_t text_dtype, int32_t q, int32_t e,
                             int32_t k, float* sim, float* scores, int32_t* idx, void* stream);
 
+/* Weighted similarity heat-map of text queries over one frame's patches
+ * (arXiv 2603.03935, Sec. III-C, the feature-similarity figure: the dense
+ * similarity of a text query with the patch features, weighted by the
+ * distinctiveness map):
+ *   heat[j][p] = D_p * cos(text_j, y_p),   y_p = f_p^T P,
+ * f_p the patch token (as for disc_embed_masks: F32, BF16 or FP8 + scale),
+ * P the projection [c][e], D_p of Eq. (1) with epsilon eps; 0 where text_j
+ * or y_p is the zero vector.  |heat| <= D_p.
+ *   text [q][e] (text_dtype DISC_F32 or DISC_BF16), heat [q][gh*gw] FP32
+ *   written, patch-row-major.  FP32 arithmetic (tokens and P widened
+ *   exactly), FP32 accumulation.
+ * Device pointers, 16-byte aligned; 0 <= q <= 2^20 (0: no-op); eps >= 0.
+ * Invalid arguments: nothing is enqueued, DISC_ERR_* is returned.
+ * Asynchronous on `stream`. */
+disc_status disc_query_heatmap(const disc_tokens* tokens, const disc_proj* proj, const void* text, int32_t text_dtype,
+                               int32_t q, float eps, float* heat, void* stream);
+
 /* ---- view quality and fusion (consumers of the embeddings) ---- */
 
 /* View quality of each observation (arXiv 2603.03935, Sec. III-C, Eqs. 2-3):

@@ -42,7 +42,7 @@ EXPORTS = [
     "disc_trace_enable", "disc_trace_select", "disc_trace_reset", "disc_trace_read", "disc_trace_stage_name",
     "disc_server_config_default", "disc_server_create", "disc_server_submit", "disc_server_poll",
     "disc_server_wait", "disc_server_drain", "disc_server_get_stats", "disc_server_destroy",
-    "disc_query_topk", "disc_view_quality", "disc_angle_score", "disc_fuse",
+    "disc_query_topk", "disc_query_heatmap", "disc_view_quality", "disc_angle_score", "disc_fuse",
     "disc_backproject_count", "disc_backproject", "disc_dbscan_denoise", "disc_voxelize", "disc_voxel_overlap",
 ]
 STAGES = ["scan", "token_stats", "edt", "weights", "pool", "proj"]
@@ -150,6 +150,7 @@ def load(path: str = LIB_PATH):
     lib.disc_pool_project.argtypes = [P(Tokens), vp, i32, P(Proj), P(Out), i32, vp]
     lib.disc_pack_masks.argtypes = [vp, i32, i32, i32, vp, vp]
     lib.disc_query_topk.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp, vp, vp, vp]
+    lib.disc_query_heatmap.argtypes = [P(Tokens), P(Proj), vp, i32, i32, ctypes.c_float, vp, vp]
     lib.disc_view_quality.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, ctypes.c_float, vp, vp, vp]
     lib.disc_angle_score.argtypes = [vp, vp, i32, vp, i32, vp, vp]
     lib.disc_fuse.argtypes = [vp, vp, vp, i32, i32, vp, vp, i32, vp, vp]
@@ -187,7 +188,7 @@ def load(path: str = LIB_PATH):
     lib.disc_abi_version.restype = i32
     for name in ("disc_embed_masks", "disc_embed_masks_ex", "disc_embed_frames", "disc_release_workspace",
                  "disc_edt_sq", "disc_patch_weights", "disc_token_stats", "disc_pool_project", "disc_pack_masks",
-                 "disc_query_topk", "disc_view_quality", "disc_angle_score", "disc_fuse",
+                 "disc_query_topk", "disc_query_heatmap", "disc_view_quality", "disc_angle_score", "disc_fuse",
                  "disc_backproject_count", "disc_backproject", "disc_dbscan_denoise", "disc_voxelize",
                  "disc_voxel_overlap"):
         getattr(lib, name).restype = ctypes.c_int
@@ -434,6 +435,21 @@ def query_topk(emb, text, k: int, stream=None):
     _check(load().disc_query_topk(_ptr(emb), m, _ptr(text), tdt, q, e, k, _ptr(sim), _ptr(scores), _ptr(idx),
                                   _stream_handle(stream)))
     return scores, idx, sim[:, :m]
+
+
+def query_heatmap(tokens, proj, text, patch: int, scale=None, eps: float = 1e-6, stream=None):
+    """disc_query_heatmap: heat [q][gh][gw] = D_p cos(text_j, f_p^T P)."""
+    lib = load()
+    torch = _torch()
+    gh, gw = tokens.shape[0], tokens.shape[1]
+    q = text.shape[0]
+    heat = torch.empty((q, gh, gw), dtype=torch.float32, device=tokens.device)
+    tk = make_tokens(tokens, patch, scale)
+    pj = make_proj(proj)
+    tdt = DISC_BF16 if text.dtype == torch.bfloat16 else DISC_F32
+    _check(lib.disc_query_heatmap(ctypes.byref(tk), ctypes.byref(pj), _ptr(text), tdt, q, eps, _ptr(heat),
+                                  _stream_handle(stream)))
+    return heat
 
 
 def view_quality(area, dbar, emb, g, img_h: int, img_w: int, angle=None, lam: float = 3.3, stream=None):

@@ -173,6 +173,7 @@ Layout make_layout(const Shape& s) {
   L.ppack = take(s.gemm_bf16 ? 2 * (size_t)s.C * s.E : 0);
   L.edt_part = take(4 * (size_t)kDirSplitPackets * kDirPartFloats);
   L.tkp = take(s.gemm_bf16 ? (size_t)s.tkp_elems * s.tkp_esize : 0);
+  L.extra = take((size_t)s.extra_bytes);
   L.total = off;
   return L;
 }
@@ -836,6 +837,55 @@ disc_status disc_token_stats(const disc_tokens* tokens, float eps, float* mean, 
   if (mean) launch_copy_f32(w.mean, mean, tokens->c, cx.st);
   if (r) launch_copy_f32(w.r, r, G, cx.st);
   if (D) launch_d_from_r(w.r, G, eps, D, cx.st);
+  if ((st = check_launch(who))) return st;
+  return ok();
+}
+
+disc_status disc_query_heatmap(const disc_tokens* tokens, const disc_proj* proj, const void* text, int32_t text_dtype,
+                               int32_t q, float eps, float* heat, void* stream) {
+  const char* who = "disc_query_heatmap";
+  disc_status st;
+  if ((st = check_tokens(tokens, who))) return st;
+  if ((st = check_proj(proj, tokens->c, who))) return st;
+  if (q < 0) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: negative query count", who);
+  if (q > (1 << 20)) return fail(DISC_ERR_LIMIT, "%s: at most 2^20 queries per call", who);
+  if (text_dtype != DISC_F32 && text_dtype != DISC_BF16)
+    return fail(DISC_ERR_UNSUPPORTED_DTYPE, "%s: text dtype must be F32 or BF16", who);
+  if (!(eps >= 0.f)) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: eps must be >= 0", who);
+  if (q == 0) return ok();
+  if (!text || !heat) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: text and heat must not be NULL", who);
+  if (!aligned16(text) || !aligned16(heat)) return fail(DISC_ERR_ALIGNMENT, "%s: text and heat must be 16-byte aligned", who);
+  const int G = tokens->gh * tokens->gw, C = tokens->c, E = proj->e;
+  FrameIn f;
+  f.tokens = tokens->data;
+  f.scale = tokens->scale;
+  f.gh = tokens->gh;
+  f.gw = tokens->gw;
+  f.patch = tokens->patch;
+  f.h = tokens->gh * tokens->patch;
+  f.w = tokens->gw * tokens->patch;
+  f.m = 0;
+  Plan p;
+  build_plan({f}, C, 128, 0, p);
+  // projected tokens Y [G][E], D [G], per-patch factors [G], text inverse norms [q]
+  const int64_t yb = round_up(4 * (int64_t)G * E, 256), gb = round_up(4 * (int64_t)G, 256);
+  p.shape.extra_bytes = yb + 2 * gb + round_up(4 * (int64_t)q, 256);
+  p.L = make_layout(p.shape);
+  Ctx cx;
+  if ((st = acquire(static_cast<hipStream_t>(stream), p.L, nullptr, cx))) return st;
+  stage_host(p, cx.host_stage, cx.dev_ws);
+  if ((st = upload(cx, p.L))) return st;
+  const Batch b = make_batch(p, cx.dev_ws, tokens->dtype, 0, 1);
+  const Work w = work_ptrs(cx.dev_ws, p.L);
+  char* x = cx.dev_ws + p.L.extra;
+  float* Y = reinterpret_cast<float*>(x);
+  float* D = reinterpret_cast<float*>(x + yb);
+  float* fac = reinterpret_cast<float*>(x + yb + gb);
+  float* inv_text = reinterpret_cast<float*>(x + yb + 2 * gb);
+  launch_token_stats(b, w, G, 1, 0, cx.st);
+  launch_d_from_r(w.r, G, eps, D, cx.st);
+  launch_heatmap(tokens->data, tokens->dtype, tokens->scale, G, C, proj->data, proj->dtype == DISC_BF16, E, text,
+                 text_dtype == DISC_BF16, q, D, Y, fac, inv_text, heat, cx.st);
   if ((st = check_launch(who))) return st;
   return ok();
 }

@@ -238,6 +238,9 @@ void launch_query(const float* emb, int m, const void* text, int text_bf16, int 
 void launch_pack(const uint8_t* u8, int m, int h, int w, uint64_t* bits, hipStream_t st);
 void launch_dense_weights(const Batch& b, const Work& w, float* out, float eps, hipStream_t st);
 void launch_d_from_r(const float* r, int G, float eps, float* D, hipStream_t st);
+void launch_heatmap(const void* tok, int tok_dtype, const float* scale, int G, int C, const void* P, int p_bf16, int E,
+                    const void* text, int text_bf16, int q, const float* D, float* Y, float* fac, float* inv_text,
+                    float* heat, hipStream_t st);
 void launch_user_weights(const Batch& b, const Work& w, const float* wts, hipStream_t st);
 void launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st);
 

@@ -13,7 +13,9 @@ namespace host {
 
 struct Layout {
   size_t frames, mask_frame, tiles, dyn, staged_end;  // staged region (uploaded from the host)
-  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, rbar, s, W, Z, mstat, perm, X, ppart, ptile, qpart, ppack, edt_part, tkp, total;
+  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, rbar, s, W, Z, mstat, perm, X, ppart, ptile, qpart, ppack, edt_part, tkp;
+  size_t extra;  // extra_bytes for an entry point's own buffers
+  size_t total;
 };
 
 struct Shape {
@@ -26,6 +28,7 @@ struct Shape {
   int pool_split = 1, proj_split = 1;
   bool want_dbar = false;  // some frame asks for the mean distinctiveness (needs r and its mean)
   int max_rows = kMaxRows;  // tallest frame + 2 (distance-transform rows of the tallest item)
+  int64_t extra_bytes = 0;  // appended region (e.g. the heat-map's projected tokens)
 };
 
 // Split K of the pooling / projection GEMMs when their tiles alone would not
