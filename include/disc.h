@@ -37,6 +37,12 @@
  *   - m == 0 masks is a no-op that returns DISC_OK.
  *   - Calls on different streams may run concurrently; the library keeps one
  *     workspace per (device, stream) unless the caller passes its own.
+ *   - Stream capture: the entry points that take a stream stage their
+ *     descriptors through a host buffer that the next call reuses (and may
+ *     time tuning candidates or grow a workspace), so they refuse a stream
+ *     that is being captured (DISC_ERR_INVALID_ARGUMENT, nothing enqueued).
+ *     disc_embed_masks_noalloc enqueues kernels only and can be captured;
+ *     the serving runtime captures its own graphs.
  *
  * Layouts:
  *   tokens  [gh][gw][c] row-major, c fastest; gh = ceil(h/patch), gw = ceil(w/patch)
@@ -402,13 +408,21 @@ disc_status disc_server_create(const disc_server_config* cfg, disc_server** out)
 /* Validate and enqueue one frame; *ticket identifies it. */
 disc_status disc_server_submit(disc_server* s, const disc_tokens* tokens, const disc_masks* masks, disc_out* out,
                                uint64_t* ticket);
-/* *done = 1 once the ticket completed; *result is then its status. */
+/* *done = 1 once the ticket completed; *result is then its status.  A ticket
+ * whose completion poll or wait has reported is forgotten (a later poll or
+ * wait of it fails with DISC_ERR_INVALID_ARGUMENT), so the server's memory
+ * does not grow with the number of requests served. */
 disc_status disc_server_poll(disc_server* s, uint64_t ticket, int32_t* done, int32_t* result);
 /* Block until the ticket completed; *result = its status. */
 disc_status disc_server_wait(disc_server* s, uint64_t ticket, int32_t* result);
 /* Block until every submitted request completed. */
 disc_status disc_server_drain(disc_server* s);
+/* Counts since the server started or since the last reset; p50/p99/max/mean
+ * over the latencies of the last 2^20 successful requests in that span. */
 disc_status disc_server_get_stats(disc_server* s, disc_server_stats* st);
+/* Restart the counts and latency samples from zero (e.g. after a warm-up;
+ * requests still in flight are counted when they complete). */
+disc_status disc_server_reset_stats(disc_server* s);
 /* Drain, stop the lanes and free the server's memory. */
 void disc_server_destroy(disc_server* s);
 

@@ -41,7 +41,8 @@ EXPORTS = [
     "disc_token_stats", "disc_pool_project", "disc_pack_masks", "disc_last_error", "disc_abi_version",
     "disc_trace_enable", "disc_trace_select", "disc_trace_reset", "disc_trace_read", "disc_trace_stage_name",
     "disc_server_config_default", "disc_server_create", "disc_server_submit", "disc_server_poll",
-    "disc_server_wait", "disc_server_drain", "disc_server_get_stats", "disc_server_destroy",
+    "disc_server_wait", "disc_server_drain", "disc_server_get_stats", "disc_server_reset_stats",
+    "disc_server_destroy",
     "disc_query_topk", "disc_query_heatmap", "disc_view_quality", "disc_angle_score", "disc_fuse",
     "disc_backproject_count", "disc_backproject", "disc_dbscan_denoise", "disc_voxelize", "disc_voxel_overlap",
 ]
@@ -179,6 +180,7 @@ def load(path: str = LIB_PATH):
     lib.disc_server_wait.argtypes = [vp, ctypes.c_uint64, P(i32)]
     lib.disc_server_drain.argtypes = [vp]
     lib.disc_server_get_stats.argtypes = [vp, P(ServerStats)]
+    lib.disc_server_reset_stats.argtypes = [vp]
     lib.disc_server_destroy.argtypes = [vp]
     lib.disc_server_destroy.restype = None
     for name in ("disc_server_create", "disc_server_submit", "disc_server_poll", "disc_server_wait",
@@ -635,6 +637,10 @@ class Server:
         st = ServerStats()
         _check(load().disc_server_get_stats(self.h, ctypes.byref(st)))
         return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        """Restart counts and latency samples (e.g. after a warm-up)."""
+        _check(load().disc_server_reset_stats(self.h))
 
     def close(self):
         if self.h:

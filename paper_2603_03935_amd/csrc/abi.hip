@@ -213,6 +213,14 @@ struct Ctx {
 };
 
 disc_status acquire(hipStream_t st, const Layout& L, const disc_options* opts, Ctx& cx) {
+  // The staged descriptors go through a host buffer that the next call on
+  // this stream reuses, and a new shape may time the pooling candidates or
+  // grow the workspace: none of that may be recorded into a graph.
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(DISC_ERR_INVALID_ARGUMENT,
+                "the stream is being captured: this entry point stages through a reused host buffer; "
+                "capture disc_embed_masks_noalloc instead");
   hipError_t e = hipGetDevice(&cx.dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   cx.st = st;
@@ -604,15 +612,20 @@ int pool_tile_choice(const Plan& p, int tok_dtype, const disc_options& o, bool t
   (void)hipEventSynchronize(ev.back());
   int best = cand[0];
   float best_ms = 1e30f;
+  bool timed = true;  // keep a choice only when every candidate was timed
   for (size_t i = 0; i < cand.size(); ++i) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ev[4 * i + 2], ev[4 * i + 3]) == hipSuccess && ms < best_ms) {
+    if (hipEventElapsedTime(&ms, ev[4 * i + 2], ev[4 * i + 3]) != hipSuccess) {
+      timed = false;
+      continue;
+    }
+    if (ms < best_ms) {
       best_ms = ms;
       best = cand[i];
     }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
-  {
+  if (timed) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = best;
   }

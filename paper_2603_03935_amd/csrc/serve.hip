@@ -91,7 +91,18 @@ struct disc_server {
   int in_flight = 0;
   bool stopping = false;
   uint64_t submitted = 0, completed = 0, failed = 0, rejected = 0, batches = 0, batch_frames = 0;
+  // latencies of the last kLatWindow successful requests (a ring)
+  static constexpr size_t kLatWindow = (size_t)1 << 20;
   std::vector<double> lat_ms;
+  size_t lat_next = 0;
+  void add_latency(double ms) {
+    if (lat_ms.size() < kLatWindow) {
+      lat_ms.push_back(ms);
+    } else {
+      lat_ms[lat_next] = ms;
+      lat_next = (lat_next + 1) % kLatWindow;
+    }
+  }
 
   void lane_loop(int li);
   int32_t run_batch(Lane& ln, const std::vector<Request>& batch);
@@ -205,7 +216,7 @@ void disc_server::lane_loop(int li) {
         t.result = res;
         if (res == DISC_OK) {
           ++completed;
-          lat_ms.push_back(ms_since(r.t_sub, done));
+          add_latency(ms_since(r.t_sub, done));
         } else {
           ++failed;
         }
@@ -332,7 +343,7 @@ disc_status disc_server_submit(disc_server* s, const disc_tokens* t, const disc_
     if (m->m == 0) {  // nothing to compute
       s->tickets[r.ticket].state = 2;
       ++s->completed;
-      s->lat_ms.push_back(0.0);
+      s->add_latency(0.0);
     } else {
       s->pending.push_back(r);
     }
@@ -350,16 +361,19 @@ disc_status disc_server_poll(disc_server* s, uint64_t ticket, int32_t* done, int
   if (it == s->tickets.end()) return fail(DISC_ERR_INVALID_ARGUMENT, "disc_server_poll: unknown ticket");
   *done = it->second.state == 2;
   if (result) *result = it->second.result;
+  if (*done) s->tickets.erase(it);  // reported: the ticket is forgotten
   return ok();
 }
 
 disc_status disc_server_wait(disc_server* s, uint64_t ticket, int32_t* result) {
   if (!s) return fail(DISC_ERR_INVALID_ARGUMENT, "disc_server_wait: NULL server");
   std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->tickets.find(ticket);
-  if (it == s->tickets.end()) return fail(DISC_ERR_INVALID_ARGUMENT, "disc_server_wait: unknown ticket");
+  if (s->tickets.find(ticket) == s->tickets.end())
+    return fail(DISC_ERR_INVALID_ARGUMENT, "disc_server_wait: unknown ticket");
   s->cv_done.wait(lk, [&] { return s->tickets[ticket].state == 2; });
-  if (result) *result = s->tickets[ticket].result;
+  auto it = s->tickets.find(ticket);
+  if (result) *result = it->second.result;
+  s->tickets.erase(it);  // reported: the ticket is forgotten
   return ok();
 }
 
@@ -372,18 +386,21 @@ disc_status disc_server_drain(disc_server* s) {
 
 disc_status disc_server_get_stats(disc_server* s, disc_server_stats* st) {
   if (!s || !st) return fail(DISC_ERR_INVALID_ARGUMENT, "disc_server_get_stats: NULL argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  std::memset(st, 0, sizeof *st);
-  st->submitted = s->submitted;
-  st->completed = s->completed;
-  st->failed = s->failed;
-  st->rejected = s->rejected;
-  st->batches = s->batches;
-  st->mean_batch_frames = s->batches ? (double)s->batch_frames / (double)s->batches : 0.0;
-  st->lanes = (int32_t)s->lanes.size();
-  st->lane_workspace_bytes = s->cap.L.total;
-  if (!s->lat_ms.empty()) {
-    std::vector<double> v = s->lat_ms;
+  std::vector<double> v;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(st, 0, sizeof *st);
+    st->submitted = s->submitted;
+    st->completed = s->completed;
+    st->failed = s->failed;
+    st->rejected = s->rejected;
+    st->batches = s->batches;
+    st->mean_batch_frames = s->batches ? (double)s->batch_frames / (double)s->batches : 0.0;
+    st->lanes = (int32_t)s->lanes.size();
+    st->lane_workspace_bytes = s->cap.L.total;
+    v = s->lat_ms;  // copied under the lock, sorted outside it
+  }
+  if (!v.empty()) {
     std::sort(v.begin(), v.end());
     auto pct = [&](double q) { return v[std::min(v.size() - 1, (size_t)(q * (double)(v.size() - 1) + 0.5))]; };
     st->p50_ms = pct(0.50);
@@ -393,6 +410,15 @@ disc_status disc_server_get_stats(disc_server* s, disc_server_stats* st) {
     for (double x : v) sum += x;
     st->mean_ms = sum / (double)v.size();
   }
+  return ok();
+}
+
+disc_status disc_server_reset_stats(disc_server* s) {
+  if (!s) return fail(DISC_ERR_INVALID_ARGUMENT, "disc_server_reset_stats: NULL server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->submitted = s->completed = s->failed = s->rejected = s->batches = s->batch_frames = 0;
+  s->lat_ms.clear();
+  s->lat_next = 0;
   return ok();
 }
 

@@ -144,3 +144,23 @@ def test_zero_mask_request_completes_immediately():
     with make() as s:
         t = s.submit(*req(m=0))
         assert s.poll(t) == (True, 0)
+
+
+def test_reported_tickets_are_forgotten_and_stats_reset():
+    """A ticket whose completion was reported is dropped (the server does not
+    grow with the requests served); reset_stats restarts counts and latency
+    samples, so a warm-up can be left out of p50/p99."""
+    with make(lanes=1, dry_run=2000) as s:
+        warm = [s.submit(*req()) for _ in range(3)]
+        for t in warm:
+            assert s.wait(t) == 0
+        with pytest.raises(disc.DiscError):
+            s.poll(warm[0])
+        s.reset_stats()
+        st = s.stats()
+        assert st["submitted"] == 0 and st["completed"] == 0 and st["p99_ms"] == 0.0
+        tickets = [s.submit(*req()) for _ in range(5)]
+        s.drain()
+        assert all(s.poll(t) == (True, 0) for t in tickets)
+        st = s.stats()
+        assert st["submitted"] == 5 and st["completed"] == 5 and st["p50_ms"] > 0.0
