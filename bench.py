@@ -3,28 +3,31 @@
 (arXiv 2603.03935, Sec. III-C) on one MI355X.
 
 A step is one pass of the whole hot path -- bounding-box scan (which also
-lists the distance-transform work), exact EDT fused with the per-patch sqrt(EDT) sums, token statistics (Eq. 1),
-weight finalisation, pooling GEMM, projection GEMM with L2 normalisation --
-over one batch of synthetic input already resident in HBM.
+lists the distance-transform work), exact EDT fused with the per-patch
+sqrt(EDT) sums, token statistics (Eq. 1), weight finalisation, pooling GEMM,
+projection GEMM with L2 normalisation -- over one batch of synthetic input
+already resident in HBM.
 
-Default workload: the plain-FP32 single frame (480x640, 30x40x1024 tokens with
-16-px patches, 128 instance masks, projection 1024x768), one disc_embed_frames
-call per step.  ``--config cfg3`` / ``cfg5`` run the batched BF16 / large FP8
-workloads instead.
-
-Beside the plain path the default run also drives the serving loop with BF16
-operands (16 camera streams, Poisson 30 frames/s each, 480x640 and 720x1280
-frames with Poisson(80) masks; continuous batching with graph replay) and
-reports its latency at that offered load and its saturated throughput.
-
-Prints ONE JSON line.  ``value`` is mask embeddings per second of the plain
-path over exactly K timed steps; ``roofline`` reports the dominant kernel's
-achieved algorithmic rate against the MI355X peak, its duration taken from
-HIP events recorded on the launch stream around that stage in every timed
-step (only that stage: each event record costs a few microseconds);
-``config.stage_avg_ms`` comes from an untimed pass with every stage between
-events and ``p50_ms``/``p99_ms`` from an untimed pass with per-step events;
-``cpu_baseline`` times the FP64 CPU oracle on a bounded sample.
+Default run (one JSON line on stdout; progress on stderr):
+  * the plain-FP32 single frame (480x640, 30x40x1024 tokens with 16-px
+    patches, 128 instance masks, projection 1024x768), one disc_embed_frames
+    call per step: ``value`` is its mask embeddings/s over exactly K timed
+    steps; ``roofline`` the dominant kernel's algorithmic rate, its duration
+    from HIP events recorded on the launch stream around that stage in every
+    timed step; stage breakdown and p50/p99 step latency from untimed passes;
+  * ``batched_bf16`` (64 frames, BF16) and ``large_fp8`` (16 frames 1080p, FP8
+    tokens): masks/s, frames/s, p50/p99 batch latency and stage breakdown;
+  * ``served_bf16``: the serving loop (16 camera streams, Poisson 30 frames/s
+    each, 480x640 and 720x1280 frames, Poisson(80) masks; continuous batching
+    with graph replay): 2 s warm-up, 20 s at the nominal 480 frames/s, a rate
+    sweep (x2, x4, ...) up to the first rate whose p99 exceeds 33 ms, and the
+    saturated throughput;
+  * ``cpu_baseline``: the FP64 oracle as it stands on the host, one thread and
+    every thread of the GPU's host share; the same oracle checks sampled masks
+    of every leg (``accuracy``: min / median / worst-10 cosine, max abs error);
+  * short legs for the open-vocabulary query, view quality / fusion, the
+    weighting-mode ablation and the geometry workload.
+``--config cfg3`` / ``cfg5`` make a batched workload the main one instead.
 """
 from __future__ import annotations
 
@@ -69,21 +72,23 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="cfg2", choices=sorted(CONFIG_DESC))
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-baseline time budget")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=20, help="timed steps of the cfg3 leg (cfg5: half)")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="oracle time per CPU-baseline run (1 and N threads)")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="threads of the all-core CPU baseline (0: host share)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="measured duration at the nominal offered load")
+    ap.add_argument("--serve-warmup", type=float, default=2.0, help="warm-up arrivals before the served measurement")
+    ap.add_argument("--sweep-seconds", type=float, default=4.0, help="duration of each rate of the served sweep")
+    ap.add_argument("--skip", default="", help="comma list of legs to leave out: cfg3, cfg5, serve, query, quality, "
+                                               "ablation, geometry, cpu")
     ap.add_argument("--no-trace", action="store_true", help="skip per-stage event timing")
-    ap.add_argument("--serve-seconds", type=float, default=3.0, help="offered-load duration of the served leg")
-    ap.add_argument("--no-serve", action="store_true", help="skip the served BF16 leg")
-    ap.add_argument("--no-query", action="store_true", help="skip the open-vocabulary query leg")
-    ap.add_argument("--no-quality", action="store_true", help="skip the view-quality / fusion leg")
-    ap.add_argument("--no-ablation", action="store_true", help="skip the weighting-mode ablation leg")
-    ap.add_argument("--no-geometry", action="store_true", help="skip the geometry (back-projection .. overlap) leg")
     ap.add_argument("--edt-layout", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="distance-transform band layout (-1: chosen per call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
-    return ap.parse_args()
+    a = ap.parse_args()
+    a.skip = set(x.strip() for x in a.skip.split(",") if x.strip())
+    return a
 
 
 # ---------------------------------------------------------------- algorithmic work
@@ -225,11 +230,47 @@ def roofline(stage: str, avg_ms: float, units, workload: str):
 
 # ---------------------------------------------------------------- served leg
 
-def served_leg(disc, di, dev, seconds: float):
-    """Serving loop, BF16 operands: 16 streams at Poisson 30 frames/s each,
-    streams 0-7 480x640 frames, 8-15 720x1280, Poisson(80) masks.  Reports the
-    latency at that offered load (arrival -> completion, measured by the
-    server) and the throughput when the same frames are submitted at once."""
+def _arrivals(di, seconds: float, rate_x: float, n_frames: int, seed_frame: int):
+    """Open-loop arrivals of the serving mix: 16 streams with exponential gaps
+    at 30 x rate_x frames/s each, streams 0-7 carrying the 480x640 frames of
+    the pool and 8-15 the 720x1280 ones.  Returns [(t, frame index)]."""
+    out = []
+    for s in range(16):
+        n = int(seconds * 30 * rate_x * 2) + 16
+        gaps = di.exponential_gaps(di.frame_seed(4, seed_frame), s, n, 1.0 / (30.0 * rate_x))
+        t = np.cumsum(gaps)
+        for k, tt in enumerate(t[t < seconds]):
+            idx = (s % 8) + (8 if s >= 8 else 0) + 16 * (k % 2)
+            out.append((float(tt), idx % n_frames))
+    out.sort()
+    return out
+
+
+def _offer(srv, ins, outs, arrivals):
+    """Submit the arrivals at their times (late ones at once), wait for all;
+    returns the wall time from the first arrival to the last completion."""
+    t0 = time.perf_counter()
+    tickets = []
+    for ta, idx in arrivals:
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        tickets.append(srv.submit_frame(ins[idx], outs[idx])[0])
+    for t in tickets:
+        if srv.wait(t) != 0:
+            raise RuntimeError("served frame failed")
+    return time.perf_counter() - t0
+
+
+def served_leg(disc, di, dev, seconds: float, warm_seconds: float, sweep_seconds: float, p99_limit_ms: float = 33.0):
+    """Serving loop, BF16 operands, the serving mix (16 streams, Poisson 30
+    frames/s each; 480x640 and 720x1280 frames, Poisson(80) masks), inputs
+    resident.  Warm-up arrivals first (graph capture, caches), then the
+    nominal offered load (480 frames/s) for `seconds` with latency
+    arrival -> completion as the server measures it, then a sweep of the
+    offered rate (x2, x4, ...) for `sweep_seconds` each that stops at the
+    first rate whose p99 exceeds one frame period (33 ms), then the saturated
+    throughput with every frame submitted at once."""
     import torch
 
     wl = di.workload("cfg4")
@@ -242,42 +283,40 @@ def served_leg(disc, di, dev, seconds: float):
     torch.cuda.synchronize()
     cfg = dict(proj=proj, tok_dtype=disc.DISC_BF16, c=1024, e=wl.proj.shape[1], max_frames=8, max_masks=2400,
                max_h=720, max_w=1280, min_patch=16, lanes=2, use_graph=True, mem_budget=16 << 30)
-    res = {}
-    # offered load: per-stream exponential gaps, merged into one arrival list
-    arrivals = []
-    for s in range(16):
-        gaps = di.exponential_gaps(di.frame_seed(4, 990), s, int(seconds * 30 * 2) + 8, 1.0 / 30.0)
-        t = np.cumsum(gaps)
-        for k, tt in enumerate(t[t < seconds]):
-            # stream s carries the frames of its resolution (s < 8: 480x640)
-            idx = (s % 8) + (8 if s >= 8 else 0) + 16 * (k % 2)
-            arrivals.append((float(tt), idx % len(ins)))
-    arrivals.sort()
-    with disc.Server(**cfg) as srv:
-        for x, o in zip(ins[:4], outs[:4]):  # warm-up: capture graphs, fill caches
-            srv.wait(srv.submit_frame(x, o)[0])
-        srv_stats0 = srv.stats()
-        t0 = time.perf_counter()
-        tickets = []
-        for ta, idx in arrivals:
-            now = time.perf_counter() - t0
-            if ta > now:
-                time.sleep(ta - now)
-            tickets.append(srv.submit_frame(ins[idx], outs[idx])[0])
-        for t in tickets:
-            if srv.wait(t) != 0:
-                raise RuntimeError("served frame failed")
-        wall = time.perf_counter() - t0
+    masks_of = [x.m for x in ins]
+
+    def level(srv, rate_x, secs, seed):
+        arr = _arrivals(di, secs, rate_x, len(ins), seed)
+        srv.reset_stats()
+        wall = _offer(srv, ins, outs, arr)
         st = srv.stats()
-    masks = sum(ins[i].m for _, i in arrivals)
-    res["offered"] = {"streams": 16, "fps_per_stream": 30, "frames": len(arrivals), "masks": masks,
-                      "seconds": wall, "masks_per_s": masks / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-                      "max_ms": st["max_ms"], "batches": st["batches"] - srv_stats0["batches"],
-                      "mean_batch_frames": st["mean_batch_frames"]}
+        masks = sum(masks_of[i] for _, i in arr)
+        return {"rate_x": rate_x, "offered_fps": 480.0 * rate_x, "frames": len(arr), "masks": masks,
+                "seconds": wall, "frames_per_s": len(arr) / wall, "masks_per_s": masks / wall,
+                "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"], "batches": st["batches"],
+                "mean_batch_frames": st["mean_batch_frames"]}
+
+    res = {"streams": 16, "fps_per_stream": 30, "frame_pool": len(ins), "p99_limit_ms": p99_limit_ms}
+    with disc.Server(**cfg) as srv:
+        _offer(srv, ins, outs, _arrivals(di, warm_seconds, 1.0, len(ins), 989))  # warm-up, not reported
+        res["warmup_seconds"] = warm_seconds
+        res["nominal"] = level(srv, 1.0, seconds, 990)
+        sweep = []
+        rate = 2.0
+        while rate <= 64.0:
+            lv = level(srv, rate, sweep_seconds, 990 + int(rate))
+            sweep.append(lv)
+            if lv["p99_ms"] > p99_limit_ms:
+                break
+            rate *= 2.0
+        res["sweep"] = sweep
+        ok = [lv["rate_x"] for lv in [res["nominal"]] + sweep if lv["p99_ms"] <= p99_limit_ms]
+        res["max_rate_x_within_limit"] = max(ok) if ok else None
     # saturated: every frame of the mix submitted back to back, several rounds
     with disc.Server(**cfg) as srv:
         for x, o in zip(ins[:4], outs[:4]):
             srv.wait(srv.submit_frame(x, o)[0])
+        srv.reset_stats()
         rounds = 8
         t0 = time.perf_counter()
         tickets = [srv.submit_frame(ins[i], outs[i])[0] for _ in range(rounds) for i in range(len(ins))]
@@ -286,7 +325,7 @@ def served_leg(disc, di, dev, seconds: float):
                 raise RuntimeError("served frame failed")
         wall = time.perf_counter() - t0
         st = srv.stats()
-    masks = rounds * sum(x.m for x in ins)
+    masks = rounds * sum(masks_of)
     res["saturated"] = {"frames": rounds * len(ins), "masks": masks, "seconds": wall, "masks_per_s": masks / wall,
                         "frames_per_s": rounds * len(ins) / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                         "mean_batch_frames": st["mean_batch_frames"]}
@@ -464,6 +503,175 @@ def ablation_leg(disc, di, dev, ins, proj, outs, masks: int, reps: int = 50):
     return res
 
 
+# ---------------------------------------------------------------- workload legs
+
+def gemm_bf16_of(wl) -> bool:
+    return not (wl.proj_dtype == "f32" and wl.frames[0].tokens.dtype == "f32")
+
+
+def run_workload(disc, di, dev, name: str, steps: int, warmup: int, opts, trace: bool, live_roof: bool,
+                 sample_masks: int):
+    """One workload: warm-up, an untimed pass with every stage between HIP
+    events (stage breakdown), exactly `steps` timed steps (wall clock around
+    them; with live_roof the dominant stage is also bracketed by events on its
+    launch stream, its average duration giving the roofline), then an untimed
+    pass with per-step events (p50/p99 step latency).  Returns the result and
+    the host copies of `sample_masks` output rows spread over the batch (the
+    oracle leg checks them)."""
+    import torch
+
+    wl = di.workload(name)
+    ins = []
+    for f in wl.frames:
+        data, scale = dev.dev_tokens(f.tokens)
+        ins.append(disc.FrameInput(data, dev.dev_bits(f.bits), f.h, f.w, f.tokens.patch, scale))
+    proj = dev.dev_proj(wl.proj, wl.proj_dtype)
+    outs = disc.alloc_outputs(ins, wl.proj.shape[1])
+    stream = torch.cuda.current_stream()
+    units, totals = workload_units(wl, gemm_bf16_of(wl))
+
+    def step():
+        disc.embed_frames(ins, proj, outputs=outs, options=opts, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stages = {}
+    if trace:
+        disc.trace_select(None)
+        disc.trace_reset()
+        disc.trace_enable(True)
+        for _ in range(min(steps, 50)):
+            step()
+        torch.cuda.synchronize()
+        disc.trace_enable(False)
+        stages = disc.trace_read()
+    avg = {k: (ms / n if n else 0.0) for k, (ms, n) in stages.items()}
+    dom = max(avg, key=avg.get) if avg else None
+    if dom and live_roof:
+        disc.trace_select([dom])
+        disc.trace_reset()
+        disc.trace_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    roof = None
+    if dom and live_roof:
+        disc.trace_enable(False)
+        live_ms, live_n = disc.trace_read()[dom]
+        disc.trace_select(None)
+        roof = roofline(dom, live_ms / max(live_n, 1), units, name)
+    ms_per_step = wall * 1000.0 / steps
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for i in range(steps):
+        starts[i].record(stream)
+        step()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    # output rows to check against the oracle: spread over frames and masks
+    picks = []
+    nf = len(wl.frames)
+    per = max(1, sample_masks // nf)
+    for fi in range(nf):
+        m = wl.frames[fi].m
+        if len(picks) >= sample_masks or m == 0:
+            continue
+        k = min(m, per, sample_masks - len(picks))
+        idx = sorted(set(int(x) for x in np.linspace(0, m - 1, k).round()))
+        picks.append((fi, idx, outs[fi].out[idx].cpu().numpy(), outs[fi].status[idx].cpu().numpy()))
+    res = {"workload": name, "desc": CONFIG_DESC[name], "frames": nf, "masks_per_step": totals["masks"],
+           "steps": steps, "ms_per_step": ms_per_step, "masks_per_s": totals["masks"] / (ms_per_step / 1000.0),
+           "frames_per_s": nf / (ms_per_step / 1000.0), "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "stage_avg_ms": avg,
+           "stage_roofline": stage_rooflines(avg, units, totals), "edt_pixels": totals["edt_pixels"],
+           "touched_patches": totals["touched_patches"],
+           "dtype": "f32" if not gemm_bf16_of(wl) else ("f8+bf16" if wl.frames[0].tokens.dtype == "f8" else "bf16")}
+    return res, roof, {"wl": wl, "picks": picks}, (ins, proj, outs, totals)
+
+
+# ---------------------------------------------------------------- oracle leg (CPU baseline + accuracy)
+
+def host_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "affinity": aff}
+
+
+def oracle_leg(checks: dict, main_wl, seconds: float, threads: int) -> tuple:
+    """The FP64 oracle as it stands (single-threaded C, no tuning), timed on
+    the host: one thread over the first 16 masks of the main workload's frame
+    0, repeated for `seconds`; then `threads` threads at once, each running
+    the same single-threaded oracle on the same sample, for `seconds`.  Its
+    results for the masks sampled from every GPU leg give that leg's
+    accuracy: per-mask cosine against the FP64 result (min, median, worst 10),
+    the largest absolute element difference and the status agreement."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from tests.gpu_common import cosines, oracle_frame
+
+    fr = main_wl.frames[0]
+    n = min(fr.m, 16)
+    idx = list(range(n))
+
+    def run_for(secs):
+        done = reps = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle_frame(fr, main_wl.proj, main_wl.proj_dtype, idx=idx)
+            done += n
+            reps += 1
+            if time.perf_counter() - t0 > secs:
+                return done, time.perf_counter() - t0
+
+    d1, e1 = run_for(seconds)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda _: run_for(seconds), range(threads)))
+    dn = sum(p[0] for p in parts)
+    en = max(p[1] for p in parts)
+    info = host_info()
+    cpu = {"value": dn / en, "unit": "mask embeddings/s", "cores": threads, "kind": "oracle",
+           "sample": f"{main_wl.name} frame 0, its first {n} masks (token statistics, full-frame FP64 EDT, pooling, "
+                     f"projection per call), repeated: {threads} threads x {en:.1f} s, each the single-threaded "
+                     f"oracle",
+           "single_core": {"value": d1 / e1, "cores": 1, "seconds": e1, "masks": d1},
+           "host": info}
+    acc = {}
+    for name, chk in checks.items():
+        wl = chk["wl"]
+        cos_all, err, stat_ok, nm = [], 0.0, True, 0
+        bound = 1.0 - 1e-6 if not gemm_bf16_of(wl) else 0.9995
+        for fi, idx2, got, st in chk["picks"]:
+            ref = oracle_frame(wl.frames[fi], wl.proj, wl.proj_dtype, idx=idx2)
+            stat_ok &= bool(np.array_equal(st, ref["status"]))
+            okm = ref["status"] == 0
+            nm += len(idx2)
+            if okm.any():
+                cos_all.extend(cosines(got[okm].astype(np.float64), ref["out"][okm]).tolist())
+            err = max(err, float(np.abs(got.astype(np.float64) - ref["out"]).max()))
+        c = np.sort(np.array(cos_all))
+        acc[name] = {"masks_checked": nm, "bound_cos": bound, "min_cos": float(c[0]) if c.size else None,
+                     "median_cos": float(np.median(c)) if c.size else None, "worst10_cos": c[:10].tolist(),
+                     "max_abs_err": err, "status_equal": stat_ok,
+                     "pass": bool(stat_ok and (c.size == 0 or c[0] >= bound))}
+    return cpu, acc
+
+
 # ---------------------------------------------------------------- main
 
 def main():
@@ -489,101 +697,50 @@ def main():
     import paper_2603_03935_amd as disc
 
     disc.load()
-    wl = di.workload(args.config)
-    ins = []
-    for f in wl.frames:
-        data, scale = dev.dev_tokens(f.tokens)
-        ins.append(disc.FrameInput(data, dev.dev_bits(f.bits), f.h, f.w, f.tokens.patch, scale))
-    proj = dev.dev_proj(wl.proj, wl.proj_dtype)
-    outs = disc.alloc_outputs(ins, wl.proj.shape[1])
     opts = disc.make_options(edt_layout=args.edt_layout)
-    stream = torch.cuda.current_stream()
-    gemm_bf16 = not (wl.proj_dtype == "f32" and wl.frames[0].tokens.dtype == "f32")
-    units, totals = workload_units(wl, gemm_bf16)
+    main_res, roof, main_chk, (ins, proj, outs, totals) = run_workload(
+        disc, di, dev, args.config, args.steps, args.warmup, opts, not args.no_trace, True,
+        sample_masks=128 if args.config in ("cfg1", "cfg2") else 24)
+    checks = {args.config: main_chk}
+    ms_per_step = main_res["ms_per_step"]
+    value = main_res["masks_per_s"]
+    progress(f"main {args.config}: {value:.0f} masks/s")
 
-    def step():
-        disc.embed_frames(ins, proj, outputs=outs, options=opts, stream=stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    # untimed breakdown pass: every stage between HIP events (each event record
-    # costs a few microseconds, so the timed region below carries only the
-    # dominant stage's events)
-    stages = {}
-    if not args.no_trace:
-        disc.trace_select(None)
-        disc.trace_reset()
-        disc.trace_enable(True)
-        for _ in range(min(args.steps, 50)):
-            step()
-        torch.cuda.synchronize()
-        disc.trace_enable(False)
-        stages = disc.trace_read()
-    avg = {k: (ms / n if n else 0.0) for k, (ms, n) in stages.items()}
-    dom = max(avg, key=avg.get) if avg else None
-
-    # timed region: exactly K steps; the dominant stage is timed live with
-    # events on its launch stream
-    if dom:
-        disc.trace_select([dom])
-        disc.trace_reset()
-        disc.trace_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    roof = None
-    if dom:
-        disc.trace_enable(False)
-        live_ms, live_n = disc.trace_read()[dom]
-        disc.trace_select(None)
-        roof = roofline(dom, live_ms / max(live_n, 1), units, args.config)
-    ms_per_step = wall * 1000.0 / args.steps
-    value = totals["masks"] / (ms_per_step / 1000.0)
-
-    # latency pass: per-step events (untimed)
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    for i in range(args.steps):
-        starts[i].record(stream)
-        step()
-        ends[i].record(stream)
-    torch.cuda.synchronize()
-    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    # batched BF16 and large FP8 workloads (throughput, latency, breakdown)
+    batched = {}
+    if args.config == "cfg2":
+        for name, steps, leg in (("cfg3", args.batch_steps, "batched_bf16"), ("cfg5", max(args.batch_steps // 2, 3),
+                                                                             "large_fp8")):
+            if name in args.skip:
+                continue
+            r, _, chk, _ = run_workload(disc, di, dev, name, steps, 3, opts, not args.no_trace, False,
+                                        sample_masks=32 if name == "cfg3" else 12)
+            batched[leg] = r
+            checks[name] = chk
+            torch.cuda.empty_cache()
+            progress(f"{leg} ({name}): {r['masks_per_s']:.0f} masks/s")
 
     served = None
-    if not args.no_serve and args.config == "cfg2":
-        served = served_leg(disc, di, dev, args.serve_seconds)
-    query = None if args.no_query else query_leg(disc, di)
-    quality = None if args.no_quality else quality_leg(disc, di, dev, ins, proj, outs, opts)
-    ablation = None if args.no_ablation else ablation_leg(disc, di, dev, ins, proj, outs, totals["masks"])
-    geometry = None if args.no_geometry else geometry_leg(disc, di, dev)
+    if "serve" not in args.skip and args.config == "cfg2":
+        served = served_leg(disc, di, dev, args.serve_seconds, args.serve_warmup, args.sweep_seconds)
+        progress("served leg done")
+    query = None if "query" in args.skip else query_leg(disc, di)
+    quality = None if "quality" in args.skip else quality_leg(disc, di, dev, ins, proj, outs, opts)
+    ablation = None if "ablation" in args.skip else ablation_leg(disc, di, dev, ins, proj, outs, totals["masks"])
+    geometry = None if "geometry" in args.skip else geometry_leg(disc, di, dev)
 
-    # CPU baseline: the FP64 oracle as it stands, one core, bounded sample
+    # the oracle: CPU baseline (one thread, then every host thread of the
+    # GPU's share) and the accuracy of every leg's sampled masks
     cpu = None
-    if not args.no_cpu_baseline:
-        from tests.gpu_common import oracle_frame
+    if "cpu" not in args.skip:
+        threads = args.cpu_threads or min(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or host_info()["affinity"], 16)
+        cpu, acc = oracle_leg(checks, main_chk["wl"], args.cpu_seconds, max(1, threads))
+        main_res["accuracy"] = acc.get(args.config)
+        for leg, r in batched.items():
+            r["accuracy"] = acc.get(r["workload"])
+        progress("oracle leg done")
 
-        fr = wl.frames[0]
-        n = min(fr.m, 16)
-        t0 = time.perf_counter()
-        done = 0
-        reps = 0
-        while True:
-            oracle_frame(fr, wl.proj, wl.proj_dtype, idx=list(range(n)))
-            done += n
-            reps += 1
-            if time.perf_counter() - t0 > args.cpu_seconds:
-                break
-        el = time.perf_counter() - t0
-        cpu = {"value": done / el, "unit": "mask embeddings/s", "cores": 1, "kind": "oracle",
-               "sample": f"{done} masks of {args.config} frame 0 ({reps} runs over its first {n} masks: token "
-                         f"statistics, full-frame FP64 EDT, pooling, projection), {el:.1f} s on one host thread"}
-
+    config = {k: v for k, v in main_res.items() if k not in ("masks_per_s", "ms_per_step", "steps", "dtype")}
     res = {
         "metric": "mask embeddings/sec and p99 frame latency, BF16 served vs FP32 plain, 1 MI355X",
         "value": value,
@@ -595,16 +752,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if not gemm_bf16 else ("f8+bf16" if wl.frames[0].tokens.dtype == "f8" else "bf16"),
+        "dtype": main_res["dtype"],
         "data": "synthetic",
-        "config": {"workload": args.config, "desc": CONFIG_DESC[args.config], "frames": len(wl.frames),
-                   "masks_per_step": totals["masks"], "frames_per_s": len(wl.frames) / (ms_per_step / 1000.0),
-                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                   "stage_avg_ms": avg, "stage_roofline": stage_rooflines(avg, units, totals),
-                   "edt_pixels": totals["edt_pixels"],
-                   "touched_patches": totals["touched_patches"]},
+        "config": config,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched_bf16": batched.get("batched_bf16"),
+        "large_fp8": batched.get("large_fp8"),
         "served_bf16": served,
         "query_topk": query,
         "view_quality_fusion": quality,
@@ -612,6 +766,11 @@ def main():
         "geometry": geometry,
     }
     print(json.dumps(res))
+
+
+def progress(msg: str):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
 
 
 if __name__ == "__main__":

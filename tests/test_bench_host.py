@@ -51,3 +51,24 @@ def test_stage_rooflines():
     assert abs(r["proj"]["hbm_gbs"] * 2e-5 * 1e9 - (f.m * C * 4 + C * E * 4 + f.m * E * 4)) < 1e-3
     for v in r.values():
         assert abs(v["frac"] - v["achieved"] / v["peak"]) < 1e-15
+
+
+def test_served_arrivals_rate_and_mix():
+    """The served leg's open-loop arrivals: 16 streams at 30 x rate frames/s,
+    sorted, within the horizon, streams 0-7 on the 480x640 half of the pool."""
+    for rate in (1.0, 4.0):
+        arr = bench._arrivals(di, 5.0, rate, 32, 990)
+        t = np.array([a for a, _ in arr])
+        assert np.all(np.diff(t) >= 0) and t.min() >= 0 and t.max() < 5.0
+        n = len(arr)
+        want = 16 * 30 * rate * 5.0
+        assert abs(n - want) < 4 * np.sqrt(want), (n, want)
+        idx = np.array([i for _, i in arr])
+        assert set(idx) <= set(range(32))
+        small = np.isin(idx % 16, np.arange(8))
+        assert 0.4 < small.mean() < 0.6
+
+
+def test_host_info():
+    info = bench.host_info()
+    assert info["nproc"] >= 1 and info["affinity"] >= 1
