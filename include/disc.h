@@ -171,6 +171,25 @@ disc_status disc_embed_frames(const disc_tokens* tokens, const disc_masks* masks
 size_t disc_workspace_bytes(const disc_tokens* tokens, const disc_masks* masks, int32_t n_frames,
                             const disc_proj* proj, const disc_options* opts);
 
+/* For callers that cannot allocate (code under hipGraph / stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): disc_embed_masks_ex
+ * for one frame, with the same arguments and the same results bit for bit,
+ * that allocates nothing.  Its workspace is a device array inside the library
+ * (one per GPU, DISC_NOALLOC_SCRATCH_BYTES, held until the process ends)
+ * instead of library-allocated or caller memory, and it enqueues no memset,
+ * no copy and no event.  The pooling tile width comes from the autotuner's
+ * stored choice or its size rule (this call never times candidates).
+ *   opts->workspace must be NULL.  A frame whose workspace
+ *   (disc_workspace_bytes for this one frame) exceeds the array fails with
+ *   DISC_ERR_LIMIT before anything is enqueued.
+ *   Every call on a GPU works in that GPU's one array and the next call
+ *   overwrites it: calls that overlap on one GPU (several streams or threads)
+ *   race and must be ordered by the caller.
+ * Other errors as for disc_embed_masks_ex. */
+#define DISC_NOALLOC_SCRATCH_BYTES (64u << 20)
+disc_status disc_embed_masks_noalloc(const disc_tokens* tokens, const disc_masks* masks, const disc_proj* proj,
+                                     disc_out* out, const disc_options* opts, void* stream);
+
 /* Free the library-owned workspaces (synchronises the device first). */
 disc_status disc_release_workspace(void);
 

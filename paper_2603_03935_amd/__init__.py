@@ -27,6 +27,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdisc.so")
 
 DISC_F32, DISC_BF16, DISC_F8E4M3 = 0, 1, 2
+DISC_ERR_INVALID_ARGUMENT, DISC_ERR_LIMIT = 1, 9
+# bytes of the device scratch array of disc_embed_masks_noalloc (DISC_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 SPATIAL_EDT, SPATIAL_AREA = 0, 1
 STATUS_NAMES = {
     0: "DISC_OK", 1: "DISC_ERR_INVALID_ARGUMENT", 2: "DISC_ERR_SHAPE", 3: "DISC_ERR_UNSUPPORTED_DTYPE",
@@ -36,7 +39,7 @@ STATUS_NAMES = {
 
 # Every symbol include/disc.h declares (checked by the CPU test suite).
 EXPORTS = [
-    "disc_options_default", "disc_embed_masks", "disc_embed_masks_ex", "disc_embed_frames",
+    "disc_options_default", "disc_embed_masks", "disc_embed_masks_ex", "disc_embed_frames", "disc_embed_masks_noalloc",
     "disc_workspace_bytes", "disc_release_workspace", "disc_edt_sq", "disc_patch_weights",
     "disc_token_stats", "disc_pool_project", "disc_pack_masks", "disc_last_error", "disc_abi_version",
     "disc_trace_enable", "disc_trace_select", "disc_trace_reset", "disc_trace_read", "disc_trace_stage_name",
@@ -142,6 +145,7 @@ def load(path: str = LIB_PATH):
     lib.disc_embed_masks.argtypes = [P(Tokens), P(Masks), P(Proj), P(Out)]
     lib.disc_embed_masks_ex.argtypes = [P(Tokens), P(Masks), P(Proj), P(Out), P(Options), vp]
     lib.disc_embed_frames.argtypes = [P(Tokens), P(Masks), i32, P(Proj), P(Out), P(Options), vp]
+    lib.disc_embed_masks_noalloc.argtypes = [P(Tokens), P(Masks), P(Proj), P(Out), P(Options), vp]
     lib.disc_workspace_bytes.argtypes = [P(Tokens), P(Masks), i32, P(Proj), P(Options)]
     lib.disc_workspace_bytes.restype = ctypes.c_size_t
     lib.disc_release_workspace.argtypes = []
@@ -346,6 +350,23 @@ def embed_masks(tokens, bits, h: int, w: int, proj, patch: int, scale=None, pool
     """disc_embed_masks_ex for one frame."""
     return embed_frames([FrameInput(tokens, bits, h, w, patch, scale)], proj, pooled=pooled, options=options,
                         stream=stream, quality=quality)[0]
+
+
+def embed_masks_noalloc(frame: FrameInput, proj, output: Optional[FrameOutput] = None, pooled: bool = False,
+                        options: Optional[Options] = None, stream=None) -> FrameOutput:
+    """disc_embed_masks_noalloc: one frame, working in the library's own
+    device scratch array (no allocation inside the call)."""
+    lib = load()
+    if output is None:
+        output = alloc_outputs([frame], proj.shape[1], pooled)[0]
+    tk = make_tokens(frame.tokens, frame.patch, frame.scale)
+    mk = make_masks(frame.bits, frame.h, frame.w)
+    ot = _out(output)
+    pj = make_proj(proj)
+    opts = options if options is not None else make_options()
+    _check(lib.disc_embed_masks_noalloc(ctypes.byref(tk), ctypes.byref(mk), ctypes.byref(pj), ctypes.byref(ot),
+                                        ctypes.byref(opts), _stream_handle(stream)))
+    return output
 
 
 def workspace_bytes(frames: Sequence[FrameInput], proj, options: Optional[Options] = None) -> int:

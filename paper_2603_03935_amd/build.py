@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdisc.so")
 SOURCES = ["abi.hip", "serve.hip", "k_scan.hip", "k_edt.hip", "k_stats.hip", "k_gemm.hip", "k_query.hip",
-           "k_quality.hip", "k_geom.hip"]
+           "k_quality.hip", "k_geom.hip", "noalloc.hip"]
 ARCH = os.environ.get("DISC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -307,67 +307,82 @@ Work work_ptrs(char* base, const Layout& L) {
 // --------------------------------------------------------------------------
 
 
-void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p, int tok_dtype) {
+// One frame's descriptor, appended to the capacity totals of a plan.
+FrameDesc plan_frame(const FrameIn& f, int C, Shape& s, PlanAcc& a) {
+  FrameDesc d{};
+  d.tokens = f.tokens;
+  d.scale = f.scale;
+  d.bits = f.bits;
+  d.out = f.out;
+  d.status = f.status;
+  d.pooled = f.pooled;
+  d.dbar = f.dbar;
+  d.area_out = f.area;
+  if (f.dbar) s.want_dbar = true;
+  s.max_rows = std::max(s.max_rows, std::min(f.h + 2, kMaxRows));
+  d.gh = f.gh;
+  d.gw = f.gw;
+  d.patch = f.patch;
+  d.G = f.gh * f.gw;
+  d.h = f.h;
+  d.w = f.w;
+  d.wq = (f.w + 63) / 64;
+  d.m = f.m;
+  d.mask_base = (int32_t)a.M;
+  d.Gs = (int32_t)round_up(d.G, 8);
+  d.w_base = a.sumMGs;
+  d.r_base = a.sumG;
+  d.t_base = a.tkp;
+  a.M += f.m;
+  a.sumG += d.G;
+  a.sumMGs += (int64_t)f.m * d.Gs;
+  a.tkp += (int64_t)round_up(d.G, 8) * C;
+  a.gmax = std::max(a.gmax, d.G);
+  a.nchunk = std::max(a.nchunk, stat_nchunk(d.G));
+  a.item_cap += (int64_t)f.m * ((f.w + strip_width(f.patch) - 1) / strip_width(f.patch) + 1);
+  a.n_tiles += (f.m + 63) / 64 * (C / 64);
+  return d;
+}
+
+// Shape totals and the workspace layout once every frame is in.
+void finish_plan(Plan& p, const PlanAcc& a) {
   Shape& s = p.shape;
-  s.n_frames = (int)fr.size();
+  s.M = a.M;
+  s.sumG = a.sumG;
+  s.sumMGs = a.sumMGs;
+  s.tkp_elems = a.tkp;
+  s.tkp_esize = 2;
+  s.gmax = a.gmax;
+  s.nchunk = a.nchunk;
+  s.item_cap = (int)std::min<int64_t>(a.item_cap, INT32_MAX / 2);
+  s.n_tiles = a.n_tiles;
+  choose_splits(s);
+  p.L = make_layout(s);
+}
+
+void begin_plan(Plan& p, int n_frames, int C, int E, int gemm_bf16) {
+  Shape& s = p.shape;
+  s.n_frames = n_frames;
   s.want_dbar = false;
   s.max_rows = 0;
   s.C = C;
   s.E = E;
   s.gemm_bf16 = gemm_bf16;
-  int64_t M = 0, sumG = 0, sumMGs = 0, tkp = 0;
-  int gmax = 0, nchunk = 1;
-  int64_t item_cap = 1;
+}
+
+void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p, int tok_dtype) {
+  (void)tok_dtype;
+  begin_plan(p, (int)fr.size(), C, E, gemm_bf16);
+  PlanAcc a;
   p.fds.resize(fr.size());
   for (size_t i = 0; i < fr.size(); ++i) {
     const FrameIn& f = fr[i];
-    FrameDesc d{};
-    d.tokens = f.tokens;
-    d.scale = f.scale;
-    d.bits = f.bits;
-    d.out = f.out;
-    d.status = f.status;
-    d.pooled = f.pooled;
-    d.dbar = f.dbar;
-    d.area_out = f.area;
-    if (f.dbar) s.want_dbar = true;
-    s.max_rows = std::max(s.max_rows, std::min(f.h + 2, kMaxRows));
-    d.gh = f.gh;
-    d.gw = f.gw;
-    d.patch = f.patch;
-    d.G = f.gh * f.gw;
-    d.h = f.h;
-    d.w = f.w;
-    d.wq = (f.w + 63) / 64;
-    d.m = f.m;
-    d.mask_base = (int32_t)M;
-    d.Gs = (int32_t)round_up(d.G, 8);
-    d.w_base = sumMGs;
-    d.r_base = sumG;
-    d.t_base = tkp;
-    p.fds[i] = d;
+    p.fds[i] = plan_frame(f, C, p.shape, a);
     for (int j = 0; j < f.m; ++j) p.mask_frame.push_back((int32_t)i);
     for (int m0 = 0; m0 < f.m; m0 += 64)
       for (int n0 = 0; n0 < C; n0 += 64) p.tiles.push_back(make_int4((int)i, m0, n0, 0));
-    M += f.m;
-    sumG += d.G;
-    sumMGs += (int64_t)f.m * d.Gs;
-    tkp += (int64_t)round_up(d.G, 8) * C;
-    gmax = std::max(gmax, d.G);
-    nchunk = std::max(nchunk, stat_nchunk(d.G));
-    item_cap += (int64_t)f.m * ((f.w + strip_width(f.patch) - 1) / strip_width(f.patch) + 1);
   }
-  s.M = M;
-  s.sumG = sumG;
-  s.sumMGs = sumMGs;
-  s.tkp_elems = tkp;
-  s.tkp_esize = 2;
-  s.gmax = gmax;
-  s.nchunk = nchunk;
-  s.item_cap = (int)std::min<int64_t>(item_cap, INT32_MAX / 2);
-  s.n_tiles = (int)p.tiles.size();
-  choose_splits(s);
-  p.L = make_layout(s);
+  finish_plan(p, a);
 }
 
 void choose_splits(Shape& s) {
@@ -437,6 +452,25 @@ disc_options defaults() {
   return o;
 }
 
+FrameIn frame_in(const disc_tokens& t, const disc_masks& m, const disc_out& o) {
+  FrameIn f;
+  f.tokens = t.data;
+  f.scale = t.scale;
+  f.bits = m.bits;
+  f.out = o.data;
+  f.status = o.mask_status;
+  f.pooled = o.pooled;
+  f.dbar = o.dbar;
+  f.area = o.area;
+  f.gh = t.gh;
+  f.gw = t.gw;
+  f.patch = t.patch;
+  f.h = m.h;
+  f.w = m.w;
+  f.m = m.m;
+  return f;
+}
+
 // Validate a ragged batch and describe it.
 disc_status describe(const disc_tokens* tokens, const disc_masks* masks, int32_t n, const disc_proj* proj, disc_out* out,
                      const disc_options* opts, const char* who, std::vector<FrameIn>& fr) {
@@ -457,23 +491,22 @@ disc_status describe(const disc_tokens* tokens, const disc_masks* masks, int32_t
       if ((st = check_out(&out[i], masks[i].m, proj->e, who))) return st;
   }
   fr.resize(n);
-  for (int i = 0; i < n; ++i) {
-    FrameIn& f = fr[i];
-    f.tokens = tokens[i].data;
-    f.scale = tokens[i].scale;
-    f.bits = masks[i].bits;
-    f.out = out[i].data;
-    f.status = out[i].mask_status;
-    f.pooled = out[i].pooled;
-    f.dbar = out[i].dbar;
-    f.area = out[i].area;
-    f.gh = tokens[i].gh;
-    f.gw = tokens[i].gw;
-    f.patch = tokens[i].patch;
-    f.h = masks[i].h;
-    f.w = masks[i].w;
-    f.m = masks[i].m;
-  }
+  for (int i = 0; i < n; ++i) fr[i] = frame_in(tokens[i], masks[i], out[i]);
+  return DISC_OK;
+}
+
+// Validate one frame (the checks describe() applies) without building vectors.
+disc_status describe_one(const disc_tokens* tokens, const disc_masks* masks, const disc_proj* proj, disc_out* out,
+                         const disc_options* opts, const char* who, FrameIn& f) {
+  if (!tokens || !masks || !out) return fail(DISC_ERR_INVALID_ARGUMENT, "%s: NULL frame arguments", who);
+  disc_status st;
+  if ((st = check_opts(opts, who))) return st;
+  if ((st = check_tokens(tokens, who))) return st;
+  if ((st = check_masks(masks, who))) return st;
+  if ((st = check_grid(tokens, masks, who))) return st;
+  if ((st = check_proj(proj, tokens->c, who))) return st;
+  if ((st = check_out(out, masks->m, proj->e, who))) return st;
+  f = frame_in(*tokens, *masks, *out);
   return DISC_OK;
 }
 

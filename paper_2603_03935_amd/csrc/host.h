@@ -55,6 +55,12 @@ struct Plan {
   std::vector<int4> tiles;
 };
 
+// Capacity totals accumulated while frames are added to a plan.
+struct PlanAcc {
+  int64_t M = 0, sumG = 0, sumMGs = 0, tkp = 0, item_cap = 1;
+  int gmax = 0, nchunk = 1, n_tiles = 0;
+};
+
 extern thread_local std::string g_err;
 bool aligned16(const void* p);
 int64_t round_up(int64_t x, int64_t a);
@@ -70,6 +76,15 @@ disc_status check_opts(const disc_options* o, const char* who);
 disc_status check_launch(const char* who);
 Layout make_layout(const Shape& s);
 void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p, int tok_dtype = DISC_BF16);
+// The same in steps, for callers that build no host vectors: begin_plan, then
+// plan_frame per frame (its descriptor and the pooling tiles
+// (frame, m0, n0) for m0 in steps of 64, n0 in steps of 64 below C), then
+// finish_plan (totals and layout).
+void begin_plan(Plan& p, int n_frames, int C, int E, int gemm_bf16);
+FrameDesc plan_frame(const FrameIn& f, int C, Shape& s, PlanAcc& a);
+void finish_plan(Plan& p, const PlanAcc& a);
+disc_status describe_one(const disc_tokens* tokens, const disc_masks* masks, const disc_proj* proj, disc_out* out,
+                         const disc_options* opts, const char* who, FrameIn& f);
 void stage_host(const Plan& p, char* host, char* dev);
 Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int distinct);
 Work work_ptrs(char* base, const Layout& L);

@@ -204,3 +204,24 @@ def test_geometry_validation(lib):
     assert lib.disc_voxel_overlap(FAKE, FAKE, 1, FAKE, FAKE, 1, FAKE, -1, FAKE, None) == 1
     assert lib.disc_voxel_overlap(FAKE, FAKE, 1, FAKE, FAKE, 1, None, 3, FAKE, None) == 1
     assert lib.disc_voxel_overlap(FAKE, FAKE, 1, FAKE, FAKE, 1, FAKE, 0, FAKE, None) == 0
+
+
+def test_noalloc_limits_before_device_work(lib):
+    """The entry point that allocates nothing rejects a caller workspace and a
+    frame whose workspace exceeds its scratch array on the host (a 1080p
+    FP8 frame with 500 masks needs more than the array holds)."""
+    t, m, p, o = good()
+    opts = disc.make_options()
+    opts.workspace = ctypes.c_void_p(FAKE)
+    opts.workspace_bytes = 1 << 30
+    rc = lib.disc_embed_masks_noalloc(ctypes.byref(t), ctypes.byref(m), ctypes.byref(p), ctypes.byref(o),
+                                      ctypes.byref(opts), None)
+    assert rc == disc.DISC_ERR_INVALID_ARGUMENT and b"workspace" in lib.disc_last_error()
+    t = disc.Tokens(FAKE, disc.DISC_F8E4M3, 68, 120, 1280, 16, FAKE)
+    m = disc.Masks(FAKE, 500, 1080, 1920)
+    p = disc.Proj(FAKE, disc.DISC_BF16, 1280, 1024)
+    o = disc.Out(FAKE, 500, 1024, None, None)
+    need = lib.disc_workspace_bytes(ctypes.byref(t), ctypes.byref(m), 1, ctypes.byref(p), None)
+    assert need > disc.NOALLOC_SCRATCH_BYTES
+    rc = lib.disc_embed_masks_noalloc(ctypes.byref(t), ctypes.byref(m), ctypes.byref(p), ctypes.byref(o), None, None)
+    assert rc == disc.DISC_ERR_LIMIT and b"scratch" in lib.disc_last_error()
