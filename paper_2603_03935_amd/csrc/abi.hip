@@ -172,7 +172,7 @@ Layout make_layout(const Shape& s) {
   L.qpart = take(s.proj_split > 1 ? 4 * (size_t)((s.C + kProjKG - 1) / kProjKG) * s.M * s.E : 0);
   L.ppack = take(s.gemm_bf16 ? 2 * (size_t)s.C * s.E : 0);
   L.edt_part = take(4 * (size_t)kDirSplitPackets * kDirPartFloats);
-  L.tkp = take(s.gemm_bf16 ? (size_t)s.tkp_elems * s.tkp_esize : 0);
+  L.tkp = take(s.pack_tokens ? 2 * (size_t)s.tkp_elems : 0);
   L.extra = take((size_t)s.extra_bytes);
   L.total = off;
   return L;
@@ -351,7 +351,6 @@ void finish_plan(Plan& p, const PlanAcc& a) {
   s.sumG = a.sumG;
   s.sumMGs = a.sumMGs;
   s.tkp_elems = a.tkp;
-  s.tkp_esize = 2;
   s.gmax = a.gmax;
   s.nchunk = a.nchunk;
   s.item_cap = (int)std::min<int64_t>(a.item_cap, INT32_MAX / 2);
@@ -360,8 +359,9 @@ void finish_plan(Plan& p, const PlanAcc& a) {
   p.L = make_layout(s);
 }
 
-void begin_plan(Plan& p, int n_frames, int C, int E, int gemm_bf16) {
+void begin_plan(Plan& p, int n_frames, int C, int E, int gemm_bf16, int tok_dtype) {
   Shape& s = p.shape;
+  s.pack_tokens = gemm_bf16 && tok_dtype == DISC_F8E4M3;
   s.n_frames = n_frames;
   s.want_dbar = false;
   s.max_rows = 0;
@@ -371,8 +371,7 @@ void begin_plan(Plan& p, int n_frames, int C, int E, int gemm_bf16) {
 }
 
 void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Plan& p, int tok_dtype) {
-  (void)tok_dtype;
-  begin_plan(p, (int)fr.size(), C, E, gemm_bf16);
+  begin_plan(p, (int)fr.size(), C, E, gemm_bf16, tok_dtype);
   PlanAcc a;
   p.fds.resize(fr.size());
   for (size_t i = 0; i < fr.size(); ++i) {
@@ -675,9 +674,9 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   const int4* tiles = reinterpret_cast<const int4*>(dev_ws + p.L.tiles);
   // token statistics first: the mask scan folds r into the mean distinctiveness
   const bool want_r = o.distinct || p.shape.want_dbar;
-  if (want_r || p.shape.gemm_bf16) {
+  if (want_r || p.shape.pack_tokens) {
     StageTimer t(sid < 0 ? -1 : ST_STATS, st);
-    launch_token_stats(b, w, p.shape.gmax, want_r, p.shape.gemm_bf16, st);
+    launch_token_stats(b, w, p.shape.gmax, want_r, p.shape.pack_tokens, st);
     if (p.shape.want_dbar) launch_rbar(b, w, st);
   }
   { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st, p.shape.want_dbar); }
@@ -973,8 +972,8 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32
   const Work w = work_ptrs(cx.dev_ws, p.L);
   const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
   launch_user_weights(b, w, wts, cx.st);
+  if (p.shape.pack_tokens) launch_token_stats(b, w, p.shape.gmax, 0, 1, cx.st);
   launch_pool_order(b, w, cx.st);
-  if (p.shape.gemm_bf16) launch_token_stats(b, w, p.shape.gmax, 0, 1, cx.st);
   launch_pool(b, w, tiles, cx.st, o.pool_tile > 0 ? o.pool_tile : 1);
   launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, cx.st);
   if ((st = check_launch(who))) return st;

@@ -87,6 +87,16 @@ __device__ __forceinline__ float e4m3_to_f32(uint32_t code) {
 
 __device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
 
+// Workgroup b of a launch runs on XCD b % 8 (each XCD has its own L2).
+// xcd_remap gives each XCD a contiguous range of the n live workgroups of a
+// launch (a bijection of [0, n)), so workgroups that read the same data (the
+// channel tiles of one mask tile, the strips of one mask) share an L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
+  return x * q + min(x, r) + k;
+}
+
 struct FrameDesc {
   const void* tokens;     // [G][C] in tok_dtype
   const float* scale;     // [G] for FP8 tokens
@@ -102,7 +112,7 @@ struct FrameDesc {
   int32_t Gs;             // row stride of the per-mask weight rows (G rounded up to 8)
   int64_t w_base;         // element offset of this frame's [m][Gs] block in s/W
   int64_t r_base;         // offset of this frame's G entries in r
-  int64_t t_base;         // element offset of this frame's k-packed tokens
+  int64_t t_base;         // element offset of this frame's k-packed tokens (FP8 tokens, BF16 GEMMs)
 };
 
 // Scalar arguments shared by the kernels of one call.  n_frames and M are
@@ -147,9 +157,9 @@ struct Work {
   float* ppart;        // pooling group sums [tile][kgroups][64*64] (split K only)
   int4* ptile;         // per pooling tile: (first, end K group), then its 64 rows as pool_rows gives them (split K only)
   float* qpart;        // projection group sums [C/256][M][E] (split K only)
+  void* tkp;           // FP8 tokens with BF16 GEMMs: k-packed copy [sum ceil(G/8)][C][8], the code values widened to BF16
   float* edt_part;     // direct EDT block partial sums of shared packets [kDirSplitPackets][kDirPartFloats]
   void* ppack;         // k-packed BF16 copy of P [C/8][E][8] (BF16 GEMMs)
-  void* tkp;           // k-packed tokens [sum ceil(G/8)][C][8], BF16 bits (FP8 tokens: their code values)
 };
 
 // Host-side launchers (stream = hipStream_t).
@@ -202,7 +212,8 @@ void launch_pool_order(const Batch& b, const Work& w, hipStream_t st);
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode = -1,
                 bool order_pool = false);
 void edt_prepare();
-// want_r: residual norms (needs the mean); pack: k-packed token copy for the BF16 pooling GEMM
+// want_r: frame means and residual norms r (gmax: the largest G); pack: the
+// k-packed BF16 copy of FP8 tokens that the BF16 pooling GEMM reads
 void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
 void launch_rbar(const Batch& b, const Work& w, hipStream_t st);

@@ -22,12 +22,12 @@ struct Shape {
   int n_frames = 0;
   int64_t M = 0, sumG = 0, sumMGs = 0;
   int C = 0, E = 0, gmax = 0, nchunk = 1, item_cap = 1, n_tiles = 0, gemm_bf16 = 0;
-  int64_t tkp_elems = 0;  // sum over frames of ceil(G/8)*8*C (k-packed tokens, BF16 GEMM only)
-  int tkp_esize = 2;      // bytes per k-packed element (BF16)
   int kgroups = 1;        // pooling K groups of the largest frame
   int pool_split = 1, proj_split = 1;
   bool want_dbar = false;  // some frame asks for the mean distinctiveness (needs r and its mean)
   int max_rows = kMaxRows;  // tallest frame + 2 (distance-transform rows of the tallest item)
+  int pack_tokens = 0;     // FP8 tokens with BF16 GEMMs: the k-packed BF16 copy is kept
+  int64_t tkp_elems = 0;  // sum over frames of ceil(G/8)*8*C (that copy)
   int64_t extra_bytes = 0;  // appended region (e.g. the heat-map's projected tokens)
 };
 
@@ -80,7 +80,7 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
 // plan_frame per frame (its descriptor and the pooling tiles
 // (frame, m0, n0) for m0 in steps of 64, n0 in steps of 64 below C), then
 // finish_plan (totals and layout).
-void begin_plan(Plan& p, int n_frames, int C, int E, int gemm_bf16);
+void begin_plan(Plan& p, int n_frames, int C, int E, int gemm_bf16, int tok_dtype);
 FrameDesc plan_frame(const FrameIn& f, int C, Shape& s, PlanAcc& a);
 void finish_plan(Plan& p, const PlanAcc& a);
 disc_status describe_one(const disc_tokens* tokens, const disc_masks* masks, const disc_proj* proj, disc_out* out,

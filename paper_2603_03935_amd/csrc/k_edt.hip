@@ -144,12 +144,12 @@ __device__ __forceinline__ int g_rec(uint4 r, int l) {
 // Site m (p < m < q, parabola heights F) never lies strictly below both p and
 // q: q overtakes p no later than m does, i.e. Aq/(q-p) <= Am/(m-p) with
 // A = F - Fp + (site^2 - p^2).  |A| < 2^27 (g < 2^14) and the row distances
-// are below 2^11, so both products are below 2^38 and exact in double
-// precision (cheaper on gfx950 than 64-bit integer products).
+// are below 2^11, so both products are below 2^38: exact 64-bit integer
+// products.
 __device__ __forceinline__ bool dominated(int p, int Fp, int m, int Fm, int q, int Fq) {
   const int Am = (Fm - Fp) + __mul24(m - p, m + p);
   const int Aq = (Fq - Fp) + __mul24(q - p, q + p);
-  return (double)Aq * (double)(m - p) <= (double)Am * (double)(q - p);
+  return (int64_t)Aq * (m - p) <= (int64_t)Am * (q - p);
 }
 
 __device__ __forceinline__ int parab(int site, int F, int y) { return __mul24(y - site, y - site) + F; }
@@ -444,11 +444,11 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
     BandBits<NW> w;
     // Stack top s1 and the site below it, s2, with K = F + site^2.  The top
     // is dominated by a new site u iff (Ku - K2)(s1 - s2) <= (K1 - K2)(u - s2)
-    // (the three-site test above in this form); the products are below 2^39
-    // and exact in FP64.  d12 = s1 - s2 and dK = K1 - K2 are kept in FP64
+    // (the three-site test above in this form); the products are below 2^39,
+    // exact in 64-bit integers.  d12 = s1 - s2 and dK = K1 - K2 are kept
     // while the stack is unchanged.
     int depth = 0, s1 = 0, s2 = 0, K1 = 0, K2 = 0;
-    double d12 = 0.0, dK = 0.0;
+    int d12 = 0, dK = 0;
     for (int u = b0; u < b1; ++u) {
       uint4 ru;
       if (NR == 1) {
@@ -460,7 +460,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
       }
       const int gu = many ? g_rec(ru, lane) : g_runs(ru, lane);
       const int Ku = (lane_ok ? sq16(gu) : 0) + u * u;
-      bool pop = depth >= 2 && (double)(Ku - K2) * d12 <= dK * (double)(u - s2);
+      bool pop = depth >= 2 && (int64_t)(Ku - K2) * d12 <= (int64_t)dK * (u - s2);
       while (pop) {
         w.clear(s1 - b0);
         --depth;
@@ -470,9 +470,9 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
         if (depth >= 2) {
           s2 = b0 + w.prev(s1 - b0);
           K2 = gsq(rec, s2, lane, lane_ok, many) + __mul24(s2, s2);
-          d12 = (double)(s1 - s2);
-          dK = (double)(K1 - K2);
-          pop = (double)(Ku - K2) * d12 <= dK * (double)(u - s2);
+          d12 = s1 - s2;
+          dK = K1 - K2;
+          pop = (int64_t)(Ku - K2) * d12 <= (int64_t)dK * (u - s2);
         }
       }
       w.set(u - b0);
@@ -481,8 +481,8 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
       s1 = u;
       K1 = Ku;
       ++depth;
-      d12 = (double)(s1 - s2);
-      dK = (double)(K1 - K2);
+      d12 = s1 - s2;
+      dK = K1 - K2;
     }
 #pragma unroll
     for (int i = 0; i < NW; ++i) bm[((b0 >> 5) + i) * 64 + lane] = w.word(i);
@@ -965,14 +965,6 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
         const int b0v = best[0], b1v = best[1], b2v = best[2], b3v = best[3];
         us2 B[2] = {as_us2((uint32_t)b0v | ((uint32_t)b1v << 16)), as_us2((uint32_t)b2v | ((uint32_t)b3v << 16))};
         int pmax = max(max(b0v, b1v), max(b2v, b3v));
-        // (d + i)^2 for the step's distances, both halves alike, advanced by
-        // saturating adds of 8 (d + i) + 16 per step of four
-        us2 D[kDirSteps], inc[kDirSteps];
-#pragma unroll
-        for (int i = 0; i < kDirSteps; ++i) {
-          D[i] = as_us2((uint32_t)((1 + i) * (1 + i)) * 0x10001u);
-          inc[i] = as_us2((uint32_t)(8 * (1 + i) + 16) * 0x10001u);
-        }
         for (int d = 1; d * d < pmax; d += kDirSteps) {
           const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * 64;
           const uint2* pd = base + ((d - 1) >> 2) * 64;
@@ -987,15 +979,17 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
           }
 #pragma unroll
           for (int i = 0; i < kDirSteps; ++i) {
+            // (d + i)^2 is the same for every lane: scalar arithmetic, one
+            // scalar operand of the packed adds
+            const uint32_t dd = (uint32_t)min((d + i) * (d + i), 65535);
+            const us2 D = as_us2(dd | (dd << 16));
 #pragma unroll
             for (int q = 0; q < 2; ++q) {  // rows 2q, 2q + 1 at distance d + i
               const uint32_t up = (i & 1) ? U[(3 + 2 * q - i) >> 1] : Uo[(2 + 2 * q - i) >> 1];
               const uint32_t dn = (i & 1) ? Dn[(1 + 2 * q + i) >> 1] : Do[(2 * q + i) >> 1];
               B[q] = __builtin_elementwise_min(
-                  B[q], __builtin_elementwise_add_sat(__builtin_elementwise_min(as_us2(up), as_us2(dn)), D[i]));
+                  B[q], __builtin_elementwise_add_sat(__builtin_elementwise_min(as_us2(up), as_us2(dn)), D));
             }
-            D[i] = __builtin_elementwise_add_sat(D[i], inc[i]);
-            inc[i] = inc[i] + as_us2(32u * 0x10001u);
           }
           pmax = max4(B[0], B[1]);
         }
@@ -1041,7 +1035,18 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
   int cnt[kClasses];
   const int total = direct_count(counts, item_cap, ROWS > 512, cnt);
   const int S = direct_split(ROWS > 512, total, gridDim.x);
-  for (int vp = blockIdx.x; vp < total * S; vp += gridDim.x) {
+  // Virtual packets (packet, share) in chunks of kXcds: chunk c goes to the
+  // workgroups on XCD c % kXcds, which take its packets in order.  The shares
+  // of a packet and neighbouring packets (the strips of one mask, in scan
+  // order) then read the same mask rows through one L2, while every XCD
+  // still starts with the tallest packets.
+  const int N = total * S;
+  const int x = blockIdx.x % kXcds, nb = (gridDim.x - x + kXcds - 1) / kXcds;
+  const bool by_xcd = gridDim.x >= kXcds;  // else a plain stride
+  for (int i = 0;; ++i) {
+    const int t = blockIdx.x / kXcds + i * nb;
+    const int vp = by_xcd ? kXcds * (x + kXcds * (t / kXcds)) + t % kXcds : blockIdx.x + i * gridDim.x;
+    if (vp >= N) break;
     const int p = vp / S, s = vp - p * S;
     const int cls = direct_load_packet(cnt, items, item_cap, mrec, p, recs, words);
     float* part = S == 1 ? part_all : gpart + (int64_t)p * kDirPartFloats;

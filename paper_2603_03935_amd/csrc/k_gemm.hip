@@ -157,9 +157,15 @@ template <int BF16, int TOK, int NT>
 __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tiles) {
   constexpr int BN = PBN * NT;  // channels per workgroup
   const int S = b.pool_split;
-  const int stix = blockIdx.x / S, sidx = blockIdx.x - stix * S;
+  const int nlive = b.dyn[2] / NT * S;  // live workgroups (NT divides the channel tiles of a mask tile)
+  if ((int)blockIdx.x >= nlive) return;
+  // without split K, one XCD takes consecutive super-tiles (the channel tiles
+  // of one mask tile share its weight rows through that XCD's L2; cfg5
+  // pooling 0.44 -> 0.29 ms); split launches (small batches) keep the plain
+  // order, which measured faster for them
+  const int vb = S == 1 ? xcd_remap(blockIdx.x, nlive) : (int)blockIdx.x;
+  const int stix = vb / S, sidx = vb - stix * S;
   const int tix = stix * NT;  // first 64-channel tile
-  if (tix >= b.dyn[2]) return;
   const int4 t = tiles[tix];
   const FrameDesc fd = b.frames[t.x];
   const int m0 = t.y, n0 = t.z, C = b.C;
@@ -203,7 +209,13 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   const int ar = tid >> 2, ak = (tid & 3) * 8;        // A: row, first k of 8
   const bool arow_ok = ar < mrows;
   const int64_t wrow0 = fd.w_base + (int64_t)(arow_ok ? wk.perm[fd.mask_base + m0 + ar] : 0) * fd.Gs;
-  // B (BF16): channels (tid & 63) + 64 j, patches 8*(tid >> 6) .. +7
+  // B (BF16), BF16 and FP32 tokens: the caller's [G][C] tokens, patches
+  // 2 pp, 2 pp + 1 and channels c4 .. c4 + 3 (+ 64 j) per thread, transposed
+  // into LDS.  FP8 tokens: the k-packed copy (channels (tid & 63) + 64 j,
+  // patches 8 (tid >> 6) .. +7, one 16-byte load), whose code values were
+  // widened once by the statistics pass (widening in every pooling workgroup
+  // that reads a token measured 2.7x slower at 16 x 1080p)
+  const int bpp = tid >> 4, bc4 = (tid & 15) * 4;
   const int bn16 = tid & 63, bk16 = (tid >> 6) * 8;
   // B (FP32): patch tid >> 3, channels 8*(tid & 7) + 64 j .. +7
   const int bk32 = tid >> 3, bn32 = (tid & 7) * 8;
@@ -212,51 +224,80 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   // flight while step k computes (small batches are latency-bound).  BF16:
   // one set, one step ahead (more resident workgroups hide the latency).
   constexpr int DIST = BF16 ? 1 : 2;
-  uint4 ra16[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)}, rb16[2][NT];
+  uint4 ra16[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+  uint4 rbr[2][NT][2];  // raw token words: FP32 float4 bits, BF16 .xy, FP8 .x
   float ra32[2][8], rb32[2][NT][8];
 
   auto fetch = [&](int k0, int q) {
     const int kk = k0 + ak;
+    // weight rows are Gs (a multiple of 8) long and hold exact zeros outside
+    // the mask's patch rectangle
     if (BF16) {
       const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0 + kk;
-      if (arow_ok && kk + 8 <= G) {
-        ra16[q] = *reinterpret_cast<const uint4*>(src);
-      } else {
-        uint16_t tmp[8];
-        for (int j = 0; j < 8; ++j) tmp[j] = (arow_ok && kk + j < G) ? src[j] : (uint16_t)0;
-        ra16[q] = make_uint4(tmp[0] | (tmp[1] << 16), tmp[2] | (tmp[3] << 16), tmp[4] | (tmp[5] << 16), tmp[6] | (tmp[7] << 16));
+      ra16[q] = arow_ok && kk < G ? *reinterpret_cast<const uint4*>(src) : make_uint4(0u, 0u, 0u, 0u);
+      if (TOK == 2) {
+        const int grp = (k0 + bk16) >> 3;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          rbr[q][j][0] = grp * 8 < G ? *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(wk.tkp) + fd.t_base +
+                                                                        ((int64_t)grp * C + n0 + bn16 + 64 * j) * 8)
+                                     : make_uint4(0u, 0u, 0u, 0u);
+        }
+        return;
       }
-      // k-packed tokens: one vector load gives one channel's 8 patches
-      const int grp = (k0 + bk16) >> 3;
+      const int kb = k0 + 2 * bpp;
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
-        if (grp * 8 < G) {
-          const int64_t e = fd.t_base + ((int64_t)grp * C + n0 + bn16 + 64 * j) * 8;
-          rb16[q][j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(wk.tkp) + e);
-        } else {
-          rb16[q][j] = make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          uint4 v = make_uint4(0u, 0u, 0u, 0u);
+          if (kb + h < G) {
+            const int64_t off = (int64_t)(kb + h) * C + n0 + 64 * j + bc4;
+            if (TOK == 0) {
+              v = *reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(fd.tokens) + off);
+            } else if (TOK == 1) {
+              const uint2 t2 = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(fd.tokens) + off);
+              v.x = t2.x;
+              v.y = t2.y;
+            }
+          }
+          rbr[q][j][h] = v;
         }
       }
     } else {
       // weight rows start on 8 elements (Gs and the frame bases are multiples of 8)
       const float* src = reinterpret_cast<const float*>(wk.W) + wrow0 + kk;
-      if (arow_ok && kk + 8 <= G) {
+      if (arow_ok && kk < G) {
         const float4 x = reinterpret_cast<const float4*>(src)[0], y = reinterpret_cast<const float4*>(src)[1];
         ra32[q][0] = x.x; ra32[q][1] = x.y; ra32[q][2] = x.z; ra32[q][3] = x.w;
         ra32[q][4] = y.x; ra32[q][5] = y.y; ra32[q][6] = y.z; ra32[q][7] = y.w;
       } else {
-        for (int j = 0; j < 8; ++j) ra32[q][j] = (arow_ok && kk + j < G) ? src[j] : 0.f;
+        for (int j = 0; j < 8; ++j) ra32[q][j] = 0.f;
       }
       const int kr = k0 + bk32;
 #pragma unroll
       for (int j = 0; j < NT; ++j) load_tok8<TOK, 0>(fd.tokens, (int64_t)kr * C + n0 + bn32 + 64 * j, kr < G, nullptr, rb32[q][j]);
     }
   };
+  // BF16 bits of channel e of a raw token word (FP32 or BF16 tokens)
+  auto raw_bf16 = [&](const uint4& v, int e) -> uint32_t {
+    if (TOK == 0) return f2bf(__uint_as_float(e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w));
+    return ((e < 2 ? v.x : v.y) >> (16 * (e & 1))) & 0xFFFFu;
+  };
   auto stage = [&](int q) {
     if (BF16) {
       *reinterpret_cast<uint4*>(&As16[ar * PAS + ak]) = ra16[q];
+      if (TOK == 2) {
 #pragma unroll
-      for (int j = 0; j < NT; ++j) *reinterpret_cast<uint4*>(&Bs16[(bn16 + 64 * j) * PAS + bk16]) = rb16[q][j];
+        for (int j = 0; j < NT; ++j) *reinterpret_cast<uint4*>(&Bs16[(bn16 + 64 * j) * PAS + bk16]) = rbr[q][j][0];
+        return;
+      }
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)  // channel bc4 + e: patches 2 pp and 2 pp + 1 as one word
+          *reinterpret_cast<uint32_t*>(&Bs16[(64 * j + bc4 + e) * PAS + 2 * bpp]) =
+              raw_bf16(rbr[q][j][0], e) | (raw_bf16(rbr[q][j][1], e) << 16);
     } else {
       for (int j = 0; j < 8; ++j) As32[ar * (PBK + 1) + ak + j] = ra32[q][j];
 #pragma unroll
@@ -283,15 +324,20 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   };
 
   const int lr = lane & 31, lk = lane >> 5;
-  int cur = kstart / kPoolKG;
-  auto step = [&](int k0, int q) {
-    if (k0 / kPoolKG != cur) {
+  // K groups of this share, each folded once, in order
+  int cur = ga;
+  auto advance = [&](int g) {
+    while (cur < g) {
       fold(cur);
-      cur = k0 / kPoolKG;
+      ++cur;
     }
+  };
+  // one K step on register set q; kf: the step to fetch into q meanwhile
+  auto step = [&](int k0, int q, int kf) {
+    advance(k0 / kPoolKG);
     stage(q);
     __syncthreads();
-    if (k0 + DIST * PBK < kstop) fetch(k0 + DIST * PBK, q);
+    if (kf < kstop) fetch(kf, q);
     if (BF16) {
 #pragma unroll
       for (int kk = 0; kk < PBK; kk += 16) {
@@ -319,14 +365,14 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   if (DIST == 2) {
     if (kstart + PBK < kstop) fetch(kstart + PBK, 1);
     for (int k0 = kstart; k0 < kstop; k0 += 2 * PBK) {
-      step(k0, 0);
+      step(k0, 0, k0 + 2 * PBK);
       if (k0 + PBK >= kstop) break;
-      step(k0 + PBK, 1);
+      step(k0 + PBK, 1, k0 + 3 * PBK);
     }
   } else {
-    for (int k0 = kstart; k0 < kstop; k0 += PBK) step(k0, 0);
+    for (int k0 = kstart; k0 < kstop; k0 += PBK) step(k0, 0, k0 + PBK);
   }
-  if (kstart < kstop) fold(cur);
+  advance(gb);
   if (S == 1) {
     __shared__ int4 rows[PBM];
     pool_rows(wk, fd, m0, tid, rows);

@@ -117,40 +117,41 @@ __global__ __launch_bounds__(256) void k_mean(Batch b, Work wk) {
 
 // One workgroup per group of 8 consecutive tokens p0..p0+7 of a frame:
 //   * WANT_R: r_p = ||f_p - mean|| for the 8 tokens (block reduction);
-//   * PACK:   the k-packed copy tkp[p0/8][c][0..7] = (f_p0..f_p7)[c] that the
-//             BF16 pooling GEMM reads with one vector load per (8 patches,
-//             channel): BF16 bits (FP32 tokens rounded to nearest even; the
-//             unscaled e4m3 code values for FP8 tokens, exact).  Tokens past
-//             G pack as 0.
-// Each thread owns CW consecutive channels and loads them for all 8 tokens.
+//   * PACK (FP8 tokens with BF16 GEMMs only): the k-packed copy
+//     tkp[p0/8][c][0..7] = the 8 tokens' code values of channel c widened
+//     exactly to BF16, which the pooling GEMM reads with one vector load per
+//     (8 patches, channel).  Widening once here is cheaper than in every
+//     pooling workgroup that reads the token.  BF16 and FP32 tokens are read
+//     by the pooling GEMM in the caller's layout.
+// Each thread owns CW consecutive channels and loads them for all 8 tokens
+// (FP8: value = scale * code).
 template <int TOK, int WANT_R, int PACK>
-__global__ __launch_bounds__(256) void k_tokpack(Batch b, Work wk) {
+__global__ __launch_bounds__(256) void k_resid(Batch b, Work wk) {
   constexpr int CW = TOK == 2 ? 8 : 4;
   const int f = blockIdx.y;
   if (f >= b.dyn[0]) return;
   const FrameDesc fd = b.frames[f];
   const int G = fd.G, C = b.C;
-  const int grp = blockIdx.x, p0 = grp * 8;
+  const int p0 = blockIdx.x * 8;
   if (p0 >= G) return;
   const int tid = threadIdx.x;
   const float* mu = wk.mean + (int64_t)f * C;
   float ss[8];
   for (int i = 0; i < 8; ++i) ss[i] = 0.f;
-  if (TOK == 2) {
-    // FP8: each code is widened once to BF16 bits (exact), which serve both
-    // the k-packed copy and (times the token's scale) the residual norms;
-    // channel by channel, so nothing is held per (token, channel)
-    float sc[8];
-    for (int i = 0; i < 8; ++i) sc[i] = (WANT_R && p0 + i < G) ? fd.scale[p0 + i] : 0.f;
-    for (int chunk = tid; chunk < C / CW; chunk += 256) {
-      const int c = chunk * CW;
+  for (int chunk = tid; chunk < C / CW; chunk += 256) {
+    const int c = chunk * CW;
+    if (TOK == 2) {
+      // each code widened once to BF16 bits (exact): the packed copy and,
+      // times the token's scale, the residual norms
       uint2 codes[8];
+      float sc[8];
       for (int i = 0; i < 8; ++i) {
         const int p = p0 + i;
         codes[i] = p < G ? *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(fd.tokens) + (int64_t)p * C + c)
                          : make_uint2(0u, 0u);
+        sc[i] = (WANT_R && p < G) ? fd.scale[p] : 0.f;
       }
-      uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
+      uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)blockIdx.x * C + c) * 8);
       for (int j = 0; j < 8; ++j) {
         uint32_t q[8];
         for (int i = 0; i < 8; ++i) q[i] = e4m3_to_bf16_bits(((j < 4 ? codes[i].x : codes[i].y) >> (8 * (j & 3))) & 0xFFu);
@@ -163,64 +164,27 @@ __global__ __launch_bounds__(256) void k_tokpack(Batch b, Work wk) {
           }
         }
       }
-    }
-  } else {
-  for (int chunk = tid; chunk < C / CW; chunk += 256) {
-      const int c = chunk * CW;
+    } else {
       float v[8][CW];
-      uint2 codes[8];  // FP8 only: the 8 raw codes of channels c..c+7
       for (int i = 0; i < 8; ++i) {
         const int p = p0 + i;
-        codes[i] = make_uint2(0u, 0u);
         for (int j = 0; j < CW; ++j) v[i][j] = 0.f;
         if (p >= G) continue;
         const int64_t off = (int64_t)p * C + c;
         if (TOK == 0) {
-          const float4 a = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(fd.tokens) + off);
-          v[i][0] = a.x; v[i][1] = a.y; v[i][2] = a.z; v[i][3] = a.w;
-        } else if (TOK == 1) {
-          const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(fd.tokens) + off);
-          v[i][0] = bf16_to_f32(a.x & 0xFFFFu); v[i][1] = bf16_to_f32(a.x >> 16);
-          v[i][2] = bf16_to_f32(a.y & 0xFFFFu); v[i][3] = bf16_to_f32(a.y >> 16);
+          const float4 x = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(fd.tokens) + off);
+          v[i][0] = x.x; v[i][1] = x.y; v[i][2] = x.z; v[i][3] = x.w;
         } else {
-          const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(fd.tokens) + off);
-          codes[i] = a;
-          if (WANT_R) {
-            const float sc = fd.scale[p];
-            for (int j = 0; j < 8; ++j) v[i][j] = sc * e4m3_to_f32(((j < 4 ? a.x : a.y) >> (8 * (j & 3))) & 0xFFu);
-          }
+          const uint2 x = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(fd.tokens) + off);
+          v[i][0] = bf16_to_f32(x.x & 0xFFFFu); v[i][1] = bf16_to_f32(x.x >> 16);
+          v[i][2] = bf16_to_f32(x.y & 0xFFFFu); v[i][3] = bf16_to_f32(x.y >> 16);
         }
       }
-      if (WANT_R) {
-        for (int j = 0; j < CW; ++j) {
-          const float m = mu[c + j];
-          for (int i = 0; i < 8; ++i) {
-            const float dd = (p0 + i < G) ? v[i][j] - m : 0.f;
-            ss[i] += dd * dd;
-          }
-        }
-      }
-      if (PACK) {
-        if (TOK == 2) {
-          // channel j: the code values of tokens 0..7 widened (exactly) to BF16
-          // -> 16 bytes; the per-token scales live in the weights
-          uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
-          for (int j = 0; j < 8; ++j) {
-            uint32_t q[8];
-            for (int i = 0; i < 8; ++i) q[i] = e4m3_to_bf16_bits(((j < 4 ? codes[i].x : codes[i].y) >> (8 * (j & 3))) & 0xFFu);
-            dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
-          }
-        } else {
-          // channel j: the BF16 values of tokens 0..7 -> 16 bytes
-          uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)grp * C + c) * 8);
-          for (int j = 0; j < 4; ++j) {
-            uint32_t q[8];
-            for (int i = 0; i < 8; ++i) {
-              const uint32_t u = __float_as_uint(v[i][j]);
-              q[i] = TOK == 1 ? (u >> 16) : ((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-            }
-            dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
-          }
+      for (int j = 0; j < CW; ++j) {
+        const float m = mu[c + j];
+        for (int i = 0; i < 8; ++i) {
+          const float dd = (p0 + i < G) ? v[i][j] - m : 0.f;
+          ss[i] += dd * dd;
         }
       }
     }
@@ -229,9 +193,9 @@ __global__ __launch_bounds__(256) void k_tokpack(Batch b, Work wk) {
     __shared__ float red[4][8];
     const int lane = tid & 63, wv = tid >> 6;
     for (int i = 0; i < 8; ++i) {
-      float a = ss[i];
-      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-      if (lane == 0) red[wv][i] = a;
+      float x = ss[i];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+      if (lane == 0) red[wv][i] = x;
     }
     __syncthreads();
     if (tid < 8 && p0 + tid < G)
@@ -239,14 +203,8 @@ __global__ __launch_bounds__(256) void k_tokpack(Batch b, Work wk) {
   }
 }
 
-template <int TOK>
-static void launch_tokpack_t(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st) {
-  const dim3 grid((gmax + 7) / 8, b.n_frames), block(256);
-  if (want_r && pack) hipLaunchKernelGGL((k_tokpack<TOK, 1, 1>), grid, block, 0, st, b, w);
-  else if (want_r) hipLaunchKernelGGL((k_tokpack<TOK, 1, 0>), grid, block, 0, st, b, w);
-  else if (pack) hipLaunchKernelGGL((k_tokpack<TOK, 0, 1>), grid, block, 0, st, b, w);
-}
-
+// Token statistics of every frame (want_r): chunk partial sums, the frame
+// mean, then r; and (pack) the k-packed copy of FP8 tokens.
 void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st) {
   if (want_r) {
     const dim3 cgrid(b.nchunk, b.n_frames);
@@ -255,10 +213,16 @@ void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int
     else hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
     hipLaunchKernelGGL(k_mean, dim3((b.C + 255) / 256, b.n_frames), dim3(256), 0, st, b, w);
   }
-  if (!want_r && !pack) return;
-  if (b.tok_dtype == 0) launch_tokpack_t<0>(b, w, gmax, want_r, pack, st);
-  else if (b.tok_dtype == 1) launch_tokpack_t<1>(b, w, gmax, want_r, pack, st);
-  else launch_tokpack_t<2>(b, w, gmax, want_r, pack, st);
+  pack = pack && b.tok_dtype == 2;
+  const dim3 rgrid((gmax + 7) / 8, b.n_frames);
+  if (b.tok_dtype == 2) {
+    if (want_r && pack) hipLaunchKernelGGL((k_resid<2, 1, 1>), rgrid, dim3(256), 0, st, b, w);
+    else if (want_r) hipLaunchKernelGGL((k_resid<2, 1, 0>), rgrid, dim3(256), 0, st, b, w);
+    else if (pack) hipLaunchKernelGGL((k_resid<2, 0, 1>), rgrid, dim3(256), 0, st, b, w);
+  } else if (want_r) {
+    if (b.tok_dtype == 0) hipLaunchKernelGGL((k_resid<0, 1, 0>), rgrid, dim3(256), 0, st, b, w);
+    else hipLaunchKernelGGL((k_resid<1, 1, 0>), rgrid, dim3(256), 0, st, b, w);
+  }
 }
 
 // D = r / (mean(r) + eps) for one frame (stage entry point only).
@@ -345,42 +309,53 @@ __device__ __forceinline__ float z_term(float wr, float wu, bool fp8, float sc) 
   return BF16 ? __uint_as_float((uint32_t)f32_to_bf16_rne(wu) << 16) : wu;
 }
 
+// The GEMM weights of one mask: a dense row of Gs elements (G rounded up to
+// 8), the weight inside the mask's patch rectangle and exact zeros elsewhere,
+// stored 8 elements at a time (the pooling GEMM loads whole 8-element chunks
+// and needs no masking).  Chunks outside the rectangle are plain zero stores.
 template <int BF16>
 __device__ float write_row(const Batch& b, const Work& wk, const FrameDesc& fd, int64_t rowoff, int pr0, int pr1,
                            int pc0, int pc1, bool use_r, Neu& z, float& ssum) {
-  const int G = fd.G, gw = fd.gw;
+  const int gw = fd.gw, G = fd.G, nch = fd.Gs / 8;
   const bool fp8 = b.tok_dtype == 2;
   const float* r = wk.r + fd.r_base;
-  int pr = threadIdx.x / gw, pc = threadIdx.x % gw;
-  const int dpr = 256 / gw, dpc = 256 % gw;
-  for (int p = threadIdx.x; p < G; p += 256) {
-    float wv = 0.f, wu = 0.f, sc = 1.f;
-    if (pr >= pr0 && pr <= pr1 && pc >= pc0 && pc <= pc1) {
-      const float sv = wk.s[rowoff + p];
-      ssum += sv;
-      wu = use_r ? sv * r[p] : sv;
-      wv = wu;
-      if (fp8) {
-        sc = fd.scale[p];
-        wv *= sc;
+  const int rlo = pr1 >= pr0 ? pr0 * gw + pc0 : G, rhi = pr1 >= pr0 ? pr1 * gw + pc1 : -1;
+  for (int c = threadIdx.x; c < nch; c += 256) {
+    const int p0 = 8 * c;
+    float wv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) wv[e] = 0.f;
+    if (p0 <= rhi && p0 + 7 >= rlo) {
+      int pr = p0 / gw, pc = p0 - pr * gw;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int p = p0 + e;
+        if (p < G && pr >= pr0 && pr <= pr1 && pc >= pc0 && pc <= pc1) {
+          const float sv = wk.s[rowoff + p];
+          ssum += sv;
+          const float wu = use_r ? sv * r[p] : sv;
+          const float sc = fp8 ? fd.scale[p] : 1.f;
+          float w = fp8 ? wu * sc : wu;
+          if (BF16) w = __uint_as_float((uint32_t)f32_to_bf16_rne(w) << 16);
+          wv[e] = w;
+          const float zt = z_term<BF16>(w, wu, fp8, sc);
+          if (zt != 0.f) neu_add(z, zt);
+        }
+        if (++pc == gw) {
+          pc = 0;
+          ++pr;
+        }
       }
     }
-    float wr;
     if (BF16) {
-      const uint16_t hb = f32_to_bf16_rne(wv);
-      reinterpret_cast<uint16_t*>(wk.W)[rowoff + p] = hb;
-      wr = __uint_as_float((uint32_t)hb << 16);
+      uint32_t h[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) h[e] = (__float_as_uint(wv[2 * e]) >> 16) | (__float_as_uint(wv[2 * e + 1]) & 0xFFFF0000u);
+      *reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.W) + rowoff + p0) = make_uint4(h[0], h[1], h[2], h[3]);
     } else {
-      reinterpret_cast<float*>(wk.W)[rowoff + p] = wv;
-      wr = wv;
-    }
-    const float zt = z_term<BF16>(wr, wu, fp8, sc);
-    if (zt != 0.f) neu_add(z, zt);
-    pc += dpc;
-    pr += dpr;
-    if (pc >= gw) {
-      pc -= gw;
-      pr += 1;
+      float4* dst = reinterpret_cast<float4*>(reinterpret_cast<float*>(wk.W) + rowoff + p0);
+      dst[0] = make_float4(wv[0], wv[1], wv[2], wv[3]);
+      dst[1] = make_float4(wv[4], wv[5], wv[6], wv[7]);
     }
   }
   return 0.f;
@@ -503,6 +478,10 @@ __global__ __launch_bounds__(256) void k_user_weights(Batch b, Work wk, const fl
   const bool fp8 = b.tok_dtype == 2;
   __shared__ float red[8];
   Neu z{0.f, 0.f};
+  for (int p = G + threadIdx.x; p < fd.Gs; p += 256) {  // the row's tail: zeros (the GEMM loads 8 at a time)
+    if (BF16) reinterpret_cast<uint16_t*>(wk.W)[rowoff + p] = 0;
+    else reinterpret_cast<float*>(wk.W)[rowoff + p] = 0.f;
+  }
   for (int p = threadIdx.x; p < G; p += 256) {
     const float wu = wts[(int64_t)(g - fd.mask_base) * G + p];
     const float sc = fp8 ? fd.scale[p] : 1.f;

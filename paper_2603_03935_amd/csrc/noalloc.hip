@@ -85,7 +85,7 @@ extern "C" disc_status disc_embed_masks_noalloc(const disc_tokens* tokens, const
   const disc_options o = opts ? *opts : defaults();
   if (f.m == 0) return ok();
   Plan p;  // its host vectors stay empty
-  begin_plan(p, 1, tokens->c, proj->e, resolve_gemm(&o, tokens->dtype, proj->dtype));
+  begin_plan(p, 1, tokens->c, proj->e, resolve_gemm(&o, tokens->dtype, proj->dtype), tokens->dtype);
   PlanAcc acc;
   const FrameDesc d = plan_frame(f, tokens->c, p.shape, acc);
   finish_plan(p, acc);
