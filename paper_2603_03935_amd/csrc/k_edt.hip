@@ -788,13 +788,22 @@ __device__ __forceinline__ int max4(us2 a, us2 b) {
 // e changes) and the table holds g^2 (< 2^16).  The search runs in packed
 // 16-bit arithmetic, two rows per instruction: sums saturate at 65535, which
 // is never below the best value (<= 65025).
-// PK = 0: taller items; the table holds g and the search is exact 32-bit.
-// (A packed search of min(g, 255)^2 for the taller items, with an exact
-// re-search of the rare groups that end at 255^2 or above, was measured: its
-// per-step saving was eaten by the clamp and the extra control flow.)
-template <int SPATIAL, bool WE, int PK>
-__device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint32_t* recs, const int* words,
-                                              uint2* gt_all, float* part, int lane, int kb, int32_t* e_out) {
+// PK = 2: taller items (up to 1152 rows).  Every e is at most 575^2, so g is
+// clamped to 576, and the table holds T(g) = g^2 for g < 255 and
+// 255^2 + (g - 255) above (at most 65346, 16 bits; T(g) <= g^2 and T grows
+// with g).  The packed search over T is exact for every row whose e is below
+// 255^2 (each clamped candidate is at least 255^2); a group in which some row
+// ends at 255^2 or above is searched again in exact 32-bit arithmetic,
+// decoding g^2 from T.  Those are the rows more than 254 pixels from the
+// mask's outside, a small share of the tallest items.
+// PK = 0: the table holds g and the search is exact 32-bit (AREA of the
+// taller items).
+// The g table of a packet (PK 1: min(g, 255)^2; PK 2: T(min(g, 576)); PK 0:
+// g; 0 past each slot's item), 16 bits per (row, column), four rows per
+// 64-bit word.
+template <int PK>
+__device__ __forceinline__ void direct_table(int cls, const uint32_t* recs, const int* words, uint2* gt_all,
+                                             int lane, int kb) {
   const int rows_c = class_rows(cls), ipp = direct_items(cls);
   const int nbs = rows_c / kBlkRows;  // blocks per slot
   const int nblk = ipp * nbs;         // blocks of the packet
@@ -863,6 +872,11 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
               const s16x2 cap = {255, 255};
               const us2 gc = __builtin_bit_cast(us2, __builtin_elementwise_min(g, cap));
               wd[q] = lane_ok ? __builtin_bit_cast(uint32_t, gc * gc) : 0u;
+            } else if (PK == 2) {
+              const s16x2 cap = {255, 255}, top = {576, 576};
+              const us2 g1 = __builtin_bit_cast(us2, __builtin_elementwise_min(g, top));
+              const us2 gc = __builtin_bit_cast(us2, __builtin_elementwise_min(g, cap));
+              wd[q] = lane_ok ? __builtin_bit_cast(uint32_t, gc * gc + (g1 - gc)) : 0u;
             } else {
               wd[q] = lane_ok ? __builtin_bit_cast(uint32_t, g) : 0u;
             }
@@ -875,6 +889,7 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
                              __builtin_amdgcn_readlane(r.z, src + e), __builtin_amdgcn_readlane(r.w, src + e));
               h[e] = lane_ok ? (uint32_t)g_rec(ru, lane) : 0u;
               if (PK == 1) h[e] = min(h[e], 255u) * min(h[e], 255u);
+              if (PK == 2) h[e] = min(h[e], 255u) * min(h[e], 255u) + (min(h[e], 576u) - min(h[e], 255u));
             }
             wd[q] = h[0] | (h[1] << 16);
           }
@@ -883,6 +898,16 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
       }
     }
   }
+}
+
+template <int SPATIAL, bool WE, int PK>
+__device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint32_t* recs, const int* words,
+                                              uint2* gt_all, float* part, int lane, int kb, int32_t* e_out) {
+  const int rows_c = class_rows(cls), ipp = direct_items(cls);
+  const int nbs = rows_c / kBlkRows;  // blocks per slot
+  const int nblk = ipp * nbs;         // blocks of the packet
+
+  direct_table<PK>(cls, recs, words, gt_all, lane, kb);
   __syncthreads();
 
   // ---- search: this workgroup's blocks (every S-th from s), one wavefront
@@ -911,8 +936,11 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
       const uint2* base = tb + (gi >> 2) * 64;  // row u0 = b0 + gi
       int best[kDirRows];
       int bmax = 0;
-      // exact initial values g^2 (PK 1: the table already holds them)
-      auto init_exact = [&]() {
+      // g^2 of a table entry (PK 1: the entry itself, PK 2: decoded from T)
+      auto gsq_of = [](int t) { return PK == 1 ? t : PK == 2 ? (t < 65025 ? t : (t - 64770) * (t - 64770)) : t * t; };
+      // initial values: the rows' own entries, g^2 (exact = false with PK 2:
+      // T itself, for the packed search)
+      auto init_exact = [&](bool exact) {
         bmax = 0;
 #pragma unroll
         for (int q = 0; q < kDirRows / 4; ++q) {
@@ -920,7 +948,7 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
           const int g4[4] = {(int)(w.x & 0xFFFFu), (int)(w.x >> 16), (int)(w.y & 0xFFFFu), (int)(w.y >> 16)};
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            best[4 * q + k] = SPATIAL != 0 ? (g4[k] > 0 ? 1 : 0) : PK == 1 ? g4[k] : g4[k] * g4[k];
+            best[4 * q + k] = SPATIAL != 0 ? (g4[k] > 0 ? 1 : 0) : (PK == 2 && !exact) ? g4[k] : gsq_of(g4[k]);
             bmax = max(bmax, best[4 * q + k]);
           }
         }
@@ -938,14 +966,14 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
             const uint2 x = pu[q * 64], y = pd[q * 64];
             const int xa = (int)(x.x & 0xFFFFu), xb = (int)(x.x >> 16), xc = (int)(x.y & 0xFFFFu), xd = (int)(x.y >> 16);
             const int ya = (int)(y.x & 0xFFFFu), yb = (int)(y.x >> 16), yc = (int)(y.y & 0xFFFFu), yd = (int)(y.y >> 16);
-            su[4 * q] = xa * xa;
-            su[4 * q + 1] = xb * xb;
-            su[4 * q + 2] = xc * xc;
-            su[4 * q + 3] = xd * xd;
-            sd[4 * q] = ya * ya;
-            sd[4 * q + 1] = yb * yb;
-            sd[4 * q + 2] = yc * yc;
-            sd[4 * q + 3] = yd * yd;
+            su[4 * q] = gsq_of(xa);
+            su[4 * q + 1] = gsq_of(xb);
+            su[4 * q + 2] = gsq_of(xc);
+            su[4 * q + 3] = gsq_of(xd);
+            sd[4 * q] = gsq_of(ya);
+            sd[4 * q + 1] = gsq_of(yb);
+            sd[4 * q + 2] = gsq_of(yc);
+            sd[4 * q + 3] = gsq_of(yd);
           }
           bmax = 0;
 #pragma unroll
@@ -957,7 +985,7 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
           }
         }
       };
-      init_exact();
+      init_exact(false);
       if (SPATIAL == 0 && PK != 0) {
         // packed: rows (0,1) and (2,3) of the group in one register each;
         // the window rows as aligned pairs (2j, 2j+1) and odd pairs
@@ -997,6 +1025,11 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
         best[1] = B[0].y;
         best[2] = B[1].x;
         best[3] = B[1].y;
+        if (PK == 2 && max(max(best[0], best[1]), max(best[2], best[3])) >= 65025) {
+          // some row of the group is at least 255 from the outside: exact search
+          init_exact(true);
+          search32();
+        }
       } else if (SPATIAL == 0) {
         search32();
       }
@@ -1050,7 +1083,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const int p = vp / S, s = vp - p * S;
     const int cls = direct_load_packet(cnt, items, item_cap, mrec, p, recs, words);
     float* part = S == 1 ? part_all : gpart + (int64_t)p * kDirPartFloats;
-    direct_packet<SPATIAL, WE, (ROWS <= 512 ? 1 : 0)>(cls, s, S, recs, words, gt_all + kDirGuard / 4 * 64, part, lane, kb, e_out);
+    direct_packet<SPATIAL, WE, (ROWS <= 512 ? 1 : SPATIAL == 0 ? 2 : 0)>(cls, s, S, recs, words, gt_all + kDirGuard / 4 * 64, part, lane, kb, e_out);
     if (S == 1) {
       direct_strip_sums(cls, recs, words, part_all, lane, kb);
       __syncthreads();
