@@ -74,18 +74,18 @@ struct MaskRec {
   int32_t w, h, xs0, g;    // frame width/height, first strip column, global mask index
 };
 
-// One frame of a (possibly ragged) batch, in device memory.
-// OCP e4m3fn code -> float (exact)
-__device__ __forceinline__ float e4m3_to_f32(uint32_t code) {
-  const uint32_t sign = (code & 0x80u) << 24;
-  const uint32_t mag = code & 0x7Fu;
-  if (mag == 0x7Fu) return __builtin_nanf("");
-  if (mag >= 8u) return __uint_as_float(sign | ((mag << 20) + (120u << 23)));
-  const float v = (float)mag * 0x1p-9f;
-  return sign ? -v : v;
-}
-
 __device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+// The four e4m3fn codes of w (lowest byte first) as floats, by the hardware
+// conversion (exact: sign x 2^(e - 7) x (1 + m / 8), subnormals m x 2^-9,
+// codes 0x7F and 0xFF NaN).  Every e4m3fn value is also exact in BF16 (its
+// FP32 bits end in 16 zeros).
+__device__ __forceinline__ float4 e4m3x4_to_f32(uint32_t w) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+  const f2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+  return make_float4(lo.x, lo.y, hi.x, hi.y);
+}
 
 // Workgroup b of a launch runs on XCD b % 8 (each XCD has its own L2).
 // xcd_remap gives each XCD a contiguous range of the n live workgroups of a
@@ -97,6 +97,7 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return x * q + min(x, r) + k;
 }
 
+// One frame of a (possibly ragged) batch, in device memory.
 struct FrameDesc {
   const void* tokens;     // [G][C] in tok_dtype
   const float* scale;     // [G] for FP8 tokens

@@ -26,17 +26,6 @@ __device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even (f
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// e4m3fn code -> bf16 bits (exact: every e4m3 value is a bf16 value)
-__device__ __forceinline__ uint16_t e4m3_to_bf16(uint32_t code) {
-  const uint32_t sign = (code & 0x80u) << 8;
-  const uint32_t mag = code & 0x7Fu;
-  if (mag == 0x7Fu) return (uint16_t)(sign | 0x7FC0u);
-  if (mag >= 8u) return (uint16_t)(sign | ((mag << 4) + (120u << 7)));
-  const float v = (float)mag * 0x1p-9f;  // subnormal e4m3 -> normal bf16
-  return (uint16_t)(sign | (__float_as_uint(v) >> 16));
-}
-__device__ __forceinline__ float e4m3_to_f32g(uint32_t code) { return bf2f(e4m3_to_bf16(code)); }
-
 // 8 consecutive elements of a token row as GEMM operands (zero past G)
 template <int TOK, int BF16>
 __device__ __forceinline__ void load_tok8(const void* base, int64_t off, bool ok, uint16_t* ob, float* of) {
@@ -62,9 +51,10 @@ __device__ __forceinline__ void load_tok8(const void* base, int64_t off, bool ok
     }
   } else {
     const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(base) + off);
+    const float4 x0 = e4m3x4_to_f32(a.x), x1 = e4m3x4_to_f32(a.y);
+    const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
     for (int j = 0; j < 8; ++j) {
-      const uint32_t code = ((j < 4 ? a.x : a.y) >> (8 * (j & 3))) & 0xFFu;
-      if (BF16) ob[j] = e4m3_to_bf16(code); else of[j] = e4m3_to_f32g(code);
+      if (BF16) ob[j] = (uint16_t)(__float_as_uint(v[j]) >> 16); else of[j] = v[j];  // exact either way
     }
   }
 }
@@ -88,7 +78,7 @@ template <int TOK>
 __device__ __forceinline__ uint16_t tok_bf16(const void* base, int64_t off) {
   if (TOK == 0) return f2bf(reinterpret_cast<const float*>(base)[off]);
   if (TOK == 1) return reinterpret_cast<const uint16_t*>(base)[off];
-  return e4m3_to_bf16(reinterpret_cast<const uint8_t*>(base)[off]);
+  return (uint16_t)(__float_as_uint(e4m3x4_to_f32(reinterpret_cast<const uint8_t*>(base)[off]).x) >> 16);
 }
 
 // K range [kbeg, kend) of a tile: the union of its masks' patch-row ranges

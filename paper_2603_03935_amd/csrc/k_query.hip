@@ -136,8 +136,8 @@ __device__ __forceinline__ float4 load_tok4(const void* base, const float* scale
   // e4m3fn codes times the token's scale (every code value is exact in FP32)
   const uint32_t q = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(base) + off);
   const float sc = scale[row];
-  return make_float4(e4m3_to_f32(q & 0xFFu) * sc, e4m3_to_f32((q >> 8) & 0xFFu) * sc,
-                     e4m3_to_f32((q >> 16) & 0xFFu) * sc, e4m3_to_f32(q >> 24) * sc);
+  const float4 x = e4m3x4_to_f32(q);
+  return make_float4(x.x * sc, x.y * sc, x.z * sc, x.w * sc);
 }
 
 // Y[G][E] = tokens[G][C] P[C][E]: 64 x 64 tiles (4 wavefronts of 32 x 32),

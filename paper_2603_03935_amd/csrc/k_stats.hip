@@ -13,13 +13,6 @@ namespace disc {
 
 
 // e4m3fn code -> BF16 bits of the same value (exact: e4m3 values are BF16 values)
-__device__ __forceinline__ uint32_t e4m3_to_bf16_bits(uint32_t code) {
-  const uint32_t sign = (code & 0x80u) << 8;
-  const uint32_t mag = code & 0x7Fu;
-  if (mag == 0x7Fu) return sign | 0x7FC0u;
-  if (mag >= 8u) return sign | ((mag << 4) + (120u << 7));
-  return sign | (__float_as_uint((float)mag * 0x1p-9f) >> 16);  // subnormal e4m3 -> normal bf16
-}
 
 // four consecutive channels of token p as floats (value = scale * code for FP8)
 __device__ __forceinline__ float4 load4(const void* base, int dtype, const float* scale, int64_t p, int C, int c) {
@@ -32,8 +25,8 @@ __device__ __forceinline__ float4 load4(const void* base, int dtype, const float
   }
   const uint32_t v = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(base) + off);
   const float s = scale[p];
-  return make_float4(s * e4m3_to_f32(v & 0xFFu), s * e4m3_to_f32((v >> 8) & 0xFFu), s * e4m3_to_f32((v >> 16) & 0xFFu),
-                     s * e4m3_to_f32(v >> 24));
+  const float4 x = e4m3x4_to_f32(v);
+  return make_float4(s * x.x, s * x.y, s * x.z, s * x.w);
 }
 
 // Partial channel sums over chunks of stat_chunk(G) tokens (k_colsum), folded
@@ -57,7 +50,13 @@ __device__ __forceinline__ void load_vec(const void* base, const float* scale, i
     const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint8_t*>(base) + off);
     const uint32_t w[4] = {a.x, a.y, a.z, a.w};
     const float sc = scale[p];
-    for (int j = 0; j < 16; ++j) v[j] = sc * e4m3_to_f32((w[j >> 2] >> (8 * (j & 3))) & 0xFFu);
+    for (int j = 0; j < 4; ++j) {
+      const float4 x = e4m3x4_to_f32(w[j]);
+      v[4 * j] = sc * x.x;
+      v[4 * j + 1] = sc * x.y;
+      v[4 * j + 2] = sc * x.z;
+      v[4 * j + 3] = sc * x.w;
+    }
   }
 }
 
@@ -152,9 +151,18 @@ __global__ __launch_bounds__(256) void k_resid(Batch b, Work wk) {
         sc[i] = (WANT_R && p < G) ? fd.scale[p] : 0.f;
       }
       uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)blockIdx.x * C + c) * 8);
+      float4 cv[8][2];  // the codes as floats (exact), channels c .. c + 7 of each token
+      for (int i = 0; i < 8; ++i) {
+        cv[i][0] = e4m3x4_to_f32(codes[i].x);
+        cv[i][1] = e4m3x4_to_f32(codes[i].y);
+      }
       for (int j = 0; j < 8; ++j) {
         uint32_t q[8];
-        for (int i = 0; i < 8; ++i) q[i] = e4m3_to_bf16_bits(((j < 4 ? codes[i].x : codes[i].y) >> (8 * (j & 3))) & 0xFFu);
+        for (int i = 0; i < 8; ++i) {
+          const float4 x = cv[i][j >> 2];
+          const float y = (j & 3) == 0 ? x.x : (j & 3) == 1 ? x.y : (j & 3) == 2 ? x.z : x.w;
+          q[i] = __float_as_uint(y) >> 16;  // exact BF16 bits
+        }
         if (PACK) dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
         if (WANT_R) {
           const float m = mu[c + j];

@@ -159,6 +159,29 @@ def test_token_stats(gpu, dtype):
         assert np.abs(D.cpu().numpy() - oD).max() <= REL_S * oD.max()
 
 
+def test_fp8_every_code(gpu):
+    """Every finite e4m3fn code is decoded exactly: token p holds code p in
+    every channel (scale 1, with two scaled tokens), so each token's residual
+    norm sqrt(C) |v_p - mean| shows a wrong value of its code."""
+    codes = np.array([c for c in range(256) if c & 0x7F != 0x7F], dtype=np.uint8)  # 254 finite codes
+    G, C = 256, 64
+    data = np.zeros((G, C), dtype=np.uint8)
+    data[:codes.size] = codes[:, None]
+    data[codes.size:] = np.array([0x38, 0xB8], dtype=np.uint8)[:, None]  # +1, -1
+    scale = np.ones(G, dtype=np.float32)
+    scale[codes.size:] = [0.5, 3.0]
+    tok = di.Tokens(data.reshape(16, 16, C), "f8", scale, 16)
+    d, sc = dev_tokens(tok)
+    mean, r, D = gpu.token_stats(d, tok.patch, sc)
+    f64 = oracle.decode_tokens(tok.data, tok.dtype, tok.scale)
+    om, orr, oD = oracle.token_stats(f64, 1e-6)
+    assert np.isfinite(f64).all()
+    assert np.abs(mean.cpu().numpy() - om).max() <= REL_S * np.abs(f64).max()
+    got_r = r.cpu().numpy().astype(np.float64)
+    bad = np.nonzero(np.abs(got_r - orr) > 1e-5 * orr + 1e-7 * orr.max())[0]
+    assert bad.size == 0, f"codes decoded wrongly: {[hex(int(data[i, 0])) for i in bad[:8]]}"
+
+
 # ---------------------------------------------------------------- pooling / projection
 
 @pytest.mark.parametrize("gemm", [0, 1])
