@@ -130,7 +130,6 @@ def workload_units(wl, gemm_bf16: bool):
     bits_bytes = sum(f.bits.nbytes for f in wl.frames)
     tok_bytes = 0
     r_bytes = 0
-    tkp_bytes = 0
     w_bytes = 0
     edt_px = 0
     nnz = 0
@@ -139,8 +138,6 @@ def workload_units(wl, gemm_bf16: bool):
         G = t.gh * t.gw
         tok_bytes += t.data.nbytes + (t.scale.nbytes if t.scale is not None else 0)
         r_bytes += 4 * G
-        if gemm_bf16:
-            tkp_bytes += G * C * 2
         w_bytes += f.m * G * (2 if gemm_bf16 else 4)
         for bb in _bbox(f.bits):
             if bb is not None:
@@ -151,13 +148,13 @@ def workload_units(wl, gemm_bf16: bool):
     # bytes a GEMM must move at least: pooling reads each frame's tokens (as
     # the GEMM operand) and the weights once and writes X; projection reads X
     # and P once and writes the FP32 rows
-    pool_bytes = (tkp_bytes if gemm_bf16 else tok_bytes) + w_bytes + M * C * gb
+    pool_bytes = tok_bytes + w_bytes + M * C * gb
     proj_bytes = M * C * gb + C * E * gb + M * E * 4
     hbm_views = {"pool": pool_bytes, "proj": proj_bytes}
     return {
         "scan": ("hbm", bits_bytes, "B"),
         "edt": ("alu", EDT_OPS_PER_PIXEL * edt_px, "op"),
-        "token_stats": ("hbm", tok_bytes + r_bytes + tkp_bytes, "B"),
+        "token_stats": ("hbm", tok_bytes + r_bytes, "B"),
         "weights": ("hbm", w_bytes, "B"),
         "pool": ("mfma:" + gdt, 2.0 * nnz * C, "flop"),
         "proj": ("mfma:" + gdt, 2.0 * M * C * E, "flop"),

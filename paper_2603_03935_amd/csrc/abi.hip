@@ -172,7 +172,6 @@ Layout make_layout(const Shape& s) {
   L.qpart = take(s.proj_split > 1 ? 4 * (size_t)((s.C + kProjKG - 1) / kProjKG) * s.M * s.E : 0);
   L.ppack = take(s.gemm_bf16 ? 2 * (size_t)s.C * s.E : 0);
   L.edt_part = take(4 * (size_t)kDirSplitPackets * kDirPartFloats);
-  L.tkp = take(s.pack_tokens ? 2 * (size_t)s.tkp_elems : 0);
   L.extra = take((size_t)s.extra_bytes);
   L.total = off;
   return L;
@@ -298,7 +297,6 @@ Work work_ptrs(char* base, const Layout& L) {
   w.qpart = reinterpret_cast<float*>(base + L.qpart);
   w.ppack = base + L.ppack;
   w.edt_part = reinterpret_cast<float*>(base + L.edt_part);
-  w.tkp = base + L.tkp;
   return w;
 }
 
@@ -332,11 +330,9 @@ FrameDesc plan_frame(const FrameIn& f, int C, Shape& s, PlanAcc& a) {
   d.Gs = (int32_t)round_up(d.G, 8);
   d.w_base = a.sumMGs;
   d.r_base = a.sumG;
-  d.t_base = a.tkp;
   a.M += f.m;
   a.sumG += d.G;
   a.sumMGs += (int64_t)f.m * d.Gs;
-  a.tkp += (int64_t)round_up(d.G, 8) * C;
   a.gmax = std::max(a.gmax, d.G);
   a.nchunk = std::max(a.nchunk, stat_nchunk(d.G));
   a.item_cap += (int64_t)f.m * ((f.w + strip_width(f.patch) - 1) / strip_width(f.patch) + 1);
@@ -350,7 +346,6 @@ void finish_plan(Plan& p, const PlanAcc& a) {
   s.M = a.M;
   s.sumG = a.sumG;
   s.sumMGs = a.sumMGs;
-  s.tkp_elems = a.tkp;
   s.gmax = a.gmax;
   s.nchunk = a.nchunk;
   s.item_cap = (int)std::min<int64_t>(a.item_cap, INT32_MAX / 2);
@@ -361,7 +356,6 @@ void finish_plan(Plan& p, const PlanAcc& a) {
 
 void begin_plan(Plan& p, int n_frames, int C, int E, int gemm_bf16, int tok_dtype) {
   Shape& s = p.shape;
-  s.pack_tokens = gemm_bf16 && tok_dtype == DISC_F8E4M3;
   s.n_frames = n_frames;
   s.want_dbar = false;
   s.max_rows = 0;
@@ -674,9 +668,9 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   const int4* tiles = reinterpret_cast<const int4*>(dev_ws + p.L.tiles);
   // token statistics first: the mask scan folds r into the mean distinctiveness
   const bool want_r = o.distinct || p.shape.want_dbar;
-  if (want_r || p.shape.pack_tokens) {
+  if (want_r) {
     StageTimer t(sid < 0 ? -1 : ST_STATS, st);
-    launch_token_stats(b, w, p.shape.gmax, want_r, p.shape.pack_tokens, st);
+    launch_token_stats(b, w, p.shape.gmax, st);
     if (p.shape.want_dbar) launch_rbar(b, w, st);
   }
   { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st, p.shape.want_dbar); }
@@ -846,7 +840,7 @@ disc_status disc_patch_weights(const disc_tokens* tokens, const disc_masks* mask
   const Batch b = make_batch(p, cx.dev_ws, o.distinct ? tokens->dtype : DISC_F32, o.spatial, o.distinct);
   const Work w = work_ptrs(cx.dev_ws, p.L);
   launch_scan(b, w, cx.st);
-  if (o.distinct) launch_token_stats(b, w, p.shape.gmax, 1, 0, cx.st);
+  if (o.distinct) launch_token_stats(b, w, p.shape.gmax, cx.st);
   launch_edt(b, w, nullptr, num_cus(cx.dev), cx.st, o.edt_layout);
   launch_dense_weights(b, w, wout, o.eps, cx.st);
   if ((st = check_launch(who))) return st;
@@ -878,7 +872,7 @@ disc_status disc_token_stats(const disc_tokens* tokens, float eps, float* mean, 
   const Batch b = make_batch(p, cx.dev_ws, tokens->dtype, 0, 1);
   const Work w = work_ptrs(cx.dev_ws, p.L);
   const int G = tokens->gh * tokens->gw;
-  launch_token_stats(b, w, G, 1, 0, cx.st);
+  launch_token_stats(b, w, G, cx.st);
   if (mean) launch_copy_f32(w.mean, mean, tokens->c, cx.st);
   if (r) launch_copy_f32(w.r, r, G, cx.st);
   if (D) launch_d_from_r(w.r, G, eps, D, cx.st);
@@ -927,7 +921,7 @@ disc_status disc_query_heatmap(const disc_tokens* tokens, const disc_proj* proj,
   float* D = reinterpret_cast<float*>(x + yb);
   float* fac = reinterpret_cast<float*>(x + yb + gb);
   float* inv_text = reinterpret_cast<float*>(x + yb + 2 * gb);
-  launch_token_stats(b, w, G, 1, 0, cx.st);
+  launch_token_stats(b, w, G, cx.st);
   launch_d_from_r(w.r, G, eps, D, cx.st);
   launch_heatmap(tokens->data, tokens->dtype, tokens->scale, G, C, proj->data, proj->dtype == DISC_BF16, E, text,
                  text_dtype == DISC_BF16, q, D, Y, fac, inv_text, heat, cx.st);
@@ -972,7 +966,6 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32
   const Work w = work_ptrs(cx.dev_ws, p.L);
   const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
   launch_user_weights(b, w, wts, cx.st);
-  if (p.shape.pack_tokens) launch_token_stats(b, w, p.shape.gmax, 0, 1, cx.st);
   launch_pool_order(b, w, cx.st);
   launch_pool(b, w, tiles, cx.st, o.pool_tile > 0 ? o.pool_tile : 1);
   launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, cx.st);

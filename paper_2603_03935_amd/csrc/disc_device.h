@@ -113,7 +113,6 @@ struct FrameDesc {
   int32_t Gs;             // row stride of the per-mask weight rows (G rounded up to 8)
   int64_t w_base;         // element offset of this frame's [m][Gs] block in s/W
   int64_t r_base;         // offset of this frame's G entries in r
-  int64_t t_base;         // element offset of this frame's k-packed tokens (FP8 tokens, BF16 GEMMs)
 };
 
 // Scalar arguments shared by the kernels of one call.  n_frames and M are
@@ -158,7 +157,6 @@ struct Work {
   float* ppart;        // pooling group sums [tile][kgroups][64*64] (split K only)
   int4* ptile;         // per pooling tile: (first, end K group), then its 64 rows as pool_rows gives them (split K only)
   float* qpart;        // projection group sums [C/256][M][E] (split K only)
-  void* tkp;           // FP8 tokens with BF16 GEMMs: k-packed copy [sum ceil(G/8)][C][8], the code values widened to BF16
   float* edt_part;     // direct EDT block partial sums of shared packets [kDirSplitPackets][kDirPartFloats]
   void* ppack;         // k-packed BF16 copy of P [C/8][E][8] (BF16 GEMMs)
 };
@@ -213,9 +211,8 @@ void launch_pool_order(const Batch& b, const Work& w, hipStream_t st);
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode = -1,
                 bool order_pool = false);
 void edt_prepare();
-// want_r: frame means and residual norms r (gmax: the largest G); pack: the
-// k-packed BF16 copy of FP8 tokens that the BF16 pooling GEMM reads
-void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st);
+// Frame means and residual norms r (gmax: the largest G).
+void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
 void launch_rbar(const Batch& b, const Work& w, hipStream_t st);
 void launch_quality(const int32_t* area, const float* dbar, const float* emb, const float* g, const float* angle, int m,

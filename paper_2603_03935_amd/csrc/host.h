@@ -13,7 +13,7 @@ namespace host {
 
 struct Layout {
   size_t frames, mask_frame, tiles, dyn, staged_end;  // staged region (uploaded from the host)
-  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, rbar, s, W, Z, mstat, perm, X, ppart, ptile, qpart, ppack, edt_part, tkp;
+  size_t bbox, area, meta, mrec, items, counts, psum, mean, r, rbar, s, W, Z, mstat, perm, X, ppart, ptile, qpart, ppack, edt_part;
   size_t extra;  // extra_bytes for an entry point's own buffers
   size_t total;
 };
@@ -26,8 +26,6 @@ struct Shape {
   int pool_split = 1, proj_split = 1;
   bool want_dbar = false;  // some frame asks for the mean distinctiveness (needs r and its mean)
   int max_rows = kMaxRows;  // tallest frame + 2 (distance-transform rows of the tallest item)
-  int pack_tokens = 0;     // FP8 tokens with BF16 GEMMs: the k-packed BF16 copy is kept
-  int64_t tkp_elems = 0;  // sum over frames of ceil(G/8)*8*C (that copy)
   int64_t extra_bytes = 0;  // appended region (e.g. the heat-map's projected tokens)
 };
 
@@ -57,7 +55,7 @@ struct Plan {
 
 // Capacity totals accumulated while frames are added to a plan.
 struct PlanAcc {
-  int64_t M = 0, sumG = 0, sumMGs = 0, tkp = 0, item_cap = 1;
+  int64_t M = 0, sumG = 0, sumMGs = 0, item_cap = 1;
   int gmax = 0, nchunk = 1, n_tiles = 0;
 };
 

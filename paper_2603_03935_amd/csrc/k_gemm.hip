@@ -62,17 +62,23 @@ __device__ __forceinline__ void load_tok8(const void* base, int64_t off, bool ok
 // ---------------------------------------------------------------------------
 // pooling: tile 64 masks x 64 channels, K = patches in chunks of 32.
 // A (weights, k contiguous) is staged row-major; for BF16 operands B is read
-// from the k-packed token copy written by the statistics pass (8 consecutive
-// patches of one channel contiguous, BF16; FP8 code values were widened there,
-// once per token), so each B load is one vector and the MFMA operand of a lane
-// is one 16-byte LDS read.  The next K chunk is fetched into registers while the current one
+// from the caller's [G][C] tokens and transposed into LDS (8 consecutive
+// patches of one channel contiguous, BF16; FP8 codes widened exactly by the
+// hardware conversion), so the MFMA operand of a lane is one 16-byte LDS
+// read.  The next K chunk is fetched into registers while the current one
 // is multiplied.  A workgroup may take NT = 1, 2 or 4 adjacent 64-channel
 // tiles of the same masks (one A fetch for NT x 64 channels); the tile list,
 // the K order and therefore the result do not depend on NT, which the pooling
 // autotuner picks per problem shape.
 // ---------------------------------------------------------------------------
 constexpr int PBM = 64, PBN = 64, PBK = 32;
-constexpr int PAS = PBK + 8;  // LDS row stride (elements) of A and k-packed B
+constexpr int PAS = PBK + 8;  // LDS row stride (elements) of A and B
+// B rows (channels) hold the step's 32 patches as four 8-patch chunks; chunk
+// c of row r sits at position c ^ ((r >> 4) & 3), so that the staging
+// writes (4 channels x 16 patch pairs of a wavefront, rows 80 bytes apart)
+// fall in 64 different banks.  The MFMA reads (16 bytes of 8 consecutive
+// rows with one chunk) see the same bank pattern as without the swizzle.
+__device__ __forceinline__ int bsw(int row, int chunk) { return chunk ^ ((row >> 4) & 3); }
 
 template <int TOK>
 __device__ __forceinline__ uint16_t tok_bf16(const void* base, int64_t off) {
@@ -199,14 +205,10 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   const int ar = tid >> 2, ak = (tid & 3) * 8;        // A: row, first k of 8
   const bool arow_ok = ar < mrows;
   const int64_t wrow0 = fd.w_base + (int64_t)(arow_ok ? wk.perm[fd.mask_base + m0 + ar] : 0) * fd.Gs;
-  // B (BF16), BF16 and FP32 tokens: the caller's [G][C] tokens, patches
-  // 2 pp, 2 pp + 1 and channels c4 .. c4 + 3 (+ 64 j) per thread, transposed
-  // into LDS.  FP8 tokens: the k-packed copy (channels (tid & 63) + 64 j,
-  // patches 8 (tid >> 6) .. +7, one 16-byte load), whose code values were
-  // widened once by the statistics pass (widening in every pooling workgroup
-  // that reads a token measured 2.7x slower at 16 x 1080p)
+  // B (BF16): the caller's [G][C] tokens, patches 2 pp, 2 pp + 1 and
+  // channels c4 .. c4 + 3 (+ 64 j) per thread, transposed into LDS as
+  // (patch pair, channel) words
   const int bpp = tid >> 4, bc4 = (tid & 15) * 4;
-  const int bn16 = tid & 63, bk16 = (tid >> 6) * 8;
   // B (FP32): patch tid >> 3, channels 8*(tid & 7) + 64 j .. +7
   const int bk32 = tid >> 3, bn32 = (tid & 7) * 8;
 
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   // one set, one step ahead (more resident workgroups hide the latency).
   constexpr int DIST = BF16 ? 1 : 2;
   uint4 ra16[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
-  uint4 rbr[2][NT][2];  // raw token words: FP32 float4 bits, BF16 .xy, FP8 .x
+  uint4 rbr[2][NT][2];  // raw token words of patches 2 pp, 2 pp + 1: FP32 float4 bits, BF16 .xy, FP8 .x
   float ra32[2][8], rb32[2][NT][8];
 
   auto fetch = [&](int k0, int q) {
@@ -225,16 +227,6 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
     if (BF16) {
       const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0 + kk;
       ra16[q] = arow_ok && kk < G ? *reinterpret_cast<const uint4*>(src) : make_uint4(0u, 0u, 0u, 0u);
-      if (TOK == 2) {
-        const int grp = (k0 + bk16) >> 3;
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          rbr[q][j][0] = grp * 8 < G ? *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(wk.tkp) + fd.t_base +
-                                                                        ((int64_t)grp * C + n0 + bn16 + 64 * j) * 8)
-                                     : make_uint4(0u, 0u, 0u, 0u);
-        }
-        return;
-      }
       const int kb = k0 + 2 * bpp;
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
@@ -249,6 +241,8 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
               const uint2 t2 = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(fd.tokens) + off);
               v.x = t2.x;
               v.y = t2.y;
+            } else {
+              v.x = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(fd.tokens) + off);
             }
           }
           rbr[q][j][h] = v;
@@ -269,25 +263,37 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
       for (int j = 0; j < NT; ++j) load_tok8<TOK, 0>(fd.tokens, (int64_t)kr * C + n0 + bn32 + 64 * j, kr < G, nullptr, rb32[q][j]);
     }
   };
-  // BF16 bits of channel e of a raw token word (FP32 or BF16 tokens)
-  auto raw_bf16 = [&](const uint4& v, int e) -> uint32_t {
-    if (TOK == 0) return f2bf(__uint_as_float(e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w));
-    return ((e < 2 ? v.x : v.y) >> (16 * (e & 1))) & 0xFFFFu;
-  };
   auto stage = [&](int q) {
     if (BF16) {
       *reinterpret_cast<uint4*>(&As16[ar * PAS + ak]) = ra16[q];
-      if (TOK == 2) {
 #pragma unroll
-        for (int j = 0; j < NT; ++j) *reinterpret_cast<uint4*>(&Bs16[(bn16 + 64 * j) * PAS + bk16]) = rbr[q][j][0];
-        return;
+      for (int j = 0; j < NT; ++j) {
+        // channel bc4 + e: patches 2 pp and 2 pp + 1 as one word (BF16 bits)
+        uint32_t wd[4];
+        const uint4 v0 = rbr[q][j][0], v1 = rbr[q][j][1];
+        if (TOK == 0) {
+          const uint32_t a[4] = {v0.x, v0.y, v0.z, v0.w}, c[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) wd[e] = f2bf(__uint_as_float(a[e])) | ((uint32_t)f2bf(__uint_as_float(c[e])) << 16);
+        } else if (TOK == 1) {
+          wd[0] = __builtin_amdgcn_perm(v1.x, v0.x, 0x05040100u);
+          wd[1] = __builtin_amdgcn_perm(v1.x, v0.x, 0x07060302u);
+          wd[2] = __builtin_amdgcn_perm(v1.y, v0.y, 0x05040100u);
+          wd[3] = __builtin_amdgcn_perm(v1.y, v0.y, 0x07060302u);
+        } else {
+          // e4m3fn codes: exact floats, whose upper halves are the BF16 bits
+          const float4 x0 = e4m3x4_to_f32(v0.x), x1 = e4m3x4_to_f32(v1.x);
+          wd[0] = __builtin_amdgcn_perm(__float_as_uint(x1.x), __float_as_uint(x0.x), 0x07060302u);
+          wd[1] = __builtin_amdgcn_perm(__float_as_uint(x1.y), __float_as_uint(x0.y), 0x07060302u);
+          wd[2] = __builtin_amdgcn_perm(__float_as_uint(x1.z), __float_as_uint(x0.z), 0x07060302u);
+          wd[3] = __builtin_amdgcn_perm(__float_as_uint(x1.w), __float_as_uint(x0.w), 0x07060302u);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = 64 * j + bc4 + e;
+          *reinterpret_cast<uint32_t*>(&Bs16[row * PAS + bsw(row, bpp >> 2) * 8 + ((2 * bpp) & 7)]) = wd[e];
+        }
       }
-#pragma unroll
-      for (int j = 0; j < NT; ++j)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)  // channel bc4 + e: patches 2 pp and 2 pp + 1 as one word
-          *reinterpret_cast<uint32_t*>(&Bs16[(64 * j + bc4 + e) * PAS + 2 * bpp]) =
-              raw_bf16(rbr[q][j][0], e) | (raw_bf16(rbr[q][j][1], e) << 16);
     } else {
       for (int j = 0; j < 8; ++j) As32[ar * (PBK + 1) + ak + j] = ra32[q][j];
 #pragma unroll
@@ -334,7 +340,8 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
         const u16x8 av = *reinterpret_cast<const u16x8*>(&As16[(32 * wm + lr) * PAS + kk + 8 * lk]);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-          const u16x8 bv = *reinterpret_cast<const u16x8*>(&Bs16[(64 * j + 32 * wn + lr) * PAS + kk + 8 * lk]);
+          const int row = 64 * j + 32 * wn + lr;
+          const u16x8 bv = *reinterpret_cast<const u16x8*>(&Bs16[row * PAS + bsw(row, (kk >> 3) + lk) * 8]);
           acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc[j], 0, 0, 0);
         }
       }

@@ -115,16 +115,10 @@ __global__ __launch_bounds__(256) void k_mean(Batch b, Work wk) {
 }
 
 // One workgroup per group of 8 consecutive tokens p0..p0+7 of a frame:
-//   * WANT_R: r_p = ||f_p - mean|| for the 8 tokens (block reduction);
-//   * PACK (FP8 tokens with BF16 GEMMs only): the k-packed copy
-//     tkp[p0/8][c][0..7] = the 8 tokens' code values of channel c widened
-//     exactly to BF16, which the pooling GEMM reads with one vector load per
-//     (8 patches, channel).  Widening once here is cheaper than in every
-//     pooling workgroup that reads the token.  BF16 and FP32 tokens are read
-//     by the pooling GEMM in the caller's layout.
-// Each thread owns CW consecutive channels and loads them for all 8 tokens
-// (FP8: value = scale * code).
-template <int TOK, int WANT_R, int PACK>
+// r_p = ||f_p - mean|| for the 8 tokens (block reduction).  Each thread owns
+// CW consecutive channels and loads them for all 8 tokens (FP8: value =
+// scale * code).
+template <int TOK>
 __global__ __launch_bounds__(256) void k_resid(Batch b, Work wk) {
   constexpr int CW = TOK == 2 ? 8 : 4;
   const int f = blockIdx.y;
@@ -140,36 +134,22 @@ __global__ __launch_bounds__(256) void k_resid(Batch b, Work wk) {
   for (int chunk = tid; chunk < C / CW; chunk += 256) {
     const int c = chunk * CW;
     if (TOK == 2) {
-      // each code widened once to BF16 bits (exact): the packed copy and,
-      // times the token's scale, the residual norms
       uint2 codes[8];
       float sc[8];
       for (int i = 0; i < 8; ++i) {
         const int p = p0 + i;
         codes[i] = p < G ? *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(fd.tokens) + (int64_t)p * C + c)
                          : make_uint2(0u, 0u);
-        sc[i] = (WANT_R && p < G) ? fd.scale[p] : 0.f;
+        sc[i] = p < G ? fd.scale[p] : 0.f;
       }
-      uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(wk.tkp) + fd.t_base + ((int64_t)blockIdx.x * C + c) * 8);
-      float4 cv[8][2];  // the codes as floats (exact), channels c .. c + 7 of each token
+      float m[8];
+      for (int j = 0; j < 8; ++j) m[j] = mu[c + j];
       for (int i = 0; i < 8; ++i) {
-        cv[i][0] = e4m3x4_to_f32(codes[i].x);
-        cv[i][1] = e4m3x4_to_f32(codes[i].y);
-      }
-      for (int j = 0; j < 8; ++j) {
-        uint32_t q[8];
-        for (int i = 0; i < 8; ++i) {
-          const float4 x = cv[i][j >> 2];
-          const float y = (j & 3) == 0 ? x.x : (j & 3) == 1 ? x.y : (j & 3) == 2 ? x.z : x.w;
-          q[i] = __float_as_uint(y) >> 16;  // exact BF16 bits
-        }
-        if (PACK) dst[j] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
-        if (WANT_R) {
-          const float m = mu[c + j];
-          for (int i = 0; i < 8; ++i) {
-            const float dd = (p0 + i < G) ? sc[i] * bf16_to_f32(q[i]) - m : 0.f;
-            ss[i] += dd * dd;
-          }
+        const float4 x0 = e4m3x4_to_f32(codes[i].x), x1 = e4m3x4_to_f32(codes[i].y);
+        const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        for (int j = 0; j < 8; ++j) {
+          const float dd = (p0 + i < G) ? sc[i] * v[j] - m[j] : 0.f;
+          ss[i] += dd * dd;
         }
       }
     } else {
@@ -197,40 +177,29 @@ __global__ __launch_bounds__(256) void k_resid(Batch b, Work wk) {
       }
     }
   }
-  if (WANT_R) {
-    __shared__ float red[4][8];
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int i = 0; i < 8; ++i) {
-      float x = ss[i];
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-      if (lane == 0) red[wv][i] = x;
-    }
-    __syncthreads();
-    if (tid < 8 && p0 + tid < G)
-      wk.r[fd.r_base + p0 + tid] = __builtin_sqrtf(red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid]);
+  __shared__ float red[4][8];
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int i = 0; i < 8; ++i) {
+    float x = ss[i];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == 0) red[wv][i] = x;
   }
+  __syncthreads();
+  if (tid < 8 && p0 + tid < G)
+    wk.r[fd.r_base + p0 + tid] = __builtin_sqrtf(red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid]);
 }
 
-// Token statistics of every frame (want_r): chunk partial sums, the frame
-// mean, then r; and (pack) the k-packed copy of FP8 tokens.
-void launch_token_stats(const Batch& b, const Work& w, int gmax, int want_r, int pack, hipStream_t st) {
-  if (want_r) {
-    const dim3 cgrid(b.nchunk, b.n_frames);
-    if (b.tok_dtype == 0) hipLaunchKernelGGL(k_colsum<0>, cgrid, dim3(256), 0, st, b, w);
-    else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_colsum<1>, cgrid, dim3(256), 0, st, b, w);
-    else hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
-    hipLaunchKernelGGL(k_mean, dim3((b.C + 255) / 256, b.n_frames), dim3(256), 0, st, b, w);
-  }
-  pack = pack && b.tok_dtype == 2;
+// Token statistics of every frame: chunk partial sums, the frame mean, then r.
+void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st) {
+  const dim3 cgrid(b.nchunk, b.n_frames);
+  if (b.tok_dtype == 0) hipLaunchKernelGGL(k_colsum<0>, cgrid, dim3(256), 0, st, b, w);
+  else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_colsum<1>, cgrid, dim3(256), 0, st, b, w);
+  else hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
+  hipLaunchKernelGGL(k_mean, dim3((b.C + 255) / 256, b.n_frames), dim3(256), 0, st, b, w);
   const dim3 rgrid((gmax + 7) / 8, b.n_frames);
-  if (b.tok_dtype == 2) {
-    if (want_r && pack) hipLaunchKernelGGL((k_resid<2, 1, 1>), rgrid, dim3(256), 0, st, b, w);
-    else if (want_r) hipLaunchKernelGGL((k_resid<2, 1, 0>), rgrid, dim3(256), 0, st, b, w);
-    else if (pack) hipLaunchKernelGGL((k_resid<2, 0, 1>), rgrid, dim3(256), 0, st, b, w);
-  } else if (want_r) {
-    if (b.tok_dtype == 0) hipLaunchKernelGGL((k_resid<0, 1, 0>), rgrid, dim3(256), 0, st, b, w);
-    else hipLaunchKernelGGL((k_resid<1, 1, 0>), rgrid, dim3(256), 0, st, b, w);
-  }
+  if (b.tok_dtype == 2) hipLaunchKernelGGL(k_resid<2>, rgrid, dim3(256), 0, st, b, w);
+  else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_resid<1>, rgrid, dim3(256), 0, st, b, w);
+  else hipLaunchKernelGGL(k_resid<0>, rgrid, dim3(256), 0, st, b, w);
 }
 
 // D = r / (mean(r) + eps) for one frame (stage entry point only).

@@ -66,8 +66,6 @@ Shape capacity_shape(const disc_server_config& c, int E, int gemm_bf16) {
   s.n_tiles = ((c.max_masks + 63) / 64 + c.max_frames) * (c.c / 64);
   s.gemm_bf16 = gemm_bf16;
   s.want_dbar = true;  // any request may ask for the mean distinctiveness
-  s.pack_tokens = gemm_bf16 && c.tok_dtype == DISC_F8E4M3;
-  s.tkp_elems = (int64_t)c.max_frames * round_up(G, 8) * c.c;
   s.max_rows = c.max_h + 2;
   choose_splits(s);
   return s;

@@ -48,7 +48,7 @@ def test_noalloc_equals_embed_masks_ex(gpu):
     f1 = wl1.frames[0]
     print("noalloc: cfg1 frame, 8 masks, FP32", flush=True)
     _same(gpu, f1, dev_proj(wl1.proj, "f32"), False, "cfg1 FP32")
-    # BF16 operands (k-packed token copy in the scratch), then smaller again
+    # BF16 operands, then smaller again
     wl3 = di.workload("cfg3", frames=2)
     pb = dev_proj(wl3.proj, "bf16")
     print("noalloc: cfg3 frames 0-1, BF16", flush=True)
