@@ -83,6 +83,10 @@ def parse():
     ap.add_argument("--no-trace", action="store_true", help="skip per-stage event timing")
     ap.add_argument("--edt-layout", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="distance-transform band layout (-1: chosen per call)")
+    ap.add_argument("--pool-tile", type=int, default=-1, choices=[-1, 1, 2, 4],
+                    help="pooling channels per workgroup in units of 64 (-1: autotuned)")
+    ap.add_argument("--pool-rows", type=int, default=-1, choices=[-1, 64, 128],
+                    help="pooling masks per workgroup (-1: autotuned)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -694,7 +698,7 @@ def main():
     import paper_2603_03935_amd as disc
 
     disc.load()
-    opts = disc.make_options(edt_layout=args.edt_layout)
+    opts = disc.make_options(edt_layout=args.edt_layout, pool_tile=args.pool_tile, pool_rows=args.pool_rows)
     main_res, roof, main_chk, (ins, proj, outs, totals) = run_workload(
         disc, di, dev, args.config, args.steps, args.warmup, opts, not args.no_trace, True,
         sample_masks=128 if args.config in ("cfg1", "cfg2") else 24)

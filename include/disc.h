@@ -143,10 +143,14 @@ typedef struct disc_options {
                              every layout. */
   int32_t pool_tile;      /* channels per pooling workgroup in units of 64:
                              -1 (default) autotuned (the first call with a
-                             new problem shape times every width and keeps
-                             the fastest), or 1, 2 or 4 (4 and 2 only when
-                             they divide c / 64).  Results are identical bit
-                             for bit for every width. */
+                             new problem shape times every candidate shape
+                             and keeps the fastest), or 1, 2 or 4 (4 and 2
+                             only when they divide c / 64).  Results are
+                             identical bit for bit for every shape. */
+  int32_t pool_rows;      /* masks per pooling workgroup: -1 (default)
+                             autotuned together with pool_tile, 64 or 128
+                             (128 shares each token chunk between two mask
+                             tiles; it runs with pool_tile 1 or 2). */
 } disc_options;
 
 /* Fill *o with the defaults listed above. */

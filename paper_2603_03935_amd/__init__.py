@@ -102,7 +102,7 @@ class Out(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("spatial", ctypes.c_int32), ("distinct", ctypes.c_int32), ("eps", ctypes.c_float),
                 ("gemm_dtype", ctypes.c_int32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("edt_layout", ctypes.c_int32), ("pool_tile", ctypes.c_int32)]
+                ("edt_layout", ctypes.c_int32), ("pool_tile", ctypes.c_int32), ("pool_rows", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -267,12 +267,13 @@ def make_proj(proj) -> Proj:
 
 
 def make_options(spatial: int = SPATIAL_EDT, distinct: int = 1, eps: float = 1e-6, gemm_dtype: int = -1,
-                 workspace=None, edt_layout: int = -1, pool_tile: int = -1) -> Options:
+                 workspace=None, edt_layout: int = -1, pool_tile: int = -1, pool_rows: int = -1) -> Options:
     o = Options()
     load().disc_options_default(ctypes.byref(o))
     o.spatial, o.distinct, o.eps, o.gemm_dtype = spatial, distinct, eps, gemm_dtype
     o.edt_layout = edt_layout
     o.pool_tile = pool_tile
+    o.pool_rows = pool_rows
     if workspace is not None:
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()

@@ -126,6 +126,8 @@ disc_status check_opts(const disc_options* o, const char* who) {
     return fail(DISC_ERR_INVALID_ARGUMENT, "%s: edt_layout must be -1, 0, 1 or 2", who);
   if (o->pool_tile != -1 && o->pool_tile != 1 && o->pool_tile != 2 && o->pool_tile != 4)
     return fail(DISC_ERR_INVALID_ARGUMENT, "%s: pool_tile must be -1, 1, 2 or 4", who);
+  if (o->pool_rows != -1 && o->pool_rows != 64 && o->pool_rows != 128)
+    return fail(DISC_ERR_INVALID_ARGUMENT, "%s: pool_rows must be -1, 64 or 128", who);
   return DISC_OK;
 }
 
@@ -373,7 +375,7 @@ void build_plan(const std::vector<FrameIn>& fr, int C, int E, int gemm_bf16, Pla
     p.fds[i] = plan_frame(f, C, p.shape, a);
     for (int j = 0; j < f.m; ++j) p.mask_frame.push_back((int32_t)i);
     for (int m0 = 0; m0 < f.m; m0 += 64)
-      for (int n0 = 0; n0 < C; n0 += 64) p.tiles.push_back(make_int4((int)i, m0, n0, 0));
+      for (int n0 = 0; n0 < C; n0 += 64) p.tiles.push_back(make_int4((int)i, m0, n0, pool_pair_flag(m0, f.m)));
   }
   finish_plan(p, a);
 }
@@ -588,14 +590,15 @@ struct PoolKey {
 std::mutex g_tune_mu;
 std::map<PoolKey, int> g_tune;
 
-// launch the pooling GEMM for a choice nt | (unsplit << 4)
+// launch the pooling GEMM for a choice nt | (unsplit << 4) | ((mw - 1) << 5)
 void launch_pool_choice(const Batch& b, const Work& w, const int4* tiles, hipStream_t st, int choice) {
-  if (choice >> 4) {
+  const int nt = choice & 15, mw = 1 + ((choice >> 5) & 1);
+  if ((choice >> 4) & 1) {
     Batch b1 = b;
     b1.pool_split = 1;
-    launch_pool(b1, w, tiles, st, choice & 15);
+    launch_pool(b1, w, tiles, st, nt, mw);
   } else {
-    launch_pool(b, w, tiles, st, choice & 15);
+    launch_pool(b, w, tiles, st, nt, mw);
   }
 }
 
@@ -606,15 +609,20 @@ int pool_nt_rule(const Shape& s) {
 }
 }  // namespace
 
-// The pooling launch of a problem shape: channels per workgroup (NT x 64) and
-// whether K is split over several workgroups.  Every choice gives the same
-// bits (fixed K groups added in group order), so the first call of a shape
-// times each candidate twice and keeps the fastest; captured graphs and
-// untuned calls use a rule.  Returned as nt | (unsplit << 4).
+// The pooling launch of a problem shape: channels per workgroup (NT x 64),
+// masks per workgroup (64 or 128) and whether K is split over several
+// workgroups.  Every choice gives the same bits (each mask row sees the same
+// K steps, and fixed K groups are added in group order), so the first call of
+// a shape times each candidate twice and keeps the fastest; captured graphs
+// and untuned calls use a rule.  Returned as nt | (unsplit << 4) | ((mw - 1)
+// << 5).
 int pool_tile_choice(const Plan& p, int tok_dtype, const disc_options& o, bool tune, const Batch& b, const Work& w,
                      const int4* tiles, hipStream_t st, bool* ran) {
   *ran = false;
-  if (o.pool_tile > 0) return pool_nt_valid(p.shape.C, o.pool_tile) ? o.pool_tile : 1;
+  if (o.pool_tile > 0 || o.pool_rows > 0) {
+    const int nt = o.pool_tile > 0 && pool_nt_valid(p.shape.C, o.pool_tile) ? o.pool_tile : 1;
+    return o.pool_rows == 128 ? std::min(nt, 2) | (1 << 5) : nt;
+  }
   const Shape& s = p.shape;
   const PoolKey key{s.C, s.gemm_bf16, tok_dtype, s.n_tiles, s.pool_split, s.kgroups};
   {
@@ -627,6 +635,8 @@ int pool_tile_choice(const Plan& p, int tok_dtype, const disc_options& o, bool t
   for (int uns = 0; uns < (s.pool_split > 1 ? 2 : 1); ++uns)
     for (int nt : {1, 2, 4})
       if (pool_nt_valid(s.C, nt)) cand.push_back(nt | (uns << 4));
+  for (int nt : {1, 2})  // 128-mask workgroups, K never split
+    if (pool_nt_valid(s.C, nt) && s.M > 64) cand.push_back(nt | (1 << 5));
   std::vector<hipEvent_t> ev(4 * cand.size());
   for (auto& e : ev) (void)hipEventCreate(&e);
   for (size_t i = 0; i < cand.size(); ++i)
@@ -706,6 +716,7 @@ void disc_options_default(disc_options* o) {
   o->workspace_bytes = 0;
   o->edt_layout = -1;
   o->pool_tile = -1;
+  o->pool_rows = -1;
 }
 
 int32_t disc_abi_version(void) { return DISC_ABI_VERSION; }
@@ -967,7 +978,7 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32
   const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
   launch_user_weights(b, w, wts, cx.st);
   launch_pool_order(b, w, cx.st);
-  launch_pool(b, w, tiles, cx.st, o.pool_tile > 0 ? o.pool_tile : 1);
+  launch_pool(b, w, tiles, cx.st, o.pool_tile > 0 ? o.pool_tile : 1, o.pool_rows == 128 ? 2 : 1);
   launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, cx.st);
   if ((st = check_launch(who))) return st;
   return ok();

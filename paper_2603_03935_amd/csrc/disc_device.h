@@ -236,7 +236,13 @@ void launch_overlap(const int32_t* va, const int32_t* oa, int na, const int32_t*
 void launch_fuse(const int32_t* ids, const float* q, const float* emb, int m, int e, float* map_q, float* map_emb,
                  int n_map, int32_t* won, uint64_t* best, hipStream_t st);
 // nt: 64-channel tiles per workgroup (1, 2 or 4; any value gives the same result)
-void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st, int nt = 1);
+// A pooling tile (frame, m0, n0, pair flag): the flag is 1 when the frame's
+// next mask tile (m0 + 64) exists and joins this one in a 128-mask
+// workgroup, 0 when this tile stays alone, -1 when it is the second of a pair.
+__host__ __device__ inline int pool_pair_flag(int m0, int m) { return (m0 & 64) ? -1 : (m0 + 64 < m ? 1 : 0); }
+// nt: 64-channel tiles per workgroup (1, 2, 4); mw: 64-mask tiles per
+// workgroup (1, or 2 with nt <= 2 and K not split)
+void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st, int nt = 1, int mw = 1);
 bool pool_nt_valid(int C, int nt);
 void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st);
 // stage helpers

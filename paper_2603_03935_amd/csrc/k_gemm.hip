@@ -114,8 +114,9 @@ __device__ __forceinline__ void tile_krange(const Work& wk, const FrameDesc& fd,
 // The tile's rows resolved once (all threads call it; it synchronises):
 // (global mask index, index in the frame, Z bits, 1 if the row is stored
 // divided by Z else 0), or g = -1 past the frame's masks.
-__device__ __forceinline__ void pool_rows(const Work& wk, const FrameDesc& fd, int m0, int tid, int4* rows) {
-  if (tid < PBM) {
+__device__ __forceinline__ void pool_rows(const Work& wk, const FrameDesc& fd, int m0, int tid, int4* rows,
+                                          int nrows = PBM) {
+  if (tid < nrows) {
     int4 v = make_int4(-1, 0, 0, 0);
     if (m0 + tid < fd.m) {
       const int mi = wk.perm[fd.mask_base + m0 + tid];
@@ -148,11 +149,15 @@ __device__ __forceinline__ void pool_store(const Work& wk, const FrameDesc& fd, 
 }
 
 // grid: (tiles / NT) x S; workgroup (super-tile, s) takes the s-th share of the
-// K groups of NT adjacent tiles
-template <int BF16, int TOK, int NT>
+// K groups of NT adjacent tiles.  MW = 2: 128 masks (the tile and the next
+// mask tile of its frame, its partner, whose tiles are C / 64 entries later in
+// the list) share each token chunk, which halves the token reads; the
+// partner's own workgroups return at once.  Every mask row sees the same K
+// steps and group folds either way, so the bits do not depend on MW.
+template <int BF16, int TOK, int NT, int MW>
 __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tiles) {
   constexpr int BN = PBN * NT;  // channels per workgroup
-  const int S = b.pool_split;
+  const int S = MW == 1 ? b.pool_split : 1;
   const int nlive = b.dyn[2] / NT * S;  // live workgroups (NT divides the channel tiles of a mask tile)
   if ((int)blockIdx.x >= nlive) return;
   // without split K, one XCD takes consecutive super-tiles (the channel tiles
@@ -163,16 +168,17 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   const int stix = vb / S, sidx = vb - stix * S;
   const int tix = stix * NT;  // first 64-channel tile
   const int4 t = tiles[tix];
+  if (MW == 2 && t.w < 0) return;  // the second half of a 128-mask tile
   const FrameDesc fd = b.frames[t.x];
   const int m0 = t.y, n0 = t.z, C = b.C;
-  const int mrows = min(PBM, fd.m - m0);
+  const int mrows = min(PBM * MW, fd.m - m0);
   const int G = fd.G;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
 
   __shared__ int kmin_sh, kmax_sh;
-  __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? PBM * PAS : 1];
+  __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? PBM * MW * PAS : 1];
   __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? BN * PAS : 1];
-  __shared__ float As32[BF16 ? 1 : PBM * (PBK + 1)];
+  __shared__ float As32[BF16 ? 1 : PBM * MW * (PBK + 1)];
   __shared__ __attribute__((aligned(16))) float Bs32[BF16 ? 1 : PBK * BN];
 
   int kbeg, kend;
@@ -198,13 +204,20 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   }
 
   const floatx16 zero16 = {};
-  floatx16 total[NT], acc[NT];
+  floatx16 total[MW][NT], acc[MW][NT];
 #pragma unroll
-  for (int j = 0; j < NT; ++j) total[j] = acc[j] = zero16;
+  for (int h = 0; h < MW; ++h)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) total[h][j] = acc[h][j] = zero16;
 
-  const int ar = tid >> 2, ak = (tid & 3) * 8;        // A: row, first k of 8
-  const bool arow_ok = ar < mrows;
-  const int64_t wrow0 = fd.w_base + (int64_t)(arow_ok ? wk.perm[fd.mask_base + m0 + ar] : 0) * fd.Gs;
+  const int ar = tid >> 2, ak = (tid & 3) * 8;        // A: rows ar (+ 64 h), first k of 8
+  bool arow_ok[MW];
+  int64_t wrow0[MW];
+#pragma unroll
+  for (int h = 0; h < MW; ++h) {
+    arow_ok[h] = ar + 64 * h < mrows;
+    wrow0[h] = fd.w_base + (int64_t)(arow_ok[h] ? wk.perm[fd.mask_base + m0 + 64 * h + ar] : 0) * fd.Gs;
+  }
   // B (BF16): the caller's [G][C] tokens, patches 2 pp, 2 pp + 1 and
   // channels c4 .. c4 + 3 (+ 64 j) per thread, transposed into LDS as
   // (patch pair, channel) words
@@ -216,17 +229,20 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   // flight while step k computes (small batches are latency-bound).  BF16:
   // one set, one step ahead (more resident workgroups hide the latency).
   constexpr int DIST = BF16 ? 1 : 2;
-  uint4 ra16[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+  uint4 ra16[2][MW];
   uint4 rbr[2][NT][2];  // raw token words of patches 2 pp, 2 pp + 1: FP32 float4 bits, BF16 .xy, FP8 .x
-  float ra32[2][8], rb32[2][NT][8];
+  float ra32[2][MW][8], rb32[2][NT][8];
 
   auto fetch = [&](int k0, int q) {
     const int kk = k0 + ak;
     // weight rows are Gs (a multiple of 8) long and hold exact zeros outside
     // the mask's patch rectangle
     if (BF16) {
-      const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0 + kk;
-      ra16[q] = arow_ok && kk < G ? *reinterpret_cast<const uint4*>(src) : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int h = 0; h < MW; ++h) {
+        const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0[h] + kk;
+        ra16[q][h] = arow_ok[h] && kk < G ? *reinterpret_cast<const uint4*>(src) : make_uint4(0u, 0u, 0u, 0u);
+      }
       const int kb = k0 + 2 * bpp;
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
@@ -250,13 +266,16 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
       }
     } else {
       // weight rows start on 8 elements (Gs and the frame bases are multiples of 8)
-      const float* src = reinterpret_cast<const float*>(wk.W) + wrow0 + kk;
-      if (arow_ok && kk < G) {
-        const float4 x = reinterpret_cast<const float4*>(src)[0], y = reinterpret_cast<const float4*>(src)[1];
-        ra32[q][0] = x.x; ra32[q][1] = x.y; ra32[q][2] = x.z; ra32[q][3] = x.w;
-        ra32[q][4] = y.x; ra32[q][5] = y.y; ra32[q][6] = y.z; ra32[q][7] = y.w;
-      } else {
-        for (int j = 0; j < 8; ++j) ra32[q][j] = 0.f;
+#pragma unroll
+      for (int h = 0; h < MW; ++h) {
+        const float* src = reinterpret_cast<const float*>(wk.W) + wrow0[h] + kk;
+        if (arow_ok[h] && kk < G) {
+          const float4 x = reinterpret_cast<const float4*>(src)[0], y = reinterpret_cast<const float4*>(src)[1];
+          ra32[q][h][0] = x.x; ra32[q][h][1] = x.y; ra32[q][h][2] = x.z; ra32[q][h][3] = x.w;
+          ra32[q][h][4] = y.x; ra32[q][h][5] = y.y; ra32[q][h][6] = y.z; ra32[q][h][7] = y.w;
+        } else {
+          for (int j = 0; j < 8; ++j) ra32[q][h][j] = 0.f;
+        }
       }
       const int kr = k0 + bk32;
 #pragma unroll
@@ -265,7 +284,8 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   };
   auto stage = [&](int q) {
     if (BF16) {
-      *reinterpret_cast<uint4*>(&As16[ar * PAS + ak]) = ra16[q];
+#pragma unroll
+      for (int h = 0; h < MW; ++h) *reinterpret_cast<uint4*>(&As16[(ar + 64 * h) * PAS + ak]) = ra16[q][h];
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
         // channel bc4 + e: patches 2 pp and 2 pp + 1 as one word (BF16 bits)
@@ -295,7 +315,9 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
         }
       }
     } else {
-      for (int j = 0; j < 8; ++j) As32[ar * (PBK + 1) + ak + j] = ra32[q][j];
+#pragma unroll
+      for (int h = 0; h < MW; ++h)
+        for (int j = 0; j < 8; ++j) As32[(ar + 64 * h) * (PBK + 1) + ak + j] = ra32[q][h][j];
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
         *reinterpret_cast<float4*>(&Bs32[bk32 * BN + bn32 + 64 * j]) = make_float4(rb32[q][j][0], rb32[q][j][1], rb32[q][j][2], rb32[q][j][3]);
@@ -306,17 +328,20 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   // a finished K group: add it to the running total, or store it for the reduce pass
   auto fold = [&](int grp) {
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      if (S == 1) {
-        total[j] += acc[j];
-      } else {
-        // sub-tile j of this wavefront lies in 64-channel tile tix + j
-        float4* dst = reinterpret_cast<float4*>(wk.ppart + (((int64_t)(tix + j) * b.kgroups + grp) * (PBM * PBN)) + tid * 16);
+    for (int h = 0; h < MW; ++h)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dst[i] = make_float4(acc[j][4 * i], acc[j][4 * i + 1], acc[j][4 * i + 2], acc[j][4 * i + 3]);
+      for (int j = 0; j < NT; ++j) {
+        if (S == 1) {
+          total[h][j] += acc[h][j];
+        } else {
+          // sub-tile j of this wavefront lies in 64-channel tile tix + j (MW = 1)
+          float4* dst = reinterpret_cast<float4*>(wk.ppart + (((int64_t)(tix + j) * b.kgroups + grp) * (PBM * PBN)) + tid * 16);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            dst[i] = make_float4(acc[h][j][4 * i], acc[h][j][4 * i + 1], acc[h][j][4 * i + 2], acc[h][j][4 * i + 3]);
+        }
+        acc[h][j] = zero16;
       }
-      acc[j] = zero16;
-    }
   };
 
   const int lr = lane & 31, lk = lane >> 5;
@@ -337,22 +362,30 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
     if (BF16) {
 #pragma unroll
       for (int kk = 0; kk < PBK; kk += 16) {
-        const u16x8 av = *reinterpret_cast<const u16x8*>(&As16[(32 * wm + lr) * PAS + kk + 8 * lk]);
+        u16x8 av[MW];
+#pragma unroll
+        for (int h = 0; h < MW; ++h) av[h] = *reinterpret_cast<const u16x8*>(&As16[(64 * h + 32 * wm + lr) * PAS + kk + 8 * lk]);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const int row = 64 * j + 32 * wn + lr;
           const u16x8 bv = *reinterpret_cast<const u16x8*>(&Bs16[row * PAS + bsw(row, (kk >> 3) + lk) * 8]);
-          acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc[j], 0, 0, 0);
+#pragma unroll
+          for (int h = 0; h < MW; ++h)
+            acc[h][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[h]),
+                                                                __builtin_bit_cast(bf16x8, bv), acc[h][j], 0, 0, 0);
         }
       }
     } else {
 #pragma unroll
       for (int kk = 0; kk < PBK; kk += 2) {
-        const float a = As32[(32 * wm + lr) * (PBK + 1) + kk + lk];
+        float a[MW];
+#pragma unroll
+        for (int h = 0; h < MW; ++h) a[h] = As32[(64 * h + 32 * wm + lr) * (PBK + 1) + kk + lk];
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const float bb = Bs32[(kk + lk) * BN + 64 * j + 32 * wn + lr];
-          acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc[j], 0, 0, 0);
+#pragma unroll
+          for (int h = 0; h < MW; ++h) acc[h][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h], bb, acc[h][j], 0, 0, 0);
         }
       }
     }
@@ -371,10 +404,12 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   }
   advance(gb);
   if (S == 1) {
-    __shared__ int4 rows[PBM];
-    pool_rows(wk, fd, m0, tid, rows);
+    __shared__ int4 rows[PBM * MW];
+    pool_rows(wk, fd, m0, tid, rows, PBM * MW);
 #pragma unroll
-    for (int j = 0; j < NT; ++j) pool_store<BF16>(wk, fd, rows, n0 + 64 * j, C, lane, wm, wn, total[j]);
+    for (int h = 0; h < MW; ++h)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) pool_store<BF16>(wk, fd, rows + 64 * h, n0 + 64 * j, C, lane, wm, wn, total[h][j]);
   }
 }
 
@@ -408,32 +443,40 @@ __global__ __launch_bounds__(256) void k_pool_reduce(Batch b, Work wk, const int
 }
 
 template <int BF16, int TOK>
-static void launch_pool_t(const Batch& b, const Work& w, const int4* tiles, int nt, hipStream_t st) {
+static void launch_pool_t(const Batch& b, const Work& w, const int4* tiles, int nt, int mw, hipStream_t st) {
   const dim3 block(256);
-  const int S = b.pool_split;
+  const int S = mw == 2 ? 1 : b.pool_split;
+  if (mw == 2) {
+    if (nt == 2)
+      hipLaunchKernelGGL((k_pool<BF16, TOK, 2, 2>), dim3(b.n_tiles / 2), block, 0, st, b, w, tiles);
+    else
+      hipLaunchKernelGGL((k_pool<BF16, TOK, 1, 2>), dim3(b.n_tiles), block, 0, st, b, w, tiles);
+    return;
+  }
   if (nt == 4)
-    hipLaunchKernelGGL((k_pool<BF16, TOK, 4>), dim3(b.n_tiles / 4 * S), block, 0, st, b, w, tiles);
+    hipLaunchKernelGGL((k_pool<BF16, TOK, 4, 1>), dim3(b.n_tiles / 4 * S), block, 0, st, b, w, tiles);
   else if (nt == 2)
-    hipLaunchKernelGGL((k_pool<BF16, TOK, 2>), dim3(b.n_tiles / 2 * S), block, 0, st, b, w, tiles);
+    hipLaunchKernelGGL((k_pool<BF16, TOK, 2, 1>), dim3(b.n_tiles / 2 * S), block, 0, st, b, w, tiles);
   else
-    hipLaunchKernelGGL((k_pool<BF16, TOK, 1>), dim3(b.n_tiles * S), block, 0, st, b, w, tiles);
+    hipLaunchKernelGGL((k_pool<BF16, TOK, 1, 1>), dim3(b.n_tiles * S), block, 0, st, b, w, tiles);
   if (S > 1) hipLaunchKernelGGL((k_pool_reduce<BF16>), dim3(b.n_tiles), block, 0, st, b, w, tiles);
 }
 
 // NT must divide C / 64 (the tiles of one mask tile are consecutive in the list)
 bool pool_nt_valid(int C, int nt) { return nt == 1 || ((C / 64) % nt == 0); }
 
-void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st, int nt) {
+void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st, int nt, int mw) {
   if (b.n_tiles <= 0) return;
   if (!pool_nt_valid(b.C, nt)) nt = 1;
+  if (mw == 2 && nt > 2) nt = 2;
   if (b.gemm_bf16) {
-    if (b.tok_dtype == 0) launch_pool_t<1, 0>(b, w, tiles, nt, st);
-    else if (b.tok_dtype == 1) launch_pool_t<1, 1>(b, w, tiles, nt, st);
-    else launch_pool_t<1, 2>(b, w, tiles, nt, st);
+    if (b.tok_dtype == 0) launch_pool_t<1, 0>(b, w, tiles, nt, mw, st);
+    else if (b.tok_dtype == 1) launch_pool_t<1, 1>(b, w, tiles, nt, mw, st);
+    else launch_pool_t<1, 2>(b, w, tiles, nt, mw, st);
   } else {
-    if (b.tok_dtype == 0) launch_pool_t<0, 0>(b, w, tiles, nt, st);
-    else if (b.tok_dtype == 1) launch_pool_t<0, 1>(b, w, tiles, nt, st);
-    else launch_pool_t<0, 2>(b, w, tiles, nt, st);
+    if (b.tok_dtype == 0) launch_pool_t<0, 0>(b, w, tiles, nt, mw, st);
+    else if (b.tok_dtype == 1) launch_pool_t<0, 1>(b, w, tiles, nt, mw, st);
+    else launch_pool_t<0, 2>(b, w, tiles, nt, mw, st);
   }
 }
 

@@ -64,7 +64,10 @@ __global__ void k_stage_frame(FrameDesc d, int32_t M, int32_t C, int32_t n_tiles
   if (i < 32) counts[i] = 0;
   const int nct = C / 64;
   for (int k = i; k < M; k += stride) mask_frame[k] = 0;
-  for (int t = i; t < n_tiles; t += stride) tiles[t] = make_int4(0, (t / nct) * 64, (t % nct) * 64, 0);
+  for (int t = i; t < n_tiles; t += stride) {
+    const int m0 = (t / nct) * 64;
+    tiles[t] = make_int4(0, m0, (t % nct) * 64, pool_pair_flag(m0, M));
+  }
 }
 
 }  // namespace host

@@ -40,7 +40,7 @@ def test_abi_version_and_defaults(lib):
     assert lib.disc_abi_version() == 4
     o = disc.Options()
     lib.disc_options_default(ctypes.byref(o))
-    assert (o.spatial, o.distinct, o.gemm_dtype, o.edt_layout, o.pool_tile) == (0, 1, -1, -1, -1)
+    assert (o.spatial, o.distinct, o.gemm_dtype, o.edt_layout, o.pool_tile, o.pool_rows) == (0, 1, -1, -1, -1, -1)
     assert abs(o.eps - 1e-6) < 1e-12 and o.workspace is None and o.workspace_bytes == 0
 
 
@@ -102,6 +102,9 @@ def test_null_arguments(lib):
     assert call(lib, t, m, p, o, opts) == 1
     lib.disc_options_default(ctypes.byref(opts))
     opts.pool_tile = 3
+    assert call(lib, t, m, p, o, opts) == 1
+    lib.disc_options_default(ctypes.byref(opts))
+    opts.pool_rows = 96
     assert call(lib, t, m, p, o, opts) == 1
 
 

@@ -376,18 +376,21 @@ def test_cfg5_full_batch_sampled(gpu):
 
 @pytest.mark.parametrize("name,frames", [("cfg2", None), ("cfg3", 6), ("cfg5", 2)])
 def test_pool_tile_widths_agree_bitwise(gpu, name, frames):
-    """The pooling GEMM's tile widths (1, 2, 4 x 64 channels per workgroup) and
-    the autotuned choice give the same bits."""
+    """Every pooling tile shape the autotuner searches (1, 2, 4 x 64 channels
+    and 64 or 128 masks per workgroup) and the tuned choice give the same
+    pooled features and embeddings, bit for bit."""
     wl = di.workload(name, frames=frames)
     ins = [frame_input(f) for f in wl.frames]
     proj = dev_proj(wl.proj, wl.proj_dtype)
     res = {}
-    for nt in (-1, 1, 2, 4):
-        outs = gpu.embed_frames(ins, proj, options=gpu.make_options(pool_tile=nt))
-        res[nt] = [o.out.cpu().numpy() for o in outs]
-    for nt in (1, 2, 4):
-        for i, (a, b) in enumerate(zip(res[-1], res[nt])):
-            assert np.array_equal(a, b), f"{name}: pool_tile {nt} differs from the tuned width on frame {i}"
+    shapes = [(-1, -1), (1, 64), (2, 64), (4, 64), (1, 128), (2, 128)]
+    for nt, rows in shapes:
+        outs = gpu.embed_frames(ins, proj, pooled=True, options=gpu.make_options(pool_tile=nt, pool_rows=rows))
+        res[(nt, rows)] = [(o.out.cpu().numpy(), o.pooled.cpu().numpy()) for o in outs]
+    for key in shapes[1:]:
+        for i, ((a, pa), (b, pb)) in enumerate(zip(res[shapes[0]], res[key])):
+            assert np.array_equal(pa, pb), f"{name}: pooled features of shape {key} differ from the tuned one on frame {i}"
+            assert np.array_equal(a, b), f"{name}: embeddings of shape {key} differ from the tuned one on frame {i}"
 
 
 def test_projection_split_invariance(gpu):
