@@ -351,8 +351,9 @@ disc_status disc_dbscan_denoise(const float* points, const int32_t* offsets, int
  *   voffsets [m + 1] int32 written (prefix sums of the voxel counts),
  *   voxels [n][3] int32 (capacity n rows; rows [voffsets[i], voffsets[i+1])
  *   written), status [m] int32 or NULL: 0 ok, 1 some point's voxel lies
- *   beyond +-32767 per axis (the point is left out), 2 more than 8192
- *   distinct voxels (the segment's rows are left unwritten).
+ *   beyond +-32767 per axis (the point is left out).  Any number of voxels
+ *   per segment (beyond 8192 the segment is sorted in chunks and merged by
+ *   rank, within its workgroup).
  * n <= 2^23, m <= 65535, voxel > 0.  Asynchronous on `stream`. */
 disc_status disc_voxelize(const float* points, const int32_t* offsets, const int32_t* keep, int32_t m, int32_t n,
                           float voxel, int32_t* voffsets, int32_t* voxels, int32_t* status, void* stream);

@@ -440,23 +440,20 @@ __global__ __launch_bounds__(256) void k_vox_gather(VoxWork d, int n, const int3
   if (act) d.tmp[voff[seg] + r] = k;
 }
 
-// one workgroup per segment: bitonic sort of its keys in LDS (at most
-// kVoxSortMax), written as int32 (x, y, z) triples
+// One workgroup per segment sorts its keys (distinct, so every key has one
+// rank).  Up to kVoxSortMax keys: a bitonic sort in LDS.  More: each chunk of
+// kVoxSortMax keys is sorted in LDS and written back in place, then every
+// key's rank is its place in its own chunk plus, for every other chunk,
+// the number of that chunk's keys below it (a binary search with the chunk
+// in LDS); the keys are scattered to their ranks in `sorted` (this segment's
+// range of a scratch array) and written out from there.  The ranks are kept
+// in the segment's output rows until the scatter.
 constexpr int kVoxSortMax = 8192;
 
-__global__ __launch_bounds__(1024) void k_vox_sort(const uint64_t* tmp, const int32_t* voff, int32_t* vox,
-                                                   int32_t* status) {
-  __shared__ uint64_t sk[kVoxSortMax];
-  const int seg = blockIdx.x;
-  const int b = voff[seg], n = voff[seg + 1] - b;
-  if (n == 0) return;
-  if (n > kVoxSortMax) {  // more distinct voxels than one workgroup sorts: status 2, rows left unwritten
-    if (threadIdx.x == 0 && status) status[seg] = 2;
-    return;
-  }
+__device__ void vox_bitonic(uint64_t* sk, int n) {
   int N = 1;
   while (N < n) N <<= 1;
-  for (int k = threadIdx.x; k < N; k += 1024) sk[k] = k < n ? tmp[b + k] : kEmpty;
+  for (int k = n + threadIdx.x; k < N; k += 1024) sk[k] = kEmpty;
   __syncthreads();
   for (int size = 2; size <= N; size <<= 1)
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -472,13 +469,58 @@ __global__ __launch_bounds__(1024) void k_vox_sort(const uint64_t* tmp, const in
       }
       __syncthreads();
     }
-  for (int k = threadIdx.x; k < n; k += 1024) {
-    const uint64_t key = sk[k];
-    int32_t* o = vox + 3 * (int64_t)(b + k);
-    o[0] = (int32_t)((key >> 32) & 0xFFFF) - 32768;
-    o[1] = (int32_t)((key >> 16) & 0xFFFF) - 32768;
-    o[2] = (int32_t)(key & 0xFFFF) - 32768;
+}
+
+__device__ __forceinline__ void vox_write(int32_t* o, uint64_t key) {
+  o[0] = (int32_t)((key >> 32) & 0xFFFF) - 32768;
+  o[1] = (int32_t)((key >> 16) & 0xFFFF) - 32768;
+  o[2] = (int32_t)(key & 0xFFFF) - 32768;
+}
+
+__global__ __launch_bounds__(1024) void k_vox_sort(uint64_t* tmp, const int32_t* voff, int32_t* vox, uint64_t* sorted) {
+  __shared__ uint64_t sk[kVoxSortMax];
+  const int seg = blockIdx.x;
+  const int b = voff[seg], n = voff[seg + 1] - b;
+  if (n == 0) return;
+  if (n <= kVoxSortMax) {
+    for (int k = threadIdx.x; k < n; k += 1024) sk[k] = tmp[b + k];
+    vox_bitonic(sk, n);
+    for (int k = threadIdx.x; k < n; k += 1024) vox_write(vox + 3 * (int64_t)(b + k), sk[k]);
+    return;
   }
+  const int nch = (n + kVoxSortMax - 1) / kVoxSortMax;
+  // sorted chunks, in place; each key's rank starts at its place in its chunk
+  for (int c = 0; c < nch; ++c) {
+    const int c0 = c * kVoxSortMax, len = min(kVoxSortMax, n - c0);
+    for (int k = threadIdx.x; k < len; k += 1024) sk[k] = tmp[b + c0 + k];
+    vox_bitonic(sk, len);
+    for (int k = threadIdx.x; k < len; k += 1024) {
+      tmp[b + c0 + k] = sk[k];
+      vox[3 * (int64_t)(b + c0 + k)] = k;
+    }
+    __syncthreads();
+  }
+  // plus the keys below it in every other chunk
+  for (int c = 0; c < nch; ++c) {
+    const int c0 = c * kVoxSortMax, len = min(kVoxSortMax, n - c0);
+    for (int k = threadIdx.x; k < len; k += 1024) sk[k] = tmp[b + c0 + k];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 1024) {
+      if (i >= c0 && i < c0 + len) continue;
+      const uint64_t key = tmp[b + i];
+      int lo = 0, hi = len;  // first entry not below key
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sk[mid] < key) lo = mid + 1;
+        else hi = mid;
+      }
+      vox[3 * (int64_t)(b + i)] += lo;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += 1024) sorted[b + vox[3 * (int64_t)(b + i)]] = tmp[b + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 1024) vox_write(vox + 3 * (int64_t)(b + i), sorted[b + i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -649,7 +691,8 @@ void launch_voxelize(const float* pts, const int32_t* off, const int32_t* keep, 
     hipLaunchKernelGGL(k_vox_insert, dim3((n + 255) / 256), dim3(256), 0, st, pts, off, keep, m, n, v, d, status);
   exclusive_scan(d.vcnt, m, voff, true, scratch, st);
   if (n > 0) hipLaunchKernelGGL(k_vox_gather, dim3((n + 255) / 256), dim3(256), 0, st, d, n, voff);
-  if (m > 0) hipLaunchKernelGGL(k_vox_sort, dim3(m), dim3(1024), 0, st, d.tmp, voff, vox, status);
+  // the hash table is free once the keys are gathered: it holds the scattered keys of large segments
+  if (m > 0) hipLaunchKernelGGL(k_vox_sort, dim3(m), dim3(1024), 0, st, d.tmp, voff, vox, d.keys);
 }
 
 void launch_overlap(const int32_t* va, const int32_t* oa, int na, const int32_t* vb, const int32_t* ob, int nb,

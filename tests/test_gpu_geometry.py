@@ -115,8 +115,9 @@ def test_voxel_overlap_vs_oracle(gpu):
 
 def test_cloud_edge_cases(gpu):
     """Empty segments, a one-point segment, a segment with more distinct voxels
-    than one workgroup sorts (status 2, its count still exact) and a point
-    whose voxel lies beyond the key range (status 1, the point left out)."""
+    than one workgroup sorts in LDS at once (10000: two chunks merged by rank)
+    and a point whose voxel lies beyond the key range (status 1, the point
+    left out)."""
     t = torch()
     rng = np.random.default_rng(71)
     v = 0.05
@@ -131,9 +132,33 @@ def test_cloud_edge_cases(gpu):
     assert np.array_equal(keep, og.dbscan_keep(pts, off, 0.05, 3))
     vox, voff, status = gpu.voxelize(dp, doff, v)
     voff, status, vox = voff.cpu().numpy(), status.cpu().numpy(), vox.cpu().numpy()
-    assert status.tolist() == [0, 0, 0, 0, 2, 1]
+    assert status.tolist() == [0, 0, 0, 0, 0, 1]
     far = np.arange(len(pts)) != len(pts) - 1  # the oracle without the out-of-range point
     rv, roff = og.voxelize(pts, off, far.astype(np.uint8), v)
-    assert np.array_equal(voff, roff), "voxel counts (exact also for the oversized segment)"
-    for s in (0, 1, 2, 3, 5):
+    assert np.array_equal(voff, roff), "voxel counts"
+    for s in range(6):
         assert np.array_equal(vox[voff[s]:voff[s + 1]], rv[roff[s]:roff[s + 1]]), f"segment {s}"
+
+
+def test_large_segment_voxels(gpu):
+    """A 4 m x 4 m floor at 2 cm voxels (40000 distinct voxels, five sorted
+    chunks merged by rank) beside small segments, with points in shuffled
+    order and several points per voxel: the same sorted voxel list as the
+    oracle."""
+    t = torch()
+    rng = np.random.default_rng(72)
+    v = 0.02
+    ij = np.stack(np.meshgrid(np.arange(200), np.arange(200), indexing="ij"), -1).reshape(-1, 2)
+    floor = np.concatenate([(ij + rng.uniform(0.05, 0.95, ij.shape)) * v for _ in range(2)])
+    floor = np.concatenate([floor, np.full((len(floor), 1), 0.013)], axis=1)
+    floor = floor[rng.permutation(len(floor))]
+    segs = [0.5 + 0.1 * rng.standard_normal((300, 3)), floor, np.zeros((0, 3)), rng.uniform(-3, 3, (9000, 3))]
+    pts = np.concatenate(segs).astype(np.float32)
+    off = np.cumsum([0] + [len(x) for x in segs]).astype(np.int64)
+    vox, voff, status = gpu.voxelize(t.from_numpy(pts).cuda(), t.from_numpy(off.astype(np.int32)).cuda(), v)
+    voff, status, vox = voff.cpu().numpy(), status.cpu().numpy(), vox.cpu().numpy()
+    rv, roff = og.voxelize(pts, off, None, v)
+    assert not status.any()
+    assert roff[2] - roff[1] == 40000
+    assert np.array_equal(voff, roff)
+    assert np.array_equal(vox, rv)
