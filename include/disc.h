@@ -117,7 +117,9 @@ typedef struct disc_proj {
 typedef struct disc_out {
   float* data;          /* [m][e] FP32 */
   int32_t m, e;
-  int32_t* mask_status; /* optional [m]: 0 ok, 1 empty mask, 2 zero projection */
+  int32_t* mask_status; /* optional [m]: 0 ok, 1 empty mask, 2 zero projection,
+                           3 the frame's FP8 scales hold a NaN, infinite or
+                           negative value (every mask of that frame) */
   float* pooled;        /* optional [m][c] FP32 weighted-mean features F */
   float* dbar;          /* optional [m]: the mask's mean distinctiveness, D of
                            Eq. (1) (with eps) averaged over the mask's pixels,

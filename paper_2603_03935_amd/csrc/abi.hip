@@ -152,7 +152,7 @@ Layout make_layout(const Shape& s) {
   L.mask_frame = take(4 * (size_t)s.M);
   L.tiles = take(16 * (size_t)s.n_tiles);
   L.dyn = take(16);
-  L.counts = take(4 * 32);
+  L.counts = take(4 * (32 + (size_t)s.n_frames));  // class counters, then the per-frame scale flags
   L.staged_end = off;
   L.bbox = take(16 * (size_t)s.M);
   L.area = take(4 * (size_t)s.M);
@@ -284,6 +284,7 @@ Work work_ptrs(char* base, const Layout& L) {
   w.mrec = reinterpret_cast<MaskRec*>(base + L.mrec);
   w.items = reinterpret_cast<int32_t*>(base + L.items);
   w.counts = reinterpret_cast<int32_t*>(base + L.counts);
+  w.fbad = w.counts + 32;
   w.psum = reinterpret_cast<float*>(base + L.psum);
   w.mean = reinterpret_cast<float*>(base + L.mean);
   w.r = reinterpret_cast<float*>(base + L.r);
@@ -402,7 +403,7 @@ void stage_host(const Plan& p, char* host, char* dev) {
   if (!p.tiles.empty()) std::memcpy(host + p.L.tiles, p.tiles.data(), 16 * p.tiles.size());
   const int32_t dyn[4] = {p.shape.n_frames, (int32_t)p.shape.M, p.shape.n_tiles, 0};
   std::memcpy(host + p.L.dyn, dyn, sizeof dyn);
-  std::memset(host + p.L.counts, 0, 4 * 32);
+  std::memset(host + p.L.counts, 0, 4 * (32 + (size_t)p.shape.n_frames));
 }
 
 Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int distinct) {
@@ -678,9 +679,10 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   const int4* tiles = reinterpret_cast<const int4*>(dev_ws + p.L.tiles);
   // token statistics first: the mask scan folds r into the mean distinctiveness
   const bool want_r = o.distinct || p.shape.want_dbar;
-  if (want_r) {
+  if (want_r || tok_dtype == DISC_F8E4M3) {
     StageTimer t(sid < 0 ? -1 : ST_STATS, st);
-    launch_token_stats(b, w, p.shape.gmax, st);
+    if (tok_dtype == DISC_F8E4M3) launch_scale_check(b, w, p.shape.gmax, st);
+    if (want_r) launch_token_stats(b, w, p.shape.gmax, st);
     if (p.shape.want_dbar) launch_rbar(b, w, st);
   }
   { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st, p.shape.want_dbar); }
@@ -976,6 +978,7 @@ disc_status disc_pool_project(const disc_tokens* tokens, const float* wts, int32
   const Batch b = make_batch(p, cx.dev_ws, tokens->dtype, 0, 1);
   const Work w = work_ptrs(cx.dev_ws, p.L);
   const int4* tiles = reinterpret_cast<const int4*>(cx.dev_ws + p.L.tiles);
+  if (tokens->dtype == DISC_F8E4M3) launch_scale_check(b, w, p.shape.gmax, cx.st);
   launch_user_weights(b, w, wts, cx.st);
   launch_pool_order(b, w, cx.st);
   launch_pool(b, w, tiles, cx.st, o.pool_tile > 0 ? o.pool_tile : 1, o.pool_rows == 128 ? 2 : 1);

@@ -144,6 +144,7 @@ struct Work {
   MaskRec* mrec;       // [M]
   int32_t* items;      // [kClasses][item_cap] (mask << 8) | strip, one list per class
   int32_t* counts;     // [kClasses] items per class (zeroed when a batch is staged)
+  int32_t* fbad;       // [frames] 1 when a frame's FP8 scales include a non-finite or negative value (zeroed when staged)
   float* psum;         // [F][nchunk][C]
   float* mean;         // [F][C]
   float* r;            // [sum G]
@@ -215,6 +216,8 @@ void edt_prepare();
 void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
 void launch_rbar(const Batch& b, const Work& w, hipStream_t st);
+// FP8 tokens: flag the frames whose scales hold a non-finite or negative value
+void launch_scale_check(const Batch& b, const Work& w, int gmax, hipStream_t st);
 void launch_quality(const int32_t* area, const float* dbar, const float* emb, const float* g, const float* angle, int m,
                     int e, int img_h, int img_w, float lambda, float* q, float* comp, hipStream_t st);
 void launch_angle(const float* rays, const float* normals, int nv, const int32_t* off, int m, float* angle,

@@ -812,7 +812,7 @@ __global__ __launch_bounds__(256) void k_norm(Batch b, Work wk) {
     const int c = lane * 4 + 256 * k;
     if (c < E) *reinterpret_cast<float4*>(o + c) = make_float4(v[k].x * inv, v[k].y * inv, v[k].z * inv, v[k].w * inv);
   }
-  if (lane == 0 && fd.status) fd.status[i] = st_in != 0 ? 1 : (ss > 0.f ? 0 : 2);
+  if (lane == 0 && fd.status) fd.status[i] = st_in != 0 ? st_in : (ss > 0.f ? 0 : 2);
 }
 
 void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st) {

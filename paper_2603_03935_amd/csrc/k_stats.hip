@@ -392,8 +392,28 @@ __global__ __launch_bounds__(256) void k_weights(Batch b, Work wk) {
   }
   if (threadIdx.x == 0) {
     wk.Z[g] = Z;
-    wk.mstat[g] = (empty || !(stot > 0.f)) ? 1 : 0;
+    wk.mstat[g] = wk.fbad[b.mask_frame[g]] ? 3 : (empty || !(stot > 0.f)) ? 1 : 0;
   }
+}
+
+// One workgroup per (chunk of tokens, frame): a scale that is NaN, infinite
+// or negative flags its frame (its masks then get status 3 and zero rows).
+__global__ __launch_bounds__(256) void k_scale_check(Batch b, Work wk) {
+  const int f = blockIdx.y;
+  if (f >= b.dyn[0]) return;
+  const FrameDesc fd = b.frames[f];
+  bool bad = false;
+  for (int p = blockIdx.x * 256 + threadIdx.x; p < fd.G; p += gridDim.x * 256) {
+    const float s = fd.scale[p];
+    bad |= !(s >= 0.f && s <= 3.402823466e38f);  // false for NaN, +-inf and negatives
+  }
+  if (bad) atomicOr(&wk.fbad[f], 1);
+}
+
+void launch_scale_check(const Batch& b, const Work& w, int gmax, hipStream_t st) {
+  if (b.n_frames <= 0) return;
+  hipLaunchKernelGGL(k_scale_check, dim3(std::max(1, std::min(32, (gmax + 255) / 256)), b.n_frames), dim3(256), 0, st,
+                     b, w);
 }
 
 void launch_weights(const Batch& b, const Work& w, hipStream_t st) {
@@ -479,7 +499,7 @@ __global__ __launch_bounds__(256) void k_user_weights(Batch b, Work wk, const fl
   if (threadIdx.x == 0) {
     const float Z = tot.s + tot.c;
     wk.Z[g] = Z;
-    wk.mstat[g] = Z > 0.f ? 0 : 1;
+    wk.mstat[g] = wk.fbad[b.mask_frame[g]] ? 3 : Z > 0.f ? 0 : 1;
     wk.bbox[g] = make_int4(0, fd.h - 1, 0, fd.w - 1);
   }
 }

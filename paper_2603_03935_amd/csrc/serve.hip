@@ -115,7 +115,7 @@ static void stage_capacity(const Plan& actual, const Plan& cap, char* host) {
   if (!actual.tiles.empty()) std::memcpy(host + cap.L.tiles, actual.tiles.data(), 16 * actual.tiles.size());
   const int32_t dyn[4] = {actual.shape.n_frames, (int32_t)actual.shape.M, actual.shape.n_tiles, 0};
   std::memcpy(host + cap.L.dyn, dyn, sizeof dyn);
-  std::memset(host + cap.L.counts, 0, 4 * 32);
+  std::memset(host + cap.L.counts, 0, 4 * (32 + (size_t)cap.shape.n_frames));
 }
 
 int32_t disc_server::capture(Lane& ln) {

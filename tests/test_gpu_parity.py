@@ -159,6 +159,32 @@ def test_token_stats(gpu, dtype):
         assert np.abs(D.cpu().numpy() - oD).max() <= REL_S * oD.max()
 
 
+def test_fp8_bad_scales(gpu):
+    """A NaN, an infinite or a negative FP8 scale anywhere in a frame gives
+    every mask of that frame status 3 and a zero row (with and without D);
+    the other frames of the batch are untouched and match the oracle."""
+    h, w, patch, C, E = 160, 200, 16, 256, 256
+    gh, gw = -(-h // patch), -(-w // patch)
+    tok = di.tokens_normal(81, gh, gw, C, "f8", patch)
+    bits = di.masks_mixed(82, 6, h, w, 0.02, 0.3)
+    P = di.projection(83, C, E, "bf16")
+    frames = []
+    for k, bad in enumerate([np.nan, np.inf, -0.5, None]):
+        sc = tok.scale.copy()
+        if bad is not None:
+            sc[7 + 13 * k] = bad
+        frames.append(di.Frame(di.Tokens(tok.data, "f8", sc, patch), bits, h, w))
+    for distinct in (1, 0):
+        outs = run_frames(gpu, frames, P, "bf16", options=gpu.make_options(distinct=distinct))
+        for k in range(3):
+            assert (outs[k].status.cpu().numpy() == 3).all(), f"frame {k}: status {outs[k].status.cpu().numpy()}"
+            assert not outs[k].out.cpu().numpy().any(), f"frame {k}: rows must be zero"
+        ref = oracle_frame(frames[3], P, "bf16", distinct=distinct)
+        st = outs[3].status.cpu().numpy()
+        assert np.array_equal(st, ref["status"])
+        check_embeddings(outs[3].out.cpu().numpy(), st, ref, COS_LOWP, f"clean frame, distinct={distinct}")
+
+
 def test_fp8_every_code(gpu):
     """Every finite e4m3fn code is decoded exactly: token p holds code p in
     every channel (scale 1, with two scaled tokens), so each token's residual
