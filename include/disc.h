@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define DISC_ABI_VERSION 4
+#define DISC_ABI_VERSION 5
 
 typedef enum disc_status {
   DISC_OK = 0,

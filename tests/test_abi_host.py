@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.disc_abi_version() == 4
+    assert lib.disc_abi_version() == 5
     o = disc.Options()
     lib.disc_options_default(ctypes.byref(o))
     assert (o.spatial, o.distinct, o.gemm_dtype, o.edt_layout, o.pool_tile, o.pool_rows) == (0, 1, -1, -1, -1, -1)
