@@ -92,6 +92,11 @@ __device__ __forceinline__ float4 e4m3x4_to_f32(uint32_t w) {
 // launch (a bijection of [0, n)), so workgroups that read the same data (the
 // channel tiles of one mask tile, the strips of one mask) share an L2.
 constexpr int kXcds = 8;
+// The direct EDT's packet queues: one counter per XCD and launch in the
+// class-counter block (zeroed with it whenever a batch is staged): entries
+// kDirQueue .. + 7 for the launch of classes 0-4, the next 8 for class 5.
+constexpr int kDirQueue = 8;
+static_assert(kDirQueue >= 6 && kDirQueue + 2 * kXcds <= 32, "queues share the 32 zeroed counters");
 __device__ __forceinline__ int xcd_remap(int b, int n) {
   const int x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
   return x * q + min(x, r) + k;

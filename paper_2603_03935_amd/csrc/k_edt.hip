@@ -902,13 +902,17 @@ __device__ __forceinline__ void direct_table(int cls, const uint32_t* recs, cons
 
 template <int SPATIAL, bool WE, int PK>
 __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint32_t* recs, const int* words,
-                                              uint2* gt_all, float* part, int lane, int kb, int32_t* e_out) {
+                                              uint2* gt_all, float* part, int lane, int kb, int32_t* e_out,
+                                              int32_t* queue, int nb, int& next) {
   const int rows_c = class_rows(cls), ipp = direct_items(cls);
   const int nbs = rows_c / kBlkRows;  // blocks per slot
   const int nblk = ipp * nbs;         // blocks of the packet
 
   direct_table<PK>(cls, recs, words, gt_all, lane, kb);
   __syncthreads();
+  // the workgroup's next packet (no barrier waits for this atomic before the
+  // packet's end)
+  if (queue && threadIdx.x == 0) next = nb + atomicAdd(queue, 1);
 
   // ---- search: this workgroup's blocks (every S-th from s), one wavefront
   // per block in a stride.  Rows are searched kDirRows at a time, kDirSteps
@@ -1057,37 +1061,50 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
 // ROWS: table rows of one workgroup (512: classes 0-4, 1152: class 5)
 template <int SPATIAL, bool WE, int ROWS>
 __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(ROWS > 512 ? 4 : 8))) void k_edt_direct(
-    const int32_t* __restrict__ counts, const int32_t* __restrict__ items, int item_cap,
+    int32_t* __restrict__ counts, const int32_t* __restrict__ items, int item_cap,
     const MaskRec* __restrict__ mrec, int32_t* e_out, float* gpart) {
   __shared__ uint2 gt_all[(ROWS + 2 * kDirGuard) / 4 * 64];  // g table, 4 rows per word; zero guard rows at each end
   __shared__ float part_all[kEdtBlocks * kEdtPartRows * 8];
   __shared__ uint32_t recs[kEdtWaves * 16];
   __shared__ int words[kEdtWaves];
+  __shared__ int taken;
   const int lane = threadIdx.x & 63, kb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int i = threadIdx.x; i < (ROWS + 2 * kDirGuard) / 4 * 64; i += kEdtWaves * 64) gt_all[i] = make_uint2(0u, 0u);
   int cnt[kClasses];
   const int total = direct_count(counts, item_cap, ROWS > 512, cnt);
   const int S = direct_split(ROWS > 512, total, gridDim.x);
-  // Virtual packets (packet, share) in chunks of kXcds: chunk c goes to the
-  // workgroups on XCD c % kXcds, which take its packets in order.  The shares
-  // of a packet and neighbouring packets (the strips of one mask, in scan
-  // order) then read the same mask rows through one L2, while every XCD
-  // still starts with the tallest packets.
+  // Virtual packets (packet, share) in chunks of kXcds: chunk c belongs to
+  // XCD c % kXcds.  The XCD's nb workgroups take its first nb packets one
+  // each, then the rest in order from a queue of their own (a counter per
+  // XCD: a workgroup that finishes early takes the next packet instead of
+  // waiting for a fixed share of the list).  The shares of a packet and
+  // neighbouring packets (the strips of one mask, in scan order) then read
+  // the same mask rows through one L2, and every XCD starts with the tallest
+  // packets.  Which workgroup takes a packet never changes its result.
   const int N = total * S;
-  const int x = blockIdx.x % kXcds, nb = (gridDim.x - x + kXcds - 1) / kXcds;
-  const bool by_xcd = gridDim.x >= kXcds;  // else a plain stride
-  for (int i = 0;; ++i) {
-    const int t = blockIdx.x / kXcds + i * nb;
-    const int vp = by_xcd ? kXcds * (x + kXcds * (t / kXcds)) + t % kXcds : blockIdx.x + i * gridDim.x;
-    if (vp >= N) break;
+  const bool by_xcd = gridDim.x >= kXcds;  // else one queue in plain order
+  const int x = by_xcd ? blockIdx.x % kXcds : 0;
+  const int nb = by_xcd ? (gridDim.x - x + kXcds - 1) / kXcds : gridDim.x;
+  // no queue when the XCD's list ends within its first nb packets
+  const bool queued = (by_xcd ? kXcds * (x + kXcds * (nb / kXcds)) + nb % kXcds : nb) < N;
+  int32_t* queue = queued ? counts + kDirQueue + (ROWS > 512 ? kXcds : 0) + x : nullptr;
+  int next = N;  // past every list (by_xcd: t >= N gives vp >= N)
+  for (int t = by_xcd ? blockIdx.x / kXcds : blockIdx.x;;) {
+    const int vp = by_xcd ? kXcds * (x + kXcds * (t / kXcds)) + t % kXcds : t;
+    if (vp >= N) break;  // the XCD's list is in increasing order: nothing after it either
     const int p = vp / S, s = vp - p * S;
     const int cls = direct_load_packet(cnt, items, item_cap, mrec, p, recs, words);
     float* part = S == 1 ? part_all : gpart + (int64_t)p * kDirPartFloats;
-    direct_packet<SPATIAL, WE, (ROWS <= 512 ? 1 : SPATIAL == 0 ? 2 : 0)>(cls, s, S, recs, words, gt_all + kDirGuard / 4 * 64, part, lane, kb, e_out);
+    direct_packet<SPATIAL, WE, (ROWS <= 512 ? 1 : SPATIAL == 0 ? 2 : 0)>(cls, s, S, recs, words, gt_all + kDirGuard / 4 * 64, part, lane, kb, e_out,
+                                                                         queue, nb, next);
     if (S == 1) {
       direct_strip_sums(cls, recs, words, part_all, lane, kb);
       __syncthreads();
     }
+    // every thread has read the previous value of taken (barriers above)
+    if (threadIdx.x == 0) taken = next;
+    __syncthreads();
+    t = taken;
   }
 }
 
