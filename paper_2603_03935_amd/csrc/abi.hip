@@ -152,13 +152,13 @@ Layout make_layout(const Shape& s) {
   L.mask_frame = take(4 * (size_t)s.M);
   L.tiles = take(16 * (size_t)s.n_tiles);
   L.dyn = take(16);
-  L.counts = take(4 * (32 + (size_t)s.n_frames));  // class counters, then the per-frame scale flags
+  L.counts = take(4 * (kCounters + (size_t)s.n_frames));  // work-list and queue counters, then the per-frame scale flags
   L.staged_end = off;
   L.bbox = take(16 * (size_t)s.M);
   L.area = take(4 * (size_t)s.M);
   L.meta = take(4 * (size_t)s.M);
   L.mrec = take(sizeof(MaskRec) * (size_t)s.M);
-  L.items = take(4 * (size_t)kClasses * s.item_cap);
+  L.items = take(4 * (size_t)kClasses * kLists * s.item_cap);
   L.psum = take(4 * (size_t)s.n_frames * s.nchunk * s.C);
   L.mean = take(4 * (size_t)s.n_frames * s.C);
   L.r = take(4 * (size_t)s.sumG);
@@ -284,7 +284,7 @@ Work work_ptrs(char* base, const Layout& L) {
   w.mrec = reinterpret_cast<MaskRec*>(base + L.mrec);
   w.items = reinterpret_cast<int32_t*>(base + L.items);
   w.counts = reinterpret_cast<int32_t*>(base + L.counts);
-  w.fbad = w.counts + 32;
+  w.fbad = w.counts + kCounters;
   w.psum = reinterpret_cast<float*>(base + L.psum);
   w.mean = reinterpret_cast<float*>(base + L.mean);
   w.r = reinterpret_cast<float*>(base + L.r);
@@ -338,7 +338,17 @@ FrameDesc plan_frame(const FrameIn& f, int C, Shape& s, PlanAcc& a) {
   a.sumMGs += (int64_t)f.m * d.Gs;
   a.gmax = std::max(a.gmax, d.G);
   a.nchunk = std::max(a.nchunk, stat_nchunk(d.G));
-  a.item_cap += (int64_t)f.m * ((f.w + strip_width(f.patch) - 1) / strip_width(f.patch) + 1);
+  {
+    // the frame's masks are g = mask_base .. mask_base + m - 1; mask g
+    // appends at most `strips` items to sub-list g % kLists of its class
+    const int64_t strips = (f.w + strip_width(f.patch) - 1) / strip_width(f.patch) + 1;
+    const int64_t g0 = d.mask_base, g1 = g0 + f.m;
+    for (int j = 0; j < kLists; ++j) {
+      const int64_t first = g0 + ((j - g0 % kLists) + kLists) % kLists;  // first g >= g0 with g % kLists == j
+      const int64_t n = first < g1 ? (g1 - 1 - first) / kLists + 1 : 0;
+      a.item_sub[j] += n * strips;
+    }
+  }
   a.n_tiles += (f.m + 63) / 64 * (C / 64);
   return d;
 }
@@ -351,7 +361,9 @@ void finish_plan(Plan& p, const PlanAcc& a) {
   s.sumMGs = a.sumMGs;
   s.gmax = a.gmax;
   s.nchunk = a.nchunk;
-  s.item_cap = (int)std::min<int64_t>(a.item_cap, INT32_MAX / 2);
+  int64_t cap = 1;
+  for (int j = 0; j < kLists; ++j) cap = std::max(cap, a.item_sub[j]);
+  s.item_cap = (int)std::min<int64_t>(cap, INT32_MAX / 2 / kLists);
   s.n_tiles = a.n_tiles;
   choose_splits(s);
   p.L = make_layout(s);
@@ -403,7 +415,7 @@ void stage_host(const Plan& p, char* host, char* dev) {
   if (!p.tiles.empty()) std::memcpy(host + p.L.tiles, p.tiles.data(), 16 * p.tiles.size());
   const int32_t dyn[4] = {p.shape.n_frames, (int32_t)p.shape.M, p.shape.n_tiles, 0};
   std::memcpy(host + p.L.dyn, dyn, sizeof dyn);
-  std::memset(host + p.L.counts, 0, 4 * (32 + (size_t)p.shape.n_frames));
+  std::memset(host + p.L.counts, 0, 4 * (kCounters + (size_t)p.shape.n_frames));
 }
 
 Batch make_batch(const Plan& p, char* dev, int tok_dtype, int spatial, int distinct) {

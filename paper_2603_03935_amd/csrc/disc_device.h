@@ -92,11 +92,36 @@ __device__ __forceinline__ float4 e4m3x4_to_f32(uint32_t w) {
 // launch (a bijection of [0, n)), so workgroups that read the same data (the
 // channel tiles of one mask tile, the strips of one mask) share an L2.
 constexpr int kXcds = 8;
-// The direct EDT's packet queues: one counter per XCD and launch in the
-// class-counter block (zeroed with it whenever a batch is staged): entries
-// kDirQueue .. + 7 for the launch of classes 0-4, the next 8 for class 5.
-constexpr int kDirQueue = 8;
-static_assert(kDirQueue >= 6 && kDirQueue + 2 * kXcds <= 32, "queues share the 32 zeroed counters");
+// Work lists of the distance transform: each class has kLists sub-lists,
+// mask g appending its strips to sub-list g % kLists, so that the scan's
+// atomics spread over kClasses x kLists counters instead of kClasses (one
+// hot counter per class serialised thousands of device-scope atomics).  A
+// class's items are its sub-lists one after another.
+constexpr int kLists = 8;
+// Counters zeroed whenever a batch is staged: the sub-list sizes
+// [kClasses][kLists], then the direct EDT's packet queues (one counter per
+// XCD and launch: kDirQueue .. + 7 for classes 0-4, the next 8 for class 5),
+// then the per-frame FP8 scale flags.
+constexpr int kDirQueue = kClasses * kLists;
+constexpr int kCounters = 64;
+static_assert(kDirQueue + 2 * kXcds <= kCounters, "counters");
+// items of class c (each sub-list capped at item_cap)
+__device__ __forceinline__ int class_count(const int32_t* counts, int item_cap, int c) {
+  int n = 0;
+#pragma unroll
+  for (int j = 0; j < kLists; ++j) n += min(counts[c * kLists + j], item_cap);
+  return n;
+}
+// item k of class c (k below class_count): the item word of its sub-list
+__device__ __forceinline__ int class_item(const int32_t* counts, const int32_t* items, int item_cap, int c, int k) {
+  int j = 0;
+  for (; j < kLists - 1; ++j) {
+    const int n = min(counts[c * kLists + j], item_cap);
+    if (k < n) break;
+    k -= n;
+  }
+  return items[((int64_t)c * kLists + j) * item_cap + k];
+}
 __device__ __forceinline__ int xcd_remap(int b, int n) {
   const int x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
   return x * q + min(x, r) + k;
@@ -133,7 +158,7 @@ struct Batch {
   int32_t gemm_bf16;          // 1: BF16 operands, 0: FP32 operands
   int32_t spatial, distinct;
   int32_t nchunk;             // token-statistics chunks per frame (capacity)
-  int32_t item_cap;           // capacity of each class's work list (and the list stride)
+  int32_t item_cap;           // capacity of each work sub-list (and the sub-list stride)
   int32_t n_tiles;            // pooling tiles (capacity)
   int32_t kgroups;            // pooling K groups of the largest frame
   int32_t pool_split, proj_split;  // workgroups sharing one GEMM tile's K range
@@ -147,8 +172,8 @@ struct Work {
   int32_t* area;       // [M]
   int32_t* meta;       // [M] (class << 16) | strips, -1 empty
   MaskRec* mrec;       // [M]
-  int32_t* items;      // [kClasses][item_cap] (mask << 8) | strip, one list per class
-  int32_t* counts;     // [kClasses] items per class (zeroed when a batch is staged)
+  int32_t* items;      // [kClasses][kLists][item_cap] (mask << 8) | strip: the sub-lists of each class
+  int32_t* counts;     // [kCounters] sub-list sizes and EDT queues (zeroed when a batch is staged)
   int32_t* fbad;       // [frames] 1 when a frame's FP8 scales include a non-finite or negative value (zeroed when staged)
   float* psum;         // [F][nchunk][C]
   float* mean;         // [F][C]

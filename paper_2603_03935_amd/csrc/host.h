@@ -55,7 +55,8 @@ struct Plan {
 
 // Capacity totals accumulated while frames are added to a plan.
 struct PlanAcc {
-  int64_t M = 0, sumG = 0, sumMGs = 0, item_cap = 1;
+  int64_t M = 0, sumG = 0, sumMGs = 0;
+  int64_t item_sub[kLists] = {};  // work-list capacity of each sub-list (masks g with g % kLists == j)
   int gmax = 0, nchunk = 1, n_tiles = 0;
 };
 

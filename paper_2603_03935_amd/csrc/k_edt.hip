@@ -365,18 +365,18 @@ __device__ __forceinline__ void strip_patch_sums(const float* part, float* srow,
 // packets of the tallest class come first so that the longest work starts
 // first.  Returns the class of packet p (or -1 past the end) and the item word
 // of wavefront kb's slot in it (or -1 when that slot is empty).
-__device__ __forceinline__ int packet_slot(int mode, const int32_t* counts, const int32_t* items, int item_cap, int p,
-                                           int kb, int& word) {
+__device__ __forceinline__ int packet_slot(int mode, const int* ccnt, const int32_t* counts, const int32_t* items,
+                                           int item_cap, int p, int kb, int& word) {
   word = -1;
 #pragma unroll
   for (int c = kClasses - 1; c >= 0; --c) {
     const int ipp = class_items(mode, c);
-    const int cnt = counts[c];
+    const int cnt = ccnt[c];
     const int np = (cnt + ipp - 1) / ipp;
     if (p < np) {
       const int slot = kb / class_waves(mode, c);
       const int k = p * ipp + slot;
-      if (slot < ipp && k < cnt) word = items[(int64_t)c * item_cap + k];
+      if (slot < ipp && k < cnt) word = class_item(counts, items, item_cap, c, k);
       return c;
     }
     p -= np;
@@ -599,7 +599,7 @@ __device__ __forceinline__ void edt_packet(int K, uint32_t pf, int word, uint4* 
 __device__ __forceinline__ int pick_mode(const int32_t* counts, int item_cap, int mode_arg) {
   if (mode_arg >= 0) return mode_arg;
   int64_t waves0 = 0;
-  for (int c = 0; c < kClasses; ++c) waves0 += (int64_t)min(counts[c], item_cap) * class_waves(0, c);
+  for (int c = 0; c < kClasses; ++c) waves0 += (int64_t)class_count(counts, item_cap, c) * class_waves(0, c);
   return waves0 > 4ll * gridDim.x * kEdtWaves ? 1 : 0;
 }
 
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
   const int mode = pick_mode(counts, item_cap, mode_arg);
   int total = 0;
   int cnt[kClasses];
-  for (int c = 0; c < kClasses; ++c) cnt[c] = min(counts[c], item_cap);
+  for (int c = 0; c < kClasses; ++c) cnt[c] = class_count(counts, item_cap, c);
   for (int c = 0; c < kClasses; ++c) total += (cnt[c] + class_items(mode, c) - 1) / class_items(mode, c);
 
   // Packets are taken in a fixed stride (no shared queue).  Each wavefront
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
   int p = blockIdx.x;
   if (p >= total) return;
   int word = -1;
-  int cls = packet_slot(mode, cnt, items, item_cap, p, kb, word);
+  int cls = packet_slot(mode, cnt, counts, items, item_cap, p, kb, word);
   uint32_t pf = 0u;
   if (word >= 0 && lane < 16) pf = reinterpret_cast<const uint32_t*>(mrec + (word >> kItemStripBits))[lane];
 
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
     uint32_t npf = pf;
     auto prefetch = [&]() {
       if (p + (int)gridDim.x < total) {
-        ncls = packet_slot(mode, cnt, items, item_cap, p + gridDim.x, kb, nword);
+        ncls = packet_slot(mode, cnt, counts, items, item_cap, p + gridDim.x, kb, nword);
         if (nword >= 0 && lane < 16) npf = reinterpret_cast<const uint32_t*>(mrec + (nword >> kItemStripBits))[lane];
       }
     };
@@ -690,7 +690,7 @@ __device__ __forceinline__ int direct_count(const int32_t* counts, int item_cap,
   int total = 0;
 #pragma unroll
   for (int c = 0; c < kClasses; ++c) {
-    cnt[c] = tall == (c == 5) ? min(counts[c], item_cap) : 0;
+    cnt[c] = tall == (c == 5) ? class_count(counts, item_cap, c) : 0;
     total += (cnt[c] + direct_items(c) - 1) / direct_items(c);
   }
   return total;
@@ -715,15 +715,15 @@ __device__ __forceinline__ int direct_packet_class(const int* cnt, int p, int& f
   return -1;
 }
 // item words and mask records of packet p's slots into LDS (recs: 16 dwords per slot)
-__device__ __forceinline__ int direct_load_packet(const int* cnt, const int32_t* items, int item_cap,
-                                                  const MaskRec* mrec, int p, uint32_t* recs, int* words) {
+__device__ __forceinline__ int direct_load_packet(const int* cnt, const int32_t* counts, const int32_t* items,
+                                                  int item_cap, const MaskRec* mrec, int p, uint32_t* recs, int* words) {
   int first = 0, ccount = 0;
   const int cls = direct_packet_class(cnt, p, first, ccount);
   const int ipp = direct_items(cls);
   if ((int)threadIdx.x < ipp * 16) {
     const int sl = threadIdx.x >> 4, q = threadIdx.x & 15;
     const int k = first + sl;
-    const int word = k < ccount ? items[(int64_t)cls * item_cap + k] : -1;
+    const int word = k < ccount ? class_item(counts, items, item_cap, cls, k) : -1;
     if (q == 0) words[sl] = word;
     recs[sl * 16 + q] = word >= 0 ? reinterpret_cast<const uint32_t*>(mrec + (word >> kItemStripBits))[q] : 0u;
   }
@@ -1093,7 +1093,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const int vp = by_xcd ? kXcds * (x + kXcds * (t / kXcds)) + t % kXcds : t;
     if (vp >= N) break;  // the XCD's list is in increasing order: nothing after it either
     const int p = vp / S, s = vp - p * S;
-    const int cls = direct_load_packet(cnt, items, item_cap, mrec, p, recs, words);
+    const int cls = direct_load_packet(cnt, counts, items, item_cap, mrec, p, recs, words);
     float* part = S == 1 ? part_all : gpart + (int64_t)p * kDirPartFloats;
     direct_packet<SPATIAL, WE, (ROWS <= 512 ? 1 : SPATIAL == 0 ? 2 : 0)>(cls, s, S, recs, words, gt_all + kDirGuard / 4 * 64, part, lane, kb, e_out,
                                                                          queue, nb, next);
@@ -1128,7 +1128,7 @@ __global__ __launch_bounds__(kEdtWaves * 64) void k_edt_dsums(Batch b, const int
   const int total = direct_count(counts, item_cap, false, cnt);
   if (direct_split(false, total, direct_grid) == 1) return;
   for (int p = blockIdx.x; p < total; p += gridDim.x) {
-    const int cls = direct_load_packet(cnt, items, item_cap, mrec, p, recs, words);
+    const int cls = direct_load_packet(cnt, counts, items, item_cap, mrec, p, recs, words);
     direct_strip_sums(cls, recs, words, gpart + (int64_t)p * kDirPartFloats, lane, kb);
     __syncthreads();
   }

@@ -155,10 +155,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Batch b, Work wk) {
       r.g = g;
       wk.mrec[g] = r;
       if (cls < kClasses) {
-        // the order of items inside a class list does not affect any result
+        // the order of items inside a class's lists does not affect any result
         app[0] = cls;
         app[1] = strips;
-        app[2] = atomicAdd(wk.counts + cls, strips);
+        app[2] = atomicAdd(wk.counts + cls * kLists + g % kLists, strips);
       }
     } else {
       wk.bbox[g] = make_int4(1, 0, 1, 0);
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Batch b, Work wk) {
   __syncthreads();
   const int strips = app[1];
   if (strips > 0) {
-    int32_t* list = wk.items + (int64_t)app[0] * b.item_cap + app[2];
+    int32_t* list = wk.items + ((int64_t)app[0] * kLists + g % kLists) * b.item_cap + app[2];
     for (int j = threadIdx.x; j < strips; j += kScanThreads)
       if (app[2] + j < b.item_cap) list[j] = (g << kItemStripBits) | j;
   }

@@ -61,7 +61,7 @@ __global__ void k_stage_frame(FrameDesc d, int32_t M, int32_t C, int32_t n_tiles
     dyn[2] = n_tiles;
     dyn[3] = 0;
   }
-  if (i < 33) counts[i] = 0;  // class counters and the frame's scale flag
+  if (i < kCounters + 1) counts[i] = 0;  // work-list and queue counters and the frame's scale flag
   const int nct = C / 64;
   for (int k = i; k < M; k += stride) mask_frame[k] = 0;
   for (int t = i; t < n_tiles; t += stride) {

@@ -62,7 +62,10 @@ Shape capacity_shape(const disc_server_config& c, int E, int gemm_bf16) {
   s.gmax = G;
   s.nchunk = 64;  // stat_nchunk(G) <= 64 for every frame size
   // a strip is at least 33 columns wide for every patch size in [8, 64]
-  s.item_cap = (int)std::min<int64_t>((int64_t)c.max_masks * ((c.max_w + 31) / 32 + 1) + 1, INT32_MAX / 2);
+  // per work sub-list: at most ceil(max_masks / kLists) masks, each with at
+  // most max_w / 32 + 1 strips (a strip is at least 33 columns wide)
+  s.item_cap = (int)std::min<int64_t>(((int64_t)c.max_masks + kLists - 1) / kLists * ((c.max_w + 31) / 32 + 1) + 1,
+                                      INT32_MAX / 2 / kLists);
   s.n_tiles = ((c.max_masks + 63) / 64 + c.max_frames) * (c.c / 64);
   s.gemm_bf16 = gemm_bf16;
   s.want_dbar = true;  // any request may ask for the mean distinctiveness
@@ -115,7 +118,7 @@ static void stage_capacity(const Plan& actual, const Plan& cap, char* host) {
   if (!actual.tiles.empty()) std::memcpy(host + cap.L.tiles, actual.tiles.data(), 16 * actual.tiles.size());
   const int32_t dyn[4] = {actual.shape.n_frames, (int32_t)actual.shape.M, actual.shape.n_tiles, 0};
   std::memcpy(host + cap.L.dyn, dyn, sizeof dyn);
-  std::memset(host + cap.L.counts, 0, 4 * (32 + (size_t)cap.shape.n_frames));
+  std::memset(host + cap.L.counts, 0, 4 * (kCounters + (size_t)cap.shape.n_frames));
 }
 
 int32_t disc_server::capture(Lane& ln) {
