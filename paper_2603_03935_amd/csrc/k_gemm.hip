@@ -93,7 +93,7 @@ __device__ __forceinline__ uint16_t tok_bf16(const void* base, int64_t off) {
 // first patch row of their box, so that a tile's range is narrow); which masks
 // share a tile never changes a mask's result.
 __device__ __forceinline__ void tile_krange(const Work& wk, const FrameDesc& fd, int m0, int mrows, int tid,
-                                            int* kmin_sh, int* kmax_sh, int& kbeg, int& kend) {
+                                            int* kmin_sh, int* kmax_sh, int& kbeg, int& kend, int kalign = PBK) {
   if (tid == 0) {
     *kmin_sh = INT32_MAX;
     *kmax_sh = 0;
@@ -107,7 +107,7 @@ __device__ __forceinline__ void tile_krange(const Work& wk, const FrameDesc& fd,
     }
   }
   __syncthreads();
-  kbeg = (*kmin_sh / PBK) * PBK;
+  kbeg = (*kmin_sh / kalign) * kalign;
   kend = min(*kmax_sh, fd.G);
 }
 
@@ -157,6 +157,9 @@ __device__ __forceinline__ void pool_store(const Work& wk, const FrameDesc& fd, 
 template <int BF16, int TOK, int NT, int MW>
 __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tiles) {
   constexpr int BN = PBN * NT;  // channels per workgroup
+  // K step: 64 patches with BF16 operands (two A chunks and two token
+  // passes per thread), 32 with FP32 operands
+  constexpr int KS = BF16 ? 2 * PBK : PBK, KP = KS + 8, NKS = KS / PBK;
   const int S = MW == 1 ? b.pool_split : 1;
   const int nlive = b.dyn[2] / NT * S;  // live workgroups (NT divides the channel tiles of a mask tile)
   if ((int)blockIdx.x >= nlive) return;
@@ -176,13 +179,13 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
 
   __shared__ int kmin_sh, kmax_sh;
-  __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? PBM * MW * PAS : 1];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? BN * PAS : 1];
+  __shared__ __attribute__((aligned(16))) uint16_t As16[BF16 ? PBM * MW * KP : 1];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs16[BF16 ? BN * KP : 1];
   __shared__ float As32[BF16 ? 1 : PBM * MW * (PBK + 1)];
   __shared__ __attribute__((aligned(16))) float Bs32[BF16 ? 1 : PBK * BN];
 
   int kbeg, kend;
-  tile_krange(wk, fd, m0, mrows, tid, &kmin_sh, &kmax_sh, kbeg, kend);
+  tile_krange(wk, fd, m0, mrows, tid, &kmin_sh, &kmax_sh, kbeg, kend, KS);
   const int gbeg = kbeg / kPoolKG, gend = kbeg < kend ? (kend + kPoolKG - 1) / kPoolKG : gbeg;
   const int per = (gend - gbeg + S - 1) / S;
   const int ga = gbeg + sidx * per, gb = min(gend, ga + per);
@@ -229,8 +232,8 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   // flight while step k computes (small batches are latency-bound).  BF16:
   // one set, one step ahead (more resident workgroups hide the latency).
   constexpr int DIST = BF16 ? 1 : 2;
-  uint4 ra16[2][MW];
-  uint4 rbr[2][NT][2];  // raw token words of patches 2 pp, 2 pp + 1: FP32 float4 bits, BF16 .xy, FP8 .x
+  uint4 ra16[2][MW][NKS];
+  uint4 rbr[2][NT][NKS][2];  // raw token words of patches 2 pp, 2 pp + 1 (+ 32 per pass): BF16 .xy, FP8 .x
   float ra32[2][MW][8], rb32[2][NT][8];
 
   auto fetch = [&](int k0, int q) {
@@ -239,29 +242,35 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
     // the mask's patch rectangle
     if (BF16) {
 #pragma unroll
-      for (int h = 0; h < MW; ++h) {
-        const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0[h] + kk;
-        ra16[q][h] = arow_ok[h] && kk < G ? *reinterpret_cast<const uint4*>(src) : make_uint4(0u, 0u, 0u, 0u);
-      }
-      const int kb = k0 + 2 * bpp;
+      for (int h = 0; h < MW; ++h)
 #pragma unroll
-      for (int j = 0; j < NT; ++j) {
+        for (int a = 0; a < NKS; ++a) {
+          const int ka = kk + PBK * a;
+          const uint16_t* src = reinterpret_cast<const uint16_t*>(wk.W) + wrow0[h] + ka;
+          ra16[q][h][a] = arow_ok[h] && ka < G ? *reinterpret_cast<const uint4*>(src) : make_uint4(0u, 0u, 0u, 0u);
+        }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          uint4 v = make_uint4(0u, 0u, 0u, 0u);
-          if (kb + h < G) {
-            const int64_t off = (int64_t)(kb + h) * C + n0 + 64 * j + bc4;
-            if (TOK == 0) {
-              v = *reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(fd.tokens) + off);
-            } else if (TOK == 1) {
-              const uint2 t2 = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(fd.tokens) + off);
-              v.x = t2.x;
-              v.y = t2.y;
-            } else {
-              v.x = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(fd.tokens) + off);
+      for (int a = 0; a < NKS; ++a) {
+        const int kb = k0 + PBK * a + 2 * bpp;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (kb + h < G) {
+              const int64_t off = (int64_t)(kb + h) * C + n0 + 64 * j + bc4;
+              if (TOK == 0) {
+                v = *reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(fd.tokens) + off);
+              } else if (TOK == 1) {
+                const uint2 t2 = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(fd.tokens) + off);
+                v.x = t2.x;
+                v.y = t2.y;
+              } else {
+                v.x = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(fd.tokens) + off);
+              }
             }
+            rbr[q][j][a][h] = v;
           }
-          rbr[q][j][h] = v;
         }
       }
     } else {
@@ -285,12 +294,17 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
   auto stage = [&](int q) {
     if (BF16) {
 #pragma unroll
-      for (int h = 0; h < MW; ++h) *reinterpret_cast<uint4*>(&As16[(ar + 64 * h) * PAS + ak]) = ra16[q][h];
+      for (int h = 0; h < MW; ++h)
+#pragma unroll
+        for (int a = 0; a < NKS; ++a) *reinterpret_cast<uint4*>(&As16[(ar + 64 * h) * KP + ak + PBK * a]) = ra16[q][h][a];
+#pragma unroll
+      for (int a = 0; a < NKS; ++a)
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
         // channel bc4 + e: patches 2 pp and 2 pp + 1 as one word (BF16 bits)
         uint32_t wd[4];
-        const uint4 v0 = rbr[q][j][0], v1 = rbr[q][j][1];
+        const int pp = bpp + (PBK / 2) * a;  // patch pair within the step
+        const uint4 v0 = rbr[q][j][a][0], v1 = rbr[q][j][a][1];
         if (TOK == 0) {
           const uint32_t a[4] = {v0.x, v0.y, v0.z, v0.w}, c[4] = {v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
@@ -311,7 +325,7 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int row = 64 * j + bc4 + e;
-          *reinterpret_cast<uint32_t*>(&Bs16[row * PAS + bsw(row, bpp >> 2) * 8 + ((2 * bpp) & 7)]) = wd[e];
+          *reinterpret_cast<uint32_t*>(&Bs16[row * KP + bsw(row, pp >> 2) * 8 + ((2 * pp) & 7)]) = wd[e];
         }
       }
     } else {
@@ -361,14 +375,14 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
     if (kf < kstop) fetch(kf, q);
     if (BF16) {
 #pragma unroll
-      for (int kk = 0; kk < PBK; kk += 16) {
+      for (int kk = 0; kk < KS; kk += 16) {
         u16x8 av[MW];
 #pragma unroll
-        for (int h = 0; h < MW; ++h) av[h] = *reinterpret_cast<const u16x8*>(&As16[(64 * h + 32 * wm + lr) * PAS + kk + 8 * lk]);
+        for (int h = 0; h < MW; ++h) av[h] = *reinterpret_cast<const u16x8*>(&As16[(64 * h + 32 * wm + lr) * KP + kk + 8 * lk]);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const int row = 64 * j + 32 * wn + lr;
-          const u16x8 bv = *reinterpret_cast<const u16x8*>(&Bs16[row * PAS + bsw(row, (kk >> 3) + lk) * 8]);
+          const u16x8 bv = *reinterpret_cast<const u16x8*>(&Bs16[row * KP + bsw(row, (kk >> 3) + lk) * 8]);
 #pragma unroll
           for (int h = 0; h < MW; ++h)
             acc[h][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[h]),
@@ -400,7 +414,7 @@ __global__ __launch_bounds__(256) void k_pool(Batch b, Work wk, const int4* tile
       step(k0 + PBK, 1, k0 + 3 * PBK);
     }
   } else {
-    for (int k0 = kstart; k0 < kstop; k0 += PBK) step(k0, 0, k0 + PBK);
+    for (int k0 = kstart; k0 < kstop; k0 += KS) step(k0, 0, k0 + KS);
   }
   advance(gb);
   if (S == 1) {
