@@ -900,6 +900,115 @@ __device__ __forceinline__ void direct_table(int cls, const uint32_t* recs, cons
   }
 }
 
+// The squared distances (AREA: 1 inside, 0 outside) of the kDirRows rows of
+// one group, whose first table word is `base` (one lane per column; RS: the
+// table's words per row quad).  Rows are searched together, kDirSteps
+// distances per step: the candidates at distances d .. d + kDirSteps - 1 come
+// from consecutive table rows on each side, and a step runs while any row of
+// the group can still improve (rows that are done are updated with
+// candidates that cannot win).
+template <int SPATIAL, int PK, int RS>
+__device__ __forceinline__ void direct_group(const uint2* base, int* best) {
+  int bmax = 0;
+  // g^2 of a table entry (PK 1: the entry itself, PK 2: decoded from T)
+  auto gsq_of = [](int t) { return PK == 1 ? t : PK == 2 ? (t < 65025 ? t : (t - 64770) * (t - 64770)) : t * t; };
+  // initial values: the rows' own entries, g^2 (exact = false with PK 2:
+  // T itself, for the packed search)
+  auto init_exact = [&](bool exact) {
+    bmax = 0;
+#pragma unroll
+    for (int q = 0; q < kDirRows / 4; ++q) {
+      const uint2 w = base[q * RS];
+      const int g4[4] = {(int)(w.x & 0xFFFFu), (int)(w.x >> 16), (int)(w.y & 0xFFFFu), (int)(w.y >> 16)};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        best[4 * q + k] = SPATIAL != 0 ? (g4[k] > 0 ? 1 : 0) : (PK == 2 && !exact) ? g4[k] : gsq_of(g4[k]);
+        bmax = max(bmax, best[4 * q + k]);
+      }
+    }
+  };
+  // exact 32-bit search.  d = 1 (mod 4): the windows start on words, up
+  // at u0 - d - 3, down at u0 + d - 1 (one row early)
+  auto search32 = [&]() {
+    for (int d = 1; d * d < bmax; d += kDirSteps) {
+      constexpr int NQ = (kDirRows + kDirSteps) / 4;  // words per window
+      const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * RS;
+      const uint2* pd = base + ((d - 1) >> 2) * RS;
+      int su[4 * NQ], sd[4 * NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const uint2 x = pu[q * RS], y = pd[q * RS];
+        const int xa = (int)(x.x & 0xFFFFu), xb = (int)(x.x >> 16), xc = (int)(x.y & 0xFFFFu), xd = (int)(x.y >> 16);
+        const int ya = (int)(y.x & 0xFFFFu), yb = (int)(y.x >> 16), yc = (int)(y.y & 0xFFFFu), yd = (int)(y.y >> 16);
+        su[4 * q] = gsq_of(xa);
+        su[4 * q + 1] = gsq_of(xb);
+        su[4 * q + 2] = gsq_of(xc);
+        su[4 * q + 3] = gsq_of(xd);
+        sd[4 * q] = gsq_of(ya);
+        sd[4 * q + 1] = gsq_of(yb);
+        sd[4 * q + 2] = gsq_of(yc);
+        sd[4 * q + 3] = gsq_of(yd);
+      }
+      bmax = 0;
+#pragma unroll
+      for (int k = 0; k < kDirRows; ++k) {
+#pragma unroll
+        for (int i = 0; i < kDirSteps; ++i)  // row u0 + k at distance d + i: up index k - i + 3, down k + i + 1
+          best[k] = min(best[k], (d + i) * (d + i) + min(su[k - i + kDirSteps - 1], sd[k + i + 1]));
+        bmax = max(bmax, best[k]);
+      }
+    }
+  };
+  init_exact(false);
+  if (SPATIAL == 0 && PK != 0) {
+    // packed: rows (0,1) and (2,3) of the group in one register each;
+    // the window rows as aligned pairs (2j, 2j+1) and odd pairs
+    // (2j+1, 2j+2); the table holds g^2.
+    const int b0v = best[0], b1v = best[1], b2v = best[2], b3v = best[3];
+    us2 B[2] = {as_us2((uint32_t)b0v | ((uint32_t)b1v << 16)), as_us2((uint32_t)b2v | ((uint32_t)b3v << 16))};
+    int pmax = max(max(b0v, b1v), max(b2v, b3v));
+    for (int d = 1; d * d < pmax; d += kDirSteps) {
+      const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * RS;
+      const uint2* pd = base + ((d - 1) >> 2) * RS;
+      const uint2 u0w = pu[0], u1w = pu[RS], d0w = pd[0], d1w = pd[RS];
+      const uint32_t U[4] = {u0w.x, u0w.y, u1w.x, u1w.y};
+      const uint32_t Dn[4] = {d0w.x, d0w.y, d1w.x, d1w.y};
+      uint32_t Uo[3], Do[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        Uo[j] = __builtin_amdgcn_alignbyte(U[j + 1], U[j], 2);
+        Do[j] = __builtin_amdgcn_alignbyte(Dn[j + 1], Dn[j], 2);
+      }
+#pragma unroll
+      for (int i = 0; i < kDirSteps; ++i) {
+        // (d + i)^2 is the same for every lane: scalar arithmetic, one
+        // scalar operand of the packed adds
+        const uint32_t dd = (uint32_t)min((d + i) * (d + i), 65535);
+        const us2 D = as_us2(dd | (dd << 16));
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {  // rows 2q, 2q + 1 at distance d + i
+          const uint32_t up = (i & 1) ? U[(3 + 2 * q - i) >> 1] : Uo[(2 + 2 * q - i) >> 1];
+          const uint32_t dn = (i & 1) ? Dn[(1 + 2 * q + i) >> 1] : Do[(2 * q + i) >> 1];
+          B[q] = __builtin_elementwise_min(
+              B[q], __builtin_elementwise_add_sat(__builtin_elementwise_min(as_us2(up), as_us2(dn)), D));
+        }
+      }
+      pmax = max4(B[0], B[1]);
+    }
+    best[0] = B[0].x;
+    best[1] = B[0].y;
+    best[2] = B[1].x;
+    best[3] = B[1].y;
+    if (PK == 2 && max(max(best[0], best[1]), max(best[2], best[3])) >= 65025) {
+      // some row of the group is at least 255 from the outside: exact search
+      init_exact(true);
+      search32();
+    }
+  } else if (SPATIAL == 0) {
+    search32();
+  }
+}
+
 template <int SPATIAL, bool WE, int PK>
 __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint32_t* recs, const int* words,
                                               uint2* gt_all, float* part, int lane, int kb, int32_t* e_out,
@@ -915,12 +1024,8 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
   if (queue && threadIdx.x == 0) next = nb + atomicAdd(queue, 1);
 
   // ---- search: this workgroup's blocks (every S-th from s), one wavefront
-  // per block in a stride.  Rows are searched kDirRows at a time, kDirSteps
-  // distances per step: the group's candidates at distances d .. d +
-  // kDirSteps - 1 come from consecutive table rows on each side, and a step
-  // runs while any row of the group can still improve (rows that are done
-  // are updated with candidates that cannot win).  Each group's rows are then
-  // added in row order. ----
+  // per block in a stride, kDirRows rows at a time (direct_group); each
+  // group's rows are then added in row order. ----
   for (int b = s + S * kb; b < nblk; b += S * kEdtWaves) {
     const int slot = b / nbs, lb = b - slot * nbs, b0 = lb * kBlkRows;
     const DirItem it = direct_item(recs, words, slot);
@@ -939,104 +1044,7 @@ __device__ __forceinline__ void direct_packet(int cls, int s, int S, const uint3
       if (b0 + gi >= ub) break;
       const uint2* base = tb + (gi >> 2) * 64;  // row u0 = b0 + gi
       int best[kDirRows];
-      int bmax = 0;
-      // g^2 of a table entry (PK 1: the entry itself, PK 2: decoded from T)
-      auto gsq_of = [](int t) { return PK == 1 ? t : PK == 2 ? (t < 65025 ? t : (t - 64770) * (t - 64770)) : t * t; };
-      // initial values: the rows' own entries, g^2 (exact = false with PK 2:
-      // T itself, for the packed search)
-      auto init_exact = [&](bool exact) {
-        bmax = 0;
-#pragma unroll
-        for (int q = 0; q < kDirRows / 4; ++q) {
-          const uint2 w = base[q * 64];
-          const int g4[4] = {(int)(w.x & 0xFFFFu), (int)(w.x >> 16), (int)(w.y & 0xFFFFu), (int)(w.y >> 16)};
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            best[4 * q + k] = SPATIAL != 0 ? (g4[k] > 0 ? 1 : 0) : (PK == 2 && !exact) ? g4[k] : gsq_of(g4[k]);
-            bmax = max(bmax, best[4 * q + k]);
-          }
-        }
-      };
-      // exact 32-bit search.  d = 1 (mod 4): the windows start on words, up
-      // at u0 - d - 3, down at u0 + d - 1 (one row early)
-      auto search32 = [&]() {
-        for (int d = 1; d * d < bmax; d += kDirSteps) {
-          constexpr int NQ = (kDirRows + kDirSteps) / 4;  // words per window
-          const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * 64;
-          const uint2* pd = base + ((d - 1) >> 2) * 64;
-          int su[4 * NQ], sd[4 * NQ];
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            const uint2 x = pu[q * 64], y = pd[q * 64];
-            const int xa = (int)(x.x & 0xFFFFu), xb = (int)(x.x >> 16), xc = (int)(x.y & 0xFFFFu), xd = (int)(x.y >> 16);
-            const int ya = (int)(y.x & 0xFFFFu), yb = (int)(y.x >> 16), yc = (int)(y.y & 0xFFFFu), yd = (int)(y.y >> 16);
-            su[4 * q] = gsq_of(xa);
-            su[4 * q + 1] = gsq_of(xb);
-            su[4 * q + 2] = gsq_of(xc);
-            su[4 * q + 3] = gsq_of(xd);
-            sd[4 * q] = gsq_of(ya);
-            sd[4 * q + 1] = gsq_of(yb);
-            sd[4 * q + 2] = gsq_of(yc);
-            sd[4 * q + 3] = gsq_of(yd);
-          }
-          bmax = 0;
-#pragma unroll
-          for (int k = 0; k < kDirRows; ++k) {
-#pragma unroll
-            for (int i = 0; i < kDirSteps; ++i)  // row u0 + k at distance d + i: up index k - i + 3, down k + i + 1
-              best[k] = min(best[k], (d + i) * (d + i) + min(su[k - i + kDirSteps - 1], sd[k + i + 1]));
-            bmax = max(bmax, best[k]);
-          }
-        }
-      };
-      init_exact(false);
-      if (SPATIAL == 0 && PK != 0) {
-        // packed: rows (0,1) and (2,3) of the group in one register each;
-        // the window rows as aligned pairs (2j, 2j+1) and odd pairs
-        // (2j+1, 2j+2); the table holds g^2.
-        const int b0v = best[0], b1v = best[1], b2v = best[2], b3v = best[3];
-        us2 B[2] = {as_us2((uint32_t)b0v | ((uint32_t)b1v << 16)), as_us2((uint32_t)b2v | ((uint32_t)b3v << 16))};
-        int pmax = max(max(b0v, b1v), max(b2v, b3v));
-        for (int d = 1; d * d < pmax; d += kDirSteps) {
-          const uint2* pu = base - ((d + kDirSteps - 1) >> 2) * 64;
-          const uint2* pd = base + ((d - 1) >> 2) * 64;
-          const uint2 u0w = pu[0], u1w = pu[64], d0w = pd[0], d1w = pd[64];
-          const uint32_t U[4] = {u0w.x, u0w.y, u1w.x, u1w.y};
-          const uint32_t Dn[4] = {d0w.x, d0w.y, d1w.x, d1w.y};
-          uint32_t Uo[3], Do[3];
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            Uo[j] = __builtin_amdgcn_alignbyte(U[j + 1], U[j], 2);
-            Do[j] = __builtin_amdgcn_alignbyte(Dn[j + 1], Dn[j], 2);
-          }
-#pragma unroll
-          for (int i = 0; i < kDirSteps; ++i) {
-            // (d + i)^2 is the same for every lane: scalar arithmetic, one
-            // scalar operand of the packed adds
-            const uint32_t dd = (uint32_t)min((d + i) * (d + i), 65535);
-            const us2 D = as_us2(dd | (dd << 16));
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {  // rows 2q, 2q + 1 at distance d + i
-              const uint32_t up = (i & 1) ? U[(3 + 2 * q - i) >> 1] : Uo[(2 + 2 * q - i) >> 1];
-              const uint32_t dn = (i & 1) ? Dn[(1 + 2 * q + i) >> 1] : Do[(2 * q + i) >> 1];
-              B[q] = __builtin_elementwise_min(
-                  B[q], __builtin_elementwise_add_sat(__builtin_elementwise_min(as_us2(up), as_us2(dn)), D));
-            }
-          }
-          pmax = max4(B[0], B[1]);
-        }
-        best[0] = B[0].x;
-        best[1] = B[0].y;
-        best[2] = B[1].x;
-        best[3] = B[1].y;
-        if (PK == 2 && max(max(best[0], best[1]), max(best[2], best[3])) >= 65025) {
-          // some row of the group is at least 255 from the outside: exact search
-          init_exact(true);
-          search32();
-        }
-      } else if (SPATIAL == 0) {
-        search32();
-      }
+      direct_group<SPATIAL, PK, 64>(base, best);
 #pragma unroll
       for (int k = 0; k < kDirRows; ++k) {
         const int u = b0 + gi + k;

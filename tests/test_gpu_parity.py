@@ -107,6 +107,40 @@ def test_edt_deep_tall_items(gpu):
     assert np.array_equal(w0, w2), "direct search disagrees with the band layout"
 
 
+@pytest.mark.parametrize("P", [8, 10, 12, 14, 16, 20, 32, 64])
+def test_edt_tall_patch_sizes(gpu, P):
+    """Items taller than 512 rows (ellipses, a near-full box, a cut disc,
+    random holes, thin columns with many runs per row) at patch sizes that
+    leave 1 to 8 whole patches per strip: the direct search's patch weights
+    equal the band layout's bit for bit and match the oracle, and its squared
+    distances match the oracle."""
+    h, w = 700, 400
+    rng = np.random.default_rng(P)
+    yy, xx = np.indices((h, w))
+    u8 = np.zeros((6, h, w), np.uint8)
+    u8[0] = ((yy - 350) / 340.0) ** 2 + ((xx - 200) / 190.0) ** 2 <= 1.0
+    u8[1, 3:697, 5:390] = 1
+    u8[2] = ((yy - 350) / 345.0) ** 2 + ((xx - 120) / 60.0) ** 2 <= 1.0
+    u8[3] = rng.random((h, w)) < 0.97  # many short runs
+    u8[3, :2] = 0
+    u8[4] = ((yy - 350) ** 2 + (xx - 200) ** 2) <= 300 ** 2
+    u8[4, 340:350, :] = 0
+    u8[5, 1:699, 7:391:3] = 1  # thin columns: many runs per row
+    bits = di.pack_masks(u8)
+    b = dev_bits(bits)
+    w0 = gpu.patch_weights(b, h, w, P, distinct=0, edt_layout=0).cpu().numpy()
+    w2 = gpu.patch_weights(b, h, w, P, distinct=0, edt_layout=2).cpu().numpy()
+    assert np.array_equal(w0, w2), f"P={P}: direct search disagrees with the band layout"
+    s = oracle.spatial_weights(bits, w, P, 0)
+    err = np.abs(w2.astype(np.float64) - s).max() / max(np.abs(s).max(), 1e-30)
+    assert err < REL_S, err
+    if P == 16:
+        got = _edt_gpu(gpu, bits, h, w)
+        want = oracle.edt_sq(bits, w)
+        for i in range(len(u8)):
+            assert np.array_equal(got[i], want[i]), f"tall mask {i}: {np.argwhere(got[i] != want[i])[:5]}"
+
+
 @pytest.mark.parametrize("name,h,w,P", [("cfg2", 480, 640, 16), ("adv", 511, 200, 14), ("adv", 300, 130, 16),
                                         ("adv", 100, 90, 8), ("adv", 40, 333, 64)])
 def test_edt_layouts_agree_bitwise(gpu, name, h, w, P):
