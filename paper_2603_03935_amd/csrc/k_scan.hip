@@ -31,8 +31,11 @@ __device__ inline int wave_sum(int v) {
   return v;
 }
 
+// append = 1: each mask appends its strips to its class's work sub-list
+// (one device-scope atomic per mask); 0: k_lists builds the lists afterwards
+// from the masks' (class, strips) records.
 template <int kScanThreads>
-__global__ __launch_bounds__(kScanThreads) void k_scan(Batch b, Work wk) {
+__global__ __launch_bounds__(kScanThreads) void k_scan(Batch b, Work wk, int append) {
   constexpr int kScanWaves = kScanThreads / 64;
   const int g = blockIdx.x;
   if (g >= b.dyn[1]) return;
@@ -154,7 +157,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Batch b, Work wk) {
       r.xs0 = xs0;
       r.g = g;
       wk.mrec[g] = r;
-      if (cls < kClasses) {
+      if (cls < kClasses && append) {
         // the order of items inside a class's lists does not affect any result
         app[0] = cls;
         app[1] = strips;
@@ -183,12 +186,58 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Batch b, Work wk) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// k_lists: the work sub-lists of batches of more than kListsMasks masks.  A
+// mask's atomic append at the end of its scan workgroup kept the workgroup
+// (and its CU slot) waiting for the atomic's round trip: for large batches
+// the scan only records (class, strips) per mask, and one workgroup per
+// (class, sub-list j) writes the items of the masks g = j, j + kLists, ...
+// of that class in mask order (a block-wide prefix sum of their strips).
+// ---------------------------------------------------------------------------
+constexpr int kListsMasks = 512;
+
+__global__ __launch_bounds__(1024) void k_lists(Batch b, Work wk) {
+  const int c = blockIdx.x / kLists, j = blockIdx.x % kLists;
+  const int M = b.dyn[1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ int wsum[16];
+  int32_t* list = wk.items + ((int64_t)c * kLists + j) * b.item_cap;
+  int total = 0;  // items of the sub-list so far
+  for (int i0 = 0; j + kLists * i0 < M; i0 += 1024) {
+    const int g = j + kLists * (i0 + (int)threadIdx.x);
+    const int meta = g < M ? wk.meta[g] : -1;
+    const int v = (meta >= 0 && (meta >> 16) == c) ? (meta & 0xFFFF) : 0;
+    // inclusive scan over the wavefront, then over the wavefront totals
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(x, o);
+      if (lane >= o) x += t;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int k = 0; k < 16; ++k) {
+      const int t = wsum[k];
+      before += k < wv ? t : 0;
+      all += t;
+    }
+    const int first = total + before + x - v;
+    for (int k = 0; k < v; ++k)
+      if (first + k < b.item_cap) list[first + k] = (g << kItemStripBits) | k;
+    total += all;
+    __syncthreads();  // wsum is rewritten by the next chunk
+  }
+  if (threadIdx.x == 0) wk.counts[c * kLists + j] = total;
+}
+
 void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar) {
   if (b.M <= 0) return;
+  const int append = b.M <= kListsMasks ? 1 : 0;
   if (b.M <= 512 && !any_dbar)
-    hipLaunchKernelGGL(k_scan<1024>, dim3(b.M), dim3(1024), 0, st, b, w);
+    hipLaunchKernelGGL(k_scan<1024>, dim3(b.M), dim3(1024), 0, st, b, w, append);
   else
-    hipLaunchKernelGGL(k_scan<256>, dim3(b.M), dim3(256), 0, st, b, w);
+    hipLaunchKernelGGL(k_scan<256>, dim3(b.M), dim3(256), 0, st, b, w, append);
+  if (!append) hipLaunchKernelGGL(k_lists, dim3(kClasses * kLists), dim3(1024), 0, st, b, w);
 }
 
 // ---------------------------------------------------------------------------
