@@ -630,68 +630,82 @@ __global__ __launch_bounds__(256) void k_pack_proj(const void* proj, int C, int 
   ppack[t] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
 }
 
+// TM x TN output tile per workgroup (128 x 128, or 64 x 64 for batches with
+// fewer 128 x 128 tiles than CUs: four times the workgroups, three resident
+// per CU); each wavefront computes (TM / 2) x (TN / 2) as MI x NJ MFMA tiles
+// of 32 x 32.  Every output element sees the same MFMA K steps and K groups
+// with either shape, so the bits do not depend on it.
+template <int TM, int TN>
 __global__ __launch_bounds__(256) void k_proj_bf16(Batch b, Work wk) {
-  constexpr int BK = 128, AS = BK + 8;
+  constexpr int BK = 128, AS = BK + 8, MI = TM / 64, NJ = TN / 64;
+  constexpr int NA = TM * (BK / 8) / 256, NB = TN * (BK / 8) / 256;  // 16-byte chunks per thread
   const int C = b.C, E = b.E, S = b.proj_split;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
   const int rt = blockIdx.x / S, sidx = blockIdx.x - rt * S;
-  const int gbase = rt * 128, c0 = blockIdx.y * 128;
+  const int gbase = rt * TM, c0 = blockIdx.y * TN;
   const int M = b.dyn[1];
   if (gbase >= M) return;
   const int ngr = (C + kProjKG - 1) / kProjKG;
   const int per = (ngr + S - 1) / S;
   const int ga = sidx * per, gb = min(ngr, ga + per);
   const int kstart = ga * kProjKG, kstop = min(C, gb * kProjKG);
-  __shared__ __attribute__((aligned(16))) uint16_t As[128 * AS];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[128 * AS];
+  __shared__ __attribute__((aligned(16))) uint16_t As[TM * AS];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN * AS];
   // running sum of the K groups (unsplit K), one float4 slot set per thread:
-  // slot (4 (2 i + j) + v / 4) of thread t at [slot][t]
-  __shared__ float4 Ts[16 * 256];
+  // slot (4 (NJ i + j) + v / 4) of thread t at [slot][t]
+  __shared__ float4 Ts[4 * MI * NJ * 256];
 
   const floatx16 zero16 = {};
-  floatx16 acc[2][2];
+  floatx16 acc[MI][NJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = zero16;
+    for (int j = 0; j < NJ; ++j) acc[i][j] = zero16;
   if (S == 1)
-    for (int t = 0; t < 16; ++t) Ts[t * 256 + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int t = 0; t < 4 * MI * NJ; ++t) Ts[t * 256 + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
 
-  // loaders, 8 chunks of 8 k (16 bytes) per thread and operand: A chunk
-  // q = tid + 256 i is row q >> 4, k 8 (q & 15); B chunk q is k group q >> 7
-  // of column q & 127.  Chunks past the K range (C a multiple of 64 only)
+  // loaders, NA / NB chunks of 8 k (16 bytes) per thread: A chunk
+  // q = tid + 256 i is row q >> 4, k 8 (q & 15); B chunk q is k group q / TN
+  // of column q % TN.  Chunks past the K range (C a multiple of 64 only)
   // load zeros and their MFMAs are skipped.
   const uint16_t* X = reinterpret_cast<const uint16_t*>(wk.X);
   const uint4* pp = reinterpret_cast<const uint4*>(wk.ppack);
-  uint4 ra[8], rb[8];
+  uint4 ra[NA], rb[NB];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NA; ++i) {
       const int q = tid + 256 * i, r = q >> 4, ka = k0 + 8 * (q & 15);
       ra[i] = gbase + r < M && ka < kstop ? *reinterpret_cast<const uint4*>(X + (int64_t)(gbase + r) * C + ka)
                                           : make_uint4(0, 0, 0, 0);
-      const int kb = k0 + 8 * (q >> 7);
-      rb[i] = kb < kstop ? pp[(int64_t)(kb >> 3) * E + c0 + (q & 127)] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + 256 * i, kb = k0 + 8 * (q / TN);
+      rb[i] = kb < kstop ? pp[(int64_t)(kb >> 3) * E + c0 + (q % TN)] : make_uint4(0, 0, 0, 0);
     }
   };
   auto stage = [&]() {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NA; ++i) {
       const int q = tid + 256 * i;
       *reinterpret_cast<uint4*>(&As[(q >> 4) * AS + 8 * (q & 15)]) = ra[i];
-      *reinterpret_cast<uint4*>(&Bs[(q & 127) * AS + 8 * (q >> 7)]) = rb[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int q = tid + 256 * i;
+      *reinterpret_cast<uint4*>(&Bs[(q % TN) * AS + 8 * (q / TN)]) = rb[i];
     }
   };
   const int lr = lane & 31, lk = lane >> 5;
   auto fold = [&](int grp) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         if (S == 1) {
 #pragma unroll
           for (int v4 = 0; v4 < 4; ++v4) {
-            float4& t = Ts[(4 * (2 * i + j) + v4) * 256 + tid];
+            float4& t = Ts[(4 * (NJ * i + j) + v4) * 256 + tid];
             float4 u = t;
             u.x += acc[i][j][4 * v4];
             u.y += acc[i][j][4 * v4 + 1];
@@ -700,10 +714,10 @@ __global__ __launch_bounds__(256) void k_proj_bf16(Batch b, Work wk) {
             t = u;
           }
         } else {
-          const int col = c0 + 64 * wn + 32 * j + lr;
+          const int col = c0 + (TN / 2) * wn + 32 * j + lr;
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
-            const int g = gbase + 64 * wm + 32 * i + 8 * (v >> 2) + 4 * lk + (v & 3);
+            const int g = gbase + (TM / 2) * wm + 32 * i + 8 * (v >> 2) + 4 * lk + (v & 3);
             if (g < M) wk.qpart[((int64_t)grp * b.M + g) * E + col] = acc[i][j][v];
           }
         }
@@ -724,15 +738,17 @@ __global__ __launch_bounds__(256) void k_proj_bf16(Batch b, Work wk) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       if (k0 + kk >= kstop) break;
-      u16x8 av[2], bv[2];
+      u16x8 av[MI], bv[NJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = *reinterpret_cast<const u16x8*>(&As[(64 * wm + 32 * i + lr) * AS + kk + 8 * lk]);
+      for (int i = 0; i < MI; ++i)
+        av[i] = *reinterpret_cast<const u16x8*>(&As[((TM / 2) * wm + 32 * i + lr) * AS + kk + 8 * lk]);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const u16x8*>(&Bs[(64 * wn + 32 * j + lr) * AS + kk + 8 * lk]);
+      for (int j = 0; j < NJ; ++j)
+        bv[j] = *reinterpret_cast<const u16x8*>(&Bs[((TN / 2) * wn + 32 * j + lr) * AS + kk + 8 * lk]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[i]),
                                                               __builtin_bit_cast(bf16x8, bv[j]), acc[i][j], 0, 0, 0);
     }
@@ -741,8 +757,8 @@ __global__ __launch_bounds__(256) void k_proj_bf16(Batch b, Work wk) {
   if (kstart < kstop) fold(cur);
   if (S > 1) return;
   // output row pointers of the tile, resolved once
-  __shared__ float* rowp[128];
-  if (tid < 128) {
+  __shared__ float* rowp[TM];
+  if (tid < TM) {
     const int g = gbase + tid;
     float* p = nullptr;
     if (g < M) {
@@ -753,17 +769,17 @@ __global__ __launch_bounds__(256) void k_proj_bf16(Batch b, Work wk) {
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = c0 + 64 * wn + 32 * j + lr;
+    for (int j = 0; j < NJ; ++j) {
+      const int col = c0 + (TN / 2) * wn + 32 * j + lr;
 #pragma unroll
       for (int v4 = 0; v4 < 4; ++v4) {
-        const float4 t = Ts[(4 * (2 * i + j) + v4) * 256 + tid];
+        const float4 t = Ts[(4 * (NJ * i + j) + v4) * 256 + tid];
         const float tv[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int r = 64 * wm + 32 * i + 8 * v4 + 4 * lk + u;
+          const int r = (TM / 2) * wm + 32 * i + 8 * v4 + 4 * lk + u;
           if (gbase + r < M) rowp[r][col] = tv[u];
         }
       }
@@ -829,6 +845,8 @@ __global__ __launch_bounds__(256) void k_norm(Batch b, Work wk) {
   if (lane == 0 && fd.status) fd.status[i] = st_in != 0 ? st_in : (ss > 0.f ? 0 : 2);
 }
 
+constexpr int kProjSmallTiles = 256;  // 128 x 128 projection tiles below which the 64 x 64 shape runs
+
 void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st) {
   if (b.M <= 0) return;
   const dim3 block(256);
@@ -837,7 +855,12 @@ void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16,
     const dim3 pg((unsigned)((np + 255) / 256));
     if (proj_bf16) hipLaunchKernelGGL((k_pack_proj<1>), pg, block, 0, st, proj, b.C, b.E, reinterpret_cast<uint4*>(w.ppack));
     else hipLaunchKernelGGL((k_pack_proj<0>), pg, block, 0, st, proj, b.C, b.E, reinterpret_cast<uint4*>(w.ppack));
-    hipLaunchKernelGGL(k_proj_bf16, dim3((b.M + 127) / 128 * b.proj_split, b.E / 128), block, 0, st, b, w);
+    // 64 x 64 tiles when 128 x 128 ones would leave CUs idle
+    if ((int64_t)(b.M + 127) / 128 * (b.E / 128) * b.proj_split < kProjSmallTiles)
+      hipLaunchKernelGGL((k_proj_bf16<64, 64>), dim3((b.M + 63) / 64 * b.proj_split, b.E / 64), block, 0, st, b, w);
+    else
+      hipLaunchKernelGGL((k_proj_bf16<128, 128>), dim3((b.M + 127) / 128 * b.proj_split, b.E / 128), block, 0, st, b,
+                         w);
   } else {
     const dim3 grid((b.M + 31) / 32 * b.proj_split, b.E / 128);
     if (proj_bf16) hipLaunchKernelGGL((k_proj<1>), grid, block, 0, st, b, w, proj);
