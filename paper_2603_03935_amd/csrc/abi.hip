@@ -398,12 +398,12 @@ void choose_splits(Shape& s) {
   const int pool_tiles = std::max(1, s.n_tiles);
   s.pool_split = pool_tiles >= kTargetWGs ? 1 : std::min(s.kgroups, (kTargetWGs + pool_tiles - 1) / pool_tiles);
   const int qgroups = std::max(1, (s.C + kProjKG - 1) / kProjKG);
-  // BF16 tiles are 128 rows and run a whole K in a few microseconds, so they
-  // split K only when too few to spread over the chip: the group sums cost
-  // 8 bytes per group, row and column of extra traffic.
-  const int rows = s.gemm_bf16 ? 128 : 32;
-  const int64_t proj_tiles = std::max<int64_t>(1, (s.M + rows - 1) / rows * (s.E / 128));
-  const int64_t enough = s.gemm_bf16 ? kTargetWGs / 8 : kTargetWGs;
+  // BF16 tiles (64 x 64) run a whole K in a few microseconds, so they split K
+  // only when too few to spread over the chip: the group sums cost 8 bytes
+  // per group, row and column of extra traffic.
+  const int rows = s.gemm_bf16 ? 64 : 32, cols = s.gemm_bf16 ? 64 : 128;
+  const int64_t proj_tiles = std::max<int64_t>(1, (s.M + rows - 1) / rows * (s.E / cols));
+  const int64_t enough = s.gemm_bf16 ? kTargetWGs / 2 : kTargetWGs;
   s.proj_split = proj_tiles >= enough ? 1 : (int)std::min<int64_t>(qgroups, (kTargetWGs + proj_tiles - 1) / proj_tiles);
 }
 

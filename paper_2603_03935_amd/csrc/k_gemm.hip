@@ -630,11 +630,11 @@ __global__ __launch_bounds__(256) void k_pack_proj(const void* proj, int C, int 
   ppack[t] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
 }
 
-// TM x TN output tile per workgroup (128 x 128, or 64 x 64 for batches with
-// fewer 128 x 128 tiles than CUs: four times the workgroups, three resident
-// per CU); each wavefront computes (TM / 2) x (TN / 2) as MI x NJ MFMA tiles
-// of 32 x 32.  Every output element sees the same MFMA K steps and K groups
-// with either shape, so the bits do not depend on it.
+// TM x TN output tile per workgroup, each wavefront (TM / 2) x (TN / 2) as
+// MI x NJ MFMA tiles of 32 x 32.  64 x 64 tiles (51 KB of LDS, three
+// workgroups per CU) measured faster than 128 x 128 ones (136 KB, one per
+// CU) at every batch size here (cfg3 44 -> 34 us, cfg5 91 -> 82 us); every
+// output element sees the same MFMA K steps and K groups with either shape.
 template <int TM, int TN>
 __global__ __launch_bounds__(256) void k_proj_bf16(Batch b, Work wk) {
   constexpr int BK = 128, AS = BK + 8, MI = TM / 64, NJ = TN / 64;
@@ -845,8 +845,6 @@ __global__ __launch_bounds__(256) void k_norm(Batch b, Work wk) {
   if (lane == 0 && fd.status) fd.status[i] = st_in != 0 ? st_in : (ss > 0.f ? 0 : 2);
 }
 
-constexpr int kProjSmallTiles = 256;  // 128 x 128 projection tiles below which the 64 x 64 shape runs
-
 void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st) {
   if (b.M <= 0) return;
   const dim3 block(256);
@@ -855,12 +853,7 @@ void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16,
     const dim3 pg((unsigned)((np + 255) / 256));
     if (proj_bf16) hipLaunchKernelGGL((k_pack_proj<1>), pg, block, 0, st, proj, b.C, b.E, reinterpret_cast<uint4*>(w.ppack));
     else hipLaunchKernelGGL((k_pack_proj<0>), pg, block, 0, st, proj, b.C, b.E, reinterpret_cast<uint4*>(w.ppack));
-    // 64 x 64 tiles when 128 x 128 ones would leave CUs idle
-    if ((int64_t)(b.M + 127) / 128 * (b.E / 128) * b.proj_split < kProjSmallTiles)
-      hipLaunchKernelGGL((k_proj_bf16<64, 64>), dim3((b.M + 63) / 64 * b.proj_split, b.E / 64), block, 0, st, b, w);
-    else
-      hipLaunchKernelGGL((k_proj_bf16<128, 128>), dim3((b.M + 127) / 128 * b.proj_split, b.E / 128), block, 0, st, b,
-                         w);
+    hipLaunchKernelGGL((k_proj_bf16<64, 64>), dim3((b.M + 63) / 64 * b.proj_split, b.E / 64), block, 0, st, b, w);
   } else {
     const dim3 grid((b.M + 31) / 32 * b.proj_split, b.E / 128);
     if (proj_bf16) hipLaunchKernelGGL((k_proj<1>), grid, block, 0, st, b, w, proj);

@@ -454,23 +454,22 @@ def test_pool_tile_widths_agree_bitwise(gpu, name, frames):
 
 
 def test_projection_split_invariance(gpu):
-    """The BF16 projection runs whole-K 64 x 64 tiles on a full cfg3 batch,
-    whole-K 128 x 128 tiles on the cfg3 frames taken twice (more than 256 of
-    those tiles) and split-K tiles (group sums added in group order) on a few
-    of its frames: the same frames get the same bits every way."""
+    """The BF16 projection runs whole-K tiles on a full cfg3 batch (and on the
+    cfg3 frames taken twice) and split-K tiles (group sums added in group
+    order) on a few of its frames: the same frames get the same bits every
+    way."""
     wl = di.workload("cfg3")
     ins = [frame_input(f) for f in wl.frames]
     proj = dev_proj(wl.proj, wl.proj_dtype)
     full = gpu.embed_frames(ins, proj)
     few = gpu.embed_frames(ins[:3], proj)
     m = sum(o.out.shape[0] for o in full)
-    assert m > 128 * 64 // 6, "the full batch must take the whole-K path"
+    assert -(-m // 64) * (768 // 64) >= 256, "the full batch must take the whole-K path"
     big = gpu.embed_frames(ins + ins, proj)
-    assert -(-2 * m // 128) * (768 // 128) >= 256, "the doubled batch must take the 128 x 128 tiles"
     for i in range(3):
         a = full[i].out.cpu().numpy()
         assert np.array_equal(a, few[i].out.cpu().numpy()), f"frame {i}: split-K result differs"
-        assert np.array_equal(a, big[i].out.cpu().numpy()), f"frame {i}: 128 x 128 tiles differ from 64 x 64"
+        assert np.array_equal(a, big[i].out.cpu().numpy()), f"frame {i}: result in the doubled batch differs"
         assert np.array_equal(a, big[len(ins) + i].out.cpu().numpy()), f"frame {i}: second copy differs"
 
 
