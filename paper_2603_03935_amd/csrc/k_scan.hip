@@ -1,6 +1,6 @@
 // Mask scan (bounding box + area per mask), which also appends each mask's
-// distance-transform work items to its class's list; the bit-packing and fill
-// helpers.
+// distance-transform work items to its class's lists (small batches; larger
+// ones build the lists in k_lists); the bit-packing and fill helpers.
 #include "disc_device.h"
 
 namespace disc {
