@@ -44,8 +44,10 @@ __device__ __forceinline__ uint64_t valid_bits(int k, int wq, int w) {
   return (k == wq - 1 && (w & 63)) ? ((1ull << (w & 63)) - 1) : ~0ull;
 }
 
-// mask pixels in an unbroken run ending at column x (inclusive), going left
-__device__ __forceinline__ int run_left(const uint64_t* row, int x, int wq, int w) {
+// mask pixels in an unbroken run ending at column x (inclusive), going left;
+// the walk stops once the count reaches cap (the result is then >= cap, not
+// the run's length: callers that clamp g at cap or below lose nothing)
+__device__ __forceinline__ int run_left(const uint64_t* row, int x, int wq, int w, int cap = INT32_MAX) {
   if (x < 0) return 0;
   int k = x >> 6;
   const int bpos = x & 63;
@@ -53,7 +55,7 @@ __device__ __forceinline__ int run_left(const uint64_t* row, int x, int wq, int 
   const uint64_t z = ~wd & ((2ull << bpos) - 1);
   if (z) return bpos - 63 + __builtin_clzll(z);
   int L = bpos + 1;
-  for (--k; k >= 0; --k) {
+  for (--k; k >= 0 && L < cap; --k) {
     wd = row[k];
     if (~wd) return L + __builtin_clzll(~wd);
     L += 64;
@@ -61,8 +63,9 @@ __device__ __forceinline__ int run_left(const uint64_t* row, int x, int wq, int 
   return L;
 }
 
-// mask pixels in an unbroken run starting at column x, going right
-__device__ __forceinline__ int run_right(const uint64_t* row, int x, int wq, int w) {
+// mask pixels in an unbroken run starting at column x, going right (the walk
+// stops at cap as in run_left)
+__device__ __forceinline__ int run_right(const uint64_t* row, int x, int wq, int w, int cap = INT32_MAX) {
   if (x >= w) return 0;
   int k = x >> 6;
   const int bpos = x & 63;
@@ -70,7 +73,7 @@ __device__ __forceinline__ int run_right(const uint64_t* row, int x, int wq, int
   const uint64_t z = ~wd & (~0ull << bpos);
   if (z) return __builtin_ctzll(z) - bpos;
   int R = 64 - bpos;
-  for (++k; k < wq; ++k) {
+  for (++k; k < wq && R < cap; ++k) {
     wd = row[k] & valid_bits(k, wq, w);
     if (~wd) return R + __builtin_ctzll(~wd);
     R += 64;
@@ -672,6 +675,9 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
 // sums go to global memory and k_edt_dsums adds them.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int direct_items(int c) { return c == 5 ? 1 : (kEdtWaves >> c); }
+// run lengths past a strip window's ends are needed up to the largest g the
+// tables keep (576, the bound of the tallest class); AREA needs only g > 0
+constexpr int kDirRunCap = 576;
 constexpr int kDirRows = 4;   // rows searched together
 constexpr int kDirSteps = 4;  // distances per search step (windows start on 4-row words)
 // A group's search reads at most kDirRows + kDirSteps - 2 rows past its item
@@ -829,8 +835,10 @@ __device__ __forceinline__ void direct_table(int cls, const uint32_t* recs, cons
           const int xs = (int)rc[14] + (word & ((1 << kItemStripBits) - 1)) * strip_width((int)rc[9]);
           const uint64_t* row = mb + (int64_t)(y0 - 1 + u) * wq;
           const uint64_t win = load_window(row, xs, wq, fw);
-          const int L = (win & 1ull) ? run_left(row, xs - 1, wq, fw) : 0;
-          const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw) : 0;
+          // the table clamps g at 576 or below: runs past the window's ends
+          // matter up to that length
+          const int L = (win & 1ull) ? run_left(row, xs - 1, wq, fw, kDirRunCap) : 0;
+          const int R = (win >> 63) ? run_right(row, xs + 64, wq, fw, kDirRunCap) : 0;
           r = make_rowrec(win, L, R);
         }
       }
