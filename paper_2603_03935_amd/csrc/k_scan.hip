@@ -190,13 +190,84 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Batch b, Work wk, int app
 // k_lists: the work sub-lists of batches of more than kListsMasks masks.  A
 // mask's atomic append at the end of its scan workgroup kept the workgroup
 // (and its CU slot) waiting for the atomic's round trip: for large batches
-// the scan only records (class, strips) per mask, and one workgroup per
-// (class, sub-list j) writes the items of the masks g = j, j + kLists, ...
-// of that class in mask order (a block-wide prefix sum of their strips).
+// the scan only records (class, strips) per mask.  One workgroup per (class
+// c < 5, sub-list j) writes the items of the masks g = j, j + kLists, ... of
+// that class in mask order (a block-wide prefix sum of their strips).  The
+// items taller than 512 rows (class 5), whose search costs differ by two
+// orders of magnitude, are written by one more workgroup in decreasing order
+// of an estimated cost (counting sort over kCostBuckets buckets of
+// n * min(n, box width), a mask's strips kept together), filling the
+// sub-lists one after another: the XCD queues of the direct search then hand
+// out the longest packets first.
 // ---------------------------------------------------------------------------
 constexpr int kListsMasks = 512;
+constexpr int kCostBuckets = 64;
 
+__device__ __forceinline__ int tall_cost_bucket(const Work& wk, int g) {
+  const int4 bb = wk.bbox[g];
+  const int n = bb.y - bb.x + 3, bw = bb.w - bb.z + 1;
+  const float key = (float)n * (float)min(n, bw);  // >= 1
+  return min(kCostBuckets - 1, (int)(2.f * __log2f(key)));
+}
+
+__device__ __forceinline__ void lists_tall(const Batch& b, const Work& wk) {
+  __shared__ int cnt[kCostBuckets], cur[kCostBuckets];
+  const int M = b.dyn[1];
+  const int cap = b.item_cap;
+  if (threadIdx.x < kCostBuckets) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  // eight masks per thread and round, their records loaded together
+  for (int g0 = 0; g0 < M; g0 += 8 * 1024) {
+    int mt[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int g = g0 + 1024 * i + (int)threadIdx.x;
+      mt[i] = g < M ? wk.meta[g] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (mt[i] >= 0 && (mt[i] >> 16) == 5)
+        atomicAdd(&cnt[tall_cost_bucket(wk, g0 + 1024 * i + (int)threadIdx.x)], mt[i] & 0xFFFF);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;  // descending cost: the last bucket first
+    for (int k = kCostBuckets - 1; k >= 0; --k) {
+      cur[k] = acc;
+      acc += cnt[k];
+    }
+    cnt[0] = acc;  // the class's item count
+  }
+  __syncthreads();
+  const int total = cnt[0];
+  int32_t* list = wk.items + (int64_t)5 * kLists * cap;  // sub-lists 0 .. kLists - 1 back to back
+  for (int g0 = 0; g0 < M; g0 += 8 * 1024) {
+    int mt[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int g = g0 + 1024 * i + (int)threadIdx.x;
+      mt[i] = g < M ? wk.meta[g] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (mt[i] < 0 || (mt[i] >> 16) != 5) continue;
+      const int g = g0 + 1024 * i + (int)threadIdx.x, strips = mt[i] & 0xFFFF;
+      const int first = atomicAdd(&cur[tall_cost_bucket(wk, g)], strips);
+      for (int k = 0; k < strips; ++k)
+        if (first + k < kLists * cap) list[first + k] = (g << kItemStripBits) | k;
+    }
+  }
+  if (threadIdx.x < kLists)
+    wk.counts[5 * kLists + threadIdx.x] = max(0, min(cap, total - (int)threadIdx.x * cap));
+}
+
+// grid: (kClasses - 1) * kLists workgroups for classes 0-4, plus one for
+// class 5 when the batch can have such items (it runs beside the others)
 __global__ __launch_bounds__(1024) void k_lists(Batch b, Work wk) {
+  if ((int)blockIdx.x == (kClasses - 1) * kLists) {
+    lists_tall(b, wk);
+    return;
+  }
   const int c = blockIdx.x / kLists, j = blockIdx.x % kLists;
   const int M = b.dyn[1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -237,7 +308,11 @@ void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar) {
     hipLaunchKernelGGL(k_scan<1024>, dim3(b.M), dim3(1024), 0, st, b, w, append);
   else
     hipLaunchKernelGGL(k_scan<256>, dim3(b.M), dim3(256), 0, st, b, w, append);
-  if (!append) hipLaunchKernelGGL(k_lists, dim3(kClasses * kLists), dim3(1024), 0, st, b, w);
+  if (!append) {
+    // class-5 counters stay 0 (zeroed when staged) when no item can be that tall
+    const int tall = b.max_rows > class_rows(kClasses - 2) ? 1 : 0;
+    hipLaunchKernelGGL(k_lists, dim3((kClasses - 1) * kLists + tall), dim3(1024), 0, st, b, w);
+  }
 }
 
 // ---------------------------------------------------------------------------
