@@ -453,6 +453,28 @@ def test_pool_tile_widths_agree_bitwise(gpu, name, frames):
             assert np.array_equal(a, b), f"{name}: embeddings of shape {key} differ from the tuned one on frame {i}"
 
 
+def test_mask_order_and_subset_invariance(gpu):
+    """A mask's embedding does not depend on the other masks of its frame:
+    a 500-mask 1080p frame, the same masks reversed, and subsets above and
+    below the size at which the pooling order moves the largest boxes to the
+    front give each mask the same pooled features and embedding, bit for bit."""
+    wl = di.workload("cfg5", frames=1)
+    fr = wl.frames[0]
+    proj = dev_proj(wl.proj, wl.proj_dtype)
+    m = fr.m
+    orders = {"all": np.arange(m), "reversed": np.arange(m)[::-1].copy(),
+              "300": np.random.default_rng(3).permutation(m)[:300], "200": np.arange(0, m, 2)[:200]}
+    res = {}
+    for name, idx in orders.items():
+        sub = di.Frame(fr.tokens, np.ascontiguousarray(fr.bits[idx]), fr.h, fr.w)
+        o = gpu.embed_frames([frame_input(sub)], proj, pooled=True)[0]
+        res[name] = (idx, o.out.cpu().numpy(), o.pooled.cpu().numpy())
+    _, full, fullp = res["all"]
+    for name, (idx, out, pooled) in res.items():
+        assert np.array_equal(pooled, fullp[idx]), f"pooled features of the {name} masks differ from the full frame"
+        assert np.array_equal(out, full[idx]), f"embeddings of the {name} masks differ from the full frame"
+
+
 def test_projection_split_invariance(gpu):
     """The BF16 projection runs whole-K tiles on a full cfg3 batch (and on the
     cfg3 frames taken twice) and split-K tiles (group sums added in group
