@@ -114,80 +114,65 @@ __global__ __launch_bounds__(256) void k_mean(Batch b, Work wk) {
   wk.mean[(int64_t)f * b.C + c] = a * (1.0f / (float)G);
 }
 
-// One workgroup per group of 8 consecutive tokens p0..p0+7 of a frame:
-// r_p = ||f_p - mean|| for the 8 tokens (block reduction).  Each thread owns
-// CW consecutive channels and loads them for all 8 tokens (FP8: value =
-// scale * code).
+// r_p = ||f_p - mean|| over the tokens of a frame.  A thread owns one vector
+// of VEC channels (16 or 32 bytes of a token row, as k_colsum reads them)
+// and reads it for tpt <= 8 tokens, so its slice of the mean is read once;
+// the nthr = min(C / VEC, 256) threads of a token row sit side by side,
+// R = 256 / nthr rows of them, so a workgroup covers tpt·R consecutive tokens
+// and every 16-byte load instruction of a wavefront reads 1 KB of one or two
+// token rows.  The per-thread partial sums of each token are added in thread
+// order from LDS.
 template <int TOK>
-__global__ __launch_bounds__(256) void k_resid(Batch b, Work wk) {
-  constexpr int CW = TOK == 2 ? 8 : 4;
+__global__ __launch_bounds__(256) void k_resid(Batch b, Work wk, int tpt) {
+  constexpr int VEC = TOK == 2 ? 16 : 8;
   const int f = blockIdx.y;
   if (f >= b.dyn[0]) return;
   const FrameDesc fd = b.frames[f];
   const int G = fd.G, C = b.C;
-  const int p0 = blockIdx.x * 8;
+  const int nch = C / VEC, nthr = min(nch, 256), R = 256 / nthr, ntok = tpt * R;
+  const int p0 = blockIdx.x * ntok;
   if (p0 >= G) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, ro = tid / nthr, cl = tid % nthr;
   const float* mu = wk.mean + (int64_t)f * C;
   float ss[8];
   for (int i = 0; i < 8; ++i) ss[i] = 0.f;
-  for (int chunk = tid; chunk < C / CW; chunk += 256) {
-    const int c = chunk * CW;
-    if (TOK == 2) {
-      uint2 codes[8];
-      float sc[8];
-      for (int i = 0; i < 8; ++i) {
-        const int p = p0 + i;
-        codes[i] = p < G ? *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(fd.tokens) + (int64_t)p * C + c)
-                         : make_uint2(0u, 0u);
-        sc[i] = p < G ? fd.scale[p] : 0.f;
+  if (ro < R) {
+    for (int cg = cl; cg < nch; cg += nthr) {
+      const int c = cg * VEC;
+      float m[VEC];
+      for (int j = 0; j < VEC; j += 4) {
+        const float4 q = *reinterpret_cast<const float4*>(mu + c + j);
+        m[j] = q.x; m[j + 1] = q.y; m[j + 2] = q.z; m[j + 3] = q.w;
       }
-      float m[8];
-      for (int j = 0; j < 8; ++j) m[j] = mu[c + j];
+#pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const float4 x0 = e4m3x4_to_f32(codes[i].x), x1 = e4m3x4_to_f32(codes[i].y);
-        const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-        for (int j = 0; j < 8; ++j) {
-          const float dd = (p0 + i < G) ? sc[i] * v[j] - m[j] : 0.f;
-          ss[i] += dd * dd;
-        }
-      }
-    } else {
-      float v[8][CW];
-      for (int i = 0; i < 8; ++i) {
-        const int p = p0 + i;
-        for (int j = 0; j < CW; ++j) v[i][j] = 0.f;
-        if (p >= G) continue;
-        const int64_t off = (int64_t)p * C + c;
-        if (TOK == 0) {
-          const float4 x = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(fd.tokens) + off);
-          v[i][0] = x.x; v[i][1] = x.y; v[i][2] = x.z; v[i][3] = x.w;
-        } else {
-          const uint2 x = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(fd.tokens) + off);
-          v[i][0] = bf16_to_f32(x.x & 0xFFFFu); v[i][1] = bf16_to_f32(x.x >> 16);
-          v[i][2] = bf16_to_f32(x.y & 0xFFFFu); v[i][3] = bf16_to_f32(x.y >> 16);
-        }
-      }
-      for (int j = 0; j < CW; ++j) {
-        const float m = mu[c + j];
-        for (int i = 0; i < 8; ++i) {
-          const float dd = (p0 + i < G) ? v[i][j] - m : 0.f;
-          ss[i] += dd * dd;
+        const int p = p0 + ro + R * i;
+        if (i < tpt && p < G) {
+          float v[VEC];
+          load_vec<TOK>(fd.tokens, fd.scale, p, C, c, v);
+          for (int j = 0; j < VEC; ++j) {
+            const float dd = v[j] - m[j];
+            ss[i] += dd * dd;
+          }
         }
       }
     }
   }
-  __shared__ float red[4][8];
-  const int lane = tid & 63, wv = tid >> 6;
-  for (int i = 0; i < 8; ++i) {
-    float x = ss[i];
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    if (lane == 0) red[wv][i] = x;
-  }
+  __shared__ float part[8 * 256];  // [token of the group][thread of its row]
+  if (ro < R)
+    for (int i = 0; i < tpt; ++i) part[(ro + R * i) * nthr + cl] = ss[i];
   __syncthreads();
-  if (tid < 8 && p0 + tid < G)
-    wk.r[fd.r_base + p0 + tid] = __builtin_sqrtf(red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid]);
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int t = wv; t < ntok; t += 4) {
+    float x = 0.f;
+    for (int k = lane; k < nthr; k += 64) x += part[t * nthr + k];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == 0 && p0 + t < G) wk.r[fd.r_base + p0 + t] = __builtin_sqrtf(x);
+  }
 }
+
+// token rows side by side in a k_resid workgroup
+inline int resid_rows(int C, int tok_dtype) { return 256 / std::min(C / (tok_dtype == 2 ? 16 : 8), 256); }
 
 // Token statistics of every frame: chunk partial sums, the frame mean, then r.
 void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st) {
@@ -196,10 +181,14 @@ void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st)
   else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_colsum<1>, cgrid, dim3(256), 0, st, b, w);
   else hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
   hipLaunchKernelGGL(k_mean, dim3((b.C + 255) / 256, b.n_frames), dim3(256), 0, st, b, w);
-  const dim3 rgrid((gmax + 7) / 8, b.n_frames);
-  if (b.tok_dtype == 2) hipLaunchKernelGGL(k_resid<2>, rgrid, dim3(256), 0, st, b, w);
-  else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_resid<1>, rgrid, dim3(256), 0, st, b, w);
-  else hipLaunchKernelGGL(k_resid<0>, rgrid, dim3(256), 0, st, b, w);
+  // 8 tokens per thread, fewer where that would leave under 1024 workgroups
+  const int R = resid_rows(b.C, b.tok_dtype);
+  int tpt = 8;
+  while (tpt > 1 && (int64_t)((gmax + tpt * R - 1) / (tpt * R)) * b.n_frames < 1024) tpt /= 2;
+  const dim3 rgrid((gmax + tpt * R - 1) / (tpt * R), b.n_frames);
+  if (b.tok_dtype == 2) hipLaunchKernelGGL(k_resid<2>, rgrid, dim3(256), 0, st, b, w, tpt);
+  else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_resid<1>, rgrid, dim3(256), 0, st, b, w, tpt);
+  else hipLaunchKernelGGL(k_resid<0>, rgrid, dim3(256), 0, st, b, w, tpt);
 }
 
 // D = r / (mean(r) + eps) for one frame (stage entry point only).
