@@ -292,15 +292,27 @@ __device__ float write_row(const Batch& b, const Work& wk, const FrameDesc& fd, 
 #pragma unroll
     for (int e = 0; e < 8; ++e) wv[e] = 0.f;
     if (p0 <= rhi && p0 + 7 >= rlo) {
+      // every load of the chunk first (in bounds: the row holds Gs >= p0 + 8
+      // elements, r and the scales G), then the elements inside the rectangle
+      const float4* sp = reinterpret_cast<const float4*>(wk.s + rowoff + p0);
+      const float4 sa = sp[0], sb = sp[1];
+      const float s8[8] = {sa.x, sa.y, sa.z, sa.w, sb.x, sb.y, sb.z, sb.w};
+      float r8[8], c8[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int p = min(p0 + e, G - 1);
+        r8[e] = use_r ? r[p] : 1.f;
+        c8[e] = fp8 ? fd.scale[p] : 1.f;
+      }
       int pr = p0 / gw, pc = p0 - pr * gw;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int p = p0 + e;
         if (p < G && pr >= pr0 && pr <= pr1 && pc >= pc0 && pc <= pc1) {
-          const float sv = wk.s[rowoff + p];
+          const float sv = s8[e];
           ssum += sv;
-          const float wu = use_r ? sv * r[p] : sv;
-          const float sc = fp8 ? fd.scale[p] : 1.f;
+          const float wu = use_r ? sv * r8[e] : sv;
+          const float sc = c8[e];
           float w = fp8 ? wu * sc : wu;
           if (BF16) w = __uint_as_float((uint32_t)f32_to_bf16_rne(w) << 16);
           wv[e] = w;
