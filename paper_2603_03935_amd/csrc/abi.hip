@@ -689,15 +689,22 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   b.eps = o.eps;
   const Work w = work_ptrs(dev_ws, p.L);
   const int4* tiles = reinterpret_cast<const int4*>(dev_ws + p.L.tiles);
-  // token statistics first: the mask scan folds r into the mean distinctiveness
+  // token statistics first: the mask scan folds r into the mean
+  // distinctiveness.  Without that, a small batch's scan launch also takes
+  // the statistics' channel sums (one launch fewer; the stage trace then
+  // counts them under the scan) and the rest of the statistics follow it.
   const bool want_r = o.distinct || p.shape.want_dbar;
-  if (want_r || tok_dtype == DISC_F8E4M3) {
+  const bool stats = want_r || tok_dtype == DISC_F8E4M3;
+  const bool fused = want_r && scan_takes_colsum(b, p.shape.want_dbar);
+  auto run_stats = [&](bool colsum_done) {
     StageTimer t(sid < 0 ? -1 : ST_STATS, st);
     if (tok_dtype == DISC_F8E4M3) launch_scale_check(b, w, p.shape.gmax, st);
-    if (want_r) launch_token_stats(b, w, p.shape.gmax, st);
+    if (want_r) launch_token_stats(b, w, p.shape.gmax, st, colsum_done);
     if (p.shape.want_dbar) launch_rbar(b, w, st);
-  }
-  { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st, p.shape.want_dbar); }
+  };
+  if (stats && !fused) run_stats(false);
+  { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st, p.shape.want_dbar, fused); }
+  if (fused) run_stats(true);
   // the pooling order rides on the launch after the distance transform
   { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st, o.edt_layout, true); }
   { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); }

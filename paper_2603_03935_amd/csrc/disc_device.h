@@ -195,7 +195,11 @@ struct Work {
 // Host-side launchers (stream = hipStream_t).
 // any_dbar: some frame of the batch asks for the mean distinctiveness (its
 // float sum is formed per scan thread, so such batches always use one width)
-void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar = true);
+// colsum: when scan_takes_colsum(b, any_dbar), the scan's launch also takes
+// the token statistics' channel sums (launch_token_stats then runs with
+// colsum_done)
+void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar = true, bool colsum = false);
+bool scan_takes_colsum(const Batch& b, bool any_dbar);
 // Pooling order of frame f's masks: a counting sort over 256 buckets by the
 // first patch row of the box (empty masks last), so that each 64-mask pooling
 // tile reads a narrow band of token rows.  A frame of more than kPoolBigMin
@@ -265,6 +269,82 @@ __device__ inline void pool_order_frame(const Batch& b, const Work& wk, int f, i
   __syncthreads();
 }
 
+// Token statistics: partial channel sums over chunks of stat_chunk(G) tokens
+// of a frame, folded in chunk order into the frame mean by k_mean.  The first
+// 256 threads of the block do the work (the same partition and order in a
+// 256-thread k_colsum workgroup and in the 1024-thread mask-scan workgroups
+// that carry it for small batches); every thread of the block must call it.
+// Each thread reads 16-byte vectors (VEC channels) of several token rows.
+template <int TOK>
+__device__ __forceinline__ void load_vec(const void* base, const float* scale, int64_t p, int C, int c, float* v) {
+  const int64_t off = p * C + c;
+  if (TOK == 0) {
+    const float4* q = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(base) + off);
+    const float4 a = q[0], d = q[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = d.x; v[5] = d.y; v[6] = d.z; v[7] = d.w;
+  } else if (TOK == 1) {
+    const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(base) + off);
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+    for (int j = 0; j < 4; ++j) {
+      v[2 * j] = bf16_to_f32(w[j] & 0xFFFFu);
+      v[2 * j + 1] = bf16_to_f32(w[j] >> 16);
+    }
+  } else {
+    const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint8_t*>(base) + off);
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+    const float sc = scale[p];
+    for (int j = 0; j < 4; ++j) {
+      const float4 x = e4m3x4_to_f32(w[j]);
+      v[4 * j] = sc * x.x;
+      v[4 * j + 1] = sc * x.y;
+      v[4 * j + 2] = sc * x.z;
+      v[4 * j + 3] = sc * x.w;
+    }
+  }
+}
+
+template <int TOK>
+__device__ inline void colsum_chunk(const Batch& b, const Work& wk, int f, int chunk) {
+  constexpr int VEC = TOK == 2 ? 16 : 8;
+  if (f >= b.dyn[0]) return;
+  const FrameDesc fd = b.frames[f];
+  const int G = fd.G, C = b.C;
+  const int nch = stat_nchunk(G);
+  if (chunk >= nch) return;
+  const int tpr = C / VEC, rpp = 256 / tpr;
+  const int tid = threadIdx.x, cg = tid % tpr, ro = tid / tpr;
+  const int p0 = chunk * stat_chunk(G), p1 = min(p0 + stat_chunk(G), G);
+  __shared__ float part[256 * 16];
+  float acc[VEC];
+  for (int j = 0; j < VEC; ++j) acc[j] = 0.f;
+  if (ro < rpp) {
+    int p = p0 + ro;
+    for (; p + 3 * rpp < p1; p += 4 * rpp) {
+      float v0[VEC], v1[VEC], v2[VEC], v3[VEC];
+      load_vec<TOK>(fd.tokens, fd.scale, p, C, cg * VEC, v0);
+      load_vec<TOK>(fd.tokens, fd.scale, p + rpp, C, cg * VEC, v1);
+      load_vec<TOK>(fd.tokens, fd.scale, p + 2 * rpp, C, cg * VEC, v2);
+      load_vec<TOK>(fd.tokens, fd.scale, p + 3 * rpp, C, cg * VEC, v3);
+      for (int j = 0; j < VEC; ++j) acc[j] += ((v0[j] + v1[j]) + v2[j]) + v3[j];
+    }
+    for (; p < p1; p += rpp) {
+      float v0[VEC];
+      load_vec<TOK>(fd.tokens, fd.scale, p, C, cg * VEC, v0);
+      for (int j = 0; j < VEC; ++j) acc[j] += v0[j];
+    }
+    for (int j = 0; j < VEC; ++j) part[ro * C + cg * VEC + j] = acc[j];
+  }
+  __syncthreads();
+  float* ps = wk.psum + ((int64_t)f * b.nchunk + chunk) * C;
+  if (tid < 256) {
+    for (int c = tid; c < C; c += 256) {
+      float a = 0.f;
+      for (int r = 0; r < rpp; ++r) a += part[r * C + c];
+      ps[c] = a;
+    }
+  }
+}
+
 void launch_pool_order(const Batch& b, const Work& w, hipStream_t st);
 // order_pool: also order every frame's masks for the pooling (as
 // launch_pool_order), inside the launch that follows the distance transform
@@ -272,7 +352,8 @@ void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipS
                 bool order_pool = false);
 void edt_prepare();
 // Frame means and residual norms r (gmax: the largest G).
-void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st);
+// colsum_done: the channel sums were taken by the mask scan's launch
+void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st, bool colsum_done = false);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
 void launch_rbar(const Batch& b, const Work& w, hipStream_t st);
 // FP8 tokens: flag the frames whose scales hold a non-finite or negative value

@@ -33,11 +33,21 @@ __device__ inline int wave_sum(int v) {
 
 // append = 1: each mask appends its strips to its class's work sub-list
 // (one device-scope atomic per mask); 0: k_lists builds the lists afterwards
-// from the masks' (class, strips) records.
-template <int kScanThreads>
-__global__ __launch_bounds__(kScanThreads) void k_scan(Batch b, Work wk, int append) {
+// from the masks' (class, strips) records.  CS >= 0: the workgroups past the
+// first scan_blocks take the token statistics' channel-sum chunks (tokens of
+// type CS; chunk-major per frame, as k_colsum's grid), so a small batch
+// saves that launch.
+template <int kScanThreads, int CS = -1>
+__global__ __launch_bounds__(kScanThreads) void k_scan(Batch b, Work wk, int append, int scan_blocks = 0) {
   constexpr int kScanWaves = kScanThreads / 64;
   const int g = blockIdx.x;
+  if constexpr (CS >= 0) {
+    if (g >= scan_blocks) {
+      const int k = g - scan_blocks;
+      colsum_chunk<CS>(b, wk, k / b.nchunk, k % b.nchunk);
+      return;
+    }
+  }
   if (g >= b.dyn[1]) return;
   const FrameDesc fd = b.frames[b.mask_frame[g]];
   const int wq = fd.wq, h = fd.h;
@@ -301,13 +311,24 @@ __global__ __launch_bounds__(1024) void k_lists(Batch b, Work wk) {
   if (threadIdx.x == 0) wk.counts[c * kLists + j] = total;
 }
 
-void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar) {
+bool scan_takes_colsum(const Batch& b, bool any_dbar) { return b.M > 0 && b.M <= 512 && !any_dbar; }
+
+void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar, bool colsum) {
   if (b.M <= 0) return;
   const int append = b.M <= kListsMasks ? 1 : 0;
-  if (b.M <= 512 && !any_dbar)
-    hipLaunchKernelGGL(k_scan<1024>, dim3(b.M), dim3(1024), 0, st, b, w, append);
-  else
-    hipLaunchKernelGGL(k_scan<256>, dim3(b.M), dim3(256), 0, st, b, w, append);
+  if (scan_takes_colsum(b, any_dbar)) {
+    const int nb = b.M + (colsum ? b.nchunk * b.n_frames : 0);
+    if (!colsum)
+      hipLaunchKernelGGL((k_scan<1024>), dim3(b.M), dim3(1024), 0, st, b, w, append, 0);
+    else if (b.tok_dtype == 0)
+      hipLaunchKernelGGL((k_scan<1024, 0>), dim3(nb), dim3(1024), 0, st, b, w, append, (int)b.M);
+    else if (b.tok_dtype == 1)
+      hipLaunchKernelGGL((k_scan<1024, 1>), dim3(nb), dim3(1024), 0, st, b, w, append, (int)b.M);
+    else
+      hipLaunchKernelGGL((k_scan<1024, 2>), dim3(nb), dim3(1024), 0, st, b, w, append, (int)b.M);
+  } else {
+    hipLaunchKernelGGL((k_scan<256>), dim3(b.M), dim3(256), 0, st, b, w, append, 0);
+  }
   if (!append) {
     // class-5 counters stay 0 (zeroed when staged) when no item can be that tall
     const int tall = b.max_rows > class_rows(kClasses - 2) ? 1 : 0;

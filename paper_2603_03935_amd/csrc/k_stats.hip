@@ -29,76 +29,12 @@ __device__ __forceinline__ float4 load4(const void* base, int dtype, const float
   return make_float4(s * x.x, s * x.y, s * x.z, s * x.w);
 }
 
-// Partial channel sums over chunks of stat_chunk(G) tokens (k_colsum), folded
-// in a fixed order into the frame mean by k_mean.  Each thread reads 16-byte
-// vectors (VEC channels) of several token rows.
-template <int TOK>
-__device__ __forceinline__ void load_vec(const void* base, const float* scale, int64_t p, int C, int c, float* v) {
-  const int64_t off = p * C + c;
-  if (TOK == 0) {
-    const float4* q = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(base) + off);
-    const float4 a = q[0], d = q[1];
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = d.x; v[5] = d.y; v[6] = d.z; v[7] = d.w;
-  } else if (TOK == 1) {
-    const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(base) + off);
-    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
-    for (int j = 0; j < 4; ++j) {
-      v[2 * j] = bf16_to_f32(w[j] & 0xFFFFu);
-      v[2 * j + 1] = bf16_to_f32(w[j] >> 16);
-    }
-  } else {
-    const uint4 a = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint8_t*>(base) + off);
-    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
-    const float sc = scale[p];
-    for (int j = 0; j < 4; ++j) {
-      const float4 x = e4m3x4_to_f32(w[j]);
-      v[4 * j] = sc * x.x;
-      v[4 * j + 1] = sc * x.y;
-      v[4 * j + 2] = sc * x.z;
-      v[4 * j + 3] = sc * x.w;
-    }
-  }
-}
-
+// Partial channel sums of one (frame, chunk): colsum_chunk (the device
+// helpers header); a standalone launch, or workgroups of the mask scan's
+// launch for small batches.
 template <int TOK>
 __global__ __launch_bounds__(256) void k_colsum(Batch b, Work wk) {
-  constexpr int VEC = TOK == 2 ? 16 : 8;
-  const int f = blockIdx.y, chunk = blockIdx.x;
-  if (f >= b.dyn[0]) return;
-  const FrameDesc fd = b.frames[f];
-  const int G = fd.G, C = b.C;
-  const int nch = stat_nchunk(G);
-  if (chunk >= nch) return;
-  const int tpr = C / VEC, rpp = 256 / tpr;
-  const int tid = threadIdx.x, cg = tid % tpr, ro = tid / tpr;
-  const int p0 = chunk * stat_chunk(G), p1 = min(p0 + stat_chunk(G), G);
-  __shared__ float part[256 * 16];
-  float acc[VEC];
-  for (int j = 0; j < VEC; ++j) acc[j] = 0.f;
-  if (ro < rpp) {
-    int p = p0 + ro;
-    for (; p + 3 * rpp < p1; p += 4 * rpp) {
-      float v0[VEC], v1[VEC], v2[VEC], v3[VEC];
-      load_vec<TOK>(fd.tokens, fd.scale, p, C, cg * VEC, v0);
-      load_vec<TOK>(fd.tokens, fd.scale, p + rpp, C, cg * VEC, v1);
-      load_vec<TOK>(fd.tokens, fd.scale, p + 2 * rpp, C, cg * VEC, v2);
-      load_vec<TOK>(fd.tokens, fd.scale, p + 3 * rpp, C, cg * VEC, v3);
-      for (int j = 0; j < VEC; ++j) acc[j] += ((v0[j] + v1[j]) + v2[j]) + v3[j];
-    }
-    for (; p < p1; p += rpp) {
-      float v0[VEC];
-      load_vec<TOK>(fd.tokens, fd.scale, p, C, cg * VEC, v0);
-      for (int j = 0; j < VEC; ++j) acc[j] += v0[j];
-    }
-    for (int j = 0; j < VEC; ++j) part[ro * C + cg * VEC + j] = acc[j];
-  }
-  __syncthreads();
-  float* ps = wk.psum + ((int64_t)f * b.nchunk + chunk) * C;
-  for (int c = tid; c < C; c += 256) {
-    float a = 0.f;
-    for (int r = 0; r < rpp; ++r) a += part[r * C + c];
-    ps[c] = a;
-  }
+  colsum_chunk<TOK>(b, wk, blockIdx.y, blockIdx.x);
 }
 
 // mean[f][c] = (sum of the chunk partials in chunk order) / G
@@ -175,11 +111,16 @@ __global__ __launch_bounds__(256) void k_resid(Batch b, Work wk, int tpt) {
 inline int resid_rows(int C, int tok_dtype) { return 256 / std::min(C / (tok_dtype == 2 ? 16 : 8), 256); }
 
 // Token statistics of every frame: chunk partial sums, the frame mean, then r.
-void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st) {
+void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st, bool colsum_done) {
   const dim3 cgrid(b.nchunk, b.n_frames);
-  if (b.tok_dtype == 0) hipLaunchKernelGGL(k_colsum<0>, cgrid, dim3(256), 0, st, b, w);
-  else if (b.tok_dtype == 1) hipLaunchKernelGGL(k_colsum<1>, cgrid, dim3(256), 0, st, b, w);
-  else hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
+  if (colsum_done) {
+  } else if (b.tok_dtype == 0) {
+    hipLaunchKernelGGL(k_colsum<0>, cgrid, dim3(256), 0, st, b, w);
+  } else if (b.tok_dtype == 1) {
+    hipLaunchKernelGGL(k_colsum<1>, cgrid, dim3(256), 0, st, b, w);
+  } else {
+    hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
+  }
   hipLaunchKernelGGL(k_mean, dim3((b.C + 255) / 256, b.n_frames), dim3(256), 0, st, b, w);
   // 8 tokens per thread, fewer where that would leave under 1024 workgroups
   const int R = resid_rows(b.C, b.tok_dtype);
