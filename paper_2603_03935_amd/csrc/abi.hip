@@ -696,10 +696,14 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   const bool want_r = o.distinct || p.shape.want_dbar;
   const bool stats = want_r || tok_dtype == DISC_F8E4M3;
   const bool fused = want_r && scan_takes_colsum(b, p.shape.want_dbar);
+  // with BF16 GEMMs the frame-mean launch also packs P for the projection
+  const bool packed = want_r && b.gemm_bf16;
   auto run_stats = [&](bool colsum_done) {
     StageTimer t(sid < 0 ? -1 : ST_STATS, st);
     if (tok_dtype == DISC_F8E4M3) launch_scale_check(b, w, p.shape.gmax, st);
-    if (want_r) launch_token_stats(b, w, p.shape.gmax, st, colsum_done);
+    if (want_r)
+      launch_token_stats(b, w, p.shape.gmax, st, colsum_done, packed ? proj->data : nullptr,
+                         proj->dtype == DISC_BF16);
     if (p.shape.want_dbar) launch_rbar(b, w, st);
   };
   if (stats && !fused) run_stats(false);
@@ -714,7 +718,7 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
     const int nt = pool_tile_choice(p, tok_dtype, o, tune, b, w, tiles, st, &ran);
     if (!ran) launch_pool_choice(b, w, tiles, st, nt);
   }
-  { StageTimer t(sid < 0 ? -1 : ST_PROJ, st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, st); }
+  { StageTimer t(sid < 0 ? -1 : ST_PROJ, st); launch_proj(b, w, proj->data, proj->dtype == DISC_BF16, st, packed); }
 }
 
 }  // namespace host

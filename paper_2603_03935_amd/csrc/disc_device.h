@@ -75,6 +75,10 @@ struct MaskRec {
 };
 
 __device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+__device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even (finite inputs)
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
 
 // The four e4m3fn codes of w (lowest byte first) as floats, by the hardware
 // conversion (exact: sign x 2^(e - 7) x (1 + m / 8), subnormals m x 2^-9,
@@ -345,6 +349,22 @@ __device__ inline void colsum_chunk(const Batch& b, const Work& wk, int f, int c
   }
 }
 
+// One thread t of the projection's k-packed BF16 copy: column n, channels
+// 8 kg .. 8 kg + 7 of P ([C][E], FP32 or BF16 bits) as 16 bytes at ppack[t]
+// ([C/8][E][8]).
+template <int PBF16>
+__device__ __forceinline__ void pack_proj_chunk(const void* proj, int C, int E, uint4* ppack, int64_t t) {
+  if (t >= (int64_t)(C / 8) * E) return;
+  const int kg = (int)(t / E), n = (int)(t - (int64_t)kg * E);
+  uint32_t q[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t off = (int64_t)(kg * 8 + j) * E + n;
+    q[j] = PBF16 ? reinterpret_cast<const uint16_t*>(proj)[off] : f2bf(reinterpret_cast<const float*>(proj)[off]);
+  }
+  ppack[t] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
+}
+
 void launch_pool_order(const Batch& b, const Work& w, hipStream_t st);
 // order_pool: also order every frame's masks for the pooling (as
 // launch_pool_order), inside the launch that follows the distance transform
@@ -352,8 +372,12 @@ void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipS
                 bool order_pool = false);
 void edt_prepare();
 // Frame means and residual norms r (gmax: the largest G).
-// colsum_done: the channel sums were taken by the mask scan's launch
-void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st, bool colsum_done = false);
+// colsum_done: the channel sums were taken by the mask scan's launch.
+// pack_proj (BF16 GEMMs): also write the projection's k-packed BF16 copy
+// (proj_bf16: P is stored as BF16), from the workgroups of the frame-mean
+// launch, so the projection stage skips that launch.
+void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st, bool colsum_done = false,
+                        const void* pack_proj = nullptr, int proj_bf16 = 0);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
 void launch_rbar(const Batch& b, const Work& w, hipStream_t st);
 // FP8 tokens: flag the frames whose scales hold a non-finite or negative value
@@ -387,7 +411,9 @@ __host__ __device__ inline int pool_pair_flag(int m0, int m) { return (m0 & 64) 
 // workgroup (1, or 2 with nt <= 2 and K not split)
 void launch_pool(const Batch& b, const Work& w, const int4* tiles, hipStream_t st, int nt = 1, int mw = 1);
 bool pool_nt_valid(int C, int nt);
-void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st);
+// packed: the k-packed BF16 copy of P is already in the workspace (written
+// by launch_token_stats' pack_proj)
+void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st, bool packed = false);
 // stage helpers
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 // open-vocabulary query: inv holds m + q floats of scratch

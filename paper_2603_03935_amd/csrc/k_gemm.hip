@@ -20,10 +20,6 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even (finite inputs)
-  const uint32_t u = __float_as_uint(x);
-  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // 8 consecutive elements of a token row as GEMM operands (zero past G)
@@ -618,16 +614,7 @@ __global__ __launch_bounds__(256) void k_proj(Batch b, Work wk, const void* proj
 // ---------------------------------------------------------------------------
 template <int PBF16>
 __global__ __launch_bounds__(256) void k_pack_proj(const void* proj, int C, int E, uint4* ppack) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)(C / 8) * E) return;
-  const int kg = (int)(t / E), n = (int)(t - (int64_t)kg * E);
-  uint32_t q[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int64_t off = (int64_t)(kg * 8 + j) * E + n;
-    q[j] = PBF16 ? reinterpret_cast<const uint16_t*>(proj)[off] : f2bf(reinterpret_cast<const float*>(proj)[off]);
-  }
-  ppack[t] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
+  pack_proj_chunk<PBF16>(proj, C, E, ppack, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 // TM x TN output tile per workgroup, each wavefront (TM / 2) x (TN / 2) as
@@ -845,14 +832,18 @@ __global__ __launch_bounds__(256) void k_norm(Batch b, Work wk) {
   if (lane == 0 && fd.status) fd.status[i] = st_in != 0 ? st_in : (ss > 0.f ? 0 : 2);
 }
 
-void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st) {
+void launch_proj(const Batch& b, const Work& w, const void* proj, int proj_bf16, hipStream_t st, bool packed) {
   if (b.M <= 0) return;
   const dim3 block(256);
   if (b.gemm_bf16) {
     const int64_t np = (int64_t)(b.C / 8) * b.E;
     const dim3 pg((unsigned)((np + 255) / 256));
-    if (proj_bf16) hipLaunchKernelGGL((k_pack_proj<1>), pg, block, 0, st, proj, b.C, b.E, reinterpret_cast<uint4*>(w.ppack));
-    else hipLaunchKernelGGL((k_pack_proj<0>), pg, block, 0, st, proj, b.C, b.E, reinterpret_cast<uint4*>(w.ppack));
+    if (packed) {
+    } else if (proj_bf16) {
+      hipLaunchKernelGGL((k_pack_proj<1>), pg, block, 0, st, proj, b.C, b.E, reinterpret_cast<uint4*>(w.ppack));
+    } else {
+      hipLaunchKernelGGL((k_pack_proj<0>), pg, block, 0, st, proj, b.C, b.E, reinterpret_cast<uint4*>(w.ppack));
+    }
     hipLaunchKernelGGL((k_proj_bf16<64, 64>), dim3((b.M + 63) / 64 * b.proj_split, b.E / 64), block, 0, st, b, w);
   } else {
     const dim3 grid((b.M + 31) / 32 * b.proj_split, b.E / 128);

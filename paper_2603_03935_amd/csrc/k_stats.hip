@@ -37,8 +37,18 @@ __global__ __launch_bounds__(256) void k_colsum(Batch b, Work wk) {
   colsum_chunk<TOK>(b, wk, blockIdx.y, blockIdx.x);
 }
 
-// mean[f][c] = (sum of the chunk partials in chunk order) / G
-__global__ __launch_bounds__(256) void k_mean(Batch b, Work wk) {
+// mean[f][c] = (sum of the chunk partials in chunk order) / G.  PACK >= 0:
+// the rows of the grid past the frames write the projection's k-packed BF16
+// copy (PACK = 1: P stored as BF16).
+template <int PACK>
+__global__ __launch_bounds__(256) void k_mean(Batch b, Work wk, const void* proj, uint4* ppack) {
+  if constexpr (PACK >= 0) {
+    if ((int)blockIdx.y >= b.n_frames) {
+      const int64_t t = ((int64_t)(blockIdx.y - b.n_frames) * gridDim.x + blockIdx.x) * 256 + threadIdx.x;
+      pack_proj_chunk<PACK>(proj, b.C, b.E, ppack, t);
+      return;
+    }
+  }
   const int f = blockIdx.y, c = blockIdx.x * 256 + threadIdx.x;
   if (f >= b.dyn[0] || c >= b.C) return;
   const int G = b.frames[f].G;
@@ -111,7 +121,8 @@ __global__ __launch_bounds__(256) void k_resid(Batch b, Work wk, int tpt) {
 inline int resid_rows(int C, int tok_dtype) { return 256 / std::min(C / (tok_dtype == 2 ? 16 : 8), 256); }
 
 // Token statistics of every frame: chunk partial sums, the frame mean, then r.
-void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st, bool colsum_done) {
+void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st, bool colsum_done,
+                        const void* pack_proj, int proj_bf16) {
   const dim3 cgrid(b.nchunk, b.n_frames);
   if (colsum_done) {
   } else if (b.tok_dtype == 0) {
@@ -121,7 +132,16 @@ void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st,
   } else {
     hipLaunchKernelGGL(k_colsum<2>, cgrid, dim3(256), 0, st, b, w);
   }
-  hipLaunchKernelGGL(k_mean, dim3((b.C + 255) / 256, b.n_frames), dim3(256), 0, st, b, w);
+  const int mx = (b.C + 255) / 256;
+  uint4* pp = reinterpret_cast<uint4*>(w.ppack);
+  if (!pack_proj) {
+    hipLaunchKernelGGL(k_mean<-1>, dim3(mx, b.n_frames), dim3(256), 0, st, b, w, nullptr, nullptr);
+  } else {
+    const int64_t np = (int64_t)(b.C / 8) * b.E, row = (int64_t)mx * 256;
+    const dim3 mg(mx, b.n_frames + (unsigned)((np + row - 1) / row));
+    if (proj_bf16) hipLaunchKernelGGL(k_mean<1>, mg, dim3(256), 0, st, b, w, pack_proj, pp);
+    else hipLaunchKernelGGL(k_mean<0>, mg, dim3(256), 0, st, b, w, pack_proj, pp);
+  }
   // 8 tokens per thread, fewer where that would leave under 1024 workgroups
   const int R = resid_rows(b.C, b.tok_dtype);
   int tpt = 8;
