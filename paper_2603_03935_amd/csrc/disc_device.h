@@ -365,19 +365,36 @@ __device__ __forceinline__ void pack_proj_chunk(const void* proj, int C, int E, 
   ppack[t] = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16), q[6] | (q[7] << 16));
 }
 
+// mean[f][c] of the token statistics: the chunk partials of channel c in
+// chunk order, divided by G (one thread per channel; k_mean, or the
+// distance transform's last launch for small batches)
+__device__ __forceinline__ void frame_mean_channel(const Batch& b, const Work& wk, int f, int c) {
+  const int G = b.frames[f].G;
+  const int nch = stat_nchunk(G);
+  const float* ps = wk.psum + (int64_t)f * b.nchunk * b.C + c;
+  float a = 0.f;
+#pragma unroll 8
+  for (int j = 0; j < nch; ++j) a += ps[(int64_t)j * b.C];
+  wk.mean[(int64_t)f * b.C + c] = a * (1.0f / (float)G);
+}
+
 void launch_pool_order(const Batch& b, const Work& w, hipStream_t st);
 // order_pool: also order every frame's masks for the pooling (as
 // launch_pool_order), inside the launch that follows the distance transform
+// take_mean (direct search only, mode -1 or 2): the last launch also takes
+// the token statistics' frame means (the channel sums must be done)
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode = -1,
-                bool order_pool = false);
+                bool order_pool = false, bool take_mean = false);
 void edt_prepare();
 // Frame means and residual norms r (gmax: the largest G).
 // colsum_done: the channel sums were taken by the mask scan's launch.
 // pack_proj (BF16 GEMMs): also write the projection's k-packed BF16 copy
 // (proj_bf16: P is stored as BF16), from the workgroups of the frame-mean
 // launch, so the projection stage skips that launch.
+// mean_done: the frame means were taken by the distance transform's last
+// launch (launch_edt with take_mean; pack_proj is then not used).
 void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st, bool colsum_done = false,
-                        const void* pack_proj = nullptr, int proj_bf16 = 0);
+                        const void* pack_proj = nullptr, int proj_bf16 = 0, bool mean_done = false);
 void launch_weights(const Batch& b, const Work& w, hipStream_t st);
 void launch_rbar(const Batch& b, const Work& w, hipStream_t st);
 // FP8 tokens: flag the frames whose scales hold a non-finite or negative value

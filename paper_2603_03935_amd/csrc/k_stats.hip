@@ -51,13 +51,7 @@ __global__ __launch_bounds__(256) void k_mean(Batch b, Work wk, const void* proj
   }
   const int f = blockIdx.y, c = blockIdx.x * 256 + threadIdx.x;
   if (f >= b.dyn[0] || c >= b.C) return;
-  const int G = b.frames[f].G;
-  const int nch = stat_nchunk(G);
-  const float* ps = wk.psum + (int64_t)f * b.nchunk * b.C + c;
-  float a = 0.f;
-#pragma unroll 8
-  for (int j = 0; j < nch; ++j) a += ps[(int64_t)j * b.C];
-  wk.mean[(int64_t)f * b.C + c] = a * (1.0f / (float)G);
+  frame_mean_channel(b, wk, f, c);
 }
 
 // r_p = ||f_p - mean|| over the tokens of a frame.  A thread owns one vector
@@ -122,7 +116,7 @@ inline int resid_rows(int C, int tok_dtype) { return 256 / std::min(C / (tok_dty
 
 // Token statistics of every frame: chunk partial sums, the frame mean, then r.
 void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st, bool colsum_done,
-                        const void* pack_proj, int proj_bf16) {
+                        const void* pack_proj, int proj_bf16, bool mean_done) {
   const dim3 cgrid(b.nchunk, b.n_frames);
   if (colsum_done) {
   } else if (b.tok_dtype == 0) {
@@ -134,7 +128,8 @@ void launch_token_stats(const Batch& b, const Work& w, int gmax, hipStream_t st,
   }
   const int mx = (b.C + 255) / 256;
   uint4* pp = reinterpret_cast<uint4*>(w.ppack);
-  if (!pack_proj) {
+  if (mean_done) {
+  } else if (!pack_proj) {
     hipLaunchKernelGGL(k_mean<-1>, dim3(mx, b.n_frames), dim3(256), 0, st, b, w, nullptr, nullptr);
   } else {
     const int64_t np = (int64_t)(b.C / 8) * b.E, row = (int64_t)mx * 256;
