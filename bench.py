@@ -678,7 +678,7 @@ def oracle_leg(checks: dict, main_wl, seconds: float, threads: int) -> tuple:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this program runs on one GPU; --gpus must be 1 "
                                    "(the path shards by frames with no exchange between GPUs)"}))
         sys.exit(2)
     import torch
