@@ -475,6 +475,27 @@ def test_mask_order_and_subset_invariance(gpu):
         assert np.array_equal(out, full[idx]), f"embeddings of the {name} masks differ from the full frame"
 
 
+@pytest.mark.parametrize("name,frames", [("cfg2", None), ("cfg3", 3)])
+def test_embed_edt_layouts_agree_bitwise(gpu, name, frames):
+    """Whole calls with every distance-transform layout give the same pooled
+    features and embeddings, bit for bit.  Small batches split the token
+    statistics over other launches (channel sums with the mask scan; the
+    frame means with the direct search's patch sums, or in their own launch
+    after the band layouts, which then also pack P for a BF16 projection), so
+    this also checks that every such arrangement computes the same r."""
+    wl = di.workload(name, frames=frames)
+    ins = [frame_input(f) for f in wl.frames]
+    proj = dev_proj(wl.proj, wl.proj_dtype)
+    res = {}
+    for lay in (-1, 0, 1, 2):
+        outs = gpu.embed_frames(ins, proj, pooled=True, options=gpu.make_options(edt_layout=lay))
+        res[lay] = [(o.out.cpu().numpy(), o.pooled.cpu().numpy()) for o in outs]
+    for lay in (0, 1, 2):
+        for i, ((a, pa), (b, pb)) in enumerate(zip(res[-1], res[lay])):
+            assert np.array_equal(pa, pb), f"{name} frame {i}: pooled features with layout {lay} differ"
+            assert np.array_equal(a, b), f"{name} frame {i}: embeddings with layout {lay} differ"
+
+
 def test_projection_split_invariance(gpu):
     """The BF16 projection runs whole-K tiles on a full cfg3 batch (and on the
     cfg3 frames taken twice) and split-K tiles (group sums added in group
