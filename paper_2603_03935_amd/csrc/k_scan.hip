@@ -311,23 +311,23 @@ __global__ __launch_bounds__(1024) void k_lists(Batch b, Work wk) {
   if (threadIdx.x == 0) wk.counts[c * kLists + j] = total;
 }
 
-bool scan_takes_colsum(const Batch& b, bool any_dbar) { return b.M > 0 && b.M <= 512 && !any_dbar; }
+bool scan_takes_colsum(const Batch& b, bool any_dbar) { return b.M > 0 && !any_dbar; }
 
 void launch_scan(const Batch& b, const Work& w, hipStream_t st, bool any_dbar, bool colsum) {
   if (b.M <= 0) return;
   const int append = b.M <= kListsMasks ? 1 : 0;
-  if (scan_takes_colsum(b, any_dbar)) {
-    const int nb = b.M + (colsum ? b.nchunk * b.n_frames : 0);
-    if (!colsum)
-      hipLaunchKernelGGL((k_scan<1024>), dim3(b.M), dim3(1024), 0, st, b, w, append, 0);
-    else if (b.tok_dtype == 0)
-      hipLaunchKernelGGL((k_scan<1024, 0>), dim3(nb), dim3(1024), 0, st, b, w, append, (int)b.M);
-    else if (b.tok_dtype == 1)
-      hipLaunchKernelGGL((k_scan<1024, 1>), dim3(nb), dim3(1024), 0, st, b, w, append, (int)b.M);
-    else
-      hipLaunchKernelGGL((k_scan<1024, 2>), dim3(nb), dim3(1024), 0, st, b, w, append, (int)b.M);
+  colsum = colsum && scan_takes_colsum(b, any_dbar);
+  const int nb = b.M + (colsum ? b.nchunk * b.n_frames : 0), sb = (int)b.M;
+  if (b.M <= 512 && !any_dbar) {
+    if (!colsum) hipLaunchKernelGGL((k_scan<1024>), dim3(b.M), dim3(1024), 0, st, b, w, append, 0);
+    else if (b.tok_dtype == 0) hipLaunchKernelGGL((k_scan<1024, 0>), dim3(nb), dim3(1024), 0, st, b, w, append, sb);
+    else if (b.tok_dtype == 1) hipLaunchKernelGGL((k_scan<1024, 1>), dim3(nb), dim3(1024), 0, st, b, w, append, sb);
+    else hipLaunchKernelGGL((k_scan<1024, 2>), dim3(nb), dim3(1024), 0, st, b, w, append, sb);
   } else {
-    hipLaunchKernelGGL((k_scan<256>), dim3(b.M), dim3(256), 0, st, b, w, append, 0);
+    if (!colsum) hipLaunchKernelGGL((k_scan<256>), dim3(b.M), dim3(256), 0, st, b, w, append, 0);
+    else if (b.tok_dtype == 0) hipLaunchKernelGGL((k_scan<256, 0>), dim3(nb), dim3(256), 0, st, b, w, append, sb);
+    else if (b.tok_dtype == 1) hipLaunchKernelGGL((k_scan<256, 1>), dim3(nb), dim3(256), 0, st, b, w, append, sb);
+    else hipLaunchKernelGGL((k_scan<256, 2>), dim3(nb), dim3(256), 0, st, b, w, append, sb);
   }
   if (!append) {
     // class-5 counters stay 0 (zeroed when staged) when no item can be that tall
