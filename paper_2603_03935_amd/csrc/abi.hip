@@ -690,30 +690,35 @@ void enqueue_path(const Plan& p, char* dev_ws, int tok_dtype, const disc_options
   const Work w = work_ptrs(dev_ws, p.L);
   const int4* tiles = reinterpret_cast<const int4*>(dev_ws + p.L.tiles);
   // token statistics first: the mask scan folds r into the mean
-  // distinctiveness.  Without that, a small batch's scan launch also takes
-  // the statistics' channel sums, the last launch of the distance transform
-  // (direct search) the frame means, and the rest of the statistics follow
-  // the distance transform (two launches fewer; the stage trace then counts
-  // those parts under the scan and the distance transform).
+  // distinctiveness.  Without that, the scan's launch also takes the
+  // statistics' channel sums, the last launch of the distance transform
+  // (direct search) the frame means and the BF16 packing of P, and the rest
+  // of the statistics follow the distance transform (launches fewer; the
+  // stage trace then counts those parts under the scan and the distance
+  // transform).
   const bool want_r = o.distinct || p.shape.want_dbar;
   const bool stats = want_r || tok_dtype == DISC_F8E4M3;
   const bool fused = want_r && scan_takes_colsum(b, p.shape.want_dbar);
   const bool mean_in_edt = fused && o.edt_layout != 0 && o.edt_layout != 1;
-  // with BF16 GEMMs the frame-mean launch (when there is one) also packs P
-  // for the projection
-  const bool packed = want_r && b.gemm_bf16 && !mean_in_edt;
+  // with BF16 GEMMs the launch that takes the frame means also packs P for
+  // the projection
+  const bool packed = want_r && b.gemm_bf16;
   auto run_stats = [&](bool colsum_done) {
     StageTimer t(sid < 0 ? -1 : ST_STATS, st);
     if (tok_dtype == DISC_F8E4M3) launch_scale_check(b, w, p.shape.gmax, st);
     if (want_r)
-      launch_token_stats(b, w, p.shape.gmax, st, colsum_done, packed ? proj->data : nullptr,
+      launch_token_stats(b, w, p.shape.gmax, st, colsum_done, packed && !mean_in_edt ? proj->data : nullptr,
                          proj->dtype == DISC_BF16, mean_in_edt);
     if (p.shape.want_dbar) launch_rbar(b, w, st);
   };
   if (stats && !fused) run_stats(false);
   { StageTimer t(sid < 0 ? -1 : ST_SCAN, st); launch_scan(b, w, st, p.shape.want_dbar, fused); }
   // the pooling order rides on the launch after the distance transform
-  { StageTimer t(sid < 0 ? -1 : ST_EDT, st); launch_edt(b, w, nullptr, cus, st, o.edt_layout, true, mean_in_edt); }
+  {
+    StageTimer t(sid < 0 ? -1 : ST_EDT, st);
+    launch_edt(b, w, nullptr, cus, st, o.edt_layout, true, mean_in_edt, packed ? proj->data : nullptr,
+               proj->dtype == DISC_BF16);
+  }
   if (fused) run_stats(true);
   { StageTimer t(sid < 0 ? -1 : ST_WEIGHTS, st); launch_weights(b, w, st); }
   {

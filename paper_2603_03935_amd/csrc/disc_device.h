@@ -382,9 +382,10 @@ void launch_pool_order(const Batch& b, const Work& w, hipStream_t st);
 // order_pool: also order every frame's masks for the pooling (as
 // launch_pool_order), inside the launch that follows the distance transform
 // take_mean (direct search only, mode -1 or 2): the last launch also takes
-// the token statistics' frame means (the channel sums must be done)
+// the token statistics' frame means (the channel sums must be done) and,
+// given pack_proj (BF16 GEMMs), writes the projection's k-packed P
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode = -1,
-                bool order_pool = false, bool take_mean = false);
+                bool order_pool = false, bool take_mean = false, const void* pack_proj = nullptr, int proj_bf16 = 0);
 void edt_prepare();
 // Frame means and residual norms r (gmax: the largest G).
 // colsum_done: the channel sums were taken by the mask scan's launch.

@@ -1128,17 +1128,26 @@ __global__ __launch_bounds__(kEdtWaves * 64) __attribute__((amdgpu_waves_per_eu(
 // (nothing to do when it shared none); grid: one workgroup per CU.  With
 // order_pool it first orders every frame's masks for the pooling (one
 // workgroup per frame, in a stride); with take_mean it takes the token
-// statistics' frame means (frame f on workgroup grid - 1 - f, in a stride).
+// statistics' frame means (frame f on workgroup grid - 1 - f, in a stride)
+// and, given pack_proj, writes the projection's k-packed BF16 copy of P.
 __global__ __launch_bounds__(kEdtWaves * 64) void k_edt_dsums(Batch b, const int32_t* __restrict__ counts,
                                                               const int32_t* __restrict__ items, int item_cap,
                                                               const MaskRec* __restrict__ mrec, const float* gpart,
                                                               int direct_grid, Work wk, int order_pool,
-                                                              int take_mean) {
+                                                              int take_mean, const void* pack_proj, int proj_bf16) {
   __shared__ uint32_t recs[kEdtWaves * 16];
   __shared__ int words[kEdtWaves];
   if (take_mean)
     for (int f = (int)gridDim.x - 1 - (int)blockIdx.x; f < b.dyn[0]; f += gridDim.x)
       for (int c = threadIdx.x; c < b.C; c += blockDim.x) frame_mean_channel(b, wk, f, c);
+  if (pack_proj) {
+    const int64_t np = (int64_t)(b.C / 8) * b.E, step = (int64_t)gridDim.x * blockDim.x;
+    uint4* pp = reinterpret_cast<uint4*>(wk.ppack);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < np; t += step) {
+      if (proj_bf16) pack_proj_chunk<1>(pack_proj, b.C, b.E, pp, t);
+      else pack_proj_chunk<0>(pack_proj, b.C, b.E, pp, t);
+    }
+  }
   if (order_pool) {
     __shared__ int ocnt[256];
     __shared__ int owsum[4];
@@ -1191,7 +1200,7 @@ void edt_prepare() {
 // boxes) is written by the direct search only (callers that pass it use the
 // default layout); the AREA variants never produce distances.
 void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipStream_t st, int mode,
-                bool order_pool, bool take_mean) {
+                bool order_pool, bool take_mean, const void* pack_proj, int proj_bf16) {
   edt_prepare();
   const dim3 blk(kEdtWaves * 64);
   if (mode == 0 || mode == 1) {
@@ -1224,7 +1233,7 @@ void launch_edt(const Batch& b, const Work& w, int32_t* e_out, int num_cus, hipS
   const int g = go(2 + kind);
   const int op = order_pool && b.n_frames > 0 && b.M > 0 ? 1 : 0;
   hipLaunchKernelGGL(k_edt_dsums, dim3(num_cus), blk, 0, st, b, w.counts, w.items, b.item_cap, w.mrec, w.edt_part, g, w,
-                     op, take_mean && b.n_frames > 0 ? 1 : 0);
+                     op, take_mean && b.n_frames > 0 ? 1 : 0, take_mean ? pack_proj : nullptr, proj_bf16);
 }
 
 }  // namespace disc
